@@ -1,0 +1,171 @@
+/*
+ * gbs.h -- click-pattern probabilities of a lossy Gaussian boson sampler on
+ * one AMD Instinct MI355X (gfx950).  C ABI; no PyTorch or HIP types.
+ *
+ * Method: A. S. Popova and A. N. Rubtsov, "Cracking the Quantum Advantage
+ * threshold for Gaussian Boson Sampling".  The probability that exactly the
+ * detectors in C fire is computed two ways:
+ *   - exactly, as the signed sum over the 2^n subsets of C of vacuum
+ *     probabilities (Methods, Probability of any sample: "2^n determinants");
+ *   - approximately at order j, by the paper's scheme (Results, Approximation
+ *     scheme; Methods, Moments calculation and Approximation method):
+ *     photon-number sectors of the sub-ensemble, their click-count moments up
+ *     to order j from clusters of <= j modes, an exp-polynomial fitted per
+ *     sector, and the sum over sectors of the fitted all-click point.
+ *
+ * State conventions: a_out = U a_in; input j is a single-mode squeezed vacuum
+ * with parameter r_j (0 = vacuum), squeezed along x; output mode i then passes
+ * a pure-loss channel of transmission eta_i; hbar = 1, vacuum covariance I/2,
+ * quadratures ordered xxpp (mode i owns rows i and M+i).  At eta = 1 the state
+ * is the paper's exp(-a+ X a+)|0> with X = (1/2) U diag(tanh r) U^T (Methods,
+ * Model; the paper's U is the transpose of this one).
+ *
+ * Ownership: the caller owns every array passed in.  gbs_set_model and
+ * gbs_set_covariance copy their inputs to the device.  Calls without the _dev
+ * suffix take host pointers and return when the results are in host memory.
+ * Calls with the _dev suffix take device pointers, enqueue work on the
+ * context's stream and return without synchronising; the caller keeps the
+ * buffers alive until that stream has passed them.
+ *
+ * Errors: every call returns GBS_OK (0), a negative error code, or
+ * GBS_W_PATTERN (1) when some pattern's status is non-zero.  Argument errors
+ * are detected before any device work and write no output.  The message of the
+ * last failing call is available from gbs_last_error.  A pattern whose numerics
+ * fail gets a NaN result and a non-zero status bit; nothing is substituted.
+ *
+ * Threading: one context per host thread.  Calls on one context are not
+ * re-entrant.
+ */
+#ifndef GBS_H
+#define GBS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gbs_ctx gbs_ctx;
+typedef struct gbs_plan gbs_plan;
+
+enum {
+    GBS_OK = 0,
+    GBS_E_INVAL = -1,  /* bad argument (sizes, CSR rows, order, precision)       */
+    GBS_E_NOTPD = -2,  /* covariance + I/2 not positive definite                 */
+    GBS_E_NOMEM = -3,  /* device allocation failed                               */
+    GBS_E_HIP = -4,    /* HIP runtime error (message has the HIP error string)   */
+    GBS_E_STATE = -5,  /* no model set on the context, or plan from another ctx  */
+    GBS_W_PATTERN = 1  /* success, but some status[p] != 0                       */
+};
+
+enum { GBS_PREC_FP64 = 0 };
+
+/* per-pattern status bits */
+enum {
+    GBS_PS_OK = 0,
+    GBS_PS_FIT_NOCONV = 1, /* a sector fit carrying >1e-10 of the estimate did not converge */
+    GBS_PS_CONTOUR = 2,    /* contour radius could not meet the accuracy rule (K capped)     */
+    GBS_PS_PIVOT = 4,      /* a determinant pivot left its valid half-plane                   */
+    GBS_PS_CANCEL = 16     /* exact sum not resolved: |sum| below its rounding bound          */
+};
+
+/* Create a context on HIP device `hip_device`.  hip_stream: a hipStream_t to
+ * enqueue on (cast to void*), or NULL for a stream owned by the context. */
+int gbs_create(gbs_ctx **out, int hip_device, void *hip_stream);
+int gbs_destroy(gbs_ctx *ctx);
+/* Message of the last failing call on ctx (valid until the next call). */
+const char *gbs_last_error(const gbs_ctx *ctx);
+
+/* Model build (Methods, Model, with output loss added): M modes, U row-major
+ * M x M as separate real and imaginary planes, r[M] >= 0, eta[M] in [0, 1].
+ * Builds sigma = D O diag(e^{-2r}, e^{2r}) O^T D / 2 + (I - D^2)/2 with
+ * O = [[Re U, -Im U], [Im U, Re U]] and D = diag(sqrt eta, sqrt eta), then
+ * Q = sigma + I/2, its Cholesky factor, Q^{-1} and log det Q, all in
+ * double-double, on the device.  1 <= M <= 512.  Host pointers. */
+int gbs_set_model(gbs_ctx *ctx, int M, const double *U_re, const double *U_im,
+                  const double *r, const double *eta);
+/* Same from a covariance matrix sigma ((2M)^2, row-major, xxpp, vacuum I/2);
+ * sigma + I/2 must be positive definite.  The gradient call needs the model
+ * form and returns GBS_E_STATE after gbs_set_covariance. */
+int gbs_set_covariance(gbs_ctx *ctx, int M, const double *sigma);
+/* Copy the device model back: q_inv (2M)^2 fp64 (high part), logdet_q. */
+int gbs_get_model(gbs_ctx *ctx, double *q_inv, double *logdet_q);
+
+/*
+ * Click patterns are CSR rows: offsets[P+1] (offsets[0] = 0, non-decreasing),
+ * modes[offsets[P]]; each row lists the clicked output modes, strictly
+ * ascending, in [0, M).  Every other mode is a no-click.
+ *
+ * gbs_prob_exact: exact probability (Methods, Probability of any sample; the
+ * click projector of Methods, Model):
+ *     p(C) = det(Q)^{-1/2} sum_{Z subset C} (-1)^{n-|Z|} det((Q^{-1})_{ZZ})^{-1/2}
+ * The 2^n terms and their signed sum are evaluated in double-double, so p is
+ * accurate to ~1e-16 relative even when the sum cancels by 1e11.  Rows may hold
+ * at most 24 clicks.  Outputs (host arrays of length P): p, logp (nullable),
+ * kappa = sum|terms| / |sum| (nullable), status.
+ */
+int gbs_prob_exact(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int prec,
+                   double *p, double *logp, double *kappa, int32_t *status);
+
+/*
+ * gbs_prob_approx: the paper's order-j estimate (1 <= order <= 3), returned as
+ * log p_hat (p_hat reaches 1e-35 and below).  For each row:
+ *   1. A = (Q^{-1})_CC, eigen-decomposed (A = V diag(alpha) V^T);
+ *      log P_vac(Cbar) = -(log det Q + log det A) / 2 (eq. 3, second factor);
+ *   2. contour radius rho: the tilted mean photon number equals n, capped at
+ *      0.98 of the convergence radius 1/max|alpha-1|; K = 2^k points with
+ *      (rho/R)^K <= 1e-16 and K >= 2n+32, K <= 2048;
+ *   3. at each contour point w: M(w) = ((1-w)I + wA)^{-1} and, for every cluster
+ *      T of <= j clicked modes, G_T(w) = det(A)^{1/2} det((1-w)I+wA)^{-1/2}
+ *      det(M(w)_TT)^{-1/2} (Methods, Partition function and Moments
+ *      calculation), summed per cluster size;
+ *   4. sector moments by a discrete Fourier transform over the contour;
+ *   5. per sector kappa >= n, the exp-polynomial of degree min(j, n-1) matching
+ *      the moments (Methods, Approximation method) and its all-click value;
+ *   6. log p_hat = log P_vac(Cbar) + log sum_kappa S_0[kappa] q_kappa(n).
+ * Rows may hold at most 40 clicks.  Outputs: logp[P], status[P].
+ */
+int gbs_prob_approx(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int order,
+                    int prec, double *logp, int32_t *status);
+
+/*
+ * Plans: the per-batch layout (rows sorted by cost, device copies of the CSR,
+ * workspace) built once and reused.  gbs_plan_create copies the host CSR.
+ * The plan holds the contour radius and size per row from the first run on;
+ * set freeze = 1 in gbs_plan_freeze to keep them fixed for later runs (finite
+ * differences, fit loops).
+ */
+int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int order,
+                    int prec, gbs_plan **out);
+int gbs_plan_destroy(gbs_plan *plan);
+int gbs_plan_freeze(gbs_plan *plan, int freeze);
+/* Stream-ordered forward on a plan: logp_dev[P], status_dev[P] device arrays
+ * (status_dev nullable), results in the caller's row order. */
+int gbs_prob_approx_dev(gbs_ctx *ctx, gbs_plan *plan, double *logp_dev, int32_t *status_dev);
+
+/*
+ * gbs_grad: gradient of L = sum_p dL_dlogp[p] * log p_hat_p (order-j estimate)
+ * with respect to r[M] and eta[M] of the model set by gbs_set_model, by a
+ * hand-written adjoint of steps 1-6 (d log det X = tr(X^{-1} dX) at every
+ * determinant, implicit differentiation of each sector fit), with the contour
+ * radius and size held at their forward values.  Host pointers; logp
+ * (nullable) receives the forward values.
+ */
+int gbs_grad(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int order, int prec,
+             const double *dL_dlogp, double *logp, double *grad_r, double *grad_eta,
+             int32_t *status);
+/* Stream-ordered gradient on a plan: all pointers are device arrays. */
+int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *plan, const double *dL_dlogp_dev, double *logp_dev,
+                 double *grad_r_dev, double *grad_eta_dev, int32_t *status_dev);
+
+/* Per-row diagnostics of the last run on a plan (host arrays of length P,
+ * each nullable): contour radius, convergence radius, K, sectors fitted. */
+int gbs_plan_info(gbs_plan *plan, double *rho, double *rconv, int32_t *K, int32_t *nsectors);
+
+/* The context's stream (hipStream_t) as void*. */
+void *gbs_stream(gbs_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GBS_H */

@@ -1,0 +1,7 @@
+"""MI355X click-pattern probabilities of a lossy Gaussian boson sampler.
+
+The computation lives in libgbs.so (HIP, gfx950); see include/gbs.h for the C
+ABI and gbs.py for the Python binding.  torch_api.py wraps the device calls as
+a torch.autograd.Function.
+"""
+from .gbs import Context, Plan, GBSError, load, LIB_PATH  # noqa: F401

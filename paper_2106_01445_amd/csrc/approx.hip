@@ -1,0 +1,765 @@
+// Order-j estimate of click-pattern probabilities (Results, Approximation
+// scheme; Methods, Partition function, Moments calculation, Approximation
+// method), fp64, one MI355X.
+//
+// Pipeline per batch (all on one stream, no host synchronisation):
+//   k_prep         one workgroup per row: A = (Q^{-1})_CC gathered from HBM,
+//                  cyclic Jacobi A = V diag(alpha) V^T in LDS, log det A,
+//                  log P_vac(Cbar), contour radius rho and size K
+//   k_build_items  one workgroup: (row, chunk of contour points) work items in
+//                  decreasing-cost row order, queue counters reset
+//   k_contour      persistent workgroups pulling items from an atomic queue;
+//                  per contour point w: d = 1/(1 + w(alpha-1)),
+//                  M(w) = V diag(d) V^T as 2x2 mode blocks in LDS, and the sums
+//                  over clusters T (|T| <= j) of det(M_TT)^{-1/2}, evaluated by
+//                  2x2-block elimination with one principal square root per
+//                  block (each block's determinant lies off the negative axis);
+//                  the results, times G_0(w)/G_0(rho), go to HBM
+//   k_dft_fit      one workgroup per row: sector moments by a direct DFT over the
+//                  contour, one max-entropy fit per sector, log-sum over sectors
+#include "cplx.h"
+#include "internal.h"
+
+#define PREP_THREADS 256
+#define CONT_THREADS 256
+#define FIT_THREADS 256
+#define FIT_MAXIT 100
+#define FIT_KPT (GBS_KMAX / FIT_THREADS)
+
+namespace {
+
+__device__ double block_sum(double v, double *red)
+{
+    const int tid = threadIdx.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ double block_max(double v, double *red)
+{
+    const int tid = threadIdx.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// k_prep: gather, eigen-decompose, plan.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(PREP_THREADS) void k_prep(
+    int M, const double *__restrict__ qi, const double *__restrict__ scal,
+    const int *__restrict__ offsets, const int *__restrict__ modes, const int *__restrict__ perm,
+    const long long *__restrict__ voff, double *__restrict__ alpha_out, double *__restrict__ vt_out,
+    RowPlan *__restrict__ rows, int frozen)
+{
+    extern __shared__ double sh[];
+    __shared__ double red[PREP_THREADS];
+    __shared__ double cs_c[GBS_MAX_N_APPROX], cs_s[GBS_MAX_N_APPROX];
+    __shared__ int cs_p[GBS_MAX_N_APPROX], cs_q[GBS_MAX_N_APPROX];
+    const int p = perm[blockIdx.x];
+    const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const double logdetQ = scal[0];
+    if (n == 0) {
+        if (tid == 0) {
+            RowPlan rp = {};
+            rp.log_pvac = -0.5 * logdetQ;
+            rows[p] = rp;
+        }
+        return;
+    }
+    double *A = sh, *V = sh + N * N;
+    const int D = 2 * M;
+    for (int idx = tid; idx < N * N; idx += nt) {
+        int i = idx / N, j = idx - i * N;
+        int ri = i < n ? modes[o + i] : modes[o + i - n] + M;
+        int rj = j < n ? modes[o + j] : modes[o + j - n] + M;
+        A[idx] = qi[(long)ri * D + rj];
+        V[idx] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // cyclic Jacobi, round-robin ordering of the N/2 disjoint rotations
+    const int H = N / 2;
+    bool last = false;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        double off = 0.0, dg = 0.0;
+        for (int idx = tid; idx < N * N; idx += nt) {
+            int i = idx / N, j = idx - i * N;
+            double a = A[idx];
+            if (i == j) dg += a * a;
+            else off += a * a;
+        }
+        off = block_sum(off, red);
+        dg = block_sum(dg, red);
+        // off-diagonal at 1e-13 of the diagonal: one more (quadratically
+        // convergent) sweep reaches the rounding floor
+        if (last) break;
+        if (off <= 1e-26 * dg) last = true;
+        for (int r = 0; r < N - 1; ++r) {
+            if (tid < H) {
+                int k = tid, pp, qq;
+                if (k == 0) {
+                    pp = r;
+                    qq = N - 1;
+                } else {
+                    pp = (r + k) % (N - 1);
+                    qq = (r - k + (N - 1)) % (N - 1);
+                }
+                if (pp > qq) { int t = pp; pp = qq; qq = t; }
+                double app = A[pp * N + pp], aqq = A[qq * N + qq], apq = A[pp * N + qq];
+                double c = 1.0, s = 0.0;
+                if (apq != 0.0) {
+                    double th = (aqq - app) / (2.0 * apq);
+                    double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
+                    c = 1.0 / sqrt(fma(t, t, 1.0));
+                    s = t * c;
+                }
+                cs_c[k] = c; cs_s[k] = s; cs_p[k] = pp; cs_q[k] = qq;
+            }
+            __syncthreads();
+            for (int idx = tid; idx < H * N; idx += nt) {
+                int k = idx / N, j = idx - k * N;
+                int pp = cs_p[k], qq = cs_q[k];
+                double c = cs_c[k], s = cs_s[k];
+                double apj = A[pp * N + j], aqj = A[qq * N + j];
+                A[pp * N + j] = c * apj - s * aqj;
+                A[qq * N + j] = s * apj + c * aqj;
+            }
+            __syncthreads();
+            for (int idx = tid; idx < N * H; idx += nt) {
+                int i = idx / H, k = idx - i * H;
+                int pp = cs_p[k], qq = cs_q[k];
+                double c = cs_c[k], s = cs_s[k];
+                double aip = A[i * N + pp], aiq = A[i * N + qq];
+                A[i * N + pp] = c * aip - s * aiq;
+                A[i * N + qq] = s * aip + c * aiq;
+                double vip = V[i * N + pp], viq = V[i * N + qq];
+                V[i * N + pp] = c * vip - s * viq;
+                V[i * N + qq] = s * vip + c * viq;
+            }
+            __syncthreads();
+        }
+    }
+    // outputs: alpha, V^T (eigenvector k contiguous)
+    const long long vo = voff[p];
+    for (int idx = tid; idx < N * N; idx += nt) {
+        int k = idx / N, i = idx - k * N;
+        vt_out[vo + idx] = V[i * N + k];
+    }
+    double lsum = 0.0, amin = 1e300, dev = 0.0;
+    for (int i = tid; i < N; i += nt) {
+        double a = A[i * N + i];
+        alpha_out[2 * o + i] = a;
+        lsum += log(a);
+        amin = fmin(amin, a);
+        dev = fmax(dev, fabs(a - 1.0));
+    }
+    double logdetA = block_sum(lsum, red);
+    amin = -block_max(-amin, red);
+    dev = block_max(dev, red);
+    if (tid == 0) {
+        RowPlan rp = rows[p];
+        rp.status = 0;
+        rp.logdet_a = logdetA;
+        rp.log_pvac = -0.5 * (logdetQ + logdetA);
+        if (!(amin > 0.0)) {
+            rp.status = GBS_PS_PIVOT;
+        } else {
+            if (!frozen) {
+                double rb = dev > 1e-300 ? 1.0 / dev : 1e300;
+                double hi = 0.98 * rb;
+                auto mfun = [&](double rho) {
+                    double s = 0.0;
+                    for (int i = 0; i < N; ++i) {
+                        double a = A[i * N + i];
+                        s += 0.5 * rho * (1.0 - a) / (1.0 + rho * (a - 1.0));
+                    }
+                    return s;
+                };
+                double rho;
+                if (dev < 1e-300) rho = 1.0;
+                else if (mfun(hi) <= (double)n) rho = hi;
+                else {
+                    double lo = 0.0;
+                    for (int it = 0; it < 200; ++it) {
+                        double mid = 0.5 * (lo + hi);
+                        if (mfun(mid) < (double)n) lo = mid;
+                        else hi = mid;
+                    }
+                    rho = 0.5 * (lo + hi);
+                }
+                double kneed = 2.0 * n + 32.0;
+                if (dev >= 1e-300) kneed = fmax(kneed, log(1e-16) / log(rho / rb));
+                int K = 1;
+                while (K < kneed && K < GBS_KMAX) K *= 2;
+                rp.rho = rho;
+                rp.rconv = rb;
+                rp.K = K;
+                rp.log_rho = log(rho);
+            }
+            double s = 0.0;
+            for (int i = 0; i < N; ++i) s += log1p(rp.rho * (A[i * N + i] - 1.0));
+            rp.log_g_rho = 0.5 * logdetA - 0.5 * s;
+        }
+        rows[p] = rp;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_build_items: work items (row, chunk) in the plan's cost order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_build_items(int P, const int *__restrict__ offsets,
+                                                      const int *__restrict__ perm,
+                                                      const RowPlan *__restrict__ rows,
+                                                      int *__restrict__ items,
+                                                      int *__restrict__ counter)
+{
+    __shared__ int part[1024];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int per = (P + nt - 1) / nt;
+    const int b = tid * per, e = min(P, b + per);
+    auto nch = [&](int i) {
+        int p = perm[i];
+        int n = offsets[p + 1] - offsets[p];
+        const RowPlan &rp = rows[p];
+        if (n == 0 || rp.status != 0 || rp.K <= 0) return 0;
+        return (rp.K / 2 + 1 + GBS_QCHUNK - 1) / GBS_QCHUNK;
+    };
+    int s = 0;
+    for (int i = b; i < e; ++i) s += nch(i);
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        for (int t = 0; t < nt; ++t) {
+            int v = part[t];
+            part[t] = acc;
+            acc += v;
+        }
+        counter[0] = acc;
+        counter[1] = 0;
+    }
+    __syncthreads();
+    int off = part[tid];
+    for (int i = b; i < e; ++i) {
+        int c = nch(i), p = perm[i];
+        for (int k = 0; k < c; ++k) {
+            items[2 * (off + k)] = p;
+            items[2 * (off + k) + 1] = k;
+        }
+        off += c;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_contour: cluster sums at contour points.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ cplx warp_csum(cplx v)
+{
+    for (int m = 32; m > 0; m >>= 1) {
+        v.re += __shfl_xor(v.re, m);
+        v.im += __shfl_xor(v.im, m);
+    }
+    return v;
+}
+
+struct Blk2 {  // general 2x2 complex block
+    cplx a00, a01, a10, a11;
+};
+
+template <int ORDER>
+__global__ __launch_bounds__(CONT_THREADS) void k_contour(
+    int nmax, const int *__restrict__ offsets, const long long *__restrict__ voff,
+    const double *__restrict__ alpha, const double *__restrict__ vt,
+    const RowPlan *__restrict__ rows, const int *__restrict__ items, int *__restrict__ counter,
+    const int4 *__restrict__ citems, const int2 *__restrict__ coff, cplx *__restrict__ sw)
+{
+    extern __shared__ double sh[];
+    const int NM = 2 * nmax;
+    double *Vt = sh;                                   // NM*NM
+    double *al = Vt + NM * NM;                         // NM
+    cplx *dk = (cplx *)(al + NM);                      // NM
+    cplx *Md = dk + NM;                                // nmax*3
+    cplx *Mo = Md + 3 * nmax;                          // nmax(nmax-1)/2 * 4
+    __shared__ int s_item;
+    __shared__ cplx s_red[CONT_THREADS / 64][4];
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6;
+    const int total = counter[0];
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(&counter[1], 1);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= total) break;
+        const int p = items[2 * item], ch = items[2 * item + 1];
+        const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
+        const RowPlan rp = rows[p];
+        const long long vo = voff[p];
+        for (int idx = tid; idx < N * N; idx += nt) Vt[idx] = vt[vo + idx];
+        for (int i = tid; i < N; i += nt) al[i] = alpha[2 * o + i];
+        const int Q = rp.K / 2 + 1;
+        const int q0 = ch * GBS_QCHUNK, q1 = min(q0 + GBS_QCHUNK, Q);
+        const int nblk = n + n * (n - 1) / 2;
+        const int2 cr = coff[n];
+        __syncthreads();
+        for (int q = q0; q < q1; ++q) {
+            double sn, cs;
+            sincospi(2.0 * (double)q / (double)rp.K, &sn, &cs);
+            const cplx w = cmk(rp.rho * cs, rp.rho * sn);
+            // d_k = 1/(1 + w(alpha_k - 1)); sum of principal logs for G_0(w)
+            cplx lz = cmk(0.0, 0.0);
+            for (int k = tid; k < N; k += nt) {
+                cplx z = cmk(1.0 + w.re * (al[k] - 1.0), w.im * (al[k] - 1.0));
+                dk[k] = crecip(z);
+                lz = cadd(lz, clog_p(z));
+            }
+            lz = warp_csum(lz);
+            if (lane == 0) s_red[wid][0] = lz;
+            __syncthreads();
+            cplx slz = cmk(0.0, 0.0);
+            for (int i = 0; i < nt / 64; ++i) slz = cadd(slz, s_red[i][0]);
+            // G_0(w)/G_0(rho) = exp(logdet A/2 - sum Log/2 - log G_0(rho))
+            const cplx ghat = cexp_(cmk(0.5 * rp.logdet_a - 0.5 * slz.re - rp.log_g_rho, -0.5 * slz.im));
+            // M(w) as 2x2 mode blocks
+            for (int bi = tid; bi < nblk; bi += nt) {
+                if (bi < n) {
+                    const int a = bi, r0 = a, r1 = n + a;
+                    cplx m00 = cmk(0, 0), m01 = cmk(0, 0), m11 = cmk(0, 0);
+                    for (int k = 0; k < N; ++k) {
+                        double v0 = Vt[k * N + r0], v1 = Vt[k * N + r1];
+                        cplx d = dk[k];
+                        double p00 = v0 * v0, p01 = v0 * v1, p11 = v1 * v1;
+                        m00.re = fma(p00, d.re, m00.re); m00.im = fma(p00, d.im, m00.im);
+                        m01.re = fma(p01, d.re, m01.re); m01.im = fma(p01, d.im, m01.im);
+                        m11.re = fma(p11, d.re, m11.re); m11.im = fma(p11, d.im, m11.im);
+                    }
+                    Md[3 * a] = m00; Md[3 * a + 1] = m01; Md[3 * a + 2] = m11;
+                } else {
+                    int oi = bi - n, a = 0;
+                    while (oi >= n - 1 - a) { oi -= n - 1 - a; ++a; }
+                    const int b = a + 1 + oi;
+                    cplx b00 = cmk(0, 0), b01 = cmk(0, 0), b10 = cmk(0, 0), b11 = cmk(0, 0);
+                    for (int k = 0; k < N; ++k) {
+                        double va0 = Vt[k * N + a], va1 = Vt[k * N + n + a];
+                        double vb0 = Vt[k * N + b], vb1 = Vt[k * N + n + b];
+                        cplx d = dk[k];
+                        double p00 = va0 * vb0, p01 = va0 * vb1, p10 = va1 * vb0, p11 = va1 * vb1;
+                        b00.re = fma(p00, d.re, b00.re); b00.im = fma(p00, d.im, b00.im);
+                        b01.re = fma(p01, d.re, b01.re); b01.im = fma(p01, d.im, b01.im);
+                        b10.re = fma(p10, d.re, b10.re); b10.im = fma(p10, d.im, b10.im);
+                        b11.re = fma(p11, d.re, b11.re); b11.im = fma(p11, d.im, b11.im);
+                    }
+                    cplx *dst = Mo + 4 * (bi - n);
+                    dst[0] = b00; dst[1] = b01; dst[2] = b10; dst[3] = b11;
+                }
+            }
+            __syncthreads();
+            // cluster sums
+            cplx s1 = cmk(0, 0), s2 = cmk(0, 0), s3 = cmk(0, 0);
+            for (int a = tid; a < n; a += nt) {
+                cplx a00 = Md[3 * a], a01 = Md[3 * a + 1], a11 = Md[3 * a + 2];
+                cplx det = cfnma(a01, a01, cmul(a00, a11));
+                s1 = cadd(s1, crecip(csqrt_p(det)));
+            }
+            if (ORDER >= 2) {
+                for (int it = tid; it < cr.y; it += nt) {
+                    const int4 e = citems[cr.x + it];
+                    const int a = e.x, b = e.y, c0 = e.z, c1 = e.w & 0xffff, first = e.w >> 16;
+                    const cplx a00 = Md[3 * a], a01 = Md[3 * a + 1], a11 = Md[3 * a + 2];
+                    const cplx *pb = Mo + 4 * (a * (2 * n - a - 1) / 2 + (b - a - 1));
+                    const cplx b00 = pb[0], b01 = pb[1], b10 = pb[2], b11 = pb[3];
+                    const cplx bb00 = Md[3 * b], bb01 = Md[3 * b + 1], bb11 = Md[3 * b + 2];
+                    const cplx deta = cfnma(a01, a01, cmul(a00, a11));
+                    const cplx ideta = crecip(deta);
+                    const cplx ia00 = cmul(a11, ideta), ia11 = cmul(a00, ideta);
+                    const cplx ia01 = cmk(-(a01.re * ideta.re - a01.im * ideta.im),
+                                          -(a01.re * ideta.im + a01.im * ideta.re));
+                    // G = Maa^{-1} Mab
+                    const cplx G00 = cfma(ia00, b00, cmul(ia01, b10));
+                    const cplx G01 = cfma(ia00, b01, cmul(ia01, b11));
+                    const cplx G10 = cfma(ia01, b00, cmul(ia11, b10));
+                    const cplx G11 = cfma(ia01, b01, cmul(ia11, b11));
+                    // Sb = Mbb - Mab^T G
+                    const cplx sb00 = csub(bb00, cfma(b00, G00, cmul(b10, G10)));
+                    const cplx sb01 = csub(bb01, cfma(b00, G01, cmul(b10, G11)));
+                    const cplx sb11 = csub(bb11, cfma(b01, G01, cmul(b11, G11)));
+                    const cplx detb = cfnma(sb01, sb01, cmul(sb00, sb11));
+                    const cplx rab = crecip(cmul(csqrt_p(deta), csqrt_p(detb)));
+                    if (first) s2 = cadd(s2, rab);
+                    if (ORDER >= 3 && c1 > c0) {
+                        const cplx idetb = crecip(detb);
+                        const cplx ib00 = cmul(sb11, idetb), ib11 = cmul(sb00, idetb);
+                        const cplx ib01 = cmk(-(sb01.re * idetb.re - sb01.im * idetb.im),
+                                              -(sb01.re * idetb.im + sb01.im * idetb.re));
+                        // blocks (a,c) and (b,c): packed index off(x) + c - x - 1
+                        const int oac = a * (2 * n - a - 1) / 2 - a - 1;
+                        const int obc = b * (2 * n - b - 1) / 2 - b - 1;
+                        for (int c = c0; c < c1; ++c) {
+                            const cplx *pac = Mo + 4 * (oac + c), *pbc = Mo + 4 * (obc + c);
+                            const cplx x00 = pac[0], x01 = pac[1], x10 = pac[2], x11 = pac[3];
+                            const cplx y00 = pbc[0], y01 = pbc[1], y10 = pbc[2], y11 = pbc[3];
+                            const cplx c00 = Md[3 * c], c01 = Md[3 * c + 1], c11 = Md[3 * c + 2];
+                            // Y = Xb - G^T Xa
+                            const cplx Y00 = csub(y00, cfma(G00, x00, cmul(G10, x10)));
+                            const cplx Y01 = csub(y01, cfma(G00, x01, cmul(G10, x11)));
+                            const cplx Y10 = csub(y10, cfma(G01, x00, cmul(G11, x10)));
+                            const cplx Y11 = csub(y11, cfma(G01, x01, cmul(G11, x11)));
+                            // Za = Maa^{-1} Xa, Wb = Sb^{-1} Y
+                            const cplx Z00 = cfma(ia00, x00, cmul(ia01, x10));
+                            const cplx Z01 = cfma(ia00, x01, cmul(ia01, x11));
+                            const cplx Z10 = cfma(ia01, x00, cmul(ia11, x10));
+                            const cplx Z11 = cfma(ia01, x01, cmul(ia11, x11));
+                            const cplx W00 = cfma(ib00, Y00, cmul(ib01, Y10));
+                            const cplx W01 = cfma(ib00, Y01, cmul(ib01, Y11));
+                            const cplx W10 = cfma(ib01, Y00, cmul(ib11, Y10));
+                            const cplx W11 = cfma(ib01, Y01, cmul(ib11, Y11));
+                            // Sc = Mcc - Xa^T Za - Y^T W
+                            const cplx sc00 = csub(csub(c00, cfma(x00, Z00, cmul(x10, Z10))),
+                                                   cfma(Y00, W00, cmul(Y10, W10)));
+                            const cplx sc01 = csub(csub(c01, cfma(x00, Z01, cmul(x10, Z11))),
+                                                   cfma(Y00, W01, cmul(Y10, W11)));
+                            const cplx sc11 = csub(csub(c11, cfma(x01, Z01, cmul(x11, Z11))),
+                                                   cfma(Y01, W01, cmul(Y11, W11)));
+                            const cplx detc = cfnma(sc01, sc01, cmul(sc00, sc11));
+                            s3 = cadd(s3, cdiv(rab, csqrt_p(detc)));
+                        }
+                    }
+                }
+            }
+            s1 = warp_csum(s1);
+            s2 = warp_csum(s2);
+            s3 = warp_csum(s3);
+            __syncthreads();
+            if (lane == 0) {
+                s_red[wid][1] = s1;
+                s_red[wid][2] = s2;
+                s_red[wid][3] = s3;
+            }
+            __syncthreads();
+            if (tid <= ORDER) {
+                cplx acc = cmk(0, 0);
+                if (tid == 0) acc = cmk(1.0, 0.0);
+                else
+                    for (int i = 0; i < nt / 64; ++i) acc = cadd(acc, s_red[i][tid]);
+                sw[((long)p * (ORDER + 1) + tid) * GBS_QCAP + q] = cmul(ghat, acc);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_dft_fit: sector moments, fits, log-sum.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void fit_eval(int n, int jp, const double *ib, const double *c,
+                                         double *lse, double *E, double *E2)
+{
+    double zmax = -1e300;
+    for (int v = 0; v < n; ++v) {
+        double f1 = v * ib[0], f2 = 0.5 * v * (v - 1) * ib[1], f3 = v * (v - 1.0) * (v - 2.0) / 6.0 * ib[2];
+        double z = -(c[0] * f1 + (jp > 1 ? c[1] * f2 : 0.0) + (jp > 2 ? c[2] * f3 : 0.0));
+        zmax = fmax(zmax, z);
+    }
+    double s = 0.0, e[3] = {0, 0, 0}, e2[6] = {0, 0, 0, 0, 0, 0};
+    for (int v = 0; v < n; ++v) {
+        double f[3] = {v * ib[0], 0.5 * v * (v - 1) * ib[1], v * (v - 1.0) * (v - 2.0) / 6.0 * ib[2]};
+        double z = -(c[0] * f[0] + (jp > 1 ? c[1] * f[1] : 0.0) + (jp > 2 ? c[2] * f[2] : 0.0));
+        double wgt = exp(z - zmax);
+        s += wgt;
+        if (E) {
+            for (int t = 0; t < jp; ++t) e[t] += wgt * f[t];
+            int k = 0;
+            for (int t = 0; t < jp; ++t)
+                for (int u = t; u < jp; ++u) e2[k++] += wgt * f[t] * f[u];
+        }
+    }
+    *lse = zmax + log(s);
+    if (E) {
+        for (int t = 0; t < 3; ++t) E[t] = e[t] / s;
+        for (int k = 0; k < 6; ++k) E2[k] = e2[k] / s;
+    }
+}
+
+// Max-entropy fit on n' = 1..n (v = n - n' empty modes) of the jp moments m[];
+// returns 0 and log q(n) on success.
+__device__ int fit_last_point(int n, int jp, const double *m, double *logq)
+{
+    double ib[3] = {0, 0, 0};
+    ib[0] = 1.0 / (n - 1.0);
+    if (jp > 1) ib[1] = 2.0 / ((n - 1.0) * (n - 2.0));
+    if (jp > 2) ib[2] = 6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0));
+    double c[3] = {0, 0, 0};
+    for (int it = 0; it <= FIT_MAXIT; ++it) {
+        double lse, E[3], E2[6];
+        fit_eval(n, jp, ib, c, &lse, E, E2);
+        double g[3] = {0, 0, 0};
+        bool conv = true;
+        for (int t = 0; t < jp; ++t) {
+            g[t] = m[t] - E[t];
+            if (!(fabs(g[t]) <= 1e-15 + 1e-12 * fabs(m[t]))) conv = false;
+        }
+        // Hessian = covariance of phi, damped by 1e-14 of its trace
+        double Hm[3][3];
+        int k = 0;
+        for (int t = 0; t < jp; ++t)
+            for (int u = t; u < jp; ++u) {
+                Hm[t][u] = Hm[u][t] = E2[k++] - E[t] * E[u];
+            }
+        double tr = 0.0;
+        for (int t = 0; t < jp; ++t) tr += Hm[t][t];
+        for (int t = 0; t < jp; ++t) Hm[t][t] += 1e-14 * tr;
+        // Cholesky solve H x = -g
+        double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        bool ok = tr > 0.0;
+        for (int j = 0; j < jp && ok; ++j) {
+            double d = Hm[j][j];
+            for (int l = 0; l < j; ++l) d -= L[j][l] * L[j][l];
+            if (!(d > 0.0)) { ok = false; break; }
+            L[j][j] = sqrt(d);
+            for (int i = j + 1; i < jp; ++i) {
+                double s = Hm[i][j];
+                for (int l = 0; l < j; ++l) s -= L[i][l] * L[j][l];
+                L[i][j] = s / L[j][j];
+            }
+        }
+        if (!ok) return 1;
+        double y[3], x[3];
+        for (int i = 0; i < jp; ++i) {
+            double s = -g[i];
+            for (int l = 0; l < i; ++l) s -= L[i][l] * y[l];
+            y[i] = s / L[i][i];
+        }
+        for (int i = jp - 1; i >= 0; --i) {
+            double s = y[i];
+            for (int l = i + 1; l < jp; ++l) s -= L[l][i] * x[l];
+            x[i] = s / L[i][i];
+        }
+        if (conv) {
+            double cn[3] = {c[0] + x[0], c[1] + (jp > 1 ? x[1] : 0.0), c[2] + (jp > 2 ? x[2] : 0.0)};
+            double l2;
+            fit_eval(n, jp, ib, cn, &l2, nullptr, nullptr);
+            *logq = -l2;
+            return 0;
+        }
+        double L0 = lse, slope = 0.0;
+        for (int t = 0; t < jp; ++t) {
+            L0 += c[t] * m[t];
+            slope += g[t] * x[t];
+        }
+        double st = 1.0;
+        if (-slope > 1e-13 * fmax(1.0, fabs(L0))) {
+            while (st > 1e-12) {
+                double cn[3] = {c[0] + st * x[0], c[1] + (jp > 1 ? st * x[1] : 0.0),
+                                c[2] + (jp > 2 ? st * x[2] : 0.0)};
+                double l2;
+                fit_eval(n, jp, ib, cn, &l2, nullptr, nullptr);
+                for (int t = 0; t < jp; ++t) l2 += cn[t] * m[t];
+                if (l2 <= L0 + 1e-4 * st * slope) break;
+                st *= 0.5;
+            }
+        }
+        for (int t = 0; t < jp; ++t) c[t] += st * x[t];
+    }
+    return 1;
+}
+
+__device__ __forceinline__ void lse_add(double &mx, double &s, double v)
+{
+    if (v == -INFINITY) return;
+    if (v > mx) {
+        s = s * exp(mx - v) + 1.0;
+        mx = v;
+    } else {
+        s += exp(v - mx);
+    }
+}
+
+template <int ORDER>
+__global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__ offsets,
+                                                         RowPlan *__restrict__ rows,
+                                                         const cplx *__restrict__ sw,
+                                                         double *__restrict__ logp,
+                                                         int *__restrict__ status)
+{
+    extern __shared__ double sh[];
+    __shared__ double red[FIT_THREADS], red2[FIT_THREADS];
+    const int p = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int n = offsets[p + 1] - offsets[p];
+    RowPlan rp = rows[p];
+    if (n == 0) {
+        if (tid == 0) {
+            logp[p] = rp.log_pvac;
+            if (status) status[p] = 0;
+        }
+        return;
+    }
+    if (rp.status != 0) {
+        if (tid == 0) {
+            logp[p] = NAN;
+            if (status) status[p] = rp.status;
+        }
+        return;
+    }
+    const int K = rp.K, Q = K / 2 + 1, jp = min(ORDER, n - 1);
+    cplx *S = (cplx *)sh;                       // (jp+1) x Q
+    double *ct = (double *)(S + (ORDER + 1) * Q);  // K cos, K sin
+    double *st = ct + K;
+    for (int idx = tid; idx < (jp + 1) * Q; idx += nt) {
+        int t = idx / Q, q = idx - t * Q;
+        S[t * Q + q] = sw[((long)p * (ORDER + 1) + t) * GBS_QCAP + q];
+    }
+    for (int m = tid; m < K; m += nt) sincospi(2.0 * (double)m / (double)K, &st[m], &ct[m]);
+    __syncthreads();
+    double tau[FIT_KPT][ORDER + 1];
+    const double invK = 1.0 / K;
+    double tmax = 0.0;
+    for (int j = 0; j < FIT_KPT; ++j) {
+        const int kap = n + tid + nt * j;
+        for (int t = 0; t <= ORDER; ++t) tau[j][t] = 0.0;
+        if (kap >= K) continue;
+        for (int t = 0; t <= jp; ++t) {
+            double acc = S[t * Q].re + ((kap & 1) ? -S[t * Q + Q - 1].re : S[t * Q + Q - 1].re);
+            double acc2 = 0.0;
+            for (int q = 1; q < Q - 1; ++q) {
+                const int mi = (q * kap) & (K - 1);
+                const cplx s = S[t * Q + q];
+                acc2 = fma(s.re, ct[mi], fma(s.im, st[mi], acc2));
+            }
+            tau[j][t] = (acc + 2.0 * acc2) * invK;
+        }
+        tmax = fmax(tmax, tau[j][0]);
+    }
+    tmax = block_max(tmax, red);
+    const double thr = 1e-14 * tmax;
+    double fm = -INFINITY, fs = 0.0, um = -INFINITY, us = 0.0;
+    int nsec = 0;
+    double binv[3] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
+                      6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0))};
+    for (int j = 0; j < FIT_KPT; ++j) {
+        const int kap = n + tid + nt * j;
+        if (kap >= K) continue;
+        const double t0 = tau[j][0];
+        if (!(t0 >= thr) || !(t0 > 0.0)) continue;
+        const double lw = log(t0) + rp.log_g_rho - kap * rp.log_rho;
+        double m[3] = {0, 0, 0};
+        for (int t = 1; t <= jp; ++t) m[t - 1] = tau[j][t] / t0 * binv[t - 1];
+        // Fit with the longest feasible prefix of the moments (0 < m_t < 1,
+        // decreasing in t, since 0 <= phi_{t+1} <= phi_t <= 1).  A moment whose
+        // true value lies below the DFT's rounding floor can come out infeasible;
+        // it is then dropped, and so is the next one if the fit fails.  With
+        // m_1 <= 0 every clicked mode fires: q(n) = 1.
+        int jr = 0;
+        for (int t = 1; t <= jp; ++t) {
+            if (m[t - 1] > 0.0 && m[t - 1] < 1.0 && (t == 1 || m[t - 1] < m[t - 2])) jr = t;
+            else break;
+        }
+        double lq = 0.0;
+        int bad = 0;
+        if (jp > 0) {
+            bad = 1;
+            while (jr >= 1 && bad) {
+                bad = fit_last_point(n, jr, m, &lq);
+                if (bad) --jr;
+            }
+            if (jr == 0) {
+                bad = m[0] <= 0.0 ? 0 : 1;
+                lq = 0.0;
+            }
+        }
+        if (bad) {
+            lse_add(um, us, lw);
+        } else {
+            lse_add(fm, fs, lw + lq);
+            ++nsec;
+        }
+    }
+    // block log-sum-exp of the fitted and the unresolved sectors
+    double fmx = block_max(fm, red);
+    double fsum = block_sum(fs * (fm == -INFINITY ? 0.0 : exp(fm - fmx)), red);
+    double umx = block_max(um, red2);
+    double usum = block_sum(us * (um == -INFINITY ? 0.0 : exp(um - umx)), red2);
+    double ns = block_sum((double)nsec, red);
+    if (tid == 0) {
+        double tot = fmx + log(fsum);
+        double unres = umx + log(usum);
+        int stt = 0;
+        double out = rp.log_pvac + tot;
+        if (fsum > 0.0 && usum > 0.0 && unres > tot + log(1e-10)) {
+            stt = GBS_PS_FIT_NOCONV;
+            out = NAN;
+        }
+        if (!(fsum > 0.0)) out = -INFINITY;
+        logp[p] = out;
+        if (status) status[p] = stt;
+        rp.nsec = (int)ns;
+        rows[p].nsec = rp.nsec;
+    }
+}
+
+template <int ORDER>
+size_t contour_lds(int nmax)
+{
+    int NM = 2 * nmax;
+    return sizeof(double) * ((size_t)NM * NM + NM) + sizeof(cplx) * (NM + 3 * nmax + 2 * nmax * (nmax - 1));
+}
+
+template <int ORDER>
+int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
+{
+    hipStream_t st = ctx->stream;
+    DevModel &m = ctx->model;
+    const int P = pl->P, nmax = pl->max_n;
+    size_t lds_prep = sizeof(double) * 2 * (size_t)(2 * nmax) * (2 * nmax);
+    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_prep, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds_prep));
+    hipLaunchKernelGGL(k_prep, dim3(P), dim3(PREP_THREADS), lds_prep, st, m.M, m.qi_hi, m.scal,
+                       pl->d_offsets, pl->d_modes, pl->d_perm, pl->d_voff, pl->d_alpha, pl->d_v,
+                       pl->d_rows, pl->frozen ? 1 : 0);
+    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, st, P, pl->d_offsets, pl->d_perm,
+                       pl->d_rows, pl->d_items, pl->d_counter);
+    size_t lds_c = contour_lds<ORDER>(nmax);
+    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_contour<ORDER>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_c));
+    int occ = 0;
+    HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_contour<ORDER>, CONT_THREADS,
+                                                              lds_c));
+    if (occ < 1) occ = 1;
+    int grid = occ * ctx->num_cu;
+    hipLaunchKernelGGL(k_contour<ORDER>, dim3(grid), dim3(CONT_THREADS), lds_c, st, nmax,
+                       pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_items,
+                       pl->d_counter, (const int4 *)pl->d_cluster_items,
+                       (const int2 *)pl->d_cluster_off, pl->d_sw);
+    size_t lds_f = sizeof(cplx) * (ORDER + 1) * GBS_QCAP + sizeof(double) * 2 * GBS_KMAX;
+    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_dft_fit<ORDER>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f));
+    hipLaunchKernelGGL(k_dft_fit<ORDER>, dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
+                       pl->d_rows, pl->d_sw, logp, status);
+    HIP_TRY(ctx, hipGetLastError());
+    return 0;
+}
+
+}  // namespace
+
+int approx_forward(gbs_ctx *ctx, gbs_plan *pl, double *logp_dev, int32_t *status_dev)
+{
+    if (pl->P == 0) return 0;
+    switch (pl->order) {
+    case 1: return launch_order<1>(ctx, pl, logp_dev, status_dev);
+    case 2: return launch_order<2>(ctx, pl, logp_dev, status_dev);
+    case 3: return launch_order<3>(ctx, pl, logp_dev, status_dev);
+    default: return set_err(ctx, -1, "order must be 1, 2 or 3");
+    }
+}

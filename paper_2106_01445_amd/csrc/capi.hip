@@ -1,0 +1,445 @@
+// C ABI of the click-probability library (declared in include/gbs.h).
+// Argument validation, device buffers, plans; the kernels live in model.hip,
+// approx.hip, exact.hip and grad.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+
+#include "../../include/gbs.h"
+#include "internal.h"
+
+int model_alloc(gbs_ctx *ctx, int M);
+void model_release(gbs_ctx *ctx);
+int model_build_dev(gbs_ctx *ctx, const double *sigma_dev);
+
+int set_err(gbs_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+namespace {
+
+int check_csr(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int M,
+              int max_n)
+{
+    if (P < 0) return set_err(ctx, GBS_E_INVAL, "P must be >= 0");
+    if (P > 0 && !offsets) return set_err(ctx, GBS_E_INVAL, "offsets is NULL");
+    if (P == 0) return GBS_OK;
+    if (offsets[0] != 0) return set_err(ctx, GBS_E_INVAL, "offsets[0] must be 0");
+    if (offsets[P] > 0 && !modes) return set_err(ctx, GBS_E_INVAL, "modes is NULL");
+    for (int p = 0; p < P; ++p) {
+        int n = offsets[p + 1] - offsets[p];
+        if (n < 0)
+            return set_err(ctx, GBS_E_INVAL, "offsets must be non-decreasing (row " +
+                                                 std::to_string(p) + ")");
+        if (n > max_n)
+            return set_err(ctx, GBS_E_INVAL, "row " + std::to_string(p) + " has " +
+                                                 std::to_string(n) + " clicks; at most " +
+                                                 std::to_string(max_n) + " supported");
+        for (int i = offsets[p]; i < offsets[p + 1]; ++i) {
+            if (modes[i] < 0 || modes[i] >= M)
+                return set_err(ctx, GBS_E_INVAL, "row " + std::to_string(p) +
+                                                     ": mode out of range [0, M)");
+            if (i > offsets[p] && modes[i] <= modes[i - 1])
+                return set_err(ctx, GBS_E_INVAL, "row " + std::to_string(p) +
+                                                     ": modes must be strictly ascending");
+        }
+    }
+    return GBS_OK;
+}
+
+void plan_free_dev(gbs_plan *pl)
+{
+    void *ptrs[] = {pl->d_offsets, pl->d_modes, pl->d_perm, pl->d_voff, pl->d_alpha,
+                    pl->d_v, pl->d_rows, pl->d_sw, pl->d_items, pl->d_counter,
+                    pl->d_cluster_items, pl->d_cluster_off, pl->d_logp, pl->d_status,
+                    pl->d_gsw, pl->d_abar, pl->d_qibar, pl->d_grad, pl->d_dl};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+// Cluster work items for rows with n clicks: (a, b, c0, c1 | first << 16) for
+// each pair a < b, the third mode c split in chunks of 8 (order 3).
+void cluster_items(int n, int order, std::vector<int32_t> &out)
+{
+    for (int b = 1; b < n; ++b)
+        for (int a = 0; a < b; ++a) {
+            if (order < 3 || b == n - 1) {
+                out.insert(out.end(), {a, b, n, n | (1 << 16)});
+                continue;
+            }
+            for (int c0 = b + 1; c0 < n; c0 += 8) {
+                int c1 = std::min(c0 + 8, n);
+                out.insert(out.end(), {a, b, c0, c1 | ((c0 == b + 1 ? 1 : 0) << 16)});
+            }
+        }
+}
+
+template <class T>
+int dev_alloc(gbs_ctx *ctx, T **p, size_t count)
+{
+    if (count == 0) count = 1;
+    if (hipMalloc((void **)p, count * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        return set_err(ctx, GBS_E_NOMEM, "device allocation of " +
+                                             std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gbs_create(gbs_ctx **out, int hip_device, void *hip_stream)
+{
+    if (!out) return GBS_E_INVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return GBS_E_HIP;
+    if (hip_device < 0 || hip_device >= ndev) return GBS_E_INVAL;
+    gbs_ctx *ctx = new (std::nothrow) gbs_ctx();
+    if (!ctx) return GBS_E_NOMEM;
+    ctx->device = hip_device;
+    if (hipSetDevice(hip_device) != hipSuccess) {
+        delete ctx;
+        return GBS_E_HIP;
+    }
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreate(&ctx->stream) != hipSuccess) {
+            delete ctx;
+            return GBS_E_HIP;
+        }
+        ctx->own_stream = true;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
+    if (ctx->num_cu <= 0) ctx->num_cu = 256;
+    *out = ctx;
+    return GBS_OK;
+}
+
+int gbs_destroy(gbs_ctx *ctx)
+{
+    if (!ctx) return GBS_E_INVAL;
+    (void)hipSetDevice(ctx->device);
+    model_release(ctx);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return GBS_OK;
+}
+
+const char *gbs_last_error(const gbs_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void *gbs_stream(gbs_ctx *ctx) { return ctx ? (void *)ctx->stream : nullptr; }
+
+int gbs_set_model(gbs_ctx *ctx, int M, const double *U_re, const double *U_im, const double *r,
+                  const double *eta)
+{
+    if (!ctx) return GBS_E_INVAL;
+    if (M < 1 || M > GBS_MAX_M) return set_err(ctx, GBS_E_INVAL, "M must be in [1, 512]");
+    if (!U_re || !U_im || !r || !eta) return set_err(ctx, GBS_E_INVAL, "NULL model array");
+    for (int i = 0; i < M; ++i) {
+        if (!(r[i] >= 0.0) || !std::isfinite(r[i]))
+            return set_err(ctx, GBS_E_INVAL, "r must be finite and >= 0");
+        if (!(eta[i] >= 0.0 && eta[i] <= 1.0))
+            return set_err(ctx, GBS_E_INVAL, "eta must lie in [0, 1]");
+    }
+    for (long i = 0; i < (long)M * M; ++i)
+        if (!std::isfinite(U_re[i]) || !std::isfinite(U_im[i]))
+            return set_err(ctx, GBS_E_INVAL, "U must be finite");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    int rc = model_alloc(ctx, M);
+    if (rc) return rc;
+    DevModel &m = ctx->model;
+    size_t MM = (size_t)M * M;
+    HIP_TRY(ctx, hipMemcpyAsync(m.params, U_re, MM * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(m.params + MM, U_im, MM * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(m.params + 2 * MM, r, M * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(m.params + 2 * MM + M, eta, M * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    m.from_params = true;
+    return model_build_dev(ctx, nullptr);
+}
+
+int gbs_set_covariance(gbs_ctx *ctx, int M, const double *sigma)
+{
+    if (!ctx) return GBS_E_INVAL;
+    if (M < 1 || M > GBS_MAX_M) return set_err(ctx, GBS_E_INVAL, "M must be in [1, 512]");
+    if (!sigma) return set_err(ctx, GBS_E_INVAL, "sigma is NULL");
+    long D = 2L * M;
+    for (long i = 0; i < D; ++i)
+        for (long j = 0; j < D; ++j) {
+            if (!std::isfinite(sigma[i * D + j])) return set_err(ctx, GBS_E_INVAL, "sigma must be finite");
+            if (sigma[i * D + j] != sigma[j * D + i]) return set_err(ctx, GBS_E_INVAL, "sigma must be symmetric");
+        }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    int rc = model_alloc(ctx, M);
+    if (rc) return rc;
+    double *d_sigma = nullptr;
+    rc = dev_alloc(ctx, &d_sigma, D * D);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(d_sigma, sigma, D * D * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(d_sigma);
+        return set_err(ctx, GBS_E_HIP, hipGetErrorString(e));
+    }
+    ctx->model.from_params = false;
+    rc = model_build_dev(ctx, d_sigma);
+    (void)hipFree(d_sigma);
+    return rc;
+}
+
+int gbs_get_model(gbs_ctx *ctx, double *q_inv, double *logdet_q)
+{
+    if (!ctx) return GBS_E_INVAL;
+    if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
+    long D = 2L * ctx->model.M;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (q_inv)
+        HIP_TRY(ctx, hipMemcpyAsync(q_inv, ctx->model.qi_hi, D * D * sizeof(double),
+                                    hipMemcpyDeviceToHost, ctx->stream));
+    if (logdet_q)
+        HIP_TRY(ctx, hipMemcpyAsync(logdet_q, ctx->model.scal, sizeof(double),
+                                    hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return GBS_OK;
+}
+
+int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int order,
+                    int prec, gbs_plan **out)
+{
+    if (!ctx || !out) return GBS_E_INVAL;
+    *out = nullptr;
+    if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
+    if (order < 1 || order > 3) return set_err(ctx, GBS_E_INVAL, "order must be 1, 2 or 3");
+    if (prec != GBS_PREC_FP64) return set_err(ctx, GBS_E_INVAL, "prec must be GBS_PREC_FP64");
+    int rc = check_csr(ctx, P, offsets, modes, ctx->model.M, GBS_MAX_N_APPROX);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    gbs_plan *pl = new (std::nothrow) gbs_plan();
+    if (!pl) return set_err(ctx, GBS_E_NOMEM, "host allocation failed");
+    pl->ctx = ctx;
+    pl->P = P;
+    pl->order = order;
+    pl->prec = prec;
+    int nnz = P > 0 ? offsets[P] : 0;
+    pl->h_offsets.assign(offsets, offsets + P + 1);
+    if (P == 0) pl->h_offsets.assign(1, 0);
+    pl->h_modes.assign(modes, modes + nnz);
+    pl->h_n.resize(P);
+    std::vector<long long> voff(P);
+    long long vt = 0;
+    for (int p = 0; p < P; ++p) {
+        int n = offsets[p + 1] - offsets[p];
+        pl->h_n[p] = n;
+        pl->max_n = std::max(pl->max_n, n);
+        voff[p] = vt;
+        vt += 4LL * n * n;
+    }
+    pl->v_total = (size_t)vt;
+    // rows by decreasing cost (click count), stable
+    pl->h_perm.resize(P);
+    std::iota(pl->h_perm.begin(), pl->h_perm.end(), 0);
+    std::stable_sort(pl->h_perm.begin(), pl->h_perm.end(),
+                     [&](int a, int b) { return pl->h_n[a] > pl->h_n[b]; });
+    // cluster work lists for every click count up to max_n
+    std::vector<int32_t> citems, coff(2 * (pl->max_n + 1), 0);
+    for (int n = 0; n <= pl->max_n; ++n) {
+        coff[2 * n] = (int32_t)(citems.size() / 4);
+        if (order >= 2) cluster_items(n, order, citems);
+        coff[2 * n + 1] = (int32_t)(citems.size() / 4) - coff[2 * n];
+    }
+    pl->n_cluster_items = (int)(citems.size() / 4);
+    long long max_items = (long long)P * ((GBS_QCAP + GBS_QCHUNK - 1) / GBS_QCHUNK);
+    pl->max_items = (int)max_items;
+    int e = 0;
+    e = e ? e : dev_alloc(ctx, &pl->d_offsets, P + 1);
+    e = e ? e : dev_alloc(ctx, &pl->d_modes, nnz);
+    e = e ? e : dev_alloc(ctx, &pl->d_perm, P);
+    e = e ? e : dev_alloc(ctx, &pl->d_voff, P);
+    e = e ? e : dev_alloc(ctx, &pl->d_alpha, 2 * (size_t)nnz);
+    e = e ? e : dev_alloc(ctx, &pl->d_v, pl->v_total);
+    e = e ? e : dev_alloc(ctx, &pl->d_rows, P);
+    e = e ? e : dev_alloc(ctx, &pl->d_sw, (size_t)P * (order + 1) * GBS_QCAP);
+    e = e ? e : dev_alloc(ctx, &pl->d_items, 2 * (size_t)max_items);
+    e = e ? e : dev_alloc(ctx, &pl->d_counter, 4);
+    e = e ? e : dev_alloc(ctx, &pl->d_cluster_items, citems.size());
+    e = e ? e : dev_alloc(ctx, &pl->d_cluster_off, coff.size());
+    e = e ? e : dev_alloc(ctx, &pl->d_logp, P);
+    e = e ? e : dev_alloc(ctx, &pl->d_status, P);
+    if (e) {
+        plan_free_dev(pl);
+        delete pl;
+        return e;
+    }
+    hipStream_t st = ctx->stream;
+    auto cp = [&](void *dst, const void *src, size_t bytes) {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+    };
+    hipError_t he = hipSuccess;
+    if (he == hipSuccess) he = cp(pl->d_offsets, pl->h_offsets.data(), (P + 1) * sizeof(int32_t));
+    if (he == hipSuccess) he = cp(pl->d_modes, pl->h_modes.data(), nnz * sizeof(int32_t));
+    if (he == hipSuccess) he = cp(pl->d_perm, pl->h_perm.data(), P * sizeof(int32_t));
+    if (he == hipSuccess) he = cp(pl->d_voff, voff.data(), P * sizeof(long long));
+    if (he == hipSuccess) he = cp(pl->d_cluster_items, citems.data(), citems.size() * sizeof(int32_t));
+    if (he == hipSuccess) he = cp(pl->d_cluster_off, coff.data(), coff.size() * sizeof(int32_t));
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) {
+        plan_free_dev(pl);
+        delete pl;
+        return set_err(ctx, GBS_E_HIP, hipGetErrorString(he));
+    }
+    *out = pl;
+    return GBS_OK;
+}
+
+int gbs_plan_destroy(gbs_plan *pl)
+{
+    if (!pl) return GBS_E_INVAL;
+    if (pl->ctx) (void)hipSetDevice(pl->ctx->device);
+    plan_free_dev(pl);
+    delete pl;
+    return GBS_OK;
+}
+
+int gbs_plan_freeze(gbs_plan *pl, int freeze)
+{
+    if (!pl) return GBS_E_INVAL;
+    if (freeze && !pl->have_run)
+        return set_err(pl->ctx, GBS_E_STATE, "plan has not run yet; nothing to freeze");
+    pl->frozen = freeze != 0;
+    return GBS_OK;
+}
+
+int gbs_prob_approx_dev(gbs_ctx *ctx, gbs_plan *pl, double *logp_dev, int32_t *status_dev)
+{
+    if (!ctx || !pl) return GBS_E_INVAL;
+    if (pl->ctx != ctx) return set_err(ctx, GBS_E_STATE, "plan belongs to another context");
+    if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
+    if (pl->P > 0 && !logp_dev) return set_err(ctx, GBS_E_INVAL, "logp_dev is NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    int rc = approx_forward(ctx, pl, logp_dev, status_dev);
+    if (rc == 0) pl->have_run = true;
+    return rc;
+}
+
+int gbs_prob_approx(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int order,
+                    int prec, double *logp, int32_t *status)
+{
+    if (!ctx) return GBS_E_INVAL;
+    if (P > 0 && (!logp || !status)) return set_err(ctx, GBS_E_INVAL, "NULL output array");
+    gbs_plan *pl = nullptr;
+    int rc = gbs_plan_create(ctx, P, offsets, modes, order, prec, &pl);
+    if (rc) return rc;
+    rc = gbs_prob_approx_dev(ctx, pl, pl->d_logp, pl->d_status);
+    if (rc == 0 && P > 0) {
+        hipError_t e = hipMemcpyAsync(logp, pl->d_logp, P * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(status, pl->d_status, P * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) rc = set_err(ctx, GBS_E_HIP, hipGetErrorString(e));
+    }
+    gbs_plan_destroy(pl);
+    if (rc) return rc;
+    for (int p = 0; p < P; ++p)
+        if (status[p] != 0) return GBS_W_PATTERN;
+    return GBS_OK;
+}
+
+int gbs_plan_info(gbs_plan *pl, double *rho, double *rconv, int32_t *K, int32_t *nsectors)
+{
+    if (!pl) return GBS_E_INVAL;
+    gbs_ctx *ctx = pl->ctx;
+    std::vector<RowPlan> rows(pl->P);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (pl->P > 0) {
+        HIP_TRY(ctx, hipMemcpyAsync(rows.data(), pl->d_rows, pl->P * sizeof(RowPlan),
+                                    hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    for (int p = 0; p < pl->P; ++p) {
+        if (rho) rho[p] = rows[p].rho;
+        if (rconv) rconv[p] = rows[p].rconv;
+        if (K) K[p] = rows[p].K;
+        if (nsectors) nsectors[p] = rows[p].nsec;
+    }
+    return GBS_OK;
+}
+
+int gbs_prob_exact(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int prec,
+                   double *p, double *logp, double *kappa, int32_t *status)
+{
+    if (!ctx) return GBS_E_INVAL;
+    if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
+    if (prec != GBS_PREC_FP64) return set_err(ctx, GBS_E_INVAL, "prec must be GBS_PREC_FP64");
+    if (P > 0 && (!p || !status)) return set_err(ctx, GBS_E_INVAL, "NULL output array");
+    int rc = check_csr(ctx, P, offsets, modes, ctx->model.M, GBS_MAX_N_EXACT);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    rc = exact_run(ctx, P, offsets, modes, p, logp, kappa, status);
+    if (rc) return rc;
+    for (int i = 0; i < P; ++i)
+        if (status[i] != 0) return GBS_W_PATTERN;
+    return GBS_OK;
+}
+
+int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, double *logp_dev,
+                 double *grad_r_dev, double *grad_eta_dev, int32_t *status_dev)
+{
+    if (!ctx || !pl) return GBS_E_INVAL;
+    if (pl->ctx != ctx) return set_err(ctx, GBS_E_STATE, "plan belongs to another context");
+    if (!ctx->model.have || !ctx->model.from_params)
+        return set_err(ctx, GBS_E_STATE, "gradient needs a model set by gbs_set_model");
+    if (!dl_dev || !grad_r_dev || !grad_eta_dev) return set_err(ctx, GBS_E_INVAL, "NULL device array");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    double *lp = logp_dev ? logp_dev : pl->d_logp;
+    int32_t *stt = status_dev ? status_dev : pl->d_status;
+    int rc = approx_forward(ctx, pl, lp, stt);
+    if (rc) return rc;
+    pl->have_run = true;
+    return approx_backward(ctx, pl, dl_dev, grad_r_dev, grad_eta_dev);
+}
+
+int gbs_grad(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int order, int prec,
+             const double *dL_dlogp, double *logp, double *grad_r, double *grad_eta, int32_t *status)
+{
+    if (!ctx) return GBS_E_INVAL;
+    if (!dL_dlogp || !grad_r || !grad_eta || (P > 0 && !status))
+        return set_err(ctx, GBS_E_INVAL, "NULL array");
+    if (!ctx->model.have || !ctx->model.from_params)
+        return set_err(ctx, GBS_E_STATE, "gradient needs a model set by gbs_set_model");
+    gbs_plan *pl = nullptr;
+    int rc = gbs_plan_create(ctx, P, offsets, modes, order, prec, &pl);
+    if (rc) return rc;
+    int M = ctx->model.M;
+    rc = dev_alloc(ctx, &pl->d_dl, P > 0 ? P : 1);
+    if (!rc) rc = dev_alloc(ctx, &pl->d_grad, 2 * (size_t)M);
+    hipStream_t st = ctx->stream;
+    if (!rc && P > 0 &&
+        hipMemcpyAsync(pl->d_dl, dL_dlogp, P * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = set_err(ctx, GBS_E_HIP, "copy of dL_dlogp failed");
+    if (!rc) rc = gbs_grad_dev(ctx, pl, pl->d_dl, pl->d_logp, pl->d_grad, pl->d_grad + M, pl->d_status);
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(grad_r, pl->d_grad, M * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(grad_eta, pl->d_grad + M, M * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && logp && P > 0)
+            e = hipMemcpyAsync(logp, pl->d_logp, P * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && P > 0)
+            e = hipMemcpyAsync(status, pl->d_status, P * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = set_err(ctx, GBS_E_HIP, hipGetErrorString(e));
+    }
+    gbs_plan_destroy(pl);
+    if (rc) return rc;
+    for (int i = 0; i < P; ++i)
+        if (status[i] != 0) return GBS_W_PATTERN;
+    return GBS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Internal declarations shared by the kernels and the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "dd.h"
+#include "../../include/gbs.h"
+
+#define GBS_MAX_M 512          // modes supported by the model build
+#define GBS_MAX_N_APPROX 40    // clicks per row on the approximate path
+#define GBS_MAX_N_EXACT 24     // clicks per row on the exact path
+#define GBS_KMAX 2048          // contour size cap
+#define GBS_QCAP (GBS_KMAX / 2 + 1)
+#define GBS_QCHUNK 8           // contour points per work item
+
+struct cplx {
+    double re, im;
+};
+
+// Model held on the device.  Q and Q^{-1} in double-double (hi and lo planes),
+// row-major (2M)^2, xxpp.
+struct DevModel {
+    int M = 0;
+    bool have = false;
+    bool from_params = false;       // set_model (true) or set_covariance (false)
+    double *q_hi = nullptr, *q_lo = nullptr;
+    double *qi_hi = nullptr, *qi_lo = nullptr;
+    double *chol_hi = nullptr, *chol_lo = nullptr;  // Cholesky factor L (lower), then scratch
+    double *params = nullptr;       // U_re, U_im (M^2 each), r, eta (M each) on the device
+    double *scal = nullptr;         // [0] log det Q, [1..2] det(Q)^{-1/2} as dd, [3] flag (non-PD)
+    double *expd = nullptr;         // e^{-2r}, e^{2r} as dd (4M doubles) and sqrt(eta) dd (4M)
+};
+
+struct gbs_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    DevModel model;
+    int num_cu = 0;
+};
+
+// Per-row scalar results of the approximate path's set-up step.
+struct RowPlan {
+    double rho, rconv, log_g_rho, logdet_a, log_pvac, log_rho;
+    int K, status, nsec, pad;
+};
+
+struct gbs_plan {
+    gbs_ctx *ctx = nullptr;
+    int P = 0, order = 0, prec = 0, max_n = 0;
+    bool frozen = false;
+    bool have_run = false;
+    std::vector<int32_t> h_offsets, h_modes, h_perm, h_n;
+    // device
+    int32_t *d_offsets = nullptr, *d_modes = nullptr, *d_perm = nullptr;
+    long long *d_voff = nullptr;          // offset of row p's eigenvectors in d_v
+    double *d_alpha = nullptr;            // 2n per row, offset 2*offsets[p]
+    double *d_v = nullptr;                // (2n)^2 per row
+    RowPlan *d_rows = nullptr;            // P
+    cplx *d_sw = nullptr;                 // (order+1) * QCAP per row: sums over clusters
+    int32_t *d_items = nullptr;           // work items (row, chunk), 2 ints each
+    int32_t *d_counter = nullptr;         // [0] items total, [1] queue head
+    int32_t *d_cluster_items = nullptr;   // per click count n: (a, b, c0, c1) lists
+    int32_t *d_cluster_off = nullptr;     // [n] -> offset, count (2 ints)
+    double *d_logp = nullptr;             // P (scratch when caller passes none)
+    int32_t *d_status = nullptr;          // P
+    size_t v_total = 0;
+    int max_items = 0;
+    int n_cluster_items = 0;
+    // gradient workspace
+    double *d_gsw = nullptr;              // adjoint of the cluster sums (per row, per q)
+    double *d_abar = nullptr;             // per row adjoint of A (2n)^2
+    double *d_qibar = nullptr;            // (2M)^2 adjoint of Q^{-1}
+    double *d_grad = nullptr;             // 2M: grad r, grad eta
+    double *d_dl = nullptr;               // P
+};
+
+// error helpers ------------------------------------------------------------
+int set_err(gbs_ctx *ctx, int code, const std::string &msg);
+#define HIP_TRY(ctx, call)                                                          \
+    do {                                                                            \
+        hipError_t _e = (call);                                                     \
+        if (_e != hipSuccess)                                                       \
+            return set_err((ctx), -4, std::string(#call) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+// kernels' host launchers ----------------------------------------------------
+int model_build(gbs_ctx *ctx, const double *sigma_host);
+int approx_forward(gbs_ctx *ctx, gbs_plan *plan, double *logp_dev, int32_t *status_dev);
+int exact_run(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, double *p,
+              double *logp, double *kappa, int32_t *status);
+int approx_backward(gbs_ctx *ctx, gbs_plan *plan, const double *dl_dev, double *grad_r_dev,
+                    double *grad_eta_dev);

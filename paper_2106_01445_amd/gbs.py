@@ -1,0 +1,218 @@
+"""ctypes binding of libgbs.so (include/gbs.h).  Argument marshalling only: every
+step of the computation runs in the HIP kernels behind the C ABI.
+
+Host-array calls take numpy arrays; the *_dev calls take torch CUDA tensors (or
+raw device pointers) and are ordered on the context's stream.  There is no CPU
+fallback: if the library is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgbs.so")
+
+GBS_OK, GBS_E_INVAL, GBS_E_NOTPD, GBS_E_NOMEM, GBS_E_HIP, GBS_E_STATE, GBS_W_PATTERN = 0, -1, -2, -3, -4, -5, 1
+GBS_PREC_FP64 = 0
+GBS_PS_FIT_NOCONV, GBS_PS_CONTOUR, GBS_PS_PIVOT, GBS_PS_CANCEL = 1, 2, 4, 16
+
+EXPORTS = ["gbs_create", "gbs_destroy", "gbs_last_error", "gbs_set_model", "gbs_set_covariance",
+           "gbs_get_model", "gbs_prob_exact", "gbs_prob_approx", "gbs_plan_create",
+           "gbs_plan_destroy", "gbs_plan_freeze", "gbs_prob_approx_dev", "gbs_grad",
+           "gbs_grad_dev", "gbs_plan_info", "gbs_stream"]
+
+_lib = None
+
+
+class GBSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gbs error {code}: {msg}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Load libgbs.so and declare the C signatures.  Raises if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not built; run paper_2106_01445_amd/build.py "
+                          "(or __graft_entry__.build())")
+    # torch ships its own HIP runtime under the same soname; importing it first
+    # makes libgbs.so bind to that one copy instead of mapping a second runtime.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    vp, ip, dp, i32p = ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "gbs_create": ([pp, ip, vp], ip),
+        "gbs_destroy": ([vp], ip),
+        "gbs_last_error": ([vp], ctypes.c_char_p),
+        "gbs_set_model": ([vp, ip, dp, dp, dp, dp], ip),
+        "gbs_set_covariance": ([vp, ip, dp], ip),
+        "gbs_get_model": ([vp, dp, dp], ip),
+        "gbs_prob_exact": ([vp, ip, i32p, i32p, ip, dp, dp, dp, i32p], ip),
+        "gbs_prob_approx": ([vp, ip, i32p, i32p, ip, ip, dp, i32p], ip),
+        "gbs_plan_create": ([vp, ip, i32p, i32p, ip, ip, pp], ip),
+        "gbs_plan_destroy": ([vp], ip),
+        "gbs_plan_freeze": ([vp, ip], ip),
+        "gbs_prob_approx_dev": ([vp, vp, dp, i32p], ip),
+        "gbs_grad": ([vp, ip, i32p, i32p, ip, ip, dp, dp, dp, dp, i32p], ip),
+        "gbs_grad_dev": ([vp, vp, dp, dp, dp, dp, i32p], ip),
+        "gbs_plan_info": ([vp, dp, dp, i32p, i32p], ip),
+        "gbs_stream": ([vp], vp),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or an int address)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return ctypes.c_void_p(t)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    def __init__(self, ctx: "Context", handle: ctypes.c_void_p, P: int):
+        self.ctx, self.handle, self.P = ctx, handle, P
+
+    def freeze(self, on: bool = True):
+        self.ctx._check(load().gbs_plan_freeze(self.handle, int(on)))
+
+    def info(self):
+        rho, rc = np.zeros(self.P), np.zeros(self.P)
+        K, ns = np.zeros(self.P, np.int32), np.zeros(self.P, np.int32)
+        self.ctx._check(load().gbs_plan_info(self.handle, _ptr(rho), _ptr(rc), _ptr(K), _ptr(ns)))
+        return dict(rho=rho, rconv=rc, K=K, nsectors=ns)
+
+    def close(self):
+        if self.handle:
+            load().gbs_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """One gbs_ctx on a HIP device.  stream: a hipStream_t address (int) or None."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        lib = load()
+        h = ctypes.c_void_p()
+        rc = lib.gbs_create(ctypes.byref(h), device, ctypes.c_void_p(stream) if stream else None)
+        if rc != GBS_OK:
+            raise GBSError(rc, "gbs_create failed (is a GPU visible?)")
+        self.handle = h
+        self.M = None
+
+    def _check(self, rc: int, allow_pattern: bool = True) -> int:
+        if rc < 0:
+            raise GBSError(rc, load().gbs_last_error(self.handle).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().gbs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def stream(self) -> int:
+        return load().gbs_stream(self.handle) or 0
+
+    # model -----------------------------------------------------------------
+    def gbs_set_model(self, U: np.ndarray, r: np.ndarray, eta: np.ndarray):
+        M = U.shape[0]
+        ure, uim = _f64(U.real), _f64(U.imag)
+        self._check(load().gbs_set_model(self.handle, M, _ptr(ure), _ptr(uim), _ptr(_f64(r)),
+                                         _ptr(_f64(eta))))
+        self.M = M
+
+    def gbs_set_covariance(self, sigma: np.ndarray):
+        M = sigma.shape[0] // 2
+        self._check(load().gbs_set_covariance(self.handle, M, _ptr(_f64(sigma))))
+        self.M = M
+
+    def gbs_get_model(self) -> Tuple[np.ndarray, float]:
+        D = 2 * self.M
+        qi = np.zeros((D, D))
+        ld = np.zeros(1)
+        self._check(load().gbs_get_model(self.handle, _ptr(qi), _ptr(ld)))
+        return qi, float(ld[0])
+
+    # probabilities ----------------------------------------------------------
+    def gbs_prob_exact(self, offsets, modes, prec: int = GBS_PREC_FP64):
+        off, mod = _i32(offsets), _i32(modes)
+        P = len(off) - 1
+        p, lp, kap = np.zeros(P), np.zeros(P), np.zeros(P)
+        st = np.zeros(P, np.int32)
+        self._check(load().gbs_prob_exact(self.handle, P, _ptr(off), _ptr(mod), prec, _ptr(p),
+                                          _ptr(lp), _ptr(kap), _ptr(st)))
+        return dict(p=p, logp=lp, kappa=kap, status=st)
+
+    def gbs_prob_approx(self, offsets, modes, order: int, prec: int = GBS_PREC_FP64):
+        off, mod = _i32(offsets), _i32(modes)
+        P = len(off) - 1
+        lp = np.zeros(P)
+        st = np.zeros(P, np.int32)
+        self._check(load().gbs_prob_approx(self.handle, P, _ptr(off), _ptr(mod), order, prec,
+                                           _ptr(lp), _ptr(st)))
+        return dict(logp=lp, status=st)
+
+    def gbs_plan_create(self, offsets, modes, order: int, prec: int = GBS_PREC_FP64) -> Plan:
+        off, mod = _i32(offsets), _i32(modes)
+        h = ctypes.c_void_p()
+        self._check(load().gbs_plan_create(self.handle, len(off) - 1, _ptr(off), _ptr(mod), order,
+                                           prec, ctypes.byref(h)))
+        return Plan(self, h, len(off) - 1)
+
+    def gbs_prob_approx_dev(self, plan: Plan, logp_dev, status_dev=None):
+        return self._check(load().gbs_prob_approx_dev(self.handle, plan.handle, _dptr(logp_dev),
+                                                      _dptr(status_dev)))
+
+    def gbs_grad(self, offsets, modes, order: int, dL_dlogp, prec: int = GBS_PREC_FP64):
+        off, mod = _i32(offsets), _i32(modes)
+        P = len(off) - 1
+        lp = np.zeros(P)
+        st = np.zeros(P, np.int32)
+        gr, ge = np.zeros(self.M), np.zeros(self.M)
+        self._check(load().gbs_grad(self.handle, P, _ptr(off), _ptr(mod), order, prec,
+                                    _ptr(_f64(dL_dlogp)), _ptr(lp), _ptr(gr), _ptr(ge), _ptr(st)))
+        return dict(logp=lp, grad_r=gr, grad_eta=ge, status=st)
+
+    def gbs_grad_dev(self, plan: Plan, dl_dev, logp_dev, grad_r_dev, grad_eta_dev, status_dev=None):
+        return self._check(load().gbs_grad_dev(self.handle, plan.handle, _dptr(dl_dev),
+                                               _dptr(logp_dev), _dptr(grad_r_dev),
+                                               _dptr(grad_eta_dev), _dptr(status_dev)))
