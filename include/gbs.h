@@ -84,6 +84,11 @@ const char *gbs_last_error(const gbs_ctx *ctx);
  * double-double, on the device.  1 <= M <= 512.  Host pointers. */
 int gbs_set_model(gbs_ctx *ctx, int M, const double *U_re, const double *U_im,
                   const double *r, const double *eta);
+/* Stream-ordered model build from device arrays (same layout as
+ * gbs_set_model); no host synchronisation.  A covariance that is not positive
+ * definite is reported per row (status GBS_PS_PIVOT) by the next call. */
+int gbs_set_model_dev(gbs_ctx *ctx, int M, const double *U_re_dev, const double *U_im_dev,
+                      const double *r_dev, const double *eta_dev);
 /* Same from a covariance matrix sigma ((2M)^2, row-major, xxpp, vacuum I/2);
  * sigma + I/2 must be positive definite.  The gradient call needs the model
  * form and returns GBS_E_STATE after gbs_set_covariance. */
@@ -161,6 +166,16 @@ int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *plan, const double *dL_dlogp_dev, doubl
 /* Per-row diagnostics of the last run on a plan (host arrays of length P,
  * each nullable): contour radius, convergence radius, K, sectors fitted. */
 int gbs_plan_info(gbs_plan *plan, double *rho, double *rconv, int32_t *K, int32_t *nsectors);
+
+/* Per-kernel timing.  With on = 1, every later launch on the context is
+ * bracketed by HIP events recorded on the context's stream.  gbs_timing
+ * synchronises the stream, writes the summed milliseconds per kernel group
+ * since the last call into ms[8] and the launch counts into count[8] (0 model
+ * build, 1 row set-up, 2 work-queue build, 3 contour/cluster, 4 DFT and fit,
+ * 5 exact subsets, 6 adjoint of the fit and DFT, 7 adjoint of the clusters
+ * and model), then clears the record.  Either array may be NULL. */
+int gbs_set_timing(gbs_ctx *ctx, int on);
+int gbs_timing(gbs_ctx *ctx, double *ms, int32_t *count);
 
 /* The context's stream (hipStream_t) as void*. */
 void *gbs_stream(gbs_ctx *ctx);

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep(
         rp.status = 0;
         rp.logdet_a = logdetA;
         rp.log_pvac = -0.5 * (logdetQ + logdetA);
-        if (!(amin > 0.0)) {
+        if (!(amin > 0.0) || scal[3] != 0.0) {
             rp.status = GBS_PS_PIVOT;
         } else {
             if (!frozen) {
@@ -725,11 +725,15 @@ int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
     size_t lds_prep = sizeof(double) * 2 * (size_t)(2 * nmax) * (2 * nmax);
     HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_prep, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds_prep));
+    int ts = timer_begin(ctx, TG_PREP);
     hipLaunchKernelGGL(k_prep, dim3(P), dim3(PREP_THREADS), lds_prep, st, m.M, m.qi_hi, m.scal,
                        pl->d_offsets, pl->d_modes, pl->d_perm, pl->d_voff, pl->d_alpha, pl->d_v,
                        pl->d_rows, pl->frozen ? 1 : 0);
+    timer_end(ctx, ts);
+    ts = timer_begin(ctx, TG_ITEMS);
     hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, st, P, pl->d_offsets, pl->d_perm,
                        pl->d_rows, pl->d_items, pl->d_counter);
+    timer_end(ctx, ts);
     size_t lds_c = contour_lds<ORDER>(nmax);
     HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_contour<ORDER>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_c));
@@ -738,15 +742,19 @@ int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
                                                               lds_c));
     if (occ < 1) occ = 1;
     int grid = occ * ctx->num_cu;
+    ts = timer_begin(ctx, TG_CONTOUR);
     hipLaunchKernelGGL(k_contour<ORDER>, dim3(grid), dim3(CONT_THREADS), lds_c, st, nmax,
                        pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_items,
                        pl->d_counter, (const int4 *)pl->d_cluster_items,
                        (const int2 *)pl->d_cluster_off, pl->d_sw);
+    timer_end(ctx, ts);
     size_t lds_f = sizeof(cplx) * (ORDER + 1) * GBS_QCAP + sizeof(double) * 2 * GBS_KMAX;
     HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_dft_fit<ORDER>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f));
+    ts = timer_begin(ctx, TG_FIT);
     hipLaunchKernelGGL(k_dft_fit<ORDER>, dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
                        pl->d_rows, pl->d_sw, logp, status);
+    timer_end(ctx, ts);
     HIP_TRY(ctx, hipGetLastError());
     return 0;
 }

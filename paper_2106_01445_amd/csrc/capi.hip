@@ -12,12 +12,39 @@
 
 int model_alloc(gbs_ctx *ctx, int M);
 void model_release(gbs_ctx *ctx);
-int model_build_dev(gbs_ctx *ctx, const double *sigma_dev);
 
 int set_err(gbs_ctx *ctx, int code, const std::string &msg)
 {
     if (ctx) ctx->err = msg;
     return code;
+}
+
+static hipEvent_t pool_event(gbs_ctx *ctx)
+{
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int timer_begin(gbs_ctx *ctx, int group)
+{
+    if (!ctx->timing) return -1;
+    hipEvent_t a = pool_event(ctx), b = pool_event(ctx);
+    if (!a || !b) return -1;
+    (void)hipEventRecord(a, ctx->stream);
+    ctx->timeline.push_back(TimedLaunch{group, a, b});
+    return (int)ctx->timeline.size() - 1;
+}
+
+void timer_end(gbs_ctx *ctx, int slot)
+{
+    if (slot < 0) return;
+    (void)hipEventRecord(ctx->timeline[slot].b, ctx->stream);
 }
 
 namespace {
@@ -129,6 +156,11 @@ int gbs_destroy(gbs_ctx *ctx)
     if (!ctx) return GBS_E_INVAL;
     (void)hipSetDevice(ctx->device);
     model_release(ctx);
+    for (const TimedLaunch &t : ctx->timeline) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return GBS_OK;
@@ -163,7 +195,56 @@ int gbs_set_model(gbs_ctx *ctx, int M, const double *U_re, const double *U_im, c
     HIP_TRY(ctx, hipMemcpyAsync(m.params + 2 * MM, r, M * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(m.params + 2 * MM + M, eta, M * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     m.from_params = true;
-    return model_build_dev(ctx, nullptr);
+    return model_build_dev(ctx, nullptr, true);
+}
+
+int gbs_set_model_dev(gbs_ctx *ctx, int M, const double *U_re_dev, const double *U_im_dev,
+                      const double *r_dev, const double *eta_dev)
+{
+    if (!ctx) return GBS_E_INVAL;
+    if (M < 1 || M > GBS_MAX_M) return set_err(ctx, GBS_E_INVAL, "M must be in [1, 512]");
+    if (!U_re_dev || !U_im_dev || !r_dev || !eta_dev) return set_err(ctx, GBS_E_INVAL, "NULL model array");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    int rc = model_alloc(ctx, M);
+    if (rc) return rc;
+    DevModel &m = ctx->model;
+    size_t MM = (size_t)M * M;
+    HIP_TRY(ctx, hipMemcpyAsync(m.params, U_re_dev, MM * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(m.params + MM, U_im_dev, MM * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(m.params + 2 * MM, r_dev, M * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(m.params + 2 * MM + M, eta_dev, M * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    m.from_params = true;
+    return model_build_dev(ctx, nullptr, false);
+}
+
+int gbs_set_timing(gbs_ctx *ctx, int on)
+{
+    if (!ctx) return GBS_E_INVAL;
+    ctx->timing = on != 0;
+    return GBS_OK;
+}
+
+int gbs_timing(gbs_ctx *ctx, double *ms, int32_t *count)
+{
+    if (!ctx) return GBS_E_INVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (const TimedLaunch &t : ctx->timeline) {
+        float e = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&e, t.a, t.b));
+        acc[t.group] += e;
+        cnt[t.group] += 1;
+        ctx->event_pool.push_back(t.a);
+        ctx->event_pool.push_back(t.b);
+    }
+    ctx->timeline.clear();
+    for (int i = 0; i < 8; ++i) {
+        if (ms) ms[i] = acc[i];
+        if (count) count[i] = cnt[i];
+    }
+    return GBS_OK;
 }
 
 int gbs_set_covariance(gbs_ctx *ctx, int M, const double *sigma)
@@ -189,7 +270,7 @@ int gbs_set_covariance(gbs_ctx *ctx, int M, const double *sigma)
         return set_err(ctx, GBS_E_HIP, hipGetErrorString(e));
     }
     ctx->model.from_params = false;
-    rc = model_build_dev(ctx, d_sigma);
+    rc = model_build_dev(ctx, d_sigma, true);
     (void)hipFree(d_sigma);
     return rc;
 }

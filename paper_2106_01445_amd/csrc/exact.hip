@@ -370,6 +370,7 @@ int exact_run(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes,
         e = hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_ioff, item_off.data(), (P + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    const int ts = timer_begin(ctx, TG_EXACT);
     if (e == hipSuccess && nitems) {
         hipLaunchKernelGGL(k_exact, dim3(nitems), dim3(64), 0, st, m.M, m.qi_hi, m.qi_lo, d_off,
                            d_modes, (const int2 *)d_items, d_part);
@@ -380,6 +381,7 @@ int exact_run(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes,
                            d_part, m.scal, d_out);
         e = hipGetLastError();
     }
+    timer_end(ctx, ts);
     std::vector<double> out((size_t)P * 4);
     if (e == hipSuccess)
         e = hipMemcpyAsync(out.data(), d_out, out.size() * sizeof(double), hipMemcpyDeviceToHost, st);

@@ -33,6 +33,11 @@ struct DevModel {
     double *expd = nullptr;         // e^{-2r}, e^{2r} as dd (4M doubles) and sqrt(eta) dd (4M)
 };
 
+struct TimedLaunch {
+    int group;
+    hipEvent_t a, b;
+};
+
 struct gbs_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -40,7 +45,16 @@ struct gbs_ctx {
     std::string err;
     DevModel model;
     int num_cu = 0;
+    bool timing = false;
+    std::vector<TimedLaunch> timeline;
+    std::vector<hipEvent_t> event_pool;
 };
+
+// Bracket a group of launches with events when timing is on (no-ops otherwise).
+int timer_begin(gbs_ctx *ctx, int group);
+void timer_end(gbs_ctx *ctx, int slot);
+enum { TG_MODEL = 0, TG_PREP = 1, TG_ITEMS = 2, TG_CONTOUR = 3, TG_FIT = 4, TG_EXACT = 5,
+       TG_ADJ_FIT = 6, TG_ADJ_CLUSTER = 7 };
 
 // Per-row scalar results of the approximate path's set-up step.
 struct RowPlan {
@@ -88,7 +102,7 @@ int set_err(gbs_ctx *ctx, int code, const std::string &msg);
     } while (0)
 
 // kernels' host launchers ----------------------------------------------------
-int model_build(gbs_ctx *ctx, const double *sigma_host);
+int model_build_dev(gbs_ctx *ctx, const double *sigma_dev, bool sync);
 int approx_forward(gbs_ctx *ctx, gbs_plan *plan, double *logp_dev, int32_t *status_dev);
 int exact_run(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, double *p,
               double *logp, double *kappa, int32_t *status);

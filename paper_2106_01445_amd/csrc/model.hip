@@ -229,13 +229,14 @@ void model_release(gbs_ctx *ctx) { free_model(ctx->model); ctx->model.M = 0; }
 
 // Build Q, its factor and inverse.  Parameters must already be in
 // ctx->model.params (U_re, U_im, r, eta) unless sigma_dev is given.
-int model_build_dev(gbs_ctx *ctx, const double *sigma_dev)
+int model_build_dev(gbs_ctx *ctx, const double *sigma_dev, bool sync)
 {
     DevModel &m = ctx->model;
     int M = m.M, D = 2 * M;
     hipStream_t st = ctx->stream;
     const double *ure = m.params, *uim = m.params + (size_t)M * M;
     const double *r = m.params + 2 * (size_t)M * M, *eta = r + M;
+    const int tslot = timer_begin(ctx, TG_MODEL);
     if (!sigma_dev) {
         hipLaunchKernelGGL(k_model_scalars, dim3((M + 63) / 64), dim3(64), 0, st, M, r, eta,
                            m.expd);
@@ -249,7 +250,12 @@ int model_build_dev(gbs_ctx *ctx, const double *sigma_dev)
     hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), 0, st, D, m.chol_hi, m.chol_lo, m.scal);
     hipLaunchKernelGGL(k_chol_inv, dim3(D), dim3(64), 2 * D * sizeof(double), st, D, m.chol_hi,
                        m.chol_lo, m.scal, m.qi_hi, m.qi_lo);
+    timer_end(ctx, tslot);
     HIP_TRY(ctx, hipGetLastError());
+    if (!sync) {
+        m.have = true;  // a non-PD Q is flagged on the device and reported per row
+        return 0;
+    }
     double flag = 0.0;
     HIP_TRY(ctx, hipMemcpyAsync(&flag, m.scal + 3, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));

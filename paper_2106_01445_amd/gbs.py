@@ -20,10 +20,13 @@ GBS_OK, GBS_E_INVAL, GBS_E_NOTPD, GBS_E_NOMEM, GBS_E_HIP, GBS_E_STATE, GBS_W_PAT
 GBS_PREC_FP64 = 0
 GBS_PS_FIT_NOCONV, GBS_PS_CONTOUR, GBS_PS_PIVOT, GBS_PS_CANCEL = 1, 2, 4, 16
 
-EXPORTS = ["gbs_create", "gbs_destroy", "gbs_last_error", "gbs_set_model", "gbs_set_covariance",
-           "gbs_get_model", "gbs_prob_exact", "gbs_prob_approx", "gbs_plan_create",
-           "gbs_plan_destroy", "gbs_plan_freeze", "gbs_prob_approx_dev", "gbs_grad",
-           "gbs_grad_dev", "gbs_plan_info", "gbs_stream"]
+EXPORTS = ["gbs_create", "gbs_destroy", "gbs_last_error", "gbs_set_model", "gbs_set_model_dev",
+           "gbs_set_covariance", "gbs_get_model", "gbs_prob_exact", "gbs_prob_approx",
+           "gbs_plan_create", "gbs_plan_destroy", "gbs_plan_freeze", "gbs_prob_approx_dev",
+           "gbs_grad", "gbs_grad_dev", "gbs_plan_info", "gbs_set_timing", "gbs_timing",
+           "gbs_stream"]
+TIMING_GROUPS = ["model", "row_setup", "work_queue", "contour_clusters", "dft_fit", "exact",
+                 "adjoint_fit_dft", "adjoint_clusters_model"]
 
 _lib = None
 
@@ -53,6 +56,9 @@ def load(path: str = LIB_PATH):
         "gbs_destroy": ([vp], ip),
         "gbs_last_error": ([vp], ctypes.c_char_p),
         "gbs_set_model": ([vp, ip, dp, dp, dp, dp], ip),
+        "gbs_set_model_dev": ([vp, ip, dp, dp, dp, dp], ip),
+        "gbs_set_timing": ([vp, ip], ip),
+        "gbs_timing": ([vp, dp, i32p], ip),
         "gbs_set_covariance": ([vp, ip, dp], ip),
         "gbs_get_model": ([vp, dp, dp], ip),
         "gbs_prob_exact": ([vp, ip, i32p, i32p, ip, dp, dp, dp, i32p], ip),
@@ -159,6 +165,23 @@ class Context:
         self._check(load().gbs_set_model(self.handle, M, _ptr(ure), _ptr(uim), _ptr(_f64(r)),
                                          _ptr(_f64(eta))))
         self.M = M
+
+    def gbs_set_model_dev(self, U_re_dev, U_im_dev, r_dev, eta_dev):
+        """Stream-ordered model build from device tensors (float64, contiguous)."""
+        M = int(r_dev.shape[0])
+        self._check(load().gbs_set_model_dev(self.handle, M, _dptr(U_re_dev), _dptr(U_im_dev),
+                                             _dptr(r_dev), _dptr(eta_dev)))
+        self.M = M
+
+    def gbs_set_timing(self, on: bool = True):
+        self._check(load().gbs_set_timing(self.handle, int(on)))
+
+    def gbs_timing(self):
+        """{group: (total ms, launches)} since the last call (synchronises)."""
+        ms = np.zeros(8)
+        cnt = np.zeros(8, np.int32)
+        self._check(load().gbs_timing(self.handle, _ptr(ms), _ptr(cnt)))
+        return {g: (float(ms[i]), int(cnt[i])) for i, g in enumerate(TIMING_GROUPS)}
 
     def gbs_set_covariance(self, sigma: np.ndarray):
         M = sigma.shape[0] // 2
