@@ -21,7 +21,7 @@
 #include "internal.h"
 
 #define PREP_THREADS 256
-#define CONT_THREADS 256
+#define CONT_THREADS 512
 #define FIT_THREADS 256
 #define FIT_MAXIT 100
 #define FIT_KPT (GBS_KMAX / FIT_THREADS)
@@ -266,6 +266,20 @@ __global__ __launch_bounds__(1024) void k_build_items(int P, const int *__restri
 
 // ---------------------------------------------------------------------------
 // k_contour: cluster sums at contour points.
+//
+// A work item is (row, chunk of GBS_QCHUNK contour points).  The row's
+// eigenvectors stay in LDS for the whole item; G contour points are processed
+// per pass, G the largest power of two <= 8 whose G copies of M(w) fit in LDS
+// next to V.  Per pass: z_k = 1 + w(alpha_k - 1), d_k = 1/z_k and z_k^{-1/2} for
+// every slot; M(w) = V diag(d) V^T as 2x2 mode blocks; then the clusters, with
+// the threads split into G slot groups of whole wavefronts.
+//
+// LDS layout of M(w): the diagonal blocks (a,a) and the blocks (a,b), a < b,
+// column-major (index b(b-1)/2 + a), each of the 3 or 4 entries in its own
+// array.  A lane owns one mode pair (a,b) (pair index = block index) and loops
+// over the third mode c > b; neighbouring lanes own consecutive a of the same
+// b, so every read of the triple loop is either a broadcast (blocks (b,c),
+// (c,c)) or consecutive across lanes (block (a,c)).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ cplx warp_csum(cplx v)
 {
@@ -276,27 +290,63 @@ __device__ __forceinline__ cplx warp_csum(cplx v)
     return v;
 }
 
-struct Blk2 {  // general 2x2 complex block
-    cplx a00, a01, a10, a11;
+// z^{-1/2} on the principal branch, from |z| and the half-angle: with
+// r = |z|, A = (|Re z| + r)/2, sqrt(z) = (sqrt A, Im z/(2 sqrt A)) for Re z >= 0
+// and (|Im z|/(2 sqrt A), sign(Im z) sqrt A) otherwise; 1/sqrt(z) = conj(sqrt z)/r.
+__device__ __forceinline__ cplx crsqrt_p(cplx z)
+{
+    const double s2 = fma(z.re, z.re, z.im * z.im);
+    const double q = rsqrt(s2);          // 1/r
+    const double r = s2 * q;
+    const double A = 0.5 * (fabs(z.re) + r);
+    const double w = rsqrt(A);
+    const double big = A * w, small = 0.5 * fabs(z.im) * w;
+    double sr, si;
+    if (z.re >= 0.0) { sr = big; si = copysign(small, z.im); }
+    else { sr = small; si = copysign(big, z.im); }
+    return cmk(sr * q, -si * q);
+}
+
+constexpr int CONT_MAXG = 8;
+
+__host__ __device__ __forceinline__ int cont_vbytes(int n) { return 8 * (4 * n * n + 2 * n); }
+// per slot: d, z^{-1/2} (2n each), diagonal blocks (3n), off-diagonal (4 n(n-1)/2)
+__host__ __device__ __forceinline__ int cont_mbytes(int n) { return 16 * (2 * n * n + 5 * n); }
+__host__ __device__ __forceinline__ int cont_fixed() { return 16 * (CONT_THREADS / 64) * 4 + 16 * CONT_MAXG; }
+
+struct SlotM {
+    cplx *d, *rz, *d0, *d1, *d2, *o0, *o1, *o2, *o3;
 };
+
+__device__ __forceinline__ SlotM slot_view(cplx *base, int n)
+{
+    const int N = 2 * n, np = n * (n - 1) / 2;
+    SlotM m;
+    m.d = base;
+    m.rz = base + N;
+    m.d0 = base + 2 * N;
+    m.d1 = m.d0 + n;
+    m.d2 = m.d1 + n;
+    m.o0 = m.d2 + n;
+    m.o1 = m.o0 + np;
+    m.o2 = m.o1 + np;
+    m.o3 = m.o2 + np;
+    return m;
+}
 
 template <int ORDER>
 __global__ __launch_bounds__(CONT_THREADS) void k_contour(
-    int nmax, const int *__restrict__ offsets, const long long *__restrict__ voff,
+    int lds_bytes, const int *__restrict__ offsets, const long long *__restrict__ voff,
     const double *__restrict__ alpha, const double *__restrict__ vt,
     const RowPlan *__restrict__ rows, const int *__restrict__ items, int *__restrict__ counter,
-    const int4 *__restrict__ citems, const int2 *__restrict__ coff, cplx *__restrict__ sw)
+    cplx *__restrict__ sw)
 {
     extern __shared__ double sh[];
-    const int NM = 2 * nmax;
-    double *Vt = sh;                                   // NM*NM
-    double *al = Vt + NM * NM;                         // NM
-    cplx *dk = (cplx *)(al + NM);                      // NM
-    cplx *Md = dk + NM;                                // nmax*3
-    cplx *Mo = Md + 3 * nmax;                          // nmax(nmax-1)/2 * 4
     __shared__ int s_item;
-    __shared__ cplx s_red[CONT_THREADS / 64][4];
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6;
+    cplx *red = (cplx *)sh;                                  // [waves][4]
+    cplx *ghat = red + (CONT_THREADS / 64) * 4;              // [CONT_MAXG]
+    double *dyn = (double *)(ghat + CONT_MAXG);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int total = counter[0];
     for (;;) {
         if (tid == 0) s_item = atomicAdd(&counter[1], 1);
@@ -307,134 +357,167 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
         const int p = items[2 * item], ch = items[2 * item + 1];
         const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
         const RowPlan rp = rows[p];
+        double *Vt = dyn;                       // N*N, eigenvector k contiguous
+        double *al = Vt + N * N;                // N
+        cplx *slots = (cplx *)(al + N);         // G x (2n^2 + 5n) complex
+        const int mstride = 2 * n * n + 5 * n;
+        int G = CONT_MAXG;
+        while (G > 1 && cont_fixed() + cont_vbytes(n) + G * cont_mbytes(n) > lds_bytes) G >>= 1;
         const long long vo = voff[p];
-        for (int idx = tid; idx < N * N; idx += nt) Vt[idx] = vt[vo + idx];
-        for (int i = tid; i < N; i += nt) al[i] = alpha[2 * o + i];
+        for (int idx = tid; idx < N * N; idx += CONT_THREADS) Vt[idx] = vt[vo + idx];
+        for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
         const int Q = rp.K / 2 + 1;
         const int q0 = ch * GBS_QCHUNK, q1 = min(q0 + GBS_QCHUNK, Q);
-        const int nblk = n + n * (n - 1) / 2;
-        const int2 cr = coff[n];
+        const int np = n * (n - 1) / 2;
+        const int nblk = n + np;
         __syncthreads();
-        for (int q = q0; q < q1; ++q) {
-            double sn, cs;
-            sincospi(2.0 * (double)q / (double)rp.K, &sn, &cs);
-            const cplx w = cmk(rp.rho * cs, rp.rho * sn);
-            // d_k = 1/(1 + w(alpha_k - 1)); sum of principal logs for G_0(w)
-            cplx lz = cmk(0.0, 0.0);
-            for (int k = tid; k < N; k += nt) {
-                cplx z = cmk(1.0 + w.re * (al[k] - 1.0), w.im * (al[k] - 1.0));
-                dk[k] = crecip(z);
-                lz = cadd(lz, clog_p(z));
+        for (int qb = q0; qb < q1; qb += G) {
+            const int g = min(G, q1 - qb);
+            // contour point of each slot
+            if (tid < g) {
+                double sn, cs;
+                sincospi(2.0 * (double)(qb + tid) / (double)rp.K, &sn, &cs);
+                ghat[tid] = cmk(rp.rho * cs, rp.rho * sn);
             }
-            lz = warp_csum(lz);
-            if (lane == 0) s_red[wid][0] = lz;
             __syncthreads();
-            cplx slz = cmk(0.0, 0.0);
-            for (int i = 0; i < nt / 64; ++i) slz = cadd(slz, s_red[i][0]);
-            // G_0(w)/G_0(rho) = exp(logdet A/2 - sum Log/2 - log G_0(rho))
-            const cplx ghat = cexp_(cmk(0.5 * rp.logdet_a - 0.5 * slz.re - rp.log_g_rho, -0.5 * slz.im));
-            // M(w) as 2x2 mode blocks
-            for (int bi = tid; bi < nblk; bi += nt) {
+            // d_k = 1/z_k and z_k^{-1/2}, z_k = 1 + w(alpha_k - 1); Re z_k > 0 inside
+            // the convergence radius, so the principal root is the branch that is
+            // continuous from w = 0
+            for (int idx = tid; idx < g * N; idx += CONT_THREADS) {
+                const int sl = idx / N, k = idx - sl * N;
+                const cplx w = ghat[sl];
+                const double am1 = al[k] - 1.0;
+                const cplx z = cmk(fma(w.re, am1, 1.0), w.im * am1);
+                const cplx rz = crsqrt_p(z);
+                const SlotM m = slot_view(slots + sl * mstride, n);
+                m.d[k] = cmul(rz, rz);
+                m.rz[k] = rz;
+            }
+            __syncthreads();
+            if (tid < g) {
+                // G_0(w)/G_0(rho) = exp(log det A/2 - log G_0(rho)) prod_k z_k^{-1/2}
+                const SlotM m = slot_view(slots + tid * mstride, n);
+                cplx pr = cmk(exp(0.5 * rp.logdet_a - rp.log_g_rho), 0.0);
+                for (int k = 0; k < N; ++k) pr = cmul(pr, m.rz[k]);
+                ghat[tid] = pr;
+            }
+            // M(w) = V diag(d) V^T: n diagonal blocks, then the blocks (a,b), a < b,
+            // in column-major order (consecutive threads: consecutive a, same b)
+            for (int idx = tid; idx < g * nblk; idx += CONT_THREADS) {
+                const int sl = idx / nblk, bi = idx - sl * nblk;
+                const SlotM m = slot_view(slots + sl * mstride, n);
                 if (bi < n) {
-                    const int a = bi, r0 = a, r1 = n + a;
+                    const int a = bi;
                     cplx m00 = cmk(0, 0), m01 = cmk(0, 0), m11 = cmk(0, 0);
+#pragma unroll 1
                     for (int k = 0; k < N; ++k) {
-                        double v0 = Vt[k * N + r0], v1 = Vt[k * N + r1];
-                        cplx d = dk[k];
-                        double p00 = v0 * v0, p01 = v0 * v1, p11 = v1 * v1;
+                        const double v0 = Vt[k * N + a], v1 = Vt[k * N + n + a];
+                        const cplx d = m.d[k];
+                        const double p00 = v0 * v0, p01 = v0 * v1, p11 = v1 * v1;
                         m00.re = fma(p00, d.re, m00.re); m00.im = fma(p00, d.im, m00.im);
                         m01.re = fma(p01, d.re, m01.re); m01.im = fma(p01, d.im, m01.im);
                         m11.re = fma(p11, d.re, m11.re); m11.im = fma(p11, d.im, m11.im);
                     }
-                    Md[3 * a] = m00; Md[3 * a + 1] = m01; Md[3 * a + 2] = m11;
+                    m.d0[a] = m00; m.d1[a] = m01; m.d2[a] = m11;
                 } else {
-                    int oi = bi - n, a = 0;
-                    while (oi >= n - 1 - a) { oi -= n - 1 - a; ++a; }
-                    const int b = a + 1 + oi;
+                    const int pi = bi - n;
+                    int b = (int)floor(0.5 * (1.0 + sqrt(1.0 + 8.0 * pi)));
+                    while (b * (b - 1) / 2 > pi) --b;
+                    while ((b + 1) * b / 2 <= pi) ++b;
+                    const int a = pi - b * (b - 1) / 2;
                     cplx b00 = cmk(0, 0), b01 = cmk(0, 0), b10 = cmk(0, 0), b11 = cmk(0, 0);
+#pragma unroll 1
                     for (int k = 0; k < N; ++k) {
-                        double va0 = Vt[k * N + a], va1 = Vt[k * N + n + a];
-                        double vb0 = Vt[k * N + b], vb1 = Vt[k * N + n + b];
-                        cplx d = dk[k];
-                        double p00 = va0 * vb0, p01 = va0 * vb1, p10 = va1 * vb0, p11 = va1 * vb1;
+                        const double va0 = Vt[k * N + a], va1 = Vt[k * N + n + a];
+                        const double vb0 = Vt[k * N + b], vb1 = Vt[k * N + n + b];
+                        const cplx d = m.d[k];
+                        const double p00 = va0 * vb0, p01 = va0 * vb1, p10 = va1 * vb0, p11 = va1 * vb1;
                         b00.re = fma(p00, d.re, b00.re); b00.im = fma(p00, d.im, b00.im);
                         b01.re = fma(p01, d.re, b01.re); b01.im = fma(p01, d.im, b01.im);
                         b10.re = fma(p10, d.re, b10.re); b10.im = fma(p10, d.im, b10.im);
                         b11.re = fma(p11, d.re, b11.re); b11.im = fma(p11, d.im, b11.im);
                     }
-                    cplx *dst = Mo + 4 * (bi - n);
-                    dst[0] = b00; dst[1] = b01; dst[2] = b10; dst[3] = b11;
+                    m.o0[pi] = b00; m.o1[pi] = b01; m.o2[pi] = b10; m.o3[pi] = b11;
                 }
             }
             __syncthreads();
-            // cluster sums
+            // clusters: slot groups of SG threads (whole wavefronts)
+            const int SG = CONT_THREADS / G;
+            const int sl = tid / SG, lt = tid - sl * SG;
             cplx s1 = cmk(0, 0), s2 = cmk(0, 0), s3 = cmk(0, 0);
-            for (int a = tid; a < n; a += nt) {
-                cplx a00 = Md[3 * a], a01 = Md[3 * a + 1], a11 = Md[3 * a + 2];
-                cplx det = cfnma(a01, a01, cmul(a00, a11));
-                s1 = cadd(s1, crecip(csqrt_p(det)));
-            }
-            if (ORDER >= 2) {
-                for (int it = tid; it < cr.y; it += nt) {
-                    const int4 e = citems[cr.x + it];
-                    const int a = e.x, b = e.y, c0 = e.z, c1 = e.w & 0xffff, first = e.w >> 16;
-                    const cplx a00 = Md[3 * a], a01 = Md[3 * a + 1], a11 = Md[3 * a + 2];
-                    const cplx *pb = Mo + 4 * (a * (2 * n - a - 1) / 2 + (b - a - 1));
-                    const cplx b00 = pb[0], b01 = pb[1], b10 = pb[2], b11 = pb[3];
-                    const cplx bb00 = Md[3 * b], bb01 = Md[3 * b + 1], bb11 = Md[3 * b + 2];
-                    const cplx deta = cfnma(a01, a01, cmul(a00, a11));
-                    const cplx ideta = crecip(deta);
-                    const cplx ia00 = cmul(a11, ideta), ia11 = cmul(a00, ideta);
-                    const cplx ia01 = cmk(-(a01.re * ideta.re - a01.im * ideta.im),
-                                          -(a01.re * ideta.im + a01.im * ideta.re));
-                    // G = Maa^{-1} Mab
-                    const cplx G00 = cfma(ia00, b00, cmul(ia01, b10));
-                    const cplx G01 = cfma(ia00, b01, cmul(ia01, b11));
-                    const cplx G10 = cfma(ia01, b00, cmul(ia11, b10));
-                    const cplx G11 = cfma(ia01, b01, cmul(ia11, b11));
-                    // Sb = Mbb - Mab^T G
-                    const cplx sb00 = csub(bb00, cfma(b00, G00, cmul(b10, G10)));
-                    const cplx sb01 = csub(bb01, cfma(b00, G01, cmul(b10, G11)));
-                    const cplx sb11 = csub(bb11, cfma(b01, G01, cmul(b11, G11)));
-                    const cplx detb = cfnma(sb01, sb01, cmul(sb00, sb11));
-                    const cplx rab = crecip(cmul(csqrt_p(deta), csqrt_p(detb)));
-                    if (first) s2 = cadd(s2, rab);
-                    if (ORDER >= 3 && c1 > c0) {
-                        const cplx idetb = crecip(detb);
-                        const cplx ib00 = cmul(sb11, idetb), ib11 = cmul(sb00, idetb);
-                        const cplx ib01 = cmk(-(sb01.re * idetb.re - sb01.im * idetb.im),
-                                              -(sb01.re * idetb.im + sb01.im * idetb.re));
-                        // blocks (a,c) and (b,c): packed index off(x) + c - x - 1
-                        const int oac = a * (2 * n - a - 1) / 2 - a - 1;
-                        const int obc = b * (2 * n - b - 1) / 2 - b - 1;
-                        for (int c = c0; c < c1; ++c) {
-                            const cplx *pac = Mo + 4 * (oac + c), *pbc = Mo + 4 * (obc + c);
-                            const cplx x00 = pac[0], x01 = pac[1], x10 = pac[2], x11 = pac[3];
-                            const cplx y00 = pbc[0], y01 = pbc[1], y10 = pbc[2], y11 = pbc[3];
-                            const cplx c00 = Md[3 * c], c01 = Md[3 * c + 1], c11 = Md[3 * c + 2];
-                            // Y = Xb - G^T Xa
-                            const cplx Y00 = csub(y00, cfma(G00, x00, cmul(G10, x10)));
-                            const cplx Y01 = csub(y01, cfma(G00, x01, cmul(G10, x11)));
-                            const cplx Y10 = csub(y10, cfma(G01, x00, cmul(G11, x10)));
-                            const cplx Y11 = csub(y11, cfma(G01, x01, cmul(G11, x11)));
-                            // Za = Maa^{-1} Xa, Wb = Sb^{-1} Y
-                            const cplx Z00 = cfma(ia00, x00, cmul(ia01, x10));
-                            const cplx Z01 = cfma(ia00, x01, cmul(ia01, x11));
-                            const cplx Z10 = cfma(ia01, x00, cmul(ia11, x10));
-                            const cplx Z11 = cfma(ia01, x01, cmul(ia11, x11));
-                            const cplx W00 = cfma(ib00, Y00, cmul(ib01, Y10));
-                            const cplx W01 = cfma(ib00, Y01, cmul(ib01, Y11));
-                            const cplx W10 = cfma(ib01, Y00, cmul(ib11, Y10));
-                            const cplx W11 = cfma(ib01, Y01, cmul(ib11, Y11));
-                            // Sc = Mcc - Xa^T Za - Y^T W
-                            const cplx sc00 = csub(csub(c00, cfma(x00, Z00, cmul(x10, Z10))),
-                                                   cfma(Y00, W00, cmul(Y10, W10)));
-                            const cplx sc01 = csub(csub(c01, cfma(x00, Z01, cmul(x10, Z11))),
-                                                   cfma(Y00, W01, cmul(Y10, W11)));
-                            const cplx sc11 = csub(csub(c11, cfma(x01, Z01, cmul(x11, Z11))),
-                                                   cfma(Y01, W01, cmul(Y11, W11)));
-                            const cplx detc = cfnma(sc01, sc01, cmul(sc00, sc11));
-                            s3 = cadd(s3, cdiv(rab, csqrt_p(detc)));
+            if (sl < g) {
+                const SlotM m = slot_view(slots + sl * mstride, n);
+                for (int a = lt; a < n; a += SG) {
+                    const cplx a00 = m.d0[a], a01 = m.d1[a], a11 = m.d2[a];
+                    s1 = cadd(s1, crsqrt_p(cfnma(a01, a01, cmul(a00, a11))));
+                }
+                if (ORDER >= 2) {
+#pragma unroll 1
+                    for (int pi = lt; pi < np; pi += SG) {
+                        int b = (int)floor(0.5 * (1.0 + sqrt(1.0 + 8.0 * pi)));
+                        while (b * (b - 1) / 2 > pi) --b;
+                        while ((b + 1) * b / 2 <= pi) ++b;
+                        const int a = pi - b * (b - 1) / 2;
+                        const cplx a00 = m.d0[a], a01 = m.d1[a], a11 = m.d2[a];
+                        const cplx b00 = m.o0[pi], b01 = m.o1[pi], b10 = m.o2[pi], b11 = m.o3[pi];
+                        const cplx bb00 = m.d0[b], bb01 = m.d1[b], bb11 = m.d2[b];
+                        const cplx deta = cfnma(a01, a01, cmul(a00, a11));
+                        const cplx ra = crsqrt_p(deta);
+                        const cplx ideta = cmul(ra, ra);
+                        const cplx ia00 = cmul(a11, ideta), ia11 = cmul(a00, ideta);
+                        const cplx ia01 = cmk(-(a01.re * ideta.re - a01.im * ideta.im),
+                                              -(a01.re * ideta.im + a01.im * ideta.re));
+                        // G = Maa^{-1} Mab ; Sb = Mbb - Mab^T G
+                        const cplx G00 = cfma(ia00, b00, cmul(ia01, b10));
+                        const cplx G01 = cfma(ia00, b01, cmul(ia01, b11));
+                        const cplx G10 = cfma(ia01, b00, cmul(ia11, b10));
+                        const cplx G11 = cfma(ia01, b01, cmul(ia11, b11));
+                        const cplx sb00 = csub(bb00, cfma(b00, G00, cmul(b10, G10)));
+                        const cplx sb01 = csub(bb01, cfma(b00, G01, cmul(b10, G11)));
+                        const cplx sb11 = csub(bb11, cfma(b01, G01, cmul(b11, G11)));
+                        const cplx detb = cfnma(sb01, sb01, cmul(sb00, sb11));
+                        const cplx rb = crsqrt_p(detb);
+                        const cplx rab = cmul(ra, rb);
+                        s2 = cadd(s2, rab);
+                        if (ORDER >= 3) {
+                            const cplx idetb = cmul(rb, rb);
+                            const cplx ib00 = cmul(sb11, idetb), ib11 = cmul(sb00, idetb);
+                            const cplx ib01 = cmk(-(sb01.re * idetb.re - sb01.im * idetb.im),
+                                                  -(sb01.re * idetb.im + sb01.im * idetb.re));
+                            cplx s3p = cmk(0, 0);
+#pragma unroll 1
+                            for (int c = b + 1; c < n; ++c) {
+                                const int cb = c * (c - 1) / 2;
+                                const int iac = cb + a, ibc = cb + b;
+                                // Sc = Mcc - Xa^T Maa^{-1} Xa - Y^T Sb^{-1} Y, Y = Xb - G^T Xa,
+                                // evaluated so that each intermediate dies early
+                                const cplx x00 = m.o0[iac], x01 = m.o1[iac], x10 = m.o2[iac], x11 = m.o3[iac];
+                                cplx sc00 = m.d0[c], sc01 = m.d1[c], sc11 = m.d2[c];
+                                {
+                                    const cplx Z00 = cfma(ia00, x00, cmul(ia01, x10));
+                                    const cplx Z10 = cfma(ia01, x00, cmul(ia11, x10));
+                                    sc00 = csub(sc00, cfma(x00, Z00, cmul(x10, Z10)));
+                                    const cplx Z01 = cfma(ia00, x01, cmul(ia01, x11));
+                                    const cplx Z11 = cfma(ia01, x01, cmul(ia11, x11));
+                                    sc01 = csub(sc01, cfma(x00, Z01, cmul(x10, Z11)));
+                                    sc11 = csub(sc11, cfma(x01, Z01, cmul(x11, Z11)));
+                                }
+                                const cplx Y00 = csub(m.o0[ibc], cfma(G00, x00, cmul(G10, x10)));
+                                const cplx Y01 = csub(m.o1[ibc], cfma(G00, x01, cmul(G10, x11)));
+                                const cplx Y10 = csub(m.o2[ibc], cfma(G01, x00, cmul(G11, x10)));
+                                const cplx Y11 = csub(m.o3[ibc], cfma(G01, x01, cmul(G11, x11)));
+                                {
+                                    const cplx W00 = cfma(ib00, Y00, cmul(ib01, Y10));
+                                    const cplx W10 = cfma(ib01, Y00, cmul(ib11, Y10));
+                                    sc00 = csub(sc00, cfma(Y00, W00, cmul(Y10, W10)));
+                                    const cplx W01 = cfma(ib00, Y01, cmul(ib01, Y11));
+                                    const cplx W11 = cfma(ib01, Y01, cmul(ib11, Y11));
+                                    sc01 = csub(sc01, cfma(Y00, W01, cmul(Y10, W11)));
+                                    sc11 = csub(sc11, cfma(Y01, W01, cmul(Y11, W11)));
+                                }
+                                s3p = cadd(s3p, crsqrt_p(cfnma(sc01, sc01, cmul(sc00, sc11))));
+                            }
+                            s3 = cfma(rab, s3p, s3);
                         }
                     }
                 }
@@ -442,19 +525,21 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
             s1 = warp_csum(s1);
             s2 = warp_csum(s2);
             s3 = warp_csum(s3);
-            __syncthreads();
             if (lane == 0) {
-                s_red[wid][1] = s1;
-                s_red[wid][2] = s2;
-                s_red[wid][3] = s3;
+                red[4 * wid + 1] = s1;
+                red[4 * wid + 2] = s2;
+                red[4 * wid + 3] = s3;
             }
             __syncthreads();
-            if (tid <= ORDER) {
-                cplx acc = cmk(0, 0);
-                if (tid == 0) acc = cmk(1.0, 0.0);
-                else
-                    for (int i = 0; i < nt / 64; ++i) acc = cadd(acc, s_red[i][tid]);
-                sw[((long)p * (ORDER + 1) + tid) * GBS_QCAP + q] = cmul(ghat, acc);
+            if (tid < g * (ORDER + 1)) {
+                const int s = tid / (ORDER + 1), t = tid - s * (ORDER + 1);
+                cplx acc = cmk(1.0, 0.0);
+                if (t > 0) {
+                    acc = cmk(0.0, 0.0);
+                    const int w0 = s * (SG / 64), w1 = w0 + SG / 64;
+                    for (int w = w0; w < w1; ++w) acc = cadd(acc, red[4 * w + t]);
+                }
+                sw[((long)p * (ORDER + 1) + t) * GBS_QCAP + qb + s] = cmul(ghat[s], acc);
             }
             __syncthreads();
         }
@@ -587,6 +672,26 @@ __device__ __forceinline__ void lse_add(double &mx, double &s, double v)
     }
 }
 
+// In-place radix-2 FFT of X[0..K) in LDS (forward sign), K a power of two;
+// W[m] = exp(-2 pi i m / K), m < K/2.  Input must already be in bit-reversed
+// order.  All threads of the block take part.
+__device__ void fft_lds(cplx *X, const cplx *W, int K)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int half = 1; half < K; half <<= 1) {
+        const int tstep = K / (2 * half);
+        for (int b = tid; b < K / 2; b += nt) {
+            const int grp = b / half, pos = b - grp * half;
+            const int i = grp * 2 * half + pos, j = i + half;
+            const cplx w = W[pos * tstep];
+            const cplx u = X[i], v = cmul(w, X[j]);
+            X[i] = cadd(u, v);
+            X[j] = csub(u, v);
+        }
+        __syncthreads();
+    }
+}
+
 template <int ORDER>
 __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__ offsets,
                                                          RowPlan *__restrict__ rows,
@@ -614,53 +719,68 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
         return;
     }
     const int K = rp.K, Q = K / 2 + 1, jp = min(ORDER, n - 1);
-    cplx *S = (cplx *)sh;                       // (jp+1) x Q
-    double *ct = (double *)(S + (ORDER + 1) * Q);  // K cos, K sin
-    double *st = ct + K;
-    for (int idx = tid; idx < (jp + 1) * Q; idx += nt) {
-        int t = idx / Q, q = idx - t * Q;
-        S[t * Q + q] = sw[((long)p * (ORDER + 1) + t) * GBS_QCAP + q];
+    int lg = 0;
+    while ((1 << lg) < K) ++lg;
+    cplx *X = (cplx *)sh;            // K
+    cplx *W = X + K;                 // K/2
+    for (int m = tid; m < K / 2; m += nt) {
+        double sn, cs;
+        sincospi(-2.0 * (double)m / (double)K, &sn, &cs);
+        W[m] = cmk(cs, sn);
     }
-    for (int m = tid; m < K; m += nt) sincospi(2.0 * (double)m / (double)K, &st[m], &ct[m]);
-    __syncthreads();
+    // tilted sector moments tau_t[kappa] = Re FFT(S_t(w_q))[kappa] / K, where the
+    // points q > K/2 are the conjugates of K - q (real coefficients)
     double tau[FIT_KPT][ORDER + 1];
     const double invK = 1.0 / K;
-    double tmax = 0.0;
-    for (int j = 0; j < FIT_KPT; ++j) {
-        const int kap = n + tid + nt * j;
-        for (int t = 0; t <= ORDER; ++t) tau[j][t] = 0.0;
-        if (kap >= K) continue;
-        for (int t = 0; t <= jp; ++t) {
-            double acc = S[t * Q].re + ((kap & 1) ? -S[t * Q + Q - 1].re : S[t * Q + Q - 1].re);
-            double acc2 = 0.0;
-            for (int q = 1; q < Q - 1; ++q) {
-                const int mi = (q * kap) & (K - 1);
-                const cplx s = S[t * Q + q];
-                acc2 = fma(s.re, ct[mi], fma(s.im, st[mi], acc2));
-            }
-            tau[j][t] = (acc + 2.0 * acc2) * invK;
+    for (int t = 0; t <= jp; ++t) {
+        const cplx *src = sw + ((long)p * (ORDER + 1) + t) * GBS_QCAP;
+        for (int q = tid; q < K; q += nt) {
+            const cplx v = q < Q ? src[q] : cmk(src[K - q].re, -src[K - q].im);
+            const int rq = (int)(__brev((unsigned)q) >> (32 - lg));
+            X[rq] = v;
         }
-        tmax = fmax(tmax, tau[j][0]);
+        __syncthreads();
+        fft_lds(X, W, K);
+        for (int j = 0; j < FIT_KPT; ++j) {
+            const int kap = n + tid + nt * j;
+            tau[j][t] = kap < K ? X[kap].re * invK : 0.0;
+        }
+        __syncthreads();
     }
+    for (int j = 0; j < FIT_KPT; ++j)
+        for (int t = jp + 1; t <= ORDER; ++t) tau[j][t] = 0.0;
+    double tmax = 0.0;
+    for (int j = 0; j < FIT_KPT; ++j)
+        if (n + tid + nt * j < K) tmax = fmax(tmax, tau[j][0]);
     tmax = block_max(tmax, red);
     const double thr = 1e-14 * tmax;
+    const double binv[3] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
+                            6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0))};
     double fm = -INFINITY, fs = 0.0, um = -INFINITY, us = 0.0;
     int nsec = 0;
-    double binv[3] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
-                      6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0))};
+    double lower = -INFINITY;  // log of a lower bound of the total (after pass 0)
+    // Pass 0 fits each thread's first sector; its block log-sum is a lower
+    // bound L of the estimate.  Later sectors whose upper bound S_0[kappa]
+    // (q <= 1) is below 1e-17 L are skipped: they change the sum by < 1e-14.
     for (int j = 0; j < FIT_KPT; ++j) {
+        if (j == 1) {
+            double mx = block_max(fm, red);
+            double sm = block_sum(fm == -INFINITY ? 0.0 : fs * exp(fm - mx), red);
+            lower = sm > 0.0 ? mx + log(sm) : -INFINITY;
+        }
         const int kap = n + tid + nt * j;
         if (kap >= K) continue;
         const double t0 = tau[j][0];
         if (!(t0 >= thr) || !(t0 > 0.0)) continue;
         const double lw = log(t0) + rp.log_g_rho - kap * rp.log_rho;
+        if (lw < lower + log(1e-17)) continue;
         double m[3] = {0, 0, 0};
         for (int t = 1; t <= jp; ++t) m[t - 1] = tau[j][t] / t0 * binv[t - 1];
         // Fit with the longest feasible prefix of the moments (0 < m_t < 1,
         // decreasing in t, since 0 <= phi_{t+1} <= phi_t <= 1).  A moment whose
-        // true value lies below the DFT's rounding floor can come out infeasible;
-        // it is then dropped, and so is the next one if the fit fails.  With
-        // m_1 <= 0 every clicked mode fires: q(n) = 1.
+        // true value lies below the transform's rounding floor can come out
+        // infeasible; it is then dropped, and so is the next one if the fit
+        // fails.  With m_1 <= 0 every clicked mode fires: q(n) = 1.
         int jr = 0;
         for (int t = 1; t <= jp; ++t) {
             if (m[t - 1] > 0.0 && m[t - 1] < 1.0 && (t == 1 || m[t - 1] < m[t - 2])) jr = t;
@@ -688,9 +808,9 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
     }
     // block log-sum-exp of the fitted and the unresolved sectors
     double fmx = block_max(fm, red);
-    double fsum = block_sum(fs * (fm == -INFINITY ? 0.0 : exp(fm - fmx)), red);
+    double fsum = block_sum(fm == -INFINITY ? 0.0 : fs * exp(fm - fmx), red);
     double umx = block_max(um, red2);
-    double usum = block_sum(us * (um == -INFINITY ? 0.0 : exp(um - umx)), red2);
+    double usum = block_sum(um == -INFINITY ? 0.0 : us * exp(um - umx), red2);
     double ns = block_sum((double)nsec, red);
     if (tid == 0) {
         double tot = fmx + log(fsum);
@@ -704,16 +824,8 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
         if (!(fsum > 0.0)) out = -INFINITY;
         logp[p] = out;
         if (status) status[p] = stt;
-        rp.nsec = (int)ns;
-        rows[p].nsec = rp.nsec;
+        rows[p].nsec = (int)ns;
     }
-}
-
-template <int ORDER>
-size_t contour_lds(int nmax)
-{
-    int NM = 2 * nmax;
-    return sizeof(double) * ((size_t)NM * NM + NM) + sizeof(cplx) * (NM + 3 * nmax + 2 * nmax * (nmax - 1));
 }
 
 template <int ORDER>
@@ -734,21 +846,28 @@ int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
     hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, st, P, pl->d_offsets, pl->d_perm,
                        pl->d_rows, pl->d_items, pl->d_counter);
     timer_end(ctx, ts);
-    size_t lds_c = contour_lds<ORDER>(nmax);
+    // LDS: the whole 160 KB when the largest row needs it, else enough for
+    // eight contour points of the largest row (two workgroups may then share a CU)
+    hipFuncAttributes fa;
+    HIP_TRY(ctx, hipFuncGetAttributes(&fa, (const void *)k_contour<ORDER>));
+    const int lds_cap = ctx->lds_per_block - (int)fa.sharedSizeBytes;
+    int lds_c = cont_fixed() + cont_vbytes(nmax) + CONT_MAXG * cont_mbytes(nmax);
+    if (lds_c > lds_cap) lds_c = lds_cap;
+    if (cont_fixed() + cont_vbytes(nmax) + cont_mbytes(nmax) > lds_c)
+        return set_err(ctx, GBS_E_INVAL, "row too large for the contour kernel's LDS");
     HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_contour<ORDER>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_c));
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds_c));
     int occ = 0;
     HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_contour<ORDER>, CONT_THREADS,
                                                               lds_c));
     if (occ < 1) occ = 1;
     int grid = occ * ctx->num_cu;
     ts = timer_begin(ctx, TG_CONTOUR);
-    hipLaunchKernelGGL(k_contour<ORDER>, dim3(grid), dim3(CONT_THREADS), lds_c, st, nmax,
+    hipLaunchKernelGGL(k_contour<ORDER>, dim3(grid), dim3(CONT_THREADS), lds_c, st, lds_c,
                        pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_items,
-                       pl->d_counter, (const int4 *)pl->d_cluster_items,
-                       (const int2 *)pl->d_cluster_off, pl->d_sw);
+                       pl->d_counter, pl->d_sw);
     timer_end(ctx, ts);
-    size_t lds_f = sizeof(cplx) * (ORDER + 1) * GBS_QCAP + sizeof(double) * 2 * GBS_KMAX;
+    size_t lds_f = sizeof(cplx) * (GBS_KMAX + GBS_KMAX / 2);
     HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_dft_fit<ORDER>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f));
     ts = timer_begin(ctx, TG_FIT);

@@ -145,7 +145,14 @@ int gbs_create(gbs_ctx **out, int hip_device, void *hip_stream)
         ctx->own_stream = true;
     }
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) {
+        ctx->num_cu = prop.multiProcessorCount;
+        ctx->lds_per_block = (int)prop.sharedMemPerBlock;
+    }
+    int optin = 0;
+    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, hip_device) == hipSuccess &&
+        optin > ctx->lds_per_block)
+        ctx->lds_per_block = optin;
     if (ctx->num_cu <= 0) ctx->num_cu = 256;
     *out = ctx;
     return GBS_OK;

@@ -45,6 +45,7 @@ struct gbs_ctx {
     std::string err;
     DevModel model;
     int num_cu = 0;
+    int lds_per_block = 65536;  // largest LDS allocation of one workgroup (bytes)
     bool timing = false;
     std::vector<TimedLaunch> timeline;
     std::vector<hipEvent_t> event_pool;
