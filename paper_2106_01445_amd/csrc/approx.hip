@@ -17,44 +17,10 @@
 //                  the results, times G_0(w)/G_0(rho), go to HBM
 //   k_dft_fit      one workgroup per row: sector moments by a direct DFT over the
 //                  contour, one max-entropy fit per sector, log-sum over sectors
-#include "cplx.h"
-#include "internal.h"
+#include "contour_common.h"
 
-#define PREP_THREADS 256
-#define CONT_THREADS 512
-#define FIT_THREADS 256
-#define FIT_MAXIT 100
-#define FIT_KPT (GBS_KMAX / FIT_THREADS)
 
 namespace {
-
-__device__ double block_sum(double v, double *red)
-{
-    const int tid = threadIdx.x;
-    red[tid] = v;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
-        __syncthreads();
-    }
-    double r = red[0];
-    __syncthreads();
-    return r;
-}
-
-__device__ double block_max(double v, double *red)
-{
-    const int tid = threadIdx.x;
-    red[tid] = v;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
-        __syncthreads();
-    }
-    double r = red[0];
-    __syncthreads();
-    return r;
-}
 
 // ---------------------------------------------------------------------------
 // k_prep: gather, eigen-decompose, plan.
@@ -281,59 +247,6 @@ __global__ __launch_bounds__(1024) void k_build_items(int P, const int *__restri
 // b, so every read of the triple loop is either a broadcast (blocks (b,c),
 // (c,c)) or consecutive across lanes (block (a,c)).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ cplx warp_csum(cplx v)
-{
-    for (int m = 32; m > 0; m >>= 1) {
-        v.re += __shfl_xor(v.re, m);
-        v.im += __shfl_xor(v.im, m);
-    }
-    return v;
-}
-
-// z^{-1/2} on the principal branch, from |z| and the half-angle: with
-// r = |z|, A = (|Re z| + r)/2, sqrt(z) = (sqrt A, Im z/(2 sqrt A)) for Re z >= 0
-// and (|Im z|/(2 sqrt A), sign(Im z) sqrt A) otherwise; 1/sqrt(z) = conj(sqrt z)/r.
-__device__ __forceinline__ cplx crsqrt_p(cplx z)
-{
-    const double s2 = fma(z.re, z.re, z.im * z.im);
-    const double q = rsqrt(s2);          // 1/r
-    const double r = s2 * q;
-    const double A = 0.5 * (fabs(z.re) + r);
-    const double w = rsqrt(A);
-    const double big = A * w, small = 0.5 * fabs(z.im) * w;
-    double sr, si;
-    if (z.re >= 0.0) { sr = big; si = copysign(small, z.im); }
-    else { sr = small; si = copysign(big, z.im); }
-    return cmk(sr * q, -si * q);
-}
-
-constexpr int CONT_MAXG = 8;
-
-__host__ __device__ __forceinline__ int cont_vbytes(int n) { return 8 * (4 * n * n + 2 * n); }
-// per slot: d, z^{-1/2} (2n each), diagonal blocks (3n), off-diagonal (4 n(n-1)/2)
-__host__ __device__ __forceinline__ int cont_mbytes(int n) { return 16 * (2 * n * n + 5 * n); }
-__host__ __device__ __forceinline__ int cont_fixed() { return 16 * (CONT_THREADS / 64) * 4 + 16 * CONT_MAXG; }
-
-struct SlotM {
-    cplx *d, *rz, *d0, *d1, *d2, *o0, *o1, *o2, *o3;
-};
-
-__device__ __forceinline__ SlotM slot_view(cplx *base, int n)
-{
-    const int N = 2 * n, np = n * (n - 1) / 2;
-    SlotM m;
-    m.d = base;
-    m.rz = base + N;
-    m.d0 = base + 2 * N;
-    m.d1 = m.d0 + n;
-    m.d2 = m.d1 + n;
-    m.o0 = m.d2 + n;
-    m.o1 = m.o0 + np;
-    m.o2 = m.o1 + np;
-    m.o3 = m.o2 + np;
-    return m;
-}
-
 template <int ORDER>
 __global__ __launch_bounds__(CONT_THREADS) void k_contour(
     int lds_bytes, const int *__restrict__ offsets, const long long *__restrict__ voff,
@@ -549,149 +462,6 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
 // ---------------------------------------------------------------------------
 // k_dft_fit: sector moments, fits, log-sum.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void fit_eval(int n, int jp, const double *ib, const double *c,
-                                         double *lse, double *E, double *E2)
-{
-    double zmax = -1e300;
-    for (int v = 0; v < n; ++v) {
-        double f1 = v * ib[0], f2 = 0.5 * v * (v - 1) * ib[1], f3 = v * (v - 1.0) * (v - 2.0) / 6.0 * ib[2];
-        double z = -(c[0] * f1 + (jp > 1 ? c[1] * f2 : 0.0) + (jp > 2 ? c[2] * f3 : 0.0));
-        zmax = fmax(zmax, z);
-    }
-    double s = 0.0, e[3] = {0, 0, 0}, e2[6] = {0, 0, 0, 0, 0, 0};
-    for (int v = 0; v < n; ++v) {
-        double f[3] = {v * ib[0], 0.5 * v * (v - 1) * ib[1], v * (v - 1.0) * (v - 2.0) / 6.0 * ib[2]};
-        double z = -(c[0] * f[0] + (jp > 1 ? c[1] * f[1] : 0.0) + (jp > 2 ? c[2] * f[2] : 0.0));
-        double wgt = exp(z - zmax);
-        s += wgt;
-        if (E) {
-            for (int t = 0; t < jp; ++t) e[t] += wgt * f[t];
-            int k = 0;
-            for (int t = 0; t < jp; ++t)
-                for (int u = t; u < jp; ++u) e2[k++] += wgt * f[t] * f[u];
-        }
-    }
-    *lse = zmax + log(s);
-    if (E) {
-        for (int t = 0; t < 3; ++t) E[t] = e[t] / s;
-        for (int k = 0; k < 6; ++k) E2[k] = e2[k] / s;
-    }
-}
-
-// Max-entropy fit on n' = 1..n (v = n - n' empty modes) of the jp moments m[];
-// returns 0 and log q(n) on success.
-__device__ int fit_last_point(int n, int jp, const double *m, double *logq)
-{
-    double ib[3] = {0, 0, 0};
-    ib[0] = 1.0 / (n - 1.0);
-    if (jp > 1) ib[1] = 2.0 / ((n - 1.0) * (n - 2.0));
-    if (jp > 2) ib[2] = 6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0));
-    double c[3] = {0, 0, 0};
-    for (int it = 0; it <= FIT_MAXIT; ++it) {
-        double lse, E[3], E2[6];
-        fit_eval(n, jp, ib, c, &lse, E, E2);
-        double g[3] = {0, 0, 0};
-        bool conv = true;
-        for (int t = 0; t < jp; ++t) {
-            g[t] = m[t] - E[t];
-            if (!(fabs(g[t]) <= 1e-15 + 1e-12 * fabs(m[t]))) conv = false;
-        }
-        // Hessian = covariance of phi, damped by 1e-14 of its trace
-        double Hm[3][3];
-        int k = 0;
-        for (int t = 0; t < jp; ++t)
-            for (int u = t; u < jp; ++u) {
-                Hm[t][u] = Hm[u][t] = E2[k++] - E[t] * E[u];
-            }
-        double tr = 0.0;
-        for (int t = 0; t < jp; ++t) tr += Hm[t][t];
-        for (int t = 0; t < jp; ++t) Hm[t][t] += 1e-14 * tr;
-        // Cholesky solve H x = -g
-        double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        bool ok = tr > 0.0;
-        for (int j = 0; j < jp && ok; ++j) {
-            double d = Hm[j][j];
-            for (int l = 0; l < j; ++l) d -= L[j][l] * L[j][l];
-            if (!(d > 0.0)) { ok = false; break; }
-            L[j][j] = sqrt(d);
-            for (int i = j + 1; i < jp; ++i) {
-                double s = Hm[i][j];
-                for (int l = 0; l < j; ++l) s -= L[i][l] * L[j][l];
-                L[i][j] = s / L[j][j];
-            }
-        }
-        if (!ok) return 1;
-        double y[3], x[3];
-        for (int i = 0; i < jp; ++i) {
-            double s = -g[i];
-            for (int l = 0; l < i; ++l) s -= L[i][l] * y[l];
-            y[i] = s / L[i][i];
-        }
-        for (int i = jp - 1; i >= 0; --i) {
-            double s = y[i];
-            for (int l = i + 1; l < jp; ++l) s -= L[l][i] * x[l];
-            x[i] = s / L[i][i];
-        }
-        if (conv) {
-            double cn[3] = {c[0] + x[0], c[1] + (jp > 1 ? x[1] : 0.0), c[2] + (jp > 2 ? x[2] : 0.0)};
-            double l2;
-            fit_eval(n, jp, ib, cn, &l2, nullptr, nullptr);
-            *logq = -l2;
-            return 0;
-        }
-        double L0 = lse, slope = 0.0;
-        for (int t = 0; t < jp; ++t) {
-            L0 += c[t] * m[t];
-            slope += g[t] * x[t];
-        }
-        double st = 1.0;
-        if (-slope > 1e-13 * fmax(1.0, fabs(L0))) {
-            while (st > 1e-12) {
-                double cn[3] = {c[0] + st * x[0], c[1] + (jp > 1 ? st * x[1] : 0.0),
-                                c[2] + (jp > 2 ? st * x[2] : 0.0)};
-                double l2;
-                fit_eval(n, jp, ib, cn, &l2, nullptr, nullptr);
-                for (int t = 0; t < jp; ++t) l2 += cn[t] * m[t];
-                if (l2 <= L0 + 1e-4 * st * slope) break;
-                st *= 0.5;
-            }
-        }
-        for (int t = 0; t < jp; ++t) c[t] += st * x[t];
-    }
-    return 1;
-}
-
-__device__ __forceinline__ void lse_add(double &mx, double &s, double v)
-{
-    if (v == -INFINITY) return;
-    if (v > mx) {
-        s = s * exp(mx - v) + 1.0;
-        mx = v;
-    } else {
-        s += exp(v - mx);
-    }
-}
-
-// In-place radix-2 FFT of X[0..K) in LDS (forward sign), K a power of two;
-// W[m] = exp(-2 pi i m / K), m < K/2.  Input must already be in bit-reversed
-// order.  All threads of the block take part.
-__device__ void fft_lds(cplx *X, const cplx *W, int K)
-{
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int half = 1; half < K; half <<= 1) {
-        const int tstep = K / (2 * half);
-        for (int b = tid; b < K / 2; b += nt) {
-            const int grp = b / half, pos = b - grp * half;
-            const int i = grp * 2 * half + pos, j = i + half;
-            const cplx w = W[pos * tstep];
-            const cplx u = X[i], v = cmul(w, X[j]);
-            X[i] = cadd(u, v);
-            X[j] = csub(u, v);
-        }
-        __syncthreads();
-    }
-}
-
 template <int ORDER>
 __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__ offsets,
                                                          RowPlan *__restrict__ rows,
@@ -754,8 +524,6 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
         if (n + tid + nt * j < K) tmax = fmax(tmax, tau[j][0]);
     tmax = block_max(tmax, red);
     const double thr = 1e-14 * tmax;
-    const double binv[3] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
-                            6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0))};
     double fm = -INFINITY, fs = 0.0, um = -INFINITY, us = 0.0;
     int nsec = 0;
     double lower = -INFINITY;  // log of a lower bound of the total (after pass 0)
@@ -774,31 +542,9 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
         if (!(t0 >= thr) || !(t0 > 0.0)) continue;
         const double lw = log(t0) + rp.log_g_rho - kap * rp.log_rho;
         if (lw < lower + log(1e-17)) continue;
-        double m[3] = {0, 0, 0};
-        for (int t = 1; t <= jp; ++t) m[t - 1] = tau[j][t] / t0 * binv[t - 1];
-        // Fit with the longest feasible prefix of the moments (0 < m_t < 1,
-        // decreasing in t, since 0 <= phi_{t+1} <= phi_t <= 1).  A moment whose
-        // true value lies below the transform's rounding floor can come out
-        // infeasible; it is then dropped, and so is the next one if the fit
-        // fails.  With m_1 <= 0 every clicked mode fires: q(n) = 1.
-        int jr = 0;
-        for (int t = 1; t <= jp; ++t) {
-            if (m[t - 1] > 0.0 && m[t - 1] < 1.0 && (t == 1 || m[t - 1] < m[t - 2])) jr = t;
-            else break;
-        }
         double lq = 0.0;
-        int bad = 0;
-        if (jp > 0) {
-            bad = 1;
-            while (jr >= 1 && bad) {
-                bad = fit_last_point(n, jr, m, &lq);
-                if (bad) --jr;
-            }
-            if (jr == 0) {
-                bad = m[0] <= 0.0 ? 0 : 1;
-                lq = 0.0;
-            }
-        }
+        int jr = 0;
+        const int bad = fit_sector(n, jp, tau[j], &lq, &jr, nullptr, nullptr);
         if (bad) {
             lse_add(um, us, lw);
         } else {

@@ -83,7 +83,8 @@ void plan_free_dev(gbs_plan *pl)
     void *ptrs[] = {pl->d_offsets, pl->d_modes, pl->d_perm, pl->d_voff, pl->d_alpha,
                     pl->d_v, pl->d_rows, pl->d_sw, pl->d_items, pl->d_counter,
                     pl->d_cluster_items, pl->d_cluster_off, pl->d_logp, pl->d_status,
-                    pl->d_gsw, pl->d_abar, pl->d_qibar, pl->d_grad, pl->d_dl};
+                    pl->d_asw, pl->d_aitems, pl->d_roff, pl->d_ritem0, pl->d_rscr,
+                    pl->d_abar, pl->d_qibar, pl->d_qitmp, pl->d_pos, pl->d_grad, pl->d_dl};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -118,6 +119,42 @@ int dev_alloc(gbs_ctx *ctx, T **p, size_t count)
 }
 
 }  // namespace
+
+// Gradient workspace of a plan, allocated on first use.
+int adj_workspace(gbs_ctx *ctx, gbs_plan *pl)
+{
+    if (pl->have_adj) return 0;
+    const int P = pl->P, M = ctx->model.M, order = pl->order;
+    const int chunks = (GBS_QCAP + 63) / 64;
+    size_t rtot = 0;
+    for (int p = 0; p < P; ++p) {
+        const size_t N = 2 * (size_t)pl->h_n[p];
+        rtot += chunks * (N * (N + 1) / 2);
+    }
+    std::vector<int16_t> pos((size_t)P * M, (int16_t)-1);
+    for (int p = 0; p < P; ++p)
+        for (int i = pl->h_offsets[p]; i < pl->h_offsets[p + 1]; ++i)
+            pos[(size_t)p * M + pl->h_modes[i]] = (int16_t)(i - pl->h_offsets[p]);
+    const size_t D = 2 * (size_t)M;
+    int e = 0;
+    e = e ? e : dev_alloc(ctx, &pl->d_asw, (size_t)P * (order + 1) * GBS_QCAP);
+    e = e ? e : dev_alloc(ctx, &pl->d_aitems, 2 * (size_t)P * chunks);
+    e = e ? e : dev_alloc(ctx, &pl->d_roff, (size_t)P * chunks);
+    e = e ? e : dev_alloc(ctx, &pl->d_ritem0, (size_t)P);
+    e = e ? e : dev_alloc(ctx, &pl->d_rscr, rtot);
+    e = e ? e : dev_alloc(ctx, &pl->d_abar, pl->v_total);
+    e = e ? e : dev_alloc(ctx, &pl->d_qibar, D * D);
+    e = e ? e : dev_alloc(ctx, &pl->d_qitmp, D * D);
+    e = e ? e : dev_alloc(ctx, &pl->d_pos, pos.size());
+    if (!pl->d_grad) e = e ? e : dev_alloc(ctx, &pl->d_grad, D);
+    if (e) return e;
+    if (!pos.empty())
+        HIP_TRY(ctx, hipMemcpyAsync(pl->d_pos, pos.data(), pos.size() * sizeof(int16_t),
+                                    hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    pl->have_adj = true;
+    return 0;
+}
 
 extern "C" {
 
@@ -490,7 +527,7 @@ int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, double *logp_
     int rc = approx_forward(ctx, pl, lp, stt);
     if (rc) return rc;
     pl->have_run = true;
-    return approx_backward(ctx, pl, dl_dev, grad_r_dev, grad_eta_dev);
+    return approx_backward(ctx, pl, dl_dev, stt, grad_r_dev, grad_eta_dev);
 }
 
 int gbs_grad(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int order, int prec,

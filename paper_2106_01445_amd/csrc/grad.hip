@@ -1,5 +1,856 @@
-#include "internal.h"
-int approx_backward(gbs_ctx *ctx, gbs_plan *, const double *, double *, double *)
+// Adjoint of the order-j estimate: gradient of L = sum_p w_p log p_hat_p with
+// respect to the squeezing parameters r and the transmissions eta, with the
+// contour radius rho, the contour size K, the sector set and the number of
+// moments each sector fit uses held at their forward values.
+//
+// Every determinant enters through d log det X = tr(X^{-1} dX).  With
+// N(w) = (1-w)I + wA, M(w) = N^{-1} and dM = -w M dA M, the forward quantities
+//   S_t(w) = g(w) C_t(w),  g(w) = G_0(w)/G_0(rho),  C_t = sum_{|T|=t} det(M_TT)^{-1/2}
+// give, for a cotangent alpha_t(w) (dL = Re sum alpha dS),
+//   dL = Re[ (w/2) tr(M Z M dA) - (w/2) beta tr(M dA) + (rho/2) beta tr(M(rho) dA) ]
+// with gamma_t = alpha_t g, Z = sum_T gamma_|T| det(M_TT)^{-1/2} E_T M_TT^{-1} E_T^T
+// and beta = sum_t gamma_t C_t.  In A's eigenbasis (A = V diag(alpha) V^T,
+// M = V diag(d) V^T) this is A_bar = V R V^T with
+//   R += Re[(w/2) d_i d_j (V^T Z V)_ij] + delta_ij Re[beta (rho dr_i - w d_i)/2],
+// dr_i = 1/(1 + rho(alpha_i - 1)).  Kernels:
+//   k_adj_fit      per row: the sector transform and fits again; the log-sum and
+//                  each fit differentiated (implicitly: d log q / dm = -H^{-1} m,
+//                  H the covariance of the fitted basis); the sector cotangents
+//                  pushed back through the FFT to alpha_t(w_q)
+//   k_adj_contour  per (row, 64 contour points): M(w) and the clusters again,
+//                  Z(w) by LDS atomics, V^T Z V in column panels, R in registers
+//   k_adj_reduce   per row: sum of the items' R in a fixed order, the
+//                  contour-independent terms, A_bar = V R V^T
+//   k_adj_scatter  adjoint of Q^{-1}: Psi[u][v] = sum_p A_bar_p at (u, v)
+//   k_adj_model    Q_bar = -(sum w)/2 Q^{-1} - Q^{-1} Psi Q^{-1}, then sigma_bar,
+//                  and the chain to r and eta through the model build
+#include "contour_common.h"
+
+#define ADJ_QCHUNK 64
+#define ADJ_MAXOWN 8   // upper-triangle entries of R per thread: (2n)(2n+1)/2 <= 8 * 512
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// k_adj_fit
+// ---------------------------------------------------------------------------
+template <int ORDER>
+__global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__ offsets,
+                                                         const RowPlan *__restrict__ rows,
+                                                         const cplx *__restrict__ sw,
+                                                         const double *__restrict__ dl,
+                                                         cplx *__restrict__ asw)
 {
-    return set_err(ctx, -1, "gradient not built yet");
+    extern __shared__ double sh[];
+    __shared__ double red[FIT_THREADS];
+    const int p = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int n = offsets[p + 1] - offsets[p];
+    const RowPlan rp = rows[p];
+    const double wp = dl[p];
+    if (n == 0 || rp.status != 0 || wp == 0.0 || !isfinite(wp)) {
+        for (int i = tid; i < (ORDER + 1) * GBS_QCAP; i += nt)
+            asw[(long)p * (ORDER + 1) * GBS_QCAP + i] = cmk(0.0, 0.0);
+        return;
+    }
+    const int K = rp.K, Q = K / 2 + 1, jp = min(ORDER, n - 1);
+    int lg = 0;
+    while ((1 << lg) < K) ++lg;
+    cplx *X = (cplx *)sh;
+    cplx *W = X + K;
+    for (int m = tid; m < K / 2; m += nt) {
+        double sn, cs;
+        sincospi(-2.0 * (double)m / (double)K, &sn, &cs);
+        W[m] = cmk(cs, sn);
+    }
+    double tau[FIT_KPT][ORDER + 1];
+    const double invK = 1.0 / K;
+    for (int t = 0; t <= jp; ++t) {
+        const cplx *src = sw + ((long)p * (ORDER + 1) + t) * GBS_QCAP;
+        for (int q = tid; q < K; q += nt) {
+            const cplx v = q < Q ? src[q] : cmk(src[K - q].re, -src[K - q].im);
+            X[(int)(__brev((unsigned)q) >> (32 - lg))] = v;
+        }
+        __syncthreads();
+        fft_lds(X, W, K);
+        for (int j = 0; j < FIT_KPT; ++j) {
+            const int kap = n + tid + nt * j;
+            tau[j][t] = kap < K ? X[kap].re * invK : 0.0;
+        }
+        __syncthreads();
+    }
+    for (int j = 0; j < FIT_KPT; ++j)
+        for (int t = jp + 1; t <= ORDER; ++t) tau[j][t] = 0.0;
+    double tmax = 0.0;
+    for (int j = 0; j < FIT_KPT; ++j)
+        if (n + tid + nt * j < K) tmax = fmax(tmax, tau[j][0]);
+    tmax = block_max(tmax, red);
+    const double thr = 1e-14 * tmax;
+    // forward pass again: which sectors are fitted, their log p_hat and c
+    double ell[FIT_KPT], cc[FIT_KPT][3];
+    int jrs[FIT_KPT];
+    double fm = -INFINITY, fs = 0.0, lower = -INFINITY;
+    for (int j = 0; j < FIT_KPT; ++j) {
+        if (j == 1) {
+            double mx = block_max(fm, red);
+            double sm = block_sum(fm == -INFINITY ? 0.0 : fs * exp(fm - mx), red);
+            lower = sm > 0.0 ? mx + log(sm) : -INFINITY;
+        }
+        ell[j] = -INFINITY;
+        jrs[j] = -1;
+        const int kap = n + tid + nt * j;
+        if (kap >= K) continue;
+        const double t0 = tau[j][0];
+        if (!(t0 >= thr) || !(t0 > 0.0)) continue;
+        const double lw = log(t0) + rp.log_g_rho - kap * rp.log_rho;
+        if (lw < lower + log(1e-17)) continue;
+        double lq = 0.0;
+        int jr = 0;
+        if (fit_sector(n, jp, tau[j], &lq, &jr, cc[j], nullptr)) continue;
+        ell[j] = lw + lq;
+        jrs[j] = jr;
+        lse_add(fm, fs, ell[j]);
+    }
+    const double fmx = block_max(fm, red);
+    const double fsum = block_sum(fm == -INFINITY ? 0.0 : fs * exp(fm - fmx), red);
+    const double total = fmx + log(fsum);
+    // sector cotangents: pi_kappa w_p d ell / d tau_t
+    const double binv[3] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
+                            6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0))};
+    double tbar[FIT_KPT][ORDER + 1];
+    for (int j = 0; j < FIT_KPT; ++j) {
+        for (int t = 0; t <= ORDER; ++t) tbar[j][t] = 0.0;
+        if (jrs[j] < 0 || !(fsum > 0.0)) continue;
+        const double pi = wp * exp(ell[j] - total);
+        const double t0 = tau[j][0];
+        const int jr = jrs[j];
+        double u[3] = {0, 0, 0}, m[3] = {0, 0, 0};
+        for (int t = 1; t <= jr; ++t) m[t - 1] = tau[j][t] / t0 * binv[t - 1];
+        if (jr > 0) {
+            // H = Cov_c[phi] at the fitted c; u = H^{-1} m
+            double lse, E[3], E2[6];
+            fit_eval(n, jr, binv, cc[j], &lse, E, E2);
+            double Hm[3][3];
+            int k = 0;
+            for (int t = 0; t < jr; ++t)
+                for (int v = t; v < jr; ++v) Hm[t][v] = Hm[v][t] = E2[k++] - E[t] * E[v];
+            double tr = 0.0;
+            for (int t = 0; t < jr; ++t) tr += Hm[t][t];
+            for (int t = 0; t < jr; ++t) Hm[t][t] += 1e-14 * tr;
+            double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            bool ok = true;
+            for (int a = 0; a < jr && ok; ++a) {
+                double d = Hm[a][a];
+                for (int l = 0; l < a; ++l) d -= L[a][l] * L[a][l];
+                if (!(d > 0.0)) { ok = false; break; }
+                L[a][a] = sqrt(d);
+                for (int i = a + 1; i < jr; ++i) {
+                    double s = Hm[i][a];
+                    for (int l = 0; l < a; ++l) s -= L[i][l] * L[a][l];
+                    L[i][a] = s / L[a][a];
+                }
+            }
+            if (ok) {
+                double y[3];
+                for (int i = 0; i < jr; ++i) {
+                    double s = m[i];
+                    for (int l = 0; l < i; ++l) s -= L[i][l] * y[l];
+                    y[i] = s / L[i][i];
+                }
+                for (int i = jr - 1; i >= 0; --i) {
+                    double s = y[i];
+                    for (int l = i + 1; l < jr; ++l) s -= L[l][i] * u[l];
+                    u[i] = s / L[i][i];
+                }
+            }
+        }
+        double um = 0.0;
+        for (int t = 0; t < jr; ++t) um += u[t] * m[t];
+        tbar[j][0] = pi * (1.0 + um) / t0;
+        for (int t = 1; t <= jr; ++t) tbar[j][t] = -pi * u[t - 1] * binv[t - 1] / t0;
+    }
+    // alpha_t(w_q) = c_q FFT(tbar_t)[q], c_q = 1/K at q = 0, K/2 and 2/K otherwise
+    for (int t = 0; t <= ORDER; ++t) {
+        cplx *dst = asw + ((long)p * (ORDER + 1) + t) * GBS_QCAP;
+        if (t > jp) {
+            for (int q = tid; q < Q; q += nt) dst[q] = cmk(0.0, 0.0);
+            continue;
+        }
+        for (int k = tid; k < K; k += nt) X[k] = cmk(0.0, 0.0);
+        __syncthreads();
+        for (int j = 0; j < FIT_KPT; ++j) {
+            const int kap = n + tid + nt * j;
+            if (kap < K) X[(int)(__brev((unsigned)kap) >> (32 - lg))] = cmk(tbar[j][t], 0.0);
+        }
+        __syncthreads();
+        fft_lds(X, W, K);
+        for (int q = tid; q < Q; q += nt) {
+            const double cq = (q == 0 || q == K / 2) ? invK : 2.0 * invK;
+            dst[q] = cscale(X[q], cq);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_adj_contour
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ int adj_vbytes(int n) { return 8 * (2 * n * (2 * n + 1) + 2 * n); }
+// per q: d, rz (2n each), M blocks (3n + 4 n(n-1)/2), Z blocks (same)
+__host__ __device__ __forceinline__ int adj_mbytes(int n) { return 16 * (4 * n + 2 * (3 * n + 2 * n * (n - 1))); }
+__host__ __device__ __forceinline__ int adj_fixed() { return 16 * (CONT_THREADS / 64 + 8); }
+
+__device__ __forceinline__ void catomic(cplx *dst, cplx v)
+{
+    atomicAdd(&dst->re, v.re);
+    atomicAdd(&dst->im, v.im);
+}
+
+// upper-triangle (column-major) packed index e -> (i, j), i <= j
+__device__ __forceinline__ void upper_ij(int e, int &i, int &j)
+{
+    j = (int)floor(0.5 * (sqrt(8.0 * e + 1.0) - 1.0));
+    while (j * (j + 1) / 2 > e) --j;
+    while ((j + 1) * (j + 2) / 2 <= e) ++j;
+    i = e - j * (j + 1) / 2;
+}
+
+template <int ORDER>
+__global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
+    const int *__restrict__ offsets, const long long *__restrict__ voff,
+    const double *__restrict__ alpha, const double *__restrict__ vt,
+    const RowPlan *__restrict__ rows, const int *__restrict__ items, int *__restrict__ counter,
+    const cplx *__restrict__ asw, const long long *__restrict__ roff, double *__restrict__ rscr)
+{
+    extern __shared__ double sh[];
+    __shared__ int s_item;
+    __shared__ cplx s_g[ORDER + 1];
+    __shared__ cplx s_w, s_ghat, s_beta;
+    cplx *red = (cplx *)sh;                        // [waves]
+    double *dyn = (double *)(red + CONT_THREADS / 64 + 8);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int total = counter[2];
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(&counter[3], 1);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= total) break;
+        const int p = items[2 * item], ch = items[2 * item + 1];
+        const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n, NP = N + 1;
+        const RowPlan rp = rows[p];
+        double *Vt = dyn;                    // N rows of stride NP: Vt[k*NP + i] = V[i][k]
+        double *al = Vt + N * NP;            // N
+        cplx *dk = (cplx *)(al + N);         // N
+        cplx *rz = dk + N;                   // N
+        const int np = n * (n - 1) / 2;
+        cplx *Md0 = rz + N, *Md1 = Md0 + n, *Md2 = Md1 + n;
+        cplx *Mo0 = Md2 + n, *Mo1 = Mo0 + np, *Mo2 = Mo1 + np, *Mo3 = Mo2 + np;
+        cplx *Zd0 = Mo3 + np, *Zd1 = Zd0 + n, *Zd2 = Zd1 + n;
+        cplx *Zo0 = Zd2 + n, *Zo1 = Zo0 + np, *Zo2 = Zo1 + np, *Zo3 = Zo2 + np;
+        cplx *Yp = Md0;                      // column panel of Z V (reuses M after the clusters)
+        const long long vo = voff[p];
+        for (int idx = tid; idx < N * N; idx += CONT_THREADS) {
+            const int k = idx / N, i = idx - k * N;
+            Vt[k * NP + i] = vt[vo + idx];
+        }
+        for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
+        const int Qn = rp.K / 2 + 1;
+        const int q0 = ch * ADJ_QCHUNK, q1 = min(q0 + ADJ_QCHUNK, Qn);
+        const int nup = N * (N + 1) / 2;
+        double racc[ADJ_MAXOWN];
+#pragma unroll
+        for (int m = 0; m < ADJ_MAXOWN; ++m) racc[m] = 0.0;
+        __syncthreads();
+        for (int q = q0; q < q1; ++q) {
+            if (tid == 0) {
+                double sn, cs;
+                sincospi(2.0 * (double)q / (double)rp.K, &sn, &cs);
+                s_w = cmk(rp.rho * cs, rp.rho * sn);
+            }
+            __syncthreads();
+            const cplx w = s_w;
+            for (int k = tid; k < N; k += CONT_THREADS) {
+                const double am1 = al[k] - 1.0;
+                const cplx z = cmk(fma(w.re, am1, 1.0), w.im * am1);
+                const cplx r = crsqrt_p(z);
+                dk[k] = cmul(r, r);
+                rz[k] = r;
+            }
+            for (int i = tid; i < 3 * n + 4 * np; i += CONT_THREADS) Zd0[i] = cmk(0.0, 0.0);
+            __syncthreads();
+            if (tid == 0) {
+                cplx pr = cmk(exp(0.5 * rp.logdet_a - rp.log_g_rho), 0.0);
+                for (int k = 0; k < N; ++k) pr = cmul(pr, rz[k]);
+                s_ghat = pr;
+                for (int t = 0; t <= ORDER; ++t)
+                    s_g[t] = cmul(asw[((long)p * (ORDER + 1) + t) * GBS_QCAP + q], pr);
+            }
+            // M(w) blocks (same layout and order as the forward kernel)
+            for (int bi = tid; bi < n + np; bi += CONT_THREADS) {
+                if (bi < n) {
+                    const int a = bi;
+                    cplx m00 = cmk(0, 0), m01 = cmk(0, 0), m11 = cmk(0, 0);
+#pragma unroll 1
+                    for (int k = 0; k < N; ++k) {
+                        const double v0 = Vt[k * NP + a], v1 = Vt[k * NP + n + a];
+                        const cplx d = dk[k];
+                        const double p00 = v0 * v0, p01 = v0 * v1, p11 = v1 * v1;
+                        m00.re = fma(p00, d.re, m00.re); m00.im = fma(p00, d.im, m00.im);
+                        m01.re = fma(p01, d.re, m01.re); m01.im = fma(p01, d.im, m01.im);
+                        m11.re = fma(p11, d.re, m11.re); m11.im = fma(p11, d.im, m11.im);
+                    }
+                    Md0[a] = m00; Md1[a] = m01; Md2[a] = m11;
+                } else {
+                    const int pi = bi - n;
+                    int b = (int)floor(0.5 * (1.0 + sqrt(1.0 + 8.0 * pi)));
+                    while (b * (b - 1) / 2 > pi) --b;
+                    while ((b + 1) * b / 2 <= pi) ++b;
+                    const int a = pi - b * (b - 1) / 2;
+                    cplx b00 = cmk(0, 0), b01 = cmk(0, 0), b10 = cmk(0, 0), b11 = cmk(0, 0);
+#pragma unroll 1
+                    for (int k = 0; k < N; ++k) {
+                        const double va0 = Vt[k * NP + a], va1 = Vt[k * NP + n + a];
+                        const double vb0 = Vt[k * NP + b], vb1 = Vt[k * NP + n + b];
+                        const cplx d = dk[k];
+                        const double p00 = va0 * vb0, p01 = va0 * vb1, p10 = va1 * vb0, p11 = va1 * vb1;
+                        b00.re = fma(p00, d.re, b00.re); b00.im = fma(p00, d.im, b00.im);
+                        b01.re = fma(p01, d.re, b01.re); b01.im = fma(p01, d.im, b01.im);
+                        b10.re = fma(p10, d.re, b10.re); b10.im = fma(p10, d.im, b10.im);
+                        b11.re = fma(p11, d.re, b11.re); b11.im = fma(p11, d.im, b11.im);
+                    }
+                    Mo0[pi] = b00; Mo1[pi] = b01; Mo2[pi] = b10; Mo3[pi] = b11;
+                }
+            }
+            __syncthreads();
+            // clusters: Z += c_T E_T M_TT^{-1} E_T^T, c_T = gamma_|T| det(M_TT)^{-1/2}
+            cplx bsum = cmk(0.0, 0.0);
+            const cplx g1 = s_g[1 <= ORDER ? 1 : 0];
+            for (int a = tid; a < n; a += CONT_THREADS) {
+                const cplx a00 = Md0[a], a01 = Md1[a], a11 = Md2[a];
+                const cplx r = crsqrt_p(cfnma(a01, a01, cmul(a00, a11)));
+                const cplx c = cmul(g1, r);
+                const cplx id = cmul(r, r);
+                bsum = cadd(bsum, c);
+                const cplx cid = cmul(c, id);
+                catomic(&Zd0[a], cmul(cid, a11));
+                catomic(&Zd1[a], cscale(cmul(cid, a01), -1.0));
+                catomic(&Zd2[a], cmul(cid, a00));
+            }
+            if (ORDER >= 2) {
+                const cplx g2 = s_g[2 <= ORDER ? 2 : 0];
+                const cplx g3 = s_g[3 <= ORDER ? 3 : 0];
+#pragma unroll 1
+                for (int pi = tid; pi < np; pi += CONT_THREADS) {
+                    int b = (int)floor(0.5 * (1.0 + sqrt(1.0 + 8.0 * pi)));
+                    while (b * (b - 1) / 2 > pi) --b;
+                    while ((b + 1) * b / 2 <= pi) ++b;
+                    const int a = pi - b * (b - 1) / 2;
+                    const cplx a00 = Md0[a], a01 = Md1[a], a11 = Md2[a];
+                    const cplx b00 = Mo0[pi], b01 = Mo1[pi], b10 = Mo2[pi], b11 = Mo3[pi];
+                    const cplx deta = cfnma(a01, a01, cmul(a00, a11));
+                    const cplx ra = crsqrt_p(deta);
+                    const cplx ideta = cmul(ra, ra);
+                    const cplx ia00 = cmul(a11, ideta), ia11 = cmul(a00, ideta);
+                    const cplx ia01 = cscale(cmul(a01, ideta), -1.0);
+                    const cplx G00 = cfma(ia00, b00, cmul(ia01, b10));
+                    const cplx G01 = cfma(ia00, b01, cmul(ia01, b11));
+                    const cplx G10 = cfma(ia01, b00, cmul(ia11, b10));
+                    const cplx G11 = cfma(ia01, b01, cmul(ia11, b11));
+                    const cplx sb00 = csub(Md0[b], cfma(b00, G00, cmul(b10, G10)));
+                    const cplx sb01 = csub(Md1[b], cfma(b00, G01, cmul(b10, G11)));
+                    const cplx sb11 = csub(Md2[b], cfma(b01, G01, cmul(b11, G11)));
+                    const cplx rb = crsqrt_p(cfnma(sb01, sb01, cmul(sb00, sb11)));
+                    const cplx rab = cmul(ra, rb);
+                    const cplx idetb = cmul(rb, rb);
+                    const cplx ib00 = cmul(sb11, idetb), ib11 = cmul(sb00, idetb);
+                    const cplx ib01 = cscale(cmul(sb01, idetb), -1.0);
+                    // coefficient of P^{-1} (pair itself plus sum over its triples) and the
+                    // pair block of sum_c c_T U Sc^{-1} U^T (4x4 symmetric, 10 entries)
+                    cplx cp = cmul(g2, rab);
+                    bsum = cadd(bsum, cp);
+                    cplx A00 = cmk(0, 0), A01 = cmk(0, 0), A02 = cmk(0, 0), A03 = cmk(0, 0),
+                         A11 = cmk(0, 0), A12 = cmk(0, 0), A13 = cmk(0, 0), A22 = cmk(0, 0),
+                         A23 = cmk(0, 0), A33 = cmk(0, 0);
+                    if (ORDER >= 3) {
+#pragma unroll 1
+                        for (int c = b + 1; c < n; ++c) {
+                            const int cb = c * (c - 1) / 2;
+                            const int iac = cb + a, ibc = cb + b;
+                            // Za = Maa^{-1} Xa, Y = Xb - G^T Xa, W = Sb^{-1} Y,
+                            // Sc = Mcc - Xa^T Za - Y^T W, U = [Za - G W ; W]
+                            cplx Z00, Z01, Z10, Z11, W00, W01, W10, W11, sc00, sc01, sc11;
+                            {
+                                const cplx x00 = Mo0[iac], x01 = Mo1[iac], x10 = Mo2[iac], x11 = Mo3[iac];
+                                Z00 = cfma(ia00, x00, cmul(ia01, x10));
+                                Z10 = cfma(ia01, x00, cmul(ia11, x10));
+                                Z01 = cfma(ia00, x01, cmul(ia01, x11));
+                                Z11 = cfma(ia01, x01, cmul(ia11, x11));
+                                sc00 = csub(Md0[c], cfma(x00, Z00, cmul(x10, Z10)));
+                                sc01 = csub(Md1[c], cfma(x00, Z01, cmul(x10, Z11)));
+                                sc11 = csub(Md2[c], cfma(x01, Z01, cmul(x11, Z11)));
+                                const cplx Y00 = csub(Mo0[ibc], cfma(G00, x00, cmul(G10, x10)));
+                                const cplx Y10 = csub(Mo2[ibc], cfma(G01, x00, cmul(G11, x10)));
+                                W00 = cfma(ib00, Y00, cmul(ib01, Y10));
+                                W10 = cfma(ib01, Y00, cmul(ib11, Y10));
+                                sc00 = csub(sc00, cfma(Y00, W00, cmul(Y10, W10)));
+                                const cplx Y01 = csub(Mo1[ibc], cfma(G00, x01, cmul(G10, x11)));
+                                const cplx Y11 = csub(Mo3[ibc], cfma(G01, x01, cmul(G11, x11)));
+                                W01 = cfma(ib00, Y01, cmul(ib01, Y11));
+                                W11 = cfma(ib01, Y01, cmul(ib11, Y11));
+                                sc01 = csub(sc01, cfma(Y00, W01, cmul(Y10, W11)));
+                                sc11 = csub(sc11, cfma(Y01, W01, cmul(Y11, W11)));
+                            }
+                            const cplx rc = crsqrt_p(cfnma(sc01, sc01, cmul(sc00, sc11)));
+                            const cplx ct = cmul(g3, cmul(rab, rc));
+                            bsum = cadd(bsum, ct);
+                            // c_T Sc^{-1}
+                            cplx is00, is01, is11;
+                            {
+                                const cplx k = cmul(ct, cmul(rc, rc));
+                                is00 = cmul(sc11, k);
+                                is11 = cmul(sc00, k);
+                                is01 = cscale(cmul(sc01, k), -1.0);
+                            }
+                            catomic(&Zd0[c], is00);
+                            catomic(&Zd1[c], is01);
+                            catomic(&Zd2[c], is11);
+                            // rows a: U_a = Za - G W, then P_a = U_a c_T Sc^{-1}
+                            const cplx U00 = csub(Z00, cfma(G00, W00, cmul(G01, W10)));
+                            const cplx U01 = csub(Z01, cfma(G00, W01, cmul(G01, W11)));
+                            const cplx U10 = csub(Z10, cfma(G10, W00, cmul(G11, W10)));
+                            const cplx U11 = csub(Z11, cfma(G10, W01, cmul(G11, W11)));
+                            const cplx P00 = cfma(U00, is00, cmul(U01, is01));
+                            const cplx P01 = cfma(U00, is01, cmul(U01, is11));
+                            const cplx P10 = cfma(U10, is00, cmul(U11, is01));
+                            const cplx P11 = cfma(U10, is01, cmul(U11, is11));
+                            catomic(&Zo0[iac], cscale(P00, -1.0));
+                            catomic(&Zo1[iac], cscale(P01, -1.0));
+                            catomic(&Zo2[iac], cscale(P10, -1.0));
+                            catomic(&Zo3[iac], cscale(P11, -1.0));
+                            A00 = cfma(P00, U00, cfma(P01, U01, A00));
+                            A01 = cfma(P00, U10, cfma(P01, U11, A01));
+                            A11 = cfma(P10, U10, cfma(P11, U11, A11));
+                            A02 = cfma(P00, W00, cfma(P01, W01, A02));
+                            A03 = cfma(P00, W10, cfma(P01, W11, A03));
+                            A12 = cfma(P10, W00, cfma(P11, W01, A12));
+                            A13 = cfma(P10, W10, cfma(P11, W11, A13));
+                            // rows b: P_b = W c_T Sc^{-1}
+                            const cplx P20 = cfma(W00, is00, cmul(W01, is01));
+                            const cplx P21 = cfma(W00, is01, cmul(W01, is11));
+                            const cplx P30 = cfma(W10, is00, cmul(W11, is01));
+                            const cplx P31 = cfma(W10, is01, cmul(W11, is11));
+                            catomic(&Zo0[ibc], cscale(P20, -1.0));
+                            catomic(&Zo1[ibc], cscale(P21, -1.0));
+                            catomic(&Zo2[ibc], cscale(P30, -1.0));
+                            catomic(&Zo3[ibc], cscale(P31, -1.0));
+                            A22 = cfma(P20, W00, cfma(P21, W01, A22));
+                            A23 = cfma(P20, W10, cfma(P21, W11, A23));
+                            A33 = cfma(P30, W10, cfma(P31, W11, A33));
+                            cp = cadd(cp, ct);
+                        }
+                    }
+                    // P^{-1} = [[ia + G ib G^T, -G ib], [-ib G^T, ib]]
+                    const cplx H00 = cfma(ib00, G00, cmul(ib01, G01)), H01 = cfma(ib01, G00, cmul(ib11, G01));
+                    const cplx H10 = cfma(ib00, G10, cmul(ib01, G11)), H11 = cfma(ib01, G10, cmul(ib11, G11));
+                    // (G ib) rows: row0 = (H00, H01), row1 = (H10, H11)
+                    const cplx pa00 = cadd(ia00, cfma(H00, G00, cmul(H01, G01)));
+                    const cplx pa01 = cadd(ia01, cfma(H00, G10, cmul(H01, G11)));
+                    const cplx pa11 = cadd(ia11, cfma(H10, G10, cmul(H11, G11)));
+                    catomic(&Zd0[a], cfma(cp, pa00, A00));
+                    catomic(&Zd1[a], cfma(cp, pa01, A01));
+                    catomic(&Zd2[a], cfma(cp, pa11, A11));
+                    catomic(&Zo0[pi], cfnma(cp, H00, A02));
+                    catomic(&Zo1[pi], cfnma(cp, H01, A03));
+                    catomic(&Zo2[pi], cfnma(cp, H10, A12));
+                    catomic(&Zo3[pi], cfnma(cp, H11, A13));
+                    catomic(&Zd0[b], cfma(cp, ib00, A22));
+                    catomic(&Zd1[b], cfma(cp, ib01, A23));
+                    catomic(&Zd2[b], cfma(cp, ib11, A33));
+                }
+            }
+            bsum = warp_csum(bsum);
+            if (lane == 0) red[wid] = bsum;
+            __syncthreads();
+            if (tid == 0) {
+                cplx bt = s_g[0];
+                for (int i = 0; i < CONT_THREADS / 64; ++i) bt = cadd(bt, red[i]);
+                s_beta = bt;
+            }
+            __syncthreads();
+            // R += Re[(w/2) d_i d_j (V^T Z V)_ij] (+ diagonal beta terms), by
+            // column panels of 16: Y = Z V[:, J] into LDS, then owners of R entries
+            const cplx beta = s_beta;
+            const cplx hw = cscale(w, 0.5);
+            // panel width: Y (N x PW complex) must fit in M's region (2n^2 + n complex)
+            const int PW = n < 16 ? n : 16;
+            for (int J = 0; J < N; J += PW) {
+                const int nj = min(PW, N - J);
+                for (int idx = tid; idx < N * nj; idx += CONT_THREADS) {
+                    const int r = idx / nj, jl = idx - r * nj;
+                    const int a = r < n ? r : r - n, qa = r < n ? 0 : 1;
+                    const int j = J + jl;
+                    cplx acc = cmk(0.0, 0.0);
+#pragma unroll 1
+                    for (int b = 0; b < n; ++b) {
+                        cplx zx, zp;
+                        if (a < b) {
+                            const int e = b * (b - 1) / 2 + a;
+                            zx = qa ? Zo2[e] : Zo0[e];
+                            zp = qa ? Zo3[e] : Zo1[e];
+                        } else if (a > b) {
+                            const int e = a * (a - 1) / 2 + b;
+                            zx = qa ? Zo1[e] : Zo0[e];
+                            zp = qa ? Zo3[e] : Zo2[e];
+                        } else {
+                            zx = qa ? Zd1[a] : Zd0[a];
+                            zp = qa ? Zd2[a] : Zd1[a];
+                        }
+                        const double vx = Vt[j * NP + b], vp = Vt[j * NP + n + b];
+                        acc.re = fma(zx.re, vx, fma(zp.re, vp, acc.re));
+                        acc.im = fma(zx.im, vx, fma(zp.im, vp, acc.im));
+                    }
+                    Yp[r * PW + jl] = acc;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int m = 0; m < ADJ_MAXOWN; ++m) {
+                    const int e = tid + CONT_THREADS * m;
+                    if (e >= nup) break;
+                    int i, j;
+                    upper_ij(e, i, j);
+                    if (j < J || j >= J + nj) continue;
+                    const int jl = j - J;
+                    cplx zt = cmk(0.0, 0.0);
+                    for (int s = 0; s < N; ++s) {
+                        const double v = Vt[i * NP + s];
+                        const cplx y = Yp[s * PW + jl];
+                        zt.re = fma(v, y.re, zt.re);
+                        zt.im = fma(v, y.im, zt.im);
+                    }
+                    const cplx f = cmul(hw, cmul(dk[i], dk[j]));
+                    double add = f.re * zt.re - f.im * zt.im;
+                    if (i == j) {
+                        const double dr = 1.0 / (1.0 + rp.rho * (al[i] - 1.0));
+                        const cplx t = cmk(0.5 * rp.rho * dr - hw.re * dk[i].re + hw.im * dk[i].im,
+                                           -(hw.re * dk[i].im + hw.im * dk[i].re));
+                        add += beta.re * t.re - beta.im * t.im;
+                    }
+                    racc[m] += add;
+                }
+                __syncthreads();
+            }
+        }
+        const long long ro = roff[item];
+#pragma unroll
+        for (int m = 0; m < ADJ_MAXOWN; ++m) {
+            const int e = tid + CONT_THREADS * m;
+            if (e < nup) rscr[ro + e] = racc[m];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_adj_items: backward work items (row, chunk of ADJ_QCHUNK points) and the
+// offsets of their R scratch
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_adj_items(int P, const int *__restrict__ offsets,
+                                                    const int *__restrict__ perm,
+                                                    const RowPlan *__restrict__ rows,
+                                                    int *__restrict__ items, long long *__restrict__ roff,
+                                                    int *__restrict__ row_item0, int *__restrict__ counter)
+{
+    __shared__ int part[1024];
+    __shared__ long long lpart[1024];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int per = (P + nt - 1) / nt;
+    const int b = tid * per, e = min(P, b + per);
+    auto nch = [&](int i) {
+        const int p = perm[i];
+        const int n = offsets[p + 1] - offsets[p];
+        const RowPlan &rp = rows[p];
+        if (n == 0 || rp.status != 0 || rp.K <= 0) return 0;
+        return (rp.K / 2 + 1 + ADJ_QCHUNK - 1) / ADJ_QCHUNK;
+    };
+    auto rsz = [&](int i) {
+        const int p = perm[i];
+        const long long N = 2 * (offsets[p + 1] - offsets[p]);
+        return N * (N + 1) / 2;
+    };
+    int s = 0;
+    long long ls = 0;
+    for (int i = b; i < e; ++i) {
+        s += nch(i);
+        ls += nch(i) * rsz(i);
+    }
+    part[tid] = s;
+    lpart[tid] = ls;
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        long long lacc = 0;
+        for (int t = 0; t < nt; ++t) {
+            int v = part[t];
+            long long lv = lpart[t];
+            part[t] = acc;
+            lpart[t] = lacc;
+            acc += v;
+            lacc += lv;
+        }
+        counter[2] = acc;
+        counter[3] = 0;
+    }
+    __syncthreads();
+    int off = part[tid];
+    long long loff = lpart[tid];
+    for (int i = b; i < e; ++i) {
+        const int c = nch(i), p = perm[i];
+        const long long sz = rsz(i);
+        row_item0[p] = c > 0 ? off : -1;
+        for (int k = 0; k < c; ++k) {
+            items[2 * (off + k)] = p;
+            items[2 * (off + k) + 1] = k;
+            roff[off + k] = loff + k * sz;
+        }
+        off += c;
+        loff += c * sz;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_adj_reduce: per row, R = sum of the items' R (fixed order) plus the
+// contour-independent diagonal term of log G_0(rho) and log P_vac(Cbar)
+// (their A^{-1} parts cancel, leaving -w_p rho/2 M(rho)), then A_bar = V R V^T.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adj_reduce(const int *__restrict__ offsets,
+                                                    const long long *__restrict__ voff,
+                                                    const double *__restrict__ alpha,
+                                                    const double *__restrict__ vt,
+                                                    const RowPlan *__restrict__ rows,
+                                                    const double *__restrict__ dl,
+                                                    const int *__restrict__ row_item0,
+                                                    const long long *__restrict__ roff,
+                                                    const double *__restrict__ rscr,
+                                                    double *__restrict__ abar)
+{
+    extern __shared__ double sh[];
+    const int p = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
+    const RowPlan rp = rows[p];
+    const long long vo = voff[p];
+    if (n == 0) return;
+    const int it0 = row_item0[p];
+    if (it0 < 0 || rp.status != 0 || !isfinite(dl[p]) || dl[p] == 0.0) {
+        for (int i = tid; i < N * N; i += nt) abar[vo + i] = 0.0;
+        return;
+    }
+    const int nit = (rp.K / 2 + 1 + ADJ_QCHUNK - 1) / ADJ_QCHUNK;
+    double *V = sh;            // V[i][k] row-major
+    double *R = V + N * N;     // full symmetric
+    double *T = R + N * N;
+    for (int idx = tid; idx < N * N; idx += nt) {
+        const int k = idx / N, i = idx - k * N;
+        V[i * N + k] = vt[vo + idx];
+    }
+    const int nup = N * (N + 1) / 2;
+    for (int e = tid; e < nup; e += nt) {
+        int i, j;
+        upper_ij(e, i, j);
+        double s = 0.0;
+        for (int it = 0; it < nit; ++it) s += rscr[roff[it0 + it] + e];
+        if (i == j) {
+            const double dr = 1.0 / (1.0 + rp.rho * (alpha[2 * o + i] - 1.0));
+            s += -0.5 * dl[p] * rp.rho * dr;
+        }
+        R[i * N + j] = s;
+        R[j * N + i] = s;
+    }
+    __syncthreads();
+    // T = R V^T, A_bar = V T
+    for (int idx = tid; idx < N * N; idx += nt) {
+        const int k = idx / N, j = idx - k * N;
+        double s = 0.0;
+        for (int l = 0; l < N; ++l) s = fma(R[k * N + l], V[j * N + l], s);
+        T[k * N + j] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < N * N; idx += nt) {
+        const int i = idx / N, j = idx - i * N;
+        double s = 0.0;
+        for (int k = 0; k < N; ++k) s = fma(V[i * N + k], T[k * N + j], s);
+        abar[vo + idx] = s;
+    }
+}
+
+// Psi[u][v] = sum over rows containing both modes of A_bar at their positions.
+__global__ void k_adj_scatter(int M, int P, const int *__restrict__ offsets,
+                              const long long *__restrict__ voff, const short *__restrict__ pos,
+                              const double *__restrict__ abar, double *__restrict__ psi)
+{
+    const int D = 2 * M;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x, u = blockIdx.y;
+    if (v >= D || u >= D) return;
+    const int mu = u % M, mv = v % M, qu = u / M, qv = v / M;
+    double s = 0.0;
+    for (int p = 0; p < P; ++p) {
+        const int iu = pos[(long)p * M + mu];
+        if (iu < 0) continue;
+        const int iv = pos[(long)p * M + mv];
+        if (iv < 0) continue;
+        const int n = offsets[p + 1] - offsets[p], N = 2 * n;
+        s += abar[voff[p] + (long)(iu + qu * n) * N + (iv + qv * n)];
+    }
+    psi[(long)u * D + v] = s;
+}
+
+// Model adjoint, one workgroup: Q_bar = -(W/2) Q^{-1} - Q^{-1} Psi Q^{-1} with W the
+// sum of w_p over rows with a result; sigma_bar = Q_bar; then through
+// sigma = D sigma0 D + (I - D^2)/2 and sigma0 = O diag(e^{-2r}, e^{2r}) O^T / 2.
+__global__ __launch_bounds__(1024) void k_adj_model(int M, int P, const double *__restrict__ qi,
+                                                    const double *__restrict__ params,
+                                                    const double *__restrict__ dl,
+                                                    const int *__restrict__ status,
+                                                    double *__restrict__ psi, double *__restrict__ tmp,
+                                                    double *__restrict__ grad)
+{
+    __shared__ double red[1024];
+    const int D = 2 * M, tid = threadIdx.x, nt = blockDim.x;
+    const double *ure = params, *uim = params + (long)M * M;
+    const double *r = params + 2L * M * M, *eta = r + M;
+    double ws = 0.0;
+    for (int p = tid; p < P; p += nt)
+        if (status[p] == 0 && isfinite(dl[p])) ws += dl[p];
+    ws = block_sum(ws, red);
+    // tmp = Psi Q^{-1}
+    for (int idx = tid; idx < D * D; idx += nt) {
+        const int i = idx / D, j = idx - i * D;
+        double s = 0.0;
+        for (int k = 0; k < D; ++k) s = fma(psi[(long)i * D + k], qi[(long)k * D + j], s);
+        tmp[idx] = s;
+    }
+    __syncthreads();
+    // psi <- sigma_bar = -(W/2) Q^{-1} - Q^{-1} tmp
+    for (int idx = tid; idx < D * D; idx += nt) {
+        const int i = idx / D, j = idx - i * D;
+        double s = 0.0;
+        for (int k = 0; k < D; ++k) s = fma(qi[(long)i * D + k], tmp[(long)k * D + j], s);
+        psi[idx] = -0.5 * ws * qi[idx] - s;
+    }
+    __syncthreads();
+    auto O = [&](int i, int k) {
+        if (i < M) return k < M ? ure[i * M + k] : -uim[i * M + k - M];
+        return k < M ? uim[(i - M) * M + k] : ure[(i - M) * M + k - M];
+    };
+    auto sq = [&](int i) { return sqrt(eta[i % M]); };
+    // tmp = sigma0_bar O with sigma0_bar = D sigma_bar D
+    for (int idx = tid; idx < D * D; idx += nt) {
+        const int i = idx / D, k = idx - i * D;
+        double s = 0.0;
+        for (int j = 0; j < D; ++j) s = fma(psi[(long)i * D + j] * sq(j), O(j, k), s);
+        tmp[idx] = sq(i) * s;
+    }
+    __syncthreads();
+    // r_bar_j = -e^{-2 r_j} (O^T sigma0_bar O)_{jj} + e^{2 r_j} (O^T sigma0_bar O)_{M+j,M+j}
+    for (int j = tid; j < M; j += nt) {
+        double bx = 0.0, bp = 0.0;
+        for (int i = 0; i < D; ++i) {
+            bx = fma(O(i, j), tmp[(long)i * D + j], bx);
+            bp = fma(O(i, M + j), tmp[(long)i * D + M + j], bp);
+        }
+        grad[j] = -exp(-2.0 * r[j]) * bx + exp(2.0 * r[j]) * bp;
+    }
+    __syncthreads();
+    // eta_bar_m = (1/eta_m) sum_{i in quads(m)} sum_j sigma0_bar_ij sigma0_ij
+    //             - (sigma_bar_{m,m} + sigma_bar_{M+m,M+m}) / 2
+    for (int m = tid; m < M; m += nt) {
+        double s = 0.0;
+        for (int qd = 0; qd < 2; ++qd) {
+            const int i = m + qd * M;
+            for (int j = 0; j < D; ++j) {
+                double s0 = 0.0;  // sigma0_ij
+                for (int k = 0; k < M; ++k) s0 = fma(O(i, k) * O(j, k), 0.5 * exp(-2.0 * r[k]), s0);
+                for (int k = 0; k < M; ++k) s0 = fma(O(i, M + k) * O(j, M + k), 0.5 * exp(2.0 * r[k]), s0);
+                s = fma(psi[(long)i * D + j] * sq(i) * sq(j), s0, s);
+            }
+        }
+        grad[M + m] = s / eta[m] - 0.5 * (psi[(long)m * D + m] + psi[(long)(M + m) * D + M + m]);
+    }
+}
+
+__global__ void k_zero(int n, double *x)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0.0;
+}
+
+template <int ORDER>
+int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *status,
+                   double *grad_r, double *grad_eta)
+{
+    hipStream_t st = ctx->stream;
+    DevModel &m = ctx->model;
+    const int P = pl->P, nmax = pl->max_n, M = m.M;
+    size_t lds_f = sizeof(cplx) * (GBS_KMAX + GBS_KMAX / 2);
+    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_adj_fit<ORDER>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f));
+    int ts = timer_begin(ctx, TG_ADJ_FIT);
+    hipLaunchKernelGGL(k_adj_fit<ORDER>, dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
+                       pl->d_rows, pl->d_sw, dl, pl->d_asw);
+    timer_end(ctx, ts);
+    ts = timer_begin(ctx, TG_ADJ_CLUSTER);
+    hipLaunchKernelGGL(k_adj_items, dim3(1), dim3(1024), 0, st, P, pl->d_offsets, pl->d_perm,
+                       pl->d_rows, pl->d_aitems, pl->d_roff, pl->d_ritem0, pl->d_counter);
+    hipFuncAttributes fa;
+    HIP_TRY(ctx, hipFuncGetAttributes(&fa, (const void *)k_adj_contour<ORDER>));
+    const int lds_a = adj_fixed() + adj_vbytes(nmax) + adj_mbytes(nmax);
+    if (lds_a + (int)fa.sharedSizeBytes > ctx->lds_per_block)
+        return set_err(ctx, GBS_E_INVAL, "rows too large for the gradient kernel's LDS");
+    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_adj_contour<ORDER>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds_a));
+    int occ = 0;
+    HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_adj_contour<ORDER>,
+                                                              CONT_THREADS, lds_a));
+    if (occ < 1) occ = 1;
+    hipLaunchKernelGGL(k_adj_contour<ORDER>, dim3(occ * ctx->num_cu), dim3(CONT_THREADS), lds_a, st,
+                       pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_aitems,
+                       pl->d_counter, pl->d_asw, pl->d_roff, pl->d_rscr);
+    const int N = 2 * nmax;
+    size_t lds_r = sizeof(double) * 3 * (size_t)N * N;
+    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_adj_reduce,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r));
+    hipLaunchKernelGGL(k_adj_reduce, dim3(P), dim3(256), lds_r, st, pl->d_offsets, pl->d_voff,
+                       pl->d_alpha, pl->d_v, pl->d_rows, dl, pl->d_ritem0, pl->d_roff, pl->d_rscr,
+                       pl->d_abar);
+    const int D = 2 * M;
+    hipLaunchKernelGGL(k_adj_scatter, dim3((D + 127) / 128, D), dim3(128), 0, st, M, P,
+                       pl->d_offsets, pl->d_voff, pl->d_pos, pl->d_abar, pl->d_qibar);
+    hipLaunchKernelGGL(k_adj_model, dim3(1), dim3(1024), 0, st, M, P, m.qi_hi, m.params, dl,
+                       status, pl->d_qibar, pl->d_qitmp, pl->d_grad);
+    timer_end(ctx, ts);
+    HIP_TRY(ctx, hipMemcpyAsync(grad_r, pl->d_grad, M * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(ctx, hipMemcpyAsync(grad_eta, pl->d_grad + M, M * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(ctx, hipGetLastError());
+    return 0;
+}
+
+}  // namespace
+
+int adj_workspace(gbs_ctx *ctx, gbs_plan *pl);
+
+int approx_backward(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, const int32_t *status_dev,
+                    double *grad_r_dev, double *grad_eta_dev)
+{
+    int rc = adj_workspace(ctx, pl);
+    if (rc) return rc;
+    if (pl->P == 0) {
+        hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, ctx->stream, ctx->model.M, grad_r_dev);
+        hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, ctx->stream, ctx->model.M, grad_eta_dev);
+        HIP_TRY(ctx, hipGetLastError());
+        return 0;
+    }
+    switch (pl->order) {
+    case 1: return backward_order<1>(ctx, pl, dl_dev, status_dev, grad_r_dev, grad_eta_dev);
+    case 2: return backward_order<2>(ctx, pl, dl_dev, status_dev, grad_r_dev, grad_eta_dev);
+    case 3: return backward_order<3>(ctx, pl, dl_dev, status_dev, grad_r_dev, grad_eta_dev);
+    default: return set_err(ctx, GBS_E_INVAL, "order must be 1, 2 or 3");
+    }
 }

@@ -85,10 +85,17 @@ struct gbs_plan {
     size_t v_total = 0;
     int max_items = 0;
     int n_cluster_items = 0;
-    // gradient workspace
-    double *d_gsw = nullptr;              // adjoint of the cluster sums (per row, per q)
-    double *d_abar = nullptr;             // per row adjoint of A (2n)^2
-    double *d_qibar = nullptr;            // (2M)^2 adjoint of Q^{-1}
+    // gradient workspace (allocated by the first gradient call)
+    bool have_adj = false;
+    cplx *d_asw = nullptr;                // cotangents of the cluster sums, like d_sw
+    int32_t *d_aitems = nullptr;          // backward work items (row, chunk)
+    long long *d_roff = nullptr;          // per item: offset of its R in d_rscr
+    int32_t *d_ritem0 = nullptr;          // per row: first backward item
+    double *d_rscr = nullptr;             // per item: upper triangle of R
+    double *d_abar = nullptr;             // per row adjoint of A (2n)^2, offsets d_voff
+    double *d_qibar = nullptr;            // (2M)^2 adjoint of Q^{-1}, then sigma_bar
+    double *d_qitmp = nullptr;            // (2M)^2 scratch
+    int16_t *d_pos = nullptr;             // [P][M] position of a mode in the row, -1 if absent
     double *d_grad = nullptr;             // 2M: grad r, grad eta
     double *d_dl = nullptr;               // P
 };
@@ -107,5 +114,5 @@ int model_build_dev(gbs_ctx *ctx, const double *sigma_dev, bool sync);
 int approx_forward(gbs_ctx *ctx, gbs_plan *plan, double *logp_dev, int32_t *status_dev);
 int exact_run(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, double *p,
               double *logp, double *kappa, int32_t *status);
-int approx_backward(gbs_ctx *ctx, gbs_plan *plan, const double *dl_dev, double *grad_r_dev,
-                    double *grad_eta_dev);
+int approx_backward(gbs_ctx *ctx, gbs_plan *plan, const double *dl_dev, const int32_t *status_dev,
+                    double *grad_r_dev, double *grad_eta_dev);

@@ -1,0 +1,91 @@
+"""torch.autograd wrapper: log p_hat of a batch of click patterns as a
+differentiable function of the squeezing parameters r and the transmissions
+eta (the interferometer U is held fixed).
+
+Forward = gbs_set_model_dev + gbs_prob_approx_dev; backward = gbs_grad_dev
+(hand-written adjoint in libgbs.so).  The library runs on its own stream,
+ordered against torch's current stream with events; PyTorch only provides the
+device memory.  The contour plan is frozen after the first forward so that
+repeated evaluations (fit loops, finite differences) see a smooth function.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .gbs import Context
+
+
+class ClickModel:
+    """A fixed interferometer U and a fixed batch of click patterns."""
+
+    def __init__(self, U: np.ndarray, offsets, modes, order: int, device: int = 0,
+                 freeze_plan: bool = True):
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.Stream(self.device)   # default priority
+        self.ctx = Context(device, stream=self.stream.cuda_stream)
+        M = U.shape[0]
+        self.M = M
+        self.ure = torch.tensor(np.ascontiguousarray(U.real), dtype=torch.float64, device=self.device)
+        self.uim = torch.tensor(np.ascontiguousarray(U.imag), dtype=torch.float64, device=self.device)
+        # a first model is needed to validate the patterns against M
+        self.ctx.gbs_set_model(U, np.zeros(M), np.ones(M))
+        self.plan = self.ctx.gbs_plan_create(offsets, modes, order)
+        self.P = len(offsets) - 1
+        self.freeze_plan = freeze_plan
+        self._ran = False
+
+    def _enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self, *tensors):
+        cur = torch.cuda.current_stream(self.device)
+        cur.wait_stream(self.stream)
+        for t in tensors:
+            t.record_stream(self.stream)
+
+    def forward_raw(self, r: torch.Tensor, eta: torch.Tensor) -> torch.Tensor:
+        logp = torch.empty(self.P, dtype=torch.float64, device=self.device)
+        status = torch.empty(self.P, dtype=torch.int32, device=self.device)
+        r = r.detach().contiguous()
+        eta = eta.detach().contiguous()
+        self._enter()
+        self.ctx.gbs_set_model_dev(self.ure, self.uim, r, eta)
+        self.ctx.gbs_prob_approx_dev(self.plan, logp, status)
+        self._leave(logp, status, r, eta)
+        if not self._ran and self.freeze_plan:
+            self.stream.synchronize()
+            self.plan.freeze(True)
+        self._ran = True
+        return logp
+
+    def backward_raw(self, r, eta, dl):
+        gr = torch.empty(self.M, dtype=torch.float64, device=self.device)
+        ge = torch.empty(self.M, dtype=torch.float64, device=self.device)
+        logp = torch.empty(self.P, dtype=torch.float64, device=self.device)
+        status = torch.empty(self.P, dtype=torch.int32, device=self.device)
+        r = r.detach().contiguous()
+        eta = eta.detach().contiguous()
+        dl = dl.detach().to(torch.float64).contiguous()
+        self._enter()
+        self.ctx.gbs_set_model_dev(self.ure, self.uim, r, eta)
+        self.ctx.gbs_grad_dev(self.plan, dl, logp, gr, ge, status)
+        self._leave(gr, ge, logp, status, r, eta, dl)
+        return gr, ge
+
+    def __call__(self, r: torch.Tensor, eta: torch.Tensor) -> torch.Tensor:
+        return ClickLogProb.apply(r, eta, self)
+
+
+class ClickLogProb(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, r, eta, model: ClickModel):
+        ctx.model = model
+        ctx.save_for_backward(r, eta)
+        return model.forward_raw(r, eta)
+
+    @staticmethod
+    def backward(ctx, grad_logp):
+        r, eta = ctx.saved_tensors
+        gr, ge = ctx.model.backward_raw(r, eta, grad_logp)
+        return gr, ge, None
