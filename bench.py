@@ -41,6 +41,19 @@ def contour_point_flops(n: int, order: int) -> float:
     return f
 
 
+def adjoint_point_flops(n: int, order: int) -> float:
+    """Algorithmic real flops per contour point of the adjoint: M(w) again, the
+    cluster determinants again with their inverses scattered into Z(w) (56, 280,
+    620 flops for 1, 2, 3 modes), and V^T Z V (4 N^3 for Z V, 2 N^2 (N+1) for
+    the upper triangle of V^T (Z V)), N = 2n."""
+    N = 2 * n
+    f = 8.0 * n * n * (2 * n + 1) + 20.0 * N + 4.0 * N ** 3 + 2.0 * N * N * (N + 1)
+    per = {1: 56.0, 2: 280.0, 3: 620.0}
+    for t in range(1, order + 1):
+        f += per[t] * comb(n, t)
+    return f
+
+
 def cpu_baseline(wl, gpu_logp, budget_s: float = 20.0):
     """The oracle as it stands, single-threaded, on a bounded sample of rows
     spread over the click-count range; returns rows/s and the GPU's error on
@@ -92,18 +105,26 @@ def exact_leg(ctx, steps: int = 3):
             "max_kappa": float(out["kappa"].max()), "status_nonzero": int(np.sum(out["status"] != 0))}
 
 
-def load_traffic(kernel_src: str):
-    """HBM traffic of the contour kernel from the committed counter summary, if
-    it was taken on the current kernel source (hash match); else None."""
+def source_sha(paths):
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_contour_m70_order3.json")
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(srcs, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/traffic_m70_order3.json), if it was taken on the current kernel
+    sources (hash match); else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_m70_order3.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
-    if rec.get("source_sha") != h:
+    if rec.get("source_sha") != source_sha(srcs):
         return None
-    return rec.get("bytes_per_launch")
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
 
 
 def main():
@@ -136,57 +157,85 @@ def main():
     status = torch.empty(wl.P, dtype=torch.int32, device=dev)
     plan = ctx.gbs_plan_create(wl.offsets, wl.modes, wl.order)
 
-    def step():
+    dl = torch.ones(wl.P, dtype=torch.float64, device=dev)       # d/dtheta of sum_p log p_hat
+    gr = torch.empty(wl.M, dtype=torch.float64, device=dev)
+    ge = torch.empty(wl.M, dtype=torch.float64, device=dev)
+
+    def fwd():
         ctx.gbs_set_model_dev(ure, uim, r, eta)
         ctx.gbs_prob_approx_dev(plan, logp, status)
 
+    def fwd_grad():
+        ctx.gbs_set_model_dev(ure, uim, r, eta)
+        ctx.gbs_grad_dev(plan, dl, logp, gr, ge, status)
+
+    def timed(fn, steps):
+        ctx.gbs_timing()
+        ctx.gbs_set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tim = ctx.gbs_timing()
+        ctx.gbs_set_timing(False)
+        return (t1 - t0) * 1e3 / steps, tim
+
     for _ in range(args.warmup):
-        step()
+        fwd_grad()
     torch.cuda.synchronize()
     st = status.cpu().numpy()
     if np.any(st != 0):
         raise RuntimeError(f"{int(np.sum(st != 0))} rows with non-zero status")
+    if not np.all(np.isfinite(gr.cpu().numpy())) or not np.all(np.isfinite(ge.cpu().numpy())):
+        raise RuntimeError("non-finite gradient")
     info = plan.info()
-    ctx.gbs_timing()
-    ctx.gbs_set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    tim = ctx.gbs_timing()
-    ctx.gbs_set_timing(False)
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_fwd, tim_fwd = timed(fwd, args.steps)
+    ms_step, tim = timed(fwd_grad, args.steps)
     lp = logp.cpu().numpy()
 
     ns = np.diff(wl.offsets)
-    npts = info["K"] // 2 + 1
-    npts = npts.astype(np.float64)
+    npts = (info["K"] // 2 + 1).astype(np.float64)
     dets = float(sum(npts[i] * sum(comb(int(ns[i]), t) for t in range(1, wl.order + 1))
                      for i in range(wl.P)))
-    flops = float(sum(npts[i] * contour_point_flops(int(ns[i]), wl.order) for i in range(wl.P)))
-    c_ms = tim["contour_clusters"][0] / max(1, tim["contour_clusters"][1])
-    achieved = flops / (c_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "kernel": "k_contour (contour points x clusters, fp64)",
-            "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4),
-            "traffic": load_traffic(os.path.join(ROOT, "paper_2106_01445_amd", "csrc", "approx.hip")),
-            "kernel_ms": round(c_ms, 3), "flops_per_launch": flops}
+    fl_fwd = float(sum(npts[i] * contour_point_flops(int(ns[i]), wl.order) for i in range(wl.P)))
+    fl_adj = float(sum(npts[i] * adjoint_point_flops(int(ns[i]), wl.order) for i in range(wl.P)))
+    per = {k: v[0] / max(1, v[1]) for k, v in tim.items() if v[1]}
+    rates = {}
+    for key, fl, kname in (("contour_clusters", fl_fwd, "k_contour (forward contour points x clusters)"),
+                           ("adjoint_contour_clusters", fl_adj, "k_adj_contour (adjoint contour points x clusters)")):
+        ms = per.get(key, 0.0)
+        if ms > 0:
+            rates[key] = {"kernel": kname, "ms": ms, "flops": fl, "tflops": fl / (ms * 1e-3) / 1e12}
+    dom = max(rates.values(), key=lambda d: d["ms"])
+    src = [os.path.join(ROOT, "paper_2106_01445_amd", "csrc", f)
+           for f in ("approx.hip", "grad.hip", "contour_common.h", "cplx.h")]
+    roof = {"bound": "alu", "kernel": dom["kernel"],
+            "achieved": round(dom["tflops"], 3), "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(dom["tflops"] / PEAK_FP64_VALU_TFLOPS, 4),
+            "traffic": load_traffic(src, dom["kernel"].split()[0]),
+            "kernel_ms": round(dom["ms"], 3), "flops_per_launch": dom["flops"],
+            "all_kernels": {k: {"ms": round(v["ms"], 3), "tflops": round(v["tflops"], 3),
+                                "frac": round(v["tflops"] / PEAK_FP64_VALU_TFLOPS, 4)}
+                            for k, v in rates.items()}}
     out = {
         "metric": METRIC,
         "value": wl.P / (ms_step * 1e-3),
-        "unit": "click-pattern probs/s",
+        "unit": "click-pattern probs/s (forward + gradient)",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "m70_order3", "modes": 70, "squeezed_inputs": 35,
                    "r": "U[1.0,1.6]", "eta": 0.4, "patterns": wl.P, "clicks": "15-40",
-                   "order": wl.order, "pass": "forward"},
-        "subset_dets_per_s": dets / (ms_step * 1e-3),
+                   "order": wl.order, "pass": "model build + forward + adjoint (d sum log p / d r, eta)"},
+        "forward": {"ms_per_step": ms_fwd, "probs_per_s": wl.P / (ms_fwd * 1e-3),
+                    "subset_dets_per_s": dets / (ms_fwd * 1e-3),
+                    "kernel_ms": {k: round(v[0] / max(1, v[1]), 3) for k, v in tim_fwd.items() if v[1]}},
         "subset_dets_per_step": dets,
-        "kernel_ms_per_step": {k: round(v[0] / max(1, v[1]), 4) for k, v in tim.items() if v[1]},
+        "subset_dets_per_s_fwd_grad": 2 * dets / (ms_step * 1e-3),
+        "kernel_ms_per_step": {k: round(v, 3) for k, v in per.items()},
         "contour_points_per_step": int(npts.sum()),
         "roofline": roof,
     }

@@ -170,10 +170,13 @@ int gbs_plan_info(gbs_plan *plan, double *rho, double *rconv, int32_t *K, int32_
 /* Per-kernel timing.  With on = 1, every later launch on the context is
  * bracketed by HIP events recorded on the context's stream.  gbs_timing
  * synchronises the stream, writes the summed milliseconds per kernel group
- * since the last call into ms[8] and the launch counts into count[8] (0 model
- * build, 1 row set-up, 2 work-queue build, 3 contour/cluster, 4 DFT and fit,
- * 5 exact subsets, 6 adjoint of the fit and DFT, 7 adjoint of the clusters
- * and model), then clears the record.  Either array may be NULL. */
+ * since the last call into ms[GBS_TIMING_GROUPS] and the launch counts into
+ * count[GBS_TIMING_GROUPS] (0 model build, 1 row set-up, 2 work-queue build,
+ * 3 contour/cluster, 4 DFT and fit, 5 exact subsets, 6 adjoint of the fit and
+ * DFT, 7 adjoint of the contour/cluster step, 8 adjoint per row and its
+ * scatter into the mode pairs, 9 adjoint of the model build), then clears the
+ * record.  Either array may be NULL. */
+#define GBS_TIMING_GROUPS 10
 int gbs_set_timing(gbs_ctx *ctx, int on);
 int gbs_timing(gbs_ctx *ctx, double *ms, int32_t *count);
 

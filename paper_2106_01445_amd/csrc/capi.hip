@@ -84,7 +84,7 @@ void plan_free_dev(gbs_plan *pl)
                     pl->d_v, pl->d_rows, pl->d_sw, pl->d_items, pl->d_counter,
                     pl->d_cluster_items, pl->d_cluster_off, pl->d_logp, pl->d_status,
                     pl->d_asw, pl->d_aitems, pl->d_roff, pl->d_ritem0, pl->d_rscr,
-                    pl->d_abar, pl->d_qibar, pl->d_qitmp, pl->d_pos, pl->d_grad, pl->d_dl};
+                    pl->d_qibar, pl->d_qitmp, pl->d_grad, pl->d_dl};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -131,10 +131,6 @@ int adj_workspace(gbs_ctx *ctx, gbs_plan *pl)
         const size_t N = 2 * (size_t)pl->h_n[p];
         rtot += chunks * (N * (N + 1) / 2);
     }
-    std::vector<int16_t> pos((size_t)P * M, (int16_t)-1);
-    for (int p = 0; p < P; ++p)
-        for (int i = pl->h_offsets[p]; i < pl->h_offsets[p + 1]; ++i)
-            pos[(size_t)p * M + pl->h_modes[i]] = (int16_t)(i - pl->h_offsets[p]);
     const size_t D = 2 * (size_t)M;
     int e = 0;
     e = e ? e : dev_alloc(ctx, &pl->d_asw, (size_t)P * (order + 1) * GBS_QCAP);
@@ -142,15 +138,10 @@ int adj_workspace(gbs_ctx *ctx, gbs_plan *pl)
     e = e ? e : dev_alloc(ctx, &pl->d_roff, (size_t)P * chunks);
     e = e ? e : dev_alloc(ctx, &pl->d_ritem0, (size_t)P);
     e = e ? e : dev_alloc(ctx, &pl->d_rscr, rtot);
-    e = e ? e : dev_alloc(ctx, &pl->d_abar, pl->v_total);
     e = e ? e : dev_alloc(ctx, &pl->d_qibar, D * D);
     e = e ? e : dev_alloc(ctx, &pl->d_qitmp, D * D);
-    e = e ? e : dev_alloc(ctx, &pl->d_pos, pos.size());
     if (!pl->d_grad) e = e ? e : dev_alloc(ctx, &pl->d_grad, D);
     if (e) return e;
-    if (!pos.empty())
-        HIP_TRY(ctx, hipMemcpyAsync(pl->d_pos, pos.data(), pos.size() * sizeof(int16_t),
-                                    hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     pl->have_adj = true;
     return 0;
@@ -273,8 +264,8 @@ int gbs_timing(gbs_ctx *ctx, double *ms, int32_t *count)
     if (!ctx) return GBS_E_INVAL;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int32_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[GBS_TIMING_GROUPS] = {};
+    int32_t cnt[GBS_TIMING_GROUPS] = {};
     for (const TimedLaunch &t : ctx->timeline) {
         float e = 0.f;
         HIP_TRY(ctx, hipEventElapsedTime(&e, t.a, t.b));
@@ -284,7 +275,7 @@ int gbs_timing(gbs_ctx *ctx, double *ms, int32_t *count)
         ctx->event_pool.push_back(t.b);
     }
     ctx->timeline.clear();
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < GBS_TIMING_GROUPS; ++i) {
         if (ms) ms[i] = acc[i];
         if (count) count[i] = cnt[i];
     }

@@ -20,8 +20,8 @@
 //   k_adj_contour  per (row, 64 contour points): M(w) and the clusters again,
 //                  Z(w) by LDS atomics, V^T Z V in column panels, R in registers
 //   k_adj_reduce   per row: sum of the items' R in a fixed order, the
-//                  contour-independent terms, A_bar = V R V^T
-//   k_adj_scatter  adjoint of Q^{-1}: Psi[u][v] = sum_p A_bar_p at (u, v)
+//                  contour-independent terms, A_bar = V R V^T, added into the
+//                  adjoint of Q^{-1} at the row's mode pairs (global atomics)
 //   k_adj_model    Q_bar = -(sum w)/2 Q^{-1} - Q^{-1} Psi Q^{-1}, then sigma_bar,
 //                  and the chain to r and eta through the model build
 #include "contour_common.h"
@@ -620,9 +620,13 @@ __global__ __launch_bounds__(1024) void k_adj_items(int P, const int *__restrict
 // ---------------------------------------------------------------------------
 // k_adj_reduce: per row, R = sum of the items' R (fixed order) plus the
 // contour-independent diagonal term of log G_0(rho) and log P_vac(Cbar)
-// (their A^{-1} parts cancel, leaving -w_p rho/2 M(rho)), then A_bar = V R V^T.
+// (their A^{-1} parts cancel, leaving -w_p rho/2 M(rho)), then A_bar = V R V^T,
+// added into Psi at the row's mode pairs: Psi[u][v] = sum over rows holding
+// both modes of A_bar at their positions (global fp64 atomics; Psi cleared
+// before the launch).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_adj_reduce(const int *__restrict__ offsets,
+__global__ __launch_bounds__(256) void k_adj_reduce(int M, const int *__restrict__ offsets,
+                                                    const int *__restrict__ modes,
                                                     const long long *__restrict__ voff,
                                                     const double *__restrict__ alpha,
                                                     const double *__restrict__ vt,
@@ -631,7 +635,7 @@ __global__ __launch_bounds__(256) void k_adj_reduce(const int *__restrict__ offs
                                                     const int *__restrict__ row_item0,
                                                     const long long *__restrict__ roff,
                                                     const double *__restrict__ rscr,
-                                                    double *__restrict__ abar)
+                                                    double *__restrict__ psi)
 {
     extern __shared__ double sh[];
     const int p = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
@@ -640,18 +644,17 @@ __global__ __launch_bounds__(256) void k_adj_reduce(const int *__restrict__ offs
     const long long vo = voff[p];
     if (n == 0) return;
     const int it0 = row_item0[p];
-    if (it0 < 0 || rp.status != 0 || !isfinite(dl[p]) || dl[p] == 0.0) {
-        for (int i = tid; i < N * N; i += nt) abar[vo + i] = 0.0;
-        return;
-    }
+    if (it0 < 0 || rp.status != 0 || !isfinite(dl[p]) || dl[p] == 0.0) return;
     const int nit = (rp.K / 2 + 1 + ADJ_QCHUNK - 1) / ADJ_QCHUNK;
     double *V = sh;            // V[i][k] row-major
     double *R = V + N * N;     // full symmetric
     double *T = R + N * N;
+    int *g = (int *)(T + N * N);   // global index of the row's local index
     for (int idx = tid; idx < N * N; idx += nt) {
         const int k = idx / N, i = idx - k * N;
         V[i * N + k] = vt[vo + idx];
     }
+    for (int i = tid; i < N; i += nt) g[i] = modes[o + (i < n ? i : i - n)] + (i < n ? 0 : M);
     const int nup = N * (N + 1) / 2;
     for (int e = tid; e < nup; e += nt) {
         int i, j;
@@ -674,33 +677,13 @@ __global__ __launch_bounds__(256) void k_adj_reduce(const int *__restrict__ offs
         T[k * N + j] = s;
     }
     __syncthreads();
+    const long D = 2L * M;
     for (int idx = tid; idx < N * N; idx += nt) {
         const int i = idx / N, j = idx - i * N;
         double s = 0.0;
         for (int k = 0; k < N; ++k) s = fma(V[i * N + k], T[k * N + j], s);
-        abar[vo + idx] = s;
+        atomicAdd(&psi[g[i] * D + g[j]], s);
     }
-}
-
-// Psi[u][v] = sum over rows containing both modes of A_bar at their positions.
-__global__ void k_adj_scatter(int M, int P, const int *__restrict__ offsets,
-                              const long long *__restrict__ voff, const short *__restrict__ pos,
-                              const double *__restrict__ abar, double *__restrict__ psi)
-{
-    const int D = 2 * M;
-    const int v = blockIdx.x * blockDim.x + threadIdx.x, u = blockIdx.y;
-    if (v >= D || u >= D) return;
-    const int mu = u % M, mv = v % M, qu = u / M, qv = v / M;
-    double s = 0.0;
-    for (int p = 0; p < P; ++p) {
-        const int iu = pos[(long)p * M + mu];
-        if (iu < 0) continue;
-        const int iv = pos[(long)p * M + mv];
-        if (iv < 0) continue;
-        const int n = offsets[p + 1] - offsets[p], N = 2 * n;
-        s += abar[voff[p] + (long)(iu + qu * n) * N + (iv + qv * n)];
-    }
-    psi[(long)u * D + v] = s;
 }
 
 // Model adjoint, one workgroup: Q_bar = -(W/2) Q^{-1} - Q^{-1} Psi Q^{-1} with W the
@@ -761,25 +744,26 @@ __global__ __launch_bounds__(1024) void k_adj_model(int M, int P, const double *
     }
     __syncthreads();
     // eta_bar_m = (1/eta_m) sum_{i in quads(m)} sum_j sigma0_bar_ij sigma0_ij
-    //             - (sigma_bar_{m,m} + sigma_bar_{M+m,M+m}) / 2
+    //             - (sigma_bar_{m,m} + sigma_bar_{M+m,M+m}) / 2,
+    // with sum_j sigma0_bar_ij sigma0_ij = sum_k O_ik (lambda_k / 2) (sigma0_bar O)_ik,
+    // lambda = (e^{-2r}, e^{2r})
     for (int m = tid; m < M; m += nt) {
         double s = 0.0;
         for (int qd = 0; qd < 2; ++qd) {
             const int i = m + qd * M;
-            for (int j = 0; j < D; ++j) {
-                double s0 = 0.0;  // sigma0_ij
-                for (int k = 0; k < M; ++k) s0 = fma(O(i, k) * O(j, k), 0.5 * exp(-2.0 * r[k]), s0);
-                for (int k = 0; k < M; ++k) s0 = fma(O(i, M + k) * O(j, M + k), 0.5 * exp(2.0 * r[k]), s0);
-                s = fma(psi[(long)i * D + j] * sq(i) * sq(j), s0, s);
+            for (int k = 0; k < M; ++k) {
+                s = fma(O(i, k) * (0.5 * exp(-2.0 * r[k])), tmp[(long)i * D + k], s);
+                s = fma(O(i, M + k) * (0.5 * exp(2.0 * r[k])), tmp[(long)i * D + M + k], s);
             }
         }
         grad[M + m] = s / eta[m] - 0.5 * (psi[(long)m * D + m] + psi[(long)(M + m) * D + M + m]);
     }
 }
 
-__global__ void k_zero(int n, double *x)
+__global__ void k_zero(long n, double *x)
 {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0.0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        x[i] = 0.0;
 }
 
 template <int ORDER>
@@ -813,16 +797,19 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
     hipLaunchKernelGGL(k_adj_contour<ORDER>, dim3(occ * ctx->num_cu), dim3(CONT_THREADS), lds_a, st,
                        pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_aitems,
                        pl->d_counter, pl->d_asw, pl->d_roff, pl->d_rscr);
+    timer_end(ctx, ts);
+    ts = timer_begin(ctx, TG_ADJ_ROWS);
     const int N = 2 * nmax;
-    size_t lds_r = sizeof(double) * 3 * (size_t)N * N;
+    const int D = 2 * M;
+    hipLaunchKernelGGL(k_zero, dim3((D * D + 255) / 256), dim3(256), 0, st, (long)D * D, pl->d_qibar);
+    size_t lds_r = sizeof(double) * 3 * (size_t)N * N + sizeof(int) * N;
     HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_adj_reduce,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r));
-    hipLaunchKernelGGL(k_adj_reduce, dim3(P), dim3(256), lds_r, st, pl->d_offsets, pl->d_voff,
-                       pl->d_alpha, pl->d_v, pl->d_rows, dl, pl->d_ritem0, pl->d_roff, pl->d_rscr,
-                       pl->d_abar);
-    const int D = 2 * M;
-    hipLaunchKernelGGL(k_adj_scatter, dim3((D + 127) / 128, D), dim3(128), 0, st, M, P,
-                       pl->d_offsets, pl->d_voff, pl->d_pos, pl->d_abar, pl->d_qibar);
+    hipLaunchKernelGGL(k_adj_reduce, dim3(P), dim3(256), lds_r, st, M, pl->d_offsets, pl->d_modes,
+                       pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, dl, pl->d_ritem0, pl->d_roff,
+                       pl->d_rscr, pl->d_qibar);
+    timer_end(ctx, ts);
+    ts = timer_begin(ctx, TG_ADJ_MODEL);
     hipLaunchKernelGGL(k_adj_model, dim3(1), dim3(1024), 0, st, M, P, m.qi_hi, m.params, dl,
                        status, pl->d_qibar, pl->d_qitmp, pl->d_grad);
     timer_end(ctx, ts);
@@ -842,8 +829,8 @@ int approx_backward(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, const int3
     int rc = adj_workspace(ctx, pl);
     if (rc) return rc;
     if (pl->P == 0) {
-        hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, ctx->stream, ctx->model.M, grad_r_dev);
-        hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, ctx->stream, ctx->model.M, grad_eta_dev);
+        hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, ctx->stream, (long)ctx->model.M, grad_r_dev);
+        hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, ctx->stream, (long)ctx->model.M, grad_eta_dev);
         HIP_TRY(ctx, hipGetLastError());
         return 0;
     }

@@ -55,7 +55,7 @@ struct gbs_ctx {
 int timer_begin(gbs_ctx *ctx, int group);
 void timer_end(gbs_ctx *ctx, int slot);
 enum { TG_MODEL = 0, TG_PREP = 1, TG_ITEMS = 2, TG_CONTOUR = 3, TG_FIT = 4, TG_EXACT = 5,
-       TG_ADJ_FIT = 6, TG_ADJ_CLUSTER = 7 };
+       TG_ADJ_FIT = 6, TG_ADJ_CLUSTER = 7, TG_ADJ_ROWS = 8, TG_ADJ_MODEL = 9 };
 
 // Per-row scalar results of the approximate path's set-up step.
 struct RowPlan {
@@ -92,10 +92,8 @@ struct gbs_plan {
     long long *d_roff = nullptr;          // per item: offset of its R in d_rscr
     int32_t *d_ritem0 = nullptr;          // per row: first backward item
     double *d_rscr = nullptr;             // per item: upper triangle of R
-    double *d_abar = nullptr;             // per row adjoint of A (2n)^2, offsets d_voff
-    double *d_qibar = nullptr;            // (2M)^2 adjoint of Q^{-1}, then sigma_bar
+    double *d_qibar = nullptr;            // (2M)^2: Psi (adjoint of Q^{-1}), then sigma_bar
     double *d_qitmp = nullptr;            // (2M)^2 scratch
-    int16_t *d_pos = nullptr;             // [P][M] position of a mode in the row, -1 if absent
     double *d_grad = nullptr;             // 2M: grad r, grad eta
     double *d_dl = nullptr;               // P
 };

@@ -26,7 +26,8 @@ EXPORTS = ["gbs_create", "gbs_destroy", "gbs_last_error", "gbs_set_model", "gbs_
            "gbs_grad", "gbs_grad_dev", "gbs_plan_info", "gbs_set_timing", "gbs_timing",
            "gbs_stream"]
 TIMING_GROUPS = ["model", "row_setup", "work_queue", "contour_clusters", "dft_fit", "exact",
-                 "adjoint_fit_dft", "adjoint_clusters_model"]
+                 "adjoint_fit_dft", "adjoint_contour_clusters", "adjoint_rows_scatter",
+                 "adjoint_model"]
 
 _lib = None
 
@@ -178,8 +179,8 @@ class Context:
 
     def gbs_timing(self):
         """{group: (total ms, launches)} since the last call (synchronises)."""
-        ms = np.zeros(8)
-        cnt = np.zeros(8, np.int32)
+        ms = np.zeros(len(TIMING_GROUPS))
+        cnt = np.zeros(len(TIMING_GROUPS), np.int32)
         self._check(load().gbs_timing(self.handle, _ptr(ms), _ptr(cnt)))
         return {g: (float(ms[i]), int(cnt[i])) for i, g in enumerate(TIMING_GROUPS)}
 

@@ -33,6 +33,15 @@ def test_library_exports_every_declared_symbol():
     assert set(gbs.EXPORTS) == set(declared_functions())
 
 
+def test_timing_groups_match_header():
+    """The binding's timing buffers are sized from its group list; the library
+    writes GBS_TIMING_GROUPS entries."""
+    from paper_2106_01445_amd import gbs
+    text = open(os.path.join(ROOT, "include", "gbs.h")).read()
+    n = int(re.search(r"#define\s+GBS_TIMING_GROUPS\s+(\d+)", text).group(1))
+    assert len(gbs.TIMING_GROUPS) == n
+
+
 def test_binding_fails_loudly_without_library(tmp_path):
     from paper_2106_01445_amd import gbs
     saved = gbs._lib
