@@ -134,6 +134,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-exact", action="store_true", help="skip the 20-mode exact leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 3 times (calibrates the "
+                         "HBM byte counters against a kernel of known traffic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path "
@@ -141,6 +144,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": a.numel() * 8, "copy_probe_bytes_written": b.numel() * 8,
+                          "dispatches": 3}), flush=True)
+        return
     import paper_2106_01445_amd as g
     from workloads import make_workload
 

@@ -242,9 +242,10 @@ __global__ __launch_bounds__(1024) void k_build_items(int P, const int *__restri
 //
 // LDS layout of M(w): the diagonal blocks (a,a) and the blocks (a,b), a < b,
 // column-major (index b(b-1)/2 + a), each of the 3 or 4 entries in its own
-// array.  A lane owns one mode pair (a,b) (pair index = block index) and loops
-// over the third mode c > b; neighbouring lanes own consecutive a of the same
-// b, so every read of the triple loop is either a broadcast (blocks (b,c),
+// array.  The clusters come as work units (pair (a,b) and a segment [c0, c1) of
+// third modes c > b, listed longest first); the threads of a slot group take
+// units in turn.  Neighbouring lanes mostly hold consecutive a of the same b
+// and segment, so the reads of the triple loop are broadcasts (blocks (b,c),
 // (c,c)) or consecutive across lanes (block (a,c)).
 // ---------------------------------------------------------------------------
 template <int ORDER>
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
     int lds_bytes, const int *__restrict__ offsets, const long long *__restrict__ voff,
     const double *__restrict__ alpha, const double *__restrict__ vt,
     const RowPlan *__restrict__ rows, const int *__restrict__ items, int *__restrict__ counter,
-    cplx *__restrict__ sw)
+    const int *__restrict__ units, const int *__restrict__ unit_off, cplx *__restrict__ sw)
 {
     extern __shared__ double sh[];
     __shared__ int s_item;
@@ -365,12 +366,15 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                     s1 = cadd(s1, crsqrt_p(cfnma(a01, a01, cmul(a00, a11))));
                 }
                 if (ORDER >= 2) {
+                    const int *un = units + unit_off[2 * n];
+                    const int nu = unit_off[2 * n + 1];
+                    int unext = lt < nu ? un[lt] : 0;
 #pragma unroll 1
-                    for (int pi = lt; pi < np; pi += SG) {
-                        int b = (int)floor(0.5 * (1.0 + sqrt(1.0 + 8.0 * pi)));
-                        while (b * (b - 1) / 2 > pi) --b;
-                        while ((b + 1) * b / 2 <= pi) ++b;
-                        const int a = pi - b * (b - 1) / 2;
+                    for (int ui = lt; ui < nu; ui += SG) {
+                        const unsigned u = (unsigned)unext;
+                        if (ui + SG < nu) unext = un[ui + SG];
+                        const int a = u & 255, b = (u >> 8) & 255, c0 = (u >> 16) & 255, c1 = u >> 24;
+                        const int pi = b * (b - 1) / 2 + a;
                         const cplx a00 = m.d0[a], a01 = m.d1[a], a11 = m.d2[a];
                         const cplx b00 = m.o0[pi], b01 = m.o1[pi], b10 = m.o2[pi], b11 = m.o3[pi];
                         const cplx bb00 = m.d0[b], bb01 = m.d1[b], bb11 = m.d2[b];
@@ -391,7 +395,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                         const cplx detb = cfnma(sb01, sb01, cmul(sb00, sb11));
                         const cplx rb = crsqrt_p(detb);
                         const cplx rab = cmul(ra, rb);
-                        s2 = cadd(s2, rab);
+                        if (c0 == b + 1) s2 = cadd(s2, rab);
                         if (ORDER >= 3) {
                             const cplx idetb = cmul(rb, rb);
                             const cplx ib00 = cmul(sb11, idetb), ib11 = cmul(sb00, idetb);
@@ -399,7 +403,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                                                   -(sb01.re * idetb.im + sb01.im * idetb.re));
                             cplx s3p = cmk(0, 0);
 #pragma unroll 1
-                            for (int c = b + 1; c < n; ++c) {
+                            for (int c = c0; c < c1; ++c) {
                                 const int cb = c * (c - 1) / 2;
                                 const int iac = cb + a, ibc = cb + b;
                                 // Sc = Mcc - Xa^T Maa^{-1} Xa - Y^T Sb^{-1} Y, Y = Xb - G^T Xa,
@@ -611,7 +615,7 @@ int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
     ts = timer_begin(ctx, TG_CONTOUR);
     hipLaunchKernelGGL(k_contour<ORDER>, dim3(grid), dim3(CONT_THREADS), lds_c, st, lds_c,
                        pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_items,
-                       pl->d_counter, pl->d_sw);
+                       pl->d_counter, pl->d_cluster_items, pl->d_cluster_off, pl->d_sw);
     timer_end(ctx, ts);
     size_t lds_f = sizeof(cplx) * (GBS_KMAX + GBS_KMAX / 2);
     HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_dft_fit<ORDER>,

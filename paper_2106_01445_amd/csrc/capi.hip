@@ -89,21 +89,42 @@ void plan_free_dev(gbs_plan *pl)
         if (p) (void)hipFree(p);
 }
 
-// Cluster work items for rows with n clicks: (a, b, c0, c1 | first << 16) for
-// each pair a < b, the third mode c split in chunks of 8 (order 3).
-void cluster_items(int n, int order, std::vector<int32_t> &out)
+// Cluster work units for rows with n clicks (orders 2 and 3), one packed int
+// each: a | b << 8 | c0 << 16 | c1 << 24.  A unit is the pair a < b plus the
+// triples (a, b, c) for c in [c0, c1); the unit with c0 = b + 1 also carries the
+// pair itself.  At order 3 the range c > b is cut into segments of
+// GBS_CLUSTER_SEG, so that no thread of a slot group waits for one long pair;
+// units are listed by decreasing length, then (b, c0, a) for the forward
+// (neighbouring lanes read neighbouring blocks of M(w)) or (a, b, c0) for the
+// adjoint (neighbouring lanes scatter into different blocks of Z(w)), so that a
+// strided assignment to threads is balanced.
+void cluster_units(int n, int order, bool adjoint, std::vector<int32_t> &out)
 {
+    struct U { int a, b, c0, c1; };
+    std::vector<U> u;
     for (int b = 1; b < n; ++b)
         for (int a = 0; a < b; ++a) {
             if (order < 3 || b == n - 1) {
-                out.insert(out.end(), {a, b, n, n | (1 << 16)});
+                u.push_back({a, b, b + 1, b + 1});
                 continue;
             }
-            for (int c0 = b + 1; c0 < n; c0 += 8) {
-                int c1 = std::min(c0 + 8, n);
-                out.insert(out.end(), {a, b, c0, c1 | ((c0 == b + 1 ? 1 : 0) << 16)});
-            }
+            for (int c0 = b + 1; c0 < n; c0 += GBS_CLUSTER_SEG)
+                u.push_back({a, b, c0, std::min(c0 + GBS_CLUSTER_SEG, n)});
         }
+    std::stable_sort(u.begin(), u.end(), [adjoint](const U &x, const U &y) {
+        if (x.c1 - x.c0 != y.c1 - y.c0) return x.c1 - x.c0 > y.c1 - y.c0;
+        if (adjoint) {
+            if (x.a != y.a) return x.a < y.a;
+            if (x.b != y.b) return x.b < y.b;
+            return x.c0 < y.c0;
+        }
+        if (x.b != y.b) return x.b < y.b;
+        if (x.c0 != y.c0) return x.c0 < y.c0;
+        return x.a < y.a;
+    });
+    for (const U &x : u)
+        out.push_back((int32_t)((unsigned)x.a | (unsigned)x.b << 8 | (unsigned)x.c0 << 16 |
+                                (unsigned)x.c1 << 24));
 }
 
 template <class T>
@@ -366,11 +387,14 @@ int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
     // cluster work lists for every click count up to max_n
     std::vector<int32_t> citems, coff(2 * (pl->max_n + 1), 0);
     for (int n = 0; n <= pl->max_n; ++n) {
-        coff[2 * n] = (int32_t)(citems.size() / 4);
-        if (order >= 2) cluster_items(n, order, citems);
-        coff[2 * n + 1] = (int32_t)(citems.size() / 4) - coff[2 * n];
+        coff[2 * n] = (int32_t)citems.size();
+        if (order >= 2) cluster_units(n, order, false, citems);
+        coff[2 * n + 1] = (int32_t)citems.size() - coff[2 * n];
     }
-    pl->n_cluster_items = (int)(citems.size() / 4);
+    pl->n_cluster_items = (int)citems.size();
+    // the adjoint's ordering of the same units follows, at the same offsets + total
+    for (int n = 0; n <= pl->max_n; ++n)
+        if (order >= 2) cluster_units(n, order, true, citems);
     long long max_items = (long long)P * ((GBS_QCAP + GBS_QCHUNK - 1) / GBS_QCHUNK);
     pl->max_items = (int)max_items;
     int e = 0;

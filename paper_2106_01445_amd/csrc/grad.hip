@@ -17,7 +17,9 @@
 //                  each fit differentiated (implicitly: d log q / dm = -H^{-1} m,
 //                  H the covariance of the fitted basis); the sector cotangents
 //                  pushed back through the FFT to alpha_t(w_q)
-//   k_adj_contour  per (row, 64 contour points): M(w) and the clusters again,
+//   k_adj_contour  per (row, 64 contour points): M(w) and the clusters again
+//                  (the same work units as the forward, in an order that spreads
+//                  neighbouring lanes over different blocks of Z(w)),
 //                  Z(w) by LDS atomics, V^T Z V in column panels, R in registers
 //   k_adj_reduce   per row: sum of the items' R in a fixed order, the
 //                  contour-independent terms, A_bar = V R V^T, added into the
@@ -219,6 +221,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
     const int *__restrict__ offsets, const long long *__restrict__ voff,
     const double *__restrict__ alpha, const double *__restrict__ vt,
     const RowPlan *__restrict__ rows, const int *__restrict__ items, int *__restrict__ counter,
+    const int *__restrict__ units, const int *__restrict__ unit_off,
     const cplx *__restrict__ asw, const long long *__restrict__ roff, double *__restrict__ rscr)
 {
     extern __shared__ double sh[];
@@ -339,12 +342,15 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             if (ORDER >= 2) {
                 const cplx g2 = s_g[2 <= ORDER ? 2 : 0];
                 const cplx g3 = s_g[3 <= ORDER ? 3 : 0];
+                const int *un = units + unit_off[2 * n];
+                const int nu = unit_off[2 * n + 1];
+                int unext = tid < nu ? un[tid] : 0;
 #pragma unroll 1
-                for (int pi = tid; pi < np; pi += CONT_THREADS) {
-                    int b = (int)floor(0.5 * (1.0 + sqrt(1.0 + 8.0 * pi)));
-                    while (b * (b - 1) / 2 > pi) --b;
-                    while ((b + 1) * b / 2 <= pi) ++b;
-                    const int a = pi - b * (b - 1) / 2;
+                for (int ui = tid; ui < nu; ui += CONT_THREADS) {
+                    const unsigned u = (unsigned)unext;
+                    if (ui + CONT_THREADS < nu) unext = un[ui + CONT_THREADS];
+                    const int a = u & 255, b = (u >> 8) & 255, c0 = (u >> 16) & 255, c1 = u >> 24;
+                    const int pi = b * (b - 1) / 2 + a;
                     const cplx a00 = Md0[a], a01 = Md1[a], a11 = Md2[a];
                     const cplx b00 = Mo0[pi], b01 = Mo1[pi], b10 = Mo2[pi], b11 = Mo3[pi];
                     const cplx deta = cfnma(a01, a01, cmul(a00, a11));
@@ -364,16 +370,17 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                     const cplx idetb = cmul(rb, rb);
                     const cplx ib00 = cmul(sb11, idetb), ib11 = cmul(sb00, idetb);
                     const cplx ib01 = cscale(cmul(sb01, idetb), -1.0);
-                    // coefficient of P^{-1} (pair itself plus sum over its triples) and the
-                    // pair block of sum_c c_T U Sc^{-1} U^T (4x4 symmetric, 10 entries)
-                    cplx cp = cmul(g2, rab);
+                    // coefficient of P^{-1} (the pair itself, carried by its first unit,
+                    // plus the unit's triples) and the pair block of
+                    // sum_c c_T U Sc^{-1} U^T (4x4 symmetric, 10 entries)
+                    cplx cp = c0 == b + 1 ? cmul(g2, rab) : cmk(0.0, 0.0);
                     bsum = cadd(bsum, cp);
                     cplx A00 = cmk(0, 0), A01 = cmk(0, 0), A02 = cmk(0, 0), A03 = cmk(0, 0),
                          A11 = cmk(0, 0), A12 = cmk(0, 0), A13 = cmk(0, 0), A22 = cmk(0, 0),
                          A23 = cmk(0, 0), A33 = cmk(0, 0);
                     if (ORDER >= 3) {
 #pragma unroll 1
-                        for (int c = b + 1; c < n; ++c) {
+                        for (int c = c0; c < c1; ++c) {
                             const int cb = c * (c - 1) / 2;
                             const int iac = cb + a, ibc = cb + b;
                             // Za = Maa^{-1} Xa, Y = Xb - G^T Xa, W = Sb^{-1} Y,
@@ -796,7 +803,8 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
     if (occ < 1) occ = 1;
     hipLaunchKernelGGL(k_adj_contour<ORDER>, dim3(occ * ctx->num_cu), dim3(CONT_THREADS), lds_a, st,
                        pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_aitems,
-                       pl->d_counter, pl->d_asw, pl->d_roff, pl->d_rscr);
+                       pl->d_counter, pl->d_cluster_items + pl->n_cluster_items, pl->d_cluster_off,
+                       pl->d_asw, pl->d_roff, pl->d_rscr);
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_ADJ_ROWS);
     const int N = 2 * nmax;

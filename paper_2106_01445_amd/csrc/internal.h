@@ -14,6 +14,7 @@
 #define GBS_KMAX 2048          // contour size cap
 #define GBS_QCAP (GBS_KMAX / 2 + 1)
 #define GBS_QCHUNK 8           // contour points per work item
+#define GBS_CLUSTER_SEG 3      // triples per cluster work unit (order 3)
 
 struct cplx {
     double re, im;
@@ -78,7 +79,8 @@ struct gbs_plan {
     cplx *d_sw = nullptr;                 // (order+1) * QCAP per row: sums over clusters
     int32_t *d_items = nullptr;           // work items (row, chunk), 2 ints each
     int32_t *d_counter = nullptr;         // [0] items total, [1] queue head
-    int32_t *d_cluster_items = nullptr;   // per click count n: (a, b, c0, c1) lists
+    int32_t *d_cluster_items = nullptr;   // per click count n: packed cluster units (a, b, c0, c1),
+                                          // forward order, then adjoint order (+ n_cluster_items)
     int32_t *d_cluster_off = nullptr;     // [n] -> offset, count (2 ints)
     double *d_logp = nullptr;             // P (scratch when caller passes none)
     int32_t *d_status = nullptr;          // P
