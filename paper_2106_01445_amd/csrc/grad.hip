@@ -28,8 +28,9 @@
 //                  and the chain to r and eta through the model build
 #include "contour_common.h"
 
+#include <algorithm>
+
 #define ADJ_QCHUNK 64
-#define ADJ_MAXOWN 8   // upper-triangle entries of R per thread: (2n)(2n+1)/2 <= 8 * 512
 
 namespace {
 
@@ -200,6 +201,27 @@ __host__ __device__ __forceinline__ int adj_vbytes(int n) { return 8 * (2 * n * 
 // per q: d, rz (2n each), M blocks (3n + 4 n(n-1)/2), Z blocks (same)
 __host__ __device__ __forceinline__ int adj_mbytes(int n) { return 16 * (4 * n + 2 * (3 * n + 2 * n * (n - 1))); }
 __host__ __device__ __forceinline__ int adj_fixed() { return 16 * (CONT_THREADS / 64 + 8); }
+// Y = Z V is formed by column panels of ADJ_PW columns (row stride ADJ_PWS,
+// complex); the panel reuses the region of M(w) when it fits there, else it
+// follows Z(w).
+#define ADJ_PW 32
+#define ADJ_PWS 33
+__host__ __device__ __forceinline__ bool adj_panel_in_m(int n)
+{
+    return 2 * n * ADJ_PWS <= 3 * n + 2 * n * (n - 1);
+}
+__host__ __device__ __forceinline__ int adj_need(int n)
+{
+    return adj_vbytes(n) + adj_mbytes(n) + (adj_panel_in_m(n) ? 0 : 16 * 2 * n * ADJ_PWS);
+}
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+// one 16x16x4 fp64 MFMA step, D += A B.  Lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; element e of D sits at row 4e + l/16, column l%16.
+__device__ __forceinline__ dbl4 mfma4(double a, double b, dbl4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 __device__ __forceinline__ void catomic(cplx *dst, cplx v)
 {
@@ -231,6 +253,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
     cplx *red = (cplx *)sh;                        // [waves]
     double *dyn = (double *)(red + CONT_THREADS / 64 + 8);
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
     const int total = counter[2];
     for (;;) {
         if (tid == 0) s_item = atomicAdd(&counter[3], 1);
@@ -250,7 +273,6 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         cplx *Mo0 = Md2 + n, *Mo1 = Mo0 + np, *Mo2 = Mo1 + np, *Mo3 = Mo2 + np;
         cplx *Zd0 = Mo3 + np, *Zd1 = Zd0 + n, *Zd2 = Zd1 + n;
         cplx *Zo0 = Zd2 + n, *Zo1 = Zo0 + np, *Zo2 = Zo1 + np, *Zo3 = Zo2 + np;
-        cplx *Yp = Md0;                      // column panel of Z V (reuses M after the clusters)
         const long long vo = voff[p];
         for (int idx = tid; idx < N * N; idx += CONT_THREADS) {
             const int k = idx / N, i = idx - k * N;
@@ -259,10 +281,22 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
         const int Qn = rp.K / 2 + 1;
         const int q0 = ch * ADJ_QCHUNK, q1 = min(q0 + ADJ_QCHUNK, Qn);
-        const int nup = N * (N + 1) / 2;
-        double racc[ADJ_MAXOWN];
+        // R in registers: the upper triangle of 16x16 tiles (it <= jt), tile u of
+        // the column-major tile list is held by wave u % 8 (at most 15 tiles)
+        const int T = (N + 15) >> 4, KS = (N + 3) >> 2, ntile = T * (T + 1) / 2;
+        cplx *Yp = adj_panel_in_m(n) ? Md0 : Zo3 + np;
+        int tit[2], tjt[2];
 #pragma unroll
-        for (int m = 0; m < ADJ_MAXOWN; ++m) racc[m] = 0.0;
+        for (int m = 0; m < 2; ++m) {
+            const int u = wid + 8 * m;
+            int jt = 0;
+            while ((jt + 1) * (jt + 2) / 2 <= u) ++jt;
+            tjt[m] = u < ntile ? jt : -1;
+            tit[m] = u - jt * (jt + 1) / 2;
+        }
+        dbl4 racc[2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) racc[m] = dbl4{0.0, 0.0, 0.0, 0.0};
         __syncthreads();
         for (int q = q0; q < q1; ++q) {
             if (tid == 0) {
@@ -484,74 +518,93 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 s_beta = bt;
             }
             __syncthreads();
-            // R += Re[(w/2) d_i d_j (V^T Z V)_ij] (+ diagonal beta terms), by
-            // column panels of 16: Y = Z V[:, J] into LDS, then owners of R entries
+            // R += Re[(w/2) d_i d_j (V^T Z V)_ij] (+ diagonal beta terms) on the
+            // matrix cores: by rounds of two 16-column tiles jt, Y = Z V for those
+            // columns into LDS, then X = V^T Y for the owned tiles (it, jt)
             const cplx beta = s_beta;
             const cplx hw = cscale(w, 0.5);
-            // panel width: Y (N x PW complex) must fit in M's region (2n^2 + n complex)
-            const int PW = n < 16 ? n : 16;
-            for (int J = 0; J < N; J += PW) {
-                const int nj = min(PW, N - J);
-                for (int idx = tid; idx < N * nj; idx += CONT_THREADS) {
-                    const int r = idx / nj, jl = idx - r * nj;
+            for (int jr = 0; jr < T; jr += 2) {
+                const int nj = min(2, T - jr);
+                for (int ch = wid; ch < nj * T; ch += CONT_THREADS / 64) {
+                    const int jt = jr + ch / T, rt = ch - (ch / T) * T;
+                    const int r = rt * 16 + l16, j = jt * 16 + l16;
+                    const bool rok = r < N, jok = j < N;
                     const int a = r < n ? r : r - n, qa = r < n ? 0 : 1;
-                    const int j = J + jl;
-                    cplx acc = cmk(0.0, 0.0);
-#pragma unroll 1
-                    for (int b = 0; b < n; ++b) {
-                        cplx zx, zp;
-                        if (a < b) {
-                            const int e = b * (b - 1) / 2 + a;
-                            zx = qa ? Zo2[e] : Zo0[e];
-                            zp = qa ? Zo3[e] : Zo1[e];
-                        } else if (a > b) {
-                            const int e = a * (a - 1) / 2 + b;
-                            zx = qa ? Zo1[e] : Zo0[e];
-                            zp = qa ? Zo3[e] : Zo2[e];
-                        } else {
-                            zx = qa ? Zd1[a] : Zd0[a];
-                            zp = qa ? Zd2[a] : Zd1[a];
-                        }
-                        const double vx = Vt[j * NP + b], vp = Vt[j * NP + n + b];
-                        acc.re = fma(zx.re, vx, fma(zp.re, vp, acc.re));
-                        acc.im = fma(zx.im, vx, fma(zp.im, vp, acc.im));
+                    dbl4 yre = {0.0, 0.0, 0.0, 0.0}, yim = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+                    for (int ks = 0; ks < KS; ++ks) {
+                        const int sidx = ks * 4 + lq;
+                        const bool ok = rok && sidx < N;
+                        const int b = sidx < n ? sidx : sidx - n, qb = sidx < n ? 0 : 1;
+                        const int lo = min(a, b), hi = max(a, b);
+                        const int kq = a < b ? 2 * qa + qb : 2 * qb + qa;
+                        // Zd0..Zd2 (stride n) are followed by Zo0..Zo3 (stride np)
+                        int off = a == b ? (qa + qb) * n + a : 3 * n + kq * np + hi * (hi - 1) / 2 + lo;
+                        off = ok ? off : 0;
+                        const cplx zl = Zd0[off];
+                        const cplx z = ok ? zl : cmk(0.0, 0.0);
+                        const bool vok = jok && sidx < N;
+                        const double vl = Vt[vok ? j * NP + sidx : 0];
+                        const double v = vok ? vl : 0.0;
+                        yre = mfma4(z.re, v, yre);
+                        yim = mfma4(z.im, v, yim);
                     }
-                    Yp[r * PW + jl] = acc;
+                    const int col = (jt - jr) * 16 + l16;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int row = rt * 16 + 4 * e + lq;
+                        if (row < N) Yp[row * ADJ_PWS + col] = cmk(yre[e], yim[e]);
+                    }
                 }
                 __syncthreads();
 #pragma unroll
-                for (int m = 0; m < ADJ_MAXOWN; ++m) {
-                    const int e = tid + CONT_THREADS * m;
-                    if (e >= nup) break;
-                    int i, j;
-                    upper_ij(e, i, j);
-                    if (j < J || j >= J + nj) continue;
-                    const int jl = j - J;
-                    cplx zt = cmk(0.0, 0.0);
-                    for (int s = 0; s < N; ++s) {
-                        const double v = Vt[i * NP + s];
-                        const cplx y = Yp[s * PW + jl];
-                        zt.re = fma(v, y.re, zt.re);
-                        zt.im = fma(v, y.im, zt.im);
+                for (int m = 0; m < 2; ++m) {
+                    const int it = tit[m], jt = tjt[m];
+                    if (jt < jr || jt >= jr + nj) continue;
+                    const int i = it * 16 + l16, col = (jt - jr) * 16 + l16;
+                    const bool iok = i < N;
+                    dbl4 xre = {0.0, 0.0, 0.0, 0.0}, xim = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+                    for (int ks = 0; ks < KS; ++ks) {
+                        const int sidx = ks * 4 + lq;
+                        const bool sok = sidx < N, vok = iok && sok;
+                        const double vl = Vt[vok ? i * NP + sidx : 0];
+                        const double v = vok ? vl : 0.0;
+                        const cplx yl = Yp[sok ? sidx * ADJ_PWS + col : 0];
+                        const cplx y = sok ? yl : cmk(0.0, 0.0);
+                        xre = mfma4(v, y.re, xre);
+                        xim = mfma4(v, y.im, xim);
                     }
-                    const cplx f = cmul(hw, cmul(dk[i], dk[j]));
-                    double add = f.re * zt.re - f.im * zt.im;
-                    if (i == j) {
-                        const double dr = 1.0 / (1.0 + rp.rho * (al[i] - 1.0));
-                        const cplx t = cmk(0.5 * rp.rho * dr - hw.re * dk[i].re + hw.im * dk[i].im,
-                                           -(hw.re * dk[i].im + hw.im * dk[i].re));
-                        add += beta.re * t.re - beta.im * t.im;
+                    const int jj = jt * 16 + l16;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int ii = it * 16 + 4 * e + lq;
+                        if (ii <= jj && jj < N) {
+                            const cplx f = cmul(hw, cmul(dk[ii], dk[jj]));
+                            double add = f.re * xre[e] - f.im * xim[e];
+                            if (ii == jj) {
+                                const double dr = 1.0 / (1.0 + rp.rho * (al[ii] - 1.0));
+                                const cplx t = cmk(0.5 * rp.rho * dr - hw.re * dk[ii].re + hw.im * dk[ii].im,
+                                                   -(hw.re * dk[ii].im + hw.im * dk[ii].re));
+                                add += beta.re * t.re - beta.im * t.im;
+                            }
+                            racc[m][e] += add;
+                        }
                     }
-                    racc[m] += add;
                 }
                 __syncthreads();
             }
         }
         const long long ro = roff[item];
 #pragma unroll
-        for (int m = 0; m < ADJ_MAXOWN; ++m) {
-            const int e = tid + CONT_THREADS * m;
-            if (e < nup) rscr[ro + e] = racc[m];
+        for (int m = 0; m < 2; ++m) {
+            if (tjt[m] < 0) continue;
+            const int jj = tjt[m] * 16 + l16;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int ii = tit[m] * 16 + 4 * e + lq;
+                if (ii <= jj && jj < N) rscr[ro + jj * (jj + 1) / 2 + ii] = racc[m][e];
+            }
         }
         __syncthreads();
     }
@@ -792,7 +845,9 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
                        pl->d_rows, pl->d_aitems, pl->d_roff, pl->d_ritem0, pl->d_counter);
     hipFuncAttributes fa;
     HIP_TRY(ctx, hipFuncGetAttributes(&fa, (const void *)k_adj_contour<ORDER>));
-    const int lds_a = adj_fixed() + adj_vbytes(nmax) + adj_mbytes(nmax);
+    int lds_a = 0;
+    for (int k = 1; k <= nmax; ++k) lds_a = std::max(lds_a, adj_need(k));
+    lds_a += adj_fixed();
     if (lds_a + (int)fa.sharedSizeBytes > ctx->lds_per_block)
         return set_err(ctx, GBS_E_INVAL, "rows too large for the gradient kernel's LDS");
     HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_adj_contour<ORDER>,
