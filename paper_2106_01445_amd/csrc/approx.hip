@@ -283,7 +283,6 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
         const int Q = rp.K / 2 + 1;
         const int q0 = ch * GBS_QCHUNK, q1 = min(q0 + GBS_QCHUNK, Q);
         const int np = n * (n - 1) / 2;
-        const int nblk = n + np;
         __syncthreads();
         for (int qb = q0; qb < q1; qb += G) {
             const int g = min(G, q1 - qb);
@@ -315,13 +314,22 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                 for (int k = 0; k < N; ++k) pr = cmul(pr, m.rz[k]);
                 ghat[tid] = pr;
             }
-            // M(w) = V diag(d) V^T: n diagonal blocks, then the blocks (a,b), a < b,
-            // in column-major order (consecutive threads: consecutive a, same b)
-            for (int idx = tid; idx < g * nblk; idx += CONT_THREADS) {
-                const int sl = idx / nblk, bi = idx - sl * nblk;
-                const SlotM m = slot_view(slots + sl * mstride, n);
-                if (bi < n) {
-                    const int a = bi;
+            // M(w) = V diag(d) V^T: at order >= 2 every 2x2 mode block, as the upper
+            // 16x16 tiles of the 2n x 2n matrix on the matrix cores (one wavefront
+            // per (slot, tile)); at order 1 only the diagonal blocks
+            if (ORDER >= 2) {
+                const int T = (N + 15) >> 4, ntile = T * (T + 1) / 2;
+                for (int c = wid; c < g * ntile; c += CONT_THREADS / 64) {
+                    const int sl = c / ntile;
+                    int it, jt;
+                    upper_tile(c - sl * ntile, it, jt);
+                    const SlotM m = slot_view(slots + sl * mstride, n);
+                    m_tile_mfma(n, it, jt, Vt, N, m.d, m.d0, lane);
+                }
+            } else {
+                for (int idx = tid; idx < g * n; idx += CONT_THREADS) {
+                    const int sl = idx / n, a = idx - sl * n;
+                    const SlotM m = slot_view(slots + sl * mstride, n);
                     cplx m00 = cmk(0, 0), m01 = cmk(0, 0), m11 = cmk(0, 0);
 #pragma unroll 1
                     for (int k = 0; k < N; ++k) {
@@ -333,25 +341,6 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                         m11.re = fma(p11, d.re, m11.re); m11.im = fma(p11, d.im, m11.im);
                     }
                     m.d0[a] = m00; m.d1[a] = m01; m.d2[a] = m11;
-                } else {
-                    const int pi = bi - n;
-                    int b = (int)floor(0.5 * (1.0 + sqrt(1.0 + 8.0 * pi)));
-                    while (b * (b - 1) / 2 > pi) --b;
-                    while ((b + 1) * b / 2 <= pi) ++b;
-                    const int a = pi - b * (b - 1) / 2;
-                    cplx b00 = cmk(0, 0), b01 = cmk(0, 0), b10 = cmk(0, 0), b11 = cmk(0, 0);
-#pragma unroll 1
-                    for (int k = 0; k < N; ++k) {
-                        const double va0 = Vt[k * N + a], va1 = Vt[k * N + n + a];
-                        const double vb0 = Vt[k * N + b], vb1 = Vt[k * N + n + b];
-                        const cplx d = m.d[k];
-                        const double p00 = va0 * vb0, p01 = va0 * vb1, p10 = va1 * vb0, p11 = va1 * vb1;
-                        b00.re = fma(p00, d.re, b00.re); b00.im = fma(p00, d.im, b00.im);
-                        b01.re = fma(p01, d.re, b01.re); b01.im = fma(p01, d.im, b01.im);
-                        b10.re = fma(p10, d.re, b10.re); b10.im = fma(p10, d.im, b10.im);
-                        b11.re = fma(p11, d.re, b11.re); b11.im = fma(p11, d.im, b11.im);
-                    }
-                    m.o0[pi] = b00; m.o1[pi] = b01; m.o2[pi] = b10; m.o3[pi] = b11;
                 }
             }
             __syncthreads();

@@ -75,6 +75,65 @@ __host__ __device__ __forceinline__ int cont_vbytes(int n) { return 8 * (4 * n *
 __host__ __device__ __forceinline__ int cont_mbytes(int n) { return 16 * (2 * n * n + 5 * n); }
 __host__ __device__ __forceinline__ int cont_fixed() { return 16 * (CONT_THREADS / 64) * 4 + 16 * CONT_MAXG; }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+// One 16x16x4 fp64 MFMA step, D += A B.  Lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; element e of D sits at row 4e + l/16, column l%16.
+__device__ __forceinline__ dbl4 mfma4(double a, double b, dbl4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// One 16x16 tile (it <= jt) of M(w) = V diag(d) V^T (2n x 2n, quadrature-major
+// rows x_0..x_{n-1}, p_0..p_{n-1}) on the matrix cores, by one wavefront.
+// Vt holds the eigenvectors as rows (entry i of eigenvector k at k*vs + i).
+// Every entry i <= j of the upper triangle is one entry of the 2x2 mode-block
+// layout at blk: diagonal blocks (x_a x_a, x_a p_a, p_a p_a) at a, n + a, 2n + a,
+// pair blocks a < b (x_a x_b, x_a p_b, p_a x_b, p_a p_b) at 3n + t np + b(b-1)/2 + a.
+__device__ __forceinline__ void m_tile_mfma(int n, int it, int jt, const double *Vt, int vs,
+                                            const cplx *d, cplx *blk, int lane)
+{
+    const int N = 2 * n, np = n * (n - 1) / 2, KS = (N + 3) >> 2;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int i = it * 16 + l16, j = jt * 16 + l16;
+    const bool iok = i < N, jok = j < N;
+    dbl4 mre = {0.0, 0.0, 0.0, 0.0}, mim = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int ks = 0; ks < KS; ++ks) {
+        const int k = ks * 4 + lq;
+        const bool kok = k < N, aok = iok && kok, bok = jok && kok;
+        const double val = Vt[aok ? k * vs + i : 0], vbl = Vt[bok ? k * vs + j : 0];
+        const cplx dl = d[kok ? k : 0];
+        const double va = aok ? val : 0.0, vb = bok ? vbl : 0.0;
+        mre = mfma4(va * dl.re, vb, mre);
+        mim = mfma4(va * dl.im, vb, mim);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int ii = it * 16 + 4 * e + lq;
+        if (ii > j || !jok) continue;
+        int off;
+        if (j < n) {
+            off = ii == j ? ii : 3 * n + j * (j - 1) / 2 + ii;
+        } else if (ii < n) {
+            const int a = ii, b = j - n;
+            off = a == b ? n + a : (a < b ? 3 * n + np + b * (b - 1) / 2 + a
+                                          : 3 * n + 2 * np + a * (a - 1) / 2 + b);
+        } else {
+            const int a = ii - n, b = j - n;
+            off = a == b ? 2 * n + a : 3 * n + 3 * np + b * (b - 1) / 2 + a;
+        }
+        blk[off] = cmk(mre[e], mim[e]);
+    }
+}
+
+// tile u of the column-major list of upper tiles (it <= jt)
+__device__ __forceinline__ void upper_tile(int u, int &it, int &jt)
+{
+    jt = 0;
+    while ((jt + 1) * (jt + 2) / 2 <= u) ++jt;
+    it = u - jt * (jt + 1) / 2;
+}
+
 struct SlotM {
     cplx *d, *rz, *d0, *d1, *d2, *o0, *o1, *o2, *o3;
 };

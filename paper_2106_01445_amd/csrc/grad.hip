@@ -215,13 +215,6 @@ __host__ __device__ __forceinline__ int adj_need(int n)
     return adj_vbytes(n) + adj_mbytes(n) + (adj_panel_in_m(n) ? 0 : 16 * 2 * n * ADJ_PWS);
 }
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-// one 16x16x4 fp64 MFMA step, D += A B.  Lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; element e of D sits at row 4e + l/16, column l%16.
-__device__ __forceinline__ dbl4 mfma4(double a, double b, dbl4 c)
-{
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
 
 __device__ __forceinline__ void catomic(cplx *dst, cplx v)
 {
@@ -289,10 +282,10 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
             const int u = wid + 8 * m;
-            int jt = 0;
-            while ((jt + 1) * (jt + 2) / 2 <= u) ++jt;
+            int it, jt;
+            upper_tile(u, it, jt);
             tjt[m] = u < ntile ? jt : -1;
-            tit[m] = u - jt * (jt + 1) / 2;
+            tit[m] = it;
         }
         dbl4 racc[2];
 #pragma unroll
@@ -322,10 +315,15 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 for (int t = 0; t <= ORDER; ++t)
                     s_g[t] = cmul(asw[((long)p * (ORDER + 1) + t) * GBS_QCAP + q], pr);
             }
-            // M(w) blocks (same layout and order as the forward kernel)
-            for (int bi = tid; bi < n + np; bi += CONT_THREADS) {
-                if (bi < n) {
-                    const int a = bi;
+            // M(w) = V diag(d) V^T on the matrix cores, upper tiles over the waves
+            if (ORDER >= 2) {
+                for (int u = wid; u < ntile; u += CONT_THREADS / 64) {
+                    int it, jt;
+                    upper_tile(u, it, jt);
+                    m_tile_mfma(n, it, jt, Vt, NP, dk, Md0, lane);
+                }
+            } else {
+                for (int a = tid; a < n; a += CONT_THREADS) {
                     cplx m00 = cmk(0, 0), m01 = cmk(0, 0), m11 = cmk(0, 0);
 #pragma unroll 1
                     for (int k = 0; k < N; ++k) {
@@ -337,25 +335,6 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                         m11.re = fma(p11, d.re, m11.re); m11.im = fma(p11, d.im, m11.im);
                     }
                     Md0[a] = m00; Md1[a] = m01; Md2[a] = m11;
-                } else {
-                    const int pi = bi - n;
-                    int b = (int)floor(0.5 * (1.0 + sqrt(1.0 + 8.0 * pi)));
-                    while (b * (b - 1) / 2 > pi) --b;
-                    while ((b + 1) * b / 2 <= pi) ++b;
-                    const int a = pi - b * (b - 1) / 2;
-                    cplx b00 = cmk(0, 0), b01 = cmk(0, 0), b10 = cmk(0, 0), b11 = cmk(0, 0);
-#pragma unroll 1
-                    for (int k = 0; k < N; ++k) {
-                        const double va0 = Vt[k * NP + a], va1 = Vt[k * NP + n + a];
-                        const double vb0 = Vt[k * NP + b], vb1 = Vt[k * NP + n + b];
-                        const cplx d = dk[k];
-                        const double p00 = va0 * vb0, p01 = va0 * vb1, p10 = va1 * vb0, p11 = va1 * vb1;
-                        b00.re = fma(p00, d.re, b00.re); b00.im = fma(p00, d.im, b00.im);
-                        b01.re = fma(p01, d.re, b01.re); b01.im = fma(p01, d.im, b01.im);
-                        b10.re = fma(p10, d.re, b10.re); b10.im = fma(p10, d.im, b10.im);
-                        b11.re = fma(p11, d.re, b11.re); b11.im = fma(p11, d.im, b11.im);
-                    }
-                    Mo0[pi] = b00; Mo1[pi] = b01; Mo2[pi] = b10; Mo3[pi] = b11;
                 }
             }
             __syncthreads();
