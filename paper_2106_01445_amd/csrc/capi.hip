@@ -95,9 +95,10 @@ void plan_free_dev(gbs_plan *pl)
 // pair itself.  At order 3 the range c > b is cut into segments of
 // GBS_CLUSTER_SEG, so that no thread of a slot group waits for one long pair;
 // units are listed by decreasing length, then (b, c0, a) for the forward
-// (neighbouring lanes read neighbouring blocks of M(w)) or (a, b, c0) for the
-// adjoint (neighbouring lanes scatter into different blocks of Z(w)), so that a
-// strided assignment to threads is balanced.
+// (neighbouring lanes read neighbouring blocks of M(w)) or (b - a, c0 - b, a)
+// for the adjoint (neighbouring lanes hold distinct a, b and c, so their
+// scatters into Z(w) never meet in one instruction), so that a strided
+// assignment to threads is balanced.
 void cluster_units(int n, int order, bool adjoint, std::vector<int32_t> &out)
 {
     struct U { int a, b, c0, c1; };
@@ -114,9 +115,9 @@ void cluster_units(int n, int order, bool adjoint, std::vector<int32_t> &out)
     std::stable_sort(u.begin(), u.end(), [adjoint](const U &x, const U &y) {
         if (x.c1 - x.c0 != y.c1 - y.c0) return x.c1 - x.c0 > y.c1 - y.c0;
         if (adjoint) {
-            if (x.a != y.a) return x.a < y.a;
-            if (x.b != y.b) return x.b < y.b;
-            return x.c0 < y.c0;
+            if (x.b - x.a != y.b - y.a) return x.b - x.a < y.b - y.a;
+            if (x.c0 - x.b != y.c0 - y.b) return x.c0 - x.b < y.c0 - y.b;
+            return x.a < y.a;
         }
         if (x.b != y.b) return x.b < y.b;
         if (x.c0 != y.c0) return x.c0 < y.c0;
