@@ -128,7 +128,10 @@ int gbs_prob_exact(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *m
  *   5. per sector kappa >= n, the exp-polynomial of degree min(j, n-1) matching
  *      the moments (Methods, Approximation method) and its all-click value;
  *   6. log p_hat = log P_vac(Cbar) + log sum_kappa S_0[kappa] q_kappa(n).
- * Rows may hold at most 40 clicks.  Outputs: logp[P], status[P].
+ * Rows may hold at most 128 clicks at orders 1 and 2 and at most 64 at order
+ * 3 (more is GBS_E_INVAL).  Rows above 40 clicks keep their eigenvectors and
+ * M(w) in device memory instead of on-chip memory (slower per contour point,
+ * same results).  Outputs: logp[P], status[P].
  */
 int gbs_prob_approx(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int order,
                     int prec, double *logp, int32_t *status);

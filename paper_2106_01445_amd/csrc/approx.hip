@@ -33,8 +33,8 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep(
 {
     extern __shared__ double sh[];
     __shared__ double red[PREP_THREADS];
-    __shared__ double cs_c[GBS_MAX_N_APPROX], cs_s[GBS_MAX_N_APPROX];
-    __shared__ int cs_p[GBS_MAX_N_APPROX], cs_q[GBS_MAX_N_APPROX];
+    __shared__ double cs_c[GBS_NSMALL], cs_s[GBS_NSMALL];
+    __shared__ int cs_p[GBS_NSMALL], cs_q[GBS_NSMALL];
     const int p = perm[blockIdx.x];
     const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -138,62 +138,25 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep(
     dev = block_max(dev, red);
     if (tid == 0) {
         RowPlan rp = rows[p];
-        rp.status = 0;
-        rp.logdet_a = logdetA;
-        rp.log_pvac = -0.5 * (logdetQ + logdetA);
-        if (!(amin > 0.0) || scal[3] != 0.0) {
-            rp.status = GBS_PS_PIVOT;
-        } else {
-            if (!frozen) {
-                double rb = dev > 1e-300 ? 1.0 / dev : 1e300;
-                double hi = 0.98 * rb;
-                auto mfun = [&](double rho) {
-                    double s = 0.0;
-                    for (int i = 0; i < N; ++i) {
-                        double a = A[i * N + i];
-                        s += 0.5 * rho * (1.0 - a) / (1.0 + rho * (a - 1.0));
-                    }
-                    return s;
-                };
-                double rho;
-                if (dev < 1e-300) rho = 1.0;
-                else if (mfun(hi) <= (double)n) rho = hi;
-                else {
-                    double lo = 0.0;
-                    for (int it = 0; it < 200; ++it) {
-                        double mid = 0.5 * (lo + hi);
-                        if (mfun(mid) < (double)n) lo = mid;
-                        else hi = mid;
-                    }
-                    rho = 0.5 * (lo + hi);
-                }
-                double kneed = 2.0 * n + 32.0;
-                if (dev >= 1e-300) kneed = fmax(kneed, log(1e-16) / log(rho / rb));
-                int K = 1;
-                while (K < kneed && K < GBS_KMAX) K *= 2;
-                rp.rho = rho;
-                rp.rconv = rb;
-                rp.K = K;
-                rp.log_rho = log(rho);
-            }
-            double s = 0.0;
-            for (int i = 0; i < N; ++i) s += log1p(rp.rho * (A[i * N + i] - 1.0));
-            rp.log_g_rho = 0.5 * logdetA - 0.5 * s;
-        }
+        row_plan(rp, n, A, N + 1, logdetQ, logdetA, amin, dev, scal[3] != 0.0, frozen);
         rows[p] = rp;
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_build_items: work items (row, chunk) in the plan's cost order.
+// k_build_items: work items (row, chunk) in the plan's cost order.  The rows
+// perm[0..nbig) (the large ones) come first: their items form the queue
+// counter[4] (length) / counter[5] (head); the rest form counter[0] (end) /
+// counter[1] (head, starting at counter[4]).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_build_items(int P, const int *__restrict__ offsets,
+__global__ __launch_bounds__(1024) void k_build_items(int P, int nbig, const int *__restrict__ offsets,
                                                       const int *__restrict__ perm,
                                                       const RowPlan *__restrict__ rows,
                                                       int *__restrict__ items,
                                                       int *__restrict__ counter)
 {
     __shared__ int part[1024];
+    __shared__ int s_big;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int per = (P + nt - 1) / nt;
     const int b = tid * per, e = min(P, b + per);
@@ -204,10 +167,16 @@ __global__ __launch_bounds__(1024) void k_build_items(int P, const int *__restri
         if (n == 0 || rp.status != 0 || rp.K <= 0) return 0;
         return (rp.K / 2 + 1 + GBS_QCHUNK - 1) / GBS_QCHUNK;
     };
-    int s = 0;
-    for (int i = b; i < e; ++i) s += nch(i);
+    if (tid == 0) s_big = 0;
+    int s = 0, sb = 0;
+    for (int i = b; i < e; ++i) {
+        const int c = nch(i);
+        s += c;
+        if (i < nbig) sb += c;
+    }
     part[tid] = s;
     __syncthreads();
+    if (sb) atomicAdd(&s_big, sb);
     if (tid == 0) {
         int acc = 0;
         for (int t = 0; t < nt; ++t) {
@@ -216,9 +185,13 @@ __global__ __launch_bounds__(1024) void k_build_items(int P, const int *__restri
             acc += v;
         }
         counter[0] = acc;
-        counter[1] = 0;
     }
     __syncthreads();
+    if (tid == 0) {
+        counter[1] = s_big;
+        counter[4] = s_big;
+        counter[5] = 0;
+    }
     int off = part[tid];
     for (int i = b; i < e; ++i) {
         int c = nch(i), p = perm[i];
@@ -248,12 +221,13 @@ __global__ __launch_bounds__(1024) void k_build_items(int P, const int *__restri
 // and segment, so the reads of the triple loop are broadcasts (blocks (b,c),
 // (c,c)) or consecutive across lanes (block (a,c)).
 // ---------------------------------------------------------------------------
-template <int ORDER>
+template <int ORDER, bool BIG>
 __global__ __launch_bounds__(CONT_THREADS) void k_contour(
     int lds_bytes, const int *__restrict__ offsets, const long long *__restrict__ voff,
     const double *__restrict__ alpha, const double *__restrict__ vt,
-    const RowPlan *__restrict__ rows, const int *__restrict__ items, int *__restrict__ counter,
-    const int *__restrict__ units, const int *__restrict__ unit_off, cplx *__restrict__ sw)
+    const RowPlan *__restrict__ rows, const int *__restrict__ items, const int *__restrict__ q_end,
+    int *__restrict__ q_head, const int *__restrict__ units, const int *__restrict__ unit_off,
+    cplx *__restrict__ mscr, long long mscr_stride, cplx *__restrict__ sw)
 {
     extern __shared__ double sh[];
     __shared__ int s_item;
@@ -261,9 +235,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
     cplx *ghat = red + (CONT_THREADS / 64) * 4;              // [CONT_MAXG]
     double *dyn = (double *)(ghat + CONT_MAXG);
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int total = counter[0];
+    const int total = *q_end;
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(&counter[1], 1);
+        if (tid == 0) s_item = atomicAdd(q_head, 1);
         __syncthreads();
         const int item = s_item;
         __syncthreads();
@@ -271,14 +245,28 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
         const int p = items[2 * item], ch = items[2 * item + 1];
         const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
         const RowPlan rp = rows[p];
-        double *Vt = dyn;                       // N*N, eigenvector k contiguous
-        double *al = Vt + N * N;                // N
-        cplx *slots = (cplx *)(al + N);         // G x (2n^2 + 5n) complex
-        const int mstride = 2 * n * n + 5 * n;
-        int G = CONT_MAXG;
-        while (G > 1 && cont_fixed() + cont_vbytes(n) + G * cont_mbytes(n) > lds_bytes) G >>= 1;
         const long long vo = voff[p];
-        for (int idx = tid; idx < N * N; idx += CONT_THREADS) Vt[idx] = vt[vo + idx];
+        const int mstride = 2 * n * n + 5 * n;
+        const double *Vt;                       // N*N, eigenvector k contiguous
+        double *al;                             // N
+        cplx *slots;                            // G x (2n^2 + 5n) complex
+        int G = 1;
+        if (BIG) {
+            // eigenvectors read from HBM (L2); M(w) in LDS when it fits, else in
+            // this workgroup's HBM scratch
+            Vt = vt + vo;
+            al = dyn;
+            slots = cont_fixed() + 8 * N + cont_mbytes(n) <= lds_bytes ? (cplx *)(al + N)
+                                                                      : mscr + blockIdx.x * mscr_stride;
+        } else {
+            double *vl = dyn;
+            al = vl + N * N;
+            slots = (cplx *)(al + N);
+            G = CONT_MAXG;
+            while (G > 1 && cont_fixed() + cont_vbytes(n) + G * cont_mbytes(n) > lds_bytes) G >>= 1;
+            for (int idx = tid; idx < N * N; idx += CONT_THREADS) vl[idx] = vt[vo + idx];
+            Vt = vl;
+        }
         for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
         const int Q = rp.K / 2 + 1;
         const int q0 = ch * GBS_QCHUNK, q1 = min(q0 + GBS_QCHUNK, Q);
@@ -567,44 +555,76 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
     }
 }
 
+template <int ORDER, bool BIG>
+int launch_contour(gbs_ctx *ctx, gbs_plan *pl, int nmax)
+{
+    hipStream_t st = ctx->stream;
+    hipFuncAttributes fa;
+    HIP_TRY(ctx, hipFuncGetAttributes(&fa, (const void *)k_contour<ORDER, BIG>));
+    const int lds_cap = ctx->lds_per_block - (int)fa.sharedSizeBytes;
+    int lds_c;
+    if (BIG) {
+        // the largest row's M(w) in LDS if it fits, else only alpha (M in HBM)
+        lds_c = cont_fixed() + 8 * 2 * nmax + cont_mbytes(nmax);
+        if (lds_c > lds_cap) lds_c = cont_fixed() + 8 * 2 * nmax;
+    } else {
+        // the whole 160 KB when the largest row needs it, else enough for eight
+        // contour points of the largest row (two workgroups may then share a CU)
+        lds_c = cont_fixed() + cont_vbytes(nmax) + CONT_MAXG * cont_mbytes(nmax);
+        if (lds_c > lds_cap) lds_c = lds_cap;
+        if (cont_fixed() + cont_vbytes(nmax) + cont_mbytes(nmax) > lds_c)
+            return set_err(ctx, GBS_E_INVAL, "row too large for the contour kernel's LDS");
+    }
+    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_contour<ORDER, BIG>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds_c));
+    int occ = 0;
+    HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_contour<ORDER, BIG>,
+                                                              CONT_THREADS, lds_c));
+    if (occ < 1) occ = 1;
+    int grid = occ * ctx->num_cu;
+    cplx *mscr = nullptr;
+    long long mstride = 0;
+    if (BIG) {
+        mstride = 2LL * nmax * nmax + 5LL * nmax;
+        if (pl->d_mscr) {
+            if (grid > pl->mscr_blocks) grid = pl->mscr_blocks;
+            mscr = pl->d_mscr;
+        }
+    }
+    const int *q_end = pl->d_counter + (BIG ? 4 : 0);
+    int *q_head = pl->d_counter + (BIG ? 5 : 1);
+    hipLaunchKernelGGL((k_contour<ORDER, BIG>), dim3(grid), dim3(CONT_THREADS), lds_c, st, lds_c,
+                       pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_items,
+                       q_end, q_head, pl->d_cluster_items, pl->d_cluster_off, mscr, mstride, pl->d_sw);
+    return 0;
+}
+
 template <int ORDER>
 int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
 {
     hipStream_t st = ctx->stream;
     DevModel &m = ctx->model;
-    const int P = pl->P, nmax = pl->max_n;
-    size_t lds_prep = sizeof(double) * 2 * (size_t)(2 * nmax) * (2 * nmax);
-    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_prep, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds_prep));
+    const int P = pl->P, nbig = pl->nbig;
+    const int nsmall_max = pl->max_n_small;
     int ts = timer_begin(ctx, TG_PREP);
-    hipLaunchKernelGGL(k_prep, dim3(P), dim3(PREP_THREADS), lds_prep, st, m.M, m.qi_hi, m.scal,
-                       pl->d_offsets, pl->d_modes, pl->d_perm, pl->d_voff, pl->d_alpha, pl->d_v,
-                       pl->d_rows, pl->frozen ? 1 : 0);
+    if (nbig < P) {
+        size_t lds_prep = sizeof(double) * 2 * (size_t)(2 * nsmall_max) * (2 * nsmall_max);
+        HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_prep,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_prep));
+        hipLaunchKernelGGL(k_prep, dim3(P - nbig), dim3(PREP_THREADS), lds_prep, st, m.M, m.qi_hi,
+                           m.scal, pl->d_offsets, pl->d_modes, pl->d_perm + nbig, pl->d_voff,
+                           pl->d_alpha, pl->d_v, pl->d_rows, pl->frozen ? 1 : 0);
+    }
+    int rc = eig_big(ctx, pl);
+    if (rc) return rc;
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_ITEMS);
-    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, st, P, pl->d_offsets, pl->d_perm,
+    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, st, P, nbig, pl->d_offsets, pl->d_perm,
                        pl->d_rows, pl->d_items, pl->d_counter);
     timer_end(ctx, ts);
-    // LDS: the whole 160 KB when the largest row needs it, else enough for
-    // eight contour points of the largest row (two workgroups may then share a CU)
-    hipFuncAttributes fa;
-    HIP_TRY(ctx, hipFuncGetAttributes(&fa, (const void *)k_contour<ORDER>));
-    const int lds_cap = ctx->lds_per_block - (int)fa.sharedSizeBytes;
-    int lds_c = cont_fixed() + cont_vbytes(nmax) + CONT_MAXG * cont_mbytes(nmax);
-    if (lds_c > lds_cap) lds_c = lds_cap;
-    if (cont_fixed() + cont_vbytes(nmax) + cont_mbytes(nmax) > lds_c)
-        return set_err(ctx, GBS_E_INVAL, "row too large for the contour kernel's LDS");
-    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_contour<ORDER>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds_c));
-    int occ = 0;
-    HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_contour<ORDER>, CONT_THREADS,
-                                                              lds_c));
-    if (occ < 1) occ = 1;
-    int grid = occ * ctx->num_cu;
     ts = timer_begin(ctx, TG_CONTOUR);
-    hipLaunchKernelGGL(k_contour<ORDER>, dim3(grid), dim3(CONT_THREADS), lds_c, st, lds_c,
-                       pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_items,
-                       pl->d_counter, pl->d_cluster_items, pl->d_cluster_off, pl->d_sw);
+    if (nbig > 0 && (rc = launch_contour<ORDER, true>(ctx, pl, pl->max_n))) return rc;
+    if (nbig < P && (rc = launch_contour<ORDER, false>(ctx, pl, nsmall_max))) return rc;
     timer_end(ctx, ts);
     size_t lds_f = sizeof(cplx) * (GBS_KMAX + GBS_KMAX / 2);
     HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_dft_fit<ORDER>,

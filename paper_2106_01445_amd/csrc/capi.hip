@@ -84,7 +84,8 @@ void plan_free_dev(gbs_plan *pl)
                     pl->d_v, pl->d_rows, pl->d_sw, pl->d_items, pl->d_counter,
                     pl->d_cluster_items, pl->d_cluster_off, pl->d_logp, pl->d_status,
                     pl->d_asw, pl->d_aitems, pl->d_roff, pl->d_ritem0, pl->d_rscr,
-                    pl->d_qibar, pl->d_qitmp, pl->d_grad, pl->d_dl};
+                    pl->d_qibar, pl->d_qitmp, pl->d_grad, pl->d_dl, pl->d_wbig, pl->d_mscr,
+                    pl->d_ascr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -163,6 +164,14 @@ int adj_workspace(gbs_ctx *ctx, gbs_plan *pl)
     e = e ? e : dev_alloc(ctx, &pl->d_qibar, D * D);
     e = e ? e : dev_alloc(ctx, &pl->d_qitmp, D * D);
     if (!pl->d_grad) e = e ? e : dev_alloc(ctx, &pl->d_grad, D);
+    if (pl->nbig > 0) {
+        // larger rows: M(w), the pair blocks of Z(w) at order <= 2 and the panel
+        // of Z V, per workgroup
+        const long long nb = pl->max_n, npb = nb * (nb - 1) / 2;
+        pl->ascr_stride = 3 * nb + 4 * npb + (order <= 2 ? 4 * npb : 0) + 2 * nb * 33;
+        pl->ascr_blocks = 2 * ctx->num_cu;
+        e = e ? e : dev_alloc(ctx, &pl->d_ascr, (size_t)pl->ascr_blocks * pl->ascr_stride);
+    }
     if (e) return e;
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     pl->have_adj = true;
@@ -356,7 +365,8 @@ int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
     if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
     if (order < 1 || order > 3) return set_err(ctx, GBS_E_INVAL, "order must be 1, 2 or 3");
     if (prec != GBS_PREC_FP64) return set_err(ctx, GBS_E_INVAL, "prec must be GBS_PREC_FP64");
-    int rc = check_csr(ctx, P, offsets, modes, ctx->model.M, GBS_MAX_N_APPROX);
+    int rc = check_csr(ctx, P, offsets, modes, ctx->model.M,
+                       order == 3 ? GBS_MAX_N_ORDER3 : GBS_MAX_N_APPROX);
     if (rc) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     gbs_plan *pl = new (std::nothrow) gbs_plan();
@@ -376,6 +386,8 @@ int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
         int n = offsets[p + 1] - offsets[p];
         pl->h_n[p] = n;
         pl->max_n = std::max(pl->max_n, n);
+        if (n > GBS_NSMALL) pl->nbig += 1;
+        else pl->max_n_small = std::max(pl->max_n_small, n);
         voff[p] = vt;
         vt += 4LL * n * n;
     }
@@ -408,7 +420,16 @@ int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
     e = e ? e : dev_alloc(ctx, &pl->d_rows, P);
     e = e ? e : dev_alloc(ctx, &pl->d_sw, (size_t)P * (order + 1) * GBS_QCAP);
     e = e ? e : dev_alloc(ctx, &pl->d_items, 2 * (size_t)max_items);
-    e = e ? e : dev_alloc(ctx, &pl->d_counter, 4);
+    e = e ? e : dev_alloc(ctx, &pl->d_counter, 8);
+    if (pl->nbig > 0) {
+        e = e ? e : dev_alloc(ctx, &pl->d_wbig, 2 * pl->v_total);
+        // M(w) of rows whose blocks do not fit in LDS: one copy per workgroup
+        const long long ms = 2LL * pl->max_n * pl->max_n + 5LL * pl->max_n;
+        if (16 * ms + 16 * 64 > (long long)ctx->lds_per_block - 8 * 1024) {
+            pl->mscr_blocks = 2 * ctx->num_cu;
+            e = e ? e : dev_alloc(ctx, &pl->d_mscr, (size_t)pl->mscr_blocks * ms);
+        }
+    }
     e = e ? e : dev_alloc(ctx, &pl->d_cluster_items, citems.size());
     e = e ? e : dev_alloc(ctx, &pl->d_cluster_off, coff.size());
     e = e ? e : dev_alloc(ctx, &pl->d_logp, P);

@@ -75,6 +75,61 @@ __host__ __device__ __forceinline__ int cont_vbytes(int n) { return 8 * (4 * n *
 __host__ __device__ __forceinline__ int cont_mbytes(int n) { return 16 * (2 * n * n + 5 * n); }
 __host__ __device__ __forceinline__ int cont_fixed() { return 16 * (CONT_THREADS / 64) * 4 + 16 * CONT_MAXG; }
 
+// Contour plan of one row from the spectrum alpha of A (entry i at
+// alpha[i * astride]), run by one thread: log P_vac(Cbar), and unless the plan is
+// frozen the radius rho (the saddle point of the photon-number generating
+// function at n photons, capped at 0.98 of the convergence radius
+// 1/max|alpha - 1|) and the size K (a power of two >= 2n + 32 whose aliasing
+// factor (rho/R_b)^K is below 1e-16, at most GBS_KMAX); then log G_0(rho).
+__device__ __forceinline__ void row_plan(RowPlan &rp, int n, const double *alpha, int astride,
+                                         double logdetQ, double logdetA, double amin, double dev,
+                                         bool nonpd, int frozen)
+{
+    const int N = 2 * n;
+    rp.status = 0;
+    rp.logdet_a = logdetA;
+    rp.log_pvac = -0.5 * (logdetQ + logdetA);
+    if (!(amin > 0.0) || nonpd) {
+        rp.status = GBS_PS_PIVOT;
+        return;
+    }
+    if (!frozen) {
+        const double rb = dev > 1e-300 ? 1.0 / dev : 1e300;
+        double hi = 0.98 * rb;
+        auto mfun = [&](double rho) {
+            double s = 0.0;
+            for (int i = 0; i < N; ++i) {
+                const double a = alpha[i * astride];
+                s += 0.5 * rho * (1.0 - a) / (1.0 + rho * (a - 1.0));
+            }
+            return s;
+        };
+        double rho;
+        if (dev < 1e-300) rho = 1.0;
+        else if (mfun(hi) <= (double)n) rho = hi;
+        else {
+            double lo = 0.0;
+            for (int it = 0; it < 200; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                if (mfun(mid) < (double)n) lo = mid;
+                else hi = mid;
+            }
+            rho = 0.5 * (lo + hi);
+        }
+        double kneed = 2.0 * n + 32.0;
+        if (dev >= 1e-300) kneed = fmax(kneed, log(1e-16) / log(rho / rb));
+        int K = 1;
+        while (K < kneed && K < GBS_KMAX) K *= 2;
+        rp.rho = rho;
+        rp.rconv = rb;
+        rp.K = K;
+        rp.log_rho = log(rho);
+    }
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) s += log1p(rp.rho * (alpha[i * astride] - 1.0));
+    rp.log_g_rho = 0.5 * logdetA - 0.5 * s;
+}
+
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 // One 16x16x4 fp64 MFMA step, D += A B.  Lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; element e of D sits at row 4e + l/16, column l%16.

@@ -231,13 +231,14 @@ __device__ __forceinline__ void upper_ij(int e, int &i, int &j)
     i = e - j * (j + 1) / 2;
 }
 
-template <int ORDER>
+template <int ORDER, bool BIG>
 __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
     const int *__restrict__ offsets, const long long *__restrict__ voff,
     const double *__restrict__ alpha, const double *__restrict__ vt,
-    const RowPlan *__restrict__ rows, const int *__restrict__ items, int *__restrict__ counter,
-    const int *__restrict__ units, const int *__restrict__ unit_off,
-    const cplx *__restrict__ asw, const long long *__restrict__ roff, double *__restrict__ rscr)
+    const RowPlan *__restrict__ rows, const int *__restrict__ items, const int *__restrict__ q_end,
+    int *__restrict__ q_head, const int *__restrict__ units, const int *__restrict__ unit_off,
+    const cplx *__restrict__ asw, const long long *__restrict__ roff, double *__restrict__ rscr,
+    cplx *__restrict__ ascr, long long ascr_stride)
 {
     extern __shared__ double sh[];
     __shared__ int s_item;
@@ -247,9 +248,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
     double *dyn = (double *)(red + CONT_THREADS / 64 + 8);
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
-    const int total = counter[2];
+    const int total = *q_end;
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(&counter[3], 1);
+        if (tid == 0) s_item = atomicAdd(q_head, 1);
         __syncthreads();
         const int item = s_item;
         __syncthreads();
@@ -257,27 +258,56 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         const int p = items[2 * item], ch = items[2 * item + 1];
         const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n, NP = N + 1;
         const RowPlan rp = rows[p];
-        double *Vt = dyn;                    // N rows of stride NP: Vt[k*NP + i] = V[i][k]
-        double *al = Vt + N * NP;            // N
-        cplx *dk = (cplx *)(al + N);         // N
-        cplx *rz = dk + N;                   // N
         const int np = n * (n - 1) / 2;
-        cplx *Md0 = rz + N, *Md1 = Md0 + n, *Md2 = Md1 + n;
-        cplx *Mo0 = Md2 + n, *Mo1 = Mo0 + np, *Mo2 = Mo1 + np, *Mo3 = Mo2 + np;
-        cplx *Zd0 = Mo3 + np, *Zd1 = Zd0 + n, *Zd2 = Zd1 + n;
-        cplx *Zo0 = Zd2 + n, *Zo1 = Zo0 + np, *Zo2 = Zo1 + np, *Zo3 = Zo2 + np;
         const long long vo = voff[p];
-        for (int idx = tid; idx < N * N; idx += CONT_THREADS) {
-            const int k = idx / N, i = idx - k * N;
-            Vt[k * NP + i] = vt[vo + idx];
+        // Vt[k*vs + i] = V[i][k].  Rows up to GBS_NSMALL clicks: V, M(w), Z(w)
+        // and the panel of Z V in LDS.  Larger rows: V read from HBM (L2), M(w)
+        // and the panel in this workgroup's HBM scratch, Z(w) in LDS (at order
+        // <= 2 only its diagonal blocks: each pair block has a single writer
+        // and goes to the scratch)
+        const int vs = BIG ? N : NP;
+        const double *Vt;
+        double *al;
+        cplx *dk, *rz, *Md0, *Zd0, *Zo0, *Yp;
+        if (BIG) {
+            Vt = vt + vo;
+            al = dyn;
+            dk = (cplx *)(al + N);
+            rz = dk + N;
+            Zd0 = rz + N;
+            Md0 = ascr + blockIdx.x * ascr_stride;
+            if (ORDER >= 3) {
+                Zo0 = Zd0 + 3 * n;
+                Yp = Md0 + 3 * n + 4 * np;
+            } else {
+                Zo0 = Md0 + 3 * n + 4 * np;
+                Yp = Zo0 + 4 * np;
+            }
+        } else {
+            double *vl = dyn;
+            al = vl + N * NP;
+            dk = (cplx *)(al + N);
+            rz = dk + N;
+            Md0 = rz + N;
+            Zd0 = Md0 + 3 * n + 4 * np;
+            Zo0 = Zd0 + 3 * n;
+            Yp = adj_panel_in_m(n) ? Md0 : Zo0 + 4 * np;
+            for (int idx = tid; idx < N * N; idx += CONT_THREADS) {
+                const int k = idx / N, i = idx - k * N;
+                vl[k * NP + i] = vt[vo + idx];
+            }
+            Vt = vl;
         }
+        cplx *Md1 = Md0 + n, *Md2 = Md1 + n;
+        cplx *Mo0 = Md2 + n, *Mo1 = Mo0 + np, *Mo2 = Mo1 + np, *Mo3 = Mo2 + np;
+        cplx *Zd1 = Zd0 + n, *Zd2 = Zd1 + n;
+        cplx *Zo1 = Zo0 + np, *Zo2 = Zo1 + np, *Zo3 = Zo2 + np;
         for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
         const int Qn = rp.K / 2 + 1;
         const int q0 = ch * ADJ_QCHUNK, q1 = min(q0 + ADJ_QCHUNK, Qn);
         // R in registers: the upper triangle of 16x16 tiles (it <= jt), tile u of
         // the column-major tile list is held by wave u % 8 (at most 15 tiles)
         const int T = (N + 15) >> 4, KS = (N + 3) >> 2, ntile = T * (T + 1) / 2;
-        cplx *Yp = adj_panel_in_m(n) ? Md0 : Zo3 + np;
         int tit[2], tjt[2];
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
@@ -290,6 +320,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         dbl4 racc[2];
 #pragma unroll
         for (int m = 0; m < 2; ++m) racc[m] = dbl4{0.0, 0.0, 0.0, 0.0};
+        const long long ro = roff[item];
+        if (BIG)
+            for (int e = tid; e < N * (N + 1) / 2; e += CONT_THREADS) rscr[ro + e] = 0.0;
         __syncthreads();
         for (int q = q0; q < q1; ++q) {
             if (tid == 0) {
@@ -306,7 +339,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 dk[k] = cmul(r, r);
                 rz[k] = r;
             }
-            for (int i = tid; i < 3 * n + 4 * np; i += CONT_THREADS) Zd0[i] = cmk(0.0, 0.0);
+            for (int i = tid; i < 3 * n; i += CONT_THREADS) Zd0[i] = cmk(0.0, 0.0);
+            if (!BIG || ORDER != 2)
+                for (int i = tid; i < 4 * np; i += CONT_THREADS) Zo0[i] = cmk(0.0, 0.0);
             __syncthreads();
             if (tid == 0) {
                 cplx pr = cmk(exp(0.5 * rp.logdet_a - rp.log_g_rho), 0.0);
@@ -320,14 +355,14 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 for (int u = wid; u < ntile; u += CONT_THREADS / 64) {
                     int it, jt;
                     upper_tile(u, it, jt);
-                    m_tile_mfma(n, it, jt, Vt, NP, dk, Md0, lane);
+                    m_tile_mfma(n, it, jt, Vt, vs, dk, Md0, lane);
                 }
             } else {
                 for (int a = tid; a < n; a += CONT_THREADS) {
                     cplx m00 = cmk(0, 0), m01 = cmk(0, 0), m11 = cmk(0, 0);
 #pragma unroll 1
                     for (int k = 0; k < N; ++k) {
-                        const double v0 = Vt[k * NP + a], v1 = Vt[k * NP + n + a];
+                        const double v0 = Vt[k * vs + a], v1 = Vt[k * vs + n + a];
                         const cplx d = dk[k];
                         const double p00 = v0 * v0, p01 = v0 * v1, p11 = v1 * v1;
                         m00.re = fma(p00, d.re, m00.re); m00.im = fma(p00, d.im, m00.im);
@@ -479,10 +514,18 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                     catomic(&Zd0[a], cfma(cp, pa00, A00));
                     catomic(&Zd1[a], cfma(cp, pa01, A01));
                     catomic(&Zd2[a], cfma(cp, pa11, A11));
-                    catomic(&Zo0[pi], cfnma(cp, H00, A02));
-                    catomic(&Zo1[pi], cfnma(cp, H01, A03));
-                    catomic(&Zo2[pi], cfnma(cp, H10, A12));
-                    catomic(&Zo3[pi], cfnma(cp, H11, A13));
+                    if (BIG && ORDER <= 2) {
+                        // one unit per pair: the pair block has a single writer
+                        Zo0[pi] = cfnma(cp, H00, A02);
+                        Zo1[pi] = cfnma(cp, H01, A03);
+                        Zo2[pi] = cfnma(cp, H10, A12);
+                        Zo3[pi] = cfnma(cp, H11, A13);
+                    } else {
+                        catomic(&Zo0[pi], cfnma(cp, H00, A02));
+                        catomic(&Zo1[pi], cfnma(cp, H01, A03));
+                        catomic(&Zo2[pi], cfnma(cp, H10, A12));
+                        catomic(&Zo3[pi], cfnma(cp, H11, A13));
+                    }
                     catomic(&Zd0[b], cfma(cp, ib00, A22));
                     catomic(&Zd1[b], cfma(cp, ib01, A23));
                     catomic(&Zd2[b], cfma(cp, ib11, A33));
@@ -517,13 +560,19 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                         const int b = sidx < n ? sidx : sidx - n, qb = sidx < n ? 0 : 1;
                         const int lo = min(a, b), hi = max(a, b);
                         const int kq = a < b ? 2 * qa + qb : 2 * qb + qa;
-                        // Zd0..Zd2 (stride n) are followed by Zo0..Zo3 (stride np)
-                        int off = a == b ? (qa + qb) * n + a : 3 * n + kq * np + hi * (hi - 1) / 2 + lo;
-                        off = ok ? off : 0;
-                        const cplx zl = Zd0[off];
+                        cplx zl;
+                        if (BIG) {
+                            const cplx *src = a == b ? Zd0 + (qa + qb) * n + a
+                                                     : Zo0 + kq * np + hi * (hi - 1) / 2 + lo;
+                            zl = *(ok ? src : Zd0);
+                        } else {
+                            // Zd0..Zd2 (stride n) are followed by Zo0..Zo3 (stride np)
+                            int off = a == b ? (qa + qb) * n + a : 3 * n + kq * np + hi * (hi - 1) / 2 + lo;
+                            zl = Zd0[ok ? off : 0];
+                        }
                         const cplx z = ok ? zl : cmk(0.0, 0.0);
                         const bool vok = jok && sidx < N;
-                        const double vl = Vt[vok ? j * NP + sidx : 0];
+                        const double vl = Vt[vok ? j * vs + sidx : 0];
                         const double v = vok ? vl : 0.0;
                         yre = mfma4(z.re, v, yre);
                         yim = mfma4(z.im, v, yim);
@@ -536,10 +585,8 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                     }
                 }
                 __syncthreads();
-#pragma unroll
-                for (int m = 0; m < 2; ++m) {
-                    const int it = tit[m], jt = tjt[m];
-                    if (jt < jr || jt >= jr + nj) continue;
+                // X = V^T Y for tile (it, jt); sink(e, ii, jj, value) takes the R terms
+                auto x_tile = [&](int it, int jt, auto &&sink) {
                     const int i = it * 16 + l16, col = (jt - jr) * 16 + l16;
                     const bool iok = i < N;
                     dbl4 xre = {0.0, 0.0, 0.0, 0.0}, xim = {0.0, 0.0, 0.0, 0.0};
@@ -547,7 +594,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                     for (int ks = 0; ks < KS; ++ks) {
                         const int sidx = ks * 4 + lq;
                         const bool sok = sidx < N, vok = iok && sok;
-                        const double vl = Vt[vok ? i * NP + sidx : 0];
+                        const double vl = Vt[vok ? i * vs + sidx : 0];
                         const double v = vok ? vl : 0.0;
                         const cplx yl = Yp[sok ? sidx * ADJ_PWS + col : 0];
                         const cplx y = sok ? yl : cmk(0.0, 0.0);
@@ -567,17 +614,34 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                                                    -(hw.re * dk[ii].im + hw.im * dk[ii].re));
                                 add += beta.re * t.re - beta.im * t.im;
                             }
-                            racc[m][e] += add;
+                            sink(e, ii, jj, add);
                         }
+                    }
+                };
+                if (BIG) {
+                    // R in the item's HBM scratch, each entry owned by one lane
+                    for (int u = wid; u < ntile; u += CONT_THREADS / 64) {
+                        int it, jt;
+                        upper_tile(u, it, jt);
+                        if (jt < jr || jt >= jr + nj) continue;
+                        x_tile(it, jt, [&](int, int ii, int jj, double add) {
+                            rscr[ro + (long long)jj * (jj + 1) / 2 + ii] += add;
+                        });
+                    }
+                } else {
+#pragma unroll
+                    for (int m = 0; m < 2; ++m) {
+                        const int it = tit[m], jt = tjt[m];
+                        if (jt < jr || jt >= jr + nj) continue;
+                        x_tile(it, jt, [&](int e, int, int, double add) { racc[m][e] += add; });
                     }
                 }
                 __syncthreads();
             }
         }
-        const long long ro = roff[item];
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
-            if (tjt[m] < 0) continue;
+            if (BIG || tjt[m] < 0) continue;
             const int jj = tjt[m] * 16 + l16;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -593,7 +657,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
 // k_adj_items: backward work items (row, chunk of ADJ_QCHUNK points) and the
 // offsets of their R scratch
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_adj_items(int P, const int *__restrict__ offsets,
+__global__ __launch_bounds__(1024) void k_adj_items(int P, int nbig, const int *__restrict__ offsets,
                                                     const int *__restrict__ perm,
                                                     const RowPlan *__restrict__ rows,
                                                     int *__restrict__ items, long long *__restrict__ roff,
@@ -616,15 +680,19 @@ __global__ __launch_bounds__(1024) void k_adj_items(int P, const int *__restrict
         const long long N = 2 * (offsets[p + 1] - offsets[p]);
         return N * (N + 1) / 2;
     };
-    int s = 0;
+    __shared__ int s_big;
+    if (tid == 0) s_big = 0;
+    int s = 0, sb = 0;
     long long ls = 0;
     for (int i = b; i < e; ++i) {
         s += nch(i);
+        if (i < nbig) sb += nch(i);
         ls += nch(i) * rsz(i);
     }
     part[tid] = s;
     lpart[tid] = ls;
     __syncthreads();
+    if (sb) atomicAdd(&s_big, sb);
     if (tid == 0) {
         int acc = 0;
         long long lacc = 0;
@@ -637,9 +705,14 @@ __global__ __launch_bounds__(1024) void k_adj_items(int P, const int *__restrict
             lacc += lv;
         }
         counter[2] = acc;
-        counter[3] = 0;
     }
     __syncthreads();
+    if (tid == 0) {
+        // items of perm[0..nbig) (the large rows) first: their own queue [6] / [7]
+        counter[3] = s_big;
+        counter[6] = s_big;
+        counter[7] = 0;
+    }
     int off = part[tid];
     long long loff = lpart[tid];
     for (int i = b; i < e; ++i) {
@@ -681,7 +754,7 @@ __global__ __launch_bounds__(256) void k_adj_reduce(int M, const int *__restrict
     const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
     const RowPlan rp = rows[p];
     const long long vo = voff[p];
-    if (n == 0) return;
+    if (n == 0 || n > GBS_NSMALL) return;
     const int it0 = row_item0[p];
     if (it0 < 0 || rp.status != 0 || !isfinite(dl[p]) || dl[p] == 0.0) return;
     const int nit = (rp.K / 2 + 1 + ADJ_QCHUNK - 1) / ADJ_QCHUNK;
@@ -721,6 +794,63 @@ __global__ __launch_bounds__(256) void k_adj_reduce(int M, const int *__restrict
         const int i = idx / N, j = idx - i * N;
         double s = 0.0;
         for (int k = 0; k < N; ++k) s = fma(V[i * N + k], T[k * N + j], s);
+        atomicAdd(&psi[g[i] * D + g[j]], s);
+    }
+}
+
+// k_adj_reduce for the larger rows (perm[0..nbig)): R and T = R V^T in HBM
+// scratch (2 N^2 per row), A_bar = V T added into Psi.
+__global__ __launch_bounds__(256) void k_adj_reduce_big(int M, const int *__restrict__ offsets,
+                                                        const int *__restrict__ modes,
+                                                        const int *__restrict__ perm,
+                                                        const long long *__restrict__ voff,
+                                                        const double *__restrict__ alpha,
+                                                        const double *__restrict__ vt,
+                                                        const RowPlan *__restrict__ rows,
+                                                        const double *__restrict__ dl,
+                                                        const int *__restrict__ row_item0,
+                                                        const long long *__restrict__ roff,
+                                                        const double *__restrict__ rscr,
+                                                        double *__restrict__ wbig,
+                                                        double *__restrict__ psi)
+{
+    __shared__ int g[2 * GBS_MAX_N_APPROX];
+    const int p = perm[blockIdx.x], tid = threadIdx.x, nt = blockDim.x;
+    const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
+    const RowPlan rp = rows[p];
+    const int it0 = row_item0[p];
+    if (n == 0 || it0 < 0 || rp.status != 0 || !isfinite(dl[p]) || dl[p] == 0.0) return;
+    const int nit = (rp.K / 2 + 1 + ADJ_QCHUNK - 1) / ADJ_QCHUNK;
+    const long long vo = voff[p];
+    const double *Vt = vt + vo;          // Vt[k*N + i] = V[i][k]
+    double *R = wbig + 2 * vo, *T = R + (long)N * N;
+    for (int i = tid; i < N; i += nt) g[i] = modes[o + (i < n ? i : i - n)] + (i < n ? 0 : M);
+    const int nup = N * (N + 1) / 2;
+    for (int e = tid; e < nup; e += nt) {
+        int i, j;
+        upper_ij(e, i, j);
+        double s = 0.0;
+        for (int it = 0; it < nit; ++it) s += rscr[roff[it0 + it] + e];
+        if (i == j) {
+            const double dr = 1.0 / (1.0 + rp.rho * (alpha[2 * o + i] - 1.0));
+            s += -0.5 * dl[p] * rp.rho * dr;
+        }
+        R[(long)i * N + j] = s;
+        R[(long)j * N + i] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < N * N; idx += nt) {
+        const int k = idx / N, j = idx - k * N;
+        double s = 0.0;
+        for (int l = 0; l < N; ++l) s = fma(R[(long)k * N + l], Vt[(long)l * N + j], s);
+        T[idx] = s;
+    }
+    __syncthreads();
+    const long D = 2L * M;
+    for (int idx = tid; idx < N * N; idx += nt) {
+        const int i = idx / N, j = idx - i * N;
+        double s = 0.0;
+        for (int k = 0; k < N; ++k) s = fma(Vt[(long)k * N + i], T[(long)k * N + j], s);
         atomicAdd(&psi[g[i] * D + g[j]], s);
     }
 }
@@ -820,36 +950,69 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
                        pl->d_rows, pl->d_sw, dl, pl->d_asw);
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_ADJ_CLUSTER);
-    hipLaunchKernelGGL(k_adj_items, dim3(1), dim3(1024), 0, st, P, pl->d_offsets, pl->d_perm,
+    hipLaunchKernelGGL(k_adj_items, dim3(1), dim3(1024), 0, st, P, pl->nbig, pl->d_offsets, pl->d_perm,
                        pl->d_rows, pl->d_aitems, pl->d_roff, pl->d_ritem0, pl->d_counter);
-    hipFuncAttributes fa;
-    HIP_TRY(ctx, hipFuncGetAttributes(&fa, (const void *)k_adj_contour<ORDER>));
-    int lds_a = 0;
-    for (int k = 1; k <= nmax; ++k) lds_a = std::max(lds_a, adj_need(k));
-    lds_a += adj_fixed();
-    if (lds_a + (int)fa.sharedSizeBytes > ctx->lds_per_block)
-        return set_err(ctx, GBS_E_INVAL, "rows too large for the gradient kernel's LDS");
-    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_adj_contour<ORDER>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds_a));
-    int occ = 0;
-    HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_adj_contour<ORDER>,
-                                                              CONT_THREADS, lds_a));
-    if (occ < 1) occ = 1;
-    hipLaunchKernelGGL(k_adj_contour<ORDER>, dim3(occ * ctx->num_cu), dim3(CONT_THREADS), lds_a, st,
-                       pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_aitems,
-                       pl->d_counter, pl->d_cluster_items + pl->n_cluster_items, pl->d_cluster_off,
-                       pl->d_asw, pl->d_roff, pl->d_rscr);
+    if (pl->nbig > 0) {
+        // larger rows: V and M(w) in HBM, Z(w) (all of it at order 3, its diagonal
+        // blocks otherwise) in LDS
+        hipFuncAttributes fa;
+        HIP_TRY(ctx, hipFuncGetAttributes(&fa, (const void *)k_adj_contour<ORDER, true>));
+        const int nb = nmax, npb = nb * (nb - 1) / 2;
+        const int lds_b = adj_fixed() + 8 * 2 * nb + 16 * 2 * 2 * nb + 16 * 3 * nb +
+                          (ORDER >= 3 ? 16 * 4 * npb : 0);
+        if (lds_b + (int)fa.sharedSizeBytes > ctx->lds_per_block)
+            return set_err(ctx, GBS_E_INVAL, "rows too large for the gradient kernel's LDS");
+        HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_adj_contour<ORDER, true>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds_b));
+        int occ = 0;
+        HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_adj_contour<ORDER, true>,
+                                                                  CONT_THREADS, lds_b));
+        if (occ < 1) occ = 1;
+        int grid = std::min(occ * ctx->num_cu, pl->ascr_blocks);
+        hipLaunchKernelGGL((k_adj_contour<ORDER, true>), dim3(grid), dim3(CONT_THREADS), lds_b, st,
+                           pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_aitems,
+                           pl->d_counter + 6, pl->d_counter + 7,
+                           pl->d_cluster_items + pl->n_cluster_items, pl->d_cluster_off, pl->d_asw,
+                           pl->d_roff, pl->d_rscr, pl->d_ascr, pl->ascr_stride);
+    }
+    const int ns = pl->max_n_small;
+    if (pl->nbig < P) {
+        hipFuncAttributes fa;
+        HIP_TRY(ctx, hipFuncGetAttributes(&fa, (const void *)k_adj_contour<ORDER, false>));
+        int lds_a = 0;
+        for (int k = 1; k <= ns; ++k) lds_a = std::max(lds_a, adj_need(k));
+        lds_a += adj_fixed();
+        if (lds_a + (int)fa.sharedSizeBytes > ctx->lds_per_block)
+            return set_err(ctx, GBS_E_INVAL, "rows too large for the gradient kernel's LDS");
+        HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_adj_contour<ORDER, false>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds_a));
+        int occ = 0;
+        HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_adj_contour<ORDER, false>,
+                                                                  CONT_THREADS, lds_a));
+        if (occ < 1) occ = 1;
+        hipLaunchKernelGGL((k_adj_contour<ORDER, false>), dim3(occ * ctx->num_cu), dim3(CONT_THREADS),
+                           lds_a, st, pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows,
+                           pl->d_aitems, pl->d_counter + 2, pl->d_counter + 3,
+                           pl->d_cluster_items + pl->n_cluster_items, pl->d_cluster_off, pl->d_asw,
+                           pl->d_roff, pl->d_rscr, (cplx *)nullptr, 0LL);
+    }
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_ADJ_ROWS);
-    const int N = 2 * nmax;
     const int D = 2 * M;
     hipLaunchKernelGGL(k_zero, dim3((D * D + 255) / 256), dim3(256), 0, st, (long)D * D, pl->d_qibar);
-    size_t lds_r = sizeof(double) * 3 * (size_t)N * N + sizeof(int) * N;
-    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_adj_reduce,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r));
-    hipLaunchKernelGGL(k_adj_reduce, dim3(P), dim3(256), lds_r, st, M, pl->d_offsets, pl->d_modes,
-                       pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, dl, pl->d_ritem0, pl->d_roff,
-                       pl->d_rscr, pl->d_qibar);
+    if (pl->nbig < P) {
+        const int N = 2 * ns;
+        size_t lds_r = sizeof(double) * 3 * (size_t)N * N + sizeof(int) * N;
+        HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_adj_reduce,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r));
+        hipLaunchKernelGGL(k_adj_reduce, dim3(P), dim3(256), lds_r, st, M, pl->d_offsets, pl->d_modes,
+                           pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, dl, pl->d_ritem0, pl->d_roff,
+                           pl->d_rscr, pl->d_qibar);
+    }
+    if (pl->nbig > 0)
+        hipLaunchKernelGGL(k_adj_reduce_big, dim3(pl->nbig), dim3(256), 0, st, M, pl->d_offsets,
+                           pl->d_modes, pl->d_perm, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, dl,
+                           pl->d_ritem0, pl->d_roff, pl->d_rscr, pl->d_wbig, pl->d_qibar);
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_ADJ_MODEL);
     hipLaunchKernelGGL(k_adj_model, dim3(1), dim3(1024), 0, st, M, P, m.qi_hi, m.params, dl,

@@ -9,7 +9,9 @@
 #include "../../include/gbs.h"
 
 #define GBS_MAX_M 512          // modes supported by the model build
-#define GBS_MAX_N_APPROX 40    // clicks per row on the approximate path
+#define GBS_MAX_N_APPROX 128   // clicks per row on the approximate path (orders 1, 2)
+#define GBS_MAX_N_ORDER3 64    // clicks per row at order 3
+#define GBS_NSMALL 40          // rows up to this many clicks keep V and M(w) in LDS
 #define GBS_MAX_N_EXACT 24     // clicks per row on the exact path
 #define GBS_KMAX 2048          // contour size cap
 #define GBS_QCAP (GBS_KMAX / 2 + 1)
@@ -67,6 +69,8 @@ struct RowPlan {
 struct gbs_plan {
     gbs_ctx *ctx = nullptr;
     int P = 0, order = 0, prec = 0, max_n = 0;
+    int nbig = 0;                         // rows with more than GBS_NSMALL clicks: perm[0..nbig)
+    int max_n_small = 0;                  // largest click count among the other rows
     bool frozen = false;
     bool have_run = false;
     std::vector<int32_t> h_offsets, h_modes, h_perm, h_n;
@@ -78,7 +82,11 @@ struct gbs_plan {
     RowPlan *d_rows = nullptr;            // P
     cplx *d_sw = nullptr;                 // (order+1) * QCAP per row: sums over clusters
     int32_t *d_items = nullptr;           // work items (row, chunk), 2 ints each
-    int32_t *d_counter = nullptr;         // [0] items total, [1] queue head
+    int32_t *d_counter = nullptr;         // work queues: [0] end, [1] head (rows <= GBS_NSMALL),
+                                          // [4] end, [5] head (larger rows); [2,3], [6,7] adjoint
+    double *d_wbig = nullptr;             // eigen-decomposition scratch of the larger rows, like d_v
+    cplx *d_mscr = nullptr;               // per-workgroup M(w) scratch of the larger rows
+    int mscr_blocks = 0;                  // workgroups d_mscr serves
     int32_t *d_cluster_items = nullptr;   // per click count n: packed cluster units (a, b, c0, c1),
                                           // forward order, then adjoint order (+ n_cluster_items)
     int32_t *d_cluster_off = nullptr;     // [n] -> offset, count (2 ints)
@@ -98,6 +106,9 @@ struct gbs_plan {
     double *d_qitmp = nullptr;            // (2M)^2 scratch
     double *d_grad = nullptr;             // 2M: grad r, grad eta
     double *d_dl = nullptr;               // P
+    cplx *d_ascr = nullptr;               // per-workgroup adjoint scratch of the larger rows
+    int ascr_blocks = 0;
+    long long ascr_stride = 0;            // complex entries per workgroup
 };
 
 // error helpers ------------------------------------------------------------
@@ -116,3 +127,4 @@ int exact_run(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes,
               double *logp, double *kappa, int32_t *status);
 int approx_backward(gbs_ctx *ctx, gbs_plan *plan, const double *dl_dev, const int32_t *status_dev,
                     double *grad_r_dev, double *grad_eta_dev);
+int eig_big(gbs_ctx *ctx, gbs_plan *plan);

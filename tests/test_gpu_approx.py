@@ -126,13 +126,14 @@ def test_frozen_plan_reuse(gpu_ctx):
 @pytest.mark.parametrize("rows,order", [
     ([[1, 0]], 2),            # not ascending
     ([[2, 2]], 2),            # duplicate
-    ([[0, 99]], 2),           # out of range
+    ([[0, 199]], 2),          # out of range
     ([[0, 1]], 4),            # order outside 1..3
-    ([list(range(41))], 2),   # more clicks than supported
+    ([list(range(65))], 3),   # more clicks than order 3 supports
+    ([list(range(129))], 2),  # more clicks than supported
 ])
 def test_argument_errors(gpu_ctx, rows, order):
     import paper_2106_01445_amd as g
-    U, r, eta = small_model(50, 13)
+    U, r, eta = small_model(140, 13)
     gpu_ctx.gbs_set_model(U, r, eta)
     off, mod = csr_from_lists(rows)
     with pytest.raises(g.GBSError) as e:
