@@ -105,6 +105,50 @@ def exact_leg(ctx, steps: int = 3):
             "max_kappa": float(out["kappa"].max()), "status_nonzero": int(np.sum(out["status"] != 0))}
 
 
+def big_leg(ctx, torch, cfg: int, name: str):
+    """One forward and one forward + adjoint pass (after a warm-up) on the 100-
+    or 144-mode batch (rows up to 60 / 110 clicks: eigenvectors and M(w) in HBM);
+    device timings per kernel group."""
+    from workloads import make_workload
+    wl = make_workload(cfg)
+    dev = torch.device("cuda:0")
+    ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    ure = torch.tensor(np.ascontiguousarray(wl.U.real), device=dev)
+    uim = torch.tensor(np.ascontiguousarray(wl.U.imag), device=dev)
+    r = torch.tensor(wl.r, device=dev)
+    eta = torch.tensor(wl.eta, device=dev)
+    logp = torch.empty(wl.P, dtype=torch.float64, device=dev)
+    st = torch.empty(wl.P, dtype=torch.int32, device=dev)
+    dl = torch.ones(wl.P, dtype=torch.float64, device=dev)
+    gr = torch.empty(wl.M, dtype=torch.float64, device=dev)
+    ge = torch.empty(wl.M, dtype=torch.float64, device=dev)
+    plan = ctx.gbs_plan_create(wl.offsets, wl.modes, wl.order)
+    out = {"workload": name, "modes": wl.M, "patterns": wl.P, "order": wl.order,
+           "clicks": f"{int(np.diff(wl.offsets).min())}-{int(np.diff(wl.offsets).max())}"}
+    for key, grad in (("forward", False), ("forward+adjoint", True)):
+        def fn():
+            ctx.gbs_set_model_dev(ure, uim, r, eta)
+            if grad:
+                ctx.gbs_grad_dev(plan, dl, logp, gr, ge, st)
+            else:
+                ctx.gbs_prob_approx_dev(plan, logp, st)
+        fn()
+        torch.cuda.synchronize()
+        ctx.gbs_timing()
+        ctx.gbs_set_timing(True)
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        tim = ctx.gbs_timing()
+        ctx.gbs_set_timing(False)
+        out[key] = {"ms": ms, "probs_per_s": wl.P / (ms * 1e-3),
+                    "status_nonzero": int((st != 0).sum().item()),
+                    "kernel_ms": {k: round(v[0], 3) for k, v in tim.items() if v[1]}}
+    plan.close()
+    return out
+
+
 def source_sha(paths):
     import hashlib
     h = hashlib.sha256()
@@ -134,6 +178,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-exact", action="store_true", help="skip the 20-mode exact leg")
+    ap.add_argument("--no-big", action="store_true", help="skip the 100- and 144-mode legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 3 times (calibrates the "
                          "HBM byte counters against a kernel of known traffic)")
@@ -253,6 +298,9 @@ def main():
     }
     if not args.no_exact:
         out["exact_m20"] = exact_leg(ctx)
+    if not args.no_big:
+        out["m100_order3"] = big_leg(ctx, torch, 4, "m100_order3")
+        out["m144_order2_grad"] = big_leg(ctx, torch, 5, "m144_order2_grad")
     if not args.no_cpu:
         cb, err = cpu_baseline(wl, lp)
         out["cpu_baseline"] = cb
