@@ -3,9 +3,9 @@
 // method), fp64, one MI355X.
 //
 // Pipeline per batch (all on one stream, no host synchronisation):
-//   k_prep         one workgroup per row: A = (Q^{-1})_CC gathered from HBM,
-//                  cyclic Jacobi A = V diag(alpha) V^T in LDS, log det A,
-//                  log P_vac(Cbar), contour radius rho and size K
+//   k_eig          (eig.hip) one workgroup per row: A = (Q^{-1})_CC gathered,
+//                  A = V diag(alpha) V^T, log det A, log P_vac(Cbar), contour
+//                  radius rho and size K
 //   k_build_items  one workgroup: (row, chunk of contour points) work items in
 //                  decreasing-cost row order, queue counters reset
 //   k_contour      persistent workgroups pulling items from an atomic queue;
@@ -21,127 +21,6 @@
 
 
 namespace {
-
-// ---------------------------------------------------------------------------
-// k_prep: gather, eigen-decompose, plan.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(PREP_THREADS) void k_prep(
-    int M, const double *__restrict__ qi, const double *__restrict__ scal,
-    const int *__restrict__ offsets, const int *__restrict__ modes, const int *__restrict__ perm,
-    const long long *__restrict__ voff, double *__restrict__ alpha_out, double *__restrict__ vt_out,
-    RowPlan *__restrict__ rows, int frozen)
-{
-    extern __shared__ double sh[];
-    __shared__ double red[PREP_THREADS];
-    __shared__ double cs_c[GBS_NSMALL], cs_s[GBS_NSMALL];
-    __shared__ int cs_p[GBS_NSMALL], cs_q[GBS_NSMALL];
-    const int p = perm[blockIdx.x];
-    const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const double logdetQ = scal[0];
-    if (n == 0) {
-        if (tid == 0) {
-            RowPlan rp = {};
-            rp.log_pvac = -0.5 * logdetQ;
-            rows[p] = rp;
-        }
-        return;
-    }
-    double *A = sh, *V = sh + N * N;
-    const int D = 2 * M;
-    for (int idx = tid; idx < N * N; idx += nt) {
-        int i = idx / N, j = idx - i * N;
-        int ri = i < n ? modes[o + i] : modes[o + i - n] + M;
-        int rj = j < n ? modes[o + j] : modes[o + j - n] + M;
-        A[idx] = qi[(long)ri * D + rj];
-        V[idx] = (i == j) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    // cyclic Jacobi, round-robin ordering of the N/2 disjoint rotations
-    const int H = N / 2;
-    bool last = false;
-    for (int sweep = 0; sweep < 30; ++sweep) {
-        double off = 0.0, dg = 0.0;
-        for (int idx = tid; idx < N * N; idx += nt) {
-            int i = idx / N, j = idx - i * N;
-            double a = A[idx];
-            if (i == j) dg += a * a;
-            else off += a * a;
-        }
-        off = block_sum(off, red);
-        dg = block_sum(dg, red);
-        // off-diagonal at 1e-13 of the diagonal: one more (quadratically
-        // convergent) sweep reaches the rounding floor
-        if (last) break;
-        if (off <= 1e-26 * dg) last = true;
-        for (int r = 0; r < N - 1; ++r) {
-            if (tid < H) {
-                int k = tid, pp, qq;
-                if (k == 0) {
-                    pp = r;
-                    qq = N - 1;
-                } else {
-                    pp = (r + k) % (N - 1);
-                    qq = (r - k + (N - 1)) % (N - 1);
-                }
-                if (pp > qq) { int t = pp; pp = qq; qq = t; }
-                double app = A[pp * N + pp], aqq = A[qq * N + qq], apq = A[pp * N + qq];
-                double c = 1.0, s = 0.0;
-                if (apq != 0.0) {
-                    double th = (aqq - app) / (2.0 * apq);
-                    double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
-                    c = 1.0 / sqrt(fma(t, t, 1.0));
-                    s = t * c;
-                }
-                cs_c[k] = c; cs_s[k] = s; cs_p[k] = pp; cs_q[k] = qq;
-            }
-            __syncthreads();
-            for (int idx = tid; idx < H * N; idx += nt) {
-                int k = idx / N, j = idx - k * N;
-                int pp = cs_p[k], qq = cs_q[k];
-                double c = cs_c[k], s = cs_s[k];
-                double apj = A[pp * N + j], aqj = A[qq * N + j];
-                A[pp * N + j] = c * apj - s * aqj;
-                A[qq * N + j] = s * apj + c * aqj;
-            }
-            __syncthreads();
-            for (int idx = tid; idx < N * H; idx += nt) {
-                int i = idx / H, k = idx - i * H;
-                int pp = cs_p[k], qq = cs_q[k];
-                double c = cs_c[k], s = cs_s[k];
-                double aip = A[i * N + pp], aiq = A[i * N + qq];
-                A[i * N + pp] = c * aip - s * aiq;
-                A[i * N + qq] = s * aip + c * aiq;
-                double vip = V[i * N + pp], viq = V[i * N + qq];
-                V[i * N + pp] = c * vip - s * viq;
-                V[i * N + qq] = s * vip + c * viq;
-            }
-            __syncthreads();
-        }
-    }
-    // outputs: alpha, V^T (eigenvector k contiguous)
-    const long long vo = voff[p];
-    for (int idx = tid; idx < N * N; idx += nt) {
-        int k = idx / N, i = idx - k * N;
-        vt_out[vo + idx] = V[i * N + k];
-    }
-    double lsum = 0.0, amin = 1e300, dev = 0.0;
-    for (int i = tid; i < N; i += nt) {
-        double a = A[i * N + i];
-        alpha_out[2 * o + i] = a;
-        lsum += log(a);
-        amin = fmin(amin, a);
-        dev = fmax(dev, fabs(a - 1.0));
-    }
-    double logdetA = block_sum(lsum, red);
-    amin = -block_max(-amin, red);
-    dev = block_max(dev, red);
-    if (tid == 0) {
-        RowPlan rp = rows[p];
-        row_plan(rp, n, A, N + 1, logdetQ, logdetA, amin, dev, scal[3] != 0.0, frozen);
-        rows[p] = rp;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // k_build_items: work items (row, chunk) in the plan's cost order.  The rows
@@ -603,19 +482,10 @@ template <int ORDER>
 int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
 {
     hipStream_t st = ctx->stream;
-    DevModel &m = ctx->model;
     const int P = pl->P, nbig = pl->nbig;
     const int nsmall_max = pl->max_n_small;
     int ts = timer_begin(ctx, TG_PREP);
-    if (nbig < P) {
-        size_t lds_prep = sizeof(double) * 2 * (size_t)(2 * nsmall_max) * (2 * nsmall_max);
-        HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_prep,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_prep));
-        hipLaunchKernelGGL(k_prep, dim3(P - nbig), dim3(PREP_THREADS), lds_prep, st, m.M, m.qi_hi,
-                           m.scal, pl->d_offsets, pl->d_modes, pl->d_perm + nbig, pl->d_voff,
-                           pl->d_alpha, pl->d_v, pl->d_rows, pl->frozen ? 1 : 0);
-    }
-    int rc = eig_big(ctx, pl);
+    int rc = eig_rows(ctx, pl);
     if (rc) return rc;
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_ITEMS);

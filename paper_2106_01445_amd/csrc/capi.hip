@@ -421,8 +421,8 @@ int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
     e = e ? e : dev_alloc(ctx, &pl->d_sw, (size_t)P * (order + 1) * GBS_QCAP);
     e = e ? e : dev_alloc(ctx, &pl->d_items, 2 * (size_t)max_items);
     e = e ? e : dev_alloc(ctx, &pl->d_counter, 8);
+    e = e ? e : dev_alloc(ctx, &pl->d_wbig, 2 * pl->v_total);
     if (pl->nbig > 0) {
-        e = e ? e : dev_alloc(ctx, &pl->d_wbig, 2 * pl->v_total);
         // M(w) of rows whose blocks do not fit in LDS: one copy per workgroup
         const long long ms = 2LL * pl->max_n * pl->max_n + 5LL * pl->max_n;
         if (16 * ms + 16 * 64 > (long long)ctx->lds_per_block - 8 * 1024) {

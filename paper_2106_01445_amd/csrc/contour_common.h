@@ -6,7 +6,6 @@
 #include "cplx.h"
 #include "internal.h"
 
-#define PREP_THREADS 256
 #define CONT_THREADS 512
 #define FIT_THREADS 256
 #define FIT_MAXIT 100

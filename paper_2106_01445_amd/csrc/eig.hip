@@ -1,6 +1,5 @@
-// Set-up of rows with more clicks than the LDS-resident path holds (the
-// 100- and 144-mode workloads): A = (Q^{-1})_CC = V diag(alpha) V^T with the
-// working matrices in HBM (L2-resident), one workgroup per row.
+// Per-row set-up of the order-j estimate: A = (Q^{-1})_CC = V diag(alpha) V^T
+// with the working matrices in HBM (L2-resident), one workgroup per row.
 //
 //   1. Householder reduction of A to tridiagonal form (symmetric rank-2
 //      updates of the trailing block, Golub & Van Loan, Matrix Computations,
@@ -15,20 +14,20 @@
 // read (eigenvector k contiguous).
 #include "contour_common.h"
 
-#define BIG_THREADS 256
+#define EIG_THREADS 256
 
 namespace {
 
-__global__ __launch_bounds__(BIG_THREADS) void k_eig_big(
+__global__ __launch_bounds__(EIG_THREADS) void k_eig(
     int M, const double *__restrict__ qi, const double *__restrict__ scal,
     const int *__restrict__ offsets, const int *__restrict__ modes, const int *__restrict__ perm,
     const long long *__restrict__ voff, double *__restrict__ wbuf, double *__restrict__ alpha_out,
     double *__restrict__ vt_out, RowPlan *__restrict__ rows, int frozen)
 {
-    __shared__ double red[BIG_THREADS];
-    __shared__ double v[BIG_THREADS], w[BIG_THREADS];
-    __shared__ double dg[BIG_THREADS], ed[BIG_THREADS], tau[BIG_THREADS];
-    __shared__ double rc[BIG_THREADS], rs[BIG_THREADS];
+    __shared__ double red[EIG_THREADS];
+    __shared__ double v[EIG_THREADS], w[EIG_THREADS];
+    __shared__ double dg[EIG_THREADS], ed[EIG_THREADS], tau[EIG_THREADS];
+    __shared__ double rc[EIG_THREADS], rs[EIG_THREADS];
     __shared__ int s_m, s_lo, s_fail;
     const int p = perm[blockIdx.x];
     const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
@@ -217,10 +216,10 @@ __global__ __launch_bounds__(BIG_THREADS) void k_eig_big(
 
 }  // namespace
 
-int eig_big(gbs_ctx *ctx, gbs_plan *pl)
+int eig_rows(gbs_ctx *ctx, gbs_plan *pl)
 {
-    if (pl->nbig == 0) return 0;
-    hipLaunchKernelGGL(k_eig_big, dim3(pl->nbig), dim3(BIG_THREADS), 0, ctx->stream, ctx->model.M,
+    if (pl->P == 0) return 0;
+    hipLaunchKernelGGL(k_eig, dim3(pl->P), dim3(EIG_THREADS), 0, ctx->stream, ctx->model.M,
                        ctx->model.qi_hi, ctx->model.scal, pl->d_offsets, pl->d_modes, pl->d_perm,
                        pl->d_voff, pl->d_wbig, pl->d_alpha, pl->d_v, pl->d_rows, pl->frozen ? 1 : 0);
     HIP_TRY(ctx, hipGetLastError());

@@ -11,7 +11,7 @@
 #define GBS_MAX_M 512          // modes supported by the model build
 #define GBS_MAX_N_APPROX 128   // clicks per row on the approximate path (orders 1, 2)
 #define GBS_MAX_N_ORDER3 64    // clicks per row at order 3
-#define GBS_NSMALL 40          // rows up to this many clicks keep V and M(w) in LDS
+#define GBS_NSMALL 40          // rows up to this many clicks keep V and M(w) in LDS (contour)
 #define GBS_MAX_N_EXACT 24     // clicks per row on the exact path
 #define GBS_KMAX 2048          // contour size cap
 #define GBS_QCAP (GBS_KMAX / 2 + 1)
@@ -84,7 +84,7 @@ struct gbs_plan {
     int32_t *d_items = nullptr;           // work items (row, chunk), 2 ints each
     int32_t *d_counter = nullptr;         // work queues: [0] end, [1] head (rows <= GBS_NSMALL),
                                           // [4] end, [5] head (larger rows); [2,3], [6,7] adjoint
-    double *d_wbig = nullptr;             // eigen-decomposition scratch of the larger rows, like d_v
+    double *d_wbig = nullptr;             // 2 (2n)^2 per row: eigen-decomposition, then adjoint scratch
     cplx *d_mscr = nullptr;               // per-workgroup M(w) scratch of the larger rows
     int mscr_blocks = 0;                  // workgroups d_mscr serves
     int32_t *d_cluster_items = nullptr;   // per click count n: packed cluster units (a, b, c0, c1),
@@ -127,4 +127,4 @@ int exact_run(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes,
               double *logp, double *kappa, int32_t *status);
 int approx_backward(gbs_ctx *ctx, gbs_plan *plan, const double *dl_dev, const int32_t *status_dev,
                     double *grad_r_dev, double *grad_eta_dev);
-int eig_big(gbs_ctx *ctx, gbs_plan *plan);
+int eig_rows(gbs_ctx *ctx, gbs_plan *plan);
