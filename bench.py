@@ -251,6 +251,17 @@ def main():
     ms_fwd, tim_fwd = timed(fwd, args.steps)
     ms_step, tim = timed(fwd_grad, args.steps)
     lp = logp.cpu().numpy()
+    # the same step recorded once into a HIP graph on the library's stream and replayed
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        fwd_grad()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / args.steps
+    graph_match = bool(np.array_equal(logp.cpu().numpy(), lp))
 
     ns = np.diff(wl.offsets)
     npts = (info["K"] // 2 + 1).astype(np.float64)
@@ -290,6 +301,8 @@ def main():
         "forward": {"ms_per_step": ms_fwd, "probs_per_s": wl.P / (ms_fwd * 1e-3),
                     "subset_dets_per_s": dets / (ms_fwd * 1e-3),
                     "kernel_ms": {k: round(v[0] / max(1, v[1]), 3) for k, v in tim_fwd.items() if v[1]}},
+        "graph": {"ms_per_step": ms_graph, "probs_per_s": wl.P / (ms_graph * 1e-3),
+                  "logp_identical_to_eager": graph_match},
         "subset_dets_per_step": dets,
         "subset_dets_per_s_fwd_grad": 2 * dets / (ms_step * 1e-3),
         "kernel_ms_per_step": {k: round(v, 3) for k, v in per.items()},

@@ -438,9 +438,10 @@ template <int ORDER, bool BIG>
 int launch_contour(gbs_ctx *ctx, gbs_plan *pl, int nmax)
 {
     hipStream_t st = ctx->stream;
-    hipFuncAttributes fa;
-    HIP_TRY(ctx, hipFuncGetAttributes(&fa, (const void *)k_contour<ORDER, BIG>));
-    const int lds_cap = ctx->lds_per_block - (int)fa.sharedSizeBytes;
+    const void *fn = (const void *)k_contour<ORDER, BIG>;
+    int lds_static = 0;
+    if (int rc = func_static_lds(ctx, fn, &lds_static)) return rc;
+    const int lds_cap = ctx->lds_per_block - lds_static;
     int lds_c;
     if (BIG) {
         // the largest row's M(w) in LDS if it fits, else only alpha (M in HBM)
@@ -454,12 +455,9 @@ int launch_contour(gbs_ctx *ctx, gbs_plan *pl, int nmax)
         if (cont_fixed() + cont_vbytes(nmax) + cont_mbytes(nmax) > lds_c)
             return set_err(ctx, GBS_E_INVAL, "row too large for the contour kernel's LDS");
     }
-    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_contour<ORDER, BIG>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds_c));
-    int occ = 0;
-    HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_contour<ORDER, BIG>,
-                                                              CONT_THREADS, lds_c));
-    if (occ < 1) occ = 1;
+    int occ = 1;
+    if (int rc = func_lds_limit(ctx, fn, lds_c)) return rc;
+    if (int rc = func_occupancy(ctx, fn, CONT_THREADS, lds_c, &occ)) return rc;
     int grid = occ * ctx->num_cu;
     cplx *mscr = nullptr;
     long long mstride = 0;
@@ -497,8 +495,7 @@ int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
     if (nbig < P && (rc = launch_contour<ORDER, false>(ctx, pl, nsmall_max))) return rc;
     timer_end(ctx, ts);
     size_t lds_f = sizeof(cplx) * (GBS_KMAX + GBS_KMAX / 2);
-    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_dft_fit<ORDER>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f));
+    if ((rc = func_lds_limit(ctx, (const void *)k_dft_fit<ORDER>, (int)lds_f))) return rc;
     ts = timer_begin(ctx, TG_FIT);
     hipLaunchKernelGGL(k_dft_fit<ORDER>, dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
                        pl->d_rows, pl->d_sw, logp, status);

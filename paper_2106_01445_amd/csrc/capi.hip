@@ -31,6 +31,40 @@ static hipEvent_t pool_event(gbs_ctx *ctx)
     return e;
 }
 
+int func_static_lds(gbs_ctx *ctx, const void *f, int *bytes)
+{
+    auto it = ctx->lds_static.find(f);
+    if (it == ctx->lds_static.end()) {
+        hipFuncAttributes fa;
+        HIP_TRY(ctx, hipFuncGetAttributes(&fa, f));
+        it = ctx->lds_static.emplace(f, (int)fa.sharedSizeBytes).first;
+    }
+    *bytes = it->second;
+    return 0;
+}
+
+int func_lds_limit(gbs_ctx *ctx, const void *f, int bytes)
+{
+    auto it = ctx->lds_limit.find(f);
+    if (it != ctx->lds_limit.end() && it->second >= bytes) return 0;
+    HIP_TRY(ctx, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    ctx->lds_limit[f] = bytes;
+    return 0;
+}
+
+int func_occupancy(gbs_ctx *ctx, const void *f, int threads, int lds, int *blocks)
+{
+    const auto key = std::make_pair(f, lds * 2048 + threads / 64);
+    auto it = ctx->occupancy.find(key);
+    if (it == ctx->occupancy.end()) {
+        int occ = 0;
+        HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, threads, lds));
+        it = ctx->occupancy.emplace(key, occ < 1 ? 1 : occ).first;
+    }
+    *blocks = it->second;
+    return 0;
+}
+
 int timer_begin(gbs_ctx *ctx, int group)
 {
     if (!ctx->timing) return -1;

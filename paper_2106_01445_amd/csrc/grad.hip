@@ -943,8 +943,7 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
     DevModel &m = ctx->model;
     const int P = pl->P, nmax = pl->max_n, M = m.M;
     size_t lds_f = sizeof(cplx) * (GBS_KMAX + GBS_KMAX / 2);
-    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_adj_fit<ORDER>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f));
+    if (int rc = func_lds_limit(ctx, (const void *)k_adj_fit<ORDER>, (int)lds_f)) return rc;
     int ts = timer_begin(ctx, TG_ADJ_FIT);
     hipLaunchKernelGGL(k_adj_fit<ORDER>, dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
                        pl->d_rows, pl->d_sw, dl, pl->d_asw);
@@ -955,19 +954,17 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
     if (pl->nbig > 0) {
         // larger rows: V and M(w) in HBM, Z(w) (all of it at order 3, its diagonal
         // blocks otherwise) in LDS
-        hipFuncAttributes fa;
-        HIP_TRY(ctx, hipFuncGetAttributes(&fa, (const void *)k_adj_contour<ORDER, true>));
+        const void *fn = (const void *)k_adj_contour<ORDER, true>;
+        int lds_static = 0;
+        if (int rc = func_static_lds(ctx, fn, &lds_static)) return rc;
         const int nb = nmax, npb = nb * (nb - 1) / 2;
         const int lds_b = adj_fixed() + 8 * 2 * nb + 16 * 2 * 2 * nb + 16 * 3 * nb +
                           (ORDER >= 3 ? 16 * 4 * npb : 0);
-        if (lds_b + (int)fa.sharedSizeBytes > ctx->lds_per_block)
+        if (lds_b + lds_static > ctx->lds_per_block)
             return set_err(ctx, GBS_E_INVAL, "rows too large for the gradient kernel's LDS");
-        HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_adj_contour<ORDER, true>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds_b));
-        int occ = 0;
-        HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_adj_contour<ORDER, true>,
-                                                                  CONT_THREADS, lds_b));
-        if (occ < 1) occ = 1;
+        int occ = 1;
+        if (int rc = func_lds_limit(ctx, fn, lds_b)) return rc;
+        if (int rc = func_occupancy(ctx, fn, CONT_THREADS, lds_b, &occ)) return rc;
         int grid = std::min(occ * ctx->num_cu, pl->ascr_blocks);
         hipLaunchKernelGGL((k_adj_contour<ORDER, true>), dim3(grid), dim3(CONT_THREADS), lds_b, st,
                            pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_aitems,
@@ -977,19 +974,17 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
     }
     const int ns = pl->max_n_small;
     if (pl->nbig < P) {
-        hipFuncAttributes fa;
-        HIP_TRY(ctx, hipFuncGetAttributes(&fa, (const void *)k_adj_contour<ORDER, false>));
+        const void *fn = (const void *)k_adj_contour<ORDER, false>;
+        int lds_static = 0;
+        if (int rc = func_static_lds(ctx, fn, &lds_static)) return rc;
         int lds_a = 0;
         for (int k = 1; k <= ns; ++k) lds_a = std::max(lds_a, adj_need(k));
         lds_a += adj_fixed();
-        if (lds_a + (int)fa.sharedSizeBytes > ctx->lds_per_block)
+        if (lds_a + lds_static > ctx->lds_per_block)
             return set_err(ctx, GBS_E_INVAL, "rows too large for the gradient kernel's LDS");
-        HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_adj_contour<ORDER, false>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds_a));
-        int occ = 0;
-        HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_adj_contour<ORDER, false>,
-                                                                  CONT_THREADS, lds_a));
-        if (occ < 1) occ = 1;
+        int occ = 1;
+        if (int rc = func_lds_limit(ctx, fn, lds_a)) return rc;
+        if (int rc = func_occupancy(ctx, fn, CONT_THREADS, lds_a, &occ)) return rc;
         hipLaunchKernelGGL((k_adj_contour<ORDER, false>), dim3(occ * ctx->num_cu), dim3(CONT_THREADS),
                            lds_a, st, pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows,
                            pl->d_aitems, pl->d_counter + 2, pl->d_counter + 3,
@@ -1003,8 +998,7 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
     if (pl->nbig < P) {
         const int N = 2 * ns;
         size_t lds_r = sizeof(double) * 3 * (size_t)N * N + sizeof(int) * N;
-        HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_adj_reduce,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r));
+        if (int rc = func_lds_limit(ctx, (const void *)k_adj_reduce, (int)lds_r)) return rc;
         hipLaunchKernelGGL(k_adj_reduce, dim3(P), dim3(256), lds_r, st, M, pl->d_offsets, pl->d_modes,
                            pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, dl, pl->d_ritem0, pl->d_roff,
                            pl->d_rscr, pl->d_qibar);

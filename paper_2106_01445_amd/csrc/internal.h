@@ -2,7 +2,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "dd.h"
@@ -52,7 +54,16 @@ struct gbs_ctx {
     bool timing = false;
     std::vector<TimedLaunch> timeline;
     std::vector<hipEvent_t> event_pool;
+    // per-kernel launch facts, queried once: a launch then makes no call besides
+    // the kernel itself, so a step can be recorded into a HIP graph
+    std::map<const void *, int> lds_limit, lds_static;
+    std::map<std::pair<const void *, int>, int> occupancy;
 };
+
+// Cached kernel queries (see gbs_ctx).
+int func_static_lds(gbs_ctx *ctx, const void *f, int *bytes);
+int func_lds_limit(gbs_ctx *ctx, const void *f, int bytes);
+int func_occupancy(gbs_ctx *ctx, const void *f, int threads, int lds, int *blocks);
 
 // Bracket a group of launches with events when timing is on (no-ops otherwise).
 int timer_begin(gbs_ctx *ctx, int group);

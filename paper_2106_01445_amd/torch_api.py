@@ -89,3 +89,49 @@ class ClickLogProb(torch.autograd.Function):
         r, eta = ctx.saved_tensors
         gr, ge = ctx.model.backward_raw(r, eta, grad_logp)
         return gr, ge, None
+
+
+class StepGraph:
+    """One model build + forward (+ adjoint when dl is given) of a ClickModel,
+    recorded once into a HIP graph on the model's stream.  The inputs live in
+    the tensors self.r, self.eta (and self.dl): copy new values into them and
+    call replay(); results land in self.logp, self.status, self.grad_r,
+    self.grad_eta.  The first, eager run allocates every workspace, so the
+    recorded launches make no allocation or host synchronisation."""
+
+    def __init__(self, model: ClickModel, r: torch.Tensor, eta: torch.Tensor,
+                 dl: torch.Tensor = None):
+        dev = model.device
+        self.model = model
+        self.r = r.detach().to(dev, torch.float64).clone()
+        self.eta = eta.detach().to(dev, torch.float64).clone()
+        self.dl = None if dl is None else dl.detach().to(dev, torch.float64).clone()
+        self.logp = torch.empty(model.P, dtype=torch.float64, device=dev)
+        self.status = torch.empty(model.P, dtype=torch.int32, device=dev)
+        self.grad_r = torch.zeros(model.M, dtype=torch.float64, device=dev)
+        self.grad_eta = torch.zeros(model.M, dtype=torch.float64, device=dev)
+        model._enter()
+        self._launch()
+        model.stream.synchronize()
+        if model.freeze_plan:
+            model.plan.freeze(True)
+            model._ran = True
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=model.stream):
+            self._launch()
+        model.stream.synchronize()
+
+    def _launch(self):
+        m = self.model
+        m.ctx.gbs_set_model_dev(m.ure, m.uim, self.r, self.eta)
+        if self.dl is None:
+            m.ctx.gbs_prob_approx_dev(m.plan, self.logp, self.status)
+        else:
+            m.ctx.gbs_grad_dev(m.plan, self.dl, self.logp, self.grad_r, self.grad_eta, self.status)
+
+    def replay(self):
+        """Re-run the recorded step on the model's stream (ordered after the
+        current stream's work; the current stream waits for it)."""
+        self.model._enter()
+        self.graph.replay()
+        torch.cuda.current_stream(self.model.device).wait_stream(self.model.stream)
