@@ -149,6 +149,23 @@ def big_leg(ctx, torch, cfg: int, name: str):
     return out
 
 
+def plain_leg(ctx, wl, tuned_logp, tuned_fwd_kernel_ms):
+    """The same forward through the plain comparison kernel (one workgroup per
+    row, contour points in sequence, own LDL^T per cluster): device time per
+    kernel group, and the speed-up of the tuned forward over it."""
+    ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    ctx.gbs_timing()
+    ctx.gbs_set_timing(True)
+    out = ctx.gbs_prob_approx_plain(wl.offsets, wl.modes, wl.order)
+    tim = ctx.gbs_timing()
+    ctx.gbs_set_timing(False)
+    km = {k: round(v[0], 3) for k, v in tim.items() if v[1]}
+    ms = sum(km.values())
+    return {"kernel_ms": km, "ms": ms, "probs_per_s": wl.P / (ms * 1e-3),
+            "speedup_of_tuned_forward": ms / tuned_fwd_kernel_ms,
+            "max_abs_dlogp_vs_tuned": float(np.max(np.abs(out["logp"] - tuned_logp)))}
+
+
 def source_sha(paths):
     import hashlib
     h = hashlib.sha256()
@@ -179,6 +196,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-exact", action="store_true", help="skip the 20-mode exact leg")
     ap.add_argument("--no-big", action="store_true", help="skip the 100- and 144-mode legs")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain comparison kernel")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 3 times (calibrates the "
                          "HBM byte counters against a kernel of known traffic)")
@@ -309,6 +327,9 @@ def main():
         "contour_points_per_step": int(npts.sum()),
         "roofline": roof,
     }
+    if not args.no_plain:
+        fwd_kernel_ms = sum(v[0] / max(1, v[1]) for k, v in tim_fwd.items() if v[1] and k != "model")
+        out["plain_forward"] = plain_leg(ctx, wl, lp, fwd_kernel_ms)
     if not args.no_exact:
         out["exact_m20"] = exact_leg(ctx)
     if not args.no_big:

@@ -137,6 +137,17 @@ int gbs_prob_approx(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
                     int prec, double *logp, int32_t *status);
 
 /*
+ * The same estimate (same eigen-decomposition, contour plan, sector transform
+ * and fits) with a plain contour kernel in place of the tuned one: one
+ * workgroup per row, contour points in sequence, M(w) by plain dot products,
+ * and every cluster determinant by its own unpivoted LDL^T.  For speed-up
+ * comparisons and as an independent check of gbs_prob_approx.  Rows may hold
+ * at most 40 clicks; arguments, outputs and errors as gbs_prob_approx.
+ */
+int gbs_prob_approx_plain(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes,
+                          int order, int prec, double *logp, int32_t *status);
+
+/*
  * Plans: the per-batch layout (rows sorted by cost, device copies of the CSR,
  * workspace) built once and reused.  gbs_plan_create copies the host CSR.
  * The plan holds the contour radius and size per row from the first run on;

@@ -504,7 +504,40 @@ int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
     return 0;
 }
 
+// The plain comparison kernel (plain.hip) in place of the contour kernels.
+template <int ORDER>
+int launch_plain(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
+{
+    hipStream_t st = ctx->stream;
+    int ts = timer_begin(ctx, TG_PREP);
+    int rc = eig_rows(ctx, pl);
+    if (rc) return rc;
+    timer_end(ctx, ts);
+    ts = timer_begin(ctx, TG_CONTOUR);
+    if ((rc = plain_contour(ctx, pl))) return rc;
+    timer_end(ctx, ts);
+    size_t lds_f = sizeof(cplx) * (GBS_KMAX + GBS_KMAX / 2);
+    if ((rc = func_lds_limit(ctx, (const void *)k_dft_fit<ORDER>, (int)lds_f))) return rc;
+    ts = timer_begin(ctx, TG_FIT);
+    hipLaunchKernelGGL(k_dft_fit<ORDER>, dim3(pl->P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
+                       pl->d_rows, pl->d_sw, logp, status);
+    timer_end(ctx, ts);
+    HIP_TRY(ctx, hipGetLastError());
+    return 0;
+}
+
 }  // namespace
+
+int approx_forward_plain(gbs_ctx *ctx, gbs_plan *pl, double *logp_dev, int32_t *status_dev)
+{
+    if (pl->P == 0) return 0;
+    switch (pl->order) {
+    case 1: return launch_plain<1>(ctx, pl, logp_dev, status_dev);
+    case 2: return launch_plain<2>(ctx, pl, logp_dev, status_dev);
+    case 3: return launch_plain<3>(ctx, pl, logp_dev, status_dev);
+    default: return set_err(ctx, -1, "order must be 1, 2 or 3");
+    }
+}
 
 int approx_forward(gbs_ctx *ctx, gbs_plan *pl, double *logp_dev, int32_t *status_dev)
 {

@@ -547,6 +547,31 @@ int gbs_prob_approx(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
     return GBS_OK;
 }
 
+int gbs_prob_approx_plain(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int order,
+                    int prec, double *logp, int32_t *status)
+{
+    if (!ctx) return GBS_E_INVAL;
+    if (P > 0 && (!logp || !status)) return set_err(ctx, GBS_E_INVAL, "NULL output array");
+    gbs_plan *pl = nullptr;
+    int rc = gbs_plan_create(ctx, P, offsets, modes, order, prec, &pl);
+    if (rc) return rc;
+    rc = pl->max_n > GBS_NSMALL
+             ? set_err(ctx, GBS_E_INVAL, "the plain kernel takes rows of at most 40 clicks")
+             : approx_forward_plain(ctx, pl, pl->d_logp, pl->d_status);
+    if (rc == 0 && P > 0) {
+        hipError_t e = hipMemcpyAsync(logp, pl->d_logp, P * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(status, pl->d_status, P * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) rc = set_err(ctx, GBS_E_HIP, hipGetErrorString(e));
+    }
+    gbs_plan_destroy(pl);
+    if (rc) return rc;
+    for (int p = 0; p < P; ++p)
+        if (status[p] != 0) return GBS_W_PATTERN;
+    return GBS_OK;
+}
+
 int gbs_plan_info(gbs_plan *pl, double *rho, double *rconv, int32_t *K, int32_t *nsectors)
 {
     if (!pl) return GBS_E_INVAL;

@@ -139,3 +139,5 @@ int exact_run(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes,
 int approx_backward(gbs_ctx *ctx, gbs_plan *plan, const double *dl_dev, const int32_t *status_dev,
                     double *grad_r_dev, double *grad_eta_dev);
 int eig_rows(gbs_ctx *ctx, gbs_plan *plan);
+int plain_contour(gbs_ctx *ctx, gbs_plan *plan);
+int approx_forward_plain(gbs_ctx *ctx, gbs_plan *plan, double *logp_dev, int32_t *status_dev);

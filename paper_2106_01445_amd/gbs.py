@@ -22,6 +22,7 @@ GBS_PS_FIT_NOCONV, GBS_PS_CONTOUR, GBS_PS_PIVOT, GBS_PS_CANCEL = 1, 2, 4, 16
 
 EXPORTS = ["gbs_create", "gbs_destroy", "gbs_last_error", "gbs_set_model", "gbs_set_model_dev",
            "gbs_set_covariance", "gbs_get_model", "gbs_prob_exact", "gbs_prob_approx",
+           "gbs_prob_approx_plain",
            "gbs_plan_create", "gbs_plan_destroy", "gbs_plan_freeze", "gbs_prob_approx_dev",
            "gbs_grad", "gbs_grad_dev", "gbs_plan_info", "gbs_set_timing", "gbs_timing",
            "gbs_stream"]
@@ -64,6 +65,7 @@ def load(path: str = LIB_PATH):
         "gbs_get_model": ([vp, dp, dp], ip),
         "gbs_prob_exact": ([vp, ip, i32p, i32p, ip, dp, dp, dp, i32p], ip),
         "gbs_prob_approx": ([vp, ip, i32p, i32p, ip, ip, dp, i32p], ip),
+        "gbs_prob_approx_plain": ([vp, ip, i32p, i32p, ip, ip, dp, i32p], ip),
         "gbs_plan_create": ([vp, ip, i32p, i32p, ip, ip, pp], ip),
         "gbs_plan_destroy": ([vp], ip),
         "gbs_plan_freeze": ([vp, ip], ip),
@@ -213,6 +215,15 @@ class Context:
         st = np.zeros(P, np.int32)
         self._check(load().gbs_prob_approx(self.handle, P, _ptr(off), _ptr(mod), order, prec,
                                            _ptr(lp), _ptr(st)))
+        return dict(logp=lp, status=st)
+
+    def gbs_prob_approx_plain(self, offsets, modes, order: int, prec: int = GBS_PREC_FP64):
+        off, mod = _i32(offsets), _i32(modes)
+        P = len(off) - 1
+        lp = np.zeros(P)
+        st = np.zeros(P, np.int32)
+        self._check(load().gbs_prob_approx_plain(self.handle, P, _ptr(off), _ptr(mod), order, prec,
+                                                 _ptr(lp), _ptr(st)))
         return dict(logp=lp, status=st)
 
     def gbs_plan_create(self, offsets, modes, order: int, prec: int = GBS_PREC_FP64) -> Plan:

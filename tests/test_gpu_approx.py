@@ -139,3 +139,17 @@ def test_argument_errors(gpu_ctx, rows, order):
     with pytest.raises(g.GBSError) as e:
         gpu_ctx.gbs_prob_approx(off, mod, order)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("cfg,order,P", [(1, 2, None), (2, 3, 512), (3, 3, 64)])
+def test_plain_kernel_agrees(gpu_ctx, cfg, order, P):
+    """The plain comparison kernel (own LDL^T per cluster, no reuse) and the tuned
+    contour kernel agree: they share only the eigen-decomposition, the plan and
+    the fits, so this cross-checks the M(w) tiles on the matrix cores, the
+    2x2-block eliminations and the work units."""
+    wl = make_workload(cfg, P=P)
+    gpu_ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    a = gpu_ctx.gbs_prob_approx(wl.offsets, wl.modes, order)
+    b = gpu_ctx.gbs_prob_approx_plain(wl.offsets, wl.modes, order)
+    assert np.all(a["status"] == 0) and np.all(b["status"] == 0)
+    assert np.max(np.abs(a["logp"] - b["logp"])) < 1e-10
