@@ -197,6 +197,7 @@ def main():
     ap.add_argument("--no-exact", action="store_true", help="skip the 20-mode exact leg")
     ap.add_argument("--no-big", action="store_true", help="skip the 100- and 144-mode legs")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain comparison kernel")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch choices")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 3 times (calibrates the "
                          "HBM byte counters against a kernel of known traffic)")
@@ -266,6 +267,19 @@ def main():
     if not np.all(np.isfinite(gr.cpu().numpy())) or not np.all(np.isfinite(ge.cpu().numpy())):
         raise RuntimeError("non-finite gradient")
     info = plan.info()
+    tuning = None
+    if not args.no_tune:
+        # default launch choices first, then the autotuner's
+        ms_fwd0, _ = timed(fwd, args.steps)
+        ms_step0, _ = timed(fwd_grad, args.steps)
+        t0 = time.perf_counter()
+        prm = plan.tune(3)
+        t_tune = time.perf_counter() - t0
+        fwd_grad()
+        torch.cuda.synchronize()
+        tuning = {"params": {"seg_forward": int(prm[0]), "seg_adjoint": int(prm[1]),
+                             "points_per_item": int(prm[2]), "points_per_pass": int(prm[3])},
+                  "tune_s": t_tune, "default_ms_per_step": ms_step0, "default_forward_ms": ms_fwd0}
     ms_fwd, tim_fwd = timed(fwd, args.steps)
     ms_step, tim = timed(fwd_grad, args.steps)
     lp = logp.cpu().numpy()
@@ -319,6 +333,7 @@ def main():
         "forward": {"ms_per_step": ms_fwd, "probs_per_s": wl.P / (ms_fwd * 1e-3),
                     "subset_dets_per_s": dets / (ms_fwd * 1e-3),
                     "kernel_ms": {k: round(v[0] / max(1, v[1]), 3) for k, v in tim_fwd.items() if v[1]}},
+        "autotune": tuning,
         "graph": {"ms_per_step": ms_graph, "probs_per_s": wl.P / (ms_graph * 1e-3),
                   "logp_identical_to_eager": graph_match},
         "subset_dets_per_step": dets,

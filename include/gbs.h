@@ -177,6 +177,28 @@ int gbs_grad(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, 
 int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *plan, const double *dL_dlogp_dev, double *logp_dev,
                  double *grad_r_dev, double *grad_eta_dev, int32_t *status_dev);
 
+/*
+ * Launch choices of a plan, params[4]: [0] third modes per cluster work unit of
+ * the forward contour kernel (order 3), [1] the same for the adjoint, [2]
+ * contour points per forward work item (4, 8, 16, 32 or 64), [3] most contour
+ * points per pass of the forward kernel (1, 2, 4 or 8).  Defaults 3, 3, 8, 8.
+ * They change the speed, not the results (up to the order of floating-point
+ * sums).  gbs_plan_set_params returns GBS_E_INVAL for values outside these sets.
+ */
+int gbs_plan_get_params(gbs_plan *plan, int32_t *params);
+int gbs_plan_set_params(gbs_plan *plan, const int32_t *params);
+
+/*
+ * Autotuner: times candidate launch choices (coordinate descent over the
+ * values listed above, two runs each, the faster counts) on a stratified
+ * sample of the plan's rows (every s-th row in cost order, s = max(1, P/1024))
+ * with the context's current model, and stores the fastest in the plan.  what:
+ * bit 0 the forward choices, bit 1 the adjoint's (needs a model set from
+ * parameters).  params (nullable) receives the chosen values.  Synchronous;
+ * allocates a temporary plan for the sample.
+ */
+int gbs_plan_tune(gbs_ctx *ctx, gbs_plan *plan, int what, int32_t *params);
+
 /* Per-row diagnostics of the last run on a plan (host arrays of length P,
  * each nullable): contour radius, convergence radius, K, sectors fitted. */
 int gbs_plan_info(gbs_plan *plan, double *rho, double *rconv, int32_t *K, int32_t *nsectors);

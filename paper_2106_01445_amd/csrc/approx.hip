@@ -28,7 +28,8 @@ namespace {
 // counter[4] (length) / counter[5] (head); the rest form counter[0] (end) /
 // counter[1] (head, starting at counter[4]).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_build_items(int P, int nbig, const int *__restrict__ offsets,
+__global__ __launch_bounds__(1024) void k_build_items(int P, int nbig, int qchunk,
+                                                      const int *__restrict__ offsets,
                                                       const int *__restrict__ perm,
                                                       const RowPlan *__restrict__ rows,
                                                       int *__restrict__ items,
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(1024) void k_build_items(int P, int nbig, const int
         int n = offsets[p + 1] - offsets[p];
         const RowPlan &rp = rows[p];
         if (n == 0 || rp.status != 0 || rp.K <= 0) return 0;
-        return (rp.K / 2 + 1 + GBS_QCHUNK - 1) / GBS_QCHUNK;
+        return (rp.K / 2 + 1 + qchunk - 1) / qchunk;
     };
     if (tid == 0) s_big = 0;
     int s = 0, sb = 0;
@@ -102,7 +103,8 @@ __global__ __launch_bounds__(1024) void k_build_items(int P, int nbig, const int
 // ---------------------------------------------------------------------------
 template <int ORDER, bool BIG>
 __global__ __launch_bounds__(CONT_THREADS) void k_contour(
-    int lds_bytes, const int *__restrict__ offsets, const long long *__restrict__ voff,
+    int lds_bytes, int qchunk, int gmax, const int *__restrict__ offsets,
+    const long long *__restrict__ voff,
     const double *__restrict__ alpha, const double *__restrict__ vt,
     const RowPlan *__restrict__ rows, const int *__restrict__ items, const int *__restrict__ q_end,
     int *__restrict__ q_head, const int *__restrict__ units, const int *__restrict__ unit_off,
@@ -141,14 +143,14 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
             double *vl = dyn;
             al = vl + N * N;
             slots = (cplx *)(al + N);
-            G = CONT_MAXG;
+            G = gmax;
             while (G > 1 && cont_fixed() + cont_vbytes(n) + G * cont_mbytes(n) > lds_bytes) G >>= 1;
             for (int idx = tid; idx < N * N; idx += CONT_THREADS) vl[idx] = vt[vo + idx];
             Vt = vl;
         }
         for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
         const int Q = rp.K / 2 + 1;
-        const int q0 = ch * GBS_QCHUNK, q1 = min(q0 + GBS_QCHUNK, Q);
+        const int q0 = ch * qchunk, q1 = min(q0 + qchunk, Q);
         const int np = n * (n - 1) / 2;
         __syncthreads();
         for (int qb = q0; qb < q1; qb += G) {
@@ -450,7 +452,7 @@ int launch_contour(gbs_ctx *ctx, gbs_plan *pl, int nmax)
     } else {
         // the whole 160 KB when the largest row needs it, else enough for eight
         // contour points of the largest row (two workgroups may then share a CU)
-        lds_c = cont_fixed() + cont_vbytes(nmax) + CONT_MAXG * cont_mbytes(nmax);
+        lds_c = cont_fixed() + cont_vbytes(nmax) + pl->gmax * cont_mbytes(nmax);
         if (lds_c > lds_cap) lds_c = lds_cap;
         if (cont_fixed() + cont_vbytes(nmax) + cont_mbytes(nmax) > lds_c)
             return set_err(ctx, GBS_E_INVAL, "row too large for the contour kernel's LDS");
@@ -471,7 +473,7 @@ int launch_contour(gbs_ctx *ctx, gbs_plan *pl, int nmax)
     const int *q_end = pl->d_counter + (BIG ? 4 : 0);
     int *q_head = pl->d_counter + (BIG ? 5 : 1);
     hipLaunchKernelGGL((k_contour<ORDER, BIG>), dim3(grid), dim3(CONT_THREADS), lds_c, st, lds_c,
-                       pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_items,
+                       pl->qchunk, pl->gmax, pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_items,
                        q_end, q_head, pl->d_cluster_items, pl->d_cluster_off, mscr, mstride, pl->d_sw);
     return 0;
 }
@@ -487,7 +489,8 @@ int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
     if (rc) return rc;
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_ITEMS);
-    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, st, P, nbig, pl->d_offsets, pl->d_perm,
+    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, st, P, nbig, pl->qchunk, pl->d_offsets,
+                       pl->d_perm,
                        pl->d_rows, pl->d_items, pl->d_counter);
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_CONTOUR);

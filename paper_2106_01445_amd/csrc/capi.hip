@@ -134,7 +134,7 @@ void plan_free_dev(gbs_plan *pl)
 // for the adjoint (neighbouring lanes hold distinct a, b and c, so their
 // scatters into Z(w) never meet in one instruction), so that a strided
 // assignment to threads is balanced.
-void cluster_units(int n, int order, bool adjoint, std::vector<int32_t> &out)
+void cluster_units(int n, int order, int seg, bool adjoint, std::vector<int32_t> &out)
 {
     struct U { int a, b, c0, c1; };
     std::vector<U> u;
@@ -144,8 +144,8 @@ void cluster_units(int n, int order, bool adjoint, std::vector<int32_t> &out)
                 u.push_back({a, b, b + 1, b + 1});
                 continue;
             }
-            for (int c0 = b + 1; c0 < n; c0 += GBS_CLUSTER_SEG)
-                u.push_back({a, b, c0, std::min(c0 + GBS_CLUSTER_SEG, n)});
+            for (int c0 = b + 1; c0 < n; c0 += seg)
+                u.push_back({a, b, c0, std::min(c0 + seg, n)});
         }
     std::stable_sort(u.begin(), u.end(), [adjoint](const U &x, const U &y) {
         if (x.c1 - x.c0 != y.c1 - y.c0) return x.c1 - x.c0 > y.c1 - y.c0;
@@ -176,6 +176,37 @@ int dev_alloc(gbs_ctx *ctx, T **p, size_t count)
 }
 
 }  // namespace
+
+// (Re)build the cluster work units of a plan for its segment lengths: the
+// forward list, then the adjoint list; offsets [n] -> (offset, count) for the
+// forward at d_cluster_off, for the adjoint at d_cluster_off + 2 (max_n + 1).
+int plan_units(gbs_ctx *ctx, gbs_plan *pl)
+{
+    const int nm = pl->max_n;
+    std::vector<int32_t> citems, coff(4 * (nm + 1), 0);
+    for (int pass = 0; pass < 2; ++pass)
+        for (int n = 0; n <= nm; ++n) {
+            int32_t *o = coff.data() + 2 * (nm + 1) * pass + 2 * n;
+            o[0] = (int32_t)citems.size();
+            if (pl->order >= 2)
+                cluster_units(n, pl->order, pass ? pl->seg_adj : pl->seg_fwd, pass == 1, citems);
+            o[1] = (int32_t)citems.size() - o[0];
+        }
+    pl->n_cluster_items = (int)citems.size();
+    if (pl->d_cluster_items) (void)hipFree(pl->d_cluster_items);
+    if (pl->d_cluster_off) (void)hipFree(pl->d_cluster_off);
+    pl->d_cluster_items = nullptr;
+    pl->d_cluster_off = nullptr;
+    int e = dev_alloc(ctx, &pl->d_cluster_items, citems.size());
+    e = e ? e : dev_alloc(ctx, &pl->d_cluster_off, coff.size());
+    if (e) return e;
+    HIP_TRY(ctx, hipMemcpyAsync(pl->d_cluster_items, citems.data(), citems.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(pl->d_cluster_off, coff.data(), coff.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return 0;
+}
 
 // Gradient workspace of a plan, allocated on first use.
 int adj_workspace(gbs_ctx *ctx, gbs_plan *pl)
@@ -431,18 +462,7 @@ int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
     std::iota(pl->h_perm.begin(), pl->h_perm.end(), 0);
     std::stable_sort(pl->h_perm.begin(), pl->h_perm.end(),
                      [&](int a, int b) { return pl->h_n[a] > pl->h_n[b]; });
-    // cluster work lists for every click count up to max_n
-    std::vector<int32_t> citems, coff(2 * (pl->max_n + 1), 0);
-    for (int n = 0; n <= pl->max_n; ++n) {
-        coff[2 * n] = (int32_t)citems.size();
-        if (order >= 2) cluster_units(n, order, false, citems);
-        coff[2 * n + 1] = (int32_t)citems.size() - coff[2 * n];
-    }
-    pl->n_cluster_items = (int)citems.size();
-    // the adjoint's ordering of the same units follows, at the same offsets + total
-    for (int n = 0; n <= pl->max_n; ++n)
-        if (order >= 2) cluster_units(n, order, true, citems);
-    long long max_items = (long long)P * ((GBS_QCAP + GBS_QCHUNK - 1) / GBS_QCHUNK);
+    long long max_items = (long long)P * ((GBS_QCAP + GBS_QCHUNK_MIN - 1) / GBS_QCHUNK_MIN);
     pl->max_items = (int)max_items;
     int e = 0;
     e = e ? e : dev_alloc(ctx, &pl->d_offsets, P + 1);
@@ -464,8 +484,6 @@ int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
             e = e ? e : dev_alloc(ctx, &pl->d_mscr, (size_t)pl->mscr_blocks * ms);
         }
     }
-    e = e ? e : dev_alloc(ctx, &pl->d_cluster_items, citems.size());
-    e = e ? e : dev_alloc(ctx, &pl->d_cluster_off, coff.size());
     e = e ? e : dev_alloc(ctx, &pl->d_logp, P);
     e = e ? e : dev_alloc(ctx, &pl->d_status, P);
     if (e) {
@@ -482,13 +500,16 @@ int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
     if (he == hipSuccess) he = cp(pl->d_modes, pl->h_modes.data(), nnz * sizeof(int32_t));
     if (he == hipSuccess) he = cp(pl->d_perm, pl->h_perm.data(), P * sizeof(int32_t));
     if (he == hipSuccess) he = cp(pl->d_voff, voff.data(), P * sizeof(long long));
-    if (he == hipSuccess) he = cp(pl->d_cluster_items, citems.data(), citems.size() * sizeof(int32_t));
-    if (he == hipSuccess) he = cp(pl->d_cluster_off, coff.data(), coff.size() * sizeof(int32_t));
     if (he == hipSuccess) he = hipStreamSynchronize(st);
     if (he != hipSuccess) {
         plan_free_dev(pl);
         delete pl;
         return set_err(ctx, GBS_E_HIP, hipGetErrorString(he));
+    }
+    if ((rc = plan_units(ctx, pl))) {
+        plan_free_dev(pl);
+        delete pl;
+        return rc;
     }
     *out = pl;
     return GBS_OK;
@@ -569,6 +590,145 @@ int gbs_prob_approx_plain(gbs_ctx *ctx, int P, const int32_t *offsets, const int
     if (rc) return rc;
     for (int p = 0; p < P; ++p)
         if (status[p] != 0) return GBS_W_PATTERN;
+    return GBS_OK;
+}
+
+int gbs_plan_get_params(gbs_plan *pl, int32_t *params)
+{
+    if (!pl || !params) return GBS_E_INVAL;
+    params[0] = pl->seg_fwd;
+    params[1] = pl->seg_adj;
+    params[2] = pl->qchunk;
+    params[3] = pl->gmax;
+    return GBS_OK;
+}
+
+int gbs_plan_set_params(gbs_plan *pl, const int32_t *params)
+{
+    if (!pl || !params) return GBS_E_INVAL;
+    gbs_ctx *ctx = pl->ctx;
+    const int sf = params[0], sa = params[1], qc = params[2], gm = params[3];
+    if (sf < 1 || sf > 64 || sa < 1 || sa > 64)
+        return set_err(ctx, GBS_E_INVAL, "segment lengths must be in [1, 64]");
+    if (qc < GBS_QCHUNK_MIN || qc > 64 || (qc & (qc - 1)))
+        return set_err(ctx, GBS_E_INVAL, "contour points per item must be 4, 8, 16, 32 or 64");
+    if (gm < 1 || gm > 8 || (gm & (gm - 1)))
+        return set_err(ctx, GBS_E_INVAL, "points per pass must be 1, 2, 4 or 8");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const bool units = sf != pl->seg_fwd || sa != pl->seg_adj;
+    pl->seg_fwd = sf;
+    pl->seg_adj = sa;
+    pl->qchunk = qc;
+    pl->gmax = gm;
+    return units ? plan_units(ctx, pl) : GBS_OK;
+}
+
+namespace {
+
+// device time (ms) of one forward, or one adjoint after a forward, on a plan;
+// the smaller of two runs
+int time_pass(gbs_ctx *ctx, gbs_plan *pl, bool adjoint, const double *dl, double *g, double *ms)
+{
+    hipEvent_t a, b;
+    HIP_TRY(ctx, hipEventCreate(&a));
+    HIP_TRY(ctx, hipEventCreate(&b));
+    double best = 1e300;
+    int rc = 0;
+    for (int rep = 0; rep < 2 && !rc; ++rep) {
+        if (adjoint && (rc = approx_forward(ctx, pl, pl->d_logp, pl->d_status))) break;
+        (void)hipEventRecord(a, ctx->stream);
+        rc = adjoint ? approx_backward(ctx, pl, dl, pl->d_status, g, g + ctx->model.M)
+                     : approx_forward(ctx, pl, pl->d_logp, pl->d_status);
+        (void)hipEventRecord(b, ctx->stream);
+        if (!rc && hipEventSynchronize(b) != hipSuccess) rc = set_err(ctx, GBS_E_HIP, "event wait failed");
+        float e = 0.f;
+        if (!rc && hipEventElapsedTime(&e, a, b) == hipSuccess) best = std::min(best, (double)e);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = best;
+    return rc;
+}
+
+}  // namespace
+
+int gbs_plan_tune(gbs_ctx *ctx, gbs_plan *pl, int what, int32_t *params_out)
+{
+    if (!ctx || !pl) return GBS_E_INVAL;
+    if (pl->ctx != ctx) return set_err(ctx, GBS_E_STATE, "plan belongs to another context");
+    if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
+    if ((what & 2) && !ctx->model.from_params)
+        return set_err(ctx, GBS_E_STATE, "tuning the gradient needs a model set by gbs_set_model");
+    if (pl->P == 0 || !(what & 3)) return params_out ? gbs_plan_get_params(pl, params_out) : GBS_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    // a stratified sample of the rows (every s-th row in cost order, at least 512 rows)
+    const int s = std::max(1, pl->P / 1024);
+    std::vector<int32_t> off(1, 0), mod;
+    for (int k = 0; k < pl->P; k += s) {
+        const int p = pl->h_perm[k];
+        for (int i = pl->h_offsets[p]; i < pl->h_offsets[p + 1]; ++i) mod.push_back(pl->h_modes[i]);
+        off.push_back((int32_t)mod.size());
+    }
+    const int Ps = (int)off.size() - 1;
+    gbs_plan *sub = nullptr;
+    int rc = gbs_plan_create(ctx, Ps, off.data(), mod.data(), pl->order, pl->prec, &sub);
+    if (rc) return rc;
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    double *dl = nullptr, *g = nullptr;
+    int32_t cur[4], best[4];
+    gbs_plan_get_params(pl, cur);
+    std::copy(cur, cur + 4, best);
+    auto measure = [&](const int32_t *prm, bool adjoint, double *ms) {
+        int r = gbs_plan_set_params(sub, prm);
+        return r ? r : time_pass(ctx, sub, adjoint, dl, g, ms);
+    };
+    if (what & 2) {
+        rc = dev_alloc(ctx, &dl, Ps);
+        rc = rc ? rc : dev_alloc(ctx, &g, 2 * (size_t)ctx->model.M);
+        if (!rc) {
+            std::vector<double> ones(Ps, 1.0);
+            if (hipMemcpy(dl, ones.data(), Ps * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+                rc = set_err(ctx, GBS_E_HIP, "upload failed");
+        }
+    }
+    // warm-up (plan of the sample, gradient workspace)
+    double ms = 0.0;
+    if (!rc) rc = measure(best, (what & 2) != 0, &ms);
+    // coordinate descent over the candidate values, one choice at a time
+    struct Axis { int index; std::vector<int> values; bool adjoint; };
+    std::vector<Axis> axes;
+    if (what & 1) {
+        if (pl->order >= 3) axes.push_back({0, {2, 3, 4, 6}, false});
+        axes.push_back({2, {4, 8, 16}, false});
+        axes.push_back({3, {2, 4, 8}, false});
+    }
+    if ((what & 2) && pl->order >= 3) axes.push_back({1, {2, 3, 4, 6}, true});
+    for (const Axis &ax : axes) {
+        if (rc) break;
+        double tbest = 1e300;
+        int vbest = best[ax.index];
+        for (int v : ax.values) {
+            int32_t prm[4];
+            std::copy(best, best + 4, prm);
+            prm[ax.index] = v;
+            double t = 0.0;
+            if ((rc = measure(prm, ax.adjoint, &t))) break;
+            if (t < tbest) {
+                tbest = t;
+                vbest = v;
+            }
+        }
+        best[ax.index] = vbest;
+    }
+    if (dl) (void)hipFree(dl);
+    if (g) (void)hipFree(g);
+    gbs_plan_destroy(sub);
+    ctx->timing = timing;
+    if (rc) return rc;
+    rc = gbs_plan_set_params(pl, best);
+    if (rc) return rc;
+    if (params_out) std::copy(best, best + 4, params_out);
     return GBS_OK;
 }
 

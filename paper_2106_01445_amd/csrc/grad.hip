@@ -969,7 +969,7 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
         hipLaunchKernelGGL((k_adj_contour<ORDER, true>), dim3(grid), dim3(CONT_THREADS), lds_b, st,
                            pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_aitems,
                            pl->d_counter + 6, pl->d_counter + 7,
-                           pl->d_cluster_items + pl->n_cluster_items, pl->d_cluster_off, pl->d_asw,
+                           pl->d_cluster_items, pl->d_cluster_off + 2 * (pl->max_n + 1), pl->d_asw,
                            pl->d_roff, pl->d_rscr, pl->d_ascr, pl->ascr_stride);
     }
     const int ns = pl->max_n_small;
@@ -988,7 +988,7 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
         hipLaunchKernelGGL((k_adj_contour<ORDER, false>), dim3(occ * ctx->num_cu), dim3(CONT_THREADS),
                            lds_a, st, pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows,
                            pl->d_aitems, pl->d_counter + 2, pl->d_counter + 3,
-                           pl->d_cluster_items + pl->n_cluster_items, pl->d_cluster_off, pl->d_asw,
+                           pl->d_cluster_items, pl->d_cluster_off + 2 * (pl->max_n + 1), pl->d_asw,
                            pl->d_roff, pl->d_rscr, (cplx *)nullptr, 0LL);
     }
     timer_end(ctx, ts);

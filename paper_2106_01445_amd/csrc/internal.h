@@ -17,8 +17,9 @@
 #define GBS_MAX_N_EXACT 24     // clicks per row on the exact path
 #define GBS_KMAX 2048          // contour size cap
 #define GBS_QCAP (GBS_KMAX / 2 + 1)
-#define GBS_QCHUNK 8           // contour points per work item
-#define GBS_CLUSTER_SEG 3      // triples per cluster work unit (order 3)
+#define GBS_QCHUNK 8           // contour points per work item (default)
+#define GBS_QCHUNK_MIN 4       // smallest tunable value (sizes the item lists)
+#define GBS_CLUSTER_SEG 3      // triples per cluster work unit at order 3 (default)
 
 struct cplx {
     double re, im;
@@ -81,6 +82,10 @@ struct gbs_plan {
     gbs_ctx *ctx = nullptr;
     int P = 0, order = 0, prec = 0, max_n = 0;
     int nbig = 0;                         // rows with more than GBS_NSMALL clicks: perm[0..nbig)
+    // tunable launch choices (gbs_plan_tune): cluster segment length of the
+    // forward and adjoint work units, contour points per forward work item,
+    // largest number of contour points per pass of the forward kernel
+    int seg_fwd = GBS_CLUSTER_SEG, seg_adj = GBS_CLUSTER_SEG, qchunk = GBS_QCHUNK, gmax = 8;
     int max_n_small = 0;                  // largest click count among the other rows
     bool frozen = false;
     bool have_run = false;
@@ -99,8 +104,9 @@ struct gbs_plan {
     cplx *d_mscr = nullptr;               // per-workgroup M(w) scratch of the larger rows
     int mscr_blocks = 0;                  // workgroups d_mscr serves
     int32_t *d_cluster_items = nullptr;   // per click count n: packed cluster units (a, b, c0, c1),
-                                          // forward order, then adjoint order (+ n_cluster_items)
-    int32_t *d_cluster_off = nullptr;     // [n] -> offset, count (2 ints)
+                                          // the forward's list, then the adjoint's
+    int32_t *d_cluster_off = nullptr;     // [n] -> offset, count (2 ints); forward, then adjoint
+                                          // at + 2 (max_n + 1)
     double *d_logp = nullptr;             // P (scratch when caller passes none)
     int32_t *d_status = nullptr;          // P
     size_t v_total = 0;
@@ -141,3 +147,4 @@ int approx_backward(gbs_ctx *ctx, gbs_plan *plan, const double *dl_dev, const in
 int eig_rows(gbs_ctx *ctx, gbs_plan *plan);
 int plain_contour(gbs_ctx *ctx, gbs_plan *plan);
 int approx_forward_plain(gbs_ctx *ctx, gbs_plan *plan, double *logp_dev, int32_t *status_dev);
+int plan_units(gbs_ctx *ctx, gbs_plan *plan);

@@ -22,7 +22,7 @@ GBS_PS_FIT_NOCONV, GBS_PS_CONTOUR, GBS_PS_PIVOT, GBS_PS_CANCEL = 1, 2, 4, 16
 
 EXPORTS = ["gbs_create", "gbs_destroy", "gbs_last_error", "gbs_set_model", "gbs_set_model_dev",
            "gbs_set_covariance", "gbs_get_model", "gbs_prob_exact", "gbs_prob_approx",
-           "gbs_prob_approx_plain",
+           "gbs_prob_approx_plain", "gbs_plan_get_params", "gbs_plan_set_params", "gbs_plan_tune",
            "gbs_plan_create", "gbs_plan_destroy", "gbs_plan_freeze", "gbs_prob_approx_dev",
            "gbs_grad", "gbs_grad_dev", "gbs_plan_info", "gbs_set_timing", "gbs_timing",
            "gbs_stream"]
@@ -66,6 +66,9 @@ def load(path: str = LIB_PATH):
         "gbs_prob_exact": ([vp, ip, i32p, i32p, ip, dp, dp, dp, i32p], ip),
         "gbs_prob_approx": ([vp, ip, i32p, i32p, ip, ip, dp, i32p], ip),
         "gbs_prob_approx_plain": ([vp, ip, i32p, i32p, ip, ip, dp, i32p], ip),
+        "gbs_plan_get_params": ([vp, i32p], ip),
+        "gbs_plan_set_params": ([vp, i32p], ip),
+        "gbs_plan_tune": ([vp, vp, ip, i32p], ip),
         "gbs_plan_create": ([vp, ip, i32p, i32p, ip, ip, pp], ip),
         "gbs_plan_destroy": ([vp], ip),
         "gbs_plan_freeze": ([vp, ip], ip),
@@ -116,6 +119,20 @@ class Plan:
         K, ns = np.zeros(self.P, np.int32), np.zeros(self.P, np.int32)
         self.ctx._check(load().gbs_plan_info(self.handle, _ptr(rho), _ptr(rc), _ptr(K), _ptr(ns)))
         return dict(rho=rho, rconv=rc, K=K, nsectors=ns)
+
+    def get_params(self):
+        prm = np.zeros(4, np.int32)
+        self.ctx._check(load().gbs_plan_get_params(self.handle, _ptr(prm)))
+        return prm
+
+    def set_params(self, params):
+        self.ctx._check(load().gbs_plan_set_params(self.handle, _ptr(_i32(params))))
+
+    def tune(self, what: int = 3):
+        """gbs_plan_tune: bit 0 forward choices, bit 1 adjoint choices."""
+        prm = np.zeros(4, np.int32)
+        self.ctx._check(load().gbs_plan_tune(self.ctx.handle, self.handle, what, _ptr(prm)))
+        return prm
 
     def close(self):
         if self.handle:

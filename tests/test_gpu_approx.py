@@ -153,3 +153,35 @@ def test_plain_kernel_agrees(gpu_ctx, cfg, order, P):
     b = gpu_ctx.gbs_prob_approx_plain(wl.offsets, wl.modes, order)
     assert np.all(a["status"] == 0) and np.all(b["status"] == 0)
     assert np.max(np.abs(a["logp"] - b["logp"])) < 1e-10
+
+
+def test_plan_params_and_tuner(gpu_ctx):
+    """Launch choices change the speed, not the results: every setting the tuner
+    may pick gives the same log p (to the order of the sums), and the tuner
+    returns values from its candidate sets; bad values are rejected."""
+    import paper_2106_01445_amd as g
+    import torch
+    wl = make_workload(2, P=300)
+    gpu_ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    plan = gpu_ctx.gbs_plan_create(wl.offsets, wl.modes, 3)
+    assert list(plan.get_params()) == [3, 3, 8, 8]
+    out = torch.empty(wl.P, dtype=torch.float64, device="cuda")
+    gpu_ctx.gbs_prob_approx_dev(plan, out)
+    torch.cuda.synchronize()
+    ref = out.cpu().numpy().copy()
+    for prm in ([2, 3, 4, 2], [6, 2, 16, 4], [1, 6, 64, 1]):
+        plan.set_params(prm)
+        gpu_ctx.gbs_prob_approx_dev(plan, out)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(out.cpu().numpy() - ref)) < 1e-12, prm
+    for bad in ([0, 3, 8, 8], [3, 3, 12, 8], [3, 3, 8, 3]):
+        with pytest.raises(g.GBSError):
+            plan.set_params(bad)
+    prm = plan.tune(3)
+    assert prm[0] in (2, 3, 4, 6) and prm[1] in (2, 3, 4, 6)
+    assert prm[2] in (4, 8, 16) and prm[3] in (2, 4, 8)
+    assert list(plan.get_params()) == list(prm)
+    gpu_ctx.gbs_prob_approx_dev(plan, out)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(out.cpu().numpy() - ref)) < 1e-12
+    plan.close()
