@@ -105,7 +105,7 @@ def exact_leg(ctx, steps: int = 3):
             "max_kappa": float(out["kappa"].max()), "status_nonzero": int(np.sum(out["status"] != 0))}
 
 
-def big_leg(ctx, torch, cfg: int, name: str):
+def big_leg(ctx, torch, cfg: int, name: str, mixed: bool = False):
     """One forward and one forward + adjoint pass (after a warm-up) on the 100-
     or 144-mode batch (rows up to 60 / 110 clicks: eigenvectors and M(w) in HBM);
     device timings per kernel group."""
@@ -146,6 +146,31 @@ def big_leg(ctx, torch, cfg: int, name: str):
                     "status_nonzero": int((st != 0).sum().item()),
                     "kernel_ms": {k: round(v[0], 3) for k, v in tim.items() if v[1]}}
     plan.close()
+    if mixed:
+        # the same forward with fp32 cluster eliminations (GBS_PREC_MIXED)
+        import paper_2106_01445_amd as g
+        ref = logp.cpu().numpy()
+        pm = ctx.gbs_plan_create(wl.offsets, wl.modes, wl.order, prec=g.GBS_PREC_MIXED)
+        lm = torch.empty(wl.P, dtype=torch.float64, device=dev)
+        for rep in range(2):
+            ctx.gbs_set_model_dev(ure, uim, r, eta)
+            if rep:
+                ctx.gbs_timing()
+                ctx.gbs_set_timing(True)
+                t0 = time.perf_counter()
+            ctx.gbs_prob_approx_dev(pm, lm, st)
+            torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        tim = ctx.gbs_timing()
+        ctx.gbs_set_timing(False)
+        d = np.abs(lm.cpu().numpy() - ref)
+        out["forward_mixed"] = {"ms": ms, "probs_per_s": wl.P / (ms * 1e-3),
+                                "status_nonzero": int((st != 0).sum().item()),
+                                "kernel_ms": {k: round(v[0], 3) for k, v in tim.items() if v[1]},
+                                "abs_dlogp_vs_fp64": {"median": float(np.median(d)),
+                                                      "p99": float(np.quantile(d, 0.99)),
+                                                      "max": float(d.max())}}
+        pm.close()
     return out
 
 
@@ -348,7 +373,7 @@ def main():
     if not args.no_exact:
         out["exact_m20"] = exact_leg(ctx)
     if not args.no_big:
-        out["m100_order3"] = big_leg(ctx, torch, 4, "m100_order3")
+        out["m100_order3"] = big_leg(ctx, torch, 4, "m100_order3", mixed=True)
         out["m144_order2_grad"] = big_leg(ctx, torch, 5, "m144_order2_grad")
     if not args.no_cpu:
         cb, err = cpu_baseline(wl, lp)

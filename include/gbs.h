@@ -58,7 +58,19 @@ enum {
     GBS_W_PATTERN = 1  /* success, but some status[p] != 0                       */
 };
 
-enum { GBS_PREC_FP64 = 0 };
+/*
+ * Precision.  GBS_PREC_FP64: every step in fp64 (double-double where stated).
+ * GBS_PREC_MIXED (approximate path, forward only): the cluster eliminations
+ * run in fp32 on an fp32 copy of M(w); the model, the eigen-decomposition, the
+ * contour plan, M(w) itself, G_0(w), the sums over clusters, the sector
+ * transform and the fits stay fp64.  The sector transform extracts small
+ * moments from contour values whose fp32 rounding is set by the largest ones,
+ * so the error grows with a row's dynamic range: measured median / worst
+ * |log p_mixed - log p_fp64| 3e-6 / 3e-5 (20 modes, order 3), 3e-5 / 4e-4
+ * (70 modes), 1e-4 / 2e-3 (100 modes).  The exact path, the plain kernel and
+ * the gradient take GBS_PREC_FP64 only (GBS_E_INVAL otherwise).
+ */
+enum { GBS_PREC_FP64 = 0, GBS_PREC_MIXED = 1 };
 
 /* per-pattern status bits */
 enum {

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(1024) void k_build_items(int P, int nbig, int qchun
 // and segment, so the reads of the triple loop are broadcasts (blocks (b,c),
 // (c,c)) or consecutive across lanes (block (a,c)).
 // ---------------------------------------------------------------------------
-template <int ORDER, bool BIG>
+template <int ORDER, bool BIG, class C>
 __global__ __launch_bounds__(CONT_THREADS) void k_contour(
     int lds_bytes, int qchunk, int gmax, const int *__restrict__ offsets,
     const long long *__restrict__ voff,
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
         const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
         const RowPlan rp = rows[p];
         const long long vo = voff[p];
-        const int mstride = 2 * n * n + 5 * n;
+        const int mstride = cont_mbytes<C>(n) / 16;  // one slot, in complex fp64 units
         const double *Vt;                       // N*N, eigenvector k contiguous
         double *al;                             // N
         cplx *slots;                            // G x (2n^2 + 5n) complex
@@ -137,14 +137,14 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
             // this workgroup's HBM scratch
             Vt = vt + vo;
             al = dyn;
-            slots = cont_fixed() + 8 * N + cont_mbytes(n) <= lds_bytes ? (cplx *)(al + N)
+            slots = cont_fixed() + 8 * N + cont_mbytes<C>(n) <= lds_bytes ? (cplx *)(al + N)
                                                                       : mscr + blockIdx.x * mscr_stride;
         } else {
             double *vl = dyn;
             al = vl + N * N;
             slots = (cplx *)(al + N);
             G = gmax;
-            while (G > 1 && cont_fixed() + cont_vbytes(n) + G * cont_mbytes(n) > lds_bytes) G >>= 1;
+            while (G > 1 && cont_fixed() + cont_vbytes(n) + G * cont_mbytes<C>(n) > lds_bytes) G >>= 1;
             for (int idx = tid; idx < N * N; idx += CONT_THREADS) vl[idx] = vt[vo + idx];
             Vt = vl;
         }
@@ -171,14 +171,14 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                 const double am1 = al[k] - 1.0;
                 const cplx z = cmk(fma(w.re, am1, 1.0), w.im * am1);
                 const cplx rz = crsqrt_p(z);
-                const SlotM m = slot_view(slots + sl * mstride, n);
+                const SlotMT<C> m = slot_view<C>(slots + sl * mstride, n);
                 m.d[k] = cmul(rz, rz);
                 m.rz[k] = rz;
             }
             __syncthreads();
             if (tid < g) {
                 // G_0(w)/G_0(rho) = exp(log det A/2 - log G_0(rho)) prod_k z_k^{-1/2}
-                const SlotM m = slot_view(slots + tid * mstride, n);
+                const SlotMT<C> m = slot_view<C>(slots + tid * mstride, n);
                 cplx pr = cmk(exp(0.5 * rp.logdet_a - rp.log_g_rho), 0.0);
                 for (int k = 0; k < N; ++k) pr = cmul(pr, m.rz[k]);
                 ghat[tid] = pr;
@@ -192,13 +192,13 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                     const int sl = c / ntile;
                     int it, jt;
                     upper_tile(c - sl * ntile, it, jt);
-                    const SlotM m = slot_view(slots + sl * mstride, n);
+                    const SlotMT<C> m = slot_view<C>(slots + sl * mstride, n);
                     m_tile_mfma(n, it, jt, Vt, N, m.d, m.d0, lane);
                 }
             } else {
                 for (int idx = tid; idx < g * n; idx += CONT_THREADS) {
                     const int sl = idx / n, a = idx - sl * n;
-                    const SlotM m = slot_view(slots + sl * mstride, n);
+                    const SlotMT<C> m = slot_view<C>(slots + sl * mstride, n);
                     cplx m00 = cmk(0, 0), m01 = cmk(0, 0), m11 = cmk(0, 0);
 #pragma unroll 1
                     for (int k = 0; k < N; ++k) {
@@ -209,7 +209,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                         m01.re = fma(p01, d.re, m01.re); m01.im = fma(p01, d.im, m01.im);
                         m11.re = fma(p11, d.re, m11.re); m11.im = fma(p11, d.im, m11.im);
                     }
-                    m.d0[a] = m00; m.d1[a] = m01; m.d2[a] = m11;
+                    m.d0[a] = from_d<C>(m00);
+                    m.d1[a] = from_d<C>(m01);
+                    m.d2[a] = from_d<C>(m11);
                 }
             }
             __syncthreads();
@@ -218,10 +220,10 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
             const int sl = tid / SG, lt = tid - sl * SG;
             cplx s1 = cmk(0, 0), s2 = cmk(0, 0), s3 = cmk(0, 0);
             if (sl < g) {
-                const SlotM m = slot_view(slots + sl * mstride, n);
+                const SlotMT<C> m = slot_view<C>(slots + sl * mstride, n);
                 for (int a = lt; a < n; a += SG) {
-                    const cplx a00 = m.d0[a], a01 = m.d1[a], a11 = m.d2[a];
-                    s1 = cadd(s1, crsqrt_p(cfnma(a01, a01, cmul(a00, a11))));
+                    const C a00 = m.d0[a], a01 = m.d1[a], a11 = m.d2[a];
+                    s1 = cadd(s1, to_d(crsqrt_p(cfnma(a01, a01, cmul(a00, a11)))));
                 }
                 if (ORDER >= 2) {
                     const int *un = units + unit_off[2 * n];
@@ -233,32 +235,30 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                         if (ui + SG < nu) unext = un[ui + SG];
                         const int a = u & 255, b = (u >> 8) & 255, c0 = (u >> 16) & 255, c1 = u >> 24;
                         const int pi = b * (b - 1) / 2 + a;
-                        const cplx a00 = m.d0[a], a01 = m.d1[a], a11 = m.d2[a];
-                        const cplx b00 = m.o0[pi], b01 = m.o1[pi], b10 = m.o2[pi], b11 = m.o3[pi];
-                        const cplx bb00 = m.d0[b], bb01 = m.d1[b], bb11 = m.d2[b];
-                        const cplx deta = cfnma(a01, a01, cmul(a00, a11));
-                        const cplx ra = crsqrt_p(deta);
-                        const cplx ideta = cmul(ra, ra);
-                        const cplx ia00 = cmul(a11, ideta), ia11 = cmul(a00, ideta);
-                        const cplx ia01 = cmk(-(a01.re * ideta.re - a01.im * ideta.im),
-                                              -(a01.re * ideta.im + a01.im * ideta.re));
+                        const C a00 = m.d0[a], a01 = m.d1[a], a11 = m.d2[a];
+                        const C b00 = m.o0[pi], b01 = m.o1[pi], b10 = m.o2[pi], b11 = m.o3[pi];
+                        const C bb00 = m.d0[b], bb01 = m.d1[b], bb11 = m.d2[b];
+                        const C deta = cfnma(a01, a01, cmul(a00, a11));
+                        const C ra = crsqrt_p(deta);
+                        const C ideta = cmul(ra, ra);
+                        const C ia00 = cmul(a11, ideta), ia11 = cmul(a00, ideta);
+                        const C ia01 = cneg(cmul(a01, ideta));
                         // G = Maa^{-1} Mab ; Sb = Mbb - Mab^T G
-                        const cplx G00 = cfma(ia00, b00, cmul(ia01, b10));
-                        const cplx G01 = cfma(ia00, b01, cmul(ia01, b11));
-                        const cplx G10 = cfma(ia01, b00, cmul(ia11, b10));
-                        const cplx G11 = cfma(ia01, b01, cmul(ia11, b11));
-                        const cplx sb00 = csub(bb00, cfma(b00, G00, cmul(b10, G10)));
-                        const cplx sb01 = csub(bb01, cfma(b00, G01, cmul(b10, G11)));
-                        const cplx sb11 = csub(bb11, cfma(b01, G01, cmul(b11, G11)));
-                        const cplx detb = cfnma(sb01, sb01, cmul(sb00, sb11));
-                        const cplx rb = crsqrt_p(detb);
-                        const cplx rab = cmul(ra, rb);
-                        if (c0 == b + 1) s2 = cadd(s2, rab);
+                        const C G00 = cfma(ia00, b00, cmul(ia01, b10));
+                        const C G01 = cfma(ia00, b01, cmul(ia01, b11));
+                        const C G10 = cfma(ia01, b00, cmul(ia11, b10));
+                        const C G11 = cfma(ia01, b01, cmul(ia11, b11));
+                        const C sb00 = csub(bb00, cfma(b00, G00, cmul(b10, G10)));
+                        const C sb01 = csub(bb01, cfma(b00, G01, cmul(b10, G11)));
+                        const C sb11 = csub(bb11, cfma(b01, G01, cmul(b11, G11)));
+                        const C detb = cfnma(sb01, sb01, cmul(sb00, sb11));
+                        const C rb = crsqrt_p(detb);
+                        const C rab = cmul(ra, rb);
+                        if (c0 == b + 1) s2 = cadd(s2, to_d(rab));
                         if (ORDER >= 3) {
-                            const cplx idetb = cmul(rb, rb);
-                            const cplx ib00 = cmul(sb11, idetb), ib11 = cmul(sb00, idetb);
-                            const cplx ib01 = cmk(-(sb01.re * idetb.re - sb01.im * idetb.im),
-                                                  -(sb01.re * idetb.im + sb01.im * idetb.re));
+                            const C idetb = cmul(rb, rb);
+                            const C ib00 = cmul(sb11, idetb), ib11 = cmul(sb00, idetb);
+                            const C ib01 = cneg(cmul(sb01, idetb));
                             cplx s3p = cmk(0, 0);
 #pragma unroll 1
                             for (int c = c0; c < c1; ++c) {
@@ -266,33 +266,33 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                                 const int iac = cb + a, ibc = cb + b;
                                 // Sc = Mcc - Xa^T Maa^{-1} Xa - Y^T Sb^{-1} Y, Y = Xb - G^T Xa,
                                 // evaluated so that each intermediate dies early
-                                const cplx x00 = m.o0[iac], x01 = m.o1[iac], x10 = m.o2[iac], x11 = m.o3[iac];
-                                cplx sc00 = m.d0[c], sc01 = m.d1[c], sc11 = m.d2[c];
+                                const C x00 = m.o0[iac], x01 = m.o1[iac], x10 = m.o2[iac], x11 = m.o3[iac];
+                                C sc00 = m.d0[c], sc01 = m.d1[c], sc11 = m.d2[c];
                                 {
-                                    const cplx Z00 = cfma(ia00, x00, cmul(ia01, x10));
-                                    const cplx Z10 = cfma(ia01, x00, cmul(ia11, x10));
+                                    const C Z00 = cfma(ia00, x00, cmul(ia01, x10));
+                                    const C Z10 = cfma(ia01, x00, cmul(ia11, x10));
                                     sc00 = csub(sc00, cfma(x00, Z00, cmul(x10, Z10)));
-                                    const cplx Z01 = cfma(ia00, x01, cmul(ia01, x11));
-                                    const cplx Z11 = cfma(ia01, x01, cmul(ia11, x11));
+                                    const C Z01 = cfma(ia00, x01, cmul(ia01, x11));
+                                    const C Z11 = cfma(ia01, x01, cmul(ia11, x11));
                                     sc01 = csub(sc01, cfma(x00, Z01, cmul(x10, Z11)));
                                     sc11 = csub(sc11, cfma(x01, Z01, cmul(x11, Z11)));
                                 }
-                                const cplx Y00 = csub(m.o0[ibc], cfma(G00, x00, cmul(G10, x10)));
-                                const cplx Y01 = csub(m.o1[ibc], cfma(G00, x01, cmul(G10, x11)));
-                                const cplx Y10 = csub(m.o2[ibc], cfma(G01, x00, cmul(G11, x10)));
-                                const cplx Y11 = csub(m.o3[ibc], cfma(G01, x01, cmul(G11, x11)));
+                                const C Y00 = csub(m.o0[ibc], cfma(G00, x00, cmul(G10, x10)));
+                                const C Y01 = csub(m.o1[ibc], cfma(G00, x01, cmul(G10, x11)));
+                                const C Y10 = csub(m.o2[ibc], cfma(G01, x00, cmul(G11, x10)));
+                                const C Y11 = csub(m.o3[ibc], cfma(G01, x01, cmul(G11, x11)));
                                 {
-                                    const cplx W00 = cfma(ib00, Y00, cmul(ib01, Y10));
-                                    const cplx W10 = cfma(ib01, Y00, cmul(ib11, Y10));
+                                    const C W00 = cfma(ib00, Y00, cmul(ib01, Y10));
+                                    const C W10 = cfma(ib01, Y00, cmul(ib11, Y10));
                                     sc00 = csub(sc00, cfma(Y00, W00, cmul(Y10, W10)));
-                                    const cplx W01 = cfma(ib00, Y01, cmul(ib01, Y11));
-                                    const cplx W11 = cfma(ib01, Y01, cmul(ib11, Y11));
+                                    const C W01 = cfma(ib00, Y01, cmul(ib01, Y11));
+                                    const C W11 = cfma(ib01, Y01, cmul(ib11, Y11));
                                     sc01 = csub(sc01, cfma(Y00, W01, cmul(Y10, W11)));
                                     sc11 = csub(sc11, cfma(Y01, W01, cmul(Y11, W11)));
                                 }
-                                s3p = cadd(s3p, crsqrt_p(cfnma(sc01, sc01, cmul(sc00, sc11))));
+                                s3p = cadd(s3p, to_d(crsqrt_p(cfnma(sc01, sc01, cmul(sc00, sc11)))));
                             }
-                            s3 = cfma(rab, s3p, s3);
+                            s3 = cfma(to_d(rab), s3p, s3);
                         }
                     }
                 }
@@ -436,25 +436,25 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
     }
 }
 
-template <int ORDER, bool BIG>
+template <int ORDER, bool BIG, class C>
 int launch_contour(gbs_ctx *ctx, gbs_plan *pl, int nmax)
 {
     hipStream_t st = ctx->stream;
-    const void *fn = (const void *)k_contour<ORDER, BIG>;
+    const void *fn = (const void *)k_contour<ORDER, BIG, C>;
     int lds_static = 0;
     if (int rc = func_static_lds(ctx, fn, &lds_static)) return rc;
     const int lds_cap = ctx->lds_per_block - lds_static;
     int lds_c;
     if (BIG) {
         // the largest row's M(w) in LDS if it fits, else only alpha (M in HBM)
-        lds_c = cont_fixed() + 8 * 2 * nmax + cont_mbytes(nmax);
+        lds_c = cont_fixed() + 8 * 2 * nmax + cont_mbytes<C>(nmax);
         if (lds_c > lds_cap) lds_c = cont_fixed() + 8 * 2 * nmax;
     } else {
         // the whole 160 KB when the largest row needs it, else enough for eight
         // contour points of the largest row (two workgroups may then share a CU)
-        lds_c = cont_fixed() + cont_vbytes(nmax) + pl->gmax * cont_mbytes(nmax);
+        lds_c = cont_fixed() + cont_vbytes(nmax) + pl->gmax * cont_mbytes<C>(nmax);
         if (lds_c > lds_cap) lds_c = lds_cap;
-        if (cont_fixed() + cont_vbytes(nmax) + cont_mbytes(nmax) > lds_c)
+        if (cont_fixed() + cont_vbytes(nmax) + cont_mbytes<C>(nmax) > lds_c)
             return set_err(ctx, GBS_E_INVAL, "row too large for the contour kernel's LDS");
     }
     int occ = 1;
@@ -464,7 +464,7 @@ int launch_contour(gbs_ctx *ctx, gbs_plan *pl, int nmax)
     cplx *mscr = nullptr;
     long long mstride = 0;
     if (BIG) {
-        mstride = 2LL * nmax * nmax + 5LL * nmax;
+        mstride = cont_mbytes<C>(nmax) / 16;
         if (pl->d_mscr) {
             if (grid > pl->mscr_blocks) grid = pl->mscr_blocks;
             mscr = pl->d_mscr;
@@ -472,7 +472,7 @@ int launch_contour(gbs_ctx *ctx, gbs_plan *pl, int nmax)
     }
     const int *q_end = pl->d_counter + (BIG ? 4 : 0);
     int *q_head = pl->d_counter + (BIG ? 5 : 1);
-    hipLaunchKernelGGL((k_contour<ORDER, BIG>), dim3(grid), dim3(CONT_THREADS), lds_c, st, lds_c,
+    hipLaunchKernelGGL((k_contour<ORDER, BIG, C>), dim3(grid), dim3(CONT_THREADS), lds_c, st, lds_c,
                        pl->qchunk, pl->gmax, pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_items,
                        q_end, q_head, pl->d_cluster_items, pl->d_cluster_off, mscr, mstride, pl->d_sw);
     return 0;
@@ -494,8 +494,14 @@ int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
                        pl->d_rows, pl->d_items, pl->d_counter);
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_CONTOUR);
-    if (nbig > 0 && (rc = launch_contour<ORDER, true>(ctx, pl, pl->max_n))) return rc;
-    if (nbig < P && (rc = launch_contour<ORDER, false>(ctx, pl, nsmall_max))) return rc;
+    if (pl->prec == GBS_PREC_MIXED) {
+        // cluster eliminations in fp32 (M(w) stored in fp32), sums in fp64
+        if (nbig > 0 && (rc = launch_contour<ORDER, true, cplxf>(ctx, pl, pl->max_n))) return rc;
+        if (nbig < P && (rc = launch_contour<ORDER, false, cplxf>(ctx, pl, nsmall_max))) return rc;
+    } else {
+        if (nbig > 0 && (rc = launch_contour<ORDER, true, cplx>(ctx, pl, pl->max_n))) return rc;
+        if (nbig < P && (rc = launch_contour<ORDER, false, cplx>(ctx, pl, nsmall_max))) return rc;
+    }
     timer_end(ctx, ts);
     size_t lds_f = sizeof(cplx) * (GBS_KMAX + GBS_KMAX / 2);
     if ((rc = func_lds_limit(ctx, (const void *)k_dft_fit<ORDER>, (int)lds_f))) return rc;

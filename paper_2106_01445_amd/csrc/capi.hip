@@ -429,7 +429,8 @@ int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
     *out = nullptr;
     if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
     if (order < 1 || order > 3) return set_err(ctx, GBS_E_INVAL, "order must be 1, 2 or 3");
-    if (prec != GBS_PREC_FP64) return set_err(ctx, GBS_E_INVAL, "prec must be GBS_PREC_FP64");
+    if (prec != GBS_PREC_FP64 && prec != GBS_PREC_MIXED)
+        return set_err(ctx, GBS_E_INVAL, "prec must be GBS_PREC_FP64 or GBS_PREC_MIXED");
     int rc = check_csr(ctx, P, offsets, modes, ctx->model.M,
                        order == 3 ? GBS_MAX_N_ORDER3 : GBS_MAX_N_APPROX);
     if (rc) return rc;
@@ -578,6 +579,8 @@ int gbs_prob_approx_plain(gbs_ctx *ctx, int P, const int32_t *offsets, const int
     if (rc) return rc;
     rc = pl->max_n > GBS_NSMALL
              ? set_err(ctx, GBS_E_INVAL, "the plain kernel takes rows of at most 40 clicks")
+         : prec != GBS_PREC_FP64
+             ? set_err(ctx, GBS_E_INVAL, "the plain kernel runs in fp64 only")
              : approx_forward_plain(ctx, pl, pl->d_logp, pl->d_status);
     if (rc == 0 && P > 0) {
         hipError_t e = hipMemcpyAsync(logp, pl->d_logp, P * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
@@ -777,6 +780,7 @@ int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, double *logp_
     if (!ctx->model.have || !ctx->model.from_params)
         return set_err(ctx, GBS_E_STATE, "gradient needs a model set by gbs_set_model");
     if (!dl_dev || !grad_r_dev || !grad_eta_dev) return set_err(ctx, GBS_E_INVAL, "NULL device array");
+    if (pl->prec != GBS_PREC_FP64) return set_err(ctx, GBS_E_INVAL, "the gradient runs in fp64 only");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     double *lp = logp_dev ? logp_dev : pl->d_logp;
     int32_t *stt = status_dev ? status_dev : pl->d_status;
@@ -792,6 +796,7 @@ int gbs_grad(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, 
     if (!ctx) return GBS_E_INVAL;
     if (!dL_dlogp || !grad_r || !grad_eta || (P > 0 && !status))
         return set_err(ctx, GBS_E_INVAL, "NULL array");
+    if (prec != GBS_PREC_FP64) return set_err(ctx, GBS_E_INVAL, "the gradient runs in fp64 only");
     if (!ctx->model.have || !ctx->model.from_params)
         return set_err(ctx, GBS_E_STATE, "gradient needs a model set by gbs_set_model");
     gbs_plan *pl = nullptr;

@@ -67,11 +67,32 @@ __device__ __forceinline__ cplx crsqrt_p(cplx z)
     return cmk(sr * q, -si * q);
 }
 
+// the same in fp32
+__device__ __forceinline__ cplxf crsqrt_p(cplxf z)
+{
+    const float s2 = fmaf(z.re, z.re, z.im * z.im);
+    const float q = rsqrtf(s2);
+    const float r = s2 * q;
+    const float A = 0.5f * (fabsf(z.re) + r);
+    const float w = rsqrtf(A);
+    const float big = A * w, small = 0.5f * fabsf(z.im) * w;
+    float sr, si;
+    if (z.re >= 0.0f) { sr = big; si = copysignf(small, z.im); }
+    else { sr = small; si = copysignf(big, z.im); }
+    return cmkf(sr * q, -si * q);
+}
+
 constexpr int CONT_MAXG = 8;
 
 __host__ __device__ __forceinline__ int cont_vbytes(int n) { return 8 * (4 * n * n + 2 * n); }
 // per slot: d, z^{-1/2} (2n each), diagonal blocks (3n), off-diagonal (4 n(n-1)/2)
-__host__ __device__ __forceinline__ int cont_mbytes(int n) { return 16 * (2 * n * n + 5 * n); }
+// bytes of one slot: d and z^{-1/2} (fp64 complex, 2n each) and the 2x2 mode
+// blocks of M(w) (3n + 4 n(n-1)/2 entries of the block type C), 16-byte aligned
+template <class C = cplx>
+__host__ __device__ __forceinline__ int cont_mbytes(int n)
+{
+    return 16 * 4 * n + (((int)sizeof(C) * (2 * n * n + n) + 15) & ~15);
+}
 __host__ __device__ __forceinline__ int cont_fixed() { return 16 * (CONT_THREADS / 64) * 4 + 16 * CONT_MAXG; }
 
 // Contour plan of one row from the spectrum alpha of A (entry i at
@@ -143,8 +164,9 @@ __device__ __forceinline__ dbl4 mfma4(double a, double b, dbl4 c)
 // Every entry i <= j of the upper triangle is one entry of the 2x2 mode-block
 // layout at blk: diagonal blocks (x_a x_a, x_a p_a, p_a p_a) at a, n + a, 2n + a,
 // pair blocks a < b (x_a x_b, x_a p_b, p_a x_b, p_a p_b) at 3n + t np + b(b-1)/2 + a.
+template <class C = cplx>
 __device__ __forceinline__ void m_tile_mfma(int n, int it, int jt, const double *Vt, int vs,
-                                            const cplx *d, cplx *blk, int lane)
+                                            const cplx *d, C *blk, int lane)
 {
     const int N = 2 * n, np = n * (n - 1) / 2, KS = (N + 3) >> 2;
     const int l16 = lane & 15, lq = lane >> 4;
@@ -176,7 +198,7 @@ __device__ __forceinline__ void m_tile_mfma(int n, int it, int jt, const double 
             const int a = ii - n, b = j - n;
             off = a == b ? 2 * n + a : 3 * n + 3 * np + b * (b - 1) / 2 + a;
         }
-        blk[off] = cmk(mre[e], mim[e]);
+        blk[off] = from_d<C>(cmk(mre[e], mim[e]));
     }
 }
 
@@ -188,17 +210,21 @@ __device__ __forceinline__ void upper_tile(int u, int &it, int &jt)
     it = u - jt * (jt + 1) / 2;
 }
 
-struct SlotM {
-    cplx *d, *rz, *d0, *d1, *d2, *o0, *o1, *o2, *o3;
+template <class C>
+struct SlotMT {
+    cplx *d, *rz;
+    C *d0, *d1, *d2, *o0, *o1, *o2, *o3;
 };
+using SlotM = SlotMT<cplx>;
 
-__device__ __forceinline__ SlotM slot_view(cplx *base, int n)
+template <class C = cplx>
+__device__ __forceinline__ SlotMT<C> slot_view(cplx *base, int n)
 {
     const int N = 2 * n, np = n * (n - 1) / 2;
-    SlotM m;
+    SlotMT<C> m;
     m.d = base;
     m.rz = base + N;
-    m.d0 = base + 2 * N;
+    m.d0 = (C *)(base + 2 * N);
     m.d1 = m.d0 + n;
     m.d2 = m.d1 + n;
     m.o0 = m.d2 + n;

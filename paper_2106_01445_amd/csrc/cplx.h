@@ -44,3 +44,30 @@ __device__ __forceinline__ cplx cexp_(cplx z)
     sincos(z.im, &s, &c);
     return cplx{e * c, e * s};
 }
+
+// fp32 complex, for the cluster eliminations of the mixed-precision tier
+struct cplxf {
+    float re, im;
+};
+__device__ __forceinline__ cplxf cmkf(float r, float i) { return cplxf{r, i}; }
+__device__ __forceinline__ cplxf cadd(cplxf a, cplxf b) { return cplxf{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cplxf csub(cplxf a, cplxf b) { return cplxf{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cplxf cmul(cplxf a, cplxf b)
+{
+    return cplxf{fmaf(a.re, b.re, -a.im * b.im), fmaf(a.re, b.im, a.im * b.re)};
+}
+__device__ __forceinline__ cplxf cfma(cplxf a, cplxf b, cplxf c)
+{
+    return cplxf{fmaf(a.re, b.re, fmaf(-a.im, b.im, c.re)), fmaf(a.re, b.im, fmaf(a.im, b.re, c.im))};
+}
+__device__ __forceinline__ cplxf cfnma(cplxf a, cplxf b, cplxf c)
+{
+    return cplxf{fmaf(-a.re, b.re, fmaf(a.im, b.im, c.re)), fmaf(-a.re, b.im, fmaf(-a.im, b.re, c.im))};
+}
+__device__ __forceinline__ cplx to_d(cplx a) { return a; }
+__device__ __forceinline__ cplx to_d(cplxf a) { return cplx{(double)a.re, (double)a.im}; }
+template <class C> __device__ __forceinline__ C from_d(cplx a);
+template <> __device__ __forceinline__ cplx from_d<cplx>(cplx a) { return a; }
+template <> __device__ __forceinline__ cplxf from_d<cplxf>(cplx a) { return cplxf{(float)a.re, (float)a.im}; }
+__device__ __forceinline__ cplx cneg(cplx a) { return cplx{-a.re, -a.im}; }
+__device__ __forceinline__ cplxf cneg(cplxf a) { return cplxf{-a.re, -a.im}; }

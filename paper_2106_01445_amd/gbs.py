@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgbs.so")
 
 GBS_OK, GBS_E_INVAL, GBS_E_NOTPD, GBS_E_NOMEM, GBS_E_HIP, GBS_E_STATE, GBS_W_PATTERN = 0, -1, -2, -3, -4, -5, 1
-GBS_PREC_FP64 = 0
+GBS_PREC_FP64, GBS_PREC_MIXED = 0, 1
 GBS_PS_FIT_NOCONV, GBS_PS_CONTOUR, GBS_PS_PIVOT, GBS_PS_CANCEL = 1, 2, 4, 16
 
 EXPORTS = ["gbs_create", "gbs_destroy", "gbs_last_error", "gbs_set_model", "gbs_set_model_dev",

@@ -185,3 +185,33 @@ def test_plan_params_and_tuner(gpu_ctx):
     torch.cuda.synchronize()
     assert np.max(np.abs(out.cpu().numpy() - ref)) < 1e-12
     plan.close()
+
+
+@pytest.mark.parametrize("cfg,order,P", [(2, 3, None), (3, 3, 1000), (4, 3, 300), (5, 2, 100)])
+def test_mixed_precision(gpu_ctx, cfg, order, P):
+    """GBS_PREC_MIXED (fp32 cluster eliminations, fp64 everything else) against
+    the fp64 path on the same batch, every row status 0.  The sector transform
+    extracts small moments from contour values whose fp32 rounding is set by
+    the largest ones, so the error grows with the dynamic range of the row:
+    measured median / worst |d log p| 3e-6 / 3e-5 at 20 modes, 3e-5 / 4e-4 at
+    70, 1e-4 / 2e-3 at 100.  Bounds: worst 5e-3, median 3e-4."""
+    import paper_2106_01445_amd as g
+    wl = make_workload(cfg, P=P)
+    gpu_ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    a = gpu_ctx.gbs_prob_approx(wl.offsets, wl.modes, order)
+    b = gpu_ctx.gbs_prob_approx(wl.offsets, wl.modes, order, prec=g.GBS_PREC_MIXED)
+    assert np.all(a["status"] == 0) and np.all(b["status"] == 0)
+    d = np.abs(a["logp"] - b["logp"])
+    assert np.max(d) < 5e-3 and np.median(d) < 3e-4, (np.median(d), np.max(d))
+
+
+def test_mixed_precision_rejected_where_unsupported(gpu_ctx):
+    import paper_2106_01445_amd as g
+    wl = make_workload(1)
+    gpu_ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    for call in (lambda: gpu_ctx.gbs_prob_exact(wl.offsets, wl.modes, prec=g.GBS_PREC_MIXED),
+                 lambda: gpu_ctx.gbs_grad(wl.offsets, wl.modes, 2, np.ones(wl.P), prec=g.GBS_PREC_MIXED),
+                 lambda: gpu_ctx.gbs_prob_approx_plain(wl.offsets, wl.modes, 2, prec=g.GBS_PREC_MIXED)):
+        with pytest.raises(g.GBSError) as e:
+            call()
+        assert e.value.code == -1
