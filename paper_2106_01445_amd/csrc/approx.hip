@@ -187,13 +187,15 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
             // 16x16 tiles of the 2n x 2n matrix on the matrix cores (one wavefront
             // per (slot, tile)); at order 1 only the diagonal blocks
             if (ORDER >= 2) {
-                const int T = (N + 15) >> 4, ntile = T * (T + 1) / 2;
+                // BIG: V comes from L2, so 2x2 blocks of tiles share each operand fetch
+                constexpr int BS = BIG ? 2 : 1;
+                const int T = (N + 16 * BS - 1) / (16 * BS), ntile = T * (T + 1) / 2;
                 for (int c = wid; c < g * ntile; c += CONT_THREADS / 64) {
                     const int sl = c / ntile;
                     int it, jt;
                     upper_tile(c - sl * ntile, it, jt);
                     const SlotMT<C> m = slot_view<C>(slots + sl * mstride, n);
-                    m_tile_mfma(n, it, jt, Vt, N, m.d, m.d0, lane);
+                    m_block_mfma<BS>(n, it, jt, Vt, N, m.d, m.d0, lane);
                 }
             } else {
                 for (int idx = tid; idx < g * n; idx += CONT_THREADS) {

@@ -158,35 +158,23 @@ __device__ __forceinline__ dbl4 mfma4(double a, double b, dbl4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// One 16x16 tile (it <= jt) of M(w) = V diag(d) V^T (2n x 2n, quadrature-major
-// rows x_0..x_{n-1}, p_0..p_{n-1}) on the matrix cores, by one wavefront.
-// Vt holds the eigenvectors as rows (entry i of eigenvector k at k*vs + i).
-// Every entry i <= j of the upper triangle is one entry of the 2x2 mode-block
-// layout at blk: diagonal blocks (x_a x_a, x_a p_a, p_a p_a) at a, n + a, 2n + a,
-// pair blocks a < b (x_a x_b, x_a p_b, p_a x_b, p_a p_b) at 3n + t np + b(b-1)/2 + a.
-template <class C = cplx>
-__device__ __forceinline__ void m_tile_mfma(int n, int it, int jt, const double *Vt, int vs,
-                                            const cplx *d, C *blk, int lane)
+// Store one 16x16 tile (it <= jt) of M(w) (2n x 2n, quadrature-major rows
+// x_0..x_{n-1}, p_0..p_{n-1}) from the MFMA layout into the 2x2 mode-block
+// layout at blk: every entry i <= j of the upper triangle is one block entry,
+// diagonal blocks (x_a x_a, x_a p_a, p_a p_a) at a, n + a, 2n + a, pair blocks
+// a < b (x_a x_b, x_a p_b, p_a x_b, p_a p_b) at 3n + t np + b(b-1)/2 + a.
+template <class C>
+__device__ __forceinline__ void m_store(int n, int it, int jt, const dbl4 &mre, const dbl4 &mim,
+                                        C *blk, int lane)
 {
-    const int N = 2 * n, np = n * (n - 1) / 2, KS = (N + 3) >> 2;
+    const int N = 2 * n, np = n * (n - 1) / 2;
     const int l16 = lane & 15, lq = lane >> 4;
-    const int i = it * 16 + l16, j = jt * 16 + l16;
-    const bool iok = i < N, jok = j < N;
-    dbl4 mre = {0.0, 0.0, 0.0, 0.0}, mim = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-    for (int ks = 0; ks < KS; ++ks) {
-        const int k = ks * 4 + lq;
-        const bool kok = k < N, aok = iok && kok, bok = jok && kok;
-        const double val = Vt[aok ? k * vs + i : 0], vbl = Vt[bok ? k * vs + j : 0];
-        const cplx dl = d[kok ? k : 0];
-        const double va = aok ? val : 0.0, vb = bok ? vbl : 0.0;
-        mre = mfma4(va * dl.re, vb, mre);
-        mim = mfma4(va * dl.im, vb, mim);
-    }
+    const int j = jt * 16 + l16;
+    if (j >= N) return;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int ii = it * 16 + 4 * e + lq;
-        if (ii > j || !jok) continue;
+        if (ii > j) continue;
         int off;
         if (j < n) {
             off = ii == j ? ii : 3 * n + j * (j - 1) / 2 + ii;
@@ -200,6 +188,64 @@ __device__ __forceinline__ void m_tile_mfma(int n, int it, int jt, const double 
         }
         blk[off] = from_d<C>(cmk(mre[e], mim[e]));
     }
+}
+
+// A BS x BS block of 16x16 tiles of M(w) = V diag(d) V^T on the matrix cores, by
+// one wavefront: tiles (BS ib + s, BS jb + t), those with it <= jt stored.  Vt
+// holds the eigenvectors as rows (entry i of eigenvector k at k*vs + i).  Each
+// operand fetched per k-step serves BS tiles (BS = 2 halves the loads per MFMA
+// where V is read from L2).
+template <int BS, class C = cplx>
+__device__ __forceinline__ void m_block_mfma(int n, int ib, int jb, const double *Vt, int vs,
+                                             const cplx *d, C *blk, int lane)
+{
+    const int N = 2 * n, KS = (N + 3) >> 2;
+    const int l16 = lane & 15, lq = lane >> 4;
+    int iv[BS], jv[BS];
+#pragma unroll
+    for (int s = 0; s < BS; ++s) {
+        iv[s] = (BS * ib + s) * 16 + l16;
+        jv[s] = (BS * jb + s) * 16 + l16;
+    }
+    dbl4 mre[BS][BS], mim[BS][BS];
+#pragma unroll
+    for (int s = 0; s < BS; ++s)
+#pragma unroll
+        for (int t = 0; t < BS; ++t) mre[s][t] = mim[s][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int ks = 0; ks < KS; ++ks) {
+        const int k = ks * 4 + lq;
+        const bool kok = k < N;
+        const cplx dl = d[kok ? k : 0];
+        double ar[BS], ai[BS], bv[BS];
+#pragma unroll
+        for (int s = 0; s < BS; ++s) {
+            const bool aok = kok && iv[s] < N, bok = kok && jv[s] < N;
+            const double va = Vt[aok ? k * vs + iv[s] : 0], vb = Vt[bok ? k * vs + jv[s] : 0];
+            ar[s] = aok ? va * dl.re : 0.0;
+            ai[s] = aok ? va * dl.im : 0.0;
+            bv[s] = bok ? vb : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < BS; ++s)
+#pragma unroll
+            for (int t = 0; t < BS; ++t) {
+                mre[s][t] = mfma4(ar[s], bv[t], mre[s][t]);
+                mim[s][t] = mfma4(ai[s], bv[t], mim[s][t]);
+            }
+    }
+#pragma unroll
+    for (int s = 0; s < BS; ++s)
+#pragma unroll
+        for (int t = 0; t < BS; ++t)
+            if (BS * ib + s <= BS * jb + t) m_store(n, BS * ib + s, BS * jb + t, mre[s][t], mim[s][t], blk, lane);
+}
+
+template <class C = cplx>
+__device__ __forceinline__ void m_tile_mfma(int n, int it, int jt, const double *Vt, int vs,
+                                            const cplx *d, C *blk, int lane)
+{
+    m_block_mfma<1, C>(n, it, jt, Vt, vs, d, blk, lane);
 }
 
 // tile u of the column-major list of upper tiles (it <= jt)

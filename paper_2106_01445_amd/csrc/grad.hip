@@ -352,10 +352,12 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             }
             // M(w) = V diag(d) V^T on the matrix cores, upper tiles over the waves
             if (ORDER >= 2) {
-                for (int u = wid; u < ntile; u += CONT_THREADS / 64) {
+                constexpr int BS = BIG ? 2 : 1;
+                const int TB = (N + 16 * BS - 1) / (16 * BS), nblk = TB * (TB + 1) / 2;
+                for (int u = wid; u < nblk; u += CONT_THREADS / 64) {
                     int it, jt;
                     upper_tile(u, it, jt);
-                    m_tile_mfma(n, it, jt, Vt, vs, dk, Md0, lane);
+                    m_block_mfma<BS>(n, it, jt, Vt, vs, dk, Md0, lane);
                 }
             } else {
                 for (int a = tid; a < n; a += CONT_THREADS) {
@@ -545,8 +547,113 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             // columns into LDS, then X = V^T Y for the owned tiles (it, jt)
             const cplx beta = s_beta;
             const cplx hw = cscale(w, 0.5);
+            // Z(r, s) for r, s in quadrature-major order (zero outside 2n x 2n)
+            auto zget = [&](int r, int sidx) {
+                const bool ok = r < N && sidx < N;
+                const int a = r < n ? r : r - n, qa = r < n ? 0 : 1;
+                const int b = sidx < n ? sidx : sidx - n, qb = sidx < n ? 0 : 1;
+                const int lo = min(a, b), hi = max(a, b);
+                const int kq = a < b ? 2 * qa + qb : 2 * qb + qa;
+                const cplx *src = a == b ? Zd0 + (qa + qb) * n + a : Zo0 + kq * np + hi * (hi - 1) / 2 + lo;
+                const cplx zl = *(ok ? src : Zd0);
+                return ok ? zl : cmk(0.0, 0.0);
+            };
             for (int jr = 0; jr < T; jr += 2) {
                 const int nj = min(2, T - jr);
+                if (BIG) {
+                    // V comes from L2: 2x2 blocks of tiles share each operand fetch.
+                    // Y for the round's two column tiles, one 32-row block per chain.
+                    const int TB = (T + 1) / 2;
+                    for (int rb = wid; rb < TB; rb += CONT_THREADS / 64) {
+                        dbl4 yre[2][2], yim[2][2];
+#pragma unroll
+                        for (int u = 0; u < 2; ++u)
+#pragma unroll
+                            for (int t = 0; t < 2; ++t) yre[u][t] = yim[u][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+                        const int r0 = (2 * rb) * 16 + l16, r1 = r0 + 16;
+                        const int j0 = jr * 16 + l16, j1 = j0 + 16;
+#pragma unroll 2
+                        for (int ks = 0; ks < KS; ++ks) {
+                            const int sidx = ks * 4 + lq;
+                            const cplx z0 = zget(r0, sidx), z1 = zget(r1, sidx);
+                            const bool v0ok = j0 < N && sidx < N, v1ok = j1 < N && sidx < N;
+                            const double v0l = Vt[v0ok ? j0 * vs + sidx : 0], v1l = Vt[v1ok ? j1 * vs + sidx : 0];
+                            const double v0 = v0ok ? v0l : 0.0, v1 = v1ok ? v1l : 0.0;
+                            yre[0][0] = mfma4(z0.re, v0, yre[0][0]);
+                            yim[0][0] = mfma4(z0.im, v0, yim[0][0]);
+                            yre[0][1] = mfma4(z0.re, v1, yre[0][1]);
+                            yim[0][1] = mfma4(z0.im, v1, yim[0][1]);
+                            yre[1][0] = mfma4(z1.re, v0, yre[1][0]);
+                            yim[1][0] = mfma4(z1.im, v0, yim[1][0]);
+                            yre[1][1] = mfma4(z1.re, v1, yre[1][1]);
+                            yim[1][1] = mfma4(z1.im, v1, yim[1][1]);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 2; ++u)
+#pragma unroll
+                            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) {
+                                    const int row = (2 * rb + u) * 16 + 4 * e + lq;
+                                    if (row < N && t < nj)
+                                        Yp[row * ADJ_PWS + t * 16 + l16] = cmk(yre[u][t][e], yim[u][t][e]);
+                                }
+                    }
+                    __syncthreads();
+                    // X = V^T Y for the upper tiles of the round's column block, by
+                    // 2x2 blocks (ib, jr / 2); R read-modified-written in the item's
+                    // HBM slot (each entry has one writer per round)
+                    for (int ib = wid; ib <= jr / 2; ib += CONT_THREADS / 64) {
+                        dbl4 xre[2][2], xim[2][2];
+#pragma unroll
+                        for (int u = 0; u < 2; ++u)
+#pragma unroll
+                            for (int t = 0; t < 2; ++t) xre[u][t] = xim[u][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+                        const int i0 = (2 * ib) * 16 + l16, i1 = i0 + 16;
+#pragma unroll 2
+                        for (int ks = 0; ks < KS; ++ks) {
+                            const int sidx = ks * 4 + lq;
+                            const bool sok = sidx < N, a0ok = sok && i0 < N, a1ok = sok && i1 < N;
+                            const double a0l = Vt[a0ok ? i0 * vs + sidx : 0], a1l = Vt[a1ok ? i1 * vs + sidx : 0];
+                            const double a0 = a0ok ? a0l : 0.0, a1 = a1ok ? a1l : 0.0;
+                            const cplx y0l = Yp[sok ? sidx * ADJ_PWS + l16 : 0];
+                            const cplx y1l = Yp[sok && nj > 1 ? sidx * ADJ_PWS + 16 + l16 : 0];
+                            const cplx y0 = sok ? y0l : cmk(0.0, 0.0);
+                            const cplx y1 = (sok && nj > 1) ? y1l : cmk(0.0, 0.0);
+                            xre[0][0] = mfma4(a0, y0.re, xre[0][0]);
+                            xim[0][0] = mfma4(a0, y0.im, xim[0][0]);
+                            xre[0][1] = mfma4(a0, y1.re, xre[0][1]);
+                            xim[0][1] = mfma4(a0, y1.im, xim[0][1]);
+                            xre[1][0] = mfma4(a1, y0.re, xre[1][0]);
+                            xim[1][0] = mfma4(a1, y0.im, xim[1][0]);
+                            xre[1][1] = mfma4(a1, y1.re, xre[1][1]);
+                            xim[1][1] = mfma4(a1, y1.im, xim[1][1]);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 2; ++u)
+#pragma unroll
+                            for (int t = 0; t < 2; ++t) {
+                                const int jj = (jr + t) * 16 + l16;
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) {
+                                    const int ii = (2 * ib + u) * 16 + 4 * e + lq;
+                                    if (ii <= jj && jj < N) {
+                                        const cplx f = cmul(hw, cmul(dk[ii], dk[jj]));
+                                        double add = f.re * xre[u][t][e] - f.im * xim[u][t][e];
+                                        if (ii == jj) {
+                                            const double dr = 1.0 / (1.0 + rp.rho * (al[ii] - 1.0));
+                                            const cplx tt = cmk(0.5 * rp.rho * dr - hw.re * dk[ii].re + hw.im * dk[ii].im,
+                                                                -(hw.re * dk[ii].im + hw.im * dk[ii].re));
+                                            add += beta.re * tt.re - beta.im * tt.im;
+                                        }
+                                        rscr[ro + (long long)jj * (jj + 1) / 2 + ii] += add;
+                                    }
+                                }
+                            }
+                    }
+                    __syncthreads();
+                    continue;
+                }
                 for (int ch = wid; ch < nj * T; ch += CONT_THREADS / 64) {
                     const int jt = jr + ch / T, rt = ch - (ch / T) * T;
                     const int r = rt * 16 + l16, j = jt * 16 + l16;
@@ -560,16 +667,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                         const int b = sidx < n ? sidx : sidx - n, qb = sidx < n ? 0 : 1;
                         const int lo = min(a, b), hi = max(a, b);
                         const int kq = a < b ? 2 * qa + qb : 2 * qb + qa;
-                        cplx zl;
-                        if (BIG) {
-                            const cplx *src = a == b ? Zd0 + (qa + qb) * n + a
-                                                     : Zo0 + kq * np + hi * (hi - 1) / 2 + lo;
-                            zl = *(ok ? src : Zd0);
-                        } else {
-                            // Zd0..Zd2 (stride n) are followed by Zo0..Zo3 (stride np)
-                            int off = a == b ? (qa + qb) * n + a : 3 * n + kq * np + hi * (hi - 1) / 2 + lo;
-                            zl = Zd0[ok ? off : 0];
-                        }
+                        // Zd0..Zd2 (stride n) are followed by Zo0..Zo3 (stride np)
+                        int off = a == b ? (qa + qb) * n + a : 3 * n + kq * np + hi * (hi - 1) / 2 + lo;
+                        const cplx zl = Zd0[ok ? off : 0];
                         const cplx z = ok ? zl : cmk(0.0, 0.0);
                         const bool vok = jok && sidx < N;
                         const double vl = Vt[vok ? j * vs + sidx : 0];
@@ -618,17 +718,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                         }
                     }
                 };
-                if (BIG) {
-                    // R in the item's HBM scratch, each entry owned by one lane
-                    for (int u = wid; u < ntile; u += CONT_THREADS / 64) {
-                        int it, jt;
-                        upper_tile(u, it, jt);
-                        if (jt < jr || jt >= jr + nj) continue;
-                        x_tile(it, jt, [&](int, int ii, int jj, double add) {
-                            rscr[ro + (long long)jj * (jj + 1) / 2 + ii] += add;
-                        });
-                    }
-                } else {
+                {
 #pragma unroll
                     for (int m = 0; m < 2; ++m) {
                         const int it = tit[m], jt = tjt[m];
