@@ -364,25 +364,31 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
     }
     // tilted sector moments tau_t[kappa] = Re FFT(S_t(w_q))[kappa] / K, where the
     // points q > K/2 are the conjugates of K - q (real coefficients)
-    double tau[FIT_KPT][ORDER + 1];
+    // (loops over t and j unrolled: every index into tau is static)
+    double tau[FIT_KPT][4];
     const double invK = 1.0 / K;
-    for (int t = 0; t <= jp; ++t) {
-        const cplx *src = sw + ((long)p * (ORDER + 1) + t) * GBS_QCAP;
-        for (int q = tid; q < K; q += nt) {
-            const cplx v = q < Q ? src[q] : cmk(src[K - q].re, -src[K - q].im);
-            const int rq = (int)(__brev((unsigned)q) >> (32 - lg));
-            X[rq] = v;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (t <= ORDER && t <= jp) {
+            const cplx *src = sw + ((long)p * (ORDER + 1) + t) * GBS_QCAP;
+            for (int q = tid; q < K; q += nt) {
+                const cplx v = q < Q ? src[q] : cmk(src[K - q].re, -src[K - q].im);
+                const int rq = (int)(__brev((unsigned)q) >> (32 - lg));
+                X[rq] = v;
+            }
+            __syncthreads();
+            fft_lds(X, W, K);
+#pragma unroll
+            for (int j = 0; j < FIT_KPT; ++j) {
+                const int kap = n + tid + nt * j;
+                tau[j][t] = kap < K ? X[kap].re * invK : 0.0;
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int j = 0; j < FIT_KPT; ++j) tau[j][t] = 0.0;
         }
-        __syncthreads();
-        fft_lds(X, W, K);
-        for (int j = 0; j < FIT_KPT; ++j) {
-            const int kap = n + tid + nt * j;
-            tau[j][t] = kap < K ? X[kap].re * invK : 0.0;
-        }
-        __syncthreads();
     }
-    for (int j = 0; j < FIT_KPT; ++j)
-        for (int t = jp + 1; t <= ORDER; ++t) tau[j][t] = 0.0;
     double tmax = 0.0;
     for (int j = 0; j < FIT_KPT; ++j)
         if (n + tid + nt * j < K) tmax = fmax(tmax, tau[j][0]);
@@ -394,6 +400,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
     // Pass 0 fits each thread's first sector; its block log-sum is a lower
     // bound L of the estimate.  Later sectors whose upper bound S_0[kappa]
     // (q <= 1) is below 1e-17 L are skipped: they change the sum by < 1e-14.
+#pragma unroll
     for (int j = 0; j < FIT_KPT; ++j) {
         if (j == 1) {
             double mx = block_max(fm, red);
@@ -406,13 +413,11 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
         if (!(t0 >= thr) || !(t0 > 0.0)) continue;
         const double lw = log(t0) + rp.log_g_rho - kap * rp.log_rho;
         if (lw < lower + log(1e-17)) continue;
-        double lq = 0.0;
-        int jr = 0;
-        const int bad = fit_sector(n, jp, tau[j], &lq, &jr, nullptr, nullptr);
-        if (bad) {
+        const SectorFit f = fit_sector(n, jp, t0, tau[j][1], tau[j][2], tau[j][3]);
+        if (f.bad) {
             lse_add(um, us, lw);
         } else {
-            lse_add(fm, fs, lw + lq);
+            lse_add(fm, fs, lw + f.lq);
             ++nsec;
         }
     }

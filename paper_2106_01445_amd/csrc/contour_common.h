@@ -280,116 +280,158 @@ __device__ __forceinline__ SlotMT<C> slot_view(cplx *base, int n)
     return m;
 }
 
-__device__ __forceinline__ void fit_eval(int n, int jp, const double *ib, const double *c,
-                                         double *lse, double *E, double *E2)
+// Log-partition sum of the exp-polynomial on n' = 1..n (v = n - n' empty modes,
+// basis phi_t = C(v, t) ib[t]) and, with WANT_E, the mean E[phi] and the
+// second moments E2 (upper triangle, row-major) of its JP features.  JP is a
+// template argument so that every array index is static (kept in registers).
+template <int JP, bool WANT_E>
+__device__ __forceinline__ void fit_eval(int n, const double *ib, const double *c, double *lse,
+                                         double *E, double *E2)
 {
     double zmax = -1e300;
     for (int v = 0; v < n; ++v) {
-        double f1 = v * ib[0], f2 = 0.5 * v * (v - 1) * ib[1], f3 = v * (v - 1.0) * (v - 2.0) / 6.0 * ib[2];
-        double z = -(c[0] * f1 + (jp > 1 ? c[1] * f2 : 0.0) + (jp > 2 ? c[2] * f3 : 0.0));
+        const double f[3] = {v * ib[0], 0.5 * v * (v - 1) * ib[1], v * (v - 1.0) * (v - 2.0) / 6.0 * ib[2]};
+        double z = 0.0;
+#pragma unroll
+        for (int t = 0; t < JP; ++t) z -= c[t] * f[t];
         zmax = fmax(zmax, z);
     }
     double s = 0.0, e[3] = {0, 0, 0}, e2[6] = {0, 0, 0, 0, 0, 0};
     for (int v = 0; v < n; ++v) {
-        double f[3] = {v * ib[0], 0.5 * v * (v - 1) * ib[1], v * (v - 1.0) * (v - 2.0) / 6.0 * ib[2]};
-        double z = -(c[0] * f[0] + (jp > 1 ? c[1] * f[1] : 0.0) + (jp > 2 ? c[2] * f[2] : 0.0));
-        double wgt = exp(z - zmax);
+        const double f[3] = {v * ib[0], 0.5 * v * (v - 1) * ib[1], v * (v - 1.0) * (v - 2.0) / 6.0 * ib[2]};
+        double z = 0.0;
+#pragma unroll
+        for (int t = 0; t < JP; ++t) z -= c[t] * f[t];
+        const double wgt = exp(z - zmax);
         s += wgt;
-        if (E) {
-            for (int t = 0; t < jp; ++t) e[t] += wgt * f[t];
+        if (WANT_E) {
+#pragma unroll
+            for (int t = 0; t < JP; ++t) e[t] += wgt * f[t];
             int k = 0;
-            for (int t = 0; t < jp; ++t)
-                for (int u = t; u < jp; ++u) e2[k++] += wgt * f[t] * f[u];
+#pragma unroll
+            for (int t = 0; t < JP; ++t)
+#pragma unroll
+                for (int u = t; u < JP; ++u) e2[k++] += wgt * f[t] * f[u];
         }
     }
     *lse = zmax + log(s);
-    if (E) {
+    if (WANT_E) {
+#pragma unroll
         for (int t = 0; t < 3; ++t) E[t] = e[t] / s;
+#pragma unroll
         for (int k = 0; k < 6; ++k) E2[k] = e2[k] / s;
     }
 }
 
-// Max-entropy fit on n' = 1..n (v = n - n' empty modes) of the jp moments m[];
-// returns 0 and log q(n) on success.
-__device__ __forceinline__ int fit_last_point(int n, int jp, const double *m, double *logq, double *c_out)
+// Cholesky solve of the JP x JP system H x = r (H from E, E2 as the covariance
+// of the features, damped by 1e-14 of its trace); false if H is not positive.
+template <int JP>
+__device__ __forceinline__ bool fit_solve(const double *E, const double *E2, const double *r, double *x)
+{
+    double Hm[3][3];
+    int k = 0;
+#pragma unroll
+    for (int t = 0; t < JP; ++t)
+#pragma unroll
+        for (int u = t; u < JP; ++u) Hm[t][u] = Hm[u][t] = E2[k++] - E[t] * E[u];
+    double tr = 0.0;
+#pragma unroll
+    for (int t = 0; t < JP; ++t) tr += Hm[t][t];
+#pragma unroll
+    for (int t = 0; t < JP; ++t) Hm[t][t] += 1e-14 * tr;
+    if (!(tr > 0.0)) return false;
+    double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int j = 0; j < JP; ++j) {
+        double d = Hm[j][j];
+#pragma unroll
+        for (int l = 0; l < j; ++l) d -= L[j][l] * L[j][l];
+        if (!(d > 0.0)) return false;
+        L[j][j] = sqrt(d);
+#pragma unroll
+        for (int i = j + 1; i < JP; ++i) {
+            double sv = Hm[i][j];
+#pragma unroll
+            for (int l = 0; l < j; ++l) sv -= L[i][l] * L[j][l];
+            L[i][j] = sv / L[j][j];
+        }
+    }
+    double y[3];
+#pragma unroll
+    for (int i = 0; i < JP; ++i) {
+        double sv = r[i];
+#pragma unroll
+        for (int l = 0; l < i; ++l) sv -= L[i][l] * y[l];
+        y[i] = sv / L[i][i];
+    }
+#pragma unroll
+    for (int i = JP - 1; i >= 0; --i) {
+        double sv = y[i];
+#pragma unroll
+        for (int l = i + 1; l < JP; ++l) sv -= L[l][i] * x[l];
+        x[i] = sv / L[i][i];
+    }
+    return true;
+}
+
+// Max-entropy fit on n' = 1..n (v = n - n' empty modes) of the JP moments m[];
+// returns 0 and log q(n) (and the parameters in c_out) on success.
+template <int JP>
+__device__ __forceinline__ int fit_last_point(int n, const double *m, double *logq, double *c_out)
 {
     double ib[3] = {0, 0, 0};
     ib[0] = 1.0 / (n - 1.0);
-    if (jp > 1) ib[1] = 2.0 / ((n - 1.0) * (n - 2.0));
-    if (jp > 2) ib[2] = 6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0));
+    if (JP > 1) ib[1] = 2.0 / ((n - 1.0) * (n - 2.0));
+    if (JP > 2) ib[2] = 6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0));
     double c[3] = {0, 0, 0};
     for (int it = 0; it <= FIT_MAXIT; ++it) {
         double lse, E[3], E2[6];
-        fit_eval(n, jp, ib, c, &lse, E, E2);
-        double g[3] = {0, 0, 0};
+        fit_eval<JP, true>(n, ib, c, &lse, E, E2);
+        double g[3] = {0, 0, 0}, mg[3] = {0, 0, 0};
         bool conv = true;
-        for (int t = 0; t < jp; ++t) {
+#pragma unroll
+        for (int t = 0; t < JP; ++t) {
             g[t] = m[t] - E[t];
+            mg[t] = -g[t];
             if (!(fabs(g[t]) <= 1e-15 + 1e-12 * fabs(m[t]))) conv = false;
         }
-        // Hessian = covariance of phi, damped by 1e-14 of its trace
-        double Hm[3][3];
-        int k = 0;
-        for (int t = 0; t < jp; ++t)
-            for (int u = t; u < jp; ++u) {
-                Hm[t][u] = Hm[u][t] = E2[k++] - E[t] * E[u];
-            }
-        double tr = 0.0;
-        for (int t = 0; t < jp; ++t) tr += Hm[t][t];
-        for (int t = 0; t < jp; ++t) Hm[t][t] += 1e-14 * tr;
-        // Cholesky solve H x = -g
-        double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        bool ok = tr > 0.0;
-        for (int j = 0; j < jp && ok; ++j) {
-            double d = Hm[j][j];
-            for (int l = 0; l < j; ++l) d -= L[j][l] * L[j][l];
-            if (!(d > 0.0)) { ok = false; break; }
-            L[j][j] = sqrt(d);
-            for (int i = j + 1; i < jp; ++i) {
-                double s = Hm[i][j];
-                for (int l = 0; l < j; ++l) s -= L[i][l] * L[j][l];
-                L[i][j] = s / L[j][j];
-            }
-        }
-        if (!ok) return 1;
-        double y[3], x[3];
-        for (int i = 0; i < jp; ++i) {
-            double s = -g[i];
-            for (int l = 0; l < i; ++l) s -= L[i][l] * y[l];
-            y[i] = s / L[i][i];
-        }
-        for (int i = jp - 1; i >= 0; --i) {
-            double s = y[i];
-            for (int l = i + 1; l < jp; ++l) s -= L[l][i] * x[l];
-            x[i] = s / L[i][i];
-        }
+        // Newton step H x = -g, H the covariance of the features
+        double x[3] = {0, 0, 0};
+        if (!fit_solve<JP>(E, E2, mg, x)) return 1;
         if (conv) {
-            double cn[3] = {c[0] + x[0], c[1] + (jp > 1 ? x[1] : 0.0), c[2] + (jp > 2 ? x[2] : 0.0)};
+            double cn[3] = {0, 0, 0};
+#pragma unroll
+            for (int t = 0; t < JP; ++t) cn[t] = c[t] + x[t];
             double l2;
-            fit_eval(n, jp, ib, cn, &l2, nullptr, nullptr);
+            fit_eval<JP, false>(n, ib, cn, &l2, nullptr, nullptr);
             *logq = -l2;
             if (c_out)
+#pragma unroll
                 for (int t = 0; t < 3; ++t) c_out[t] = cn[t];
             return 0;
         }
         double L0 = lse, slope = 0.0;
-        for (int t = 0; t < jp; ++t) {
+#pragma unroll
+        for (int t = 0; t < JP; ++t) {
             L0 += c[t] * m[t];
             slope += g[t] * x[t];
         }
         double st = 1.0;
         if (-slope > 1e-13 * fmax(1.0, fabs(L0))) {
             while (st > 1e-12) {
-                double cn[3] = {c[0] + st * x[0], c[1] + (jp > 1 ? st * x[1] : 0.0),
-                                c[2] + (jp > 2 ? st * x[2] : 0.0)};
+                double cn[3] = {0, 0, 0};
+#pragma unroll
+                for (int t = 0; t < JP; ++t) cn[t] = c[t] + st * x[t];
                 double l2;
-                fit_eval(n, jp, ib, cn, &l2, nullptr, nullptr);
-                for (int t = 0; t < jp; ++t) l2 += cn[t] * m[t];
+                fit_eval<JP, false>(n, ib, cn, &l2, nullptr, nullptr);
+#pragma unroll
+                for (int t = 0; t < JP; ++t) l2 += cn[t] * m[t];
                 if (l2 <= L0 + 1e-4 * st * slope) break;
                 st *= 0.5;
             }
         }
-        for (int t = 0; t < jp; ++t) c[t] += st * x[t];
+#pragma unroll
+        for (int t = 0; t < JP; ++t) c[t] += st * x[t];
     }
     return 1;
 }
@@ -426,45 +468,64 @@ __device__ void fft_lds(cplx *X, const cplx *W, int K)
 }
 
 
-// Fit one sector from its tilted moments tau[0..jp] (tau[0] > 0): the moments
+// Result of one sector fit: log q(n), the fitted parameters and the moments
+// (zero past the ones used), how many moments were used, and bad != 0 if no
+// fit succeeded.
+struct SectorFit {
+    double lq;
+    double c[3];
+    double m[3];
+    int jr, bad;
+};
+
+// Fit one sector from its tilted moments t0..t3 (t0 > 0): the moments
 // m_t = tau_t / (tau_0 C(n-1,t)) are used up to the longest feasible prefix
 // (0 < m_t < 1, decreasing in t, since 0 <= phi_{t+1} <= phi_t <= 1).  A moment
 // whose true value lies below the transform's rounding floor can come out
 // infeasible; it is then dropped, and so is the next one if the fit fails.
-// With m_1 <= 0 every clicked mode fires: q(n) = 1.  Returns 0 on success with
-// log q(n), the number of moments used (*jr_out) and, if c_out, the fitted
-// parameters; m_out receives the moments.
-__device__ __forceinline__ int fit_sector(int n, int jp, const double *tau, double *lq, int *jr_out, double *c_out,
-                          double *m_out)
+// With m_1 <= 0 every clicked mode fires: q(n) = 1.  The moments arrive by
+// value and the fit runs out of line, so that callers index nothing at run time.
+__device__ __noinline__ SectorFit fit_sector(int n, int jp, double t0, double t1, double t2, double t3)
 {
+    SectorFit r;
     const double binv[3] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
                             6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0))};
-    double m[3] = {0, 0, 0};
-    for (int t = 1; t <= jp; ++t) m[t - 1] = tau[t] / tau[0] * binv[t - 1];
-    if (m_out)
-        for (int t = 0; t < 3; ++t) m_out[t] = m[t];
-    int jr = 0;
-    for (int t = 1; t <= jp; ++t) {
-        if (m[t - 1] > 0.0 && m[t - 1] < 1.0 && (t == 1 || m[t - 1] < m[t - 2])) jr = t;
-        else break;
+    const double tau[3] = {t1, t2, t3};
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        r.m[t] = t < jp ? tau[t] / t0 * binv[t] : 0.0;
+        r.c[t] = 0.0;
     }
-    *lq = 0.0;
-    if (c_out) c_out[0] = c_out[1] = c_out[2] = 0.0;
+    int jr = 0;
+#pragma unroll
+    for (int t = 1; t <= 3; ++t)
+        if (jr == t - 1 && t <= jp && r.m[t - 1] > 0.0 && r.m[t - 1] < 1.0 &&
+            (t == 1 || r.m[t - 1] < r.m[t - 2]))
+            jr = t;
+    r.lq = 0.0;
     if (jp == 0) {
-        *jr_out = 0;
-        return 0;
+        r.jr = 0;
+        r.bad = 0;
+        return r;
     }
     int bad = 1;
     while (jr >= 1 && bad) {
-        bad = fit_last_point(n, jr, m, lq, c_out);
+        switch (jr) {
+        case 1: bad = fit_last_point<1>(n, r.m, &r.lq, r.c); break;
+        case 2: bad = fit_last_point<2>(n, r.m, &r.lq, r.c); break;
+        default: bad = fit_last_point<3>(n, r.m, &r.lq, r.c); break;
+        }
         if (bad) --jr;
     }
     if (jr == 0) {
-        bad = m[0] <= 0.0 ? 0 : 1;
-        *lq = 0.0;
+        bad = r.m[0] <= 0.0 ? 0 : 1;
+        r.lq = 0.0;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) r.c[t] = 0.0;
     }
-    *jr_out = jr;
-    return bad;
+    r.jr = jr;
+    r.bad = bad;
+    return r;
 }
 
 }  // namespace

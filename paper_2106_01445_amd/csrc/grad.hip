@@ -65,33 +65,41 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
         sincospi(-2.0 * (double)m / (double)K, &sn, &cs);
         W[m] = cmk(cs, sn);
     }
-    double tau[FIT_KPT][ORDER + 1];
+    // (loops over t and j unrolled: every index into the per-thread arrays is static)
+    double tau[FIT_KPT][4];
     const double invK = 1.0 / K;
-    for (int t = 0; t <= jp; ++t) {
-        const cplx *src = sw + ((long)p * (ORDER + 1) + t) * GBS_QCAP;
-        for (int q = tid; q < K; q += nt) {
-            const cplx v = q < Q ? src[q] : cmk(src[K - q].re, -src[K - q].im);
-            X[(int)(__brev((unsigned)q) >> (32 - lg))] = v;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (t <= ORDER && t <= jp) {
+            const cplx *src = sw + ((long)p * (ORDER + 1) + t) * GBS_QCAP;
+            for (int q = tid; q < K; q += nt) {
+                const cplx v = q < Q ? src[q] : cmk(src[K - q].re, -src[K - q].im);
+                X[(int)(__brev((unsigned)q) >> (32 - lg))] = v;
+            }
+            __syncthreads();
+            fft_lds(X, W, K);
+#pragma unroll
+            for (int j = 0; j < FIT_KPT; ++j) {
+                const int kap = n + tid + nt * j;
+                tau[j][t] = kap < K ? X[kap].re * invK : 0.0;
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int j = 0; j < FIT_KPT; ++j) tau[j][t] = 0.0;
         }
-        __syncthreads();
-        fft_lds(X, W, K);
-        for (int j = 0; j < FIT_KPT; ++j) {
-            const int kap = n + tid + nt * j;
-            tau[j][t] = kap < K ? X[kap].re * invK : 0.0;
-        }
-        __syncthreads();
     }
-    for (int j = 0; j < FIT_KPT; ++j)
-        for (int t = jp + 1; t <= ORDER; ++t) tau[j][t] = 0.0;
     double tmax = 0.0;
+#pragma unroll
     for (int j = 0; j < FIT_KPT; ++j)
         if (n + tid + nt * j < K) tmax = fmax(tmax, tau[j][0]);
     tmax = block_max(tmax, red);
     const double thr = 1e-14 * tmax;
-    // forward pass again: which sectors are fitted, their log p_hat and c
-    double ell[FIT_KPT], cc[FIT_KPT][3];
-    int jrs[FIT_KPT];
+    // forward pass again: which sectors are fitted, their log p_hat and fits
+    double ell[FIT_KPT];
+    SectorFit fits[FIT_KPT];
     double fm = -INFINITY, fs = 0.0, lower = -INFINITY;
+#pragma unroll
     for (int j = 0; j < FIT_KPT; ++j) {
         if (j == 1) {
             double mx = block_max(fm, red);
@@ -99,18 +107,17 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
             lower = sm > 0.0 ? mx + log(sm) : -INFINITY;
         }
         ell[j] = -INFINITY;
-        jrs[j] = -1;
+        fits[j].jr = -1;
         const int kap = n + tid + nt * j;
         if (kap >= K) continue;
         const double t0 = tau[j][0];
         if (!(t0 >= thr) || !(t0 > 0.0)) continue;
         const double lw = log(t0) + rp.log_g_rho - kap * rp.log_rho;
         if (lw < lower + log(1e-17)) continue;
-        double lq = 0.0;
-        int jr = 0;
-        if (fit_sector(n, jp, tau[j], &lq, &jr, cc[j], nullptr)) continue;
-        ell[j] = lw + lq;
-        jrs[j] = jr;
+        const SectorFit f = fit_sector(n, jp, t0, tau[j][1], tau[j][2], tau[j][3]);
+        if (f.bad) continue;
+        fits[j] = f;
+        ell[j] = lw + f.lq;
         lse_add(fm, fs, ell[j]);
     }
     const double fmx = block_max(fm, red);
@@ -119,59 +126,39 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
     // sector cotangents: pi_kappa w_p d ell / d tau_t
     const double binv[3] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
                             6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0))};
-    double tbar[FIT_KPT][ORDER + 1];
+    double tbar[FIT_KPT][4];
+#pragma unroll
     for (int j = 0; j < FIT_KPT; ++j) {
-        for (int t = 0; t <= ORDER; ++t) tbar[j][t] = 0.0;
-        if (jrs[j] < 0 || !(fsum > 0.0)) continue;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) tbar[j][t] = 0.0;
+        const int jr = fits[j].jr;
+        if (jr < 0 || !(fsum > 0.0)) continue;
         const double pi = wp * exp(ell[j] - total);
         const double t0 = tau[j][0];
-        const int jr = jrs[j];
-        double u[3] = {0, 0, 0}, m[3] = {0, 0, 0};
-        for (int t = 1; t <= jr; ++t) m[t - 1] = tau[j][t] / t0 * binv[t - 1];
+        const double *m = fits[j].m;
+        // H = Cov_c[phi] at the fitted c; u = H^{-1} m
+        double u[3] = {0, 0, 0};
         if (jr > 0) {
-            // H = Cov_c[phi] at the fitted c; u = H^{-1} m
             double lse, E[3], E2[6];
-            fit_eval(n, jr, binv, cc[j], &lse, E, E2);
-            double Hm[3][3];
-            int k = 0;
-            for (int t = 0; t < jr; ++t)
-                for (int v = t; v < jr; ++v) Hm[t][v] = Hm[v][t] = E2[k++] - E[t] * E[v];
-            double tr = 0.0;
-            for (int t = 0; t < jr; ++t) tr += Hm[t][t];
-            for (int t = 0; t < jr; ++t) Hm[t][t] += 1e-14 * tr;
-            double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-            bool ok = true;
-            for (int a = 0; a < jr && ok; ++a) {
-                double d = Hm[a][a];
-                for (int l = 0; l < a; ++l) d -= L[a][l] * L[a][l];
-                if (!(d > 0.0)) { ok = false; break; }
-                L[a][a] = sqrt(d);
-                for (int i = a + 1; i < jr; ++i) {
-                    double s = Hm[i][a];
-                    for (int l = 0; l < a; ++l) s -= L[i][l] * L[a][l];
-                    L[i][a] = s / L[a][a];
-                }
+            bool ok = false;
+            switch (jr) {
+            case 1: fit_eval<1, true>(n, binv, fits[j].c, &lse, E, E2); ok = fit_solve<1>(E, E2, m, u); break;
+            case 2: fit_eval<2, true>(n, binv, fits[j].c, &lse, E, E2); ok = fit_solve<2>(E, E2, m, u); break;
+            default: fit_eval<3, true>(n, binv, fits[j].c, &lse, E, E2); ok = fit_solve<3>(E, E2, m, u); break;
             }
-            if (ok) {
-                double y[3];
-                for (int i = 0; i < jr; ++i) {
-                    double s = m[i];
-                    for (int l = 0; l < i; ++l) s -= L[i][l] * y[l];
-                    y[i] = s / L[i][i];
-                }
-                for (int i = jr - 1; i >= 0; --i) {
-                    double s = y[i];
-                    for (int l = i + 1; l < jr; ++l) s -= L[l][i] * u[l];
-                    u[i] = s / L[i][i];
-                }
-            }
+            if (!ok) u[0] = u[1] = u[2] = 0.0;
         }
         double um = 0.0;
-        for (int t = 0; t < jr; ++t) um += u[t] * m[t];
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+            if (t < jr) um += u[t] * m[t];
         tbar[j][0] = pi * (1.0 + um) / t0;
-        for (int t = 1; t <= jr; ++t) tbar[j][t] = -pi * u[t - 1] * binv[t - 1] / t0;
+#pragma unroll
+        for (int t = 1; t <= 3; ++t)
+            if (t <= jr) tbar[j][t] = -pi * u[t - 1] * binv[t - 1] / t0;
     }
     // alpha_t(w_q) = c_q FFT(tbar_t)[q], c_q = 1/K at q = 0, K/2 and 2/K otherwise
+#pragma unroll
     for (int t = 0; t <= ORDER; ++t) {
         cplx *dst = asw + ((long)p * (ORDER + 1) + t) * GBS_QCAP;
         if (t > jp) {
@@ -180,6 +167,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
         }
         for (int k = tid; k < K; k += nt) X[k] = cmk(0.0, 0.0);
         __syncthreads();
+#pragma unroll
         for (int j = 0; j < FIT_KPT; ++j) {
             const int kap = n + tid + nt * j;
             if (kap < K) X[(int)(__brev((unsigned)kap) >> (32 - lg))] = cmk(tbar[j][t], 0.0);
