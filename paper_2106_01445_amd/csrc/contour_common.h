@@ -158,12 +158,24 @@ __device__ __forceinline__ dbl4 mfma4(double a, double b, dbl4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Position of the pair (a, b), a < b, inside one plane of pair blocks.  Column
+// layout (DIAG false): b(b-1)/2 + a, so that pairs sharing b are adjacent.
+// Diagonal layout (DIAG true): the pairs of each distance b - a in turn, so
+// that (a, b), (a+1, b+1), ... are adjacent.
+template <bool DIAG>
+__device__ __forceinline__ int pair_pos(int n, int a, int b)
+{
+    if (!DIAG) return b * (b - 1) / 2 + a;
+    const int d = b - a;
+    return (d - 1) * n - (((d - 1) * d) >> 1) + a;
+}
+
 // Store one 16x16 tile (it <= jt) of M(w) (2n x 2n, quadrature-major rows
 // x_0..x_{n-1}, p_0..p_{n-1}) from the MFMA layout into the 2x2 mode-block
 // layout at blk: every entry i <= j of the upper triangle is one block entry,
 // diagonal blocks (x_a x_a, x_a p_a, p_a p_a) at a, n + a, 2n + a, pair blocks
-// a < b (x_a x_b, x_a p_b, p_a x_b, p_a p_b) at 3n + t np + b(b-1)/2 + a.
-template <class C>
+// a < b (x_a x_b, x_a p_b, p_a x_b, p_a p_b) at 3n + t np + pair_pos(a, b).
+template <class C, bool DIAG = false>
 __device__ __forceinline__ void m_store(int n, int it, int jt, const dbl4 &mre, const dbl4 &mim,
                                         C *blk, int lane)
 {
@@ -177,14 +189,14 @@ __device__ __forceinline__ void m_store(int n, int it, int jt, const dbl4 &mre, 
         if (ii > j) continue;
         int off;
         if (j < n) {
-            off = ii == j ? ii : 3 * n + j * (j - 1) / 2 + ii;
+            off = ii == j ? ii : 3 * n + pair_pos<DIAG>(n, ii, j);
         } else if (ii < n) {
             const int a = ii, b = j - n;
-            off = a == b ? n + a : (a < b ? 3 * n + np + b * (b - 1) / 2 + a
-                                          : 3 * n + 2 * np + a * (a - 1) / 2 + b);
+            off = a == b ? n + a : (a < b ? 3 * n + np + pair_pos<DIAG>(n, a, b)
+                                          : 3 * n + 2 * np + pair_pos<DIAG>(n, b, a));
         } else {
             const int a = ii - n, b = j - n;
-            off = a == b ? 2 * n + a : 3 * n + 3 * np + b * (b - 1) / 2 + a;
+            off = a == b ? 2 * n + a : 3 * n + 3 * np + pair_pos<DIAG>(n, a, b);
         }
         blk[off] = from_d<C>(cmk(mre[e], mim[e]));
     }
@@ -195,7 +207,7 @@ __device__ __forceinline__ void m_store(int n, int it, int jt, const dbl4 &mre, 
 // holds the eigenvectors as rows (entry i of eigenvector k at k*vs + i).  Each
 // operand fetched per k-step serves BS tiles (BS = 2 halves the loads per MFMA
 // where V is read from L2).
-template <int BS, class C = cplx>
+template <int BS, class C = cplx, bool DIAG = false>
 __device__ __forceinline__ void m_block_mfma(int n, int ib, int jb, const double *Vt, int vs,
                                              const cplx *d, C *blk, int lane)
 {
@@ -238,7 +250,8 @@ __device__ __forceinline__ void m_block_mfma(int n, int ib, int jb, const double
     for (int s = 0; s < BS; ++s)
 #pragma unroll
         for (int t = 0; t < BS; ++t)
-            if (BS * ib + s <= BS * jb + t) m_store(n, BS * ib + s, BS * jb + t, mre[s][t], mim[s][t], blk, lane);
+            if (BS * ib + s <= BS * jb + t)
+                m_store<C, DIAG>(n, BS * ib + s, BS * jb + t, mre[s][t], mim[s][t], blk, lane);
 }
 
 template <class C = cplx>

@@ -345,7 +345,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 for (int u = wid; u < nblk; u += CONT_THREADS / 64) {
                     int it, jt;
                     upper_tile(u, it, jt);
-                    m_block_mfma<BS>(n, it, jt, Vt, vs, dk, Md0, lane);
+                    m_block_mfma<BS, cplx, true>(n, it, jt, Vt, vs, dk, Md0, lane);
                 }
             } else {
                 for (int a = tid; a < n; a += CONT_THREADS) {
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                     const unsigned u = (unsigned)unext;
                     if (ui + CONT_THREADS < nu) unext = un[ui + CONT_THREADS];
                     const int a = u & 255, b = (u >> 8) & 255, c0 = (u >> 16) & 255, c1 = u >> 24;
-                    const int pi = b * (b - 1) / 2 + a;
+                    const int pi = pair_pos<true>(n, a, b);
                     const cplx a00 = Md0[a], a01 = Md1[a], a11 = Md2[a];
                     const cplx b00 = Mo0[pi], b01 = Mo1[pi], b10 = Mo2[pi], b11 = Mo3[pi];
                     const cplx deta = cfnma(a01, a01, cmul(a00, a11));
@@ -417,29 +417,48 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                          A11 = cmk(0, 0), A12 = cmk(0, 0), A13 = cmk(0, 0), A22 = cmk(0, 0),
                          A23 = cmk(0, 0), A33 = cmk(0, 0);
                     if (ORDER >= 3) {
+                        // the M entries of the next third mode are read before this
+                        // one's Z updates are issued, so that they do not queue
+                        // behind them
+                        cplx nx00, nx01, nx10, nx11, ny00, ny01, ny10, ny11, nc00, nc01, nc11;
+                        int iac = pair_pos<true>(n, a, c0), ibc = pair_pos<true>(n, b, c0);
+                        if (c0 < c1) {
+                            nx00 = Mo0[iac]; nx01 = Mo1[iac]; nx10 = Mo2[iac]; nx11 = Mo3[iac];
+                            ny00 = Mo0[ibc]; ny01 = Mo1[ibc]; ny10 = Mo2[ibc]; ny11 = Mo3[ibc];
+                            nc00 = Md0[c0]; nc01 = Md1[c0]; nc11 = Md2[c0];
+                        }
 #pragma unroll 1
                         for (int c = c0; c < c1; ++c) {
-                            const int cb = c * (c - 1) / 2;
-                            const int iac = cb + a, ibc = cb + b;
+                            const cplx x00 = nx00, x01 = nx01, x10 = nx10, x11 = nx11;
+                            const cplx yy00 = ny00, yy01 = ny01, yy10 = ny10, yy11 = ny11;
+                            const cplx m00 = nc00, m01 = nc01, m11 = nc11;
+                            const int cur_ac = iac, cur_bc = ibc;
+                            if (c + 1 < c1) {
+                                // pair_pos(a, c + 1) = pair_pos(a, c) + n - (c - a)
+                                iac += n - (c - a);
+                                ibc += n - (c - b);
+                                nx00 = Mo0[iac]; nx01 = Mo1[iac]; nx10 = Mo2[iac]; nx11 = Mo3[iac];
+                                ny00 = Mo0[ibc]; ny01 = Mo1[ibc]; ny10 = Mo2[ibc]; ny11 = Mo3[ibc];
+                                nc00 = Md0[c + 1]; nc01 = Md1[c + 1]; nc11 = Md2[c + 1];
+                            }
                             // Za = Maa^{-1} Xa, Y = Xb - G^T Xa, W = Sb^{-1} Y,
                             // Sc = Mcc - Xa^T Za - Y^T W, U = [Za - G W ; W]
                             cplx Z00, Z01, Z10, Z11, W00, W01, W10, W11, sc00, sc01, sc11;
                             {
-                                const cplx x00 = Mo0[iac], x01 = Mo1[iac], x10 = Mo2[iac], x11 = Mo3[iac];
                                 Z00 = cfma(ia00, x00, cmul(ia01, x10));
                                 Z10 = cfma(ia01, x00, cmul(ia11, x10));
                                 Z01 = cfma(ia00, x01, cmul(ia01, x11));
                                 Z11 = cfma(ia01, x01, cmul(ia11, x11));
-                                sc00 = csub(Md0[c], cfma(x00, Z00, cmul(x10, Z10)));
-                                sc01 = csub(Md1[c], cfma(x00, Z01, cmul(x10, Z11)));
-                                sc11 = csub(Md2[c], cfma(x01, Z01, cmul(x11, Z11)));
-                                const cplx Y00 = csub(Mo0[ibc], cfma(G00, x00, cmul(G10, x10)));
-                                const cplx Y10 = csub(Mo2[ibc], cfma(G01, x00, cmul(G11, x10)));
+                                sc00 = csub(m00, cfma(x00, Z00, cmul(x10, Z10)));
+                                sc01 = csub(m01, cfma(x00, Z01, cmul(x10, Z11)));
+                                sc11 = csub(m11, cfma(x01, Z01, cmul(x11, Z11)));
+                                const cplx Y00 = csub(yy00, cfma(G00, x00, cmul(G10, x10)));
+                                const cplx Y10 = csub(yy10, cfma(G01, x00, cmul(G11, x10)));
                                 W00 = cfma(ib00, Y00, cmul(ib01, Y10));
                                 W10 = cfma(ib01, Y00, cmul(ib11, Y10));
                                 sc00 = csub(sc00, cfma(Y00, W00, cmul(Y10, W10)));
-                                const cplx Y01 = csub(Mo1[ibc], cfma(G00, x01, cmul(G10, x11)));
-                                const cplx Y11 = csub(Mo3[ibc], cfma(G01, x01, cmul(G11, x11)));
+                                const cplx Y01 = csub(yy01, cfma(G00, x01, cmul(G10, x11)));
+                                const cplx Y11 = csub(yy11, cfma(G01, x01, cmul(G11, x11)));
                                 W01 = cfma(ib00, Y01, cmul(ib01, Y11));
                                 W11 = cfma(ib01, Y01, cmul(ib11, Y11));
                                 sc01 = csub(sc01, cfma(Y00, W01, cmul(Y10, W11)));
@@ -468,10 +487,10 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                             const cplx P01 = cfma(U00, is01, cmul(U01, is11));
                             const cplx P10 = cfma(U10, is00, cmul(U11, is01));
                             const cplx P11 = cfma(U10, is01, cmul(U11, is11));
-                            catomic(&Zo0[iac], cscale(P00, -1.0));
-                            catomic(&Zo1[iac], cscale(P01, -1.0));
-                            catomic(&Zo2[iac], cscale(P10, -1.0));
-                            catomic(&Zo3[iac], cscale(P11, -1.0));
+                            catomic(&Zo0[cur_ac], cscale(P00, -1.0));
+                            catomic(&Zo1[cur_ac], cscale(P01, -1.0));
+                            catomic(&Zo2[cur_ac], cscale(P10, -1.0));
+                            catomic(&Zo3[cur_ac], cscale(P11, -1.0));
                             A00 = cfma(P00, U00, cfma(P01, U01, A00));
                             A01 = cfma(P00, U10, cfma(P01, U11, A01));
                             A11 = cfma(P10, U10, cfma(P11, U11, A11));
@@ -484,10 +503,10 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                             const cplx P21 = cfma(W00, is01, cmul(W01, is11));
                             const cplx P30 = cfma(W10, is00, cmul(W11, is01));
                             const cplx P31 = cfma(W10, is01, cmul(W11, is11));
-                            catomic(&Zo0[ibc], cscale(P20, -1.0));
-                            catomic(&Zo1[ibc], cscale(P21, -1.0));
-                            catomic(&Zo2[ibc], cscale(P30, -1.0));
-                            catomic(&Zo3[ibc], cscale(P31, -1.0));
+                            catomic(&Zo0[cur_bc], cscale(P20, -1.0));
+                            catomic(&Zo1[cur_bc], cscale(P21, -1.0));
+                            catomic(&Zo2[cur_bc], cscale(P30, -1.0));
+                            catomic(&Zo3[cur_bc], cscale(P31, -1.0));
                             A22 = cfma(P20, W00, cfma(P21, W01, A22));
                             A23 = cfma(P20, W10, cfma(P21, W11, A23));
                             A33 = cfma(P30, W10, cfma(P31, W11, A33));
@@ -542,7 +561,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 const int b = sidx < n ? sidx : sidx - n, qb = sidx < n ? 0 : 1;
                 const int lo = min(a, b), hi = max(a, b);
                 const int kq = a < b ? 2 * qa + qb : 2 * qb + qa;
-                const cplx *src = a == b ? Zd0 + (qa + qb) * n + a : Zo0 + kq * np + hi * (hi - 1) / 2 + lo;
+                const cplx *src = a == b ? Zd0 + (qa + qb) * n + a : Zo0 + kq * np + pair_pos<true>(n, lo, hi);
                 const cplx zl = *(ok ? src : Zd0);
                 return ok ? zl : cmk(0.0, 0.0);
             };
@@ -656,7 +675,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                         const int lo = min(a, b), hi = max(a, b);
                         const int kq = a < b ? 2 * qa + qb : 2 * qb + qa;
                         // Zd0..Zd2 (stride n) are followed by Zo0..Zo3 (stride np)
-                        int off = a == b ? (qa + qb) * n + a : 3 * n + kq * np + hi * (hi - 1) / 2 + lo;
+                        int off = a == b ? (qa + qb) * n + a : 3 * n + kq * np + pair_pos<true>(n, lo, hi);
                         const cplx zl = Zd0[ok ? off : 0];
                         const cplx z = ok ? zl : cmk(0.0, 0.0);
                         const bool vok = jok && sidx < N;
