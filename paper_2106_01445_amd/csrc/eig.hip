@@ -99,8 +99,10 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(
             dg[N - 2] = W[(long)(N - 2) * N + N - 2];
             ed[N - 2] = W[(long)(N - 2) * N + N - 1];
         }
-        dg[N - 1] = W[(long)(N - 1) * N + N - 1];
-        ed[N - 1] = 0.0;
+        if (N >= 1) {  // (an empty row has nothing to reduce)
+            dg[N - 1] = W[(long)(N - 1) * N + N - 1];
+            ed[N - 1] = 0.0;
+        }
         s_fail = 0;
     }
     // 2. factor: Qf = H_0 H_1 ... H_{N-3}, applied to the identity last first
