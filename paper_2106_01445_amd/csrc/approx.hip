@@ -176,12 +176,14 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                 m.rz[k] = rz;
             }
             __syncthreads();
-            if (tid < g) {
-                // G_0(w)/G_0(rho) = exp(log det A/2 - log G_0(rho)) prod_k z_k^{-1/2}
-                const SlotMT<C> m = slot_view<C>(slots + tid * mstride, n);
-                cplx pr = cmk(exp(0.5 * rp.logdet_a - rp.log_g_rho), 0.0);
-                for (int k = 0; k < N; ++k) pr = cmul(pr, m.rz[k]);
-                ghat[tid] = pr;
+            if (wid < g) {
+                // G_0(w)/G_0(rho) = exp(log det A/2 - log G_0(rho)) prod_k z_k^{-1/2},
+                // slot wid's product over the lanes of wavefront wid
+                const SlotMT<C> m = slot_view<C>(slots + wid * mstride, n);
+                cplx pr = cmk(1.0, 0.0);
+                for (int k = lane; k < N; k += 64) pr = cmul(pr, m.rz[k]);
+                pr = cmul(warp_cprod(pr), cmk(exp(0.5 * rp.logdet_a - rp.log_g_rho), 0.0));
+                if (lane == 0) ghat[wid] = pr;
             }
             // M(w) = V diag(d) V^T: at order >= 2 every 2x2 mode block, as the upper
             // 16x16 tiles of the 2n x 2n matrix on the matrix cores (one wavefront

@@ -50,6 +50,16 @@ __device__ __forceinline__ cplx warp_csum(cplx v)
     return v;
 }
 
+// product over the 64 lanes of a wavefront (butterfly; every lane gets it)
+__device__ __forceinline__ cplx warp_cprod(cplx v)
+{
+    for (int m = 32; m > 0; m >>= 1) {
+        const cplx o = cplx{__shfl_xor(v.re, m), __shfl_xor(v.im, m)};
+        v = cplx{fma(v.re, o.re, -v.im * o.im), fma(v.re, o.im, v.im * o.re)};
+    }
+    return v;
+}
+
 // z^{-1/2} on the principal branch, from |z| and the half-angle: with
 // r = |z|, A = (|Re z| + r)/2, sqrt(z) = (sqrt A, Im z/(2 sqrt A)) for Re z >= 0
 // and (|Im z|/(2 sqrt A), sign(Im z) sqrt A) otherwise; 1/sqrt(z) = conj(sqrt z)/r.
@@ -83,6 +93,7 @@ __device__ __forceinline__ cplxf crsqrt_p(cplxf z)
 }
 
 constexpr int CONT_MAXG = 8;
+static_assert(CONT_MAXG <= CONT_THREADS / 64, "one wavefront per contour point of a pass");
 
 __host__ __device__ __forceinline__ int cont_vbytes(int n) { return 8 * (4 * n * n + 2 * n); }
 // per slot: d, z^{-1/2} (2n each), diagonal blocks (3n), off-diagonal (4 n(n-1)/2)

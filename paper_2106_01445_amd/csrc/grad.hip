@@ -231,7 +231,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
     extern __shared__ double sh[];
     __shared__ int s_item;
     __shared__ cplx s_g[ORDER + 1];
-    __shared__ cplx s_w, s_ghat, s_beta;
+    __shared__ cplx s_wq[ADJ_QCHUNK];
     cplx *red = (cplx *)sh;                        // [waves]
     double *dyn = (double *)(red + CONT_THREADS / 64 + 8);
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -311,15 +311,17 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         const long long ro = roff[item];
         if (BIG)
             for (int e = tid; e < N * (N + 1) / 2; e += CONT_THREADS) rscr[ro + e] = 0.0;
+        // the item's contour points w_q = rho e^{2 pi i q / K}
+        if (tid < q1 - q0) {
+            double sn, cs;
+            sincospi(2.0 * (double)(q0 + tid) / (double)rp.K, &sn, &cs);
+            s_wq[tid] = cmk(rp.rho * cs, rp.rho * sn);
+        }
         __syncthreads();
+        // (every pass over a point ends with a barrier, so the next point's d_k
+        // and Z(w) may be written at once)
         for (int q = q0; q < q1; ++q) {
-            if (tid == 0) {
-                double sn, cs;
-                sincospi(2.0 * (double)q / (double)rp.K, &sn, &cs);
-                s_w = cmk(rp.rho * cs, rp.rho * sn);
-            }
-            __syncthreads();
-            const cplx w = s_w;
+            const cplx w = s_wq[q - q0];
             for (int k = tid; k < N; k += CONT_THREADS) {
                 const double am1 = al[k] - 1.0;
                 const cplx z = cmk(fma(w.re, am1, 1.0), w.im * am1);
@@ -331,12 +333,12 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             if (!BIG || ORDER != 2)
                 for (int i = tid; i < 4 * np; i += CONT_THREADS) Zo0[i] = cmk(0.0, 0.0);
             __syncthreads();
-            if (tid == 0) {
-                cplx pr = cmk(exp(0.5 * rp.logdet_a - rp.log_g_rho), 0.0);
-                for (int k = 0; k < N; ++k) pr = cmul(pr, rz[k]);
-                s_ghat = pr;
-                for (int t = 0; t <= ORDER; ++t)
-                    s_g[t] = cmul(asw[((long)p * (ORDER + 1) + t) * GBS_QCAP + q], pr);
+            if (wid == 0) {
+                // G_0(w)/G_0(rho) = exp(log det A/2 - log G_0(rho)) prod_k z_k^{-1/2}
+                cplx pr = cmk(1.0, 0.0);
+                for (int k = lane; k < N; k += 64) pr = cmul(pr, rz[k]);
+                pr = cmul(warp_cprod(pr), cmk(exp(0.5 * rp.logdet_a - rp.log_g_rho), 0.0));
+                if (lane <= ORDER) s_g[lane] = cmul(asw[((long)p * (ORDER + 1) + lane) * GBS_QCAP + q], pr);
             }
             // M(w) = V diag(d) V^T on the matrix cores, upper tiles over the waves
             if (ORDER >= 2) {
@@ -543,16 +545,11 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             bsum = warp_csum(bsum);
             if (lane == 0) red[wid] = bsum;
             __syncthreads();
-            if (tid == 0) {
-                cplx bt = s_g[0];
-                for (int i = 0; i < CONT_THREADS / 64; ++i) bt = cadd(bt, red[i]);
-                s_beta = bt;
-            }
-            __syncthreads();
             // R += Re[(w/2) d_i d_j (V^T Z V)_ij] (+ diagonal beta terms) on the
             // matrix cores: by rounds of two 16-column tiles jt, Y = Z V for those
             // columns into LDS, then X = V^T Y for the owned tiles (it, jt)
-            const cplx beta = s_beta;
+            cplx beta = s_g[0];
+            for (int i = 0; i < CONT_THREADS / 64; ++i) beta = cadd(beta, red[i]);
             const cplx hw = cscale(w, 0.5);
             // Z(r, s) for r, s in quadrature-major order (zero outside 2n x 2n)
             auto zget = [&](int r, int sidx) {
