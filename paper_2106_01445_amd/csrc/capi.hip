@@ -217,7 +217,7 @@ int adj_workspace(gbs_ctx *ctx, gbs_plan *pl)
     size_t rtot = 0;
     for (int p = 0; p < P; ++p) {
         const size_t N = 2 * (size_t)pl->h_n[p];
-        rtot += chunks * (N * (N + 1) / 2);
+        rtot += chunks * (N * (N + 1) / 2) * (pl->h_n[p] > GBS_NSMALL ? 1 : GBS_RSLOTS);
     }
     const size_t D = 2 * (size_t)M;
     int e = 0;

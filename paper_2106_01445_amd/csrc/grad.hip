@@ -189,20 +189,43 @@ __host__ __device__ __forceinline__ int adj_vbytes(int n) { return 8 * (2 * n * 
 // per q: d, rz (2n each), M blocks (3n + 4 n(n-1)/2), Z blocks (same)
 __host__ __device__ __forceinline__ int adj_mbytes(int n) { return 16 * (4 * n + 2 * (3 * n + 2 * n * (n - 1))); }
 __host__ __device__ __forceinline__ int adj_fixed() { return 16 * (CONT_THREADS / 64 + 8); }
-// Y = Z V is formed by column panels of ADJ_PW columns (row stride ADJ_PWS,
-// complex); the panel reuses the region of M(w) when it fits there, else it
-// follows Z(w).
+// Larger rows form Y = Z V by column panels of ADJ_PW columns (row stride
+// ADJ_PWS, complex) in their HBM scratch.
 #define ADJ_PW 32
 #define ADJ_PWS 33
-__host__ __device__ __forceinline__ bool adj_panel_in_m(int n)
-{
-    return 2 * n * ADJ_PWS <= 3 * n + 2 * n * (n - 1);
-}
-__host__ __device__ __forceinline__ int adj_need(int n)
-{
-    return adj_vbytes(n) + adj_mbytes(n) + (adj_panel_in_m(n) ? 0 : 16 * 2 * n * ADJ_PWS);
-}
+__host__ __device__ __forceinline__ int adj_need(int n) { return adj_vbytes(n) + adj_mbytes(n); }
 
+// Rows of at most 40 clicks (2n <= 80, at most ADJ_TMAX 16-wide tiles) form
+// V^T Z V by column units: unit u of a row with T tiles covers column tile jt
+// and row tiles rt0..rt1-1 and adds its share of R into slot `slot` of the
+// item's R scratch (ADJ_RSLOTS slots, summed in a fixed order by k_adj_reduce).
+// Each column is split into as many parts as keep the eight wavefronts about
+// equally loaded (a part costs (rt1 - rt0)(2 KS + 8 (jt + 1)) MFMAs); the
+// units of each T are listed by decreasing cost, and with eight units wave w
+// takes unit w (w < 4) or 11 - w, so that the two wavefronts of a SIMD hold a
+// large and a small unit.
+#define ADJ_TMAX 5
+#define ADJ_RSLOTS GBS_RSLOTS
+__device__ __forceinline__ int adj_col_units(int T)
+{
+    return T == 1 ? 1 : T == 2 ? 4 : 8;
+}
+__device__ __forceinline__ void adj_col_unit(int T, int u, int &jt, int &rt0, int &rt1, int &slot)
+{
+    // (jt, rt0, rt1, slot) packed 4 bits each
+    constexpr unsigned short tab[5][8] = {
+        {0x0010},
+        {0x1010, 0x1121, 0x0010, 0x0121},
+        {0x0131, 0x2010, 0x2121, 0x2232, 0x1010, 0x1121, 0x1232, 0x0010},
+        {0x3020, 0x3241, 0x2020, 0x2241, 0x1020, 0x1241, 0x0020, 0x0241},
+        {0x1050, 0x0050, 0x4251, 0x3251, 0x2251, 0x4020, 0x3020, 0x2020},
+    };
+    const unsigned v = tab[T - 1][u];
+    jt = (v >> 12) & 15;
+    rt0 = (v >> 8) & 15;
+    rt1 = (v >> 4) & 15;
+    slot = v & 15;
+}
 
 __device__ __forceinline__ void catomic(cplx *dst, cplx v)
 {
@@ -279,7 +302,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             Md0 = rz + N;
             Zd0 = Md0 + 3 * n + 4 * np;
             Zo0 = Zd0 + 3 * n;
-            Yp = adj_panel_in_m(n) ? Md0 : Zo0 + 4 * np;
+            Yp = nullptr;  // (no panel: Y stays in registers)
             for (int idx = tid; idx < N * N; idx += CONT_THREADS) {
                 const int k = idx / N, i = idx - k * N;
                 vl[k * NP + i] = vt[vo + idx];
@@ -293,24 +316,10 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
         const int Qn = rp.K / 2 + 1;
         const int q0 = ch * ADJ_QCHUNK, q1 = min(q0 + ADJ_QCHUNK, Qn);
-        // R in registers: the upper triangle of 16x16 tiles (it <= jt), tile u of
-        // the column-major tile list is held by wave u % 8 (at most 15 tiles)
-        const int T = (N + 15) >> 4, KS = (N + 3) >> 2, ntile = T * (T + 1) / 2;
-        int tit[2], tjt[2];
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            const int u = wid + 8 * m;
-            int it, jt;
-            upper_tile(u, it, jt);
-            tjt[m] = u < ntile ? jt : -1;
-            tit[m] = it;
-        }
-        dbl4 racc[2];
-#pragma unroll
-        for (int m = 0; m < 2; ++m) racc[m] = dbl4{0.0, 0.0, 0.0, 0.0};
+        const int T = (N + 15) >> 4, KS = (N + 3) >> 2;
         const long long ro = roff[item];
-        if (BIG)
-            for (int e = tid; e < N * (N + 1) / 2; e += CONT_THREADS) rscr[ro + e] = 0.0;
+        const int nslot = BIG ? 1 : ADJ_RSLOTS;
+        for (int e = tid; e < nslot * (N * (N + 1) / 2); e += CONT_THREADS) rscr[ro + e] = 0.0;
         // the item's contour points w_q = rho e^{2 pi i q / K}
         if (tid < q1 - q0) {
             double sn, cs;
@@ -562,9 +571,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 const cplx zl = *(ok ? src : Zd0);
                 return ok ? zl : cmk(0.0, 0.0);
             };
-            for (int jr = 0; jr < T; jr += 2) {
+            for (int jr = 0; BIG && jr < T; jr += 2) {
                 const int nj = min(2, T - jr);
-                if (BIG) {
+                {
                     // V comes from L2: 2x2 blocks of tiles share each operand fetch.
                     // Y for the round's two column tiles, one 32-row block per chain.
                     const int TB = (T + 1) / 2;
@@ -656,91 +665,95 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                             }
                     }
                     __syncthreads();
-                    continue;
                 }
-                for (int ch = wid; ch < nj * T; ch += CONT_THREADS / 64) {
-                    const int jt = jr + ch / T, rt = ch - (ch / T) * T;
-                    const int r = rt * 16 + l16, j = jt * 16 + l16;
-                    const bool rok = r < N, jok = j < N;
-                    const int a = r < n ? r : r - n, qa = r < n ? 0 : 1;
-                    dbl4 yre = {0.0, 0.0, 0.0, 0.0}, yim = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-                    for (int ks = 0; ks < KS; ++ks) {
-                        const int sidx = ks * 4 + lq;
-                        const bool ok = rok && sidx < N;
-                        const int b = sidx < n ? sidx : sidx - n, qb = sidx < n ? 0 : 1;
-                        const int lo = min(a, b), hi = max(a, b);
-                        const int kq = a < b ? 2 * qa + qb : 2 * qb + qa;
-                        // Zd0..Zd2 (stride n) are followed by Zo0..Zo3 (stride np)
-                        int off = a == b ? (qa + qb) * n + a : 3 * n + kq * np + pair_pos<true>(n, lo, hi);
-                        const cplx zl = Zd0[ok ? off : 0];
-                        const cplx z = ok ? zl : cmk(0.0, 0.0);
-                        const bool vok = jok && sidx < N;
-                        const double vl = Vt[vok ? j * vs + sidx : 0];
-                        const double v = vok ? vl : 0.0;
-                        yre = mfma4(z.re, v, yre);
-                        yim = mfma4(z.im, v, yim);
-                    }
-                    const int col = (jt - jr) * 16 + l16;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int row = rt * 16 + 4 * e + lq;
-                        if (row < N) Yp[row * ADJ_PWS + col] = cmk(yre[e], yim[e]);
-                    }
-                }
-                __syncthreads();
-                // X = V^T Y for tile (it, jt); sink(e, ii, jj, value) takes the R terms
-                auto x_tile = [&](int it, int jt, auto &&sink) {
-                    const int i = it * 16 + l16, col = (jt - jr) * 16 + l16;
-                    const bool iok = i < N;
-                    dbl4 xre = {0.0, 0.0, 0.0, 0.0}, xim = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-                    for (int ks = 0; ks < KS; ++ks) {
-                        const int sidx = ks * 4 + lq;
-                        const bool sok = sidx < N, vok = iok && sok;
-                        const double vl = Vt[vok ? i * vs + sidx : 0];
-                        const double v = vok ? vl : 0.0;
-                        const cplx yl = Yp[sok ? sidx * ADJ_PWS + col : 0];
-                        const cplx y = sok ? yl : cmk(0.0, 0.0);
-                        xre = mfma4(v, y.re, xre);
-                        xim = mfma4(v, y.im, xim);
-                    }
+            }
+            if (!BIG) {
+                // Column unit (jt, rows rt0..rt1-1, slot): Y(rt, jt) = Z V for each
+                // row tile rt of the part, then, with Y still in the accumulators
+                // (the 16x16x4 accumulator layout is the B operand layout of the
+                // next product), X(it, jt) += V^T(it, rt) Y(rt, jt) for it <= jt;
+                // finally R += Re[f X] (+ the diagonal beta terms in slot 0) in the
+                // part's R slot of the item (read-modified-written, L2-resident).
+                // The units split the columns so that the two wavefronts of each
+                // SIMD get about the same number of MFMAs.
+                const int nup = N * (N + 1) / 2;
+                const int nun = adj_col_units(T);
+                for (int uw = wid; uw < nun; uw += CONT_THREADS / 64) {
+                    const int u = nun == CONT_THREADS / 64 && uw >= 4 ? 11 - uw : uw;
+                    int jt, rt0, rt1, slot;
+                    adj_col_unit(T, u, jt, rt0, rt1, slot);
+                    double *Rs = rscr + ro + (long long)slot * nup;
                     const int jj = jt * 16 + l16;
+                    const bool jok = jj < N;
+                    double rold[ADJ_TMAX][4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int ii = it * 16 + 4 * e + lq;
-                        if (ii <= jj && jj < N) {
-                            const cplx f = cmul(hw, cmul(dk[ii], dk[jj]));
-                            double add = f.re * xre[e] - f.im * xim[e];
-                            if (ii == jj) {
-                                const double dr = 1.0 / (1.0 + rp.rho * (al[ii] - 1.0));
-                                const cplx t = cmk(0.5 * rp.rho * dr - hw.re * dk[ii].re + hw.im * dk[ii].im,
-                                                   -(hw.re * dk[ii].im + hw.im * dk[ii].re));
-                                add += beta.re * t.re - beta.im * t.im;
+                    for (int it = 0; it < ADJ_TMAX; ++it)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int ii = it * 16 + 4 * e + lq;
+                            rold[it][e] = it <= jt && ii <= jj && jok ? Rs[jj * (jj + 1) / 2 + ii] : 0.0;
+                        }
+                    dbl4 xre[ADJ_TMAX], xim[ADJ_TMAX];
+#pragma unroll
+                    for (int it = 0; it < ADJ_TMAX; ++it) xre[it] = xim[it] = dbl4{0.0, 0.0, 0.0, 0.0};
+                    for (int rt = rt0; rt < rt1; ++rt) {
+                        const int r = rt * 16 + l16;
+                        const bool rok = r < N;
+                        const int a = r < n ? r : r - n, qa = r < n ? 0 : 1;
+                        dbl4 yre = {0.0, 0.0, 0.0, 0.0}, yim = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+                        for (int ks = 0; ks < KS; ++ks) {
+                            const int sidx = ks * 4 + lq;
+                            const bool ok = rok && sidx < N;
+                            const int b = sidx < n ? sidx : sidx - n, qb = sidx < n ? 0 : 1;
+                            const int lo = min(a, b), hi = max(a, b);
+                            const int kq = a < b ? 2 * qa + qb : 2 * qb + qa;
+                            // Zd0..Zd2 (stride n) are followed by Zo0..Zo3 (stride np)
+                            const int off = a == b ? (qa + qb) * n + a : 3 * n + kq * np + pair_pos<true>(n, lo, hi);
+                            const cplx zl = Zd0[ok ? off : 0];
+                            const cplx z = ok ? zl : cmk(0.0, 0.0);
+                            const bool vok = jok && sidx < N;
+                            const double vl = Vt[vok ? jj * vs + sidx : 0];
+                            const double v = vok ? vl : 0.0;
+                            yre = mfma4(z.re, v, yre);
+                            yim = mfma4(z.im, v, yim);
+                        }
+                        // rows of Y beyond 2n are zero, so the A operand there only
+                        // has to be finite
+#pragma unroll
+                        for (int it = 0; it < ADJ_TMAX; ++it) {
+                            if (it > jt) continue;
+                            const int i = it * 16 + l16, ic = i < N ? i : 0;
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const int rr = rt * 16 + 4 * e + lq, rc = rr < N ? rr : 0;
+                                const double av = Vt[ic * vs + rc];
+                                xre[it] = mfma4(av, yre[e], xre[it]);
+                                xim[it] = mfma4(av, yim[e], xim[it]);
                             }
-                            sink(e, ii, jj, add);
                         }
                     }
-                };
-                {
 #pragma unroll
-                    for (int m = 0; m < 2; ++m) {
-                        const int it = tit[m], jt = tjt[m];
-                        if (jt < jr || jt >= jr + nj) continue;
-                        x_tile(it, jt, [&](int e, int, int, double add) { racc[m][e] += add; });
+                    for (int it = 0; it < ADJ_TMAX; ++it) {
+                        if (it > jt) continue;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int ii = it * 16 + 4 * e + lq;
+                            if (ii <= jj && jok) {
+                                const cplx f = cmul(hw, cmul(dk[ii], dk[jj]));
+                                double add = f.re * xre[it][e] - f.im * xim[it][e];
+                                if (ii == jj && slot == 0) {
+                                    const double dr = 1.0 / (1.0 + rp.rho * (al[ii] - 1.0));
+                                    const cplx t = cmk(0.5 * rp.rho * dr - hw.re * dk[ii].re + hw.im * dk[ii].im,
+                                                       -(hw.re * dk[ii].im + hw.im * dk[ii].re));
+                                    add += beta.re * t.re - beta.im * t.im;
+                                }
+                                Rs[jj * (jj + 1) / 2 + ii] = rold[it][e] + add;
+                            }
+                        }
                     }
                 }
                 __syncthreads();
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            if (BIG || tjt[m] < 0) continue;
-            const int jj = tjt[m] * 16 + l16;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int ii = tit[m] * 16 + 4 * e + lq;
-                if (ii <= jj && jj < N) rscr[ro + jj * (jj + 1) / 2 + ii] = racc[m][e];
             }
         }
         __syncthreads();
@@ -771,8 +784,9 @@ __global__ __launch_bounds__(1024) void k_adj_items(int P, int nbig, const int *
     };
     auto rsz = [&](int i) {
         const int p = perm[i];
-        const long long N = 2 * (offsets[p + 1] - offsets[p]);
-        return N * (N + 1) / 2;
+        const int n = offsets[p + 1] - offsets[p];
+        const long long N = 2 * n;
+        return (n > GBS_NSMALL ? 1 : ADJ_RSLOTS) * (N * (N + 1) / 2);
     };
     __shared__ int s_big;
     if (tid == 0) s_big = 0;
@@ -866,7 +880,8 @@ __global__ __launch_bounds__(256) void k_adj_reduce(int M, const int *__restrict
         int i, j;
         upper_ij(e, i, j);
         double s = 0.0;
-        for (int it = 0; it < nit; ++it) s += rscr[roff[it0 + it] + e];
+        for (int it = 0; it < nit; ++it)
+            for (int sl = 0; sl < ADJ_RSLOTS; ++sl) s += rscr[roff[it0 + it] + (long long)sl * nup + e];
         if (i == j) {
             const double dr = 1.0 / (1.0 + rp.rho * (alpha[2 * o + i] - 1.0));
             s += -0.5 * dl[p] * rp.rho * dr;

@@ -14,6 +14,7 @@
 #define GBS_MAX_N_APPROX 128   // clicks per row on the approximate path (orders 1, 2)
 #define GBS_MAX_N_ORDER3 64    // clicks per row at order 3
 #define GBS_NSMALL 40          // rows up to this many clicks keep V and M(w) in LDS (contour)
+#define GBS_RSLOTS 3           // R slots per adjoint work item of such a row (column units)
 #define GBS_MAX_N_EXACT 24     // clicks per row on the exact path
 #define GBS_KMAX 2048          // contour size cap
 #define GBS_QCAP (GBS_KMAX / 2 + 1)
