@@ -112,6 +112,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
 {
     extern __shared__ double sh[];
     __shared__ int s_item;
+    __shared__ cplx s_wq[GBS_QCHUNK_MAX];                    // the item's contour points
     cplx *red = (cplx *)sh;                                  // [waves][4]
     cplx *ghat = red + (CONT_THREADS / 64) * 4;              // [CONT_MAXG]
     double *dyn = (double *)(ghat + CONT_MAXG);
@@ -152,22 +153,23 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
         const int Q = rp.K / 2 + 1;
         const int q0 = ch * qchunk, q1 = min(q0 + qchunk, Q);
         const int np = n * (n - 1) / 2;
+        // the item's contour points w_q = rho e^{2 pi i q / K}
+        if (tid < q1 - q0) {
+            double sn, cs;
+            sincospi(2.0 * (double)(q0 + tid) / (double)rp.K, &sn, &cs);
+            s_wq[tid] = cmk(rp.rho * cs, rp.rho * sn);
+        }
         __syncthreads();
+        // (every pass ends with a barrier, so the next pass may write its slots
+        // at once)
         for (int qb = q0; qb < q1; qb += G) {
             const int g = min(G, q1 - qb);
-            // contour point of each slot
-            if (tid < g) {
-                double sn, cs;
-                sincospi(2.0 * (double)(qb + tid) / (double)rp.K, &sn, &cs);
-                ghat[tid] = cmk(rp.rho * cs, rp.rho * sn);
-            }
-            __syncthreads();
             // d_k = 1/z_k and z_k^{-1/2}, z_k = 1 + w(alpha_k - 1); Re z_k > 0 inside
             // the convergence radius, so the principal root is the branch that is
             // continuous from w = 0
             for (int idx = tid; idx < g * N; idx += CONT_THREADS) {
                 const int sl = idx / N, k = idx - sl * N;
-                const cplx w = ghat[sl];
+                const cplx w = s_wq[qb - q0 + sl];
                 const double am1 = al[k] - 1.0;
                 const cplx z = cmk(fma(w.re, am1, 1.0), w.im * am1);
                 const cplx rz = crsqrt_p(z);

@@ -613,7 +613,7 @@ int gbs_plan_set_params(gbs_plan *pl, const int32_t *params)
     const int sf = params[0], sa = params[1], qc = params[2], gm = params[3];
     if (sf < 1 || sf > 64 || sa < 1 || sa > 64)
         return set_err(ctx, GBS_E_INVAL, "segment lengths must be in [1, 64]");
-    if (qc < GBS_QCHUNK_MIN || qc > 64 || (qc & (qc - 1)))
+    if (qc < GBS_QCHUNK_MIN || qc > GBS_QCHUNK_MAX || (qc & (qc - 1)))
         return set_err(ctx, GBS_E_INVAL, "contour points per item must be 4, 8, 16, 32 or 64");
     if (gm < 1 || gm > 8 || (gm & (gm - 1)))
         return set_err(ctx, GBS_E_INVAL, "points per pass must be 1, 2, 4 or 8");

@@ -20,6 +20,7 @@
 #define GBS_QCAP (GBS_KMAX / 2 + 1)
 #define GBS_QCHUNK 8           // contour points per work item (default)
 #define GBS_QCHUNK_MIN 4       // smallest tunable value (sizes the item lists)
+#define GBS_QCHUNK_MAX 64      // largest tunable value
 #define GBS_CLUSTER_SEG 3      // triples per cluster work unit at order 3 (default)
 
 struct cplx {
