@@ -201,8 +201,10 @@ int gbs_plan_get_params(gbs_plan *plan, int32_t *params);
 int gbs_plan_set_params(gbs_plan *plan, const int32_t *params);
 
 /*
- * Autotuner: times candidate launch choices (coordinate descent over the
- * values listed above, two runs each, the faster counts) on a stratified
+ * Autotuner: times candidate launch choices (coordinate descent over third
+ * modes per unit 2, 3, 4, 6, 8, 12 for the forward and 2, 3, 4, 6 for the
+ * adjoint, points per item 4, 8, 16 and per pass 2, 4, 8; two runs each, the
+ * faster counts) on a stratified
  * sample of the plan's rows (every s-th row in cost order, s = max(1, P/1024))
  * with the context's current model, and stores the fastest in the plan.  what:
  * bit 0 the forward choices, bit 1 the adjoint's (needs a model set from

@@ -702,7 +702,7 @@ int gbs_plan_tune(gbs_ctx *ctx, gbs_plan *pl, int what, int32_t *params_out)
     struct Axis { int index; std::vector<int> values; bool adjoint; };
     std::vector<Axis> axes;
     if (what & 1) {
-        if (pl->order >= 3) axes.push_back({0, {2, 3, 4, 6}, false});
+        if (pl->order >= 3) axes.push_back({0, {2, 3, 4, 6, 8, 12}, false});
         axes.push_back({2, {4, 8, 16}, false});
         axes.push_back({3, {2, 4, 8}, false});
     }
