@@ -125,7 +125,7 @@ int gbs_prob_exact(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *m
                    double *p, double *logp, double *kappa, int32_t *status);
 
 /*
- * gbs_prob_approx: the paper's order-j estimate (1 <= order <= 3), returned as
+ * gbs_prob_approx: the paper's order-j estimate (1 <= order <= 4), returned as
  * log p_hat (p_hat reaches 1e-35 and below).  For each row:
  *   1. A = (Q^{-1})_CC, eigen-decomposed (A = V diag(alpha) V^T);
  *      log P_vac(Cbar) = -(log det Q + log det A) / 2 (eq. 3, second factor);
@@ -140,10 +140,11 @@ int gbs_prob_exact(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *m
  *   5. per sector kappa >= n, the exp-polynomial of degree min(j, n-1) matching
  *      the moments (Methods, Approximation method) and its all-click value;
  *   6. log p_hat = log P_vac(Cbar) + log sum_kappa S_0[kappa] q_kappa(n).
- * Rows may hold at most 128 clicks at orders 1 and 2 and at most 64 at order
- * 3 (more is GBS_E_INVAL).  Rows above 40 clicks keep their eigenvectors and
- * M(w) in device memory instead of on-chip memory (slower per contour point,
- * same results).  Outputs: logp[P], status[P].
+ * Rows may hold at most 128 clicks at orders 1 and 2, at most 64 at order 3
+ * and at most 40 at order 4 (more is GBS_E_INVAL); order 4 runs in fp64 only
+ * (GBS_PREC_MIXED is GBS_E_INVAL there).  Rows above 40 clicks keep their
+ * eigenvectors and M(w) in device memory instead of on-chip memory (slower per
+ * contour point, same results).  Outputs: logp[P], status[P].
  */
 int gbs_prob_approx(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int order,
                     int prec, double *logp, int32_t *status);
@@ -179,8 +180,8 @@ int gbs_prob_approx_dev(gbs_ctx *ctx, gbs_plan *plan, double *logp_dev, int32_t 
  * with respect to r[M] and eta[M] of the model set by gbs_set_model, by a
  * hand-written adjoint of steps 1-6 (d log det X = tr(X^{-1} dX) at every
  * determinant, implicit differentiation of each sector fit), with the contour
- * radius and size held at their forward values.  Host pointers; logp
- * (nullable) receives the forward values.
+ * radius and size held at their forward values.  Orders 1 to 3 (order 4 is
+ * GBS_E_INVAL).  Host pointers; logp (nullable) receives the forward values.
  */
 int gbs_grad(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int order, int prec,
              const double *dL_dlogp, double *logp, double *grad_r, double *grad_eta,
@@ -191,7 +192,8 @@ int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *plan, const double *dL_dlogp_dev, doubl
 
 /*
  * Launch choices of a plan, params[4]: [0] third modes per cluster work unit of
- * the forward contour kernel (order 3), [1] the same for the adjoint, [2]
+ * the forward contour kernel (order 3; at order 4 also the fourth modes per
+ * quadruple unit, at most 15 of them), [1] the same for the adjoint, [2]
  * contour points per forward work item (4, 8, 16, 32 or 64), [3] most contour
  * points per pass of the forward kernel (1, 2, 4 or 8).  Defaults 3, 3, 8, 8.
  * They change the speed, not the results (up to the order of floating-point

@@ -108,7 +108,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
     const double *__restrict__ alpha, const double *__restrict__ vt,
     const RowPlan *__restrict__ rows, const int *__restrict__ items, const int *__restrict__ q_end,
     int *__restrict__ q_head, const int *__restrict__ units, const int *__restrict__ unit_off,
-    cplx *__restrict__ mscr, long long mscr_stride, cplx *__restrict__ sw)
+    const int *__restrict__ unit4_off, cplx *__restrict__ mscr, long long mscr_stride, cplx *__restrict__ sw)
 {
     extern __shared__ double sh[];
     __shared__ int s_item;
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
             // clusters: slot groups of SG threads (whole wavefronts)
             const int SG = CONT_THREADS / G;
             const int sl = tid / SG, lt = tid - sl * SG;
-            cplx s1 = cmk(0, 0), s2 = cmk(0, 0), s3 = cmk(0, 0);
+            cplx s1 = cmk(0, 0), s2 = cmk(0, 0), s3 = cmk(0, 0), s4 = cmk(0, 0);
             if (sl < g) {
                 const SlotMT<C> m = slot_view<C>(slots + sl * mstride, n);
                 for (int a = lt; a < n; a += SG) {
@@ -302,15 +302,106 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                         }
                     }
                 }
+                if (ORDER >= 4) {
+                    // quadruples (a, b, c, d): units (a, b, c; d0..d0+len-1).  With the
+                    // pair P = {a, b} eliminated (Maa^{-1}, G, Sb^{-1}) and then c (its
+                    // Schur complement Sc), each d costs the 2x2 Schur complement
+                    //   Sd = Mdd - r^T P^{-1} r - u^T Sc^{-1} u,  r = [Mad; Mbd],
+                    //   u = Mcd - [Mac; Mbc]^T P^{-1} r,
+                    // where s^T P^{-1} r = (Maa^{-1} xs)^T x + Ys^T Sb^{-1} Y for
+                    // s = [xs; ys], Y = y - G^T x, Ys = ys - G^T xs; and
+                    // det M_TT = det Maa det Sb det Sc det Sd
+                    const int *un4 = units + unit4_off[2 * n];
+                    const int nu4 = unit4_off[2 * n + 1];
+#pragma unroll 1
+                    for (int ui = lt; ui < nu4; ui += SG) {
+                        const unsigned u = (unsigned)un4[ui];
+                        const int a = u & 63, b = (u >> 6) & 63, c = (u >> 12) & 63, d0 = (u >> 18) & 63,
+                                  d1 = d0 + (int)(u >> 24);
+                        const int pi = b * (b - 1) / 2 + a;
+                        const C a00 = m.d0[a], a01 = m.d1[a], a11 = m.d2[a];
+                        const C b00 = m.o0[pi], b01 = m.o1[pi], b10 = m.o2[pi], b11 = m.o3[pi];
+                        const C ra = crsqrt_p(cfnma(a01, a01, cmul(a00, a11)));
+                        const C ideta = cmul(ra, ra);
+                        const C ia00 = cmul(a11, ideta), ia11 = cmul(a00, ideta);
+                        const C ia01 = cneg(cmul(a01, ideta));
+                        const C G00 = cfma(ia00, b00, cmul(ia01, b10));
+                        const C G01 = cfma(ia00, b01, cmul(ia01, b11));
+                        const C G10 = cfma(ia01, b00, cmul(ia11, b10));
+                        const C G11 = cfma(ia01, b01, cmul(ia11, b11));
+                        const C sb00 = csub(m.d0[b], cfma(b00, G00, cmul(b10, G10)));
+                        const C sb01 = csub(m.d1[b], cfma(b00, G01, cmul(b10, G11)));
+                        const C sb11 = csub(m.d2[b], cfma(b01, G01, cmul(b11, G11)));
+                        const C rb = crsqrt_p(cfnma(sb01, sb01, cmul(sb00, sb11)));
+                        const C idetb = cmul(rb, rb);
+                        const C ib00 = cmul(sb11, idetb), ib11 = cmul(sb00, idetb);
+                        const C ib01 = cneg(cmul(sb01, idetb));
+                        // c: xc = Mac, Zc = Maa^{-1} xc, Yc = Mbc - G^T xc, Wc = Sb^{-1} Yc
+                        const int cb = c * (c - 1) / 2;
+                        const C xc00 = m.o0[cb + a], xc01 = m.o1[cb + a], xc10 = m.o2[cb + a], xc11 = m.o3[cb + a];
+                        const C Zc00 = cfma(ia00, xc00, cmul(ia01, xc10)), Zc10 = cfma(ia01, xc00, cmul(ia11, xc10));
+                        const C Zc01 = cfma(ia00, xc01, cmul(ia01, xc11)), Zc11 = cfma(ia01, xc01, cmul(ia11, xc11));
+                        const C Yc00 = csub(m.o0[cb + b], cfma(G00, xc00, cmul(G10, xc10)));
+                        const C Yc01 = csub(m.o1[cb + b], cfma(G00, xc01, cmul(G10, xc11)));
+                        const C Yc10 = csub(m.o2[cb + b], cfma(G01, xc00, cmul(G11, xc10)));
+                        const C Yc11 = csub(m.o3[cb + b], cfma(G01, xc01, cmul(G11, xc11)));
+                        const C Wc00 = cfma(ib00, Yc00, cmul(ib01, Yc10)), Wc10 = cfma(ib01, Yc00, cmul(ib11, Yc10));
+                        const C Wc01 = cfma(ib00, Yc01, cmul(ib01, Yc11)), Wc11 = cfma(ib01, Yc01, cmul(ib11, Yc11));
+                        const C sc00 = csub(m.d0[c], cfma(xc00, Zc00, cfma(xc10, Zc10, cfma(Yc00, Wc00, cmul(Yc10, Wc10)))));
+                        const C sc01 = csub(m.d1[c], cfma(xc00, Zc01, cfma(xc10, Zc11, cfma(Yc00, Wc01, cmul(Yc10, Wc11)))));
+                        const C sc11 = csub(m.d2[c], cfma(xc01, Zc01, cfma(xc11, Zc11, cfma(Yc01, Wc01, cmul(Yc11, Wc11)))));
+                        const C rc = crsqrt_p(cfnma(sc01, sc01, cmul(sc00, sc11)));
+                        const C idetc = cmul(rc, rc);
+                        const C ic00 = cmul(sc11, idetc), ic11 = cmul(sc00, idetc);
+                        const C ic01 = cneg(cmul(sc01, idetc));
+                        cplx s4p = cmk(0, 0);
+#pragma unroll 1
+                        for (int d = d0; d < d1; ++d) {
+                            const int db = d * (d - 1) / 2;
+                            const int iad = db + a, ibd = db + b, icd = db + c;
+                            const C x00 = m.o0[iad], x01 = m.o1[iad], x10 = m.o2[iad], x11 = m.o3[iad];
+                            const C Y00 = csub(m.o0[ibd], cfma(G00, x00, cmul(G10, x10)));
+                            const C Y01 = csub(m.o1[ibd], cfma(G00, x01, cmul(G10, x11)));
+                            const C Y10 = csub(m.o2[ibd], cfma(G01, x00, cmul(G11, x10)));
+                            const C Y11 = csub(m.o3[ibd], cfma(G01, x01, cmul(G11, x11)));
+                            const C W00 = cfma(ib00, Y00, cmul(ib01, Y10)), W10 = cfma(ib01, Y00, cmul(ib11, Y10));
+                            const C W01 = cfma(ib00, Y01, cmul(ib01, Y11)), W11 = cfma(ib01, Y01, cmul(ib11, Y11));
+                            C q00, q01, q11;
+                            {
+                                const C Z00 = cfma(ia00, x00, cmul(ia01, x10)), Z10 = cfma(ia01, x00, cmul(ia11, x10));
+                                const C Z01 = cfma(ia00, x01, cmul(ia01, x11)), Z11 = cfma(ia01, x01, cmul(ia11, x11));
+                                q00 = csub(m.d0[d], cfma(x00, Z00, cfma(x10, Z10, cfma(Y00, W00, cmul(Y10, W10)))));
+                                q01 = csub(m.d1[d], cfma(x00, Z01, cfma(x10, Z11, cfma(Y00, W01, cmul(Y10, W11)))));
+                                q11 = csub(m.d2[d], cfma(x01, Z01, cfma(x11, Z11, cfma(Y01, W01, cmul(Y11, W11)))));
+                            }
+                            // u[i][j] = Mcd[i][j] - sum_k (Zc[k][i] x[k][j] + Yc[k][i] W[k][j])
+                            const C u00 = csub(m.o0[icd], cfma(Zc00, x00, cfma(Zc10, x10, cfma(Yc00, W00, cmul(Yc10, W10)))));
+                            const C u01 = csub(m.o1[icd], cfma(Zc00, x01, cfma(Zc10, x11, cfma(Yc00, W01, cmul(Yc10, W11)))));
+                            const C u10 = csub(m.o2[icd], cfma(Zc01, x00, cfma(Zc11, x10, cfma(Yc01, W00, cmul(Yc11, W10)))));
+                            const C u11 = csub(m.o3[icd], cfma(Zc01, x01, cfma(Zc11, x11, cfma(Yc01, W01, cmul(Yc11, W11)))));
+                            // v = Sc^{-1} u; Sd = q - u^T v
+                            const C v00 = cfma(ic00, u00, cmul(ic01, u10)), v10 = cfma(ic01, u00, cmul(ic11, u10));
+                            const C v01 = cfma(ic00, u01, cmul(ic01, u11)), v11 = cfma(ic01, u01, cmul(ic11, u11));
+                            q00 = csub(q00, cfma(u00, v00, cmul(u10, v10)));
+                            q01 = csub(q01, cfma(u00, v01, cmul(u10, v11)));
+                            q11 = csub(q11, cfma(u01, v01, cmul(u11, v11)));
+                            s4p = cadd(s4p, to_d(crsqrt_p(cfnma(q01, q01, cmul(q00, q11)))));
+                        }
+                        s4 = cfma(to_d(cmul(cmul(ra, rb), rc)), s4p, s4);
+                    }
+                }
             }
             s1 = warp_csum(s1);
             s2 = warp_csum(s2);
             s3 = warp_csum(s3);
+            if (ORDER >= 4) s4 = warp_csum(s4);
             if (lane == 0) {
                 red[4 * wid + 1] = s1;
                 red[4 * wid + 2] = s2;
                 red[4 * wid + 3] = s3;
+                if (ORDER >= 4) red[4 * wid] = s4;  // (slot 0 is free: t = 4 takes it)
             }
+
             __syncthreads();
             if (tid < g * (ORDER + 1)) {
                 const int s = tid / (ORDER + 1), t = tid - s * (ORDER + 1);
@@ -318,7 +409,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                 if (t > 0) {
                     acc = cmk(0.0, 0.0);
                     const int w0 = s * (SG / 64), w1 = w0 + SG / 64;
-                    for (int w = w0; w < w1; ++w) acc = cadd(acc, red[4 * w + t]);
+                    for (int w = w0; w < w1; ++w) acc = cadd(acc, red[4 * w + (t & 3)]);
                 }
                 sw[((long)p * (ORDER + 1) + t) * GBS_QCAP + qb + s] = cmul(ghat[s], acc);
             }
@@ -369,10 +460,11 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
     // tilted sector moments tau_t[kappa] = Re FFT(S_t(w_q))[kappa] / K, where the
     // points q > K/2 are the conjugates of K - q (real coefficients)
     // (loops over t and j unrolled: every index into tau is static)
-    double tau[FIT_KPT][4];
+    constexpr int NT = ORDER >= 4 ? 5 : 4;  // moments held per sector
+    double tau[FIT_KPT][NT];
     const double invK = 1.0 / K;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NT; ++t) {
         if (t <= ORDER && t <= jp) {
             const cplx *src = sw + ((long)p * (ORDER + 1) + t) * GBS_QCAP;
             for (int q = tid; q < K; q += nt) {
@@ -417,7 +509,8 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
         if (!(t0 >= thr) || !(t0 > 0.0)) continue;
         const double lw = log(t0) + rp.log_g_rho - kap * rp.log_rho;
         if (lw < lower + log(1e-17)) continue;
-        const SectorFit f = fit_sector(n, jp, t0, tau[j][1], tau[j][2], tau[j][3]);
+        const SectorFitT<ORDER >= 4 ? 4 : 3> f =
+            fit_sector<ORDER >= 4 ? 4 : 3>(n, jp, t0, tau[j][1], tau[j][2], tau[j][3], ORDER >= 4 ? tau[j][NT - 1] : 0.0);
         if (f.bad) {
             lse_add(um, us, lw);
         } else {
@@ -485,7 +578,9 @@ int launch_contour(gbs_ctx *ctx, gbs_plan *pl, int nmax)
     int *q_head = pl->d_counter + (BIG ? 5 : 1);
     hipLaunchKernelGGL((k_contour<ORDER, BIG, C>), dim3(grid), dim3(CONT_THREADS), lds_c, st, lds_c,
                        pl->qchunk, pl->gmax, pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_items,
-                       q_end, q_head, pl->d_cluster_items, pl->d_cluster_off, mscr, mstride, pl->d_sw);
+                       q_end, q_head, pl->d_cluster_items, pl->d_cluster_off,
+                       pl->order >= 4 ? pl->d_cluster_off + 4 * (pl->max_n + 1) : nullptr, mscr, mstride,
+                       pl->d_sw);
     return 0;
 }
 
@@ -524,7 +619,36 @@ int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
     return 0;
 }
 
+// Order 4: rows of at most 40 clicks, fp64 (the plan enforces both).
+int launch_order4(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
+{
+    hipStream_t st = ctx->stream;
+    const int P = pl->P;
+    if (pl->nbig > 0 || pl->prec != GBS_PREC_FP64)
+        return set_err(ctx, GBS_E_INVAL, "order 4 takes rows of at most 40 clicks, in fp64");
+    int ts = timer_begin(ctx, TG_PREP);
+    int rc = eig_rows(ctx, pl);
+    if (rc) return rc;
+    timer_end(ctx, ts);
+    ts = timer_begin(ctx, TG_ITEMS);
+    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, st, P, 0, pl->qchunk, pl->d_offsets, pl->d_perm,
+                       pl->d_rows, pl->d_items, pl->d_counter);
+    timer_end(ctx, ts);
+    ts = timer_begin(ctx, TG_CONTOUR);
+    if ((rc = launch_contour<4, false, cplx>(ctx, pl, pl->max_n_small))) return rc;
+    timer_end(ctx, ts);
+    size_t lds_f = sizeof(cplx) * (GBS_KMAX + GBS_KMAX / 2);
+    if ((rc = func_lds_limit(ctx, (const void *)k_dft_fit<4>, (int)lds_f))) return rc;
+    ts = timer_begin(ctx, TG_FIT);
+    hipLaunchKernelGGL(k_dft_fit<4>, dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets, pl->d_rows, pl->d_sw,
+                       logp, status);
+    timer_end(ctx, ts);
+    HIP_TRY(ctx, hipGetLastError());
+    return 0;
+}
+
 // The plain comparison kernel (plain.hip) in place of the contour kernels.
+
 template <int ORDER>
 int launch_plain(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
 {
@@ -555,7 +679,8 @@ int approx_forward_plain(gbs_ctx *ctx, gbs_plan *pl, double *logp_dev, int32_t *
     case 1: return launch_plain<1>(ctx, pl, logp_dev, status_dev);
     case 2: return launch_plain<2>(ctx, pl, logp_dev, status_dev);
     case 3: return launch_plain<3>(ctx, pl, logp_dev, status_dev);
-    default: return set_err(ctx, -1, "order must be 1, 2 or 3");
+    case 4: return launch_plain<4>(ctx, pl, logp_dev, status_dev);
+    default: return set_err(ctx, -1, "order must be 1, 2, 3 or 4");
     }
 }
 
@@ -566,6 +691,7 @@ int approx_forward(gbs_ctx *ctx, gbs_plan *pl, double *logp_dev, int32_t *status
     case 1: return launch_order<1>(ctx, pl, logp_dev, status_dev);
     case 2: return launch_order<2>(ctx, pl, logp_dev, status_dev);
     case 3: return launch_order<3>(ctx, pl, logp_dev, status_dev);
-    default: return set_err(ctx, -1, "order must be 1, 2 or 3");
+    case 4: return launch_order4(ctx, pl, logp_dev, status_dev);
+    default: return set_err(ctx, -1, "order must be 1, 2, 3 or 4");
     }
 }

@@ -163,6 +163,31 @@ void cluster_units(int n, int order, int seg, bool adjoint, std::vector<int32_t>
                                 (unsigned)x.c1 << 24));
 }
 
+// Quadruple work units of a row with n <= 40 clicks: (a, b, c; d0 .. d0+len-1)
+// for a < b < c < d, len <= min(seg, 15), packed a | b << 6 | c << 12 |
+// d0 << 18 | len << 24, ordered by decreasing length, then (b, c, d0, a), so
+// that neighbouring lanes hold consecutive a of the same (b, c, d0).
+void quad_units(int n, int seg, std::vector<int32_t> &out)
+{
+    struct U { int a, b, c, d0, len; };
+    std::vector<U> u;
+    const int sg = std::min(seg, 15);
+    for (int c = 2; c < n - 1; ++c)
+        for (int b = 1; b < c; ++b)
+            for (int a = 0; a < b; ++a)
+                for (int d0 = c + 1; d0 < n; d0 += sg) u.push_back({a, b, c, d0, std::min(sg, n - d0)});
+    std::stable_sort(u.begin(), u.end(), [](const U &x, const U &y) {
+        if (x.len != y.len) return x.len > y.len;
+        if (x.b != y.b) return x.b < y.b;
+        if (x.c != y.c) return x.c < y.c;
+        if (x.d0 != y.d0) return x.d0 < y.d0;
+        return x.a < y.a;
+    });
+    for (const U &x : u)
+        out.push_back((int32_t)((unsigned)x.a | (unsigned)x.b << 6 | (unsigned)x.c << 12 | (unsigned)x.d0 << 18 |
+                                (unsigned)x.len << 24));
+}
+
 template <class T>
 int dev_alloc(gbs_ctx *ctx, T **p, size_t count)
 {
@@ -178,18 +203,21 @@ int dev_alloc(gbs_ctx *ctx, T **p, size_t count)
 }  // namespace
 
 // (Re)build the cluster work units of a plan for its segment lengths: the
-// forward list, then the adjoint list; offsets [n] -> (offset, count) for the
-// forward at d_cluster_off, for the adjoint at d_cluster_off + 2 (max_n + 1).
+// forward list, the adjoint list, then (order 4) the quadruple list; offsets
+// [n] -> (offset, count) for the forward at d_cluster_off, for the adjoint at
+// d_cluster_off + 2 (max_n + 1), for the quadruples at d_cluster_off +
+// 4 (max_n + 1).
 int plan_units(gbs_ctx *ctx, gbs_plan *pl)
 {
     const int nm = pl->max_n;
-    std::vector<int32_t> citems, coff(4 * (nm + 1), 0);
-    for (int pass = 0; pass < 2; ++pass)
+    std::vector<int32_t> citems, coff(6 * (nm + 1), 0);
+    for (int pass = 0; pass < 3; ++pass)
         for (int n = 0; n <= nm; ++n) {
             int32_t *o = coff.data() + 2 * (nm + 1) * pass + 2 * n;
             o[0] = (int32_t)citems.size();
-            if (pl->order >= 2)
+            if (pass < 2 && pl->order >= 2)
                 cluster_units(n, pl->order, pass ? pl->seg_adj : pl->seg_fwd, pass == 1, citems);
+            if (pass == 2 && pl->order >= 4) quad_units(n, pl->seg_fwd, citems);
             o[1] = (int32_t)citems.size() - o[0];
         }
     pl->n_cluster_items = (int)citems.size();
@@ -428,11 +456,13 @@ int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
     if (!ctx || !out) return GBS_E_INVAL;
     *out = nullptr;
     if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
-    if (order < 1 || order > 3) return set_err(ctx, GBS_E_INVAL, "order must be 1, 2 or 3");
+    if (order < 1 || order > 4) return set_err(ctx, GBS_E_INVAL, "order must be 1, 2, 3 or 4");
     if (prec != GBS_PREC_FP64 && prec != GBS_PREC_MIXED)
         return set_err(ctx, GBS_E_INVAL, "prec must be GBS_PREC_FP64 or GBS_PREC_MIXED");
+    if (order == 4 && prec != GBS_PREC_FP64)
+        return set_err(ctx, GBS_E_INVAL, "order 4 runs in fp64 only");
     int rc = check_csr(ctx, P, offsets, modes, ctx->model.M,
-                       order == 3 ? GBS_MAX_N_ORDER3 : GBS_MAX_N_APPROX);
+                       order == 4 ? GBS_MAX_N_ORDER4 : order == 3 ? GBS_MAX_N_ORDER3 : GBS_MAX_N_APPROX);
     if (rc) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     gbs_plan *pl = new (std::nothrow) gbs_plan();
@@ -660,6 +690,7 @@ int gbs_plan_tune(gbs_ctx *ctx, gbs_plan *pl, int what, int32_t *params_out)
     if (!ctx || !pl) return GBS_E_INVAL;
     if (pl->ctx != ctx) return set_err(ctx, GBS_E_STATE, "plan belongs to another context");
     if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
+    if (pl->order > 3) what &= 1;  // (no gradient at order 4)
     if ((what & 2) && !ctx->model.from_params)
         return set_err(ctx, GBS_E_STATE, "tuning the gradient needs a model set by gbs_set_model");
     if (pl->P == 0 || !(what & 3)) return params_out ? gbs_plan_get_params(pl, params_out) : GBS_OK;
@@ -781,6 +812,7 @@ int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, double *logp_
         return set_err(ctx, GBS_E_STATE, "gradient needs a model set by gbs_set_model");
     if (!dl_dev || !grad_r_dev || !grad_eta_dev) return set_err(ctx, GBS_E_INVAL, "NULL device array");
     if (pl->prec != GBS_PREC_FP64) return set_err(ctx, GBS_E_INVAL, "the gradient runs in fp64 only");
+    if (pl->order > 3) return set_err(ctx, GBS_E_INVAL, "the gradient takes orders 1, 2 and 3");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     double *lp = logp_dev ? logp_dev : pl->d_logp;
     int32_t *stt = status_dev ? status_dev : pl->d_status;

@@ -314,15 +314,17 @@ __device__ __forceinline__ void fit_eval(int n, const double *ib, const double *
 {
     double zmax = -1e300;
     for (int v = 0; v < n; ++v) {
-        const double f[3] = {v * ib[0], 0.5 * v * (v - 1) * ib[1], v * (v - 1.0) * (v - 2.0) / 6.0 * ib[2]};
+        const double f[4] = {v * ib[0], 0.5 * v * (v - 1) * ib[1], v * (v - 1.0) * (v - 2.0) / 6.0 * ib[2],
+                             v * (v - 1.0) * (v - 2.0) * (v - 3.0) / 24.0 * ib[3]};
         double z = 0.0;
 #pragma unroll
         for (int t = 0; t < JP; ++t) z -= c[t] * f[t];
         zmax = fmax(zmax, z);
     }
-    double s = 0.0, e[3] = {0, 0, 0}, e2[6] = {0, 0, 0, 0, 0, 0};
+    double s = 0.0, e[4] = {0, 0, 0, 0}, e2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int v = 0; v < n; ++v) {
-        const double f[3] = {v * ib[0], 0.5 * v * (v - 1) * ib[1], v * (v - 1.0) * (v - 2.0) / 6.0 * ib[2]};
+        const double f[4] = {v * ib[0], 0.5 * v * (v - 1) * ib[1], v * (v - 1.0) * (v - 2.0) / 6.0 * ib[2],
+                             v * (v - 1.0) * (v - 2.0) * (v - 3.0) / 24.0 * ib[3]};
         double z = 0.0;
 #pragma unroll
         for (int t = 0; t < JP; ++t) z -= c[t] * f[t];
@@ -341,9 +343,9 @@ __device__ __forceinline__ void fit_eval(int n, const double *ib, const double *
     *lse = zmax + log(s);
     if (WANT_E) {
 #pragma unroll
-        for (int t = 0; t < 3; ++t) E[t] = e[t] / s;
+        for (int t = 0; t < JP; ++t) E[t] = e[t] / s;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) E2[k] = e2[k] / s;
+        for (int k = 0; k < JP * (JP + 1) / 2; ++k) E2[k] = e2[k] / s;
     }
 }
 
@@ -352,7 +354,7 @@ __device__ __forceinline__ void fit_eval(int n, const double *ib, const double *
 template <int JP>
 __device__ __forceinline__ bool fit_solve(const double *E, const double *E2, const double *r, double *x)
 {
-    double Hm[3][3];
+    double Hm[4][4];
     int k = 0;
 #pragma unroll
     for (int t = 0; t < JP; ++t)
@@ -364,7 +366,7 @@ __device__ __forceinline__ bool fit_solve(const double *E, const double *E2, con
 #pragma unroll
     for (int t = 0; t < JP; ++t) Hm[t][t] += 1e-14 * tr;
     if (!(tr > 0.0)) return false;
-    double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double L[4][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
     for (int j = 0; j < JP; ++j) {
         double d = Hm[j][j];
@@ -380,7 +382,7 @@ __device__ __forceinline__ bool fit_solve(const double *E, const double *E2, con
             L[i][j] = sv / L[j][j];
         }
     }
-    double y[3];
+    double y[4];
 #pragma unroll
     for (int i = 0; i < JP; ++i) {
         double sv = r[i];
@@ -403,15 +405,16 @@ __device__ __forceinline__ bool fit_solve(const double *E, const double *E2, con
 template <int JP>
 __device__ __forceinline__ int fit_last_point(int n, const double *m, double *logq, double *c_out)
 {
-    double ib[3] = {0, 0, 0};
+    double ib[4] = {0, 0, 0, 0};
     ib[0] = 1.0 / (n - 1.0);
     if (JP > 1) ib[1] = 2.0 / ((n - 1.0) * (n - 2.0));
     if (JP > 2) ib[2] = 6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0));
-    double c[3] = {0, 0, 0};
+    if (JP > 3) ib[3] = 24.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0) * (n - 4.0));
+    double c[4] = {0, 0, 0, 0};
     for (int it = 0; it <= FIT_MAXIT; ++it) {
-        double lse, E[3], E2[6];
+        double lse, E[4], E2[10];
         fit_eval<JP, true>(n, ib, c, &lse, E, E2);
-        double g[3] = {0, 0, 0}, mg[3] = {0, 0, 0};
+        double g[4] = {0, 0, 0, 0}, mg[4] = {0, 0, 0, 0};
         bool conv = true;
 #pragma unroll
         for (int t = 0; t < JP; ++t) {
@@ -420,10 +423,10 @@ __device__ __forceinline__ int fit_last_point(int n, const double *m, double *lo
             if (!(fabs(g[t]) <= 1e-15 + 1e-12 * fabs(m[t]))) conv = false;
         }
         // Newton step H x = -g, H the covariance of the features
-        double x[3] = {0, 0, 0};
+        double x[4] = {0, 0, 0, 0};
         if (!fit_solve<JP>(E, E2, mg, x)) return 1;
         if (conv) {
-            double cn[3] = {0, 0, 0};
+            double cn[4] = {0, 0, 0, 0};
 #pragma unroll
             for (int t = 0; t < JP; ++t) cn[t] = c[t] + x[t];
             double l2;
@@ -431,7 +434,7 @@ __device__ __forceinline__ int fit_last_point(int n, const double *m, double *lo
             *logq = -l2;
             if (c_out)
 #pragma unroll
-                for (int t = 0; t < 3; ++t) c_out[t] = cn[t];
+                for (int t = 0; t < JP; ++t) c_out[t] = cn[t];
             return 0;
         }
         double L0 = lse, slope = 0.0;
@@ -443,7 +446,7 @@ __device__ __forceinline__ int fit_last_point(int n, const double *m, double *lo
         double st = 1.0;
         if (-slope > 1e-13 * fmax(1.0, fabs(L0))) {
             while (st > 1e-12) {
-                double cn[3] = {0, 0, 0};
+                double cn[4] = {0, 0, 0, 0};
 #pragma unroll
                 for (int t = 0; t < JP; ++t) cn[t] = c[t] + st * x[t];
                 double l2;
@@ -492,37 +495,43 @@ __device__ void fft_lds(cplx *X, const cplx *W, int K)
 }
 
 
-// Result of one sector fit: log q(n), the fitted parameters and the moments
-// (zero past the ones used), how many moments were used, and bad != 0 if no
-// fit succeeded.
-struct SectorFit {
+// Result of one sector fit with at most JM moments: log q(n), the fitted
+// parameters and the moments (zero past the ones used), how many moments were
+// used, and bad != 0 if no fit succeeded.
+template <int JM>
+struct SectorFitT {
     double lq;
-    double c[3];
-    double m[3];
+    double c[JM];
+    double m[JM];
     int jr, bad;
 };
+using SectorFit = SectorFitT<3>;
 
-// Fit one sector from its tilted moments t0..t3 (t0 > 0): the moments
-// m_t = tau_t / (tau_0 C(n-1,t)) are used up to the longest feasible prefix
-// (0 < m_t < 1, decreasing in t, since 0 <= phi_{t+1} <= phi_t <= 1).  A moment
-// whose true value lies below the transform's rounding floor can come out
-// infeasible; it is then dropped, and so is the next one if the fit fails.
-// With m_1 <= 0 every clicked mode fires: q(n) = 1.  The moments arrive by
-// value and the fit runs out of line, so that callers index nothing at run time.
-__device__ __noinline__ SectorFit fit_sector(int n, int jp, double t0, double t1, double t2, double t3)
+// Fit one sector from its tilted moments t0..t4 (t0 > 0; moments past JM are
+// ignored): the moments m_t = tau_t / (tau_0 C(n-1,t)) are used up to the
+// longest feasible prefix (0 < m_t < 1, decreasing in t, since
+// 0 <= phi_{t+1} <= phi_t <= 1).  A moment whose true value lies below the
+// transform's rounding floor can come out infeasible; it is then dropped, and
+// so is the next one if the fit fails.  With m_1 <= 0 every clicked mode
+// fires: q(n) = 1.  The moments arrive by value and the fit runs out of line,
+// so that callers index nothing at run time.
+template <int JM>
+__device__ __noinline__ SectorFitT<JM> fit_sector(int n, int jp, double t0, double t1, double t2, double t3,
+                                                  double t4)
 {
-    SectorFit r;
-    const double binv[3] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
-                            6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0))};
-    const double tau[3] = {t1, t2, t3};
+    SectorFitT<JM> r;
+    const double binv[4] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
+                            6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0)),
+                            24.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0) * (n - 4.0))};
+    const double tau[4] = {t1, t2, t3, t4};
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
+    for (int t = 0; t < JM; ++t) {
         r.m[t] = t < jp ? tau[t] / t0 * binv[t] : 0.0;
         r.c[t] = 0.0;
     }
     int jr = 0;
 #pragma unroll
-    for (int t = 1; t <= 3; ++t)
+    for (int t = 1; t <= JM; ++t)
         if (jr == t - 1 && t <= jp && r.m[t - 1] > 0.0 && r.m[t - 1] < 1.0 &&
             (t == 1 || r.m[t - 1] < r.m[t - 2]))
             jr = t;
@@ -537,7 +546,8 @@ __device__ __noinline__ SectorFit fit_sector(int n, int jp, double t0, double t1
         switch (jr) {
         case 1: bad = fit_last_point<1>(n, r.m, &r.lq, r.c); break;
         case 2: bad = fit_last_point<2>(n, r.m, &r.lq, r.c); break;
-        default: bad = fit_last_point<3>(n, r.m, &r.lq, r.c); break;
+        case 3: bad = fit_last_point<JM >= 3 ? 3 : 1>(n, r.m, &r.lq, r.c); break;
+        default: bad = fit_last_point<JM >= 4 ? 4 : 1>(n, r.m, &r.lq, r.c); break;
         }
         if (bad) --jr;
     }
@@ -545,7 +555,7 @@ __device__ __noinline__ SectorFit fit_sector(int n, int jp, double t0, double t1
         bad = r.m[0] <= 0.0 ? 0 : 1;
         r.lq = 0.0;
 #pragma unroll
-        for (int t = 0; t < 3; ++t) r.c[t] = 0.0;
+        for (int t = 0; t < JM; ++t) r.c[t] = 0.0;
     }
     r.jr = jr;
     r.bad = bad;

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
         if (!(t0 >= thr) || !(t0 > 0.0)) continue;
         const double lw = log(t0) + rp.log_g_rho - kap * rp.log_rho;
         if (lw < lower + log(1e-17)) continue;
-        const SectorFit f = fit_sector(n, jp, t0, tau[j][1], tau[j][2], tau[j][3]);
+        const SectorFit f = fit_sector<3>(n, jp, t0, tau[j][1], tau[j][2], tau[j][3], 0.0);
         if (f.bad) continue;
         fits[j] = f;
         ell[j] = lw + f.lq;

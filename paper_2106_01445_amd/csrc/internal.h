@@ -13,6 +13,7 @@
 #define GBS_MAX_M 512          // modes supported by the model build
 #define GBS_MAX_N_APPROX 128   // clicks per row on the approximate path (orders 1, 2)
 #define GBS_MAX_N_ORDER3 64    // clicks per row at order 3
+#define GBS_MAX_N_ORDER4 40    // clicks per row at order 4 (the LDS-resident path only)
 #define GBS_NSMALL 40          // rows up to this many clicks keep V and M(w) in LDS (contour)
 #define GBS_RSLOTS 3           // R slots per adjoint work item of such a row (column units)
 #define GBS_MAX_N_EXACT 24     // clicks per row on the exact path

@@ -20,8 +20,8 @@ __device__ __forceinline__ int pidx(int i, int j)
     return i <= j ? j * (j + 1) / 2 + i : i * (i + 1) / 2 + j;
 }
 
-// cluster number c (singles, then pairs a < b, then triples a < b < c, each in
-// colexicographic order) -> its modes; returns the size
+// cluster number c (singles, then pairs a < b, then triples a < b < c, then
+// quadruples, each in colexicographic order) -> its modes; returns the size
 __device__ __forceinline__ int cluster_modes(int c, int n, int *m)
 {
     if (c < n) {
@@ -38,6 +38,17 @@ __device__ __forceinline__ int cluster_modes(int c, int n, int *m)
         return 2;
     }
     c -= np;
+    const int nt3 = n * (n - 1) * (n - 2) / 6;
+    int t = 4;
+    if (c >= nt3) {
+        c -= nt3;
+        int y = 3;
+        while ((y + 1) * y * (y - 1) * (y - 2) / 24 <= c) ++y;
+        c -= y * (y - 1) * (y - 2) * (y - 3) / 24;
+        m[3] = y;
+    } else {
+        t = 3;
+    }
     int z = 2;
     while ((z + 1) * z * (z - 1) / 6 <= c) ++z;
     c -= z * (z - 1) * (z - 2) / 6;
@@ -46,7 +57,7 @@ __device__ __forceinline__ int cluster_modes(int c, int n, int *m)
     m[0] = c - b * (b - 1) / 2;
     m[1] = b;
     m[2] = z;
-    return 3;
+    return t;
 }
 
 template <int ORDER>
@@ -73,6 +84,7 @@ __global__ __launch_bounds__(PLAIN_THREADS) void k_plain(const int *__restrict__
     int nc = n;
     if (ORDER >= 2) nc += n * (n - 1) / 2;
     if (ORDER >= 3) nc += n * (n - 1) * (n - 2) / 6;
+    if (ORDER >= 4) nc += n * (n - 1) * (n - 2) * (n - 3) / 24;
     const int Q = rp.K / 2 + 1;
     __syncthreads();
     for (int q = 0; q < Q; ++q) {
@@ -111,15 +123,15 @@ __global__ __launch_bounds__(PLAIN_THREADS) void k_plain(const int *__restrict__
         cplx acc[ORDER + 1];
         for (int t = 0; t <= ORDER; ++t) acc[t] = cmk(0.0, 0.0);
         for (int c = tid; c < nc; c += PLAIN_THREADS) {
-            int m[3];
+            int m[4];
             const int t = cluster_modes(c, n, m);
             const int S = 2 * t;
-            int idx[6];
+            int idx[2 * ORDER];
             for (int u = 0; u < t; ++u) {
                 idx[u] = m[u];
                 idx[t + u] = n + m[u];
             }
-            cplx L[6][6], dv[6];
+            cplx L[2 * ORDER][2 * ORDER], dv[2 * ORDER];
             cplx r = cmk(1.0, 0.0);
             for (int k = 0; k < S; ++k) {
                 cplx dk = Mp[pidx(idx[k], idx[k])];
@@ -171,6 +183,7 @@ int plain_contour(gbs_ctx *ctx, gbs_plan *pl)
     case 1: return plain_order<1>(ctx, pl);
     case 2: return plain_order<2>(ctx, pl);
     case 3: return plain_order<3>(ctx, pl);
-    default: return set_err(ctx, GBS_E_INVAL, "order must be 1, 2 or 3");
+    case 4: return plain_order<4>(ctx, pl);
+    default: return set_err(ctx, GBS_E_INVAL, "order must be 1, 2, 3 or 4");
     }
 }

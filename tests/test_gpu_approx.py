@@ -127,8 +127,10 @@ def test_frozen_plan_reuse(gpu_ctx):
     ([[1, 0]], 2),            # not ascending
     ([[2, 2]], 2),            # duplicate
     ([[0, 199]], 2),          # out of range
-    ([[0, 1]], 4),            # order outside 1..3
+    ([[0, 1]], 5),            # order outside 1..4
+    ([[0, 1]], 0),
     ([list(range(65))], 3),   # more clicks than order 3 supports
+    ([list(range(41))], 4),   # more clicks than order 4 supports
     ([list(range(129))], 2),  # more clicks than supported
 ])
 def test_argument_errors(gpu_ctx, rows, order):
