@@ -191,6 +191,58 @@ def plain_leg(ctx, wl, tuned_logp, tuned_fwd_kernel_ms):
             "max_abs_dlogp_vs_tuned": float(np.max(np.abs(out["logp"] - tuned_logp)))}
 
 
+def order4_leg(ctx, torch):
+    """The paper's fourth-order scheme (forward) on the same 70-mode batch:
+    quadruple clusters and four-moment fits, launch choices tuned first; one
+    timed pass (model build + forward) after a warm-up, device timings per
+    kernel group, subset determinants per second, and the two rows with the
+    fewest clicks against the oracle."""
+    from workloads import make_workload, csr_rows
+    from oracle import approx, model
+    wl = make_workload(3)
+    dev = torch.device("cuda:0")
+    ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    ure = torch.tensor(np.ascontiguousarray(wl.U.real), device=dev)
+    uim = torch.tensor(np.ascontiguousarray(wl.U.imag), device=dev)
+    r = torch.tensor(wl.r, device=dev)
+    eta = torch.tensor(wl.eta, device=dev)
+    logp = torch.empty(wl.P, dtype=torch.float64, device=dev)
+    st = torch.empty(wl.P, dtype=torch.int32, device=dev)
+    plan = ctx.gbs_plan_create(wl.offsets, wl.modes, 4)
+    prm = plan.tune(1)
+
+    def fn():
+        ctx.gbs_set_model_dev(ure, uim, r, eta)
+        ctx.gbs_prob_approx_dev(plan, logp, st)
+    fn()
+    torch.cuda.synchronize()
+    ctx.gbs_timing()
+    ctx.gbs_set_timing(True)
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    tim = ctx.gbs_timing()
+    ctx.gbs_set_timing(False)
+    ns = np.diff(wl.offsets)
+    npts = (plan.info()["K"] // 2 + 1).astype(np.float64)
+    dets = float(sum(npts[i] * sum(comb(int(ns[i]), t) for t in range(1, 5)) for i in range(wl.P)))
+    lp = logp.cpu().numpy()
+    Q = model.q_matrix(model.covariance(wl.U, wl.r, wl.eta))
+    rows = csr_rows(wl.offsets, wl.modes)
+    idx = [int(i) for i in np.argsort(ns, kind="stable")[:2]]
+    err = max(abs(lp[i] - approx.prob_approx(Q, list(rows[i]), 4)) for i in idx)
+    plan.close()
+    km = {k: round(v[0], 3) for k, v in tim.items() if v[1]}
+    return {"workload": "m70_order4", "modes": wl.M, "patterns": wl.P, "order": 4,
+            "clicks": f"{int(ns.min())}-{int(ns.max())}", "pass": "model build + forward",
+            "ms": ms, "probs_per_s": wl.P / (ms * 1e-3), "subset_dets_per_s": dets / (ms * 1e-3),
+            "status_nonzero": int((st != 0).sum().item()), "kernel_ms": km,
+            "tuned_params": {"seg_forward": int(prm[0]), "points_per_item": int(prm[2]),
+                             "points_per_pass": int(prm[3])},
+            "max_abs_dlogp_vs_oracle_2_rows": float(err)}
+
+
 def source_sha(paths):
     import hashlib
     h = hashlib.sha256()
@@ -222,6 +274,7 @@ def main():
     ap.add_argument("--no-exact", action="store_true", help="skip the 20-mode exact leg")
     ap.add_argument("--no-big", action="store_true", help="skip the 100- and 144-mode legs")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain comparison kernel")
+    ap.add_argument("--no-order4", action="store_true", help="skip the fourth-order leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch choices")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 3 times (calibrates the "
@@ -370,6 +423,8 @@ def main():
     if not args.no_plain:
         fwd_kernel_ms = sum(v[0] / max(1, v[1]) for k, v in tim_fwd.items() if v[1] and k != "model")
         out["plain_forward"] = plain_leg(ctx, wl, lp, fwd_kernel_ms)
+    if not args.no_order4:
+        out["m70_order4"] = order4_leg(ctx, torch)
     if not args.no_exact:
         out["exact_m20"] = exact_leg(ctx)
     if not args.no_big:
