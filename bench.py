@@ -243,6 +243,31 @@ def order4_leg(ctx, torch):
             "max_abs_dlogp_vs_oracle_2_rows": float(err)}
 
 
+def accuracy_leg(ctx):
+    """The accuracy study of the paper's Numerical accuracy paragraph (Fig. 4)
+    on synthetic Haar interferometers: the relative deviation
+    Delta_p = |p_hat - p| / p of the order-2, -3 and -4 estimates from the exact
+    (double-double) probability, mean and standard deviation over 100 random
+    outcomes per point: against the number of modes (r = 1.6, 18 clicks,
+    m = 26, 36, 54) and against the squeezing (30 modes, 20 clicks)."""
+    from workloads import accuracy_workload
+    pts = [(m, 1.6, 18) for m in (26, 36, 54)] + [(30, r, 20) for r in (0.8, 1.2, 1.6, 2.0)]
+    res = []
+    t0 = time.perf_counter()
+    for m, r, n in pts:
+        wl = accuracy_workload(m, r, n)
+        ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+        ex = ctx.gbs_prob_exact(wl.offsets, wl.modes)
+        rec = {"modes": m, "r": r, "clicks": n, "outcomes": wl.P,
+               "exact_status_nonzero": int(np.sum(ex["status"] != 0))}
+        for order in (2, 3, 4):
+            ap = ctx.gbs_prob_approx(wl.offsets, wl.modes, order)
+            d = np.abs(np.expm1(ap["logp"] - ex["logp"]))
+            rec[f"order{order}"] = {"mean_delta_p": float(d.mean()), "std_delta_p": float(d.std())}
+        res.append(rec)
+    return {"points": res, "s": time.perf_counter() - t0}
+
+
 def source_sha(paths):
     import hashlib
     h = hashlib.sha256()
@@ -275,6 +300,7 @@ def main():
     ap.add_argument("--no-big", action="store_true", help="skip the 100- and 144-mode legs")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain comparison kernel")
     ap.add_argument("--no-order4", action="store_true", help="skip the fourth-order leg")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy-study leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch choices")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 3 times (calibrates the "
@@ -425,6 +451,8 @@ def main():
         out["plain_forward"] = plain_leg(ctx, wl, lp, fwd_kernel_ms)
     if not args.no_order4:
         out["m70_order4"] = order4_leg(ctx, torch)
+    if not args.no_accuracy:
+        out["accuracy_study"] = accuracy_leg(ctx)
     if not args.no_exact:
         out["exact_m20"] = exact_leg(ctx)
     if not args.no_big:

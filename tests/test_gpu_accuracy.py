@@ -1,0 +1,38 @@
+"""Accuracy-study workload (the paper's Numerical accuracy paragraph, Fig. 4):
+the exact double-double probability on the GPU against the binary128 oracle
+at 18 clicks, and the ordering of the estimates' deviations from it."""
+import numpy as np
+import pytest
+
+from oracle import exact128
+from workloads import accuracy_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def test_exact_18_clicks_matches_binary128(gpu_ctx):
+    """26 modes, r = 1.6 on every second input, lossless, 18 clicks: the
+    inclusion-exclusion sum cancels by kappa ~ 1e9, which double-double absorbs."""
+    wl = accuracy_workload(26, 1.6, 18, P=1)
+    gpu_ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    ex = gpu_ctx.gbs_prob_exact(wl.offsets, wl.modes)
+    assert ex["status"][0] == 0
+    ref = exact128.exact(wl.M, wl.U, wl.r, wl.eta, wl.offsets, wl.modes)
+    assert ref["kappa"][0] > 1e6
+    assert abs(ex["logp"][0] - ref["logp"][0]) < 1e-12
+
+
+def test_fourth_order_is_the_most_accurate(gpu_ctx):
+    """Results, Approximation scheme and Fig. 4: the mean relative deviation
+    from the exact probability falls with the order of the scheme (16 outcomes
+    of the 26-mode, r = 1.6, 18-click point)."""
+    wl = accuracy_workload(26, 1.6, 18, P=16)
+    gpu_ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    ex = gpu_ctx.gbs_prob_exact(wl.offsets, wl.modes)
+    assert np.all(ex["status"] == 0)
+    dev = {}
+    for order in (2, 3, 4):
+        ap = gpu_ctx.gbs_prob_approx(wl.offsets, wl.modes, order)
+        assert np.all(ap["status"] == 0)
+        dev[order] = float(np.mean(np.abs(np.expm1(ap["logp"] - ex["logp"]))))
+    assert dev[4] < dev[3] < dev[2]

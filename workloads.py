@@ -141,6 +141,22 @@ def make_workload(config: int, P: Optional[int] = None) -> Workload:
     return wl
 
 
+def accuracy_workload(M: int, r: float, n: int, P: int = 100) -> Workload:
+    """Accuracy-study setup of the paper's Numerical accuracy paragraph (Fig. 4):
+    a lossless M-mode Haar interferometer with every second input squeezed at
+    r, and P random outcomes with n clicked detectors (stream [SEED_ROOT, 97,
+    M, round(100 r), n, s])."""
+    tag = [97, M, int(round(100 * r)), n]
+    U = haar_unitary(M, np.random.default_rng([SEED_ROOT, *tag, S_U]))
+    rr = np.zeros(M)
+    rr[::2] = r
+    offsets, modes = random_patterns(M, P, n, n, np.random.default_rng([SEED_ROOT, *tag, S_PAT]))
+    return Workload(name=f"acc_m{M}_r{r:g}_n{n}", config=0, M=M, U=U, r=rr, eta=np.ones(M),
+                    offsets=offsets, modes=modes, order=4, exact=True,
+                    description=f"{M} modes, r = {r:g} on every second input, eta = 1, "
+                                f"{P} outcomes with {n} clicks; exact and orders 2-4")
+
+
 def small_model(M: int, seed: int, n_squeezed: Optional[int] = None,
                 r_range=(0.5, 1.5), eta_range=(0.3, 1.0)):
     """A small random lossy model for pins and edge cases."""
