@@ -23,7 +23,7 @@ from typing import Dict, Sequence
 import numpy as np
 
 from .exact import conditional_W
-from .fit import maxent_last_point, moment_targets
+from .fit import maxent_curve, maxent_last_point, moment_targets
 from .model import vacuum_prob
 from .sectors import cluster_moments, cluster_sector_weights
 
@@ -82,3 +82,48 @@ def sector_estimates(Q: np.ndarray, C: Sequence[int], order: int, L: int) -> Dic
     """log p_hat_kappa for each sector kappa >= n (diagnostics)."""
     _, det = prob_approx(Q, C, order, L0=L, return_detail=True)
     return det["terms"]
+
+
+def click_distribution(Q: np.ndarray, order: int, ks=(), L0: int = 0):
+    """Order-j estimate of the whole device's click distribution (Results,
+    Calculation of p(n) and of sectors p_k(n); Approximation scheme): with
+    C = every mode (no conditioning, P_vac of the empty set is 1), the cluster
+    moments S_t[k] (t <= j) give each photon-number sector k its moments;
+    the exp-polynomial fitted to them on the sector's support n' = 1..min(k, M)
+    is its curve p_k(n') / S_0[k]; p(n') = sum_k p_k(n'), p(0) = S_0[0].
+    Returns (p[0..M], {k: p_k[0..M]} for k in ks, detail)."""
+    M = Q.shape[0] // 2
+    W = Q
+    jp = min(order, M - 1)
+    L = max(L0, 4 * M + 64)
+    while True:
+        S = cluster_moments(W, jp, L)
+        S0abs = cluster_sector_weights(W, [()], L, absolute=True)[0]
+        a = max(S[0, L - 2], 0.0) + max(S[0, L - 1], 0.0)
+        b = max(S[0, L - 4], 0.0) + max(S[0, L - 3], 0.0)
+        r = a / b if b > 0 else 1.0
+        tail = a * r / (1.0 - r) if r < 1 else np.inf
+        if tail <= 1e-15 * S[0].sum() or L >= 8192:
+            break
+        L *= 2
+    p = np.zeros(M + 1)
+    p[0] = S[0, 0]
+    curves = {k: np.zeros(M + 1) for k in ks}
+    if 0 in curves:
+        curves[0][0] = S[0, 0]
+    nfail = 0
+    for k in range(1, L):
+        if not S[0, k] > 1e-10 * S0abs[k]:
+            continue
+        s = min(k, M)
+        j = min(jp, s - 1)
+        m = moment_targets(S[:, k], M, j)
+        lq, ok = maxent_curve(m, M, s)
+        if not ok:
+            nfail += 1
+            continue
+        pk = S[0, k] * np.exp(lq)
+        p[1:s + 1] += pk
+        if k in curves:
+            curves[k][1:s + 1] = pk
+    return p, curves, dict(L=L, nfail=nfail, S0_sum=float(S[0].sum()))

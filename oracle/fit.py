@@ -86,6 +86,57 @@ def maxent_last_point(m: np.ndarray, n: int, maxit: int = FIT_MAXIT) -> Tuple[fl
     return float("nan"), False, maxit
 
 
+def maxent_curve(m: np.ndarray, n: int, s: int, maxit: int = FIT_MAXIT) -> Tuple[np.ndarray, bool]:
+    """The same fit on the support n' = 1..s (s <= n; a sector of k photons
+    clicks at most k detectors, so s = min(k, n)), with the basis phi_t of the
+    full n (the moments m_t are the same S_t / (S_0 C(n-1, t))); returns
+    (log q(n') for n' = 1..s, converged).  jp = len(m) <= s - 1."""
+    jp = len(m)
+    if s == 1 or jp == 0:
+        out = np.full(s, -np.inf)
+        out[0 if s == 1 else s - 1] = 0.0
+        if s > 1:              # no moment: the uniform curve on the support
+            out[:] = -np.log(s)
+        return out, True
+    phi = basis(n, jp)[:, :s]
+    c = np.zeros(jp)
+
+    def dual(cc):
+        return _lse(-cc @ phi) + cc @ m
+
+    for it in range(maxit + 1):
+        z = -c @ phi
+        lse = _lse(z)
+        prob = np.exp(z - lse)
+        E = phi @ prob
+        g = m - E
+        H = (phi * prob) @ phi.T - np.outer(E, E)
+        H = H + 1e-14 * np.trace(H) * np.eye(jp)
+        if np.all(np.abs(g) <= 1e-15 + 1e-12 * np.abs(m)):
+            try:
+                c = c + np.linalg.solve(H, -g)
+            except np.linalg.LinAlgError:
+                pass
+            z = -c @ phi
+            return z - _lse(z), True
+        if it == maxit:
+            break
+        try:
+            step = np.linalg.solve(H, -g)
+        except np.linalg.LinAlgError:
+            step = np.linalg.lstsq(H, -g, rcond=None)[0]
+        L0 = lse + c @ m
+        slope = g @ step
+        t = 1.0
+        if -slope > 1e-13 * max(1.0, abs(L0)):
+            while t > 1e-12:
+                if dual(c + t * step) <= L0 + 1e-4 * t * slope:
+                    break
+                t *= 0.5
+        c = c + t * step
+    return np.full(s, np.nan), False
+
+
 def moment_targets(S_col: np.ndarray, n: int, jp: int) -> np.ndarray:
     """m_t = S_t / (S_0 C(n-1, t)), t = 1..jp, for one sector column S_col [>= jp+1]."""
     return np.array([S_col[t] / (S_col[0] * comb(n - 1, t)) for t in range(1, jp + 1)])

@@ -312,3 +312,33 @@ def test_central_fd_on_closed_form():
 def test_haar_unitary_is_unitary():
     U = haar_unitary(12, np.random.default_rng(3))
     assert np.allclose(U @ U.conj().T, np.eye(12), atol=1e-13)
+
+
+# ---------------------------------------------------------------- whole-device p(n)
+@pytest.mark.parametrize("M,order", [(4, 3), (5, 4)])
+def test_click_distribution_order_m_minus_1_is_exact(M, order):
+    """Results, Calculation of p(n) and of sectors p_k(n): with C = every mode,
+    j = M-1 moments fix every sector's curve on its support, so the estimated
+    p(n) equals the brute-force sum of exact pattern probabilities."""
+    import itertools
+    U, r, eta = small_model(M, 31)
+    Q = model.q_matrix(model.covariance(U, r, eta))
+    p, _, _ = approx.click_distribution(Q, order)
+    pb = np.zeros(M + 1)
+    for bits in itertools.product([0, 1], repeat=M):
+        C = [i for i in range(M) if bits[i]]
+        pb[len(C)] += exact.prob_exact_direct(Q, C)[0] if C else model.vacuum_prob(Q, list(range(M)))
+    assert np.max(np.abs(p - pb)) < 1e-13
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_click_distribution_norm_and_mean(order):
+    """Every order: the sectors' weights sum to 1 and each fit matches its first
+    moment, so sum_n p(n) = 1 and sum_n n p(n) = sum_l (1 - P_vac(l)) (Methods,
+    Moments calculation) hold exactly."""
+    U, r, eta = small_model(8, 32)
+    Q = model.q_matrix(model.covariance(U, r, eta))
+    p, _, _ = approx.click_distribution(Q, order)
+    assert p.sum() == pytest.approx(1.0, abs=1e-12)
+    mean = sum(1.0 - model.vacuum_prob(Q, [l]) for l in range(8))
+    assert float(np.arange(9) @ p) == pytest.approx(mean, abs=1e-10)
