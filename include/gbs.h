@@ -161,6 +161,27 @@ int gbs_prob_approx_plain(gbs_ctx *ctx, int P, const int32_t *offsets, const int
                           int order, int prec, double *logp, int32_t *status);
 
 /*
+ * gbs_click_distribution: the order-j estimate (1 <= order <= 4) of the whole
+ * device's click distribution p(n), n = 0..M, the probability that exactly n
+ * of the M detectors click, and of its photon-number sector curves p_k(n)
+ * (Results, Calculation of p(n) and of sectors p_k(n); Fig. 2).  The steps of
+ * gbs_prob_approx with C = every mode (no conditioning): the sector moments
+ * from clusters of <= j modes, and per sector k an exp-polynomial fitted on its
+ * support n = 1..min(k, M) (k photons click at most k detectors), whose whole
+ * curve is kept: p_k(n) = S_0[k] q_k(n), p(n) = sum_k p_k(n), p(0) = S_0[0].
+ * The contour runs at radius 1 (capped at 0.98 of the convergence radius), so
+ * every sector comes at its own weight with rounding ~1e-16 of the largest;
+ * sectors below 1e-14 of the largest are left out.  The values are therefore
+ * accurate in absolute terms (~1e-10), not relative to tiny p(n).
+ * M <= 40 modes, fp64.  ks[nk]: the sectors whose curves are wanted (host);
+ * outputs (host): p_n[M+1], p_k[nk][M+1] (row i for ks[i]; zero for a sector
+ * outside the contour's range), status[1] (GBS_PS_FIT_NOCONV if fits carrying
+ * more than 1e-10 of the weight failed; the call then returns GBS_W_PATTERN).
+ */
+int gbs_click_distribution(gbs_ctx *ctx, int order, int nk, const int32_t *ks, double *p_n, double *p_k,
+                           int32_t *status);
+
+/*
  * Plans: the per-batch layout (rows sorted by cost, device copies of the CSR,
  * workspace) built once and reused.  gbs_plan_create copies the host CSR.
  * The plan holds the contour radius and size per row from the first run on;

@@ -510,7 +510,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
         const double lw = log(t0) + rp.log_g_rho - kap * rp.log_rho;
         if (lw < lower + log(1e-17)) continue;
         const SectorFitT<ORDER >= 4 ? 4 : 3> f =
-            fit_sector<ORDER >= 4 ? 4 : 3>(n, jp, t0, tau[j][1], tau[j][2], tau[j][3], ORDER >= 4 ? tau[j][NT - 1] : 0.0);
+            fit_sector<ORDER >= 4 ? 4 : 3>(n, 0, jp, t0, tau[j][1], tau[j][2], tau[j][3], ORDER >= 4 ? tau[j][NT - 1] : 0.0);
         if (f.bad) {
             lse_add(um, us, lw);
         } else {
@@ -538,6 +538,135 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
         if (status) status[p] = stt;
         rows[p].nsec = (int)ns;
     }
+}
+
+// ---------------------------------------------------------------------------
+// k_dist_fit: the whole device's click distribution (one row, C = every mode,
+// n = M): per sector k (0 <= k < K) the tilted moments by the FFT, the
+// exp-polynomial fitted on the sector's support n' = 1..min(k, n) (k photons
+// click at most k detectors; k = 0 is the vacuum, n' = 0), and its whole curve:
+// p_k(n') = S_0[k] q_k(n'), p(n') = sum_k p_k(n') (LDS accumulators, one block).
+// Sectors below the transform's noise floor (1e-14 of the largest tilted
+// weight) are left out; a sector whose fit fails sets GBS_PS_FIT_NOCONV when
+// its weight exceeds 1e-10 of the total.
+// ---------------------------------------------------------------------------
+template <int ORDER>
+__global__ __launch_bounds__(FIT_THREADS) void k_dist_fit(const int *__restrict__ offsets,
+                                                          const RowPlan *__restrict__ rows,
+                                                          const cplx *__restrict__ sw, int nk,
+                                                          const int *__restrict__ ks, double *__restrict__ p_n,
+                                                          double *__restrict__ p_k, int *__restrict__ status)
+{
+    extern __shared__ double sh[];
+    __shared__ double red[FIT_THREADS];
+    __shared__ double pacc[2 * GBS_NSMALL + 2];
+    __shared__ double s_fail;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int n = offsets[1] - offsets[0];
+    const RowPlan rp = rows[0];
+    for (int i = tid; i <= n; i += nt) pacc[i] = 0.0;
+    for (int i = tid; i < nk * (n + 1); i += nt) p_k[i] = 0.0;
+    if (tid == 0) s_fail = 0.0;
+    if (n == 0 || rp.status != 0) {
+        for (int i = tid; i <= n; i += nt) p_n[i] = n == 0 ? 1.0 : NAN;
+        if (tid == 0) *status = rp.status;
+        return;
+    }
+    const int K = rp.K, Q = K / 2 + 1, jp = min(ORDER, n - 1);
+    int lg = 0;
+    while ((1 << lg) < K) ++lg;
+    cplx *X = (cplx *)sh;
+    cplx *W = X + K;
+    for (int m = tid; m < K / 2; m += nt) {
+        double sn, cs;
+        sincospi(-2.0 * (double)m / (double)K, &sn, &cs);
+        W[m] = cmk(cs, sn);
+    }
+    constexpr int NT = ORDER >= 4 ? 5 : 4;
+    double tau[FIT_KPT][NT];
+    const double invK = 1.0 / K;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        if (t <= ORDER && t <= jp) {
+            const cplx *src = sw + (long)t * GBS_QCAP;  // (the row's planes: row 0)
+            for (int q = tid; q < K; q += nt) {
+                const cplx v = q < Q ? src[q] : cmk(src[K - q].re, -src[K - q].im);
+                X[(int)(__brev((unsigned)q) >> (32 - lg))] = v;
+            }
+            __syncthreads();
+            fft_lds(X, W, K);
+#pragma unroll
+            for (int j = 0; j < FIT_KPT; ++j) {
+                const int kap = tid + nt * j;
+                tau[j][t] = kap < K ? X[kap].re * invK : 0.0;
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int j = 0; j < FIT_KPT; ++j) tau[j][t] = 0.0;
+        }
+    }
+    double tmax = 0.0;
+#pragma unroll
+    for (int j = 0; j < FIT_KPT; ++j)
+        if (tid + nt * j < K) tmax = fmax(tmax, tau[j][0]);
+    tmax = block_max(tmax, red);
+    const double thr = 1e-14 * tmax;
+    const double binv[4] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
+                            6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0)),
+                            24.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0) * (n - 4.0))};
+#pragma unroll
+    for (int j = 0; j < FIT_KPT; ++j) {
+        const int kap = tid + nt * j;
+        if (kap >= K) continue;
+        const double t0 = tau[j][0];
+        if (!(t0 >= thr) || !(t0 > 0.0)) continue;
+        const double w0 = exp(log(t0) + rp.log_pvac + rp.log_g_rho - kap * rp.log_rho);  // S_0[k]
+        int slot = -1;
+        for (int i = 0; i < nk; ++i)
+            if (ks[i] == kap) slot = i;
+        if (kap == 0) {
+            atomicAdd(&pacc[0], w0);
+            if (slot >= 0) p_k[slot * (n + 1)] = w0;
+            continue;
+        }
+        const int s = min(kap, n), v0 = n - s;
+        if (s == 1) {
+            atomicAdd(&pacc[1], w0);
+            if (slot >= 0) p_k[slot * (n + 1) + 1] = w0;
+            continue;
+        }
+        const SectorFitT<ORDER >= 4 ? 4 : 3> f = fit_sector<ORDER >= 4 ? 4 : 3>(
+            n, v0, min(jp, s - 1), t0, tau[j][1], tau[j][2], tau[j][3], ORDER >= 4 ? tau[j][NT - 1] : 0.0);
+        if (f.bad) {
+            atomicAdd(&s_fail, w0);
+            continue;
+        }
+        if (f.jr == 0) {
+            // no usable moment (m_1 <= 0): every detector the sector can reach fires
+            atomicAdd(&pacc[s], w0);
+            if (slot >= 0) p_k[slot * (n + 1) + s] = w0;
+            continue;
+        }
+        // q(n') = exp(lq - c . phi(v)), v = n - n' (lq = minus the log-partition sum)
+        for (int v = v0; v < n; ++v) {
+            const double ph[4] = {v * binv[0], 0.5 * v * (v - 1.0) * binv[1],
+                                  v * (v - 1.0) * (v - 2.0) / 6.0 * binv[2],
+                                  v * (v - 1.0) * (v - 2.0) * (v - 3.0) / 24.0 * binv[3]};
+            double z = f.lq;
+#pragma unroll
+            for (int t = 0; t < (ORDER >= 4 ? 4 : 3); ++t)
+                if (t < f.jr) z -= f.c[t] * ph[t];
+            const double pv = w0 * exp(z);
+            atomicAdd(&pacc[n - v], pv);
+            if (slot >= 0) p_k[slot * (n + 1) + n - v] = pv;
+        }
+    }
+    __syncthreads();
+    double tot = 0.0;
+    for (int i = 0; i <= n; ++i) tot += pacc[i];
+    for (int i = tid; i <= n; i += nt) p_n[i] = pacc[i];
+    if (tid == 0) *status = s_fail > 1e-10 * tot ? GBS_PS_FIT_NOCONV : 0;
 }
 
 template <int ORDER, bool BIG, class C>
@@ -647,6 +776,24 @@ int launch_order4(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
     return 0;
 }
 
+// The whole device's click distribution: the plan's single row is every mode.
+template <int ORDER>
+int dist_order(gbs_ctx *ctx, gbs_plan *pl, int nk, const int *ks, double *p_n, double *p_k, int32_t *status)
+{
+    hipStream_t st = ctx->stream;
+    int rc = eig_rows(ctx, pl);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, st, pl->P, 0, pl->qchunk, pl->d_offsets, pl->d_perm,
+                       pl->d_rows, pl->d_items, pl->d_counter);
+    if ((rc = launch_contour<ORDER, false, cplx>(ctx, pl, pl->max_n_small))) return rc;
+    size_t lds_f = sizeof(cplx) * (GBS_KMAX + GBS_KMAX / 2);
+    if ((rc = func_lds_limit(ctx, (const void *)k_dist_fit<ORDER>, (int)lds_f))) return rc;
+    hipLaunchKernelGGL(k_dist_fit<ORDER>, dim3(1), dim3(FIT_THREADS), lds_f, st, pl->d_offsets, pl->d_rows,
+                       pl->d_sw, nk, ks, p_n, p_k, status);
+    HIP_TRY(ctx, hipGetLastError());
+    return 0;
+}
+
 // The plain comparison kernel (plain.hip) in place of the contour kernels.
 
 template <int ORDER>
@@ -693,5 +840,18 @@ int approx_forward(gbs_ctx *ctx, gbs_plan *pl, double *logp_dev, int32_t *status
     case 3: return launch_order<3>(ctx, pl, logp_dev, status_dev);
     case 4: return launch_order4(ctx, pl, logp_dev, status_dev);
     default: return set_err(ctx, -1, "order must be 1, 2, 3 or 4");
+    }
+}
+
+int click_distribution_run(gbs_ctx *ctx, gbs_plan *pl, int nk, const int *ks_dev, double *pn_dev, double *pk_dev,
+                           int32_t *status_dev)
+{
+    if (pl->P != 1 || pl->nbig > 0) return set_err(ctx, GBS_E_INVAL, "one row of at most 40 modes");
+    switch (pl->order) {
+    case 1: return dist_order<1>(ctx, pl, nk, ks_dev, pn_dev, pk_dev, status_dev);
+    case 2: return dist_order<2>(ctx, pl, nk, ks_dev, pn_dev, pk_dev, status_dev);
+    case 3: return dist_order<3>(ctx, pl, nk, ks_dev, pn_dev, pk_dev, status_dev);
+    case 4: return dist_order<4>(ctx, pl, nk, ks_dev, pn_dev, pk_dev, status_dev);
+    default: return set_err(ctx, GBS_E_INVAL, "order must be 1, 2, 3 or 4");
     }
 }

@@ -822,6 +822,50 @@ int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, double *logp_
     return approx_backward(ctx, pl, dl_dev, stt, grad_r_dev, grad_eta_dev);
 }
 
+int gbs_click_distribution(gbs_ctx *ctx, int order, int nk, const int32_t *ks, double *p_n, double *p_k,
+                           int32_t *status)
+{
+    if (!ctx) return GBS_E_INVAL;
+    if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
+    const int M = ctx->model.M;
+    if (M > GBS_NSMALL) return set_err(ctx, GBS_E_INVAL, "the click distribution takes at most 40 modes");
+    if (nk < 0 || (nk > 0 && (!ks || !p_k)) || !p_n || !status)
+        return set_err(ctx, GBS_E_INVAL, "NULL or negative argument");
+    std::vector<int32_t> off = {0, M}, mod(M);
+    std::iota(mod.begin(), mod.end(), 0);
+    gbs_plan *pl = nullptr;
+    int rc = gbs_plan_create(ctx, 1, off.data(), mod.data(), order, GBS_PREC_FP64, &pl);
+    if (rc) return rc;
+    pl->whole = true;
+    int *dks = nullptr;
+    double *dpn = nullptr, *dpk = nullptr;
+    int32_t *dst = nullptr;
+    rc = dev_alloc(ctx, &dks, nk > 0 ? nk : 1);
+    if (!rc) rc = dev_alloc(ctx, &dpn, M + 1);
+    if (!rc) rc = dev_alloc(ctx, &dpk, nk > 0 ? (size_t)nk * (M + 1) : 1);
+    if (!rc) rc = dev_alloc(ctx, &dst, 1);
+    hipStream_t st = ctx->stream;
+    if (!rc && nk > 0 &&
+        hipMemcpyAsync(dks, ks, nk * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = set_err(ctx, GBS_E_HIP, "copy of ks failed");
+    if (!rc) rc = click_distribution_run(ctx, pl, nk, dks, dpn, dpk, dst);
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(p_n, dpn, (M + 1) * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && nk > 0)
+            e = hipMemcpyAsync(p_k, dpk, (size_t)nk * (M + 1) * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(status, dst, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = set_err(ctx, GBS_E_HIP, hipGetErrorString(e));
+    }
+    if (dks) (void)hipFree(dks);
+    if (dpn) (void)hipFree(dpn);
+    if (dpk) (void)hipFree(dpk);
+    if (dst) (void)hipFree(dst);
+    gbs_plan_destroy(pl);
+    if (rc) return rc;
+    return *status != 0 ? GBS_W_PATTERN : GBS_OK;
+}
+
 int gbs_grad(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int order, int prec,
              const double *dL_dlogp, double *logp, double *grad_r, double *grad_eta, int32_t *status)
 {

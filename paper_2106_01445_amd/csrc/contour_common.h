@@ -114,7 +114,7 @@ __host__ __device__ __forceinline__ int cont_fixed() { return 16 * (CONT_THREADS
 // factor (rho/R_b)^K is below 1e-16, at most GBS_KMAX); then log G_0(rho).
 __device__ __forceinline__ void row_plan(RowPlan &rp, int n, const double *alpha, int astride,
                                          double logdetQ, double logdetA, double amin, double dev,
-                                         bool nonpd, int frozen)
+                                         bool nonpd, int frozen, bool whole = false)
 {
     const int N = 2 * n;
     rp.status = 0;
@@ -135,14 +135,18 @@ __device__ __forceinline__ void row_plan(RowPlan &rp, int n, const double *alpha
             }
             return s;
         };
+        // the tilted mean photon number is set to n (the sectors of a click
+        // pattern of n detectors), or, for the whole distribution, to the
+        // untilted mean: rho = 1, every sector at its own weight
+        const double target = whole ? mfun(1.0) : (double)n;
         double rho;
         if (dev < 1e-300) rho = 1.0;
-        else if (mfun(hi) <= (double)n) rho = hi;
+        else if (mfun(hi) <= target) rho = hi;
         else {
             double lo = 0.0;
             for (int it = 0; it < 200; ++it) {
                 const double mid = 0.5 * (lo + hi);
-                if (mfun(mid) < (double)n) lo = mid;
+                if (mfun(mid) < target) lo = mid;
                 else hi = mid;
             }
             rho = 0.5 * (lo + hi);
@@ -304,16 +308,16 @@ __device__ __forceinline__ SlotMT<C> slot_view(cplx *base, int n)
     return m;
 }
 
-// Log-partition sum of the exp-polynomial on n' = 1..n (v = n - n' empty modes,
+// Log-partition sum of the exp-polynomial on n' = 1..n - v0 (v = n - n' empty modes,
 // basis phi_t = C(v, t) ib[t]) and, with WANT_E, the mean E[phi] and the
 // second moments E2 (upper triangle, row-major) of its JP features.  JP is a
 // template argument so that every array index is static (kept in registers).
 template <int JP, bool WANT_E>
-__device__ __forceinline__ void fit_eval(int n, const double *ib, const double *c, double *lse,
+__device__ __forceinline__ void fit_eval(int n, int v0, const double *ib, const double *c, double *lse,
                                          double *E, double *E2)
 {
     double zmax = -1e300;
-    for (int v = 0; v < n; ++v) {
+    for (int v = v0; v < n; ++v) {
         const double f[4] = {v * ib[0], 0.5 * v * (v - 1) * ib[1], v * (v - 1.0) * (v - 2.0) / 6.0 * ib[2],
                              v * (v - 1.0) * (v - 2.0) * (v - 3.0) / 24.0 * ib[3]};
         double z = 0.0;
@@ -322,7 +326,7 @@ __device__ __forceinline__ void fit_eval(int n, const double *ib, const double *
         zmax = fmax(zmax, z);
     }
     double s = 0.0, e[4] = {0, 0, 0, 0}, e2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int v = 0; v < n; ++v) {
+    for (int v = v0; v < n; ++v) {
         const double f[4] = {v * ib[0], 0.5 * v * (v - 1) * ib[1], v * (v - 1.0) * (v - 2.0) / 6.0 * ib[2],
                              v * (v - 1.0) * (v - 2.0) * (v - 3.0) / 24.0 * ib[3]};
         double z = 0.0;
@@ -400,10 +404,11 @@ __device__ __forceinline__ bool fit_solve(const double *E, const double *E2, con
     return true;
 }
 
-// Max-entropy fit on n' = 1..n (v = n - n' empty modes) of the JP moments m[];
-// returns 0 and log q(n) (and the parameters in c_out) on success.
+// Max-entropy fit on n' = 1..n - v0 (v = n - n' empty modes, v >= v0) of the JP
+// moments m[]; returns 0, minus the log-partition sum (log q(n) when v0 = 0)
+// and the parameters in c_out on success.
 template <int JP>
-__device__ __forceinline__ int fit_last_point(int n, const double *m, double *logq, double *c_out)
+__device__ __forceinline__ int fit_last_point(int n, int v0, const double *m, double *logq, double *c_out)
 {
     double ib[4] = {0, 0, 0, 0};
     ib[0] = 1.0 / (n - 1.0);
@@ -413,7 +418,7 @@ __device__ __forceinline__ int fit_last_point(int n, const double *m, double *lo
     double c[4] = {0, 0, 0, 0};
     for (int it = 0; it <= FIT_MAXIT; ++it) {
         double lse, E[4], E2[10];
-        fit_eval<JP, true>(n, ib, c, &lse, E, E2);
+        fit_eval<JP, true>(n, v0, ib, c, &lse, E, E2);
         double g[4] = {0, 0, 0, 0}, mg[4] = {0, 0, 0, 0};
         bool conv = true;
 #pragma unroll
@@ -430,7 +435,7 @@ __device__ __forceinline__ int fit_last_point(int n, const double *m, double *lo
 #pragma unroll
             for (int t = 0; t < JP; ++t) cn[t] = c[t] + x[t];
             double l2;
-            fit_eval<JP, false>(n, ib, cn, &l2, nullptr, nullptr);
+            fit_eval<JP, false>(n, v0, ib, cn, &l2, nullptr, nullptr);
             *logq = -l2;
             if (c_out)
 #pragma unroll
@@ -450,7 +455,7 @@ __device__ __forceinline__ int fit_last_point(int n, const double *m, double *lo
 #pragma unroll
                 for (int t = 0; t < JP; ++t) cn[t] = c[t] + st * x[t];
                 double l2;
-                fit_eval<JP, false>(n, ib, cn, &l2, nullptr, nullptr);
+                fit_eval<JP, false>(n, v0, ib, cn, &l2, nullptr, nullptr);
 #pragma unroll
                 for (int t = 0; t < JP; ++t) l2 += cn[t] * m[t];
                 if (l2 <= L0 + 1e-4 * st * slope) break;
@@ -508,7 +513,8 @@ struct SectorFitT {
 using SectorFit = SectorFitT<3>;
 
 // Fit one sector from its tilted moments t0..t4 (t0 > 0; moments past JM are
-// ignored): the moments m_t = tau_t / (tau_0 C(n-1,t)) are used up to the
+// ignored) on n' = 1..n - v0 (v0 > 0: a sector with fewer photons than
+// modes): the moments m_t = tau_t / (tau_0 C(n-1,t)) are used up to the
 // longest feasible prefix (0 < m_t < 1, decreasing in t, since
 // 0 <= phi_{t+1} <= phi_t <= 1).  A moment whose true value lies below the
 // transform's rounding floor can come out infeasible; it is then dropped, and
@@ -516,8 +522,8 @@ using SectorFit = SectorFitT<3>;
 // fires: q(n) = 1.  The moments arrive by value and the fit runs out of line,
 // so that callers index nothing at run time.
 template <int JM>
-__device__ __noinline__ SectorFitT<JM> fit_sector(int n, int jp, double t0, double t1, double t2, double t3,
-                                                  double t4)
+__device__ __noinline__ SectorFitT<JM> fit_sector(int n, int v0, int jp, double t0, double t1, double t2,
+                                                  double t3, double t4)
 {
     SectorFitT<JM> r;
     const double binv[4] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
@@ -544,10 +550,10 @@ __device__ __noinline__ SectorFitT<JM> fit_sector(int n, int jp, double t0, doub
     int bad = 1;
     while (jr >= 1 && bad) {
         switch (jr) {
-        case 1: bad = fit_last_point<1>(n, r.m, &r.lq, r.c); break;
-        case 2: bad = fit_last_point<2>(n, r.m, &r.lq, r.c); break;
-        case 3: bad = fit_last_point<JM >= 3 ? 3 : 1>(n, r.m, &r.lq, r.c); break;
-        default: bad = fit_last_point<JM >= 4 ? 4 : 1>(n, r.m, &r.lq, r.c); break;
+        case 1: bad = fit_last_point<1>(n, v0, r.m, &r.lq, r.c); break;
+        case 2: bad = fit_last_point<2>(n, v0, r.m, &r.lq, r.c); break;
+        case 3: bad = fit_last_point<JM >= 3 ? 3 : 1>(n, v0, r.m, &r.lq, r.c); break;
+        default: bad = fit_last_point<JM >= 4 ? 4 : 1>(n, v0, r.m, &r.lq, r.c); break;
         }
         if (bad) --jr;
     }

@@ -211,7 +211,8 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(
     dev = block_max(dev, red);
     if (tid == 0) {
         RowPlan rp = rows[p];
-        row_plan(rp, n, dg, 1, logdetQ, logdetA, amin, dev, scal[3] != 0.0 || s_fail != 0, frozen);
+        row_plan(rp, n, dg, 1, logdetQ, logdetA, amin, dev, scal[3] != 0.0 || s_fail != 0, frozen & 1,
+                 (frozen & 2) != 0);
         rows[p] = rp;
     }
 }
@@ -223,7 +224,8 @@ int eig_rows(gbs_ctx *ctx, gbs_plan *pl)
     if (pl->P == 0) return 0;
     hipLaunchKernelGGL(k_eig, dim3(pl->P), dim3(EIG_THREADS), 0, ctx->stream, ctx->model.M,
                        ctx->model.qi_hi, ctx->model.scal, pl->d_offsets, pl->d_modes, pl->d_perm,
-                       pl->d_voff, pl->d_wbig, pl->d_alpha, pl->d_v, pl->d_rows, pl->frozen ? 1 : 0);
+                       pl->d_voff, pl->d_wbig, pl->d_alpha, pl->d_v, pl->d_rows,
+                       (pl->frozen ? 1 : 0) | (pl->whole ? 2 : 0));
     HIP_TRY(ctx, hipGetLastError());
     return 0;
 }

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
         if (!(t0 >= thr) || !(t0 > 0.0)) continue;
         const double lw = log(t0) + rp.log_g_rho - kap * rp.log_rho;
         if (lw < lower + log(1e-17)) continue;
-        const SectorFit f = fit_sector<3>(n, jp, t0, tau[j][1], tau[j][2], tau[j][3], 0.0);
+        const SectorFit f = fit_sector<3>(n, 0, jp, t0, tau[j][1], tau[j][2], tau[j][3], 0.0);
         if (f.bad) continue;
         fits[j] = f;
         ell[j] = lw + f.lq;
@@ -124,8 +124,8 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
     const double fsum = block_sum(fm == -INFINITY ? 0.0 : fs * exp(fm - fmx), red);
     const double total = fmx + log(fsum);
     // sector cotangents: pi_kappa w_p d ell / d tau_t
-    const double binv[3] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
-                            6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0))};
+    const double binv[4] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
+                            6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0)), 0.0};
     double tbar[FIT_KPT][4];
 #pragma unroll
     for (int j = 0; j < FIT_KPT; ++j) {
@@ -142,9 +142,9 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
             double lse, E[3], E2[6];
             bool ok = false;
             switch (jr) {
-            case 1: fit_eval<1, true>(n, binv, fits[j].c, &lse, E, E2); ok = fit_solve<1>(E, E2, m, u); break;
-            case 2: fit_eval<2, true>(n, binv, fits[j].c, &lse, E, E2); ok = fit_solve<2>(E, E2, m, u); break;
-            default: fit_eval<3, true>(n, binv, fits[j].c, &lse, E, E2); ok = fit_solve<3>(E, E2, m, u); break;
+            case 1: fit_eval<1, true>(n, 0, binv, fits[j].c, &lse, E, E2); ok = fit_solve<1>(E, E2, m, u); break;
+            case 2: fit_eval<2, true>(n, 0, binv, fits[j].c, &lse, E, E2); ok = fit_solve<2>(E, E2, m, u); break;
+            default: fit_eval<3, true>(n, 0, binv, fits[j].c, &lse, E, E2); ok = fit_solve<3>(E, E2, m, u); break;
             }
             if (!ok) u[0] = u[1] = u[2] = 0.0;
         }

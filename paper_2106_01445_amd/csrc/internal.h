@@ -91,6 +91,7 @@ struct gbs_plan {
     int seg_fwd = GBS_CLUSTER_SEG, seg_adj = GBS_CLUSTER_SEG, qchunk = GBS_QCHUNK, gmax = 8;
     int max_n_small = 0;                  // largest click count among the other rows
     bool frozen = false;
+    bool whole = false;                   // one row of every mode: contour at rho = 1 (click distribution)
     bool have_run = false;
     std::vector<int32_t> h_offsets, h_modes, h_perm, h_n;
     // device
@@ -149,5 +150,7 @@ int approx_backward(gbs_ctx *ctx, gbs_plan *plan, const double *dl_dev, const in
                     double *grad_r_dev, double *grad_eta_dev);
 int eig_rows(gbs_ctx *ctx, gbs_plan *plan);
 int plain_contour(gbs_ctx *ctx, gbs_plan *plan);
+int click_distribution_run(gbs_ctx *ctx, gbs_plan *pl, int nk, const int *ks_dev, double *pn_dev, double *pk_dev,
+                           int32_t *status_dev);
 int approx_forward_plain(gbs_ctx *ctx, gbs_plan *plan, double *logp_dev, int32_t *status_dev);
 int plan_units(gbs_ctx *ctx, gbs_plan *plan);

@@ -25,7 +25,7 @@ EXPORTS = ["gbs_create", "gbs_destroy", "gbs_last_error", "gbs_set_model", "gbs_
            "gbs_prob_approx_plain", "gbs_plan_get_params", "gbs_plan_set_params", "gbs_plan_tune",
            "gbs_plan_create", "gbs_plan_destroy", "gbs_plan_freeze", "gbs_prob_approx_dev",
            "gbs_grad", "gbs_grad_dev", "gbs_plan_info", "gbs_set_timing", "gbs_timing",
-           "gbs_stream"]
+           "gbs_stream", "gbs_click_distribution"]
 TIMING_GROUPS = ["model", "row_setup", "work_queue", "contour_clusters", "dft_fit", "exact",
                  "adjoint_fit_dft", "adjoint_contour_clusters", "adjoint_rows_scatter",
                  "adjoint_model"]
@@ -77,6 +77,7 @@ def load(path: str = LIB_PATH):
         "gbs_grad_dev": ([vp, vp, dp, dp, dp, dp, i32p], ip),
         "gbs_plan_info": ([vp, dp, dp, i32p, i32p], ip),
         "gbs_stream": ([vp], vp),
+        "gbs_click_distribution": ([vp, ip, ip, i32p, dp, dp, i32p], ip),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -242,6 +243,17 @@ class Context:
         self._check(load().gbs_prob_approx_plain(self.handle, P, _ptr(off), _ptr(mod), order, prec,
                                                  _ptr(lp), _ptr(st)))
         return dict(logp=lp, status=st)
+
+    def gbs_click_distribution(self, order: int, ks=()):
+        """p(n), n = 0..M, of the whole device and the sector curves p_k(n) for
+        k in ks (order-j estimate); returns dict(p_n, p_k[len(ks), M+1], status)."""
+        kk = _i32(list(ks))
+        pn = np.zeros(self.M + 1)
+        pk = np.zeros((len(kk), self.M + 1))
+        st = np.zeros(1, np.int32)
+        self._check(load().gbs_click_distribution(self.handle, order, len(kk), _ptr(kk) if len(kk) else None,
+                                                  _ptr(pn), _ptr(pk) if len(kk) else None, _ptr(st)))
+        return dict(p_n=pn, p_k=pk, status=int(st[0]))
 
     def gbs_plan_create(self, offsets, modes, order: int, prec: int = GBS_PREC_FP64) -> Plan:
         off, mod = _i32(offsets), _i32(modes)

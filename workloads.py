@@ -157,6 +157,17 @@ def accuracy_workload(M: int, r: float, n: int, P: int = 100) -> Workload:
                                 f"{P} outcomes with {n} clicks; exact and orders 2-4")
 
 
+def device30_model():
+    """The device of the paper's Fig. 2: a 30-mode Haar interferometer, 15
+    inputs squeezed at r = 1.4, the others in vacuum, lossless (stream
+    [SEED_ROOT, 96, s])."""
+    M = 30
+    U = haar_unitary(M, np.random.default_rng([SEED_ROOT, 96, S_U]))
+    r = np.zeros(M)
+    r[:15] = 1.4
+    return U, r, np.ones(M)
+
+
 def small_model(M: int, seed: int, n_squeezed: Optional[int] = None,
                 r_range=(0.5, 1.5), eta_range=(0.3, 1.0)):
     """A small random lossy model for pins and edge cases."""
