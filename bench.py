@@ -268,6 +268,36 @@ def accuracy_leg(ctx):
     return {"points": res, "s": time.perf_counter() - t0}
 
 
+def distribution_leg(ctx):
+    """The whole device's click distribution p(n) and the sector curves p_k(n)
+    of the paper's Fig. 2 device (30 modes, 15 inputs at r = 1.4, Haar U,
+    lossless) at orders 2-4: wall time per call, sum p, mean clicks against the
+    exact mean, the most likely n, p(30), and for k = 20, 50, 80, 110, 140, 170
+    the peak position and weight of p_k(n)."""
+    from workloads import device30_model
+    from oracle import model
+    U, r, eta = device30_model()
+    ctx.gbs_set_model(U, r, eta)
+    Q = model.q_matrix(model.covariance(U, r, eta))
+    mean = sum(1.0 - model.vacuum_prob(Q, [l]) for l in range(30))
+    ks = (20, 50, 80, 110, 140, 170)
+    out = {"workload": "device30_r1.4", "modes": 30, "squeezed_inputs": 15, "r": 1.4, "eta": 1.0,
+           "exact_mean_clicks": mean}
+    for order in (2, 3, 4):
+        ctx.gbs_click_distribution(order, ks)
+        t0 = time.perf_counter()
+        d = ctx.gbs_click_distribution(order, ks)
+        ms = (time.perf_counter() - t0) * 1e3
+        p = d["p_n"]
+        out[f"order{order}"] = {
+            "ms": ms, "status": d["status"], "sum_p": float(p.sum()),
+            "mean_clicks": float(np.arange(31) @ p), "argmax_n": int(np.argmax(p)),
+            "p_30": float(p[30]),
+            "sectors": {str(k): {"argmax_n": int(np.argmax(d["p_k"][i])), "weight": float(d["p_k"][i].sum())}
+                        for i, k in enumerate(ks)}}
+    return out
+
+
 def source_sha(paths):
     import hashlib
     h = hashlib.sha256()
@@ -301,6 +331,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain comparison kernel")
     ap.add_argument("--no-order4", action="store_true", help="skip the fourth-order leg")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy-study leg")
+    ap.add_argument("--no-dist", action="store_true", help="skip the click-distribution leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch choices")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 3 times (calibrates the "
@@ -453,6 +484,8 @@ def main():
         out["m70_order4"] = order4_leg(ctx, torch)
     if not args.no_accuracy:
         out["accuracy_study"] = accuracy_leg(ctx)
+    if not args.no_dist:
+        out["click_distribution"] = distribution_leg(ctx)
     if not args.no_exact:
         out["exact_m20"] = exact_leg(ctx)
     if not args.no_big:
