@@ -64,7 +64,7 @@ def cpu_baseline(wl, gpu_logp, budget_s: float = 20.0):
     rows = csr_rows(wl.offsets, wl.modes)
     ns = np.diff(wl.offsets)
     order = np.argsort(ns, kind="stable")
-    pick = [int(order[int(q * (len(order) - 1))]) for q in np.linspace(0.0, 1.0, 9)]
+    pick = [int(order[int(q * (len(order) - 1))]) for q in np.linspace(0.0, 1.0, 21)]
     Q = model.q_matrix(model.covariance(wl.U, wl.r, wl.eta))
     done, errs = [], []
     t0 = time.perf_counter()
