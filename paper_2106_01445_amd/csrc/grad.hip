@@ -197,8 +197,10 @@ __host__ __device__ __forceinline__ int adj_need(int n) { return adj_vbytes(n) +
 
 // Rows of at most 40 clicks (2n <= 80, at most ADJ_TMAX 16-wide tiles) form
 // V^T Z V by column units: unit u of a row with T tiles covers column tile jt
-// and row tiles rt0..rt1-1 and adds its share of R into slot `slot` of the
-// item's R scratch (ADJ_RSLOTS slots, summed in a fixed order by k_adj_reduce).
+// and row tiles rt0..rt1-1; it is held by one wavefront, which sums its share
+// of R over the item's points in registers and writes it once, at the end of
+// the item, into slot `slot` of the item's R scratch (ADJ_RSLOTS slots, summed
+// in a fixed order by k_adj_reduce).
 // Each column is split into as many parts as keep the eight wavefronts about
 // equally loaded (a part costs (rt1 - rt0)(2 KS + 8 (jt + 1)) MFMAs); the
 // units of each T are listed by decreasing cost, and with eight units wave w
@@ -317,9 +319,32 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         const int Qn = rp.K / 2 + 1;
         const int q0 = ch * ADJ_QCHUNK, q1 = min(q0 + ADJ_QCHUNK, Qn);
         const int T = (N + 15) >> 4, KS = (N + 3) >> 2;
+        // rows up to 40 clicks: this wavefront's share of R (its column unit's
+        // tiles), summed over the item's points in registers
+        dbl4 racc[ADJ_TMAX];
+#pragma unroll
+        for (int it = 0; it < ADJ_TMAX; ++it) racc[it] = dbl4{0.0, 0.0, 0.0, 0.0};
         const long long ro = roff[item];
-        const int nslot = BIG ? 1 : ADJ_RSLOTS;
-        for (int e = tid; e < nslot * (N * (N + 1) / 2); e += CONT_THREADS) rscr[ro + e] = 0.0;
+        if (BIG) {
+            for (int e = tid; e < N * (N + 1) / 2; e += CONT_THREADS) rscr[ro + e] = 0.0;
+        } else {
+            // R slots are written once, at the end of the item, by the column
+            // units; the column strips of a slot that no unit covers are zero
+            const int nun = adj_col_units(T), nup = N * (N + 1) / 2;
+            for (int s = 0; s < ADJ_RSLOTS; ++s)
+                for (int jt = 0; jt < T; ++jt) {
+                    bool cov = false;
+                    for (int u = 0; u < nun; ++u) {
+                        int ujt, r0, r1, us;
+                        adj_col_unit(T, u, ujt, r0, r1, us);
+                        cov = cov || (ujt == jt && us == s);
+                    }
+                    if (cov) continue;
+                    const int j0 = 16 * jt, j1 = min(16 * jt + 16, N);
+                    for (int e = j0 * (j0 + 1) / 2 + tid; e < j1 * (j1 + 1) / 2; e += CONT_THREADS)
+                        rscr[ro + (long long)s * nup + e] = 0.0;
+                }
+        }
         // the item's contour points w_q = rho e^{2 pi i q / K}
         if (tid < q1 - q0) {
             double sn, cs;
@@ -428,30 +453,12 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                          A11 = cmk(0, 0), A12 = cmk(0, 0), A13 = cmk(0, 0), A22 = cmk(0, 0),
                          A23 = cmk(0, 0), A33 = cmk(0, 0);
                     if (ORDER >= 3) {
-                        // the M entries of the next third mode are read before this
-                        // one's Z updates are issued, so that they do not queue
-                        // behind them
-                        cplx nx00, nx01, nx10, nx11, ny00, ny01, ny10, ny11, nc00, nc01, nc11;
-                        int iac = pair_pos<true>(n, a, c0), ibc = pair_pos<true>(n, b, c0);
-                        if (c0 < c1) {
-                            nx00 = Mo0[iac]; nx01 = Mo1[iac]; nx10 = Mo2[iac]; nx11 = Mo3[iac];
-                            ny00 = Mo0[ibc]; ny01 = Mo1[ibc]; ny10 = Mo2[ibc]; ny11 = Mo3[ibc];
-                            nc00 = Md0[c0]; nc01 = Md1[c0]; nc11 = Md2[c0];
-                        }
 #pragma unroll 1
                         for (int c = c0; c < c1; ++c) {
-                            const cplx x00 = nx00, x01 = nx01, x10 = nx10, x11 = nx11;
-                            const cplx yy00 = ny00, yy01 = ny01, yy10 = ny10, yy11 = ny11;
-                            const cplx m00 = nc00, m01 = nc01, m11 = nc11;
-                            const int cur_ac = iac, cur_bc = ibc;
-                            if (c + 1 < c1) {
-                                // pair_pos(a, c + 1) = pair_pos(a, c) + n - (c - a)
-                                iac += n - (c - a);
-                                ibc += n - (c - b);
-                                nx00 = Mo0[iac]; nx01 = Mo1[iac]; nx10 = Mo2[iac]; nx11 = Mo3[iac];
-                                ny00 = Mo0[ibc]; ny01 = Mo1[ibc]; ny10 = Mo2[ibc]; ny11 = Mo3[ibc];
-                                nc00 = Md0[c + 1]; nc01 = Md1[c + 1]; nc11 = Md2[c + 1];
-                            }
+                            const int cur_ac = pair_pos<true>(n, a, c), cur_bc = pair_pos<true>(n, b, c);
+                            const cplx x00 = Mo0[cur_ac], x01 = Mo1[cur_ac], x10 = Mo2[cur_ac], x11 = Mo3[cur_ac];
+                            const cplx yy00 = Mo0[cur_bc], yy01 = Mo1[cur_bc], yy10 = Mo2[cur_bc], yy11 = Mo3[cur_bc];
+                            const cplx m00 = Md0[c], m01 = Md1[c], m11 = Md2[c];
                             // Za = Maa^{-1} Xa, Y = Xb - G^T Xa, W = Sb^{-1} Y,
                             // Sc = Mcc - Xa^T Za - Y^T W, U = [Za - G W ; W]
                             cplx Z00, Z01, Z10, Z11, W00, W01, W10, W11, sc00, sc01, sc11;
@@ -671,31 +678,19 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 // Column unit (jt, rows rt0..rt1-1, slot): Y(rt, jt) = Z V for each
                 // row tile rt of the part, then, with Y still in the accumulators
                 // (the 16x16x4 accumulator layout is the B operand layout of the
-                // next product), X(it, jt) += V^T(it, rt) Y(rt, jt) for it <= jt;
-                // finally R += Re[f X] (+ the diagonal beta terms in slot 0) in the
-                // part's R slot of the item (read-modified-written, L2-resident).
-                // The units split the columns so that the two wavefronts of each
-                // SIMD get about the same number of MFMAs.
-                const int nup = N * (N + 1) / 2;
+                // next product), R(it, jt) += Re[f X(it, jt)] with X = V^T Y for
+                // it <= jt (+ the diagonal beta terms in slot 0), summed in the
+                // wavefront's registers over the item's points.  The units split
+                // the columns so that the two wavefronts of each SIMD get about
+                // the same number of MFMAs.
                 const int nun = adj_col_units(T);
                 for (int uw = wid; uw < nun; uw += CONT_THREADS / 64) {
                     const int u = nun == CONT_THREADS / 64 && uw >= 4 ? 11 - uw : uw;
                     int jt, rt0, rt1, slot;
                     adj_col_unit(T, u, jt, rt0, rt1, slot);
-                    double *Rs = rscr + ro + (long long)slot * nup;
                     const int jj = jt * 16 + l16;
                     const bool jok = jj < N;
-                    double rold[ADJ_TMAX][4];
-#pragma unroll
-                    for (int it = 0; it < ADJ_TMAX; ++it)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int ii = it * 16 + 4 * e + lq;
-                            rold[it][e] = it <= jt && ii <= jj && jok ? Rs[jj * (jj + 1) / 2 + ii] : 0.0;
-                        }
-                    dbl4 xre[ADJ_TMAX], xim[ADJ_TMAX];
-#pragma unroll
-                    for (int it = 0; it < ADJ_TMAX; ++it) xre[it] = xim[it] = dbl4{0.0, 0.0, 0.0, 0.0};
+                    const cplx dkj = dk[jok ? jj : 0];
                     for (int rt = rt0; rt < rt1; ++rt) {
                         const int r = rt * 16 + l16;
                         const bool rok = r < N;
@@ -718,42 +713,62 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                             yre = mfma4(z.re, v, yre);
                             yim = mfma4(z.im, v, yim);
                         }
-                        // rows of Y beyond 2n are zero, so the A operand there only
-                        // has to be finite
+                        // Re[hw dk_i dk_j X_ij] = sum_r Re[(hw dk_i V_ri) (dk_j Y_rj)]:
+                        // the column factor scales Y in its accumulators, the row
+                        // factor the A operand, and the real part goes straight into
+                        // R.  Rows of Y beyond 2n are zero, so the A operand there
+                        // only has to be finite.
+                        dbl4 ure, uim;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            ure[e] = dkj.re * yre[e] - dkj.im * yim[e];
+                            uim[e] = dkj.im * yre[e] + dkj.re * yim[e];
+                        }
 #pragma unroll
                         for (int it = 0; it < ADJ_TMAX; ++it) {
                             if (it > jt) continue;
                             const int i = it * 16 + l16, ic = i < N ? i : 0;
+                            const cplx g = cmul(hw, dk[ic]);
 #pragma unroll
                             for (int e = 0; e < 4; ++e) {
                                 const int rr = rt * 16 + 4 * e + lq, rc = rr < N ? rr : 0;
                                 const double av = Vt[ic * vs + rc];
-                                xre[it] = mfma4(av, yre[e], xre[it]);
-                                xim[it] = mfma4(av, yim[e], xim[it]);
+                                racc[it] = mfma4(g.re * av, ure[e], racc[it]);
+                                racc[it] = mfma4(-g.im * av, uim[e], racc[it]);
                             }
                         }
                     }
+                    if (slot == 0 && jok) {
+                        // diagonal beta terms, once per point
+                        const double dr = 1.0 / (1.0 + rp.rho * (al[jj] - 1.0));
+                        const cplx t = cmk(0.5 * rp.rho * dr - hw.re * dkj.re + hw.im * dkj.im,
+                                           -(hw.re * dkj.im + hw.im * dkj.re));
+                        const double add = beta.re * t.re - beta.im * t.im;
 #pragma unroll
-                    for (int it = 0; it < ADJ_TMAX; ++it) {
-                        if (it > jt) continue;
+                        for (int it = 0; it < ADJ_TMAX; ++it)
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int ii = it * 16 + 4 * e + lq;
-                            if (ii <= jj && jok) {
-                                const cplx f = cmul(hw, cmul(dk[ii], dk[jj]));
-                                double add = f.re * xre[it][e] - f.im * xim[it][e];
-                                if (ii == jj && slot == 0) {
-                                    const double dr = 1.0 / (1.0 + rp.rho * (al[ii] - 1.0));
-                                    const cplx t = cmk(0.5 * rp.rho * dr - hw.re * dk[ii].re + hw.im * dk[ii].im,
-                                                       -(hw.re * dk[ii].im + hw.im * dk[ii].re));
-                                    add += beta.re * t.re - beta.im * t.im;
-                                }
-                                Rs[jj * (jj + 1) / 2 + ii] = rold[it][e] + add;
-                            }
-                        }
+                            for (int e = 0; e < 4; ++e)
+                                if (it == jt && 4 * e + lq == l16) racc[it][e] += add;
                     }
                 }
                 __syncthreads();
+            }
+        }
+        if (!BIG) {
+            const int nun = adj_col_units(T);
+            if (wid < nun) {
+                const int u = nun == CONT_THREADS / 64 && wid >= 4 ? 11 - wid : wid;
+                int jt, rt0, rt1, slot;
+                adj_col_unit(T, u, jt, rt0, rt1, slot);
+                double *Rs = rscr + ro + (long long)slot * (N * (N + 1) / 2);
+                const int jj = jt * 16 + l16;
+#pragma unroll
+                for (int it = 0; it < ADJ_TMAX; ++it)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int ii = it * 16 + 4 * e + lq;
+                        if (it <= jt && ii <= jj && jj < N) Rs[jj * (jj + 1) / 2 + ii] = racc[it][e];
+                    }
             }
         }
         __syncthreads();
