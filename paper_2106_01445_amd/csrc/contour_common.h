@@ -222,7 +222,9 @@ __device__ __forceinline__ void m_store(int n, int it, int jt, const dbl4 &mre, 
 // holds the eigenvectors as rows (entry i of eigenvector k at k*vs + i).  Each
 // operand fetched per k-step serves BS tiles (BS = 2 halves the loads per MFMA
 // where V is read from L2).
-template <int BS, class C = cplx, bool DIAG = false>
+// With PAD, Vt and d are zero beyond 2n up to the tile edge, and no fetch is
+// masked.
+template <int BS, class C = cplx, bool DIAG = false, bool PAD = false>
 __device__ __forceinline__ void m_block_mfma(int n, int ib, int jb, const double *Vt, int vs,
                                              const cplx *d, C *blk, int lane)
 {
@@ -242,12 +244,12 @@ __device__ __forceinline__ void m_block_mfma(int n, int ib, int jb, const double
 #pragma unroll 2
     for (int ks = 0; ks < KS; ++ks) {
         const int k = ks * 4 + lq;
-        const bool kok = k < N;
+        const bool kok = PAD || k < N;
         const cplx dl = d[kok ? k : 0];
         double ar[BS], ai[BS], bv[BS];
 #pragma unroll
         for (int s = 0; s < BS; ++s) {
-            const bool aok = kok && iv[s] < N, bok = kok && jv[s] < N;
+            const bool aok = PAD || (kok && iv[s] < N), bok = PAD || (kok && jv[s] < N);
             const double va = Vt[aok ? k * vs + iv[s] : 0], vb = Vt[bok ? k * vs + jv[s] : 0];
             ar[s] = aok ? va * dl.re : 0.0;
             ai[s] = aok ? va * dl.im : 0.0;

@@ -185,15 +185,36 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
 // ---------------------------------------------------------------------------
 // k_adj_contour
 // ---------------------------------------------------------------------------
-__host__ __device__ __forceinline__ int adj_vbytes(int n) { return 8 * (2 * n * (2 * n + 1) + 2 * n); }
-// per q: d, rz (2n each), M blocks (3n + 4 n(n-1)/2), Z blocks (same)
-__host__ __device__ __forceinline__ int adj_mbytes(int n) { return 16 * (4 * n + 2 * (3 * n + 2 * n * (n - 1))); }
+// Rows up to 40 clicks keep V in LDS zero-padded to ADJ_TP x ADJ_TP (row stride
+// ADJ_VS, a compile-time constant) and d_k zero-padded to ADJ_TP entries, so
+// that no MFMA operand fetch needs a bounds mask.
+#define ADJ_TMAX 5
+#define ADJ_TP (16 * ADJ_TMAX)
+#define ADJ_VS (ADJ_TP + 1)
+static_assert(2 * GBS_NSMALL <= ADJ_TP, "padded V must hold the rows kept in LDS");
+// After the cluster sums, Z(w) is copied into the M(w) region as the packed
+// upper triangle of a 16T x 16T matrix (T = ceil(2n/16) tiles, zero beyond
+// 2n), the A operand layout of Z V; the region is sized for both.
+__host__ __device__ __forceinline__ int adj_zpack(int n)
+{
+    const int t = (2 * n + 15) / 16;
+    return 8 * t * (16 * t + 1);
+}
+__host__ __device__ __forceinline__ int adj_mreg(int n)
+{
+    const int m = 3 * n + 2 * n * (n - 1);
+    return m > adj_zpack(n) ? m : adj_zpack(n);
+}
+// V, alpha, d, rz, the M(w) region and the Z(w) blocks (3n + 4 n(n-1)/2)
+__host__ __device__ __forceinline__ int adj_need(int n)
+{
+    return 8 * (ADJ_TP * ADJ_VS + ADJ_TP) + 16 * (2 * ADJ_TP + adj_mreg(n) + 3 * n + 2 * n * (n - 1));
+}
 __host__ __device__ __forceinline__ int adj_fixed() { return 16 * (CONT_THREADS / 64 + 8); }
 // Larger rows form Y = Z V by column panels of ADJ_PW columns (row stride
 // ADJ_PWS, complex) in their HBM scratch.
 #define ADJ_PW 32
 #define ADJ_PWS 33
-__host__ __device__ __forceinline__ int adj_need(int n) { return adj_vbytes(n) + adj_mbytes(n); }
 
 // Rows of at most 40 clicks (2n <= 80, at most ADJ_TMAX 16-wide tiles) form
 // V^T Z V by column units: unit u of a row with T tiles covers column tile jt
@@ -206,7 +227,6 @@ __host__ __device__ __forceinline__ int adj_need(int n) { return adj_vbytes(n) +
 // units of each T are listed by decreasing cost, and with eight units wave w
 // takes unit w (w < 4) or 11 - w, so that the two wavefronts of a SIMD hold a
 // large and a small unit.
-#define ADJ_TMAX 5
 #define ADJ_RSLOTS GBS_RSLOTS
 __device__ __forceinline__ int adj_col_units(int T)
 {
@@ -269,7 +289,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         __syncthreads();
         if (item >= total) break;
         const int p = items[2 * item], ch = items[2 * item + 1];
-        const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n, NP = N + 1;
+        const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
         const RowPlan rp = rows[p];
         const int np = n * (n - 1) / 2;
         const long long vo = voff[p];
@@ -278,7 +298,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         // and the panel in this workgroup's HBM scratch, Z(w) in LDS (at order
         // <= 2 only its diagonal blocks: each pair block has a single writer
         // and goes to the scratch)
-        const int vs = BIG ? N : NP;
+        const int vs = BIG ? N : ADJ_VS;
         const double *Vt;
         double *al;
         cplx *dk, *rz, *Md0, *Zd0, *Zo0, *Yp;
@@ -298,17 +318,18 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             }
         } else {
             double *vl = dyn;
-            al = vl + N * NP;
-            dk = (cplx *)(al + N);
-            rz = dk + N;
-            Md0 = rz + N;
-            Zd0 = Md0 + 3 * n + 4 * np;
+            al = vl + ADJ_TP * ADJ_VS;
+            dk = (cplx *)(al + ADJ_TP);
+            rz = dk + ADJ_TP;
+            Md0 = rz + ADJ_TP;
+            Zd0 = Md0 + adj_mreg(n);
             Zo0 = Zd0 + 3 * n;
             Yp = nullptr;  // (no panel: Y stays in registers)
-            for (int idx = tid; idx < N * N; idx += CONT_THREADS) {
-                const int k = idx / N, i = idx - k * N;
-                vl[k * NP + i] = vt[vo + idx];
+            for (int idx = tid; idx < ADJ_TP * ADJ_VS; idx += CONT_THREADS) {
+                const int k = idx / ADJ_VS, i = idx - k * ADJ_VS;
+                vl[idx] = k < N && i < N ? vt[vo + k * N + i] : 0.0;
             }
+            for (int k = N + tid; k < ADJ_TP; k += CONT_THREADS) dk[k] = cmk(0.0, 0.0);
             Vt = vl;
         }
         cplx *Md1 = Md0 + n, *Md2 = Md1 + n;
@@ -381,7 +402,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 for (int u = wid; u < nblk; u += CONT_THREADS / 64) {
                     int it, jt;
                     upper_tile(u, it, jt);
-                    m_block_mfma<BS, cplx, true>(n, it, jt, Vt, vs, dk, Md0, lane);
+                    m_block_mfma<BS, cplx, true, !BIG>(n, it, jt, Vt, vs, dk, Md0, lane);
                 }
             } else {
                 for (int a = tid; a < n; a += CONT_THREADS) {
@@ -675,6 +696,27 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 }
             }
             if (!BIG) {
+                // Z into the packed triangle Zp over the M(w) blocks (not read
+                // again for this point): Zp[j (j + 1) / 2 + i] = Z(i, j), i <= j
+                // (columns j and 16T-1-j together: 16T+1 entries, two per lane)
+                cplx *Zp = Md0;
+                for (int j = wid; j < 8 * T; j += CONT_THREADS / 64) {
+                    const int TT = 16 * T;
+                    cplx zv[2];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int k = lane + 64 * c;
+                        const int i = k <= j ? k : k - j - 1, col = k <= j ? j : TT - 1 - j;
+                        zv[c] = k <= TT ? zget(i, col) : cmk(0.0, 0.0);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int k = lane + 64 * c;
+                        const int i = k <= j ? k : k - j - 1, col = k <= j ? j : TT - 1 - j;
+                        if (k <= TT) Zp[col * (col + 1) / 2 + i] = zv[c];
+                    }
+                }
+                __syncthreads();
                 // Column unit (jt, rows rt0..rt1-1, slot): Y(rt, jt) = Z V for each
                 // row tile rt of the part, then, with Y still in the accumulators
                 // (the 16x16x4 accumulator layout is the B operand layout of the
@@ -688,28 +730,21 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                     const int u = nun == CONT_THREADS / 64 && uw >= 4 ? 11 - uw : uw;
                     int jt, rt0, rt1, slot;
                     adj_col_unit(T, u, jt, rt0, rt1, slot);
+                    // (V and d_k are zero beyond 2n: no operand masks)
                     const int jj = jt * 16 + l16;
                     const bool jok = jj < N;
-                    const cplx dkj = dk[jok ? jj : 0];
+                    const cplx dkj = dk[jj];
+                    const cplx *Zp = Md0;
                     for (int rt = rt0; rt < rt1; ++rt) {
                         const int r = rt * 16 + l16;
-                        const bool rok = r < N;
-                        const int a = r < n ? r : r - n, qa = r < n ? 0 : 1;
                         dbl4 yre = {0.0, 0.0, 0.0, 0.0}, yim = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
                         for (int ks = 0; ks < KS; ++ks) {
                             const int sidx = ks * 4 + lq;
-                            const bool ok = rok && sidx < N;
-                            const int b = sidx < n ? sidx : sidx - n, qb = sidx < n ? 0 : 1;
-                            const int lo = min(a, b), hi = max(a, b);
-                            const int kq = a < b ? 2 * qa + qb : 2 * qb + qa;
-                            // Zd0..Zd2 (stride n) are followed by Zo0..Zo3 (stride np)
-                            const int off = a == b ? (qa + qb) * n + a : 3 * n + kq * np + pair_pos<true>(n, lo, hi);
-                            const cplx zl = Zd0[ok ? off : 0];
-                            const cplx z = ok ? zl : cmk(0.0, 0.0);
-                            const bool vok = jok && sidx < N;
-                            const double vl = Vt[vok ? jj * vs + sidx : 0];
-                            const double v = vok ? vl : 0.0;
+                            // r, sidx < 16 T: inside the zero-padded triangle
+                            const int lo = min(r, sidx), hi = max(r, sidx);
+                            const cplx z = Zp[hi * (hi + 1) / 2 + lo];
+                            const double v = Vt[jj * vs + sidx];
                             yre = mfma4(z.re, v, yre);
                             yim = mfma4(z.im, v, yim);
                         }
@@ -727,12 +762,12 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
 #pragma unroll
                         for (int it = 0; it < ADJ_TMAX; ++it) {
                             if (it > jt) continue;
-                            const int i = it * 16 + l16, ic = i < N ? i : 0;
-                            const cplx g = cmul(hw, dk[ic]);
+                            const int i = it * 16 + l16;
+                            const cplx g = cmul(hw, dk[i]);
 #pragma unroll
                             for (int e = 0; e < 4; ++e) {
-                                const int rr = rt * 16 + 4 * e + lq, rc = rr < N ? rr : 0;
-                                const double av = Vt[ic * vs + rc];
+                                const int rr = rt * 16 + 4 * e + lq;
+                                const double av = Vt[i * vs + rr];
                                 racc[it] = mfma4(g.re * av, ure[e], racc[it]);
                                 racc[it] = mfma4(-g.im * av, uim[e], racc[it]);
                             }
