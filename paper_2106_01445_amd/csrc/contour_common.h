@@ -190,11 +190,14 @@ __device__ __forceinline__ int pair_pos(int n, int a, int b)
 // layout at blk: every entry i <= j of the upper triangle is one block entry,
 // diagonal blocks (x_a x_a, x_a p_a, p_a p_a) at a, n + a, 2n + a, pair blocks
 // a < b (x_a x_b, x_a p_b, p_a x_b, p_a p_b) at 3n + t np + pair_pos(a, b).
-template <class C, bool DIAG = false>
+// With FIX the arrays sit at the strides of a GBS_NSMALL-click row instead
+// (GBS_NSMALL for the diagonal-block arrays, its pair count for the others).
+template <class C, bool DIAG = false, bool FIX = false>
 __device__ __forceinline__ void m_store(int n, int it, int jt, const dbl4 &mre, const dbl4 &mim,
                                         C *blk, int lane)
 {
-    const int N = 2 * n, np = n * (n - 1) / 2;
+    const int N = 2 * n;
+    const int ds = FIX ? GBS_NSMALL : n, np = FIX ? GBS_NSMALL * (GBS_NSMALL - 1) / 2 : n * (n - 1) / 2;
     const int l16 = lane & 15, lq = lane >> 4;
     const int j = jt * 16 + l16;
     if (j >= N) return;
@@ -204,14 +207,14 @@ __device__ __forceinline__ void m_store(int n, int it, int jt, const dbl4 &mre, 
         if (ii > j) continue;
         int off;
         if (j < n) {
-            off = ii == j ? ii : 3 * n + pair_pos<DIAG>(n, ii, j);
+            off = ii == j ? ii : 3 * ds + pair_pos<DIAG>(n, ii, j);
         } else if (ii < n) {
             const int a = ii, b = j - n;
-            off = a == b ? n + a : (a < b ? 3 * n + np + pair_pos<DIAG>(n, a, b)
-                                          : 3 * n + 2 * np + pair_pos<DIAG>(n, b, a));
+            off = a == b ? ds + a : (a < b ? 3 * ds + np + pair_pos<DIAG>(n, a, b)
+                                           : 3 * ds + 2 * np + pair_pos<DIAG>(n, b, a));
         } else {
             const int a = ii - n, b = j - n;
-            off = a == b ? 2 * n + a : 3 * n + 3 * np + pair_pos<DIAG>(n, a, b);
+            off = a == b ? 2 * ds + a : 3 * ds + 3 * np + pair_pos<DIAG>(n, a, b);
         }
         blk[off] = from_d<C>(cmk(mre[e], mim[e]));
     }
@@ -223,8 +226,8 @@ __device__ __forceinline__ void m_store(int n, int it, int jt, const dbl4 &mre, 
 // operand fetched per k-step serves BS tiles (BS = 2 halves the loads per MFMA
 // where V is read from L2).
 // With PAD, Vt and d are zero beyond 2n up to the tile edge, and no fetch is
-// masked.
-template <int BS, class C = cplx, bool DIAG = false, bool PAD = false>
+// masked; FIX selects the fixed-stride block layout of m_store.
+template <int BS, class C = cplx, bool DIAG = false, bool PAD = false, bool FIX = false>
 __device__ __forceinline__ void m_block_mfma(int n, int ib, int jb, const double *Vt, int vs,
                                              const cplx *d, C *blk, int lane)
 {
@@ -268,7 +271,7 @@ __device__ __forceinline__ void m_block_mfma(int n, int ib, int jb, const double
 #pragma unroll
         for (int t = 0; t < BS; ++t)
             if (BS * ib + s <= BS * jb + t)
-                m_store<C, DIAG>(n, BS * ib + s, BS * jb + t, mre[s][t], mim[s][t], blk, lane);
+                m_store<C, DIAG, FIX>(n, BS * ib + s, BS * jb + t, mre[s][t], mim[s][t], blk, lane);
 }
 
 template <class C = cplx>

@@ -194,21 +194,18 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
 static_assert(2 * GBS_NSMALL <= ADJ_TP, "padded V must hold the rows kept in LDS");
 // After the cluster sums, Z(w) is copied into the M(w) region as the packed
 // upper triangle of a 16T x 16T matrix (T = ceil(2n/16) tiles, zero beyond
-// 2n), the A operand layout of Z V; the region is sized for both.
-__host__ __device__ __forceinline__ int adj_zpack(int n)
+// 2n), the A operand layout of Z V.
+// The M(w) and Z(w) blocks of these rows sit at the strides of a 40-click row
+// (ADJ_DS for the diagonal-block arrays, ADJ_OS for the pair-block arrays), so
+// that the arrays of one block are compile-time offsets of each other.
+#define ADJ_DS GBS_NSMALL
+#define ADJ_OS (GBS_NSMALL * (GBS_NSMALL - 1) / 2)
+#define ADJ_MREG (3 * ADJ_DS + 4 * ADJ_OS)
+static_assert(ADJ_MREG >= 8 * ADJ_TMAX * (16 * ADJ_TMAX + 1), "the M(w) region holds the packed Z");
+// V, alpha, d, rz, the M(w) region and the Z(w) blocks
+__host__ __device__ __forceinline__ int adj_need(int)
 {
-    const int t = (2 * n + 15) / 16;
-    return 8 * t * (16 * t + 1);
-}
-__host__ __device__ __forceinline__ int adj_mreg(int n)
-{
-    const int m = 3 * n + 2 * n * (n - 1);
-    return m > adj_zpack(n) ? m : adj_zpack(n);
-}
-// V, alpha, d, rz, the M(w) region and the Z(w) blocks (3n + 4 n(n-1)/2)
-__host__ __device__ __forceinline__ int adj_need(int n)
-{
-    return 8 * (ADJ_TP * ADJ_VS + ADJ_TP) + 16 * (2 * ADJ_TP + adj_mreg(n) + 3 * n + 2 * n * (n - 1));
+    return 8 * (ADJ_TP * ADJ_VS + ADJ_TP) + 16 * (2 * ADJ_TP + 2 * ADJ_MREG);
 }
 __host__ __device__ __forceinline__ int adj_fixed() { return 16 * (CONT_THREADS / 64 + 8); }
 // Larger rows form Y = Z V by column panels of ADJ_PW columns (row stride
@@ -322,8 +319,8 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             dk = (cplx *)(al + ADJ_TP);
             rz = dk + ADJ_TP;
             Md0 = rz + ADJ_TP;
-            Zd0 = Md0 + adj_mreg(n);
-            Zo0 = Zd0 + 3 * n;
+            Zd0 = Md0 + ADJ_MREG;
+            Zo0 = Zd0 + 3 * ADJ_DS;
             Yp = nullptr;  // (no panel: Y stays in registers)
             for (int idx = tid; idx < ADJ_TP * ADJ_VS; idx += CONT_THREADS) {
                 const int k = idx / ADJ_VS, i = idx - k * ADJ_VS;
@@ -332,10 +329,11 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             for (int k = N + tid; k < ADJ_TP; k += CONT_THREADS) dk[k] = cmk(0.0, 0.0);
             Vt = vl;
         }
-        cplx *Md1 = Md0 + n, *Md2 = Md1 + n;
-        cplx *Mo0 = Md2 + n, *Mo1 = Mo0 + np, *Mo2 = Mo1 + np, *Mo3 = Mo2 + np;
-        cplx *Zd1 = Zd0 + n, *Zd2 = Zd1 + n;
-        cplx *Zo1 = Zo0 + np, *Zo2 = Zo1 + np, *Zo3 = Zo2 + np;
+        const int dstr = BIG ? n : ADJ_DS, ostr = BIG ? np : ADJ_OS;
+        cplx *Md1 = Md0 + dstr, *Md2 = Md1 + dstr;
+        cplx *Mo0 = Md2 + dstr, *Mo1 = Mo0 + ostr, *Mo2 = Mo1 + ostr, *Mo3 = Mo2 + ostr;
+        cplx *Zd1 = Zd0 + dstr, *Zd2 = Zd1 + dstr;
+        cplx *Zo1 = Zo0 + ostr, *Zo2 = Zo1 + ostr, *Zo3 = Zo2 + ostr;
         for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
         const int Qn = rp.K / 2 + 1;
         const int q0 = ch * ADJ_QCHUNK, q1 = min(q0 + ADJ_QCHUNK, Qn);
@@ -384,9 +382,13 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 dk[k] = cmul(r, r);
                 rz[k] = r;
             }
-            for (int i = tid; i < 3 * n; i += CONT_THREADS) Zd0[i] = cmk(0.0, 0.0);
-            if (!BIG || ORDER != 2)
-                for (int i = tid; i < 4 * np; i += CONT_THREADS) Zo0[i] = cmk(0.0, 0.0);
+            if (BIG) {
+                for (int i = tid; i < 3 * n; i += CONT_THREADS) Zd0[i] = cmk(0.0, 0.0);
+                if (ORDER != 2)
+                    for (int i = tid; i < 4 * np; i += CONT_THREADS) Zo0[i] = cmk(0.0, 0.0);
+            } else {
+                for (int i = tid; i < ADJ_MREG; i += CONT_THREADS) Zd0[i] = cmk(0.0, 0.0);
+            }
             __syncthreads();
             if (wid == 0) {
                 // G_0(w)/G_0(rho) = exp(log det A/2 - log G_0(rho)) prod_k z_k^{-1/2}
@@ -402,7 +404,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 for (int u = wid; u < nblk; u += CONT_THREADS / 64) {
                     int it, jt;
                     upper_tile(u, it, jt);
-                    m_block_mfma<BS, cplx, true, !BIG>(n, it, jt, Vt, vs, dk, Md0, lane);
+                    m_block_mfma<BS, cplx, true, !BIG, !BIG>(n, it, jt, Vt, vs, dk, Md0, lane);
                 }
             } else {
                 for (int a = tid; a < n; a += CONT_THREADS) {
@@ -512,43 +514,45 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                                 const cplx k = cmul(ct, cmul(rc, rc));
                                 is00 = cmul(sc11, k);
                                 is11 = cmul(sc00, k);
-                                is01 = cscale(cmul(sc01, k), -1.0);
+                                is01 = cmul(cneg(sc01), k);
                             }
                             catomic(&Zd0[c], is00);
                             catomic(&Zd1[c], is01);
                             catomic(&Zd2[c], is11);
-                            // rows a: U_a = Za - G W, then P_a = U_a c_T Sc^{-1}
+                            // rows a: U_a = Za - G W, then Q_a = -P_a = -U_a c_T Sc^{-1}
+                            // (formed with the sign the Z blocks take, so that no
+                            // negated copy has to be made for the LDS adds)
                             const cplx U00 = csub(Z00, cfma(G00, W00, cmul(G01, W10)));
                             const cplx U01 = csub(Z01, cfma(G00, W01, cmul(G01, W11)));
                             const cplx U10 = csub(Z10, cfma(G10, W00, cmul(G11, W10)));
                             const cplx U11 = csub(Z11, cfma(G10, W01, cmul(G11, W11)));
-                            const cplx P00 = cfma(U00, is00, cmul(U01, is01));
-                            const cplx P01 = cfma(U00, is01, cmul(U01, is11));
-                            const cplx P10 = cfma(U10, is00, cmul(U11, is01));
-                            const cplx P11 = cfma(U10, is01, cmul(U11, is11));
-                            catomic(&Zo0[cur_ac], cscale(P00, -1.0));
-                            catomic(&Zo1[cur_ac], cscale(P01, -1.0));
-                            catomic(&Zo2[cur_ac], cscale(P10, -1.0));
-                            catomic(&Zo3[cur_ac], cscale(P11, -1.0));
-                            A00 = cfma(P00, U00, cfma(P01, U01, A00));
-                            A01 = cfma(P00, U10, cfma(P01, U11, A01));
-                            A11 = cfma(P10, U10, cfma(P11, U11, A11));
-                            A02 = cfma(P00, W00, cfma(P01, W01, A02));
-                            A03 = cfma(P00, W10, cfma(P01, W11, A03));
-                            A12 = cfma(P10, W00, cfma(P11, W01, A12));
-                            A13 = cfma(P10, W10, cfma(P11, W11, A13));
-                            // rows b: P_b = W c_T Sc^{-1}
-                            const cplx P20 = cfma(W00, is00, cmul(W01, is01));
-                            const cplx P21 = cfma(W00, is01, cmul(W01, is11));
-                            const cplx P30 = cfma(W10, is00, cmul(W11, is01));
-                            const cplx P31 = cfma(W10, is01, cmul(W11, is11));
-                            catomic(&Zo0[cur_bc], cscale(P20, -1.0));
-                            catomic(&Zo1[cur_bc], cscale(P21, -1.0));
-                            catomic(&Zo2[cur_bc], cscale(P30, -1.0));
-                            catomic(&Zo3[cur_bc], cscale(P31, -1.0));
-                            A22 = cfma(P20, W00, cfma(P21, W01, A22));
-                            A23 = cfma(P20, W10, cfma(P21, W11, A23));
-                            A33 = cfma(P30, W10, cfma(P31, W11, A33));
+                            const cplx Q00 = cfnma(U00, is00, cmul(cneg(U01), is01));
+                            const cplx Q01 = cfnma(U00, is01, cmul(cneg(U01), is11));
+                            const cplx Q10 = cfnma(U10, is00, cmul(cneg(U11), is01));
+                            const cplx Q11 = cfnma(U10, is01, cmul(cneg(U11), is11));
+                            catomic(&Zo0[cur_ac], Q00);
+                            catomic(&Zo1[cur_ac], Q01);
+                            catomic(&Zo2[cur_ac], Q10);
+                            catomic(&Zo3[cur_ac], Q11);
+                            A00 = cfnma(Q00, U00, cfnma(Q01, U01, A00));
+                            A01 = cfnma(Q00, U10, cfnma(Q01, U11, A01));
+                            A11 = cfnma(Q10, U10, cfnma(Q11, U11, A11));
+                            A02 = cfnma(Q00, W00, cfnma(Q01, W01, A02));
+                            A03 = cfnma(Q00, W10, cfnma(Q01, W11, A03));
+                            A12 = cfnma(Q10, W00, cfnma(Q11, W01, A12));
+                            A13 = cfnma(Q10, W10, cfnma(Q11, W11, A13));
+                            // rows b: Q_b = -P_b = -W c_T Sc^{-1}
+                            const cplx Q20 = cfnma(W00, is00, cmul(cneg(W01), is01));
+                            const cplx Q21 = cfnma(W00, is01, cmul(cneg(W01), is11));
+                            const cplx Q30 = cfnma(W10, is00, cmul(cneg(W11), is01));
+                            const cplx Q31 = cfnma(W10, is01, cmul(cneg(W11), is11));
+                            catomic(&Zo0[cur_bc], Q20);
+                            catomic(&Zo1[cur_bc], Q21);
+                            catomic(&Zo2[cur_bc], Q30);
+                            catomic(&Zo3[cur_bc], Q31);
+                            A22 = cfnma(Q20, W00, cfnma(Q21, W01, A22));
+                            A23 = cfnma(Q20, W10, cfnma(Q21, W11, A23));
+                            A33 = cfnma(Q30, W10, cfnma(Q31, W11, A33));
                             cp = cadd(cp, ct);
                         }
                     }
@@ -595,7 +599,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 const int b = sidx < n ? sidx : sidx - n, qb = sidx < n ? 0 : 1;
                 const int lo = min(a, b), hi = max(a, b);
                 const int kq = a < b ? 2 * qa + qb : 2 * qb + qa;
-                const cplx *src = a == b ? Zd0 + (qa + qb) * n + a : Zo0 + kq * np + pair_pos<true>(n, lo, hi);
+                const cplx *src = a == b ? Zd0 + (qa + qb) * dstr + a : Zo0 + kq * ostr + pair_pos<true>(n, lo, hi);
                 const cplx zl = *(ok ? src : Zd0);
                 return ok ? zl : cmk(0.0, 0.0);
             };
