@@ -742,15 +742,24 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                     for (int rt = rt0; rt < rt1; ++rt) {
                         const int r = rt * 16 + l16;
                         dbl4 yre = {0.0, 0.0, 0.0, 0.0}, yim = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-                        for (int ks = 0; ks < KS; ++ks) {
-                            const int sidx = ks * 4 + lq;
-                            // r, sidx < 16 T: inside the zero-padded triangle
-                            const int lo = min(r, sidx), hi = max(r, sidx);
-                            const cplx z = Zp[hi * (hi + 1) / 2 + lo];
-                            const double v = Vt[jj * vs + sidx];
-                            yre = mfma4(z.re, v, yre);
-                            yim = mfma4(z.im, v, yim);
+                        // four k-steps per pass with the loads first (MFMAs keep
+                        // the compiler from unrolling the loop); steps past KS
+                        // read inside the padding (sidx < 16 T) and add zeros
+                        for (int ks0 = 0; ks0 < KS; ks0 += 4) {
+                            cplx z[4];
+                            double v[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int sidx = min((ks0 + u) * 4 + lq, 16 * T - 1);
+                                const int lo = min(r, sidx), hi = max(r, sidx);
+                                z[u] = Zp[hi * (hi + 1) / 2 + lo];
+                                v[u] = (ks0 + u) < KS ? Vt[jj * vs + sidx] : 0.0;
+                            }
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                yre = mfma4(z[u].re, v[u], yre);
+                                yim = mfma4(z[u].im, v[u], yim);
+                            }
                         }
                         // Re[hw dk_i dk_j X_ij] = sum_r Re[(hw dk_i V_ri) (dk_j Y_rj)]:
                         // the column factor scales Y in its accumulators, the row
