@@ -129,7 +129,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
         const RowPlan rp = rows[p];
         const long long vo = voff[p];
         const int mstride = cont_mbytes<C>(n) / 16;  // one slot, in complex fp64 units
-        const double *Vt;                       // N*N, eigenvector k contiguous
+        const double *Vt;                       // eigenvector k contiguous, row stride vs
         double *al;                             // N
         cplx *slots;                            // G x (2n^2 + 5n) complex
         int G = 1;
@@ -141,15 +141,25 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
             slots = cont_fixed() + 8 * N + cont_mbytes<C>(n) <= lds_bytes ? (cplx *)(al + N)
                                                                       : mscr + blockIdx.x * mscr_stride;
         } else {
+            // V and each slot's d zero-padded to whole tiles (no operand masks)
+            const int tp = cont_tp(n), vsp = tp + 1;
             double *vl = dyn;
-            al = vl + N * N;
+            al = vl + tp * vsp;
             slots = (cplx *)(al + N);
             G = gmax;
             while (G > 1 && cont_fixed() + cont_vbytes(n) + G * cont_mbytes<C>(n) > lds_bytes) G >>= 1;
-            for (int idx = tid; idx < N * N; idx += CONT_THREADS) vl[idx] = vt[vo + idx];
+            for (int idx = tid; idx < tp * vsp; idx += CONT_THREADS) {
+                const int k = idx / vsp, i = idx - k * vsp;
+                vl[idx] = k < N && i < N ? vt[vo + k * N + i] : 0.0;
+            }
+            for (int idx = tid; idx < G * (tp - N); idx += CONT_THREADS) {
+                const int sl = idx / (tp - N), k = N + idx - sl * (tp - N);
+                slots[sl * mstride + k] = cmk(0.0, 0.0);
+            }
             Vt = vl;
         }
         for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
+        const int vs = BIG ? N : cont_tp(n) + 1;
         const int Q = rp.K / 2 + 1;
         const int q0 = ch * qchunk, q1 = min(q0 + qchunk, Q);
         const int np = n * (n - 1) / 2;
@@ -199,7 +209,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                     int it, jt;
                     upper_tile(c - sl * ntile, it, jt);
                     const SlotMT<C> m = slot_view<C>(slots + sl * mstride, n);
-                    m_block_mfma<BS>(n, it, jt, Vt, N, m.d, m.d0, lane);
+                    m_block_mfma<BS, C, false, !BIG>(n, it, jt, Vt, vs, m.d, m.d0, lane);
                 }
             } else {
                 for (int idx = tid; idx < g * n; idx += CONT_THREADS) {
@@ -208,7 +218,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                     cplx m00 = cmk(0, 0), m01 = cmk(0, 0), m11 = cmk(0, 0);
 #pragma unroll 1
                     for (int k = 0; k < N; ++k) {
-                        const double v0 = Vt[k * N + a], v1 = Vt[k * N + n + a];
+                        const double v0 = Vt[k * vs + a], v1 = Vt[k * vs + n + a];
                         const cplx d = m.d[k];
                         const double p00 = v0 * v0, p01 = v0 * v1, p11 = v1 * v1;
                         m00.re = fma(p00, d.re, m00.re); m00.im = fma(p00, d.im, m00.im);

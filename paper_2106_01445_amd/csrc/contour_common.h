@@ -95,14 +95,22 @@ __device__ __forceinline__ cplxf crsqrt_p(cplxf z)
 constexpr int CONT_MAXG = 8;
 static_assert(CONT_MAXG <= CONT_THREADS / 64, "one wavefront per contour point of a pass");
 
-__host__ __device__ __forceinline__ int cont_vbytes(int n) { return 8 * (4 * n * n + 2 * n); }
-// per slot: d, z^{-1/2} (2n each), diagonal blocks (3n), off-diagonal (4 n(n-1)/2)
-// bytes of one slot: d and z^{-1/2} (fp64 complex, 2n each) and the 2x2 mode
-// blocks of M(w) (3n + 4 n(n-1)/2 entries of the block type C), 16-byte aligned
+// 2n rounded up to whole 16-wide tiles: rows kept in LDS hold V zero-padded to
+// cont_tp x cont_tp (row stride cont_tp + 1) and d zero-padded to cont_tp
+// entries, so that the M(w) tiles fetch their operands without masks
+__host__ __device__ __forceinline__ int cont_tp(int n) { return 16 * ((2 * n + 15) / 16); }
+// V (padded) and alpha (2n)
+__host__ __device__ __forceinline__ int cont_vbytes(int n)
+{
+    return 8 * (cont_tp(n) * (cont_tp(n) + 1) + 2 * n);
+}
+// bytes of one slot: d (fp64 complex, cont_tp entries), z^{-1/2} (2n) and the
+// 2x2 mode blocks of M(w) (3n + 4 n(n-1)/2 entries of the block type C),
+// 16-byte aligned
 template <class C = cplx>
 __host__ __device__ __forceinline__ int cont_mbytes(int n)
 {
-    return 16 * 4 * n + (((int)sizeof(C) * (2 * n * n + n) + 15) & ~15);
+    return 16 * (cont_tp(n) + 2 * n) + (((int)sizeof(C) * (2 * n * n + n) + 15) & ~15);
 }
 __host__ __device__ __forceinline__ int cont_fixed() { return 16 * (CONT_THREADS / 64) * 4 + 16 * CONT_MAXG; }
 
@@ -302,8 +310,8 @@ __device__ __forceinline__ SlotMT<C> slot_view(cplx *base, int n)
     const int N = 2 * n, np = n * (n - 1) / 2;
     SlotMT<C> m;
     m.d = base;
-    m.rz = base + N;
-    m.d0 = (C *)(base + 2 * N);
+    m.rz = base + cont_tp(n);
+    m.d0 = (C *)(m.rz + N);
     m.d1 = m.d0 + n;
     m.d2 = m.d1 + n;
     m.o0 = m.d2 + n;
