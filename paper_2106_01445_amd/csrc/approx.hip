@@ -204,7 +204,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                 // BIG: V comes from L2, so 2x2 blocks of tiles share each operand fetch
                 constexpr int BS = BIG ? 2 : 1;
                 const int T = (N + 16 * BS - 1) / (16 * BS), ntile = T * (T + 1) / 2;
-                for (int c = wid; c < g * ntile; c += CONT_THREADS / 64) {
+                // (dealt from the last wavefront down: wavefronts 0..g-1 form
+                // the G_0(w) products first)
+                for (int c = CONT_THREADS / 64 - 1 - wid; c < g * ntile; c += CONT_THREADS / 64) {
                     const int sl = c / ntile;
                     int it, jt;
                     upper_tile(c - sl * ntile, it, jt);

@@ -401,7 +401,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             if (ORDER >= 2) {
                 constexpr int BS = BIG ? 2 : 1;
                 const int TB = (N + 16 * BS - 1) / (16 * BS), nblk = TB * (TB + 1) / 2;
-                for (int u = wid; u < nblk; u += CONT_THREADS / 64) {
+                // (the tiles are dealt from the last wavefront down: wavefront 0
+                // forms G_0(w) first)
+                for (int u = CONT_THREADS / 64 - 1 - wid; u < nblk; u += CONT_THREADS / 64) {
                     int it, jt;
                     upper_tile(u, it, jt);
                     m_block_mfma<BS, cplx, true, !BIG, !BIG>(n, it, jt, Vt, vs, dk, Md0, lane);
