@@ -117,7 +117,7 @@ void plan_free_dev(gbs_plan *pl)
     void *ptrs[] = {pl->d_offsets, pl->d_modes, pl->d_perm, pl->d_voff, pl->d_alpha,
                     pl->d_v, pl->d_rows, pl->d_sw, pl->d_items, pl->d_counter,
                     pl->d_cluster_items, pl->d_cluster_off, pl->d_logp, pl->d_status,
-                    pl->d_asw, pl->d_aitems, pl->d_roff, pl->d_ritem0, pl->d_rscr,
+                    pl->d_asw, pl->d_aitems, pl->d_roff, pl->d_ritem0, pl->d_axq, pl->d_rscr,
                     pl->d_qibar, pl->d_qitmp, pl->d_grad, pl->d_dl, pl->d_wbig, pl->d_mscr,
                     pl->d_ascr};
     for (void *p : ptrs)
@@ -253,6 +253,7 @@ int adj_workspace(gbs_ctx *ctx, gbs_plan *pl)
     e = e ? e : dev_alloc(ctx, &pl->d_aitems, 2 * (size_t)P * chunks);
     e = e ? e : dev_alloc(ctx, &pl->d_roff, (size_t)P * chunks);
     e = e ? e : dev_alloc(ctx, &pl->d_ritem0, (size_t)P);
+    e = e ? e : dev_alloc(ctx, &pl->d_axq, (size_t)P * chunks);
     e = e ? e : dev_alloc(ctx, &pl->d_rscr, rtot);
     e = e ? e : dev_alloc(ctx, &pl->d_qibar, D * D);
     e = e ? e : dev_alloc(ctx, &pl->d_qitmp, D * D);
@@ -261,7 +262,7 @@ int adj_workspace(gbs_ctx *ctx, gbs_plan *pl)
         // larger rows: M(w), the pair blocks of Z(w) at order <= 2 and the panel
         // of Z V, per workgroup
         const long long nb = pl->max_n, npb = nb * (nb - 1) / 2;
-        pl->ascr_stride = 3 * nb + 4 * npb + (order <= 2 ? 4 * npb : 0) + 2 * nb * 33;
+        pl->ascr_stride = adj_big_mreg(nb, order) + (order <= 2 ? 4 * npb : 0) + 2 * nb * 33;
         pl->ascr_blocks = 2 * ctx->num_cu;
         e = e ? e : dev_alloc(ctx, &pl->d_ascr, (size_t)pl->ascr_blocks * pl->ascr_stride);
     }
@@ -505,7 +506,7 @@ int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
     e = e ? e : dev_alloc(ctx, &pl->d_rows, P);
     e = e ? e : dev_alloc(ctx, &pl->d_sw, (size_t)P * (order + 1) * GBS_QCAP);
     e = e ? e : dev_alloc(ctx, &pl->d_items, 2 * (size_t)max_items);
-    e = e ? e : dev_alloc(ctx, &pl->d_counter, 8);
+    e = e ? e : dev_alloc(ctx, &pl->d_counter, GBS_NCOUNTER);
     e = e ? e : dev_alloc(ctx, &pl->d_wbig, 2 * pl->v_total);
     if (pl->nbig > 0) {
         // M(w) of rows whose blocks do not fit in LDS: one copy per workgroup

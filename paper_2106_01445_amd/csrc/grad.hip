@@ -268,7 +268,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
     const RowPlan *__restrict__ rows, const int *__restrict__ items, const int *__restrict__ q_end,
     int *__restrict__ q_head, const int *__restrict__ units, const int *__restrict__ unit_off,
     const cplx *__restrict__ asw, const long long *__restrict__ roff, double *__restrict__ rscr,
-    cplx *__restrict__ ascr, long long ascr_stride)
+    cplx *__restrict__ ascr, long long ascr_stride, const int *__restrict__ xq)
 {
     extern __shared__ double sh[];
     __shared__ int s_item;
@@ -278,13 +278,31 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
     double *dyn = (double *)(red + CONT_THREADS / 64 + 8);
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
-    const int total = *q_end;
+    const int total = BIG ? 0 : *q_end;
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(q_head, 1);
+        if (tid == 0) {
+            if (BIG) {
+                // larger rows: the queue of this workgroup's XCD first (workgroups
+                // are dealt to the XCDs in turn), so that the rows in flight on
+                // an XCD, whose V is read from its L2 at every point, are few;
+                // the other XCDs' queues once it is empty (q_head: heads, q_end:
+                // lengths then offsets, GBS_NXCD each)
+                int it = -1;
+                for (int d = 0; d < GBS_NXCD && it < 0; ++d) {
+                    const int x = (blockIdx.x + d) % GBS_NXCD;
+                    if (atomicAdd(&q_head[x], 0) >= q_end[x]) continue;
+                    const int h = atomicAdd(&q_head[x], 1);
+                    if (h < q_end[x]) it = xq[q_end[GBS_NXCD + x] + h];
+                }
+                s_item = it;
+            } else {
+                s_item = atomicAdd(q_head, 1);
+            }
+        }
         __syncthreads();
         const int item = s_item;
         __syncthreads();
-        if (item >= total) break;
+        if (BIG ? item < 0 : item >= total) break;
         const int p = items[2 * item], ch = items[2 * item + 1];
         const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
         const RowPlan rp = rows[p];
@@ -310,7 +328,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 Zo0 = Zd0 + 3 * n;
                 Yp = Md0 + 3 * n + 4 * np;
             } else {
-                Zo0 = Md0 + 3 * n + 4 * np;
+                Zo0 = Md0 + adj_big_mreg(n, ORDER);
                 Yp = Zo0 + 4 * np;
             }
         } else {
@@ -605,6 +623,40 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 const cplx zl = *(ok ? src : Zd0);
                 return ok ? zl : cmk(0.0, 0.0);
             };
+            // order <= 2: the pair blocks of Z are in this workgroup's HBM scratch;
+            // copy Z once into the packed triangle Zb over the M(w) region (not
+            // read again for this point), Zb[j (j + 1) / 2 + i] = Z(i, j), i <= j,
+            // zero beyond 2n, so that the Z V rounds read it in 64-byte runs
+            cplx *Zb = Md0;
+            if (BIG && ORDER <= 2) {
+                const int TT = 16 * T;
+                // (columns j and 16T-1-j together: 16T+1 entries, all of a
+                // wavefront's reads issued before its writes)
+                constexpr int NC = (2 * GBS_MAX_N_APPROX + 1 + 63) / 64;
+                for (int j = wid; j < TT / 2; j += CONT_THREADS / 64) {
+                    cplx zv[NC];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        const int k = lane + 64 * c;
+                        const int i = k <= j ? k : k - j - 1, col = k <= j ? j : TT - 1 - j;
+                        zv[c] = k <= TT ? zget(i, col) : cmk(0.0, 0.0);
+                    }
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        const int k = lane + 64 * c;
+                        const int i = k <= j ? k : k - j - 1, col = k <= j ? j : TT - 1 - j;
+                        if (k <= TT) Zb[col * (col + 1) / 2 + i] = zv[c];
+                    }
+                }
+                __syncthreads();
+            }
+            // Z(r, s) for the Z V rounds
+            auto zrd = [&](int r, int sidx) {
+                if (ORDER >= 3) return zget(r, sidx);
+                const int lo = min(r, sidx), hi = max(r, sidx);
+                const cplx zl = Zb[hi < 16 * T ? hi * (hi + 1) / 2 + lo : 0];
+                return hi < 16 * T ? zl : cmk(0.0, 0.0);
+            };
             for (int jr = 0; BIG && jr < T; jr += 2) {
                 const int nj = min(2, T - jr);
                 {
@@ -622,7 +674,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
 #pragma unroll 2
                         for (int ks = 0; ks < KS; ++ks) {
                             const int sidx = ks * 4 + lq;
-                            const cplx z0 = zget(r0, sidx), z1 = zget(r1, sidx);
+                            const cplx z0 = zrd(r0, sidx), z1 = zrd(r1, sidx);
                             const bool v0ok = j0 < N && sidx < N, v1ok = j1 < N && sidx < N;
                             const double v0l = Vt[v0ok ? j0 * vs + sidx : 0], v1l = Vt[v1ok ? j1 * vs + sidx : 0];
                             const double v0 = v0ok ? v0l : 0.0, v1 = v1ok ? v1l : 0.0;
@@ -833,7 +885,8 @@ __global__ __launch_bounds__(1024) void k_adj_items(int P, int nbig, const int *
                                                     const int *__restrict__ perm,
                                                     const RowPlan *__restrict__ rows,
                                                     int *__restrict__ items, long long *__restrict__ roff,
-                                                    int *__restrict__ row_item0, int *__restrict__ counter)
+                                                    int *__restrict__ row_item0, int *__restrict__ counter,
+                                                    int *__restrict__ xq)
 {
     __shared__ int part[1024];
     __shared__ long long lpart[1024];
@@ -899,6 +952,27 @@ __global__ __launch_bounds__(1024) void k_adj_items(int P, int nbig, const int *
         }
         off += c;
         loff += c * sz;
+    }
+    // the larger rows' items by XCD queue: row i (in plan order) to queue
+    // i % GBS_NXCD, its chunks together, rows in plan order (largest first)
+    __shared__ int xcnt[GBS_NXCD];
+    __syncthreads();
+    if (tid < GBS_NXCD) {
+        int c = 0;
+        for (int i = tid; i < nbig; i += GBS_NXCD) c += nch(i);
+        xcnt[tid] = c;
+    }
+    __syncthreads();
+    if (tid < GBS_NXCD) {
+        int o = 0;
+        for (int x = 0; x < tid; ++x) o += xcnt[x];
+        counter[8 + tid] = 0;
+        counter[8 + GBS_NXCD + tid] = xcnt[tid];
+        counter[8 + 2 * GBS_NXCD + tid] = o;
+        for (int i = tid; i < nbig; i += GBS_NXCD) {
+            const int c = nch(i), i0 = row_item0[perm[i]];
+            for (int k = 0; k < c; ++k) xq[o++] = i0 + k;
+        }
     }
 }
 
@@ -1124,7 +1198,7 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_ADJ_CLUSTER);
     hipLaunchKernelGGL(k_adj_items, dim3(1), dim3(1024), 0, st, P, pl->nbig, pl->d_offsets, pl->d_perm,
-                       pl->d_rows, pl->d_aitems, pl->d_roff, pl->d_ritem0, pl->d_counter);
+                       pl->d_rows, pl->d_aitems, pl->d_roff, pl->d_ritem0, pl->d_counter, pl->d_axq);
     if (pl->nbig > 0) {
         // larger rows: V and M(w) in HBM, Z(w) (all of it at order 3, its diagonal
         // blocks otherwise) in LDS
@@ -1142,9 +1216,9 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
         int grid = std::min(occ * ctx->num_cu, pl->ascr_blocks);
         hipLaunchKernelGGL((k_adj_contour<ORDER, true>), dim3(grid), dim3(CONT_THREADS), lds_b, st,
                            pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_aitems,
-                           pl->d_counter + 6, pl->d_counter + 7,
+                           pl->d_counter + 8 + GBS_NXCD, pl->d_counter + 8,
                            pl->d_cluster_items, pl->d_cluster_off + 2 * (pl->max_n + 1), pl->d_asw,
-                           pl->d_roff, pl->d_rscr, pl->d_ascr, pl->ascr_stride);
+                           pl->d_roff, pl->d_rscr, pl->d_ascr, pl->ascr_stride, pl->d_axq);
     }
     const int ns = pl->max_n_small;
     if (pl->nbig < P) {
@@ -1163,7 +1237,7 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
                            lds_a, st, pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows,
                            pl->d_aitems, pl->d_counter + 2, pl->d_counter + 3,
                            pl->d_cluster_items, pl->d_cluster_off + 2 * (pl->max_n + 1), pl->d_asw,
-                           pl->d_roff, pl->d_rscr, (cplx *)nullptr, 0LL);
+                           pl->d_roff, pl->d_rscr, (cplx *)nullptr, 0LL, (const int *)nullptr);
     }
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_ADJ_ROWS);

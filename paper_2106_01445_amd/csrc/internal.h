@@ -22,6 +22,20 @@
 #define GBS_QCHUNK 8           // contour points per work item (default)
 #define GBS_QCHUNK_MIN 4       // smallest tunable value (sizes the item lists)
 #define GBS_QCHUNK_MAX 64      // largest tunable value
+// Work-queue counters of a plan: [0..7] the forward and backward queues,
+// [8..15] heads, [16..23] lengths and [24..31] offsets of the backward queues
+// of the larger rows, one per XCD
+#define GBS_NXCD 8
+#define GBS_NCOUNTER (8 + 3 * GBS_NXCD)
+// Rows above GBS_NSMALL clicks, adjoint at order <= 2: the per-workgroup HBM
+// region of M(w) (3n + 4 n(n-1)/2 complex) also holds Z(w) as the packed upper
+// triangle of a 16T x 16T matrix (T = ceil(2n/16), zero beyond 2n) once the
+// cluster sums are done, so it is sized for both.
+__host__ __device__ inline long long adj_big_mreg(long long n, int order)
+{
+    const long long m = 3 * n + 2 * n * (n - 1), t = (2 * n + 15) / 16, zp = 8 * t * (16 * t + 1);
+    return order <= 2 && zp > m ? zp : m;
+}
 #define GBS_CLUSTER_SEG 3      // triples per cluster work unit at order 3 (default)
 
 struct cplx {
@@ -122,6 +136,7 @@ struct gbs_plan {
     int32_t *d_aitems = nullptr;          // backward work items (row, chunk)
     long long *d_roff = nullptr;          // per item: offset of its R in d_rscr
     int32_t *d_ritem0 = nullptr;          // per row: first backward item
+    int32_t *d_axq = nullptr;             // backward items of the larger rows by XCD queue
     double *d_rscr = nullptr;             // per item: upper triangle of R
     double *d_qibar = nullptr;            // (2M)^2: Psi (adjoint of Q^{-1}), then sigma_bar
     double *d_qitmp = nullptr;            // (2M)^2 scratch
