@@ -259,10 +259,10 @@ int adj_workspace(gbs_ctx *ctx, gbs_plan *pl)
     e = e ? e : dev_alloc(ctx, &pl->d_qitmp, D * D);
     if (!pl->d_grad) e = e ? e : dev_alloc(ctx, &pl->d_grad, D);
     if (pl->nbig > 0) {
-        // larger rows: M(w), the pair blocks of Z(w) at order <= 2 and the panel
-        // of Z V, per workgroup
+        // larger rows: M(w), the pair blocks of Z(w) at order <= 2 and Z V, per
+        // workgroup
         const long long nb = pl->max_n, npb = nb * (nb - 1) / 2;
-        pl->ascr_stride = adj_big_mreg(nb, order) + (order <= 2 ? 4 * npb : 0) + 2 * nb * 33;
+        pl->ascr_stride = adj_big_mreg(nb, order) + (order <= 2 ? 4 * npb : 0) + 2 * nb * (32 * ((2 * nb + 31) / 32));
         pl->ascr_blocks = 2 * ctx->num_cu;
         e = e ? e : dev_alloc(ctx, &pl->d_ascr, (size_t)pl->ascr_blocks * pl->ascr_stride);
     }

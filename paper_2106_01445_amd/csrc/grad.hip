@@ -208,10 +208,8 @@ __host__ __device__ __forceinline__ int adj_need(int)
     return 8 * (ADJ_TP * ADJ_VS + ADJ_TP) + 16 * (2 * ADJ_TP + 2 * ADJ_MREG);
 }
 __host__ __device__ __forceinline__ int adj_fixed() { return 16 * (CONT_THREADS / 64 + 8); }
-// Larger rows form Y = Z V by column panels of ADJ_PW columns (row stride
-// ADJ_PWS, complex) in their HBM scratch.
-#define ADJ_PW 32
-#define ADJ_PWS 33
+// Larger rows form Y = Z V in their HBM scratch (row stride 32 ceil(2n/32),
+// complex).
 
 // Rows of at most 40 clicks (2n <= 80, at most ADJ_TMAX 16-wide tiles) form
 // V^T Z V by column units: unit u of a row with T tiles covers column tile jt
@@ -657,101 +655,103 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 const cplx zl = Zb[hi < 16 * T ? hi * (hi + 1) / 2 + lo : 0];
                 return hi < 16 * T ? zl : cmk(0.0, 0.0);
             };
-            for (int jr = 0; BIG && jr < T; jr += 2) {
-                const int nj = min(2, T - jr);
-                {
-                    // V comes from L2: 2x2 blocks of tiles share each operand fetch.
-                    // Y for the round's two column tiles, one 32-row block per chain.
-                    const int TB = (T + 1) / 2;
-                    for (int rb = wid; rb < TB; rb += CONT_THREADS / 64) {
-                        dbl4 yre[2][2], yim[2][2];
+            if (BIG) {
+                // Y = Z V for all 32 x 32 blocks (rb, cb), then X = V^T Y for the
+                // upper blocks (ib <= jb), each phase dealt over all the
+                // wavefronts; V comes from L2 (2x2 tiles share each operand
+                // fetch), Y goes to this workgroup's HBM panel (row stride
+                // 32 TB), and R is read-modified-written in the item's HBM slot
+                // (each entry has one writer per point)
+                const int TB = (T + 1) / 2, YS = 32 * TB;
+                for (int u = wid; u < TB * TB; u += CONT_THREADS / 64) {
+                    const int rb = u / TB, cb = u - rb * TB;
+                    dbl4 yre[2][2], yim[2][2];
 #pragma unroll
-                        for (int u = 0; u < 2; ++u)
+                    for (int a = 0; a < 2; ++a)
 #pragma unroll
-                            for (int t = 0; t < 2; ++t) yre[u][t] = yim[u][t] = dbl4{0.0, 0.0, 0.0, 0.0};
-                        const int r0 = (2 * rb) * 16 + l16, r1 = r0 + 16;
-                        const int j0 = jr * 16 + l16, j1 = j0 + 16;
+                        for (int t = 0; t < 2; ++t) yre[a][t] = yim[a][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+                    const int r0 = (2 * rb) * 16 + l16, r1 = r0 + 16;
+                    const int j0 = (2 * cb) * 16 + l16, j1 = j0 + 16;
 #pragma unroll 2
-                        for (int ks = 0; ks < KS; ++ks) {
-                            const int sidx = ks * 4 + lq;
-                            const cplx z0 = zrd(r0, sidx), z1 = zrd(r1, sidx);
-                            const bool v0ok = j0 < N && sidx < N, v1ok = j1 < N && sidx < N;
-                            const double v0l = Vt[v0ok ? j0 * vs + sidx : 0], v1l = Vt[v1ok ? j1 * vs + sidx : 0];
-                            const double v0 = v0ok ? v0l : 0.0, v1 = v1ok ? v1l : 0.0;
-                            yre[0][0] = mfma4(z0.re, v0, yre[0][0]);
-                            yim[0][0] = mfma4(z0.im, v0, yim[0][0]);
-                            yre[0][1] = mfma4(z0.re, v1, yre[0][1]);
-                            yim[0][1] = mfma4(z0.im, v1, yim[0][1]);
-                            yre[1][0] = mfma4(z1.re, v0, yre[1][0]);
-                            yim[1][0] = mfma4(z1.im, v0, yim[1][0]);
-                            yre[1][1] = mfma4(z1.re, v1, yre[1][1]);
-                            yim[1][1] = mfma4(z1.im, v1, yim[1][1]);
-                        }
-#pragma unroll
-                        for (int u = 0; u < 2; ++u)
-#pragma unroll
-                            for (int t = 0; t < 2; ++t)
-#pragma unroll
-                                for (int e = 0; e < 4; ++e) {
-                                    const int row = (2 * rb + u) * 16 + 4 * e + lq;
-                                    if (row < N && t < nj)
-                                        Yp[row * ADJ_PWS + t * 16 + l16] = cmk(yre[u][t][e], yim[u][t][e]);
-                                }
+                    for (int ks = 0; ks < KS; ++ks) {
+                        const int sidx = ks * 4 + lq;
+                        const cplx z0 = zrd(r0, sidx), z1 = zrd(r1, sidx);
+                        const bool v0ok = j0 < N && sidx < N, v1ok = j1 < N && sidx < N;
+                        const double v0l = Vt[v0ok ? j0 * vs + sidx : 0], v1l = Vt[v1ok ? j1 * vs + sidx : 0];
+                        const double v0 = v0ok ? v0l : 0.0, v1 = v1ok ? v1l : 0.0;
+                        yre[0][0] = mfma4(z0.re, v0, yre[0][0]);
+                        yim[0][0] = mfma4(z0.im, v0, yim[0][0]);
+                        yre[0][1] = mfma4(z0.re, v1, yre[0][1]);
+                        yim[0][1] = mfma4(z0.im, v1, yim[0][1]);
+                        yre[1][0] = mfma4(z1.re, v0, yre[1][0]);
+                        yim[1][0] = mfma4(z1.im, v0, yim[1][0]);
+                        yre[1][1] = mfma4(z1.re, v1, yre[1][1]);
+                        yim[1][1] = mfma4(z1.im, v1, yim[1][1]);
                     }
-                    __syncthreads();
-                    // X = V^T Y for the upper tiles of the round's column block, by
-                    // 2x2 blocks (ib, jr / 2); R read-modified-written in the item's
-                    // HBM slot (each entry has one writer per round)
-                    for (int ib = wid; ib <= jr / 2; ib += CONT_THREADS / 64) {
-                        dbl4 xre[2][2], xim[2][2];
 #pragma unroll
-                        for (int u = 0; u < 2; ++u)
+                    for (int a = 0; a < 2; ++a)
 #pragma unroll
-                            for (int t = 0; t < 2; ++t) xre[u][t] = xim[u][t] = dbl4{0.0, 0.0, 0.0, 0.0};
-                        const int i0 = (2 * ib) * 16 + l16, i1 = i0 + 16;
+                        for (int t = 0; t < 2; ++t)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const int row = (2 * rb + a) * 16 + 4 * e + lq;
+                                if (row < N) Yp[row * YS + (2 * cb + t) * 16 + l16] = cmk(yre[a][t][e], yim[a][t][e]);
+                            }
+                }
+                __syncthreads();
+                for (int u = wid; u < TB * (TB + 1) / 2; u += CONT_THREADS / 64) {
+                    int ib, jb;
+                    upper_tile(u, ib, jb);
+                    dbl4 xre[2][2], xim[2][2];
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int t = 0; t < 2; ++t) xre[a][t] = xim[a][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+                    const int i0 = (2 * ib) * 16 + l16, i1 = i0 + 16;
+                    const int c0 = (2 * jb) * 16 + l16;
 #pragma unroll 2
-                        for (int ks = 0; ks < KS; ++ks) {
-                            const int sidx = ks * 4 + lq;
-                            const bool sok = sidx < N, a0ok = sok && i0 < N, a1ok = sok && i1 < N;
-                            const double a0l = Vt[a0ok ? i0 * vs + sidx : 0], a1l = Vt[a1ok ? i1 * vs + sidx : 0];
-                            const double a0 = a0ok ? a0l : 0.0, a1 = a1ok ? a1l : 0.0;
-                            const cplx y0l = Yp[sok ? sidx * ADJ_PWS + l16 : 0];
-                            const cplx y1l = Yp[sok && nj > 1 ? sidx * ADJ_PWS + 16 + l16 : 0];
-                            const cplx y0 = sok ? y0l : cmk(0.0, 0.0);
-                            const cplx y1 = (sok && nj > 1) ? y1l : cmk(0.0, 0.0);
-                            xre[0][0] = mfma4(a0, y0.re, xre[0][0]);
-                            xim[0][0] = mfma4(a0, y0.im, xim[0][0]);
-                            xre[0][1] = mfma4(a0, y1.re, xre[0][1]);
-                            xim[0][1] = mfma4(a0, y1.im, xim[0][1]);
-                            xre[1][0] = mfma4(a1, y0.re, xre[1][0]);
-                            xim[1][0] = mfma4(a1, y0.im, xim[1][0]);
-                            xre[1][1] = mfma4(a1, y1.re, xre[1][1]);
-                            xim[1][1] = mfma4(a1, y1.im, xim[1][1]);
-                        }
+                    for (int ks = 0; ks < KS; ++ks) {
+                        const int sidx = ks * 4 + lq;
+                        const bool sok = sidx < N, a0ok = sok && i0 < N, a1ok = sok && i1 < N;
+                        const double a0l = Vt[a0ok ? i0 * vs + sidx : 0], a1l = Vt[a1ok ? i1 * vs + sidx : 0];
+                        const double a0 = a0ok ? a0l : 0.0, a1 = a1ok ? a1l : 0.0;
+                        // (columns of Y beyond 2n hold zeros written above)
+                        const cplx y0l = Yp[sok ? sidx * YS + c0 : 0];
+                        const cplx y1l = Yp[sok ? sidx * YS + c0 + 16 : 0];
+                        const cplx y0 = sok ? y0l : cmk(0.0, 0.0);
+                        const cplx y1 = sok ? y1l : cmk(0.0, 0.0);
+                        xre[0][0] = mfma4(a0, y0.re, xre[0][0]);
+                        xim[0][0] = mfma4(a0, y0.im, xim[0][0]);
+                        xre[0][1] = mfma4(a0, y1.re, xre[0][1]);
+                        xim[0][1] = mfma4(a0, y1.im, xim[0][1]);
+                        xre[1][0] = mfma4(a1, y0.re, xre[1][0]);
+                        xim[1][0] = mfma4(a1, y0.im, xim[1][0]);
+                        xre[1][1] = mfma4(a1, y1.re, xre[1][1]);
+                        xim[1][1] = mfma4(a1, y1.im, xim[1][1]);
+                    }
 #pragma unroll
-                        for (int u = 0; u < 2; ++u)
+                    for (int a = 0; a < 2; ++a)
 #pragma unroll
-                            for (int t = 0; t < 2; ++t) {
-                                const int jj = (jr + t) * 16 + l16;
+                        for (int t = 0; t < 2; ++t) {
+                            const int jj = (2 * jb + t) * 16 + l16;
 #pragma unroll
-                                for (int e = 0; e < 4; ++e) {
-                                    const int ii = (2 * ib + u) * 16 + 4 * e + lq;
-                                    if (ii <= jj && jj < N) {
-                                        const cplx f = cmul(hw, cmul(dk[ii], dk[jj]));
-                                        double add = f.re * xre[u][t][e] - f.im * xim[u][t][e];
-                                        if (ii == jj) {
-                                            const double dr = 1.0 / (1.0 + rp.rho * (al[ii] - 1.0));
-                                            const cplx tt = cmk(0.5 * rp.rho * dr - hw.re * dk[ii].re + hw.im * dk[ii].im,
-                                                                -(hw.re * dk[ii].im + hw.im * dk[ii].re));
-                                            add += beta.re * tt.re - beta.im * tt.im;
-                                        }
-                                        rscr[ro + (long long)jj * (jj + 1) / 2 + ii] += add;
+                            for (int e = 0; e < 4; ++e) {
+                                const int ii = (2 * ib + a) * 16 + 4 * e + lq;
+                                if (ii <= jj && jj < N) {
+                                    const cplx f = cmul(hw, cmul(dk[ii], dk[jj]));
+                                    double add = f.re * xre[a][t][e] - f.im * xim[a][t][e];
+                                    if (ii == jj) {
+                                        const double dr = 1.0 / (1.0 + rp.rho * (al[ii] - 1.0));
+                                        const cplx tt = cmk(0.5 * rp.rho * dr - hw.re * dk[ii].re + hw.im * dk[ii].im,
+                                                            -(hw.re * dk[ii].im + hw.im * dk[ii].re));
+                                        add += beta.re * tt.re - beta.im * tt.im;
                                     }
+                                    rscr[ro + (long long)jj * (jj + 1) / 2 + ii] += add;
                                 }
                             }
-                    }
-                    __syncthreads();
+                        }
                 }
+                __syncthreads();
             }
             if (!BIG) {
                 // Z into the packed triangle Zp over the M(w) blocks (not read
