@@ -262,7 +262,7 @@ int adj_workspace(gbs_ctx *ctx, gbs_plan *pl)
         // larger rows: M(w), the pair blocks of Z(w) at order <= 2 and Z V, per
         // workgroup
         const long long nb = pl->max_n, npb = nb * (nb - 1) / 2;
-        pl->ascr_stride = adj_big_mreg(nb, order) + (order <= 2 ? 4 * npb : 0) + 2 * nb * (32 * ((2 * nb + 31) / 32));
+        pl->ascr_stride = 3 * nb + 4 * npb + (order <= 2 ? 4 * npb : 0) + 2 * nb * (32 * ((2 * nb + 31) / 32));
         pl->ascr_blocks = 2 * ctx->num_cu;
         e = e ? e : dev_alloc(ctx, &pl->d_ascr, (size_t)pl->ascr_blocks * pl->ascr_stride);
     }

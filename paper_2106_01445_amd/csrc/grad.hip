@@ -314,7 +314,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         const int vs = BIG ? N : ADJ_VS;
         const double *Vt;
         double *al;
-        cplx *dk, *rz, *Md0, *Zd0, *Zo0, *Yp;
+        cplx *dk, *rz, *Md0, *Zd0, *Zo0, *Yp, *Zs = nullptr;
         if (BIG) {
             Vt = vt + vo;
             al = dyn;
@@ -326,8 +326,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 Zo0 = Zd0 + 3 * n;
                 Yp = Md0 + 3 * n + 4 * np;
             } else {
-                Zo0 = Md0 + adj_big_mreg(n, ORDER);
+                Zo0 = Md0 + 3 * n + 4 * np;
                 Yp = Zo0 + 4 * np;
+                Zs = Zd0 + 3 * n;
             }
         } else {
             double *vl = dyn;
@@ -621,40 +622,6 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 const cplx zl = *(ok ? src : Zd0);
                 return ok ? zl : cmk(0.0, 0.0);
             };
-            // order <= 2: the pair blocks of Z are in this workgroup's HBM scratch;
-            // copy Z once into the packed triangle Zb over the M(w) region (not
-            // read again for this point), Zb[j (j + 1) / 2 + i] = Z(i, j), i <= j,
-            // zero beyond 2n, so that the Z V rounds read it in 64-byte runs
-            cplx *Zb = Md0;
-            if (BIG && ORDER <= 2) {
-                const int TT = 16 * T;
-                // (columns j and 16T-1-j together: 16T+1 entries, all of a
-                // wavefront's reads issued before its writes)
-                constexpr int NC = (2 * GBS_MAX_N_APPROX + 1 + 63) / 64;
-                for (int j = wid; j < TT / 2; j += CONT_THREADS / 64) {
-                    cplx zv[NC];
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) {
-                        const int k = lane + 64 * c;
-                        const int i = k <= j ? k : k - j - 1, col = k <= j ? j : TT - 1 - j;
-                        zv[c] = k <= TT ? zget(i, col) : cmk(0.0, 0.0);
-                    }
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) {
-                        const int k = lane + 64 * c;
-                        const int i = k <= j ? k : k - j - 1, col = k <= j ? j : TT - 1 - j;
-                        if (k <= TT) Zb[col * (col + 1) / 2 + i] = zv[c];
-                    }
-                }
-                __syncthreads();
-            }
-            // Z(r, s) for the Z V rounds
-            auto zrd = [&](int r, int sidx) {
-                if (ORDER >= 3) return zget(r, sidx);
-                const int lo = min(r, sidx), hi = max(r, sidx);
-                const cplx zl = Zb[hi < 16 * T ? hi * (hi + 1) / 2 + lo : 0];
-                return hi < 16 * T ? zl : cmk(0.0, 0.0);
-            };
             if (BIG) {
                 // Y = Z V for all 32 x 32 blocks (rb, cb), then X = V^T Y for the
                 // upper blocks (ib <= jb), each phase dealt over all the
@@ -663,8 +630,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 // 32 TB), and R is read-modified-written in the item's HBM slot
                 // (each entry has one writer per point)
                 const int TB = (T + 1) / 2, YS = 32 * TB;
-                for (int u = wid; u < TB * TB; u += CONT_THREADS / 64) {
-                    const int rb = u / TB, cb = u - rb * TB;
+                auto yblock = [&](int rb, int cb, auto zfn) {
                     dbl4 yre[2][2], yim[2][2];
 #pragma unroll
                     for (int a = 0; a < 2; ++a)
@@ -675,7 +641,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
 #pragma unroll 2
                     for (int ks = 0; ks < KS; ++ks) {
                         const int sidx = ks * 4 + lq;
-                        const cplx z0 = zrd(r0, sidx), z1 = zrd(r1, sidx);
+                        const cplx z0 = zfn(r0, sidx), z1 = zfn(r1, sidx);
                         const bool v0ok = j0 < N && sidx < N, v1ok = j1 < N && sidx < N;
                         const double v0l = Vt[v0ok ? j0 * vs + sidx : 0], v1l = Vt[v1ok ? j1 * vs + sidx : 0];
                         const double v0 = v0ok ? v0l : 0.0, v1 = v1ok ? v1l : 0.0;
@@ -697,6 +663,25 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                                 const int row = (2 * rb + a) * 16 + 4 * e + lq;
                                 if (row < N) Yp[row * YS + (2 * cb + t) * 16 + l16] = cmk(yre[a][t][e], yim[a][t][e]);
                             }
+                };
+                if (ORDER >= 3) {
+                    // Z is in LDS
+                    for (int u = wid; u < TB * TB; u += CONT_THREADS / 64) yblock(u / TB, u % TB, zget);
+                } else {
+                    // the pair blocks of Z are in this workgroup's HBM scratch:
+                    // each 32-row block of Z is gathered once into LDS (Zs, row
+                    // stride 4 KS + 1, zero beyond 2n) and serves all its Y blocks
+                    const int ZS = 4 * KS + 1;
+                    for (int rb = 0; rb < TB; ++rb) {
+                        for (int idx = tid; idx < 32 * 4 * KS; idx += CONT_THREADS) {
+                            const int rr = idx / (4 * KS), sc = idx - rr * (4 * KS);
+                            Zs[rr * ZS + sc] = zget(32 * rb + rr, sc);
+                        }
+                        __syncthreads();
+                        for (int cb = wid; cb < TB; cb += CONT_THREADS / 64)
+                            yblock(rb, cb, [&](int r, int sidx) { return Zs[(r - 32 * rb) * ZS + sidx]; });
+                        __syncthreads();
+                    }
                 }
                 __syncthreads();
                 for (int u = wid; u < TB * (TB + 1) / 2; u += CONT_THREADS / 64) {
@@ -1201,13 +1186,13 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
                        pl->d_rows, pl->d_aitems, pl->d_roff, pl->d_ritem0, pl->d_counter, pl->d_axq);
     if (pl->nbig > 0) {
         // larger rows: V and M(w) in HBM, Z(w) (all of it at order 3, its diagonal
-        // blocks otherwise) in LDS
+        // blocks and a 32-row block of it otherwise) in LDS
         const void *fn = (const void *)k_adj_contour<ORDER, true>;
         int lds_static = 0;
         if (int rc = func_static_lds(ctx, fn, &lds_static)) return rc;
         const int nb = nmax, npb = nb * (nb - 1) / 2;
         const int lds_b = adj_fixed() + 8 * 2 * nb + 16 * 2 * 2 * nb + 16 * 3 * nb +
-                          (ORDER >= 3 ? 16 * 4 * npb : 0);
+                          (ORDER >= 3 ? 16 * 4 * npb : 16 * 32 * (4 * ((2 * nb + 3) / 4) + 1));
         if (lds_b + lds_static > ctx->lds_per_block)
             return set_err(ctx, GBS_E_INVAL, "rows too large for the gradient kernel's LDS");
         int occ = 1;

@@ -27,15 +27,6 @@
 // of the larger rows, one per XCD
 #define GBS_NXCD 8
 #define GBS_NCOUNTER (8 + 3 * GBS_NXCD)
-// Rows above GBS_NSMALL clicks, adjoint at order <= 2: the per-workgroup HBM
-// region of M(w) (3n + 4 n(n-1)/2 complex) also holds Z(w) as the packed upper
-// triangle of a 16T x 16T matrix (T = ceil(2n/16), zero beyond 2n) once the
-// cluster sums are done, so it is sized for both.
-__host__ __device__ inline long long adj_big_mreg(long long n, int order)
-{
-    const long long m = 3 * n + 2 * n * (n - 1), t = (2 * n + 15) / 16, zp = 8 * t * (16 * t + 1);
-    return order <= 2 && zp > m ? zp : m;
-}
 #define GBS_CLUSTER_SEG 3      // triples per cluster work unit at order 3 (default)
 
 struct cplx {
