@@ -138,8 +138,10 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
             // this workgroup's HBM scratch
             Vt = vt + vo;
             al = dyn;
-            slots = cont_fixed() + 8 * N + cont_mbytes<C>(n) <= lds_bytes ? (cplx *)(al + N)
-                                                                      : mscr + blockIdx.x * mscr_stride;
+            // (order 2: only d, rz and the diagonal blocks are stored, in LDS)
+            slots = ORDER == 2 || cont_fixed() + 8 * N + cont_mbytes<C>(n) <= lds_bytes
+                        ? (cplx *)(al + N)
+                        : mscr + blockIdx.x * mscr_stride;
         } else {
             // V and each slot's d zero-padded to whole tiles (no operand masks)
             const int tp = cont_tp(n), vsp = tp + 1;
@@ -200,7 +202,93 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
             // M(w) = V diag(d) V^T: at order >= 2 every 2x2 mode block, as the upper
             // 16x16 tiles of the 2n x 2n matrix on the matrix cores (one wavefront
             // per (slot, tile)); at order 1 only the diagonal blocks
-            if (ORDER >= 2) {
+            static_assert(GBS_MAX_N_APPROX <= 16 * (CONT_THREADS / 64), "one diagonal mode block per wavefront");
+            cplx s2f = cmk(0.0, 0.0);  // pair sums of the fused order-2 path below
+            if (ORDER == 2 && BIG) {
+                // Order 2, V read from L2: M(w) is never stored whole.  For a 16 x 16
+                // block (I, J) of modes the four quadrant products x_a x_b, x_a p_b,
+                // p_a x_b and p_a p_b land in the same accumulator positions, so each
+                // lane holds the whole 2x2 block of its pairs (a, b) (row a = 16 I +
+                // 4e + l/16, column b = 16 J + l%16).  The diagonal blocks (I = I)
+                // come first, for the diagonal 2x2 blocks M_aa that every pair needs
+                // (stored in LDS); their pairs follow from registers.
+                const SlotMT<C> m = slot_view<C>(slots, n);
+                const int TM = (n + 15) / 16, KS = (N + 3) >> 2;
+                const int lq = lane >> 4, l16 = lane & 15;
+                auto quad = [&](int I, int J, dbl4 (&q)[4][2]) {
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) q[h][0] = q[h][1] = dbl4{0.0, 0.0, 0.0, 0.0};
+                    const int ia = 16 * I + l16, jb = 16 * J + l16;
+#pragma unroll 2
+                    for (int ks = 0; ks < KS; ++ks) {
+                        const int k = ks * 4 + lq;
+                        const bool kok = k < N, aok = kok && ia < n, bok = kok && jb < n;
+                        const cplx dl = m.d[kok ? k : 0];
+                        const double axl = Vt[aok ? k * N + ia : 0], apl = Vt[aok ? k * N + n + ia : 0];
+                        const double bxl = Vt[bok ? k * N + jb : 0], bpl = Vt[bok ? k * N + n + jb : 0];
+                        const double ax = aok ? axl : 0.0, ap = aok ? apl : 0.0;
+                        const double bx = bok ? bxl : 0.0, bp = bok ? bpl : 0.0;
+                        const double axr = ax * dl.re, axi = ax * dl.im, apr = ap * dl.re, api = ap * dl.im;
+                        q[0][0] = mfma4(axr, bx, q[0][0]);
+                        q[0][1] = mfma4(axi, bx, q[0][1]);
+                        q[1][0] = mfma4(axr, bp, q[1][0]);
+                        q[1][1] = mfma4(axi, bp, q[1][1]);
+                        q[2][0] = mfma4(apr, bx, q[2][0]);
+                        q[2][1] = mfma4(api, bx, q[2][1]);
+                        q[3][0] = mfma4(apr, bp, q[3][0]);
+                        q[3][1] = mfma4(api, bp, q[3][1]);
+                    }
+                };
+                auto pairs = [&](int I, int J, const dbl4 (&q)[4][2]) {
+                    const int b = 16 * J + l16;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int a = 16 * I + 4 * e + lq;
+                        if (a < b && b < n) {
+                            const C b00 = from_d<C>(cmk(q[0][0][e], q[0][1][e]));
+                            const C b01 = from_d<C>(cmk(q[1][0][e], q[1][1][e]));
+                            const C b10 = from_d<C>(cmk(q[2][0][e], q[2][1][e]));
+                            const C b11 = from_d<C>(cmk(q[3][0][e], q[3][1][e]));
+                            const C a00 = m.d0[a], a01 = m.d1[a], a11 = m.d2[a];
+                            const C deta = cfnma(a01, a01, cmul(a00, a11));
+                            const C ra = crsqrt_p(deta);
+                            const C ideta = cmul(ra, ra);
+                            const C ia00 = cmul(a11, ideta), ia11 = cmul(a00, ideta);
+                            const C ia01 = cneg(cmul(a01, ideta));
+                            const C G00 = cfma(ia00, b00, cmul(ia01, b10));
+                            const C G01 = cfma(ia00, b01, cmul(ia01, b11));
+                            const C G10 = cfma(ia01, b00, cmul(ia11, b10));
+                            const C G11 = cfma(ia01, b01, cmul(ia11, b11));
+                            const C sb00 = csub(m.d0[b], cfma(b00, G00, cmul(b10, G10)));
+                            const C sb01 = csub(m.d1[b], cfma(b00, G01, cmul(b10, G11)));
+                            const C sb11 = csub(m.d2[b], cfma(b01, G01, cmul(b11, G11)));
+                            const C rb = crsqrt_p(cfnma(sb01, sb01, cmul(sb00, sb11)));
+                            s2f = cadd(s2f, to_d(cmul(ra, rb)));
+                        }
+                    }
+                };
+                dbl4 qd[4][2];
+                if (wid < TM) {
+                    quad(wid, wid, qd);
+                    const int b = 16 * wid + l16;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (4 * e + lq == l16 && b < n) {
+                            m.d0[b] = from_d<C>(cmk(qd[0][0][e], qd[0][1][e]));
+                            m.d1[b] = from_d<C>(cmk(qd[1][0][e], qd[1][1][e]));
+                            m.d2[b] = from_d<C>(cmk(qd[3][0][e], qd[3][1][e]));
+                        }
+                }
+                __syncthreads();
+                if (wid < TM) pairs(wid, wid, qd);
+                for (int u = wid; u < TM * (TM - 1) / 2; u += CONT_THREADS / 64) {
+                    int I, J;
+                    upper_tile(u, I, J);
+                    dbl4 q[4][2];
+                    quad(I, J + 1, q);
+                    pairs(I, J + 1, q);
+                }
+            } else if (ORDER >= 2) {
                 // BIG: V comes from L2, so 2x2 blocks of tiles share each operand fetch
                 constexpr int BS = BIG ? 2 : 1;
                 const int T = (N + 16 * BS - 1) / (16 * BS), ntile = T * (T + 1) / 2;
@@ -243,7 +331,8 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                     const C a00 = m.d0[a], a01 = m.d1[a], a11 = m.d2[a];
                     s1 = cadd(s1, to_d(crsqrt_p(cfnma(a01, a01, cmul(a00, a11)))));
                 }
-                if (ORDER >= 2) {
+                if (ORDER == 2 && BIG) s2 = s2f;
+                if (ORDER >= 2 && !(ORDER == 2 && BIG)) {
                     const int *un = units + unit_off[2 * n];
                     const int nu = unit_off[2 * n + 1];
                     int unext = lt < nu ? un[lt] : 0;
@@ -691,9 +780,11 @@ int launch_contour(gbs_ctx *ctx, gbs_plan *pl, int nmax)
     const int lds_cap = ctx->lds_per_block - lds_static;
     int lds_c;
     if (BIG) {
-        // the largest row's M(w) in LDS if it fits, else only alpha (M in HBM)
+        // the largest row's M(w) in LDS if it fits, else only alpha (M in HBM);
+        // order 2 keeps only d, rz and the diagonal blocks
         lds_c = cont_fixed() + 8 * 2 * nmax + cont_mbytes<C>(nmax);
         if (lds_c > lds_cap) lds_c = cont_fixed() + 8 * 2 * nmax;
+        if (ORDER == 2) lds_c = cont_fixed() + 8 * 2 * nmax + 16 * (cont_tp(nmax) + 5 * nmax);
     } else {
         // the whole 160 KB when the largest row needs it, else enough for eight
         // contour points of the largest row (two workgroups may then share a CU)
