@@ -20,7 +20,10 @@
 //   k_adj_contour  per (row, 64 contour points): M(w) and the clusters again
 //                  (the same work units as the forward, in an order that spreads
 //                  neighbouring lanes over different blocks of Z(w)),
-//                  Z(w) by LDS atomics, V^T Z V in column panels, R in registers
+//                  Z(w) by LDS atomics, V^T Z V on the matrix cores (rows up to
+//                  40 clicks: column units, each wavefront's share of R in
+//                  registers over the item; larger rows: Y = Z V into an HBM
+//                  panel, then X = V^T Y, R read-modified-written per point)
 //   k_adj_reduce   per row: sum of the items' R in a fixed order, the
 //                  contour-independent terms, A_bar = V R V^T, added into the
 //                  adjoint of Q^{-1} at the row's mode pairs (global atomics)
@@ -306,11 +309,11 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         const RowPlan rp = rows[p];
         const int np = n * (n - 1) / 2;
         const long long vo = voff[p];
-        // Vt[k*vs + i] = V[i][k].  Rows up to GBS_NSMALL clicks: V, M(w), Z(w)
-        // and the panel of Z V in LDS.  Larger rows: V read from HBM (L2), M(w)
-        // and the panel in this workgroup's HBM scratch, Z(w) in LDS (at order
-        // <= 2 only its diagonal blocks: each pair block has a single writer
-        // and goes to the scratch)
+        // Vt[k*vs + i] = V[i][k].  Rows up to GBS_NSMALL clicks: V (zero-padded),
+        // d, M(w) and Z(w) in LDS.  Larger rows: V read from HBM (L2), M(w) and
+        // the Y = Z V panel in this workgroup's HBM scratch, Z(w) in LDS (at
+        // order <= 2 only its diagonal blocks, plus a staged 32-row block of Z:
+        // each pair block has a single writer and goes to the scratch)
         const int vs = BIG ? N : ADJ_VS;
         const double *Vt;
         double *al;
@@ -606,8 +609,8 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             if (lane == 0) red[wid] = bsum;
             __syncthreads();
             // R += Re[(w/2) d_i d_j (V^T Z V)_ij] (+ diagonal beta terms) on the
-            // matrix cores: by rounds of two 16-column tiles jt, Y = Z V for those
-            // columns into LDS, then X = V^T Y for the owned tiles (it, jt)
+            // matrix cores (below: the larger rows first, then the column units
+            // of the rows kept in LDS)
             cplx beta = s_g[0];
             for (int i = 0; i < CONT_THREADS / 64; ++i) beta = cadd(beta, red[i]);
             const cplx hw = cscale(w, 0.5);
