@@ -106,3 +106,56 @@ def test_big_grad_directional(gpu_ctx):
         fd = (w @ f(xp[:M], xp[M:]) - w @ f(xm[:M], xm[M:])) / (2 * h)
         assert abs(g @ v - fd) < 1e-4 * np.linalg.norm(g), (g @ v, fd)
     plan.close()
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_grad_few_large_rows(gpu_ctx, order):
+    """Two rows above 40 clicks next to two below (so most of the per-XCD
+    queues of the larger rows' adjoint are empty and their workgroups take
+    items from the others): the adjoint against central differences of the
+    GPU forward on the frozen plan along random directions in (r, eta)."""
+    import torch
+    M = 50
+    U, r, eta = small_model(M, 21, n_squeezed=25, r_range=(1.0, 1.5), eta_range=(0.3, 0.6))
+    rng = np.random.default_rng(78)
+    rows = [sorted(rng.choice(M, size=k, replace=False).tolist()) for k in (38, 41, 40, 45)]
+    off, mod = csr_from_lists(rows)
+    P = len(rows)
+    gpu_ctx.gbs_set_model(U, r, eta)
+    plan = gpu_ctx.gbs_plan_create(off, mod, order)
+    dev = torch.device("cuda")
+    ure = torch.tensor(np.ascontiguousarray(U.real), device=dev)
+    uim = torch.tensor(np.ascontiguousarray(U.imag), device=dev)
+    logp = torch.empty(P, dtype=torch.float64, device=dev)
+    st = torch.empty(P, dtype=torch.int32, device=dev)
+
+    def f(rr, ee):
+        gpu_ctx.gbs_set_model_dev(ure, uim, torch.tensor(rr, device=dev), torch.tensor(ee, device=dev))
+        gpu_ctx.gbs_prob_approx_dev(plan, logp, st)
+        torch.cuda.synchronize()
+        assert int(st.abs().sum()) == 0
+        return logp.cpu().numpy().copy()
+
+    w = np.array([0.7, 1.3, 0.9, 1.1])
+    f(r, eta)
+    plan.freeze(True)
+    dl = torch.tensor(w, device=dev)
+    gr = torch.empty(M, dtype=torch.float64, device=dev)
+    ge = torch.empty(M, dtype=torch.float64, device=dev)
+    gpu_ctx.gbs_set_model_dev(ure, uim, torch.tensor(r, device=dev), torch.tensor(eta, device=dev))
+    gpu_ctx.gbs_grad_dev(plan, dl, logp, gr, ge, st)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    g = np.concatenate([gr.cpu().numpy(), ge.cpu().numpy()])
+    assert np.all(np.isfinite(g))
+    mask = np.concatenate([r > 0, np.ones(M, bool)])
+    rng = np.random.default_rng(79)
+    h = 1e-5
+    for _ in range(3):
+        v = rng.standard_normal(2 * M) * mask
+        v /= np.linalg.norm(v)
+        xp = np.concatenate([r, eta]) + h * v
+        xm = np.concatenate([r, eta]) - h * v
+        fd = (w @ f(xp[:M], xp[M:]) - w @ f(xm[:M], xm[M:])) / (2 * h)
+        assert abs(g @ v - fd) < 1e-4 * np.linalg.norm(g), (g @ v, fd)
+    plan.close()
