@@ -151,8 +151,9 @@ __device__ __forceinline__ void row_plan(RowPlan &rp, int n, const double *alpha
         if (dev < 1e-300) rho = 1.0;
         else if (mfun(hi) <= target) rho = hi;
         else {
+            // (bisection to the last few bits of rho; at most 200 halvings)
             double lo = 0.0;
-            for (int it = 0; it < 200; ++it) {
+            for (int it = 0; it < 200 && hi - lo > 4e-16 * hi; ++it) {
                 const double mid = 0.5 * (lo + hi);
                 if (mfun(mid) < target) lo = mid;
                 else hi = mid;

@@ -142,14 +142,16 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(
                     if (fabs(ed[m]) <= eps * (fabs(dg[m]) + fabs(dg[m + 1]))) break;
                 int lo = m;  // rotations recorded for i in [lo, m-1]
                 if (m != l && iter < 60) {
+                    // (|g| < 1e16 and every other quantity of the sweep is O(1),
+                    // since ed[l] is above eps |dg|: plain square roots suffice)
                     double g = (dg[l + 1] - dg[l]) / (2.0 * ed[l]);
-                    double r = hypot(g, 1.0);
+                    double r = sqrt(fma(g, g, 1.0));
                     g = dg[m] - dg[l] + ed[l] / (g + copysign(r, g));
                     double s = 1.0, c = 1.0, pp = 0.0;
                     bool early = false;
                     for (int i = m - 1; i >= l; --i) {
                         const double f = s * ed[i], b = c * ed[i];
-                        r = hypot(f, g);
+                        r = sqrt(fma(f, f, g * g));
                         ed[i + 1] = r;
                         if (r == 0.0) {
                             dg[i + 1] -= pp;
