@@ -339,7 +339,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path "
-              "(rows are independent; see DESIGN.md for how it would shard)", file=sys.stderr)
+              "(rows are independent: a batch would shard over GPUs by cost, with one all-reduce of the 2M gradient entries)", file=sys.stderr)
         sys.exit(2)
 
     import torch
