@@ -338,7 +338,7 @@ def main():
                          "HBM byte counters against a kernel of known traffic)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path "
+        print("bench.py runs on one GPU: there is no multi-GPU path "
               "(rows are independent: a batch would shard over GPUs by cost, with one all-reduce of the 2M gradient entries)", file=sys.stderr)
         sys.exit(2)
 
