@@ -110,7 +110,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
     int *__restrict__ q_head, const int *__restrict__ units, const int *__restrict__ unit_off,
     const int *__restrict__ unit4_off, cplx *__restrict__ mscr, long long mscr_stride, cplx *__restrict__ sw)
 {
-    extern __shared__ double sh[];
+    extern __shared__ __attribute__((aligned(16))) double sh[];
     __shared__ int s_item;
     __shared__ cplx s_wq[GBS_QCHUNK_MAX];                    // the item's contour points
     cplx *red = (cplx *)sh;                                  // [waves][4]
@@ -529,7 +529,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
                                                          double *__restrict__ logp,
                                                          int *__restrict__ status)
 {
-    extern __shared__ double sh[];
+    extern __shared__ __attribute__((aligned(16))) double sh[];
     __shared__ double red[FIT_THREADS], red2[FIT_THREADS];
     const int p = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int n = offsets[p + 1] - offsets[p];
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dist_fit(const int *__restrict_
                                                           const int *__restrict__ ks, double *__restrict__ p_n,
                                                           double *__restrict__ p_k, int *__restrict__ status)
 {
-    extern __shared__ double sh[];
+    extern __shared__ __attribute__((aligned(16))) double sh[];
     __shared__ double red[FIT_THREADS];
     __shared__ double pacc[2 * GBS_NSMALL + 2];
     __shared__ double s_fail;

@@ -47,7 +47,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
                                                          const double *__restrict__ dl,
                                                          cplx *__restrict__ asw)
 {
-    extern __shared__ double sh[];
+    extern __shared__ __attribute__((aligned(16))) double sh[];
     __shared__ double red[FIT_THREADS];
     const int p = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int n = offsets[p + 1] - offsets[p];
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
     const cplx *__restrict__ asw, const long long *__restrict__ roff, double *__restrict__ rscr,
     cplx *__restrict__ ascr, long long ascr_stride, const int *__restrict__ xq)
 {
-    extern __shared__ double sh[];
+    extern __shared__ __attribute__((aligned(16))) double sh[];
     __shared__ int s_item;
     __shared__ cplx s_g[ORDER + 1];
     __shared__ cplx s_wq[ADJ_QCHUNK];
@@ -984,7 +984,7 @@ __global__ __launch_bounds__(256) void k_adj_reduce(int M, const int *__restrict
                                                     const double *__restrict__ rscr,
                                                     double *__restrict__ psi)
 {
-    extern __shared__ double sh[];
+    extern __shared__ __attribute__((aligned(16))) double sh[];
     const int p = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
     const RowPlan rp = rows[p];

@@ -29,7 +29,7 @@
 #define GBS_NCOUNTER (8 + 3 * GBS_NXCD)
 #define GBS_CLUSTER_SEG 3      // triples per cluster work unit at order 3 (default)
 
-struct cplx {
+struct alignas(16) cplx {
     double re, im;
 };
 

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(PLAIN_THREADS) void k_plain(const int *__restrict__
                                                          const RowPlan *__restrict__ rows,
                                                          cplx *__restrict__ sw)
 {
-    extern __shared__ double sh[];
+    extern __shared__ __attribute__((aligned(16))) double sh[];
     __shared__ cplx red[PLAIN_THREADS / 64][ORDER + 1];
     __shared__ cplx s_w, s_g;
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
