@@ -445,7 +445,7 @@ def main():
             rates[key] = {"kernel": kname, "ms": ms, "flops": fl, "tflops": fl / (ms * 1e-3) / 1e12}
     dom = max(rates.values(), key=lambda d: d["ms"])
     src = [os.path.join(ROOT, "paper_2106_01445_amd", "csrc", f)
-           for f in ("approx.hip", "grad.hip", "contour_common.h", "cplx.h")]
+           for f in ("approx.hip", "grad.hip", "contour_common.h", "cplx.h", "internal.h")]
     roof = {"bound": "alu", "kernel": dom["kernel"],
             "achieved": round(dom["tflops"], 3), "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
             "frac": round(dom["tflops"] / PEAK_FP64_VALU_TFLOPS, 4),
