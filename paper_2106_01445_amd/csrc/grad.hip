@@ -354,6 +354,19 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         cplx *Mo0 = Md2 + dstr, *Mo1 = Mo0 + ostr, *Mo2 = Mo1 + ostr, *Mo3 = Mo2 + ostr;
         cplx *Zd1 = Zd0 + dstr, *Zd2 = Zd1 + dstr;
         cplx *Zo1 = Zo0 + ostr, *Zo2 = Zo1 + ostr, *Zo3 = Zo2 + ostr;
+        // Z(w) accumulation.  Rows kept in LDS hold Z as two planes (real parts,
+        // then imaginary parts, ADJ_MREG doubles each) addressed by the complex
+        // index: each 64-bit LDS atomic of a wavefront then steps by 8 bytes
+        // instead of 16, which halves its bank passes.
+        auto zadd = [&](cplx *p, cplx v) {
+            if constexpr (BIG) {
+                catomic(p, v);
+            } else {
+                double *zr = (double *)Zd0 + (p - Zd0);
+                atomicAdd(zr, v.re);
+                atomicAdd(zr + ADJ_MREG, v.im);
+            }
+        };
         for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
         const int Qn = rp.K / 2 + 1;
         const int q0 = ch * ADJ_QCHUNK, q1 = min(q0 + ADJ_QCHUNK, Qn);
@@ -454,9 +467,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 const cplx id = cmul(r, r);
                 bsum = cadd(bsum, c);
                 const cplx cid = cmul(c, id);
-                catomic(&Zd0[a], cmul(cid, a11));
-                catomic(&Zd1[a], cscale(cmul(cid, a01), -1.0));
-                catomic(&Zd2[a], cmul(cid, a00));
+                zadd(&Zd0[a], cmul(cid, a11));
+                zadd(&Zd1[a], cscale(cmul(cid, a01), -1.0));
+                zadd(&Zd2[a], cmul(cid, a00));
             }
             if (ORDER >= 2) {
                 const cplx g2 = s_g[2 <= ORDER ? 2 : 0];
@@ -538,9 +551,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                                 is11 = cmul(sc00, k);
                                 is01 = cmul(cneg(sc01), k);
                             }
-                            catomic(&Zd0[c], is00);
-                            catomic(&Zd1[c], is01);
-                            catomic(&Zd2[c], is11);
+                            zadd(&Zd0[c], is00);
+                            zadd(&Zd1[c], is01);
+                            zadd(&Zd2[c], is11);
                             // rows a: U_a = Za - G W, then Q_a = -P_a = -U_a c_T Sc^{-1}
                             // (formed with the sign the Z blocks take, so that no
                             // negated copy has to be made for the LDS adds)
@@ -552,10 +565,10 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                             const cplx Q01 = cfnma(U00, is01, cmul(cneg(U01), is11));
                             const cplx Q10 = cfnma(U10, is00, cmul(cneg(U11), is01));
                             const cplx Q11 = cfnma(U10, is01, cmul(cneg(U11), is11));
-                            catomic(&Zo0[cur_ac], Q00);
-                            catomic(&Zo1[cur_ac], Q01);
-                            catomic(&Zo2[cur_ac], Q10);
-                            catomic(&Zo3[cur_ac], Q11);
+                            zadd(&Zo0[cur_ac], Q00);
+                            zadd(&Zo1[cur_ac], Q01);
+                            zadd(&Zo2[cur_ac], Q10);
+                            zadd(&Zo3[cur_ac], Q11);
                             A00 = cfnma(Q00, U00, cfnma(Q01, U01, A00));
                             A01 = cfnma(Q00, U10, cfnma(Q01, U11, A01));
                             A11 = cfnma(Q10, U10, cfnma(Q11, U11, A11));
@@ -568,10 +581,10 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                             const cplx Q21 = cfnma(W00, is01, cmul(cneg(W01), is11));
                             const cplx Q30 = cfnma(W10, is00, cmul(cneg(W11), is01));
                             const cplx Q31 = cfnma(W10, is01, cmul(cneg(W11), is11));
-                            catomic(&Zo0[cur_bc], Q20);
-                            catomic(&Zo1[cur_bc], Q21);
-                            catomic(&Zo2[cur_bc], Q30);
-                            catomic(&Zo3[cur_bc], Q31);
+                            zadd(&Zo0[cur_bc], Q20);
+                            zadd(&Zo1[cur_bc], Q21);
+                            zadd(&Zo2[cur_bc], Q30);
+                            zadd(&Zo3[cur_bc], Q31);
                             A22 = cfnma(Q20, W00, cfnma(Q21, W01, A22));
                             A23 = cfnma(Q20, W10, cfnma(Q21, W11, A23));
                             A33 = cfnma(Q30, W10, cfnma(Q31, W11, A33));
@@ -585,9 +598,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                     const cplx pa00 = cadd(ia00, cfma(H00, G00, cmul(H01, G01)));
                     const cplx pa01 = cadd(ia01, cfma(H00, G10, cmul(H01, G11)));
                     const cplx pa11 = cadd(ia11, cfma(H10, G10, cmul(H11, G11)));
-                    catomic(&Zd0[a], cfma(cp, pa00, A00));
-                    catomic(&Zd1[a], cfma(cp, pa01, A01));
-                    catomic(&Zd2[a], cfma(cp, pa11, A11));
+                    zadd(&Zd0[a], cfma(cp, pa00, A00));
+                    zadd(&Zd1[a], cfma(cp, pa01, A01));
+                    zadd(&Zd2[a], cfma(cp, pa11, A11));
                     if (BIG && ORDER <= 2) {
                         // one unit per pair: the pair block has a single writer
                         Zo0[pi] = cfnma(cp, H00, A02);
@@ -595,14 +608,14 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                         Zo2[pi] = cfnma(cp, H10, A12);
                         Zo3[pi] = cfnma(cp, H11, A13);
                     } else {
-                        catomic(&Zo0[pi], cfnma(cp, H00, A02));
-                        catomic(&Zo1[pi], cfnma(cp, H01, A03));
-                        catomic(&Zo2[pi], cfnma(cp, H10, A12));
-                        catomic(&Zo3[pi], cfnma(cp, H11, A13));
+                        zadd(&Zo0[pi], cfnma(cp, H00, A02));
+                        zadd(&Zo1[pi], cfnma(cp, H01, A03));
+                        zadd(&Zo2[pi], cfnma(cp, H10, A12));
+                        zadd(&Zo3[pi], cfnma(cp, H11, A13));
                     }
-                    catomic(&Zd0[b], cfma(cp, ib00, A22));
-                    catomic(&Zd1[b], cfma(cp, ib01, A23));
-                    catomic(&Zd2[b], cfma(cp, ib11, A33));
+                    zadd(&Zd0[b], cfma(cp, ib00, A22));
+                    zadd(&Zd1[b], cfma(cp, ib01, A23));
+                    zadd(&Zd2[b], cfma(cp, ib11, A33));
                 }
             }
             bsum = warp_csum(bsum);
@@ -622,7 +635,13 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 const int lo = min(a, b), hi = max(a, b);
                 const int kq = a < b ? 2 * qa + qb : 2 * qb + qa;
                 const cplx *src = a == b ? Zd0 + (qa + qb) * dstr + a : Zo0 + kq * ostr + pair_pos<true>(n, lo, hi);
-                const cplx zl = *(ok ? src : Zd0);
+                cplx zl;
+                if constexpr (BIG) {
+                    zl = *(ok ? src : Zd0);
+                } else {
+                    const double *zr = (const double *)Zd0 + (ok ? src - Zd0 : 0);
+                    zl = cmk(zr[0], zr[ADJ_MREG]);
+                }
                 return ok ? zl : cmk(0.0, 0.0);
             };
             if (BIG) {
