@@ -354,17 +354,22 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         cplx *Mo0 = Md2 + dstr, *Mo1 = Mo0 + ostr, *Mo2 = Mo1 + ostr, *Mo3 = Mo2 + ostr;
         cplx *Zd1 = Zd0 + dstr, *Zd2 = Zd1 + dstr;
         cplx *Zo1 = Zo0 + ostr, *Zo2 = Zo1 + ostr, *Zo3 = Zo2 + ostr;
-        // Z(w) accumulation.  Rows kept in LDS hold Z as two planes (real parts,
-        // then imaginary parts, ADJ_MREG doubles each) addressed by the complex
-        // index: each 64-bit LDS atomic of a wavefront then steps by 8 bytes
-        // instead of 16, which halves its bank passes.
+        // Z(w) accumulation.  Where the whole of Z sits in LDS (rows kept in
+        // LDS, and the larger rows at order 3 and above) it is held as two
+        // planes, the real parts and then the imaginary parts, zplane doubles
+        // each, addressed by the complex index: each 64-bit LDS atomic of a
+        // wavefront then steps by 8 bytes instead of 16, which halves its
+        // bank passes.  (At order <= 2 the larger rows keep the pair blocks in
+        // HBM and Z stays interleaved.)
+        constexpr bool ZPLANES = !BIG || ORDER >= 3;
+        const int zplane = BIG ? 3 * n + 4 * np : ADJ_MREG;
         auto zadd = [&](cplx *p, cplx v) {
-            if constexpr (BIG) {
-                catomic(p, v);
-            } else {
+            if constexpr (ZPLANES) {
                 double *zr = (double *)Zd0 + (p - Zd0);
                 atomicAdd(zr, v.re);
-                atomicAdd(zr + ADJ_MREG, v.im);
+                atomicAdd(zr + zplane, v.im);
+            } else {
+                catomic(p, v);
             }
         };
         for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
@@ -636,11 +641,11 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 const int kq = a < b ? 2 * qa + qb : 2 * qb + qa;
                 const cplx *src = a == b ? Zd0 + (qa + qb) * dstr + a : Zo0 + kq * ostr + pair_pos<true>(n, lo, hi);
                 cplx zl;
-                if constexpr (BIG) {
-                    zl = *(ok ? src : Zd0);
-                } else {
+                if constexpr (ZPLANES) {
                     const double *zr = (const double *)Zd0 + (ok ? src - Zd0 : 0);
-                    zl = cmk(zr[0], zr[ADJ_MREG]);
+                    zl = cmk(zr[0], zr[zplane]);
+                } else {
+                    zl = *(ok ? src : Zd0);
                 }
                 return ok ? zl : cmk(0.0, 0.0);
             };
