@@ -46,7 +46,7 @@ __device__ __forceinline__ cplx cexp_(cplx z)
 }
 
 // fp32 complex, for the cluster eliminations of the mixed-precision tier
-struct cplxf {
+struct alignas(8) cplxf {
     float re, im;
 };
 __device__ __forceinline__ cplxf cmkf(float r, float i) { return cplxf{r, i}; }
