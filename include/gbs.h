@@ -54,31 +54,57 @@ enum {
     GBS_E_NOTPD = -2,  /* covariance + I/2 not positive definite                 */
     GBS_E_NOMEM = -3,  /* device allocation failed                               */
     GBS_E_HIP = -4,    /* HIP runtime error (message has the HIP error string)   */
-    GBS_E_STATE = -5,  /* no model set on the context, or plan from another ctx  */
+    GBS_E_STATE = -5,  /* no model set, plan from another ctx or for another M   */
     GBS_W_PATTERN = 1  /* success, but some status[p] != 0                       */
 };
 
 /*
  * Precision.  GBS_PREC_FP64: every step in fp64 (double-double where stated).
- * GBS_PREC_MIXED (approximate path, forward only): the cluster eliminations
- * run in fp32 on an fp32 copy of M(w); the model, the eigen-decomposition, the
- * contour plan, M(w) itself, G_0(w), the sums over clusters, the sector
- * transform and the fits stay fp64.  The sector transform extracts small
- * moments from contour values whose fp32 rounding is set by the largest ones,
- * so the error grows with a row's dynamic range: measured median / worst
- * |log p_mixed - log p_fp64| 3e-6 / 3e-5 (20 modes, order 3), 3e-5 / 4e-4
- * (70 modes), 1e-4 / 2e-3 (100 modes).  The exact path, the plain kernel and
- * the gradient take GBS_PREC_FP64 only (GBS_E_INVAL otherwise).
+ * GBS_PREC_MIXED (approximate path, forward only, orders 1-3): the cluster
+ * eliminations run in fp32 on an fp32 copy of M(w); the model, the
+ * eigen-decomposition, the contour plan, M(w) itself, G_0(w), the sums over
+ * clusters, the sector transform and the fits stay fp64.  The sector transform
+ * extracts small moments from contour values whose fp32 rounding is set by the
+ * largest ones, so the error grows with a row's dynamic range.  Every row's
+ * rounding error is therefore estimated (gbs_plan_info); a row whose estimate
+ * exceeds 1e-6 is run again in fp64 within the same call, on the device, and
+ * flagged GBS_PS_ESCALATED, so that every row meets the tier's target of 1e-5
+ * in log p against fp64.  The exact path, the plain kernel and the gradient
+ * take GBS_PREC_FP64 only (GBS_E_INVAL otherwise).
  */
 enum { GBS_PREC_FP64 = 0, GBS_PREC_MIXED = 1 };
 
-/* per-pattern status bits */
+/*
+ * Per-pattern status bits.  FIT_NOCONV, PIVOT, CANCEL and BADROW mean the row
+ * has no result: its output is NaN.  CONTOUR and ESCALATED are informational:
+ * the result is returned and the bit says how it was obtained.
+ *
+ * GBS_PS_CONTOUR (Methods, Partition function: the sectors come from a sum
+ * over a discrete set of points of the generating function) is set when
+ *   (a) the transform's rounding, about 1e-16 of the contour's tilted weight
+ *       and so 1e-16 / tau_kappa relative in a sector of tilted weight
+ *       tau_kappa, summed with the sectors' shares of the estimate, exceeds
+ *       1e-9 of the estimate (the fp64 tolerance of the estimate).  This
+ *       happens when the sectors that carry the estimate lie far in the tail
+ *       of the tilted distribution: when the saddle-point radius lies beyond
+ *       the cap 0.98 R_b (on the 144-mode workload the 301 of 4096 rows whose
+ *       radius is capped keep at least 0.24 of the tilted weight above n
+ *       photons and are not flagged), or when the all-click value of the
+ *       fitted curves rises so steeply with the photon number that sectors
+ *       far above n dominate; or
+ *   (b) a frozen plan's radius no longer suits the current model:
+ *       rho max|alpha - 1| reached 1 or the aliasing factor
+ *       (rho max|alpha - 1|)^K exceeds 1e-14.  The row is then planned afresh
+ *       for this call (new rho and K).
+ */
 enum {
     GBS_PS_OK = 0,
     GBS_PS_FIT_NOCONV = 1, /* a sector fit carrying >1e-10 of the estimate did not converge */
-    GBS_PS_CONTOUR = 2,    /* contour radius could not meet the accuracy rule (K capped)     */
+    GBS_PS_CONTOUR = 2,    /* the contour deviated from its accuracy rule (see above)        */
     GBS_PS_PIVOT = 4,      /* a determinant pivot left its valid half-plane                   */
-    GBS_PS_CANCEL = 16     /* exact sum not resolved: |sum| below its rounding bound          */
+    GBS_PS_ESCALATED = 8,  /* ran at higher precision than asked (mixed -> fp64)              */
+    GBS_PS_CANCEL = 16,    /* exact sum not resolved: |sum| below its rounding bound          */
+    GBS_PS_BADROW = 32     /* device-side CSR check failed (gbs_prob_exact_dev): no result    */
 };
 
 /* Create a context on HIP device `hip_device`.  hip_stream: a hipStream_t to
@@ -118,12 +144,27 @@ int gbs_get_model(gbs_ctx *ctx, double *q_inv, double *logdet_q);
  *     p(C) = det(Q)^{-1/2} sum_{Z subset C} (-1)^{n-|Z|} det((Q^{-1})_{ZZ})^{-1/2}
  * The 2^n terms and their signed sum are evaluated in double-double, so p is
  * accurate to ~1e-16 relative even when the sum cancels by 1e11.  Rows may hold
- * at most 24 clicks.  Outputs (host arrays of length P): p, logp (nullable),
- * kappa = sum|terms| / |sum| (nullable), status.
+ * at most 30 clicks (2^30 terms; a row of 30 clicks takes of the order of a
+ * second).  Outputs (host arrays of length P): p, logp (nullable),
+ * kappa = sum|terms| / |sum| (nullable), status.  A row whose sum cancels by
+ * more than 1e20 gets NaN and GBS_PS_CANCEL.
  */
 int gbs_prob_exact(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int prec,
                    double *p, double *logp, double *kappa, int32_t *status);
-
+/*
+ * The same from device arrays, stream-ordered (no host synchronisation): CSR
+ * offsets_dev[P+1], modes_dev[offsets[P]] and outputs p_dev[P], status_dev[P],
+ * logp_dev[P] and kappa_dev[P] (both nullable), all device pointers.
+ * max_clicks (0..30) bounds the clicks of every row and sizes the launch; the
+ * rows are checked on the device: a row with more clicks, a mode outside
+ * [0, M) or modes not strictly ascending gets NaN and GBS_PS_BADROW.  The
+ * call returns GBS_OK once the work is enqueued (the per-row status is in
+ * status_dev).  Partial sums live in a context-owned device buffer of
+ * 24 P 2^min(max(max_clicks - 9, 0), 12) bytes, grown on demand (the call then
+ * waits for the stream before it frees the old one).
+ */
+int gbs_prob_exact_dev(gbs_ctx *ctx, int P, const int32_t *offsets_dev, const int32_t *modes_dev, int max_clicks,
+                       double *p_dev, double *logp_dev, double *kappa_dev, int32_t *status_dev);
 /*
  * gbs_prob_approx: the paper's order-j estimate (1 <= order <= 4), returned as
  * log p_hat (p_hat reaches 1e-35 and below).  For each row:
@@ -237,8 +278,13 @@ int gbs_plan_set_params(gbs_plan *plan, const int32_t *params);
 int gbs_plan_tune(gbs_ctx *ctx, gbs_plan *plan, int what, int32_t *params);
 
 /* Per-row diagnostics of the last run on a plan (host arrays of length P,
- * each nullable): contour radius, convergence radius, K, sectors fitted. */
-int gbs_plan_info(gbs_plan *plan, double *rho, double *rconv, int32_t *K, int32_t *nsectors);
+ * each nullable): contour radius, convergence radius, K, sectors fitted, and
+ * the estimated rounding error of log p_hat in the precision the row ran in:
+ * each tilted moment carries the rounding of its contour values (fp64 2e-16,
+ * or 2e-7 for fp32 cluster eliminations, times the transform's value at
+ * w = rho), pushed through each sector fit's sensitivity (d log q / d m =
+ * -H^{-1} m) and summed with the sectors' shares of the estimate. */
+int gbs_plan_info(gbs_plan *plan, double *rho, double *rconv, int32_t *K, int32_t *nsectors, double *err);
 
 /* Per-kernel timing.  With on = 1, every later launch on the context is
  * bracketed by HIP events recorded on the context's stream.  gbs_timing

@@ -26,14 +26,16 @@ namespace {
 // k_build_items: work items (row, chunk) in the plan's cost order.  The rows
 // perm[0..nbig) (the large ones) come first: their items form the queue
 // counter[4] (length) / counter[5] (head); the rest form counter[0] (end) /
-// counter[1] (head, starting at counter[4]).
+// counter[1] (head, starting at counter[4]).  With only_escalated, only the
+// rows marked GBS_PS_ESCALATED by the previous fit get items (the fp64 rerun
+// of the mixed precision tier).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_build_items(int P, int nbig, int qchunk,
                                                       const int *__restrict__ offsets,
                                                       const int *__restrict__ perm,
                                                       const RowPlan *__restrict__ rows,
                                                       int *__restrict__ items,
-                                                      int *__restrict__ counter)
+                                                      int *__restrict__ counter, int only_escalated = 0)
 {
     __shared__ int part[1024];
     __shared__ int s_big;
@@ -45,6 +47,7 @@ __global__ __launch_bounds__(1024) void k_build_items(int P, int nbig, int qchun
         int n = offsets[p + 1] - offsets[p];
         const RowPlan &rp = rows[p];
         if (n == 0 || rp.status != 0 || rp.K <= 0) return 0;
+        if (only_escalated && !(rp.flags & GBS_PS_ESCALATED)) return 0;
         return (rp.K / 2 + 1 + qchunk - 1) / qchunk;
     };
     if (tid == 0) s_big = 0;
@@ -520,31 +523,48 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
 }
 
 // ---------------------------------------------------------------------------
-// k_dft_fit: sector moments, fits, log-sum.
+// k_dft_fit: sector moments, fits, log-sum, and the estimated rounding error of
+// the result.
+//
+// Rounding estimate.  A contour value carries a rounding error of about u times
+// the largest value of its transform (at w = rho, where every term is
+// positive), so each tilted moment tau_t[kappa] carries d_t = u_t S_t(rho)
+// (u_0 = ROUND_FP64 for the fp64 G_0; u_t = u_clu for the cluster sums).  In a
+// fitted sector, m_t = tau_t binv_t / tau_0 and d log q / d m = -u with
+// u = H^{-1} m, so
+//   |d log(term)| <= d_0 / tau_0 (1 + sum_t |u_t m_t|) + sum_t |u_t| binv_t d_t / tau_0,
+// and the row's estimate is the sum over sectors weighted by their shares of
+// the estimate.
+//   pass 0: every row; a row whose estimate exceeds esc_bound (> 0 only in
+//           mixed precision) is marked GBS_PS_ESCALATED, to be run again in
+//           fp64 (pass 1, only the marked rows).
 // ---------------------------------------------------------------------------
 template <int ORDER>
 __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__ offsets,
                                                          RowPlan *__restrict__ rows,
                                                          const cplx *__restrict__ sw,
                                                          double *__restrict__ logp,
-                                                         int *__restrict__ status)
+                                                         int *__restrict__ status, double u_clu,
+                                                         double esc_bound, int pass)
 {
     extern __shared__ __attribute__((aligned(16))) double sh[];
     __shared__ double red[FIT_THREADS], red2[FIT_THREADS];
     const int p = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int n = offsets[p + 1] - offsets[p];
     RowPlan rp = rows[p];
+    if (pass == 1 && !(rp.flags & GBS_PS_ESCALATED)) return;
     if (n == 0) {
         if (tid == 0) {
             logp[p] = rp.log_pvac;
             if (status) status[p] = 0;
+            rows[p].err = 0.0;
         }
         return;
     }
     if (rp.status != 0) {
         if (tid == 0) {
             logp[p] = NAN;
-            if (status) status[p] = rp.status;
+            if (status) status[p] = rp.status | rp.flags;
         }
         return;
     }
@@ -591,8 +611,30 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
         if (n + tid + nt * j < K) tmax = fmax(tmax, tau[j][0]);
     tmax = block_max(tmax, red);
     const double thr = 1e-14 * tmax;
+    // rounding of the tilted moments: u_t times the scale of the transform's
+    // values (their largest, at w = rho, or with ROUND_SCALE_MEAN their mean
+    // modulus over the circle)
+    double dt[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        double s0 = 0.0;
+        if (t <= ORDER && t <= jp) {
+            const cplx *src = sw + ((long)p * (ORDER + 1) + (t <= ORDER ? t : 0)) * GBS_QCAP;
+#ifdef ROUND_SCALE_MEAN
+            double a = 0.0;
+            for (int q = tid; q < Q; q += nt)
+                a += (q == 0 || q == K / 2 ? 1.0 : 2.0) * sqrt(src[q].re * src[q].re + src[q].im * src[q].im);
+            s0 = block_sum(a, red) / K;
+#else
+            s0 = fabs(src[0].re);
+#endif
+        }
+        dt[t] = (t == 0 ? ROUND_FP64 : u_clu) * s0;
+    }
     double fm = -INFINITY, fs = 0.0, um = -INFINITY, us = 0.0;
     int nsec = 0;
+    // log-sums of term_kappa * rounding estimate of log(term_kappa)
+    double em = -INFINITY, es = 0.0, eh = -INFINITY, esh = 0.0;
     double lower = -INFINITY;  // log of a lower bound of the total (after pass 0)
     // Pass 0 fits each thread's first sector; its block log-sum is a lower
     // bound L of the estimate.  Later sectors whose upper bound S_0[kappa]
@@ -617,6 +659,21 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
         } else {
             lse_add(fm, fs, lw + f.lq);
             ++nsec;
+            double u[4];
+            fit_sensitivity<ORDER >= 4 ? 4 : 3>(n, f, u);
+            const double binv[4] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
+                                    6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0)),
+                                    24.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0) * (n - 4.0))};
+            double um0 = 1.0, e1 = 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (t < f.jr) {
+                    um0 += fabs(u[t] * f.m[t]);
+                    e1 += fabs(u[t]) * binv[t] * dt[t + 1];
+                }
+            const double e = (dt[0] * um0 + e1) / t0;
+            lse_add(em, es, lw + f.lq + log(e));
+            lse_add(eh, esh, lw + f.lq - log(t0));
         }
     }
     // block log-sum-exp of the fitted and the unresolved sectors
@@ -625,6 +682,10 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
     double umx = block_max(um, red2);
     double usum = block_sum(um == -INFINITY ? 0.0 : us * exp(um - umx), red2);
     double ns = block_sum((double)nsec, red);
+    const double emx = block_max(em, red2);
+    const double esum = block_sum(em == -INFINITY ? 0.0 : es * exp(em - emx), red2);
+    const double ehx = block_max(eh, red2);
+    const double ehsum = block_sum(eh == -INFINITY ? 0.0 : esh * exp(eh - ehx), red2);
     if (tid == 0) {
         double tot = fmx + log(fsum);
         double unres = umx + log(usum);
@@ -635,9 +696,21 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
             out = NAN;
         }
         if (!(fsum > 0.0)) out = -INFINITY;
+        // estimated rounding error of log p_hat in this precision; the
+        // contour cannot resolve the sectors that carry the estimate when their
+        // tilted weights, averaged with their shares of the estimate (the
+        // harmonic mean sum_kappa w_kappa / tau_kappa), fall below 1e-6: the
+        // transform's rounding floor (~1e-16 of the contour's tilted weight)
+        // then reaches 1e-10 of the estimate
+        const double err = fsum > 0.0 && esum > 0.0 ? exp(emx + log(esum) - tot) : 0.0;
+        int flags = rp.flags;
+        if (fsum > 0.0 && ehsum > 0.0 && ehx + log(ehsum) - tot > log(1e6)) flags |= GBS_PS_CONTOUR;
+        if (pass == 0 && esc_bound > 0.0 && !(err <= esc_bound)) flags |= GBS_PS_ESCALATED;
         logp[p] = out;
-        if (status) status[p] = stt;
+        if (status) status[p] = stt | flags;
         rows[p].nsec = (int)ns;
+        rows[p].flags = flags;
+        rows[p].err = err;
     }
 }
 
@@ -832,7 +905,8 @@ int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
                        pl->d_rows, pl->d_items, pl->d_counter);
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_CONTOUR);
-    if (pl->prec == GBS_PREC_MIXED) {
+    const bool mixed = pl->prec == GBS_PREC_MIXED;
+    if (mixed) {
         // cluster eliminations in fp32 (M(w) stored in fp32), sums in fp64
         if (nbig > 0 && (rc = launch_contour<ORDER, true, cplxf>(ctx, pl, pl->max_n))) return rc;
         if (nbig < P && (rc = launch_contour<ORDER, false, cplxf>(ctx, pl, nsmall_max))) return rc;
@@ -845,8 +919,25 @@ int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
     if ((rc = func_lds_limit(ctx, (const void *)k_dft_fit<ORDER>, (int)lds_f))) return rc;
     ts = timer_begin(ctx, TG_FIT);
     hipLaunchKernelGGL(k_dft_fit<ORDER>, dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
-                       pl->d_rows, pl->d_sw, logp, status);
+                       pl->d_rows, pl->d_sw, logp, status, mixed ? ROUND_FP32 : ROUND_FP64,
+                       mixed ? MIXED_BOUND : 0.0, 0);
     timer_end(ctx, ts);
+    if (mixed) {
+        // rows whose estimated error exceeds the mixed bound: contour and fit
+        // again in fp64, on the device (no host decision)
+        ts = timer_begin(ctx, TG_ITEMS);
+        hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, st, P, nbig, pl->qchunk, pl->d_offsets,
+                           pl->d_perm, pl->d_rows, pl->d_items, pl->d_counter, 1);
+        timer_end(ctx, ts);
+        ts = timer_begin(ctx, TG_CONTOUR);
+        if (nbig > 0 && (rc = launch_contour<ORDER, true, cplx>(ctx, pl, pl->max_n))) return rc;
+        if (nbig < P && (rc = launch_contour<ORDER, false, cplx>(ctx, pl, nsmall_max))) return rc;
+        timer_end(ctx, ts);
+        ts = timer_begin(ctx, TG_FIT);
+        hipLaunchKernelGGL(k_dft_fit<ORDER>, dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
+                           pl->d_rows, pl->d_sw, logp, status, ROUND_FP64, 0.0, 1);
+        timer_end(ctx, ts);
+    }
     HIP_TRY(ctx, hipGetLastError());
     return 0;
 }
@@ -873,7 +964,7 @@ int launch_order4(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
     if ((rc = func_lds_limit(ctx, (const void *)k_dft_fit<4>, (int)lds_f))) return rc;
     ts = timer_begin(ctx, TG_FIT);
     hipLaunchKernelGGL(k_dft_fit<4>, dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets, pl->d_rows, pl->d_sw,
-                       logp, status);
+                       logp, status, ROUND_FP64, 0.0, 0);
     timer_end(ctx, ts);
     HIP_TRY(ctx, hipGetLastError());
     return 0;
@@ -914,7 +1005,7 @@ int launch_plain(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
     if ((rc = func_lds_limit(ctx, (const void *)k_dft_fit<ORDER>, (int)lds_f))) return rc;
     ts = timer_begin(ctx, TG_FIT);
     hipLaunchKernelGGL(k_dft_fit<ORDER>, dim3(pl->P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
-                       pl->d_rows, pl->d_sw, logp, status);
+                       pl->d_rows, pl->d_sw, logp, status, ROUND_FP64, 0.0, 0);
     timer_end(ctx, ts);
     HIP_TRY(ctx, hipGetLastError());
     return 0;

@@ -240,7 +240,7 @@ int plan_units(gbs_ctx *ctx, gbs_plan *pl)
 int adj_workspace(gbs_ctx *ctx, gbs_plan *pl)
 {
     if (pl->have_adj) return 0;
-    const int P = pl->P, M = ctx->model.M, order = pl->order;
+    const int P = pl->P, M = pl->M, order = pl->order;
     const int chunks = (GBS_QCAP + 63) / 64;
     size_t rtot = 0;
     for (int p = 0; p < P; ++p) {
@@ -321,6 +321,7 @@ int gbs_destroy(gbs_ctx *ctx)
         (void)hipEventDestroy(t.b);
     }
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+    if (ctx->ex_part) (void)hipFree(ctx->ex_part);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return GBS_OK;
@@ -469,6 +470,7 @@ int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
     gbs_plan *pl = new (std::nothrow) gbs_plan();
     if (!pl) return set_err(ctx, GBS_E_NOMEM, "host allocation failed");
     pl->ctx = ctx;
+    pl->M = ctx->model.M;
     pl->P = P;
     pl->order = order;
     pl->prec = prec;
@@ -532,6 +534,9 @@ int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
     if (he == hipSuccess) he = cp(pl->d_modes, pl->h_modes.data(), nnz * sizeof(int32_t));
     if (he == hipSuccess) he = cp(pl->d_perm, pl->h_perm.data(), P * sizeof(int32_t));
     if (he == hipSuccess) he = cp(pl->d_voff, voff.data(), P * sizeof(long long));
+    // (rows start unplanned, K = 0: a frozen plan re-plans a row that never got
+    // a contour)
+    if (he == hipSuccess && P > 0) he = hipMemsetAsync(pl->d_rows, 0, P * sizeof(RowPlan), st);
     if (he == hipSuccess) he = hipStreamSynchronize(st);
     if (he != hipSuccess) {
         plan_free_dev(pl);
@@ -570,6 +575,7 @@ int gbs_prob_approx_dev(gbs_ctx *ctx, gbs_plan *pl, double *logp_dev, int32_t *s
     if (!ctx || !pl) return GBS_E_INVAL;
     if (pl->ctx != ctx) return set_err(ctx, GBS_E_STATE, "plan belongs to another context");
     if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
+    if (ctx->model.M != pl->M) return set_err(ctx, GBS_E_STATE, "plan was made for a model of another size M");
     if (pl->P > 0 && !logp_dev) return set_err(ctx, GBS_E_INVAL, "logp_dev is NULL");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     int rc = approx_forward(ctx, pl, logp_dev, status_dev);
@@ -691,6 +697,7 @@ int gbs_plan_tune(gbs_ctx *ctx, gbs_plan *pl, int what, int32_t *params_out)
     if (!ctx || !pl) return GBS_E_INVAL;
     if (pl->ctx != ctx) return set_err(ctx, GBS_E_STATE, "plan belongs to another context");
     if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
+    if (ctx->model.M != pl->M) return set_err(ctx, GBS_E_STATE, "plan was made for a model of another size M");
     if (pl->order > 3) what &= 1;  // (no gradient at order 4)
     if ((what & 2) && !ctx->model.from_params)
         return set_err(ctx, GBS_E_STATE, "tuning the gradient needs a model set by gbs_set_model");
@@ -767,7 +774,7 @@ int gbs_plan_tune(gbs_ctx *ctx, gbs_plan *pl, int what, int32_t *params_out)
     return GBS_OK;
 }
 
-int gbs_plan_info(gbs_plan *pl, double *rho, double *rconv, int32_t *K, int32_t *nsectors)
+int gbs_plan_info(gbs_plan *pl, double *rho, double *rconv, int32_t *K, int32_t *nsectors, double *err)
 {
     if (!pl) return GBS_E_INVAL;
     gbs_ctx *ctx = pl->ctx;
@@ -783,6 +790,7 @@ int gbs_plan_info(gbs_plan *pl, double *rho, double *rconv, int32_t *K, int32_t 
         if (rconv) rconv[p] = rows[p].rconv;
         if (K) K[p] = rows[p].K;
         if (nsectors) nsectors[p] = rows[p].nsec;
+        if (err) err[p] = rows[p].err;
     }
     return GBS_OK;
 }
@@ -804,6 +812,32 @@ int gbs_prob_exact(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *m
     return GBS_OK;
 }
 
+int gbs_prob_exact_dev(gbs_ctx *ctx, int P, const int32_t *offsets_dev, const int32_t *modes_dev, int max_clicks,
+                       double *p_dev, double *logp_dev, double *kappa_dev, int32_t *status_dev)
+{
+    if (!ctx) return GBS_E_INVAL;
+    if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
+    if (P < 0) return set_err(ctx, GBS_E_INVAL, "P must be >= 0");
+    if (max_clicks < 0 || max_clicks > GBS_MAX_N_EXACT)
+        return set_err(ctx, GBS_E_INVAL, "max_clicks must be in [0, " + std::to_string(GBS_MAX_N_EXACT) + "]");
+    if (P == 0) return GBS_OK;
+    if (!offsets_dev || !modes_dev || !p_dev || !status_dev) return set_err(ctx, GBS_E_INVAL, "NULL device array");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const long long need = (long long)P << exact_lgs(max_clicks);
+    if (need > ctx->ex_part_items) {
+        // (grown on demand: the previous launches on the stream may still read
+        // the old buffer, so wait for them before it is released)
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        if (ctx->ex_part) (void)hipFree(ctx->ex_part);
+        ctx->ex_part = nullptr;
+        ctx->ex_part_items = 0;
+        if (int rc = dev_alloc(ctx, &ctx->ex_part, 3 * (size_t)need)) return rc;
+        ctx->ex_part_items = need;
+    }
+    return exact_launch(ctx, P, offsets_dev, modes_dev, max_clicks, ctx->ex_part, p_dev, logp_dev, kappa_dev,
+                        status_dev);
+}
+
 int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, double *logp_dev,
                  double *grad_r_dev, double *grad_eta_dev, int32_t *status_dev)
 {
@@ -811,6 +845,7 @@ int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, double *logp_
     if (pl->ctx != ctx) return set_err(ctx, GBS_E_STATE, "plan belongs to another context");
     if (!ctx->model.have || !ctx->model.from_params)
         return set_err(ctx, GBS_E_STATE, "gradient needs a model set by gbs_set_model");
+    if (ctx->model.M != pl->M) return set_err(ctx, GBS_E_STATE, "plan was made for a model of another size M");
     if (!dl_dev || !grad_r_dev || !grad_eta_dev) return set_err(ctx, GBS_E_INVAL, "NULL device array");
     if (pl->prec != GBS_PREC_FP64) return set_err(ctx, GBS_E_INVAL, "the gradient runs in fp64 only");
     if (pl->order > 3) return set_err(ctx, GBS_E_INVAL, "the gradient takes orders 1, 2 and 3");

@@ -8,6 +8,16 @@
 
 #define CONT_THREADS 512
 #define FIT_THREADS 256
+// Rounding of a contour value relative to the largest value of its transform:
+// fp64 throughout (a few units of 2^-53), and the cluster sums of the mixed
+// precision tier, whose eliminations run in fp32 (a few units of 2^-24).
+#define ROUND_FP64 2e-16
+#define ROUND_FP32 2e-7
+// Mixed precision: a row whose estimated error exceeds this is run again in
+// fp64 (GBS_PS_ESCALATED); the tier's target is 1e-5.
+#ifndef MIXED_BOUND
+#define MIXED_BOUND 1e-6
+#endif
 #define FIT_MAXIT 100
 #define FIT_KPT (GBS_KMAX / FIT_THREADS)
 
@@ -120,17 +130,30 @@ __host__ __device__ __forceinline__ int cont_fixed() { return 16 * (CONT_THREADS
 // function at n photons, capped at 0.98 of the convergence radius
 // 1/max|alpha - 1|) and the size K (a power of two >= 2n + 32 whose aliasing
 // factor (rho/R_b)^K is below 1e-16, at most GBS_KMAX); then log G_0(rho).
+// (The radius thus tilts towards max(n, untilted mean).)
+// A frozen radius is kept only while it still lies inside the current
+// convergence disc with an aliasing factor (rho max|alpha - 1|)^K <= 1e-14 (the
+// rule above with a margin, so that small changes of the model keep the plan);
+// otherwise the row is planned afresh and flagged GBS_PS_CONTOUR.
 __device__ __forceinline__ void row_plan(RowPlan &rp, int n, const double *alpha, int astride,
                                          double logdetQ, double logdetA, double amin, double dev,
                                          bool nonpd, int frozen, bool whole = false)
 {
     const int N = 2 * n;
     rp.status = 0;
+    rp.flags = 0;
     rp.logdet_a = logdetA;
     rp.log_pvac = -0.5 * (logdetQ + logdetA);
     if (!(amin > 0.0) || nonpd) {
         rp.status = GBS_PS_PIVOT;
         return;
+    }
+    if (frozen) {
+        const double x = rp.rho * dev;
+        if (!(rp.K > 0 && rp.K <= GBS_KMAX) || !(x < 1.0) || (x > 0.0 && rp.K * log(x) > log(1e-14))) {
+            frozen = 0;
+            rp.flags = GBS_PS_CONTOUR;
+        }
     }
     if (!frozen) {
         const double rb = dev > 1e-300 ? 1.0 / dev : 1e300;
@@ -144,9 +167,12 @@ __device__ __forceinline__ void row_plan(RowPlan &rp, int n, const double *alpha
             return s;
         };
         // the tilted mean photon number is set to n (the sectors of a click
-        // pattern of n detectors), or, for the whole distribution, to the
+        // pattern of n detectors start at n), or to the untilted mean where that
+        // is larger (then the sectors that carry the estimate lie at and above
+        // the untilted mean, and a radius below 1 would push them under the
+        // transform's rounding floor); for the whole distribution, to the
         // untilted mean: rho = 1, every sector at its own weight
-        const double target = whole ? mfun(1.0) : (double)n;
+        const double target = whole ? mfun(1.0) : fmax((double)n, mfun(1.0));
         double rho;
         if (dev < 1e-300) rho = 1.0;
         else if (mfun(hi) <= target) rho = hi;
@@ -580,6 +606,37 @@ __device__ __noinline__ SectorFitT<JM> fit_sector(int n, int v0, int jp, double 
     r.jr = jr;
     r.bad = bad;
     return r;
+}
+
+// Sensitivity of a fitted sector's log q(n) to its moments: d log q / d m_t =
+// -u_t with u = H^{-1} m, H the covariance of the basis under the fitted
+// distribution (t < jr; zero for the moments the fit did not use).
+template <int JM>
+__device__ __noinline__ void fit_sensitivity(int n, const SectorFitT<JM> &f, double *u)
+{
+    const double binv[4] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
+                            6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0)),
+                            24.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0) * (n - 4.0))};
+    double lse, E[4], E2[10];
+    bool ok = true;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) u[t] = 0.0;
+    switch (f.jr) {
+    case 0: return;
+    case 1: fit_eval<1, true>(n, 0, binv, f.c, &lse, E, E2); ok = fit_solve<1>(E, E2, f.m, u); break;
+    case 2: fit_eval<2, true>(n, 0, binv, f.c, &lse, E, E2); ok = fit_solve<2>(E, E2, f.m, u); break;
+    case 3:
+        fit_eval<JM >= 3 ? 3 : 1, true>(n, 0, binv, f.c, &lse, E, E2);
+        ok = fit_solve<JM >= 3 ? 3 : 1>(E, E2, f.m, u);
+        break;
+    default:
+        fit_eval<JM >= 4 ? 4 : 1, true>(n, 0, binv, f.c, &lse, E, E2);
+        ok = fit_solve<JM >= 4 ? 4 : 1>(E, E2, f.m, u);
+        break;
+    }
+    if (!ok)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) u[t] = 1e300;
 }
 
 }  // namespace

@@ -7,19 +7,37 @@
 // mode at a time, so the subsets form a binary include/exclude tree over the
 // clicked modes and every tree edge that includes a mode costs one rank-2
 // update of the remaining matrix.  Work split:
-//   - the first h = max(0, n-9) modes: one work item (one wavefront) per
-//     included/excluded assignment z0; the wave conditions A on the included
-//     prefix modes by successive Schur steps in LDS;
+//   - the first h = max(0, n-9) modes: 2^h included/excluded assignments z0,
+//     dealt to at most 2^EX_LGI work items (one wavefront each) per row, each
+//     item taking a contiguous range of z0 in turn; for each z0 the wave
+//     conditions A on the included prefix modes by successive Schur steps in
+//     LDS;
 //   - the next m = R-3 modes (R = n-h <= 9): breadth-first expansion in LDS,
 //     level by level, ending with 2^m <= 64 nodes, one per lane;
 //   - the last 3 modes: each lane evaluates its node's 8 subsets in registers.
 // All matrices are kept as packed symmetric double-double (hi/lo planes) with
 // the two quadratures of a mode interleaved.  Signed sums are double-double,
 // reduced in a fixed order; kappa = sum|terms| / |sum| is returned.
+#include <algorithm>
+
 #include "internal.h"
 
-#define EX_R 9          // modes handled inside one work item
-#define EX_BUF 1344     // packed dd entries per LDS buffer (64 nodes x 21)
+#define EX_R 9          // modes handled inside one prefix assignment
+#define EX_BUF 1344     // packed dd entries of the 64 nodes x 21 of the last level
+#define EX_LGI 12       // at most 2^12 work items per row
+
+// packed dd entries per LDS buffer for rows of up to maxn clicks: the last
+// expansion level, or the matrix of all maxn modes
+__host__ __device__ __forceinline__ int ex_buf(int maxn)
+{
+    const int k = maxn * (2 * maxn + 1);
+    return k > EX_BUF ? k : EX_BUF;
+}
+__host__ __device__ __forceinline__ int ex_lds_bytes(int maxn)
+{
+    // two buffers (hi and lo planes) and the packed index tables (two shorts)
+    return 4 * 8 * ex_buf(maxn) + 2 * 2 * ex_buf(maxn);
+}
 
 namespace {
 
@@ -156,159 +174,204 @@ __device__ __forceinline__ dd wave_dd_sum(dd v)
     return v;
 }
 
+// One work item: row p = item >> lgS, part i = item & (S - 1) of its 2^h prefix
+// assignments (rows of more than maxn clicks, or with modes outside [0, M) or
+// not ascending, are left to k_exact_final, which flags them).
 __global__ __launch_bounds__(64) void k_exact(int M, const double *__restrict__ qi_hi,
                                               const double *__restrict__ qi_lo,
                                               const int *__restrict__ offsets,
-                                              const int *__restrict__ modes,
-                                              const int2 *__restrict__ items,
+                                              const int *__restrict__ modes, int lgS, int maxn,
                                               double *__restrict__ part)
 {
-    __shared__ double bh[2][EX_BUF], bl[2][EX_BUF];
+    extern __shared__ __attribute__((aligned(16))) double exsh[];
     __shared__ double nacc_h[2][64], nacc_l[2][64];
     __shared__ int npar[2][64];
     __shared__ double ninv_h[3][32], ninv_l[3][32];
-    __shared__ short lr[EX_BUF], lc[EX_BUF];
     __shared__ int gidx[2 * GBS_MAX_N_EXACT];
+    __shared__ int s_bad;
+    const int BUF = ex_buf(maxn);
+    double *bh0 = exsh, *bh1 = bh0 + BUF, *bl0 = bh1 + BUF, *bl1 = bl0 + BUF;
+    short *lr = (short *)(bl1 + BUF), *lc = lr + BUF;
     const int lane = threadIdx.x;
-    const int2 it = items[blockIdx.x];
-    const int p = it.x, z0 = it.y;
+    const long long item = blockIdx.x;
+    const int p = (int)(item >> lgS), ip = (int)(item & ((1LL << lgS) - 1));
     const int o = offsets[p], n = offsets[p + 1] - o;
+    if (n <= 0 || n > maxn) return;
     const int D = 2 * M;
     const int h = n > EX_R ? n - EX_R : 0;
     const int R = n - h;
-    // packed-index -> (row, col) tables for up to 2*GBS_MAX_N_EXACT rows
-    for (int r = lane; r < 2 * GBS_MAX_N_EXACT; r += 64)
+    const int lgI = h < EX_LGI ? h : EX_LGI;   // this row's items: 2^lgI
+    if (ip >= (1 << lgI)) return;
+    const int lgC = h - lgI;                    // prefix assignments per item: 2^lgC
+    if (lane == 0) {
+        int bad = 0;
+        for (int i = 0; i < n; ++i) {
+            const int m = modes[o + i];
+            if (m < 0 || m >= M || (i > 0 && m <= modes[o + i - 1])) bad = 1;
+        }
+        s_bad = bad;
+    }
+    // packed-index -> (row, col) tables for up to 2 maxn rows
+    for (int r = lane; r < 2 * maxn; r += 64)
         for (int c = 0; c <= r; ++c) {
             int e = r * (r + 1) / 2 + c;
-            if (e < EX_BUF) {
+            if (e < BUF) {
                 lr[e] = (short)r;
                 lc[e] = (short)c;
             }
         }
-    // local mode list: included prefix modes, then the last R modes
-    int kz = 0;
-    if (lane == 0) {
-        for (int i = 0; i < h; ++i)
-            if (z0 >> i & 1) gidx[kz++] = modes[o + i];
-        for (int i = h; i < n; ++i) gidx[kz++] = modes[o + i];
-    }
     __syncthreads();
-    const int nz0 = __popc(z0);
-    int k = nz0 + R;
-    Buf B0{bh[0], bl[0]}, B1{bh[1], bl[1]};
-    for (int e = lane; e < k * (2 * k + 1); e += 64) {
-        int r = lr[e], c = lc[e];
-        int gr = gidx[r >> 1] + ((r & 1) ? M : 0);
-        int gc = gidx[c >> 1] + ((c & 1) ? M : 0);
-        B0.put(e, dd{qi_hi[(long)gr * D + gc], qi_lo[(long)gr * D + gc]});
-    }
-    __syncthreads();
-    // condition on the included prefix modes
-    dd acc = dd_make(1.0);
-    int cur = 0;
-    for (int s = 0; s < nz0; ++s) {
-        Buf src = cur ? B1 : B0, dst = cur ? B0 : B1;
-        const Sym2 s00 = sblk(src, 0, 0);
-        const dd det = det2(s00);
-        const Sym2 inv = inv2(s00, det);
-        acc = dd_mul(acc, dd_rsqrt(det));
-        const int cnt = (k - 1) * (2 * k - 1);
-        for (int e = lane; e < cnt; e += 64) schur_first(src, 0, dst, 0, k, inv, e, lr, lc);
+    if (s_bad) return;
+    dd rtot = dd_make(0.0);
+    double rab = 0.0;
+    for (int zi = 0; zi < (1 << lgC); ++zi) {
+        const int z0 = (ip << lgC) | zi;
+        // local mode list: included prefix modes, then the last R modes
+        int kz = 0;
+        if (lane == 0) {
+            for (int i = 0; i < h; ++i)
+                if (z0 >> i & 1) gidx[kz++] = modes[o + i];
+            for (int i = h; i < n; ++i) gidx[kz++] = modes[o + i];
+        }
         __syncthreads();
-        cur ^= 1;
-        --k;
-    }
-    // breadth-first expansion of the next m modes
-    const int sl = R < 3 ? R : 3;
-    const int m = R - sl;
-    if (lane == 0) {
-        nacc_h[0][0] = acc.hi;
-        nacc_l[0][0] = acc.lo;
-        npar[0][0] = nz0 & 1;
-    }
-    int nc = 0;  // node-info buffer
-    __syncthreads();
-    for (int lev = 0; lev < m; ++lev) {
-        Buf src = cur ? B1 : B0, dst = cur ? B0 : B1;
-        const int nodes = 1 << lev;
-        const int cs = k * (2 * k + 1);            // packed size per parent
-        const int cd = (k - 1) * (2 * k - 1);      // packed size per child
-        // children node info: 2i exclude, 2i+1 include
-        for (int i = lane; i < nodes; i += 64) {
-            const Sym2 s00 = sblk(src, i * cs, 0);
+        const int nz0 = __popc(z0);
+        int k = nz0 + R;
+        Buf B0{bh0, bl0}, B1{bh1, bl1};
+        for (int e = lane; e < k * (2 * k + 1); e += 64) {
+            int r = lr[e], c = lc[e];
+            int gr = gidx[r >> 1] + ((r & 1) ? M : 0);
+            int gc = gidx[c >> 1] + ((c & 1) ? M : 0);
+            B0.put(e, dd{qi_hi[(long)gr * D + gc], qi_lo[(long)gr * D + gc]});
+        }
+        __syncthreads();
+        // condition on the included prefix modes
+        dd acc = dd_make(1.0);
+        int cur = 0;
+        for (int s = 0; s < nz0; ++s) {
+            Buf src = cur ? B1 : B0, dst = cur ? B0 : B1;
+            const Sym2 s00 = sblk(src, 0, 0);
             const dd det = det2(s00);
             const Sym2 inv = inv2(s00, det);
-            ninv_h[0][i] = inv.a.hi; ninv_l[0][i] = inv.a.lo;
-            ninv_h[1][i] = inv.b.hi; ninv_l[1][i] = inv.b.lo;
-            ninv_h[2][i] = inv.c.hi; ninv_l[2][i] = inv.c.lo;
-            dd a = dd{nacc_h[nc][i], nacc_l[nc][i]};
-            const int par = npar[nc][i];
-            nacc_h[nc ^ 1][2 * i] = a.hi;
-            nacc_l[nc ^ 1][2 * i] = a.lo;
-            npar[nc ^ 1][2 * i] = par;
-            dd ai = dd_mul(a, dd_rsqrt(det));
-            nacc_h[nc ^ 1][2 * i + 1] = ai.hi;
-            nacc_l[nc ^ 1][2 * i + 1] = ai.lo;
-            npar[nc ^ 1][2 * i + 1] = par ^ 1;
+            acc = dd_mul(acc, dd_rsqrt(det));
+            const int cnt = (k - 1) * (2 * k - 1);
+            for (int e = lane; e < cnt; e += 64) schur_first(src, 0, dst, 0, k, inv, e, lr, lc);
+            __syncthreads();
+            cur ^= 1;
+            --k;
         }
+        // breadth-first expansion of the next m modes
+        const int sl = R < 3 ? R : 3;
+        const int m = R - sl;
+        if (lane == 0) {
+            nacc_h[0][0] = acc.hi;
+            nacc_l[0][0] = acc.lo;
+            npar[0][0] = nz0 & 1;
+        }
+        int nc = 0;  // node-info buffer
         __syncthreads();
-        for (int e = lane; e < 2 * nodes * cd; e += 64) {
-            const int child = e / cd, idx = e - child * cd;
-            const int parent = child >> 1;
-            if (child & 1) {
-                const Sym2 inv{dd{ninv_h[0][parent], ninv_l[0][parent]},
-                               dd{ninv_h[1][parent], ninv_l[1][parent]},
-                               dd{ninv_h[2][parent], ninv_l[2][parent]}};
-                schur_first(src, parent * cs, dst, child * cd, k, inv, idx, lr, lc);
-            } else {
-                const int r = lr[idx] + 2, c = lc[idx] + 2;
-                dst.put(child * cd + idx, src.get(parent * cs + pk(r, c)));
+        for (int lev = 0; lev < m; ++lev) {
+            Buf src = cur ? B1 : B0, dst = cur ? B0 : B1;
+            const int nodes = 1 << lev;
+            const int cs = k * (2 * k + 1);            // packed size per parent
+            const int cd = (k - 1) * (2 * k - 1);      // packed size per child
+            // children node info: 2i exclude, 2i+1 include
+            for (int i = lane; i < nodes; i += 64) {
+                const Sym2 s00 = sblk(src, i * cs, 0);
+                const dd det = det2(s00);
+                const Sym2 inv = inv2(s00, det);
+                ninv_h[0][i] = inv.a.hi; ninv_l[0][i] = inv.a.lo;
+                ninv_h[1][i] = inv.b.hi; ninv_l[1][i] = inv.b.lo;
+                ninv_h[2][i] = inv.c.hi; ninv_l[2][i] = inv.c.lo;
+                dd a = dd{nacc_h[nc][i], nacc_l[nc][i]};
+                const int par = npar[nc][i];
+                nacc_h[nc ^ 1][2 * i] = a.hi;
+                nacc_l[nc ^ 1][2 * i] = a.lo;
+                npar[nc ^ 1][2 * i] = par;
+                dd ai = dd_mul(a, dd_rsqrt(det));
+                nacc_h[nc ^ 1][2 * i + 1] = ai.hi;
+                nacc_l[nc ^ 1][2 * i + 1] = ai.lo;
+                npar[nc ^ 1][2 * i + 1] = par ^ 1;
+            }
+            __syncthreads();
+            for (int e = lane; e < 2 * nodes * cd; e += 64) {
+                const int child = e / cd, idx = e - child * cd;
+                const int parent = child >> 1;
+                if (child & 1) {
+                    const Sym2 inv{dd{ninv_h[0][parent], ninv_l[0][parent]},
+                                   dd{ninv_h[1][parent], ninv_l[1][parent]},
+                                   dd{ninv_h[2][parent], ninv_l[2][parent]}};
+                    schur_first(src, parent * cs, dst, child * cd, k, inv, idx, lr, lc);
+                } else {
+                    const int r = lr[idx] + 2, c = lc[idx] + 2;
+                    dst.put(child * cd + idx, src.get(parent * cs + pk(r, c)));
+                }
+            }
+            __syncthreads();
+            cur ^= 1;
+            nc ^= 1;
+            --k;
+        }
+        // leaves: one node per lane
+        dd tot = dd_make(0.0);
+        double ab = 0.0;
+        const int leaves = 1 << m;
+        if (lane < leaves) {
+            Buf src = cur ? B1 : B0;
+            const int cs = k * (2 * k + 1);
+            dd a = dd{nacc_h[nc][lane], nacc_l[nc][lane]};
+            const int par = (n + npar[nc][lane]) & 1;
+            if (sl == 3) leaf<3>(src, lane * cs, a, par, tot, ab);
+            else if (sl == 2) leaf<2>(src, lane * cs, a, par, tot, ab);
+            else if (sl == 1) leaf<1>(src, lane * cs, a, par, tot, ab);
+            else {
+                tot = (par & 1) ? dd_neg(a) : a;  // n = 0: the empty set only
+                ab = fabs(a.hi);
             }
         }
+        tot = wave_dd_sum(tot);
+        for (int mm = 32; mm > 0; mm >>= 1) ab += __shfl_xor(ab, mm);
+        rtot = dd_add(rtot, tot);
+        rab += ab;
         __syncthreads();
-        cur ^= 1;
-        nc ^= 1;
-        --k;
     }
-    // leaves: one node per lane
-    dd tot = dd_make(0.0);
-    double ab = 0.0;
-    const int leaves = 1 << m;
-    if (lane < leaves) {
-        Buf src = cur ? B1 : B0;
-        const int cs = k * (2 * k + 1);
-        dd a = dd{nacc_h[nc][lane], nacc_l[nc][lane]};
-        const int par = (n + npar[nc][lane]) & 1;
-        if (sl == 3) leaf<3>(src, lane * cs, a, par, tot, ab);
-        else if (sl == 2) leaf<2>(src, lane * cs, a, par, tot, ab);
-        else if (sl == 1) leaf<1>(src, lane * cs, a, par, tot, ab);
-        else {
-            tot = (par & 1) ? dd_neg(a) : a;  // n = 0: the empty set only
-            ab = fabs(a.hi);
-        }
-    }
-    tot = wave_dd_sum(tot);
-    for (int mm = 32; mm > 0; mm >>= 1) ab += __shfl_xor(ab, mm);
     if (lane == 0) {
-        part[3 * (long)blockIdx.x] = tot.hi;
-        part[3 * (long)blockIdx.x + 1] = tot.lo;
-        part[3 * (long)blockIdx.x + 2] = ab;
+        part[3 * item] = rtot.hi;
+        part[3 * item + 1] = rtot.lo;
+        part[3 * item + 2] = rab;
     }
 }
 
-// Per row: fixed-order sum of the item partials, times det(Q)^{-1/2}.
-__global__ void k_exact_final(int P, const int *__restrict__ offsets, const int *__restrict__ item_off,
-                              const double *__restrict__ part, const double *__restrict__ scal,
-                              double *__restrict__ out)
+// Per row: the CSR check, the fixed-order sum of the item partials, times
+// det(Q)^{-1/2}.  Outputs: p, status (required), logp, kappa (nullable).
+__global__ void k_exact_final(int P, int M, const int *__restrict__ offsets, const int *__restrict__ modes,
+                              int lgS, int maxn, const double *__restrict__ part,
+                              const double *__restrict__ scal, double *__restrict__ p_out,
+                              double *__restrict__ logp_out, double *__restrict__ kappa_out,
+                              int *__restrict__ status_out)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
-    const int n = offsets[p + 1] - offsets[p];
+    const int o = offsets[p], n = offsets[p + 1] - o;
+    bool bad = n < 0 || n > maxn;
+    for (int i = 0; i < n && !bad; ++i) {
+        const int m = modes[o + i];
+        bad = m < 0 || m >= M || (i > 0 && m <= modes[o + i - 1]);
+    }
+    if (bad) {
+        p_out[p] = NAN;
+        if (logp_out) logp_out[p] = NAN;
+        if (kappa_out) kappa_out[p] = NAN;
+        status_out[p] = GBS_PS_BADROW;
+        return;
+    }
+    const int h = n > EX_R ? n - EX_R : 0;
+    const int ni = 1 << (h < EX_LGI ? h : EX_LGI);
+    const long long i0 = (long long)p << lgS;
     dd s = dd_make(0.0);
     double ab = 0.0;
-    for (int i = item_off[p]; i < item_off[p + 1]; ++i) {
-        s = dd_add(s, dd{part[3 * (long)i], part[3 * (long)i + 1]});
-        ab += part[3 * (long)i + 2];
+    for (int i = 0; i < ni; ++i) {
+        s = dd_add(s, dd{part[3 * (i0 + i)], part[3 * (i0 + i) + 1]});
+        ab += part[3 * (i0 + i) + 2];
     }
     if (n == 0) {
         s = dd_make(1.0);
@@ -321,78 +384,91 @@ __global__ void k_exact_final(int P, const int *__restrict__ offsets, const int 
     // double-double terms carry ~1e-30 relative error; the sum is resolved to
     // 1e-10 unless it cancels by more than 1e20
     if (!(kappa < 1e20) || !(pr.hi > 0.0)) st = GBS_PS_CANCEL;
-    out[4 * (long)p] = pr.hi;
-    out[4 * (long)p + 1] = pr.hi > 0.0 ? log(pr.hi) + pr.lo / pr.hi : -INFINITY;
-    out[4 * (long)p + 2] = kappa;
-    out[4 * (long)p + 3] = (double)st;
+    p_out[p] = st ? NAN : pr.hi;
+    if (logp_out) logp_out[p] = st ? NAN : log(pr.hi) + pr.lo / pr.hi;
+    if (kappa_out) kappa_out[p] = kappa;
+    status_out[p] = st;
 }
 
 }  // namespace
 
-int exact_run(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, double *p,
-              double *logp, double *kappa, int32_t *status)
+// work items of a batch whose rows hold at most maxn clicks: P << exact_lgs(maxn)
+int exact_lgs(int maxn)
+{
+    const int h = maxn > EX_R ? maxn - EX_R : 0;
+    return h < EX_LGI ? h : EX_LGI;
+}
+
+// The exact path on device CSR: partials in d_part (3 doubles per work item,
+// at least P << exact_lgs(maxn) items), results into the device outputs.
+int exact_launch(gbs_ctx *ctx, int P, const int32_t *d_off, const int32_t *d_modes, int maxn, double *d_part,
+                 double *p_dev, double *logp_dev, double *kappa_dev, int32_t *status_dev)
 {
     if (P == 0) return 0;
     DevModel &m = ctx->model;
     hipStream_t st = ctx->stream;
-    // work items: (row, prefix assignment)
-    std::vector<int32_t> items, item_off(P + 1, 0);
-    for (int r = 0; r < P; ++r) {
-        int n = offsets[r + 1] - offsets[r];
-        int h = n > EX_R ? n - EX_R : 0;
-        item_off[r] = (int32_t)(items.size() / 2);
-        if (n == 0) continue;
-        for (int z = 0; z < (1 << h); ++z) items.insert(items.end(), {r, z});
-    }
-    item_off[P] = (int32_t)(items.size() / 2);
-    const int nitems = item_off[P];
+    const int lgS = exact_lgs(maxn);
+    const long long nitems = (long long)P << lgS;
+    if (nitems > 0x7fffffffLL) return set_err(ctx, GBS_E_INVAL, "exact: too many work items (rows x 2^12)");
+    const int lds = ex_lds_bytes(maxn);
+    if (int rc = func_lds_limit(ctx, (const void *)k_exact, lds)) return rc;
+    const int ts = timer_begin(ctx, TG_EXACT);
+    if (maxn > 0)
+        hipLaunchKernelGGL(k_exact, dim3((unsigned)nitems), dim3(64), lds, st, m.M, m.qi_hi, m.qi_lo, d_off,
+                           d_modes, lgS, maxn, d_part);
+    hipLaunchKernelGGL(k_exact_final, dim3((P + 127) / 128), dim3(128), 0, st, P, m.M, d_off, d_modes, lgS, maxn,
+                       d_part, m.scal, p_dev, logp_dev, kappa_dev, status_dev);
+    timer_end(ctx, ts);
+    HIP_TRY(ctx, hipGetLastError());
+    return 0;
+}
+
+// Host CSR (already checked): copies in, one launch, copies out.
+int exact_run(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, double *p,
+              double *logp, double *kappa, int32_t *status)
+{
+    if (P == 0) return 0;
+    hipStream_t st = ctx->stream;
+    int maxn = 0;
+    for (int r = 0; r < P; ++r) maxn = std::max(maxn, offsets[r + 1] - offsets[r]);
+    const long long nitems = (long long)P << exact_lgs(maxn);
     const int nnz = offsets[P];
-    int32_t *d_off = nullptr, *d_modes = nullptr, *d_items = nullptr, *d_ioff = nullptr;
+    int32_t *d_off = nullptr, *d_modes = nullptr, *d_st = nullptr;
     double *d_part = nullptr, *d_out = nullptr;
     auto cleanup = [&]() {
-        void *ptrs[] = {d_off, d_modes, d_items, d_ioff, d_part, d_out};
+        void *ptrs[] = {d_off, d_modes, d_st, d_part, d_out};
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
     };
     if (hipMalloc((void **)&d_off, (P + 1) * sizeof(int32_t)) != hipSuccess ||
         hipMalloc((void **)&d_modes, std::max(nnz, 1) * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc((void **)&d_items, std::max(nitems, 1) * 2 * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc((void **)&d_ioff, (P + 1) * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc((void **)&d_part, std::max(nitems, 1) * 3 * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&d_out, (size_t)P * 4 * sizeof(double)) != hipSuccess) {
+        hipMalloc((void **)&d_st, P * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void **)&d_part, std::max(nitems, 1LL) * 3 * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&d_out, (size_t)P * 3 * sizeof(double)) != hipSuccess) {
         cleanup();
         return set_err(ctx, GBS_E_NOMEM, "exact: device allocation failed");
     }
     hipError_t e = hipMemcpyAsync(d_off, offsets, (P + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && nnz)
         e = hipMemcpyAsync(d_modes, modes, nnz * sizeof(int32_t), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && nitems)
-        e = hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d_ioff, item_off.data(), (P + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st);
-    const int ts = timer_begin(ctx, TG_EXACT);
-    if (e == hipSuccess && nitems) {
-        hipLaunchKernelGGL(k_exact, dim3(nitems), dim3(64), 0, st, m.M, m.qi_hi, m.qi_lo, d_off,
-                           d_modes, (const int2 *)d_items, d_part);
-        e = hipGetLastError();
+    if (e != hipSuccess) {
+        cleanup();
+        return set_err(ctx, GBS_E_HIP, std::string("exact: ") + hipGetErrorString(e));
     }
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_exact_final, dim3((P + 127) / 128), dim3(128), 0, st, P, d_off, d_ioff,
-                           d_part, m.scal, d_out);
-        e = hipGetLastError();
-    }
-    timer_end(ctx, ts);
-    std::vector<double> out((size_t)P * 4);
-    if (e == hipSuccess)
+    int rc = exact_launch(ctx, P, d_off, d_modes, maxn, d_part, d_out, d_out + P, d_out + 2 * P, d_st);
+    std::vector<double> out((size_t)P * 3);
+    if (!rc) {
         e = hipMemcpyAsync(out.data(), d_out, out.size() * sizeof(double), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = hipMemcpyAsync(status, d_st, P * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = set_err(ctx, GBS_E_HIP, std::string("exact: ") + hipGetErrorString(e));
+    }
     cleanup();
-    if (e != hipSuccess) return set_err(ctx, GBS_E_HIP, std::string("exact: ") + hipGetErrorString(e));
+    if (rc) return rc;
     for (int r = 0; r < P; ++r) {
-        p[r] = out[4 * (size_t)r];
-        if (logp) logp[r] = out[4 * (size_t)r + 1];
-        if (kappa) kappa[r] = out[4 * (size_t)r + 2];
-        status[r] = (int32_t)out[4 * (size_t)r + 3];
+        p[r] = out[r];
+        if (logp) logp[r] = out[P + r];
+        if (kappa) kappa[r] = out[2 * (size_t)P + r];
     }
     return 0;
 }

@@ -45,6 +45,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
                                                          const RowPlan *__restrict__ rows,
                                                          const cplx *__restrict__ sw,
                                                          const double *__restrict__ dl,
+                                                         const int *__restrict__ status,
                                                          cplx *__restrict__ asw)
 {
     extern __shared__ __attribute__((aligned(16))) double sh[];
@@ -53,7 +54,8 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
     const int n = offsets[p + 1] - offsets[p];
     const RowPlan rp = rows[p];
     const double wp = dl[p];
-    if (n == 0 || rp.status != 0 || wp == 0.0 || !isfinite(wp)) {
+    // (rows without a forward result take no part)
+    if (n == 0 || rp.status != 0 || (status[p] & GBS_PS_FAILED) || wp == 0.0 || !isfinite(wp)) {
         for (int i = tid; i < (ORDER + 1) * GBS_QCAP; i += nt)
             asw[(long)p * (ORDER + 1) * GBS_QCAP + i] = cmk(0.0, 0.0);
         return;
@@ -1003,6 +1005,7 @@ __global__ __launch_bounds__(256) void k_adj_reduce(int M, const int *__restrict
                                                     const double *__restrict__ vt,
                                                     const RowPlan *__restrict__ rows,
                                                     const double *__restrict__ dl,
+                                                    const int *__restrict__ status,
                                                     const int *__restrict__ row_item0,
                                                     const long long *__restrict__ roff,
                                                     const double *__restrict__ rscr,
@@ -1015,7 +1018,7 @@ __global__ __launch_bounds__(256) void k_adj_reduce(int M, const int *__restrict
     const long long vo = voff[p];
     if (n == 0 || n > GBS_NSMALL) return;
     const int it0 = row_item0[p];
-    if (it0 < 0 || rp.status != 0 || !isfinite(dl[p]) || dl[p] == 0.0) return;
+    if (it0 < 0 || rp.status != 0 || (status[p] & GBS_PS_FAILED) || !isfinite(dl[p]) || dl[p] == 0.0) return;
     const int nit = (rp.K / 2 + 1 + ADJ_QCHUNK - 1) / ADJ_QCHUNK;
     double *V = sh;            // V[i][k] row-major
     double *R = V + N * N;     // full symmetric
@@ -1068,6 +1071,7 @@ __global__ __launch_bounds__(256) void k_adj_reduce_big(int M, const int *__rest
                                                         const double *__restrict__ vt,
                                                         const RowPlan *__restrict__ rows,
                                                         const double *__restrict__ dl,
+                                                        const int *__restrict__ status,
                                                         const int *__restrict__ row_item0,
                                                         const long long *__restrict__ roff,
                                                         const double *__restrict__ rscr,
@@ -1079,7 +1083,9 @@ __global__ __launch_bounds__(256) void k_adj_reduce_big(int M, const int *__rest
     const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
     const RowPlan rp = rows[p];
     const int it0 = row_item0[p];
-    if (n == 0 || it0 < 0 || rp.status != 0 || !isfinite(dl[p]) || dl[p] == 0.0) return;
+    if (n == 0 || it0 < 0 || rp.status != 0 || (status[p] & GBS_PS_FAILED) || !isfinite(dl[p]) ||
+        dl[p] == 0.0)
+        return;
     const int nit = (rp.K / 2 + 1 + ADJ_QCHUNK - 1) / ADJ_QCHUNK;
     const long long vo = voff[p];
     const double *Vt = vt + vo;          // Vt[k*N + i] = V[i][k]
@@ -1131,7 +1137,7 @@ __global__ __launch_bounds__(1024) void k_adj_model(int M, int P, const double *
     const double *r = params + 2L * M * M, *eta = r + M;
     double ws = 0.0;
     for (int p = tid; p < P; p += nt)
-        if (status[p] == 0 && isfinite(dl[p])) ws += dl[p];
+        if ((status[p] & GBS_PS_FAILED) == 0 && isfinite(dl[p])) ws += dl[p];
     ws = block_sum(ws, red);
     // tmp = Psi Q^{-1}
     for (int idx = tid; idx < D * D; idx += nt) {
@@ -1206,7 +1212,7 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
     if (int rc = func_lds_limit(ctx, (const void *)k_adj_fit<ORDER>, (int)lds_f)) return rc;
     int ts = timer_begin(ctx, TG_ADJ_FIT);
     hipLaunchKernelGGL(k_adj_fit<ORDER>, dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
-                       pl->d_rows, pl->d_sw, dl, pl->d_asw);
+                       pl->d_rows, pl->d_sw, dl, status, pl->d_asw);
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_ADJ_CLUSTER);
     hipLaunchKernelGGL(k_adj_items, dim3(1), dim3(1024), 0, st, P, pl->nbig, pl->d_offsets, pl->d_perm,
@@ -1260,13 +1266,13 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
         size_t lds_r = sizeof(double) * 3 * (size_t)N * N + sizeof(int) * N;
         if (int rc = func_lds_limit(ctx, (const void *)k_adj_reduce, (int)lds_r)) return rc;
         hipLaunchKernelGGL(k_adj_reduce, dim3(P), dim3(256), lds_r, st, M, pl->d_offsets, pl->d_modes,
-                           pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, dl, pl->d_ritem0, pl->d_roff,
-                           pl->d_rscr, pl->d_qibar);
+                           pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, dl, status, pl->d_ritem0,
+                           pl->d_roff, pl->d_rscr, pl->d_qibar);
     }
     if (pl->nbig > 0)
         hipLaunchKernelGGL(k_adj_reduce_big, dim3(pl->nbig), dim3(256), 0, st, M, pl->d_offsets,
                            pl->d_modes, pl->d_perm, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, dl,
-                           pl->d_ritem0, pl->d_roff, pl->d_rscr, pl->d_wbig, pl->d_qibar);
+                           status, pl->d_ritem0, pl->d_roff, pl->d_rscr, pl->d_wbig, pl->d_qibar);
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_ADJ_MODEL);
     hipLaunchKernelGGL(k_adj_model, dim3(1), dim3(1024), 0, st, M, P, m.qi_hi, m.params, dl,

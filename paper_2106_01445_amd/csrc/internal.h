@@ -16,7 +16,7 @@
 #define GBS_MAX_N_ORDER4 40    // clicks per row at order 4 (the LDS-resident path only)
 #define GBS_NSMALL 40          // rows up to this many clicks keep V and M(w) in LDS (contour)
 #define GBS_RSLOTS 3           // R slots per adjoint work item of such a row (column units)
-#define GBS_MAX_N_EXACT 24     // clicks per row on the exact path
+#define GBS_MAX_N_EXACT 30     // clicks per row on the exact path
 #define GBS_KMAX 2048          // contour size cap
 #define GBS_QCAP (GBS_KMAX / 2 + 1)
 #define GBS_QCHUNK 8           // contour points per work item (default)
@@ -67,6 +67,9 @@ struct gbs_ctx {
     // the kernel itself, so a step can be recorded into a HIP graph
     std::map<const void *, int> lds_limit, lds_static;
     std::map<std::pair<const void *, int>, int> occupancy;
+    // partial sums of gbs_prob_exact_dev (grown on demand, freed with the context)
+    double *ex_part = nullptr;
+    long long ex_part_items = 0;
 };
 
 // Cached kernel queries (see gbs_ctx).
@@ -80,14 +83,22 @@ void timer_end(gbs_ctx *ctx, int slot);
 enum { TG_MODEL = 0, TG_PREP = 1, TG_ITEMS = 2, TG_CONTOUR = 3, TG_FIT = 4, TG_EXACT = 5,
        TG_ADJ_FIT = 6, TG_ADJ_CLUSTER = 7, TG_ADJ_ROWS = 8, TG_ADJ_MODEL = 9 };
 
-// Per-row scalar results of the approximate path's set-up step.
+// Per-row scalar results of the approximate path's set-up step.  status holds
+// the failure bits (the row has no result); flags the informational bits that
+// are reported with a valid result (GBS_PS_CONTOUR, GBS_PS_ESCALATED).
 struct RowPlan {
     double rho, rconv, log_g_rho, logdet_a, log_pvac, log_rho;
-    int K, status, nsec, pad;
+    double err;   // estimated rounding error of log p_hat (sector transform and fits)
+    int K, status, nsec, flags;
 };
+
+// status bits that mean "no result" (the output is NaN); the others are
+// informational
+#define GBS_PS_FAILED (GBS_PS_FIT_NOCONV | GBS_PS_PIVOT | GBS_PS_CANCEL)
 
 struct gbs_plan {
     gbs_ctx *ctx = nullptr;
+    int M = 0;                            // modes of the model the plan was made for
     int P = 0, order = 0, prec = 0, max_n = 0;
     int nbig = 0;                         // rows with more than GBS_NSMALL clicks: perm[0..nbig)
     // tunable launch choices (gbs_plan_tune): cluster segment length of the
@@ -152,6 +163,9 @@ int model_build_dev(gbs_ctx *ctx, const double *sigma_dev, bool sync);
 int approx_forward(gbs_ctx *ctx, gbs_plan *plan, double *logp_dev, int32_t *status_dev);
 int exact_run(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, double *p,
               double *logp, double *kappa, int32_t *status);
+int exact_lgs(int maxn);
+int exact_launch(gbs_ctx *ctx, int P, const int32_t *d_off, const int32_t *d_modes, int maxn, double *d_part,
+                 double *p_dev, double *logp_dev, double *kappa_dev, int32_t *status_dev);
 int approx_backward(gbs_ctx *ctx, gbs_plan *plan, const double *dl_dev, const int32_t *status_dev,
                     double *grad_r_dev, double *grad_eta_dev);
 int eig_rows(gbs_ctx *ctx, gbs_plan *plan);

@@ -18,14 +18,15 @@ LIB_PATH = os.path.join(_HERE, "libgbs.so")
 
 GBS_OK, GBS_E_INVAL, GBS_E_NOTPD, GBS_E_NOMEM, GBS_E_HIP, GBS_E_STATE, GBS_W_PATTERN = 0, -1, -2, -3, -4, -5, 1
 GBS_PREC_FP64, GBS_PREC_MIXED = 0, 1
-GBS_PS_FIT_NOCONV, GBS_PS_CONTOUR, GBS_PS_PIVOT, GBS_PS_CANCEL = 1, 2, 4, 16
+GBS_PS_FIT_NOCONV, GBS_PS_CONTOUR, GBS_PS_PIVOT, GBS_PS_ESCALATED, GBS_PS_CANCEL, GBS_PS_BADROW = 1, 2, 4, 8, 16, 32
+GBS_PS_FAILED = GBS_PS_FIT_NOCONV | GBS_PS_PIVOT | GBS_PS_CANCEL | GBS_PS_BADROW
 
 EXPORTS = ["gbs_create", "gbs_destroy", "gbs_last_error", "gbs_set_model", "gbs_set_model_dev",
            "gbs_set_covariance", "gbs_get_model", "gbs_prob_exact", "gbs_prob_approx",
            "gbs_prob_approx_plain", "gbs_plan_get_params", "gbs_plan_set_params", "gbs_plan_tune",
            "gbs_plan_create", "gbs_plan_destroy", "gbs_plan_freeze", "gbs_prob_approx_dev",
            "gbs_grad", "gbs_grad_dev", "gbs_plan_info", "gbs_set_timing", "gbs_timing",
-           "gbs_stream", "gbs_click_distribution"]
+           "gbs_stream", "gbs_click_distribution", "gbs_prob_exact_dev"]
 TIMING_GROUPS = ["model", "row_setup", "work_queue", "contour_clusters", "dft_fit", "exact",
                  "adjoint_fit_dft", "adjoint_contour_clusters", "adjoint_rows_scatter",
                  "adjoint_model"]
@@ -75,9 +76,10 @@ def load(path: str = LIB_PATH):
         "gbs_prob_approx_dev": ([vp, vp, dp, i32p], ip),
         "gbs_grad": ([vp, ip, i32p, i32p, ip, ip, dp, dp, dp, dp, i32p], ip),
         "gbs_grad_dev": ([vp, vp, dp, dp, dp, dp, i32p], ip),
-        "gbs_plan_info": ([vp, dp, dp, i32p, i32p], ip),
+        "gbs_plan_info": ([vp, dp, dp, i32p, i32p, dp], ip),
         "gbs_stream": ([vp], vp),
         "gbs_click_distribution": ([vp, ip, ip, i32p, dp, dp, i32p], ip),
+        "gbs_prob_exact_dev": ([vp, ip, i32p, i32p, ip, dp, dp, dp, i32p], ip),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -99,12 +101,22 @@ def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
 
 
-def _dptr(t):
-    """Device pointer of a torch tensor (or an int address)."""
+def _dptr(t, dtype: str = None, numel: Optional[int] = None, name: str = "tensor"):
+    """Device pointer of a torch tensor (or an int address, passed through
+    unchecked).  A tensor must live on a GPU, be contiguous, and, where given,
+    have the C type `dtype` ("float64" or "int32") and `numel` elements."""
     if t is None:
         return None
     if isinstance(t, int):
         return ctypes.c_void_p(t)
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor, got one on {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and str(t.dtype) != "torch." + dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -116,10 +128,10 @@ class Plan:
         self.ctx._check(load().gbs_plan_freeze(self.handle, int(on)))
 
     def info(self):
-        rho, rc = np.zeros(self.P), np.zeros(self.P)
+        rho, rc, err = np.zeros(self.P), np.zeros(self.P), np.zeros(self.P)
         K, ns = np.zeros(self.P, np.int32), np.zeros(self.P, np.int32)
-        self.ctx._check(load().gbs_plan_info(self.handle, _ptr(rho), _ptr(rc), _ptr(K), _ptr(ns)))
-        return dict(rho=rho, rconv=rc, K=K, nsectors=ns)
+        self.ctx._check(load().gbs_plan_info(self.handle, _ptr(rho), _ptr(rc), _ptr(K), _ptr(ns), _ptr(err)))
+        return dict(rho=rho, rconv=rc, K=K, nsectors=ns, err=err)
 
     def get_params(self):
         prm = np.zeros(4, np.int32)
@@ -188,10 +200,13 @@ class Context:
         self.M = M
 
     def gbs_set_model_dev(self, U_re_dev, U_im_dev, r_dev, eta_dev):
-        """Stream-ordered model build from device tensors (float64, contiguous)."""
+        """Stream-ordered model build from device tensors (float64, contiguous;
+        U planes M x M, r and eta of length M)."""
         M = int(r_dev.shape[0])
-        self._check(load().gbs_set_model_dev(self.handle, M, _dptr(U_re_dev), _dptr(U_im_dev),
-                                             _dptr(r_dev), _dptr(eta_dev)))
+        f = "float64"
+        self._check(load().gbs_set_model_dev(self.handle, M, _dptr(U_re_dev, f, M * M, "U_re"),
+                                             _dptr(U_im_dev, f, M * M, "U_im"), _dptr(r_dev, f, M, "r"),
+                                             _dptr(eta_dev, f, M, "eta")))
         self.M = M
 
     def gbs_set_timing(self, on: bool = True):
@@ -225,6 +240,16 @@ class Context:
         self._check(load().gbs_prob_exact(self.handle, P, _ptr(off), _ptr(mod), prec, _ptr(p),
                                           _ptr(lp), _ptr(kap), _ptr(st)))
         return dict(p=p, logp=lp, kappa=kap, status=st)
+
+    def gbs_prob_exact_dev(self, offsets_dev, modes_dev, max_clicks: int, p_dev, logp_dev=None,
+                           kappa_dev=None, status_dev=None):
+        """Stream-ordered exact probabilities from device CSR (int32) into
+        device outputs (float64; status int32)."""
+        P = int(offsets_dev.shape[0]) - 1 if not isinstance(offsets_dev, int) else int(p_dev.shape[0])
+        return self._check(load().gbs_prob_exact_dev(
+            self.handle, P, _dptr(offsets_dev, "int32", P + 1, "offsets"), _dptr(modes_dev, "int32", None, "modes"),
+            int(max_clicks), _dptr(p_dev, "float64", P, "p"), _dptr(logp_dev, "float64", P, "logp"),
+            _dptr(kappa_dev, "float64", P, "kappa"), _dptr(status_dev, "int32", P, "status")))
 
     def gbs_prob_approx(self, offsets, modes, order: int, prec: int = GBS_PREC_FP64):
         off, mod = _i32(offsets), _i32(modes)
@@ -263,8 +288,9 @@ class Context:
         return Plan(self, h, len(off) - 1)
 
     def gbs_prob_approx_dev(self, plan: Plan, logp_dev, status_dev=None):
-        return self._check(load().gbs_prob_approx_dev(self.handle, plan.handle, _dptr(logp_dev),
-                                                      _dptr(status_dev)))
+        return self._check(load().gbs_prob_approx_dev(self.handle, plan.handle,
+                                                      _dptr(logp_dev, "float64", plan.P, "logp"),
+                                                      _dptr(status_dev, "int32", plan.P, "status")))
 
     def gbs_grad(self, offsets, modes, order: int, dL_dlogp, prec: int = GBS_PREC_FP64):
         off, mod = _i32(offsets), _i32(modes)
@@ -277,6 +303,8 @@ class Context:
         return dict(logp=lp, grad_r=gr, grad_eta=ge, status=st)
 
     def gbs_grad_dev(self, plan: Plan, dl_dev, logp_dev, grad_r_dev, grad_eta_dev, status_dev=None):
-        return self._check(load().gbs_grad_dev(self.handle, plan.handle, _dptr(dl_dev),
-                                               _dptr(logp_dev), _dptr(grad_r_dev),
-                                               _dptr(grad_eta_dev), _dptr(status_dev)))
+        P, M, f = plan.P, self.M, "float64"
+        return self._check(load().gbs_grad_dev(self.handle, plan.handle, _dptr(dl_dev, f, P, "dL_dlogp"),
+                                               _dptr(logp_dev, f, P, "logp"), _dptr(grad_r_dev, f, M, "grad_r"),
+                                               _dptr(grad_eta_dev, f, M, "grad_eta"),
+                                               _dptr(status_dev, "int32", P, "status")))

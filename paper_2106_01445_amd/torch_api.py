@@ -44,11 +44,18 @@ class ClickModel:
         for t in tensors:
             t.record_stream(self.stream)
 
+    def _param(self, x: torch.Tensor, name: str) -> torch.Tensor:
+        """r or eta as a contiguous float64 tensor of length M on the model's device."""
+        x = x.detach().to(self.device, torch.float64).contiguous()
+        if x.numel() != self.M:
+            raise ValueError(f"{name} must have M = {self.M} elements, got {x.numel()}")
+        return x
+
     def forward_raw(self, r: torch.Tensor, eta: torch.Tensor) -> torch.Tensor:
         logp = torch.empty(self.P, dtype=torch.float64, device=self.device)
         status = torch.empty(self.P, dtype=torch.int32, device=self.device)
-        r = r.detach().contiguous()
-        eta = eta.detach().contiguous()
+        r = self._param(r, "r")
+        eta = self._param(eta, "eta")
         self._enter()
         self.ctx.gbs_set_model_dev(self.ure, self.uim, r, eta)
         self.ctx.gbs_prob_approx_dev(self.plan, logp, status)
@@ -64,9 +71,9 @@ class ClickModel:
         ge = torch.empty(self.M, dtype=torch.float64, device=self.device)
         logp = torch.empty(self.P, dtype=torch.float64, device=self.device)
         status = torch.empty(self.P, dtype=torch.int32, device=self.device)
-        r = r.detach().contiguous()
-        eta = eta.detach().contiguous()
-        dl = dl.detach().to(torch.float64).contiguous()
+        r = self._param(r, "r")
+        eta = self._param(eta, "eta")
+        dl = dl.detach().to(self.device, torch.float64).contiguous()
         self._enter()
         self.ctx.gbs_set_model_dev(self.ure, self.uim, r, eta)
         self.ctx.gbs_grad_dev(self.plan, dl, logp, gr, ge, status)

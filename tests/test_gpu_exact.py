@@ -110,9 +110,9 @@ def test_covariance_route(gpu_ctx):
 
 def test_errors(gpu_ctx):
     import paper_2106_01445_amd as g
-    U, r, eta = small_model(30, 23)
+    U, r, eta = small_model(32, 23)
     gpu_ctx.gbs_set_model(U, r, eta)
-    off, mod = csr_from_lists([list(range(25))])
+    off, mod = csr_from_lists([list(range(31))])
     with pytest.raises(g.GBSError) as e:
         gpu_ctx.gbs_prob_exact(off, mod)
     assert e.value.code == -1
