@@ -166,6 +166,21 @@ int gbs_prob_exact(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *m
 int gbs_prob_exact_dev(gbs_ctx *ctx, int P, const int32_t *offsets_dev, const int32_t *modes_dev, int max_clicks,
                        double *p_dev, double *logp_dev, double *kappa_dev, int32_t *status_dev);
 /*
+ * gbs_prob_exact_dev for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): same arguments, results and errors, but no hipMalloc, hipFree
+ * or other allocating call.  The partial sums live in a fixed device array of
+ * 24 MiB per GPU (2^20 work items), set up when the first context is created
+ * on that GPU and held until the process ends; a batch needing more than
+ * P 2^min(max(max_clicks - 9, 0), 12) = 2^20 work items is GBS_E_INVAL.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other contexts, other host threads) race and give wrong results.
+ */
+int gbs_prob_exact_dev_noalloc(gbs_ctx *ctx, int P, const int32_t *offsets_dev, const int32_t *modes_dev,
+                               int max_clicks, double *p_dev, double *logp_dev, double *kappa_dev,
+                               int32_t *status_dev);
+
+/*
  * gbs_prob_approx: the paper's order-j estimate (1 <= order <= 4), returned as
  * log p_hat (p_hat reaches 1e-35 and below).  For each row:
  *   1. A = (Q^{-1})_CC, eigen-decomposed (A = V diag(alpha) V^T);

@@ -307,6 +307,13 @@ int gbs_create(gbs_ctx **out, int hip_device, void *hip_stream)
         optin > ctx->lds_per_block)
         ctx->lds_per_block = optin;
     if (ctx->num_cu <= 0) ctx->num_cu = 256;
+    // the device address of the fixed scratch of gbs_prob_exact_dev_noalloc
+    // (once per device; this device is current)
+    if (exact_scratch_init(hip_device) != 0) {
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+        delete ctx;
+        return GBS_E_HIP;
+    }
     *out = ctx;
     return GBS_OK;
 }
@@ -836,6 +843,28 @@ int gbs_prob_exact_dev(gbs_ctx *ctx, int P, const int32_t *offsets_dev, const in
     }
     return exact_launch(ctx, P, offsets_dev, modes_dev, max_clicks, ctx->ex_part, p_dev, logp_dev, kappa_dev,
                         status_dev);
+}
+
+int gbs_prob_exact_dev_noalloc(gbs_ctx *ctx, int P, const int32_t *offsets_dev, const int32_t *modes_dev,
+                               int max_clicks, double *p_dev, double *logp_dev, double *kappa_dev,
+                               int32_t *status_dev)
+{
+    if (!ctx) return GBS_E_INVAL;
+    if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
+    if (P < 0) return set_err(ctx, GBS_E_INVAL, "P must be >= 0");
+    if (max_clicks < 0 || max_clicks > GBS_MAX_N_EXACT)
+        return set_err(ctx, GBS_E_INVAL, "max_clicks must be in [0, " + std::to_string(GBS_MAX_N_EXACT) + "]");
+    if (P == 0) return GBS_OK;
+    if (!offsets_dev || !modes_dev || !p_dev || !status_dev) return set_err(ctx, GBS_E_INVAL, "NULL device array");
+    const long long need = (long long)P << exact_lgs(max_clicks);
+    if (need > exact_noalloc_items())
+        return set_err(ctx, GBS_E_INVAL, "P * 2^min(max(max_clicks - 9, 0), 12) = " + std::to_string(need) +
+                                             " work items exceed the fixed scratch of " +
+                                             std::to_string(exact_noalloc_items()));
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    double *part = exact_scratch(ctx->device);
+    if (!part) return set_err(ctx, GBS_E_STATE, "fixed scratch of this device not initialised");
+    return exact_launch(ctx, P, offsets_dev, modes_dev, max_clicks, part, p_dev, logp_dev, kappa_dev, status_dev);
 }
 
 int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, double *logp_dev,

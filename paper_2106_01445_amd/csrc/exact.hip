@@ -19,6 +19,7 @@
 // the two quadratures of a mode interleaved.  Signed sums are double-double,
 // reduced in a fixed order; kappa = sum|terms| / |sum| is returned.
 #include <algorithm>
+#include <mutex>
 
 #include "internal.h"
 
@@ -421,6 +422,46 @@ int exact_launch(gbs_ctx *ctx, int P, const int32_t *d_off, const int32_t *d_mod
     timer_end(ctx, ts);
     HIP_TRY(ctx, hipGetLastError());
     return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed scratch for gbs_prob_exact_dev_noalloc: the partial sums of up to
+// EX_NOALLOC_ITEMS work items (3 doubles each, 24 MiB), one copy per GPU that
+// the library runs on, held until the process ends.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in for the
+// symbol): its device address is taken once per device, with that device
+// current, and kept in scratch_ptr.
+// ---------------------------------------------------------------------------
+#define EX_NOALLOC_ITEMS (1 << 20)
+#define EX_MAX_DEVICES 64
+static __device__ __align__(256) double scratch[3 * EX_NOALLOC_ITEMS];
+
+namespace {
+std::mutex scratch_mu;
+double *scratch_ptr[EX_MAX_DEVICES] = {};
+}  // namespace
+
+// Once per device (the caller has made it current): the device address of
+// `scratch`.  Returns a HIP error code.
+int exact_scratch_init(int device)
+{
+    if (device < 0 || device >= EX_MAX_DEVICES) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (scratch_ptr[device]) return 0;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    scratch_ptr[device] = (double *)ptr;
+    return 0;
+}
+
+long long exact_noalloc_items() { return EX_NOALLOC_ITEMS; }
+
+double *exact_scratch(int device)
+{
+    if (device < 0 || device >= EX_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    return scratch_ptr[device];
 }
 
 // Host CSR (already checked): copies in, one launch, copies out.

@@ -164,6 +164,9 @@ int approx_forward(gbs_ctx *ctx, gbs_plan *plan, double *logp_dev, int32_t *stat
 int exact_run(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, double *p,
               double *logp, double *kappa, int32_t *status);
 int exact_lgs(int maxn);
+int exact_scratch_init(int device);
+double *exact_scratch(int device);
+long long exact_noalloc_items();
 int exact_launch(gbs_ctx *ctx, int P, const int32_t *d_off, const int32_t *d_modes, int maxn, double *d_part,
                  double *p_dev, double *logp_dev, double *kappa_dev, int32_t *status_dev);
 int approx_backward(gbs_ctx *ctx, gbs_plan *plan, const double *dl_dev, const int32_t *status_dev,

@@ -26,7 +26,7 @@ EXPORTS = ["gbs_create", "gbs_destroy", "gbs_last_error", "gbs_set_model", "gbs_
            "gbs_prob_approx_plain", "gbs_plan_get_params", "gbs_plan_set_params", "gbs_plan_tune",
            "gbs_plan_create", "gbs_plan_destroy", "gbs_plan_freeze", "gbs_prob_approx_dev",
            "gbs_grad", "gbs_grad_dev", "gbs_plan_info", "gbs_set_timing", "gbs_timing",
-           "gbs_stream", "gbs_click_distribution", "gbs_prob_exact_dev"]
+           "gbs_stream", "gbs_click_distribution", "gbs_prob_exact_dev", "gbs_prob_exact_dev_noalloc"]
 TIMING_GROUPS = ["model", "row_setup", "work_queue", "contour_clusters", "dft_fit", "exact",
                  "adjoint_fit_dft", "adjoint_contour_clusters", "adjoint_rows_scatter",
                  "adjoint_model"]
@@ -80,6 +80,7 @@ def load(path: str = LIB_PATH):
         "gbs_stream": ([vp], vp),
         "gbs_click_distribution": ([vp, ip, ip, i32p, dp, dp, i32p], ip),
         "gbs_prob_exact_dev": ([vp, ip, i32p, i32p, ip, dp, dp, dp, i32p], ip),
+        "gbs_prob_exact_dev_noalloc": ([vp, ip, i32p, i32p, ip, dp, dp, dp, i32p], ip),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -242,11 +243,13 @@ class Context:
         return dict(p=p, logp=lp, kappa=kap, status=st)
 
     def gbs_prob_exact_dev(self, offsets_dev, modes_dev, max_clicks: int, p_dev, logp_dev=None,
-                           kappa_dev=None, status_dev=None):
+                           kappa_dev=None, status_dev=None, noalloc: bool = False):
         """Stream-ordered exact probabilities from device CSR (int32) into
-        device outputs (float64; status int32)."""
+        device outputs (float64; status int32).  noalloc: the entry point that
+        allocates nothing (gbs_prob_exact_dev_noalloc)."""
         P = int(offsets_dev.shape[0]) - 1 if not isinstance(offsets_dev, int) else int(p_dev.shape[0])
-        return self._check(load().gbs_prob_exact_dev(
+        fn = load().gbs_prob_exact_dev_noalloc if noalloc else load().gbs_prob_exact_dev
+        return self._check(fn(
             self.handle, P, _dptr(offsets_dev, "int32", P + 1, "offsets"), _dptr(modes_dev, "int32", None, "modes"),
             int(max_clicks), _dptr(p_dev, "float64", P, "p"), _dptr(logp_dev, "float64", P, "logp"),
             _dptr(kappa_dev, "float64", P, "kappa"), _dptr(status_dev, "int32", P, "status")))
