@@ -526,10 +526,10 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
 // k_dft_fit: sector moments, fits, log-sum, and the estimated rounding error of
 // the result.
 //
-// Rounding estimate.  A contour value carries a rounding error of about u times
-// the largest value of its transform (at w = rho, where every term is
-// positive), so each tilted moment tau_t[kappa] carries d_t = u_t S_t(rho)
-// (u_0 = ROUND_FP64 for the fp64 G_0; u_t = u_clu for the cluster sums).  In a
+// Rounding estimate.  A contour value S_t(w_q) carries a relative rounding
+// error of about u_t (u_0 = ROUND_FP64 for the fp64 G_0; u_t = u_clu for the
+// cluster sums), so each tilted moment tau_t[kappa] carries at most
+// d_t = u_t mean_q |S_t(w_q)| (the transform's triangle inequality).  In a
 // fitted sector, m_t = tau_t binv_t / tau_0 and d log q / d m = -u with
 // u = H^{-1} m, so
 //   |d log(term)| <= d_0 / tau_0 (1 + sum_t |u_t m_t|) + sum_t |u_t| binv_t d_t / tau_0,
@@ -611,23 +611,19 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
         if (n + tid + nt * j < K) tmax = fmax(tmax, tau[j][0]);
     tmax = block_max(tmax, red);
     const double thr = 1e-14 * tmax;
-    // rounding of the tilted moments: u_t times the scale of the transform's
-    // values (their largest, at w = rho, or with ROUND_SCALE_MEAN their mean
-    // modulus over the circle)
+    // rounding of the tilted moments: tau_t[kappa] = (1/K) sum_q S_t(w_q)
+    // e^{-2 pi i q kappa / K}, so contour values with relative errors u_t
+    // leave at most u_t (1/K) sum_q |S_t(w_q)| in each moment
     double dt[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         double s0 = 0.0;
         if (t <= ORDER && t <= jp) {
             const cplx *src = sw + ((long)p * (ORDER + 1) + (t <= ORDER ? t : 0)) * GBS_QCAP;
-#ifdef ROUND_SCALE_MEAN
             double a = 0.0;
             for (int q = tid; q < Q; q += nt)
                 a += (q == 0 || q == K / 2 ? 1.0 : 2.0) * sqrt(src[q].re * src[q].re + src[q].im * src[q].im);
             s0 = block_sum(a, red) / K;
-#else
-            s0 = fabs(src[0].re);
-#endif
         }
         dt[t] = (t == 0 ? ROUND_FP64 : u_clu) * s0;
     }
@@ -705,7 +701,8 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
         const double err = fsum > 0.0 && esum > 0.0 ? exp(emx + log(esum) - tot) : 0.0;
         int flags = rp.flags;
         if (fsum > 0.0 && ehsum > 0.0 && ehx + log(ehsum) - tot > log(1e6)) flags |= GBS_PS_CONTOUR;
-        if (pass == 0 && esc_bound > 0.0 && !(err <= esc_bound)) flags |= GBS_PS_ESCALATED;
+        // (mixed precision: rows over the bound, and rows whose fits failed)
+        if (pass == 0 && esc_bound > 0.0 && (!(err <= esc_bound) || stt != 0)) flags |= GBS_PS_ESCALATED;
         logp[p] = out;
         if (status) status[p] = stt | flags;
         rows[p].nsec = (int)ns;

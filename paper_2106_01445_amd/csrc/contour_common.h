@@ -13,10 +13,10 @@
 // precision tier, whose eliminations run in fp32 (a few units of 2^-24).
 #define ROUND_FP64 2e-16
 #define ROUND_FP32 2e-7
-// Mixed precision: a row whose estimated error exceeds this is run again in
-// fp64 (GBS_PS_ESCALATED); the tier's target is 1e-5.
+// Mixed precision: a row whose estimated error exceeds the tier's target is
+// run again in fp64 (GBS_PS_ESCALATED).
 #ifndef MIXED_BOUND
-#define MIXED_BOUND 1e-6
+#define MIXED_BOUND 1e-5
 #endif
 #define FIT_MAXIT 100
 #define FIT_KPT (GBS_KMAX / FIT_THREADS)

@@ -193,10 +193,9 @@ def test_plan_params_and_tuner(gpu_ctx):
 def test_mixed_precision(gpu_ctx, cfg, order, P):
     """GBS_PREC_MIXED (fp32 cluster eliminations, fp64 everything else) against
     the fp64 path on the same batch: every row within the tier's target,
-    |d log p| <= 1e-5, where rows whose estimated rounding error exceeds 1e-6
-    have been run again in fp64 (GBS_PS_ESCALATED, and then equal to the fp64
-    value); no other status bit.  The estimate of every row that was not
-    escalated bounds its measured error."""
+    |d log p| <= 1e-5, where rows whose rounding bound exceeds 1e-5 have been
+    run again in fp64 (GBS_PS_ESCALATED, and then equal to the fp64 value); no
+    other status bit.  The bound of every row that was not escalated holds."""
     import torch
     import paper_2106_01445_amd as g
     wl = make_workload(cfg, P=P)
@@ -217,7 +216,7 @@ def test_mixed_precision(gpu_ctx, cfg, order, P):
     assert np.max(d) <= 1e-5, (np.max(d), np.median(d), esc.mean())
     assert np.max(d[esc], initial=0.0) < 1e-9
     assert np.all(d[~esc] <= np.maximum(err[~esc], 1e-9)), np.max(d[~esc] / err[~esc])
-    assert np.all(err[~esc] <= 1e-6)
+    assert np.all(err[~esc] <= 1e-5)
 
 
 def test_mixed_precision_rejected_where_unsupported(gpu_ctx):
