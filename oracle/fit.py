@@ -41,9 +41,16 @@ def _lse(z: np.ndarray) -> float:
 
 def maxent_last_point(m: np.ndarray, n: int, maxit: int = FIT_MAXIT) -> Tuple[float, bool, int]:
     """Fit and return (log q(n), converged, iterations) for targets m [jp]."""
+    lq, ok, it, _ = maxent_fit(m, n, maxit)
+    return lq, ok, it
+
+
+def maxent_fit(m: np.ndarray, n: int, maxit: int = FIT_MAXIT):
+    """The fit of maxent_last_point, also returning the fitted parameters c:
+    (log q(n), converged, iterations, c)."""
     jp = len(m)
     if jp == 0:          # n = 1: a single support point, q(1) = 1
-        return 0.0, True, 0
+        return 0.0, True, 0, np.zeros(0)
     phi = basis(n, jp)
     c = np.zeros(jp)
 
@@ -63,7 +70,7 @@ def maxent_last_point(m: np.ndarray, n: int, maxit: int = FIT_MAXIT) -> Tuple[fl
                 c = c + np.linalg.solve(H + 1e-14 * np.trace(H) * np.eye(jp), -g)
             except np.linalg.LinAlgError:
                 pass
-            return -_lse(-c @ phi), True, it
+            return -_lse(-c @ phi), True, it, c
         if it == maxit:
             break
         H = (phi * prob) @ phi.T - np.outer(E, E)
@@ -83,7 +90,7 @@ def maxent_last_point(m: np.ndarray, n: int, maxit: int = FIT_MAXIT) -> Tuple[fl
                     break
                 t *= 0.5
         c = c + t * step
-    return float("nan"), False, maxit
+    return float("nan"), False, maxit, c
 
 
 def maxent_curve(m: np.ndarray, n: int, s: int, maxit: int = FIT_MAXIT) -> Tuple[np.ndarray, bool]:

@@ -159,3 +159,28 @@ def test_grad_few_large_rows(gpu_ctx, order):
         fd = (w @ f(xp[:M], xp[M:]) - w @ f(xm[:M], xm[M:])) / (2 * h)
         assert abs(g @ v - fd) < 1e-4 * np.linalg.norm(g), (g @ v, fd)
     plan.close()
+
+
+def test_grad_m144_vs_reference_gradient(gpu_ctx):
+    """144 modes, order 2: the hand-written adjoint (gbs_grad: forward, then
+    the adjoint with the forward's contour plan) against the reference
+    gradient of the oracle (torch fp64 autograd through the power-series
+    oracle, tests/golden/grad_rows.json) for five rows of 40-110 clicks, two of
+    them with a capped contour radius: every component of d L / d r and
+    d L / d eta within 1e-7 of the largest."""
+    rec = json.load(open(os.path.join(HERE, "golden", "grad_rows.json")))
+    wl = make_workload(5).subset(rec["rows"])
+    gpu_ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    out = gpu_ctx.gbs_grad(wl.offsets, wl.modes, 2, np.array(rec["weights"]))
+    assert np.all(out["status"] == 0), out["status"]
+    g = np.concatenate([out["grad_r"], out["grad_eta"]])
+    ref = np.concatenate([rec["grad_r"], rec["grad_eta"]])
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(g - ref)) < 1e-7 * scale, (np.max(np.abs(g - ref)) / scale, int(np.argmax(np.abs(g - ref))))
+    assert abs(float(np.dot(rec["weights"], out["logp"])) - rec["loss"]) < 1e-8
+
+
+def test_capped_rows_in_golden_set():
+    """The forward golden set holds at least five 144-mode rows whose radius is
+    capped (they are checked with the whole batch above)."""
+    assert sum(1 for c in golden(5) if c.get("capped_radius")) >= 5

@@ -342,3 +342,89 @@ def test_click_distribution_norm_and_mean(order):
     assert p.sum() == pytest.approx(1.0, abs=1e-12)
     mean = sum(1.0 - model.vacuum_prob(Q, [l]) for l in range(8))
     assert float(np.arange(9) @ p) == pytest.approx(mean, abs=1e-10)
+
+
+# ------------------------------------------------- P8 at scale (binary128 series)
+def _sector_pin_cases():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sector_pins.json")
+    return json.load(open(path))["cases"]
+
+
+@pytest.mark.parametrize("case", _sector_pin_cases(), ids=lambda c: f"m{ {3: 70, 4: 100, 5: 144}[c['config']]}_row{c['row']}_n{c['n']}")
+def test_sector_series_at_scale_matches_binary128(case):
+    """Methods, Partition function and Moments calculation: the fp64 power
+    series of the sector weights (sectors.cluster_sector_weights) against the
+    same definition evaluated in binary128 (oracle/sectors128.c, written by
+    tests/golden/make_sector_pins.py) on the rows of the 70-, 100- and 144-mode
+    batches (the largest click counts, and capped-radius rows of the 144-mode
+    batch), for the empty cluster and one cluster of each size up to the
+    order, on every sector that carries at least 1e-8 of the estimate:
+    relative 1e-12."""
+    from oracle.exact import conditional_W
+    from workloads import csr_rows, make_workload
+    wl = make_workload(case["config"])
+    C = list(csr_rows(wl.offsets, wl.modes)[case["row"]])
+    Q = model.q_matrix(model.covariance(wl.U, wl.r, wl.eta))
+    W = conditional_W(Q, C)
+    W = 0.5 * (W + W.T)
+    for cl in case["clusters"]:
+        kap = np.array(cl["kappa"])
+        ref = np.array(cl["g_hi"]) + np.array(cl["g_lo"])
+        got = sectors.cluster_sector_weights(W, [tuple(cl["T"])], int(kap.max()) + 1)[0][kap]
+        rel = np.abs(got / ref - 1)
+        assert rel.max() < 1e-12, (cl["T"], rel.max(), int(kap[np.argmax(rel)]))
+
+
+# ------------------------------------------------- P14: reference gradient
+def _fd_loss(U, rows, order, w):
+    def f(x):
+        M = U.shape[0]
+        Q = model.q_matrix(model.covariance(U, x[:M], x[M:]))
+        return float(sum(wi * approx.prob_approx(Q, C, order) for wi, C in zip(w, rows)))
+    return f
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_reference_gradient_matches_central_differences(order):
+    """The torch autograd reference gradient (oracle/grad_ref.py) against
+    central differences of the numpy oracle (h = 1e-5) on a 6-mode lossy model:
+    relative 1e-7 of the largest component (FD truncation ~1e-10); its value
+    equals the oracle's sum of log p_hat."""
+    from oracle import grad_ref
+    M = 6
+    U, r, eta = small_model(M, 31, r_range=(0.6, 1.3), eta_range=(0.4, 0.9))
+    rows = [[0, 2], [1, 3, 5], [0, 1, 4, 5], [1, 2, 3, 4, 5], []]
+    w = np.array([0.7, 1.3, 0.9, 1.1, 0.5])
+    val, gr, ge = grad_ref.loss_and_grad(U, r, eta, rows, order, w)
+    f = _fd_loss(U, rows, order, w)
+    x0 = np.concatenate([r, eta])
+    assert val == pytest.approx(f(x0), abs=1e-12)
+    fd = grad.central_fd(f, x0, range(2 * M), h=1e-5)
+    g = np.concatenate([gr, ge])
+    assert np.max(np.abs(g - fd)) < 1e-7 * np.max(np.abs(fd)), (g, fd)
+
+
+def test_reference_gradient_product_state_closed_form():
+    """U = I: p(C) = prod_C (1 - P0_i) prod_Cbar P0_i with P0_i =
+    (1 + eta_i (2 - eta_i) sinh^2 r_i)^{-1/2} (Methods, Model, with loss); an
+    order >= n - 1 estimate is exact, so d log p / d(r_i, eta_i) have closed
+    forms."""
+    from oracle import grad_ref
+    M = 6
+    rng = np.random.default_rng([SEED_ROOT, 96, 1])
+    r = rng.uniform(0.5, 1.4, M)
+    eta = rng.uniform(0.3, 0.9, M)
+    C = [0, 2, 3]
+    val, gr, ge = grad_ref.loss_and_grad(np.eye(M, dtype=complex), r, eta, [C], 2, [1.0])
+    a = eta * (2 - eta)
+    s2 = np.sinh(r) ** 2
+    P0 = (1 + a * s2) ** -0.5
+    dP0_dr = -0.5 * (1 + a * s2) ** -1.5 * a * 2 * np.sinh(r) * np.cosh(r)
+    dP0_de = -0.5 * (1 + a * s2) ** -1.5 * (2 - 2 * eta) * s2
+    click = np.isin(np.arange(M), C)
+    dlog = np.where(click, -1.0 / (1 - P0), 1.0 / P0)
+    assert val == pytest.approx(np.sum(np.log(np.where(click, 1 - P0, P0))), abs=1e-12)
+    assert np.allclose(gr, dlog * dP0_dr, rtol=1e-9, atol=1e-12)
+    assert np.allclose(ge, dlog * dP0_de, rtol=1e-9, atol=1e-12)
