@@ -281,7 +281,28 @@ def order4_leg(ctx, torch):
     err = max(abs(lp[i] - approx.prob_approx(Q, list(rows[i]), 4)) for i in idx)
     plan.close()
     km = {k: round(v[0], 3) for k, v in tim.items() if v[1]}
+    # the same scheme with its adjoint on 512 rows of the batch (forward + gradient)
+    sub = wl.subset(range(512))
+    ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    ctx.gbs_grad(sub.offsets, sub.modes, 4, np.ones(sub.P))
+    t0 = time.perf_counter()
+    gout = ctx.gbs_grad(sub.offsets, sub.modes, 4, np.ones(sub.P))
+    ms_grad = (time.perf_counter() - t0) * 1e3
+    # the paper's headline case: 50 clicks of a lossless 70-mode device (every
+    # second input squeezed at r = 1.6), rows above 40 clicks
+    from workloads import accuracy_workload
+    hw = accuracy_workload(70, 1.6, 50, P=256)
+    ctx.gbs_set_model(hw.U, hw.r, hw.eta)
+    ctx.gbs_prob_approx(hw.offsets, hw.modes, 4)
+    t0 = time.perf_counter()
+    hout = ctx.gbs_prob_approx(hw.offsets, hw.modes, 4)
+    ms_head = (time.perf_counter() - t0) * 1e3
     return {"workload": "m70_order4", "modes": wl.M, "patterns": wl.P, "order": 4,
+            "forward_adjoint_512_rows": {"ms_host_call": ms_grad, "status_nonzero": int(np.sum(gout["status"] != 0))},
+            "headline_lossless_50_clicks": {"patterns": hw.P, "ms_host_call": ms_head,
+                                            "probs_per_s": hw.P / (ms_head * 1e-3),
+                                            "status_nonzero": int(np.sum(hout["status"] != 0)),
+                                            "median_log10_p_hat": float(np.median(hout["logp"]) / np.log(10))},
             "clicks": f"{int(ns.min())}-{int(ns.max())}", "pass": "model build + forward",
             "ms": ms, "probs_per_s": wl.P / (ms * 1e-3), "subset_dets_per_s": dets / (ms * 1e-3),
             "status_nonzero": int((st != 0).sum().item()), "kernel_ms": km,

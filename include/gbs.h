@@ -73,8 +73,9 @@ enum {
  * eliminations leave |d log p| of median 3e-6 / 3e-5 / 1e-4 at 20 / 70 / 100
  * modes, and the bound, which holds on every measured row, escalates nearly
  * every row of these workloads: on this GPU the fp32 vector rate equals the
- * fp64 rate, so the tier saves registers and on-chip memory, not arithmetic.)  The exact path, the plain kernel and the gradient
- * take GBS_PREC_FP64 only (GBS_E_INVAL otherwise).
+ * fp64 rate, so the tier saves registers and on-chip memory, not arithmetic.)
+ * The exact path, the plain kernel and the gradient take GBS_PREC_FP64 only
+ * (GBS_E_INVAL otherwise).
  */
 enum { GBS_PREC_FP64 = 0, GBS_PREC_MIXED = 1 };
 
@@ -85,17 +86,20 @@ enum { GBS_PREC_FP64 = 0, GBS_PREC_MIXED = 1 };
  *
  * GBS_PS_CONTOUR (Methods, Partition function: the sectors come from a sum
  * over a discrete set of points of the generating function) is set when
- *   (a) the transform's rounding, about 1e-16 of the contour's tilted weight
- *       and so 1e-16 / tau_kappa relative in a sector of tilted weight
- *       tau_kappa, summed with the sectors' shares of the estimate, exceeds
- *       1e-9 of the estimate (the fp64 tolerance of the estimate).  This
- *       happens when the sectors that carry the estimate lie far in the tail
- *       of the tilted distribution: when the saddle-point radius lies beyond
- *       the cap 0.98 R_b (on the 144-mode workload the 301 of 4096 rows whose
- *       radius is capped keep at least 0.24 of the tilted weight above n
- *       photons and are not flagged), or when the all-click value of the
- *       fitted curves rises so steeply with the photon number that sectors
- *       far above n dominate; or
+ *   (a) the contour cannot resolve the sectors that carry the estimate: their
+ *       tilted weights tau_kappa (the contour's total is 1), averaged with
+ *       their shares of the estimate as sum_kappa w_kappa / tau_kappa, fall
+ *       below 1e-6, so that the transform's rounding floor (about 1e-16 of
+ *       the total) reaches 1e-10 of the estimate.  Such a row is first run
+ *       again, on the device within the same call, on a contour whose tilted
+ *       mean photon number is the mean of those sectors (not on a frozen
+ *       plan, whose radii stay fixed); the bit is set when the re-tilted
+ *       radius still leaves them unresolved, which happens when it hits the
+ *       cap 0.98 R_b (the lossless 70-mode device with 50 clicks: every row
+ *       resolved at orders 1 and 2, 3 of 16 flagged at orders 3 and 4; on the
+ *       144-mode workload the 301 of 4096 rows whose radius is capped keep at
+ *       least 0.24 of the tilted weight above n photons and are not
+ *       flagged); or
  *   (b) a frozen plan's radius no longer suits the current model:
  *       rho max|alpha - 1| reached 1 or the aliasing factor
  *       (rho max|alpha - 1|)^K exceeds 1e-14.  The row is then planned afresh
@@ -200,11 +204,12 @@ int gbs_prob_exact_dev_noalloc(gbs_ctx *ctx, int P, const int32_t *offsets_dev, 
  *   5. per sector kappa >= n, the exp-polynomial of degree min(j, n-1) matching
  *      the moments (Methods, Approximation method) and its all-click value;
  *   6. log p_hat = log P_vac(Cbar) + log sum_kappa S_0[kappa] q_kappa(n).
- * Rows may hold at most 128 clicks at orders 1 and 2, at most 64 at order 3
- * and at most 40 at order 4 (more is GBS_E_INVAL); order 4 runs in fp64 only
- * (GBS_PREC_MIXED is GBS_E_INVAL there).  Rows above 40 clicks keep their
- * eigenvectors and M(w) in device memory instead of on-chip memory (slower per
- * contour point, same results).  Outputs: logp[P], status[P].
+ * Rows may hold at most 128 clicks at orders 1 and 2 and at most 64 at orders
+ * 3 and 4 (more is GBS_E_INVAL); order 4 runs in fp64 only (GBS_PREC_MIXED is
+ * GBS_E_INVAL there).  Rows above 40 clicks read their eigenvectors from
+ * device memory (L2) instead of on-chip memory, and beyond 64 clicks (orders 1
+ * and 2) keep only the diagonal blocks of M(w) on chip (slower per contour
+ * point, same results).  Outputs: logp[P], status[P].
  */
 int gbs_prob_approx(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int order,
                     int prec, double *logp, int32_t *status);
@@ -261,8 +266,11 @@ int gbs_prob_approx_dev(gbs_ctx *ctx, gbs_plan *plan, double *logp_dev, int32_t 
  * with respect to r[M] and eta[M] of the model set by gbs_set_model, by a
  * hand-written adjoint of steps 1-6 (d log det X = tr(X^{-1} dX) at every
  * determinant, implicit differentiation of each sector fit), with the contour
- * radius and size held at their forward values.  Orders 1 to 3 (order 4 is
- * GBS_E_INVAL).  Host pointers; logp (nullable) receives the forward values.
+ * radius and size held at their forward values.  Orders 1 to 4, the row
+ * limits of gbs_prob_approx; at order 4 each quadruple's c_T M_TT^{-1} comes
+ * from the bordered inverse of its triple (y = M3^{-1} r_d by back-substitution
+ * through the elimination's factors).  fp64 only.  Host pointers; logp
+ * (nullable) receives the forward values.
  */
 int gbs_grad(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int order, int prec,
              const double *dL_dlogp, double *logp, double *grad_r, double *grad_eta,

@@ -26,16 +26,16 @@ namespace {
 // k_build_items: work items (row, chunk) in the plan's cost order.  The rows
 // perm[0..nbig) (the large ones) come first: their items form the queue
 // counter[4] (length) / counter[5] (head); the rest form counter[0] (end) /
-// counter[1] (head, starting at counter[4]).  With only_escalated, only the
-// rows marked GBS_PS_ESCALATED by the previous fit get items (the fp64 rerun
-// of the mixed precision tier).
+// counter[1] (head, starting at counter[4]).  With only_flags, only the rows
+// carrying one of those flags from the previous fit get items (the fp64 rerun
+// of the mixed precision tier, and the re-tilted rows).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_build_items(int P, int nbig, int qchunk,
                                                       const int *__restrict__ offsets,
                                                       const int *__restrict__ perm,
                                                       const RowPlan *__restrict__ rows,
                                                       int *__restrict__ items,
-                                                      int *__restrict__ counter, int only_escalated = 0)
+                                                      int *__restrict__ counter, int only_flags = 0)
 {
     __shared__ int part[1024];
     __shared__ int s_big;
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(1024) void k_build_items(int P, int nbig, int qchun
         int n = offsets[p + 1] - offsets[p];
         const RowPlan &rp = rows[p];
         if (n == 0 || rp.status != 0 || rp.K <= 0) return 0;
-        if (only_escalated && !(rp.flags & GBS_PS_ESCALATED)) return 0;
+        if (only_flags && !(rp.flags & only_flags)) return 0;
         return (rp.K / 2 + 1 + qchunk - 1) / qchunk;
     };
     if (tid == 0) s_big = 0;
@@ -537,7 +537,13 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
 // the estimate.
 //   pass 0: every row; a row whose estimate exceeds esc_bound (> 0 only in
 //           mixed precision) is marked GBS_PS_ESCALATED, to be run again in
-//           fp64 (pass 1, only the marked rows).
+//           fp64 (pass 1, only the marked rows).  A row whose estimate sits in
+//           sectors the contour does not resolve (their tilted weights, as a
+//           harmonic mean weighted by their shares of the estimate, below
+//           1e-6) is marked for a re-tilt when allow_retilt: k_retilt centres
+//           its contour on the estimate's mean photon number kbar and pass 1
+//           runs it again; where that is not possible it is flagged
+//           GBS_PS_CONTOUR.
 // ---------------------------------------------------------------------------
 template <int ORDER>
 __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__ offsets,
@@ -545,14 +551,14 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
                                                          const cplx *__restrict__ sw,
                                                          double *__restrict__ logp,
                                                          int *__restrict__ status, double u_clu,
-                                                         double esc_bound, int pass)
+                                                         double esc_bound, int pass, int allow_retilt)
 {
     extern __shared__ __attribute__((aligned(16))) double sh[];
     __shared__ double red[FIT_THREADS], red2[FIT_THREADS];
     const int p = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int n = offsets[p + 1] - offsets[p];
     RowPlan rp = rows[p];
-    if (pass == 1 && !(rp.flags & GBS_PS_ESCALATED)) return;
+    if (pass == 1 && !(rp.flags & (GBS_PS_ESCALATED | GBS_ROW_RETILT))) return;
     if (n == 0) {
         if (tid == 0) {
             logp[p] = rp.log_pvac;
@@ -564,7 +570,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
     if (rp.status != 0) {
         if (tid == 0) {
             logp[p] = NAN;
-            if (status) status[p] = rp.status | rp.flags;
+            if (status) status[p] = rp.status | (rp.flags & GBS_PS_PUBLIC);
         }
         return;
     }
@@ -630,7 +636,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
     double fm = -INFINITY, fs = 0.0, um = -INFINITY, us = 0.0;
     int nsec = 0;
     // log-sums of term_kappa * rounding estimate of log(term_kappa)
-    double em = -INFINITY, es = 0.0, eh = -INFINITY, esh = 0.0;
+    double em = -INFINITY, es = 0.0, eh = -INFINITY, esh = 0.0, ek = -INFINITY, esk = 0.0;
     double lower = -INFINITY;  // log of a lower bound of the total (after pass 0)
     // Pass 0 fits each thread's first sector; its block log-sum is a lower
     // bound L of the estimate.  Later sectors whose upper bound S_0[kappa]
@@ -670,6 +676,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
             const double e = (dt[0] * um0 + e1) / t0;
             lse_add(em, es, lw + f.lq + log(e));
             lse_add(eh, esh, lw + f.lq - log(t0));
+            lse_add(ek, esk, lw + f.lq + log((double)kap));
         }
     }
     // block log-sum-exp of the fitted and the unresolved sectors
@@ -682,6 +689,8 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
     const double esum = block_sum(em == -INFINITY ? 0.0 : es * exp(em - emx), red2);
     const double ehx = block_max(eh, red2);
     const double ehsum = block_sum(eh == -INFINITY ? 0.0 : esh * exp(eh - ehx), red2);
+    const double ekx = block_max(ek, red2);
+    const double eksum = block_sum(ek == -INFINITY ? 0.0 : esk * exp(ek - ekx), red2);
     if (tid == 0) {
         double tot = fmx + log(fsum);
         double unres = umx + log(usum);
@@ -699,12 +708,25 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
         // transform's rounding floor (~1e-16 of the contour's tilted weight)
         // then reaches 1e-10 of the estimate
         const double err = fsum > 0.0 && esum > 0.0 ? exp(emx + log(esum) - tot) : 0.0;
-        int flags = rp.flags;
-        if (fsum > 0.0 && ehsum > 0.0 && ehx + log(ehsum) - tot > log(1e6)) flags |= GBS_PS_CONTOUR;
+        int flags = rp.flags & ~GBS_ROW_RETILT;
+        if (fsum > 0.0 && ehsum > 0.0 && ehx + log(ehsum) - tot > log(1e6)) {
+            // the estimate's sectors lie far out in the tilted distribution: on
+            // the first pass, tilt the contour afresh towards their mean photon
+            // number and run the row again; otherwise report it
+            const double kbar = eksum > 0.0 ? exp(ekx + log(eksum) - tot) : 0.0;
+            const bool moves = kbar > 1.02 * rp.kbar ? rp.rho < 0.97 * rp.rconv : kbar < rp.kbar / 1.02;
+            if (pass == 0 && allow_retilt && moves) {
+                flags |= GBS_ROW_RETILT;
+                rows[p].kbar = kbar;
+                if (esc_bound > 0.0) flags |= GBS_PS_ESCALATED;  // (the rerun is fp64)
+            } else {
+                flags |= GBS_PS_CONTOUR;
+            }
+        }
         // (mixed precision: rows over the bound, and rows whose fits failed)
         if (pass == 0 && esc_bound > 0.0 && (!(err <= esc_bound) || stt != 0)) flags |= GBS_PS_ESCALATED;
         logp[p] = out;
-        if (status) status[p] = stt | flags;
+        if (status) status[p] = stt | (flags & GBS_PS_PUBLIC);
         rows[p].nsec = (int)ns;
         rows[p].flags = flags;
         rows[p].err = err;
@@ -840,6 +862,27 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dist_fit(const int *__restrict_
     if (tid == 0) *status = s_fail > 1e-10 * tot ? GBS_PS_FIT_NOCONV : 0;
 }
 
+// ---------------------------------------------------------------------------
+// k_retilt: the rows marked for a re-tilt get a contour whose tilted mean
+// photon number is kbar (radius, size and log G_0(rho) from their spectrum),
+// one thread per row.
+// ---------------------------------------------------------------------------
+__global__ void k_retilt(int P, const int *__restrict__ offsets, const double *__restrict__ alpha,
+                         RowPlan *__restrict__ rows)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    RowPlan rp = rows[p];
+    if (!(rp.flags & GBS_ROW_RETILT) || rp.status != 0) return;
+    const int o = offsets[p], n = offsets[p + 1] - o;
+    const int flags = rp.flags;
+    const double logdet_q = -2.0 * rp.log_pvac - rp.logdet_a;
+    const double dev = rp.rconv < 1e299 ? 1.0 / rp.rconv : 0.0;
+    row_plan(rp, n, alpha + 2 * o, 1, logdet_q, rp.logdet_a, 1.0, dev, false, 0, false, rp.kbar);
+    rp.flags = flags;
+    rows[p] = rp;
+}
+
 template <int ORDER, bool BIG, class C>
 int launch_contour(gbs_ctx *ctx, gbs_plan *pl, int nmax)
 {
@@ -886,6 +929,12 @@ int launch_contour(gbs_ctx *ctx, gbs_plan *pl, int nmax)
     return 0;
 }
 
+// Forward on a plan: row set-up, work items, the contour kernels (rows above
+// 40 clicks and the others), the fits; then, on the device, a second pass for
+// the rows the fit marked: escalated rows of the mixed tier (fp64 rerun) and
+// rows whose contour is re-tilted (new radius, rerun) -- not on a frozen plan,
+// whose radii stay as they are.  Order 4 runs in fp64 only (the plan
+// enforces it).
 template <int ORDER>
 int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
 {
@@ -903,28 +952,34 @@ int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_CONTOUR);
     const bool mixed = pl->prec == GBS_PREC_MIXED;
-    if (mixed) {
-        // cluster eliminations in fp32 (M(w) stored in fp32), sums in fp64
-        if (nbig > 0 && (rc = launch_contour<ORDER, true, cplxf>(ctx, pl, pl->max_n))) return rc;
-        if (nbig < P && (rc = launch_contour<ORDER, false, cplxf>(ctx, pl, nsmall_max))) return rc;
-    } else {
+    if constexpr (ORDER < 4) {
+        if (mixed) {
+            // cluster eliminations in fp32 (M(w) stored in fp32), sums in fp64
+            if (nbig > 0 && (rc = launch_contour<ORDER, true, cplxf>(ctx, pl, pl->max_n))) return rc;
+            if (nbig < P && (rc = launch_contour<ORDER, false, cplxf>(ctx, pl, nsmall_max))) return rc;
+        }
+    } else if (mixed) {
+        return set_err(ctx, GBS_E_INVAL, "order 4 runs in fp64");
+    }
+    if (!mixed) {
         if (nbig > 0 && (rc = launch_contour<ORDER, true, cplx>(ctx, pl, pl->max_n))) return rc;
         if (nbig < P && (rc = launch_contour<ORDER, false, cplx>(ctx, pl, nsmall_max))) return rc;
     }
     timer_end(ctx, ts);
     size_t lds_f = sizeof(cplx) * (GBS_KMAX + GBS_KMAX / 2);
     if ((rc = func_lds_limit(ctx, (const void *)k_dft_fit<ORDER>, (int)lds_f))) return rc;
+    const int retilt = !pl->frozen && !pl->whole;
     ts = timer_begin(ctx, TG_FIT);
     hipLaunchKernelGGL(k_dft_fit<ORDER>, dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
                        pl->d_rows, pl->d_sw, logp, status, mixed ? ROUND_FP32 : ROUND_FP64,
-                       mixed ? MIXED_BOUND : 0.0, 0);
+                       mixed ? MIXED_BOUND : 0.0, 0, retilt);
     timer_end(ctx, ts);
-    if (mixed) {
-        // rows whose estimated error exceeds the mixed bound: contour and fit
-        // again in fp64, on the device (no host decision)
+    if (mixed || retilt) {
         ts = timer_begin(ctx, TG_ITEMS);
+        hipLaunchKernelGGL(k_retilt, dim3((P + 255) / 256), dim3(256), 0, st, P, pl->d_offsets, pl->d_alpha,
+                           pl->d_rows);
         hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, st, P, nbig, pl->qchunk, pl->d_offsets,
-                           pl->d_perm, pl->d_rows, pl->d_items, pl->d_counter, 1);
+                           pl->d_perm, pl->d_rows, pl->d_items, pl->d_counter, GBS_PS_ESCALATED | GBS_ROW_RETILT);
         timer_end(ctx, ts);
         ts = timer_begin(ctx, TG_CONTOUR);
         if (nbig > 0 && (rc = launch_contour<ORDER, true, cplx>(ctx, pl, pl->max_n))) return rc;
@@ -932,37 +987,9 @@ int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
         timer_end(ctx, ts);
         ts = timer_begin(ctx, TG_FIT);
         hipLaunchKernelGGL(k_dft_fit<ORDER>, dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
-                           pl->d_rows, pl->d_sw, logp, status, ROUND_FP64, 0.0, 1);
+                           pl->d_rows, pl->d_sw, logp, status, ROUND_FP64, 0.0, 1, 0);
         timer_end(ctx, ts);
     }
-    HIP_TRY(ctx, hipGetLastError());
-    return 0;
-}
-
-// Order 4: rows of at most 40 clicks, fp64 (the plan enforces both).
-int launch_order4(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
-{
-    hipStream_t st = ctx->stream;
-    const int P = pl->P;
-    if (pl->nbig > 0 || pl->prec != GBS_PREC_FP64)
-        return set_err(ctx, GBS_E_INVAL, "order 4 takes rows of at most 40 clicks, in fp64");
-    int ts = timer_begin(ctx, TG_PREP);
-    int rc = eig_rows(ctx, pl);
-    if (rc) return rc;
-    timer_end(ctx, ts);
-    ts = timer_begin(ctx, TG_ITEMS);
-    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, st, P, 0, pl->qchunk, pl->d_offsets, pl->d_perm,
-                       pl->d_rows, pl->d_items, pl->d_counter);
-    timer_end(ctx, ts);
-    ts = timer_begin(ctx, TG_CONTOUR);
-    if ((rc = launch_contour<4, false, cplx>(ctx, pl, pl->max_n_small))) return rc;
-    timer_end(ctx, ts);
-    size_t lds_f = sizeof(cplx) * (GBS_KMAX + GBS_KMAX / 2);
-    if ((rc = func_lds_limit(ctx, (const void *)k_dft_fit<4>, (int)lds_f))) return rc;
-    ts = timer_begin(ctx, TG_FIT);
-    hipLaunchKernelGGL(k_dft_fit<4>, dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets, pl->d_rows, pl->d_sw,
-                       logp, status, ROUND_FP64, 0.0, 0);
-    timer_end(ctx, ts);
     HIP_TRY(ctx, hipGetLastError());
     return 0;
 }
@@ -1002,7 +1029,7 @@ int launch_plain(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
     if ((rc = func_lds_limit(ctx, (const void *)k_dft_fit<ORDER>, (int)lds_f))) return rc;
     ts = timer_begin(ctx, TG_FIT);
     hipLaunchKernelGGL(k_dft_fit<ORDER>, dim3(pl->P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
-                       pl->d_rows, pl->d_sw, logp, status, ROUND_FP64, 0.0, 0);
+                       pl->d_rows, pl->d_sw, logp, status, ROUND_FP64, 0.0, 0, 0);
     timer_end(ctx, ts);
     HIP_TRY(ctx, hipGetLastError());
     return 0;
@@ -1029,7 +1056,7 @@ int approx_forward(gbs_ctx *ctx, gbs_plan *pl, double *logp_dev, int32_t *status
     case 1: return launch_order<1>(ctx, pl, logp_dev, status_dev);
     case 2: return launch_order<2>(ctx, pl, logp_dev, status_dev);
     case 3: return launch_order<3>(ctx, pl, logp_dev, status_dev);
-    case 4: return launch_order4(ctx, pl, logp_dev, status_dev);
+    case 4: return launch_order<4>(ctx, pl, logp_dev, status_dev);
     default: return set_err(ctx, -1, "order must be 1, 2, 3 or 4");
     }
 }

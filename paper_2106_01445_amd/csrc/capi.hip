@@ -705,7 +705,6 @@ int gbs_plan_tune(gbs_ctx *ctx, gbs_plan *pl, int what, int32_t *params_out)
     if (pl->ctx != ctx) return set_err(ctx, GBS_E_STATE, "plan belongs to another context");
     if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
     if (ctx->model.M != pl->M) return set_err(ctx, GBS_E_STATE, "plan was made for a model of another size M");
-    if (pl->order > 3) what &= 1;  // (no gradient at order 4)
     if ((what & 2) && !ctx->model.from_params)
         return set_err(ctx, GBS_E_STATE, "tuning the gradient needs a model set by gbs_set_model");
     if (pl->P == 0 || !(what & 3)) return params_out ? gbs_plan_get_params(pl, params_out) : GBS_OK;
@@ -877,7 +876,6 @@ int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, double *logp_
     if (ctx->model.M != pl->M) return set_err(ctx, GBS_E_STATE, "plan was made for a model of another size M");
     if (!dl_dev || !grad_r_dev || !grad_eta_dev) return set_err(ctx, GBS_E_INVAL, "NULL device array");
     if (pl->prec != GBS_PREC_FP64) return set_err(ctx, GBS_E_INVAL, "the gradient runs in fp64 only");
-    if (pl->order > 3) return set_err(ctx, GBS_E_INVAL, "the gradient takes orders 1, 2 and 3");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     double *lp = logp_dev ? logp_dev : pl->d_logp;
     int32_t *stt = status_dev ? status_dev : pl->d_status;

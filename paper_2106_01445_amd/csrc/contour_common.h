@@ -135,9 +135,12 @@ __host__ __device__ __forceinline__ int cont_fixed() { return 16 * (CONT_THREADS
 // convergence disc with an aliasing factor (rho max|alpha - 1|)^K <= 1e-14 (the
 // rule above with a margin, so that small changes of the model keep the plan);
 // otherwise the row is planned afresh and flagged GBS_PS_CONTOUR.
+// With target > 0 the tilted mean is set to target instead (the re-tilt of a
+// row whose estimate lies in sectors far from the first target); the target
+// used is kept in kbar.
 __device__ __forceinline__ void row_plan(RowPlan &rp, int n, const double *alpha, int astride,
                                          double logdetQ, double logdetA, double amin, double dev,
-                                         bool nonpd, int frozen, bool whole = false)
+                                         bool nonpd, int frozen, bool whole = false, double target_in = 0.0)
 {
     const int N = 2 * n;
     rp.status = 0;
@@ -172,7 +175,7 @@ __device__ __forceinline__ void row_plan(RowPlan &rp, int n, const double *alpha
         // the untilted mean, and a radius below 1 would push them under the
         // transform's rounding floor); for the whole distribution, to the
         // untilted mean: rho = 1, every sector at its own weight
-        const double target = whole ? mfun(1.0) : fmax((double)n, mfun(1.0));
+        const double target = target_in > 0.0 ? target_in : whole ? mfun(1.0) : fmax((double)n, mfun(1.0));
         double rho;
         if (dev < 1e-300) rho = 1.0;
         else if (mfun(hi) <= target) rho = hi;
@@ -191,6 +194,7 @@ __device__ __forceinline__ void row_plan(RowPlan &rp, int n, const double *alpha
         int K = 1;
         while (K < kneed && K < GBS_KMAX) K *= 2;
         rp.rho = rho;
+        rp.kbar = target;
         rp.rconv = rb;
         rp.K = K;
         rp.log_rho = log(rho);

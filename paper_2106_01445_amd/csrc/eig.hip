@@ -5,10 +5,10 @@
 //      updates of the trailing block, Golub & Van Loan, Matrix Computations,
 //      section 8.3.1);
 //   2. the orthogonal factor accumulated explicitly, last reflector first;
-//   3. implicit QL iterations with Wilkinson shifts on the tridiagonal matrix
-//      (ibid., section 8.3.3, in its QL form): one thread chases the bulge of a
-//      sweep and records its plane rotations, then every thread applies them to
-//      its own row of the factor;
+//   3. implicit symmetric QR steps with Wilkinson shifts on the tridiagonal
+//      matrix (ibid., section 8.3): one thread chases the bulge of a step with
+//      plane rotations and records them, then every thread applies them to its
+//      own row of the factor;
 //   4. the contour plan of the row from its spectrum.
 // The factor is kept column-major, which is the layout the contour kernels
 // read (eigenvector k contiguous).
@@ -103,7 +103,6 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(
             dg[N - 1] = W[(long)(N - 1) * N + N - 1];
             ed[N - 1] = 0.0;
         }
-        s_fail = 0;
     }
     // 2. factor: Qf = H_0 H_1 ... H_{N-3}, applied to the identity last first
     for (int idx = tid; idx < N * N; idx += nt) {
@@ -132,73 +131,83 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(
         }
         __syncthreads();
     }
-    // 3. implicit QL on (dg, ed); ed[i] couples i and i+1
+    // 3. implicit symmetric QR steps with Wilkinson shifts on (dg, ed); ed[i]
+    //    couples i and i+1.  The active block [lo, hi] is the lowest unreduced
+    //    one.  One thread chases the bulge of a step down the block with plane
+    //    rotations G_k on (k, k+1), choosing G_0 from the shifted first column
+    //    and every later one to annihilate the bulge below the subdiagonal,
+    //    and records (c_k, s_k); every thread then applies the rotations in
+    //    order to its own row of the factor (Qf <- Qf G_k).
     const double eps = 2.220446049250313e-16;
-    for (int l = 0; l < N; ++l) {
-        for (int iter = 0;; ++iter) {
-            if (tid == 0) {
-                int m = l;
-                for (; m < N - 1; ++m)
-                    if (fabs(ed[m]) <= eps * (fabs(dg[m]) + fabs(dg[m + 1]))) break;
-                int lo = m;  // rotations recorded for i in [lo, m-1]
-                if (m != l && iter < 60) {
-                    // (|g| < 1e16 and every other quantity of the sweep is O(1),
-                    // since ed[l] is above eps |dg|: plain square roots suffice)
-                    double g = (dg[l + 1] - dg[l]) / (2.0 * ed[l]);
-                    double r = sqrt(fma(g, g, 1.0));
-                    g = dg[m] - dg[l] + ed[l] / (g + copysign(r, g));
-                    double s = 1.0, c = 1.0, pp = 0.0;
-                    bool early = false;
-                    for (int i = m - 1; i >= l; --i) {
-                        const double f = s * ed[i], b = c * ed[i];
-                        r = sqrt(fma(f, f, g * g));
-                        ed[i + 1] = r;
-                        if (r == 0.0) {
-                            dg[i + 1] -= pp;
-                            ed[m] = 0.0;
-                            early = true;
-                            break;
-                        }
-                        s = f / r;
-                        c = g / r;
-                        g = dg[i + 1] - pp;
-                        r = (dg[i] - g) * s + 2.0 * c * b;
-                        pp = s * r;
-                        dg[i + 1] = g + pp;
-                        g = c * r - b;
-                        rc[i] = c;
-                        rs[i] = s;
-                        lo = i;
-                    }
-                    if (!early) {
-                        dg[l] -= pp;
-                        ed[l] = g;
-                        ed[m] = 0.0;
-                    }
-                } else if (m != l) {
-                    s_fail = 1;
-                    m = l;
-                }
-                s_m = m;
-                s_lo = lo;
-            }
-            __syncthreads();
-            const int m = s_m, lo = s_lo;
-            if (m == l) break;
-            // rows of the factor: Qf[r][i], Qf[r][i+1] rotated for i = m-1 down to lo
-            for (int r = tid; r < N; r += nt) {
-                double up = Qf[(long)m * N + r];
-                for (int i = m - 1; i >= lo; --i) {
-                    const double lo_v = Qf[(long)i * N + r];
-                    const double c = rc[i], s = rs[i];
-                    Qf[(long)(i + 1) * N + r] = s * lo_v + c * up;
-                    up = c * lo_v - s * up;
-                }
-                Qf[(long)lo * N + r] = up;
-            }
-            __syncthreads();
-        }
+    if (tid == 0) {
+        s_fail = 0;
+        s_m = N - 1;
     }
+    __syncthreads();
+    for (int guard = 0; guard < 60 * N + 60; ++guard) {
+        if (tid == 0) {
+            int hi = s_m, lo = -1;
+            // deflate converged entries at the bottom
+            while (hi > 0 && fabs(ed[hi - 1]) <= eps * (fabs(dg[hi - 1]) + fabs(dg[hi]))) {
+                ed[hi - 1] = 0.0;
+                --hi;
+            }
+            if (hi > 0) {
+                lo = hi - 1;
+                while (lo > 0 && !(fabs(ed[lo - 1]) <= eps * (fabs(dg[lo - 1]) + fabs(dg[lo])))) --lo;
+                if (lo > 0) ed[lo - 1] = 0.0;
+                // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block
+                // closer to its last diagonal entry
+                const double e = ed[hi - 1];
+                const double dd = 0.5 * (dg[hi - 1] - dg[hi]);
+                const double den = dd + copysign(sqrt(fma(dd, dd, e * e)), dd);
+                const double mu = den != 0.0 ? dg[hi] - e * e / den : dg[hi];
+                double x = dg[lo] - mu, z = ed[lo], bulge = 0.0;
+                for (int k = lo; k < hi; ++k) {
+                    const double r = sqrt(fma(x, x, z * z));
+                    double c = 1.0, sn = 0.0;
+                    if (r != 0.0) {
+                        c = x / r;
+                        sn = z / r;
+                    }
+                    if (k > lo) ed[k - 1] = r;  // the bulge is gone
+                    const double a = dg[k], b = ed[k], d = dg[k + 1];
+                    const double cs = c * sn, c2 = c * c, s2 = sn * sn;
+                    dg[k] = c2 * a + 2.0 * cs * b + s2 * d;
+                    dg[k + 1] = s2 * a - 2.0 * cs * b + c2 * d;
+                    ed[k] = cs * (d - a) + (c2 - s2) * b;
+                    if (k + 1 < hi) {
+                        const double en = ed[k + 1];
+                        bulge = sn * en;
+                        ed[k + 1] = c * en;
+                    }
+                    rc[k] = c;
+                    rs[k] = sn;
+                    x = ed[k];
+                    z = bulge;
+                }
+            }
+            s_m = hi;
+            s_lo = lo;
+            if (hi > 0 && guard == 60 * N + 59) s_fail = 1;
+        }
+        __syncthreads();
+        const int hi = s_m, lo = s_lo;
+        if (hi == 0) break;
+        // the factor's rows: columns k and k+1 rotated for k = lo .. hi-1
+        for (int r = tid; r < N; r += nt) {
+            double qk = Qf[(long)lo * N + r];
+            for (int k = lo; k < hi; ++k) {
+                const double qn = Qf[(long)(k + 1) * N + r];
+                const double c = rc[k], sn = rs[k];
+                Qf[(long)k * N + r] = c * qk + sn * qn;
+                qk = c * qn - sn * qk;
+            }
+            Qf[(long)hi * N + r] = qk;
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && s_m > 0) s_fail = 1;
     // 4. spectrum and plan
     double lsum = 0.0, amin = 1e300, dev = 0.0;
     for (int i = tid; i < N; i += nt) {

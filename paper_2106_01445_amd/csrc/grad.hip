@@ -71,10 +71,12 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
         W[m] = cmk(cs, sn);
     }
     // (loops over t and j unrolled: every index into the per-thread arrays is static)
-    double tau[FIT_KPT][4];
+    constexpr int NT = ORDER >= 4 ? 5 : 4;  // moments held per sector
+    constexpr int JM = ORDER >= 4 ? 4 : 3;  // most moments a fit uses
+    double tau[FIT_KPT][NT];
     const double invK = 1.0 / K;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NT; ++t) {
         if (t <= ORDER && t <= jp) {
             const cplx *src = sw + ((long)p * (ORDER + 1) + t) * GBS_QCAP;
             for (int q = tid; q < K; q += nt) {
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
     const double thr = 1e-14 * tmax;
     // forward pass again: which sectors are fitted, their log p_hat and fits
     double ell[FIT_KPT];
-    SectorFit fits[FIT_KPT];
+    SectorFitT<JM> fits[FIT_KPT];
     double fm = -INFINITY, fs = 0.0, lower = -INFINITY;
 #pragma unroll
     for (int j = 0; j < FIT_KPT; ++j) {
@@ -119,7 +121,8 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
         if (!(t0 >= thr) || !(t0 > 0.0)) continue;
         const double lw = log(t0) + rp.log_g_rho - kap * rp.log_rho;
         if (lw < lower + log(1e-17)) continue;
-        const SectorFit f = fit_sector<3>(n, 0, jp, t0, tau[j][1], tau[j][2], tau[j][3], 0.0);
+        const SectorFitT<JM> f = fit_sector<JM>(n, 0, jp, t0, tau[j][1], tau[j][2], tau[j][3],
+                                                 ORDER >= 4 ? tau[j][NT - 1] : 0.0);
         if (f.bad) continue;
         fits[j] = f;
         ell[j] = lw + f.lq;
@@ -130,36 +133,31 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
     const double total = fmx + log(fsum);
     // sector cotangents: pi_kappa w_p d ell / d tau_t
     const double binv[4] = {1.0 / (n - 1.0), 2.0 / ((n - 1.0) * (n - 2.0)),
-                            6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0)), 0.0};
-    double tbar[FIT_KPT][4];
+                            6.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0)),
+                            24.0 / ((n - 1.0) * (n - 2.0) * (n - 3.0) * (n - 4.0))};
+    double tbar[FIT_KPT][NT];
 #pragma unroll
     for (int j = 0; j < FIT_KPT; ++j) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) tbar[j][t] = 0.0;
+        for (int t = 0; t < NT; ++t) tbar[j][t] = 0.0;
         const int jr = fits[j].jr;
         if (jr < 0 || !(fsum > 0.0)) continue;
         const double pi = wp * exp(ell[j] - total);
         const double t0 = tau[j][0];
         const double *m = fits[j].m;
-        // H = Cov_c[phi] at the fitted c; u = H^{-1} m
-        double u[3] = {0, 0, 0};
-        if (jr > 0) {
-            double lse, E[3], E2[6];
-            bool ok = false;
-            switch (jr) {
-            case 1: fit_eval<1, true>(n, 0, binv, fits[j].c, &lse, E, E2); ok = fit_solve<1>(E, E2, m, u); break;
-            case 2: fit_eval<2, true>(n, 0, binv, fits[j].c, &lse, E, E2); ok = fit_solve<2>(E, E2, m, u); break;
-            default: fit_eval<3, true>(n, 0, binv, fits[j].c, &lse, E, E2); ok = fit_solve<3>(E, E2, m, u); break;
-            }
-            if (!ok) u[0] = u[1] = u[2] = 0.0;
-        }
+        // H = Cov_c[phi] at the fitted c; u = H^{-1} m (zero if H is singular)
+        double u[4];
+        fit_sensitivity<JM>(n, fits[j], u);
+        if (!(fabs(u[0]) < 1e299))
+#pragma unroll
+            for (int t = 0; t < 4; ++t) u[t] = 0.0;
         double um = 0.0;
 #pragma unroll
-        for (int t = 0; t < 3; ++t)
+        for (int t = 0; t < JM; ++t)
             if (t < jr) um += u[t] * m[t];
         tbar[j][0] = pi * (1.0 + um) / t0;
 #pragma unroll
-        for (int t = 1; t <= 3; ++t)
+        for (int t = 1; t <= JM; ++t)
             if (t <= jr) tbar[j][t] = -pi * u[t - 1] * binv[t - 1] / t0;
     }
     // alpha_t(w_q) = c_q FFT(tbar_t)[q], c_q = 1/K at q = 0, K/2 and 2/K otherwise
@@ -249,6 +247,64 @@ __device__ __forceinline__ void adj_col_unit(int T, int u, int &jt, int &rt0, in
     slot = v & 15;
 }
 
+// 2x2 complex blocks of the fourth-order adjoint: general [[a, b], [c, d]] and
+// symmetric [[a, b], [b, d]].
+struct Blk {
+    cplx a, b, c, d;
+};
+struct Sym {
+    cplx a, b, d;
+};
+__device__ __forceinline__ Blk bmul(const Blk &x, const Blk &y)  // x y
+{
+    return Blk{cfma(x.a, y.a, cmul(x.b, y.c)), cfma(x.a, y.b, cmul(x.b, y.d)), cfma(x.c, y.a, cmul(x.d, y.c)),
+               cfma(x.c, y.b, cmul(x.d, y.d))};
+}
+__device__ __forceinline__ Blk smul(const Sym &s, const Blk &y)  // s y
+{
+    return Blk{cfma(s.a, y.a, cmul(s.b, y.c)), cfma(s.a, y.b, cmul(s.b, y.d)), cfma(s.b, y.a, cmul(s.d, y.c)),
+               cfma(s.b, y.b, cmul(s.d, y.d))};
+}
+__device__ __forceinline__ Blk bsmul(const Blk &x, const Sym &s)  // x s
+{
+    return Blk{cfma(x.a, s.a, cmul(x.b, s.b)), cfma(x.a, s.b, cmul(x.b, s.d)), cfma(x.c, s.a, cmul(x.d, s.b)),
+               cfma(x.c, s.b, cmul(x.d, s.d))};
+}
+__device__ __forceinline__ Blk tmul(const Blk &x, const Blk &y)  // x^T y
+{
+    return Blk{cfma(x.a, y.a, cmul(x.c, y.c)), cfma(x.a, y.b, cmul(x.c, y.d)), cfma(x.b, y.a, cmul(x.d, y.c)),
+               cfma(x.b, y.b, cmul(x.d, y.d))};
+}
+__device__ __forceinline__ Sym tmul_sym(const Blk &x, const Blk &y)  // x^T y, known symmetric
+{
+    return Sym{cfma(x.a, y.a, cmul(x.c, y.c)), cfma(x.a, y.b, cmul(x.c, y.d)), cfma(x.b, y.b, cmul(x.d, y.d))};
+}
+__device__ __forceinline__ Blk bmul_t(const Blk &x, const Blk &y)  // x y^T
+{
+    return Blk{cfma(x.a, y.a, cmul(x.b, y.b)), cfma(x.a, y.c, cmul(x.b, y.d)), cfma(x.c, y.a, cmul(x.d, y.b)),
+               cfma(x.c, y.c, cmul(x.d, y.d))};
+}
+__device__ __forceinline__ Sym bmul_t_sym(const Blk &x, const Blk &y)  // x y^T, known symmetric
+{
+    return Sym{cfma(x.a, y.a, cmul(x.b, y.b)), cfma(x.a, y.c, cmul(x.b, y.d)), cfma(x.c, y.c, cmul(x.d, y.d))};
+}
+__device__ __forceinline__ Blk bsub(const Blk &x, const Blk &y)
+{
+    return Blk{csub(x.a, y.a), csub(x.b, y.b), csub(x.c, y.c), csub(x.d, y.d)};
+}
+__device__ __forceinline__ Sym ssub(const Sym &x, const Sym &y) { return Sym{csub(x.a, y.a), csub(x.b, y.b), csub(x.d, y.d)}; }
+__device__ __forceinline__ Sym sadd(const Sym &x, const Sym &y) { return Sym{cadd(x.a, y.a), cadd(x.b, y.b), cadd(x.d, y.d)}; }
+__device__ __forceinline__ Blk bneg(const Blk &x) { return Blk{cneg(x.a), cneg(x.b), cneg(x.c), cneg(x.d)}; }
+__device__ __forceinline__ Blk bscale(const Blk &x, cplx k) { return Blk{cmul(x.a, k), cmul(x.b, k), cmul(x.c, k), cmul(x.d, k)}; }
+__device__ __forceinline__ Sym sscale(const Sym &x, cplx k) { return Sym{cmul(x.a, k), cmul(x.b, k), cmul(x.d, k)}; }
+// det(s)^{-1/2} on the principal branch (r) and s^{-1} = r^2 adj(s)
+__device__ __forceinline__ Sym sinv(const Sym &s, cplx &r)
+{
+    r = crsqrt_p(cfnma(s.b, s.b, cmul(s.a, s.d)));
+    const cplx r2 = cmul(r, r);
+    return Sym{cmul(s.d, r2), cneg(cmul(s.b, r2)), cmul(s.a, r2)};
+}
+
 __device__ __forceinline__ void catomic(cplx *dst, cplx v)
 {
     atomicAdd(&dst->re, v.re);
@@ -270,6 +326,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
     const double *__restrict__ alpha, const double *__restrict__ vt,
     const RowPlan *__restrict__ rows, const int *__restrict__ items, const int *__restrict__ q_end,
     int *__restrict__ q_head, const int *__restrict__ units, const int *__restrict__ unit_off,
+    const int *__restrict__ unit4_off,
     const cplx *__restrict__ asw, const long long *__restrict__ roff, double *__restrict__ rscr,
     cplx *__restrict__ ascr, long long ascr_stride, const int *__restrict__ xq)
 {
@@ -623,6 +680,96 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                     zadd(&Zd0[b], cfma(cp, ib00, A22));
                     zadd(&Zd1[b], cfma(cp, ib01, A23));
                     zadd(&Zd2[b], cfma(cp, ib11, A33));
+                }
+            }
+            if constexpr (ORDER >= 4) {
+                // quadruples T = {a, b, c, d}: units (a, b, c; d0 .. d0+len-1).  With
+                // the triple {a, b, c} eliminated as in the forward (ia = Maa^{-1},
+                // G = ia Mab, ib = Sb^{-1}, Zc = ia Mac, Wc = ib (Mbc - G^T Mac),
+                // ic = Sc^{-1}), each d has y = M3^{-1} r_d, r_d = [Mad; Mbd; Mcd],
+                // by back-substitution through those factors:
+                //   y3 = v = ic u,  y2 = W - Wc v,  y1 = Z - G y2 - Zc v,
+                // and M_TT^{-1} = [[M3^{-1} + y Sd^{-1} y^T, -y Sd^{-1}], [., Sd^{-1}]].
+                // c_T M_TT^{-1} goes into Z; the M3^{-1} part, the same for every d of
+                // the unit, once per unit with the sum of the unit's c_T.
+                const cplx g4 = s_g[ORDER >= 4 ? 4 : 0];
+                auto Mdiag = [&](int x) { return Sym{Md0[x], Md1[x], Md2[x]}; };
+                auto Mpair = [&](int x, int y) {
+                    const int q = pair_pos<true>(n, x, y);
+                    return Blk{Mo0[q], Mo1[q], Mo2[q], Mo3[q]};
+                };
+                auto zdiag = [&](int x, const Sym &v) {
+                    zadd(&Zd0[x], v.a);
+                    zadd(&Zd1[x], v.b);
+                    zadd(&Zd2[x], v.d);
+                };
+                auto zpair = [&](int x, int y, const Blk &v) {
+                    const int q = pair_pos<true>(n, x, y);
+                    zadd(&Zo0[q], v.a);
+                    zadd(&Zo1[q], v.b);
+                    zadd(&Zo2[q], v.c);
+                    zadd(&Zo3[q], v.d);
+                };
+                const int *un4 = units + unit4_off[2 * n];
+                const int nu4 = unit4_off[2 * n + 1];
+#pragma unroll 1
+                for (int ui = tid; ui < nu4; ui += CONT_THREADS) {
+                    const unsigned u4 = (unsigned)un4[ui];
+                    const int a = u4 & 63, b = (u4 >> 6) & 63, c = (u4 >> 12) & 63, d0 = (u4 >> 18) & 63,
+                              d1 = d0 + (int)(u4 >> 24);
+                    cplx ra, rb, rc;
+                    const Sym ia = sinv(Mdiag(a), ra);
+                    const Blk Mab = Mpair(a, b);
+                    const Blk G = smul(ia, Mab);
+                    const Sym ib = sinv(ssub(Mdiag(b), tmul_sym(Mab, G)), rb);
+                    const Blk Mac = Mpair(a, c);
+                    const Blk Zc = smul(ia, Mac);
+                    const Blk Yc = bsub(Mpair(b, c), tmul(G, Mac));
+                    const Blk Wc = smul(ib, Yc);
+                    const Sym ic = sinv(ssub(ssub(Mdiag(c), tmul_sym(Mac, Zc)), tmul_sym(Yc, Wc)), rc);
+                    const cplx rabc = cmul(cmul(ra, rb), rc);
+                    cplx csum = cmk(0.0, 0.0);
+#pragma unroll 1
+                    for (int d = d0; d < d1; ++d) {
+                        const Blk x = Mpair(a, d);
+                        const Blk Y = bsub(Mpair(b, d), tmul(G, x));
+                        const Blk W = smul(ib, Y);
+                        const Blk Z = smul(ia, x);
+                        const Sym q = ssub(ssub(Mdiag(d), tmul_sym(x, Z)), tmul_sym(Y, W));
+                        const Blk u = bsub(bsub(Mpair(c, d), tmul(Zc, x)), tmul(Wc, Y));
+                        const Blk v = smul(ic, u);
+                        cplx rd;
+                        const Sym isd0 = sinv(ssub(q, tmul_sym(u, v)), rd);
+                        const cplx ct = cmul(g4, cmul(rabc, rd));
+                        csum = cadd(csum, ct);
+                        const Sym isd = sscale(isd0, ct);
+                        const Blk y2 = bsub(W, bmul(Wc, v));
+                        const Blk y1 = bsub(bsub(Z, bmul(G, y2)), bmul(Zc, v));
+                        const Blk t1 = bsmul(y1, isd), t2 = bsmul(y2, isd), t3 = bsmul(v, isd);
+                        zdiag(d, isd);
+                        zpair(a, d, bneg(t1));
+                        zpair(b, d, bneg(t2));
+                        zpair(c, d, bneg(t3));
+                        zdiag(a, bmul_t_sym(t1, y1));
+                        zdiag(b, bmul_t_sym(t2, y2));
+                        zdiag(c, bmul_t_sym(t3, v));
+                        zpair(a, b, bmul_t(t1, y2));
+                        zpair(a, c, bmul_t(t1, v));
+                        zpair(b, c, bmul_t(t2, v));
+                    }
+                    bsum = cadd(bsum, csum);
+                    // csum M3^{-1}: cc = ic, ac = -Ua ic, bc = -Wc ic,
+                    // aa = ia + G ib G^T + Ua ic Ua^T, ab = -G ib + Ua ic Wc^T,
+                    // bb = ib + Wc ic Wc^T, with Ua = Zc - G Wc
+                    const Blk Ua = bsub(Zc, bmul(G, Wc));
+                    const Blk Uic = bsmul(Ua, ic), Wic = bsmul(Wc, ic), Gib = bsmul(G, ib);
+                    const cplx ncs = cneg(csum);
+                    zdiag(c, sscale(ic, csum));
+                    zpair(a, c, bscale(Uic, ncs));
+                    zpair(b, c, bscale(Wic, ncs));
+                    zdiag(a, sscale(sadd(sadd(ia, bmul_t_sym(Gib, G)), bmul_t_sym(Uic, Ua)), csum));
+                    zpair(a, b, bscale(bsub(bmul_t(Uic, Wc), Gib), csum));
+                    zdiag(b, sscale(sadd(ib, bmul_t_sym(Wic, Wc)), csum));
                 }
             }
             bsum = warp_csum(bsum);
@@ -1235,7 +1382,8 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
         hipLaunchKernelGGL((k_adj_contour<ORDER, true>), dim3(grid), dim3(CONT_THREADS), lds_b, st,
                            pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_aitems,
                            pl->d_counter + 8 + GBS_NXCD, pl->d_counter + 8,
-                           pl->d_cluster_items, pl->d_cluster_off + 2 * (pl->max_n + 1), pl->d_asw,
+                           pl->d_cluster_items, pl->d_cluster_off + 2 * (pl->max_n + 1),
+                           pl->order >= 4 ? pl->d_cluster_off + 4 * (pl->max_n + 1) : nullptr, pl->d_asw,
                            pl->d_roff, pl->d_rscr, pl->d_ascr, pl->ascr_stride, pl->d_axq);
     }
     const int ns = pl->max_n_small;
@@ -1254,7 +1402,8 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
         hipLaunchKernelGGL((k_adj_contour<ORDER, false>), dim3(occ * ctx->num_cu), dim3(CONT_THREADS),
                            lds_a, st, pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows,
                            pl->d_aitems, pl->d_counter + 2, pl->d_counter + 3,
-                           pl->d_cluster_items, pl->d_cluster_off + 2 * (pl->max_n + 1), pl->d_asw,
+                           pl->d_cluster_items, pl->d_cluster_off + 2 * (pl->max_n + 1),
+                           pl->order >= 4 ? pl->d_cluster_off + 4 * (pl->max_n + 1) : nullptr, pl->d_asw,
                            pl->d_roff, pl->d_rscr, (cplx *)nullptr, 0LL, (const int *)nullptr);
     }
     timer_end(ctx, ts);
@@ -1303,6 +1452,7 @@ int approx_backward(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, const int3
     case 1: return backward_order<1>(ctx, pl, dl_dev, status_dev, grad_r_dev, grad_eta_dev);
     case 2: return backward_order<2>(ctx, pl, dl_dev, status_dev, grad_r_dev, grad_eta_dev);
     case 3: return backward_order<3>(ctx, pl, dl_dev, status_dev, grad_r_dev, grad_eta_dev);
-    default: return set_err(ctx, GBS_E_INVAL, "order must be 1, 2 or 3");
+    case 4: return backward_order<4>(ctx, pl, dl_dev, status_dev, grad_r_dev, grad_eta_dev);
+    default: return set_err(ctx, GBS_E_INVAL, "order must be 1, 2, 3 or 4");
     }
 }

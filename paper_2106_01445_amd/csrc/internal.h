@@ -13,7 +13,7 @@
 #define GBS_MAX_M 512          // modes supported by the model build
 #define GBS_MAX_N_APPROX 128   // clicks per row on the approximate path (orders 1, 2)
 #define GBS_MAX_N_ORDER3 64    // clicks per row at order 3
-#define GBS_MAX_N_ORDER4 40    // clicks per row at order 4 (the LDS-resident path only)
+#define GBS_MAX_N_ORDER4 64    // clicks per row at order 4 (M(w) in LDS)
 #define GBS_NSMALL 40          // rows up to this many clicks keep V and M(w) in LDS (contour)
 #define GBS_RSLOTS 3           // R slots per adjoint work item of such a row (column units)
 #define GBS_MAX_N_EXACT 30     // clicks per row on the exact path
@@ -89,12 +89,18 @@ enum { TG_MODEL = 0, TG_PREP = 1, TG_ITEMS = 2, TG_CONTOUR = 3, TG_FIT = 4, TG_E
 struct RowPlan {
     double rho, rconv, log_g_rho, logdet_a, log_pvac, log_rho;
     double err;   // estimated rounding error of log p_hat (sector transform and fits)
+    double kbar;  // tilted mean photon number of the contour (the re-tilt sets it to the
+                  // mean photon number of the sectors that carry the estimate)
     int K, status, nsec, flags;
 };
 
 // status bits that mean "no result" (the output is NaN); the others are
 // informational
 #define GBS_PS_FAILED (GBS_PS_FIT_NOCONV | GBS_PS_PIVOT | GBS_PS_CANCEL)
+// internal flag (never reported): the row's contour is tilted afresh towards
+// the sectors that carry its estimate and the row is run again
+#define GBS_ROW_RETILT (1 << 8)
+#define GBS_PS_PUBLIC 0xff
 
 struct gbs_plan {
     gbs_ctx *ctx = nullptr;

@@ -130,7 +130,7 @@ def test_frozen_plan_reuse(gpu_ctx):
     ([[0, 1]], 5),            # order outside 1..4
     ([[0, 1]], 0),
     ([list(range(65))], 3),   # more clicks than order 3 supports
-    ([list(range(41))], 4),   # more clicks than order 4 supports
+    ([list(range(65))], 4),   # more clicks than order 4 supports
     ([list(range(129))], 2),  # more clicks than supported
 ])
 def test_argument_errors(gpu_ctx, rows, order):

@@ -28,7 +28,7 @@ def oracle_loss(U, rows, order, w):
     return f
 
 
-@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 def test_grad_vs_oracle_fd(gpu_ctx, order):
     M = 7
     U, r, eta = small_model(M, 31, r_range=(0.6, 1.3), eta_range=(0.4, 0.9))
@@ -127,3 +127,77 @@ def test_torch_autograd_wrapper():
     ref = m.ctx.gbs_grad(wl.offsets, wl.modes, 2, w.cpu().numpy())
     assert np.allclose(r.grad.cpu().numpy(), ref["grad_r"], rtol=1e-9, atol=1e-12)
     assert np.allclose(eta.grad.cpu().numpy(), ref["grad_eta"], rtol=1e-9, atol=1e-12)
+
+
+def test_grad_order4_product_state_closed_form(gpu_ctx):
+    """U = I with five clicks: the order-4 estimate is exact (order n - 1), so
+    the fourth-order adjoint (quadruple clusters) must give the closed-form
+    derivatives of log p = sum_C log(1 - P0_i) + sum_Cbar log P0_i."""
+    M = 7
+    rng = np.random.default_rng([SEED_ROOT, 96, 4])
+    r = rng.uniform(0.5, 1.4, M)
+    eta = rng.uniform(0.3, 0.9, M)
+    C = [0, 1, 3, 4, 6]
+    off, mod = csr_from_lists([C])
+    gpu_ctx.gbs_set_model(np.eye(M, dtype=complex), r, eta)
+    out = gpu_ctx.gbs_grad(off, mod, 4, np.array([1.0]))
+    assert np.all(out["status"] == 0)
+    a = eta * (2 - eta)
+    s2 = np.sinh(r) ** 2
+    P0 = (1 + a * s2) ** -0.5
+    dP0_dr = -0.5 * (1 + a * s2) ** -1.5 * a * 2 * np.sinh(r) * np.cosh(r)
+    dP0_de = -0.5 * (1 + a * s2) ** -1.5 * (2 - 2 * eta) * s2
+    click = np.isin(np.arange(M), C)
+    dlog = np.where(click, -1.0 / (1 - P0), 1.0 / P0)
+    assert np.allclose(out["grad_r"], dlog * dP0_dr, rtol=1e-7, atol=1e-9)
+    assert np.allclose(out["grad_eta"], dlog * dP0_de, rtol=1e-7, atol=1e-9)
+
+
+def test_grad_order4_rows_above_40_clicks(gpu_ctx):
+    """Order 4 on rows of 38-45 clicks of a 50-mode model (both contour
+    kernels of the adjoint): the adjoint against central differences of the
+    GPU forward on the frozen plan along random directions in (r, eta)."""
+    import torch
+    M = 50
+    U, r, eta = small_model(M, 21, n_squeezed=25, r_range=(1.0, 1.5), eta_range=(0.3, 0.6))
+    rng = np.random.default_rng(80)
+    rows = [sorted(rng.choice(M, size=k, replace=False).tolist()) for k in (38, 42, 45)]
+    off, mod = csr_from_lists(rows)
+    P = len(rows)
+    gpu_ctx.gbs_set_model(U, r, eta)
+    plan = gpu_ctx.gbs_plan_create(off, mod, 4)
+    dev = torch.device("cuda")
+    ure = torch.tensor(np.ascontiguousarray(U.real), device=dev)
+    uim = torch.tensor(np.ascontiguousarray(U.imag), device=dev)
+    logp = torch.empty(P, dtype=torch.float64, device=dev)
+    st = torch.empty(P, dtype=torch.int32, device=dev)
+
+    def f(rr, ee):
+        gpu_ctx.gbs_set_model_dev(ure, uim, torch.tensor(rr, device=dev), torch.tensor(ee, device=dev))
+        gpu_ctx.gbs_prob_approx_dev(plan, logp, st)
+        torch.cuda.synchronize()
+        assert int(st.abs().sum()) == 0
+        return logp.cpu().numpy().copy()
+
+    w = np.array([0.8, 1.2, 1.0])
+    f(r, eta)
+    plan.freeze(True)
+    dl = torch.tensor(w, device=dev)
+    gr = torch.empty(M, dtype=torch.float64, device=dev)
+    ge = torch.empty(M, dtype=torch.float64, device=dev)
+    gpu_ctx.gbs_set_model_dev(ure, uim, torch.tensor(r, device=dev), torch.tensor(eta, device=dev))
+    gpu_ctx.gbs_grad_dev(plan, dl, logp, gr, ge, st)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    g = np.concatenate([gr.cpu().numpy(), ge.cpu().numpy()])
+    assert np.all(np.isfinite(g))
+    mask = np.concatenate([r > 0, np.ones(M, bool)])
+    h = 1e-5
+    for _ in range(3):
+        v = rng.standard_normal(2 * M) * mask
+        v /= np.linalg.norm(v)
+        xp = np.concatenate([r, eta]) + h * v
+        xm = np.concatenate([r, eta]) - h * v
+        fd = (w @ f(xp[:M], xp[M:]) - w @ f(xm[:M], xm[M:])) / (2 * h)
+        assert abs(g @ v - fd) < 1e-4 * np.linalg.norm(g), (g @ v, fd)
+    plan.close()

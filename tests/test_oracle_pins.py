@@ -386,7 +386,7 @@ def _fd_loss(U, rows, order, w):
     return f
 
 
-@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 def test_reference_gradient_matches_central_differences(order):
     """The torch autograd reference gradient (oracle/grad_ref.py) against
     central differences of the numpy oracle (h = 1e-5) on a 6-mode lossy model:
