@@ -388,18 +388,19 @@ def source_sha(paths):
     return h.hexdigest()[:16]
 
 
-def load_traffic(srcs, kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (profiles/traffic_m70_order3.json), if it was taken on the current kernel
-    sources (hash match); else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_m70_order3.json")
+def load_counters(srcs, kernel: str):
+    """Counter figures per launch of `kernel` from the committed summary
+    (profiles/counters_m70_order3.json: HBM bytes from FETCH_SIZE/WRITE_SIZE,
+    executed fp64 VALU and MFMA flops from SQ_INSTS_VALU_FLOPS_FP64 and
+    SQ_INSTS_VALU_MFMA_MOPS_F64, each calibrated on a kernel of known count), if
+    they were taken on the current kernel sources (hash match); else None."""
+    path = os.path.join(ROOT, "profiles", "counters_m70_order3.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("source_sha") != source_sha(srcs):
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+    return rec.get("kernels", {}).get(kernel)
 
 
 def main():
@@ -418,6 +419,10 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 3 times (calibrates the "
                          "HBM byte counters against a kernel of known traffic)")
+    ap.add_argument("--flop-probe", action="store_true",
+                    help="only run kernels of known fp64 operation counts (an elementwise product "
+                         "of 2^27 doubles, 3 times; a 4096^3 fp64 matrix product, 3 times): "
+                         "calibrates the fp64 instruction counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: there is no multi-GPU path "
@@ -433,6 +438,21 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": a.numel() * 8, "copy_probe_bytes_written": b.numel() * 8,
                           "dispatches": 3}), flush=True)
+        return
+    if args.flop_probe:
+        a = torch.rand(1 << 27, dtype=torch.float64, device="cuda:0")
+        b = torch.rand_like(a)
+        c = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, b, out=c)
+        x = torch.rand(4096, 4096, dtype=torch.float64, device="cuda:0")
+        y = torch.rand_like(x)
+        for _ in range(3):
+            z = x @ y
+        torch.cuda.synchronize()
+        print(json.dumps({"elementwise_mul_f64_per_dispatch": a.numel(),
+                          "matmul_f64_flops_per_dispatch": 2 * 4096 ** 3, "dispatches": 3,
+                          "check": float(z[0, 0])}), flush=True)
         return
     import paper_2106_01445_amd as g
     from workloads import make_workload
@@ -528,14 +548,24 @@ def main():
     dom = max(rates.values(), key=lambda d: d["ms"])
     src = [os.path.join(ROOT, "paper_2106_01445_amd", "csrc", f)
            for f in ("approx.hip", "grad.hip", "contour_common.h", "cplx.h", "internal.h")]
+    cnt = load_counters(src, dom["kernel"].split()[0])
     roof = {"bound": "alu", "kernel": dom["kernel"],
             "achieved": round(dom["tflops"], 3), "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
             "frac": round(dom["tflops"] / PEAK_FP64_VALU_TFLOPS, 4),
-            "traffic": load_traffic(src, dom["kernel"].split()[0]),
+            "traffic": (cnt or {}).get("bytes_per_launch"),
             "kernel_ms": round(dom["ms"], 3), "flops_per_launch": dom["flops"],
             "all_kernels": {k: {"ms": round(v["ms"], 3), "tflops": round(v["tflops"], 3),
                                 "frac": round(v["tflops"] / PEAK_FP64_VALU_TFLOPS, 4)}
                             for k, v in rates.items()}}
+    if cnt and cnt.get("valu_fp64_flops") is not None:
+        # executed fp64 work of the same launch, from the committed counters
+        # (taken on these kernel sources), over this run's kernel time
+        ex = cnt["valu_fp64_flops"] + cnt["mfma_fp64_flops"]
+        roof["executed"] = {
+            "valu_fp64_tflops": round(cnt["valu_fp64_flops"] / (dom["ms"] * 1e-3) / 1e12, 3),
+            "mfma_fp64_tflops": round(cnt["mfma_fp64_flops"] / (dom["ms"] * 1e-3) / 1e12, 3),
+            "executed_over_algorithmic": round(ex / dom["flops"], 3),
+            "source": "profiles/counters_m70_order3.md"}
     out = {
         "metric": METRIC,
         "value": wl.P / (ms_step * 1e-3),

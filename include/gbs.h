@@ -74,8 +74,12 @@ enum {
  * modes, and the bound, which holds on every measured row, escalates nearly
  * every row of these workloads: on this GPU the fp32 vector rate equals the
  * fp64 rate, so the tier saves registers and on-chip memory, not arithmetic.)
- * The exact path, the plain kernel and the gradient take GBS_PREC_FP64 only
- * (GBS_E_INVAL otherwise).
+ * Where no fp32 kernel exists the tier is accepted and the work runs at the
+ * higher precision, every row flagged GBS_PS_ESCALATED: the exact path (fp32
+ * terms would meet 1e-6 only where kappa_IE <= 10, far below the measured
+ * 5e5 .. 1e11 of 20-mode rows; it runs in double-double), order 4 (fp64), and
+ * the gradient (forward and adjoint in fp64).  The plain comparison kernel
+ * takes GBS_PREC_FP64 only (GBS_E_INVAL otherwise).
  */
 enum { GBS_PREC_FP64 = 0, GBS_PREC_MIXED = 1 };
 
@@ -110,7 +114,7 @@ enum {
     GBS_PS_FIT_NOCONV = 1, /* a sector fit carrying >1e-10 of the estimate did not converge */
     GBS_PS_CONTOUR = 2,    /* the contour deviated from its accuracy rule (see above)        */
     GBS_PS_PIVOT = 4,      /* a determinant pivot left its valid half-plane                   */
-    GBS_PS_ESCALATED = 8,  /* ran at higher precision than asked (mixed -> fp64)              */
+    GBS_PS_ESCALATED = 8,  /* ran at higher precision than asked (mixed -> fp64 / dd)         */
     GBS_PS_CANCEL = 16,    /* exact sum not resolved: |sum| below its rounding bound          */
     GBS_PS_BADROW = 32     /* device-side CSR check failed (gbs_prob_exact_dev): no result    */
 };
@@ -155,7 +159,9 @@ int gbs_get_model(gbs_ctx *ctx, double *q_inv, double *logdet_q);
  * at most 30 clicks (2^30 terms; a row of 30 clicks takes of the order of a
  * second).  Outputs (host arrays of length P): p, logp (nullable),
  * kappa = sum|terms| / |sum| (nullable), status.  A row whose sum cancels by
- * more than 1e20 gets NaN and GBS_PS_CANCEL.
+ * more than 1e20 gets NaN and GBS_PS_CANCEL.  prec: GBS_PREC_FP64, or
+ * GBS_PREC_MIXED (the same double-double run, every row flagged
+ * GBS_PS_ESCALATED; see Precision above).
  */
 int gbs_prob_exact(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int prec,
                    double *p, double *logp, double *kappa, int32_t *status);
@@ -193,8 +199,9 @@ int gbs_prob_exact_dev_noalloc(gbs_ctx *ctx, int P, const int32_t *offsets_dev, 
  * log p_hat (p_hat reaches 1e-35 and below).  For each row:
  *   1. A = (Q^{-1})_CC, eigen-decomposed (A = V diag(alpha) V^T);
  *      log P_vac(Cbar) = -(log det Q + log det A) / 2 (eq. 3, second factor);
- *   2. contour radius rho: the tilted mean photon number equals n, capped at
- *      0.98 of the convergence radius 1/max|alpha-1|; K = 2^k points with
+ *   2. contour radius rho: the tilted mean photon number equals max(n, the
+ *      untilted mean), capped at 0.98 of the convergence radius
+ *      1/max|alpha-1|; K points, K the smallest r 2^k (r = 1, 3 or 5) with
  *      (rho/R)^K <= 1e-16 and K >= 2n+32, K <= 2048;
  *   3. at each contour point w: M(w) = ((1-w)I + wA)^{-1} and, for every cluster
  *      T of <= j clicked modes, G_T(w) = det(A)^{1/2} det((1-w)I+wA)^{-1/2}
@@ -205,8 +212,8 @@ int gbs_prob_exact_dev_noalloc(gbs_ctx *ctx, int P, const int32_t *offsets_dev, 
  *      the moments (Methods, Approximation method) and its all-click value;
  *   6. log p_hat = log P_vac(Cbar) + log sum_kappa S_0[kappa] q_kappa(n).
  * Rows may hold at most 128 clicks at orders 1 and 2 and at most 64 at orders
- * 3 and 4 (more is GBS_E_INVAL); order 4 runs in fp64 only (GBS_PREC_MIXED is
- * GBS_E_INVAL there).  Rows above 40 clicks read their eigenvectors from
+ * 3 and 4 (more is GBS_E_INVAL); order 4 runs in fp64 (GBS_PREC_MIXED there:
+ * fp64, every row flagged GBS_PS_ESCALATED).  Rows above 40 clicks read their eigenvectors from
  * device memory (L2) instead of on-chip memory, and beyond 64 clicks (orders 1
  * and 2) keep only the diagonal blocks of M(w) on chip (slower per contour
  * point, same results).  Outputs: logp[P], status[P].
@@ -269,8 +276,9 @@ int gbs_prob_approx_dev(gbs_ctx *ctx, gbs_plan *plan, double *logp_dev, int32_t 
  * radius and size held at their forward values.  Orders 1 to 4, the row
  * limits of gbs_prob_approx; at order 4 each quadruple's c_T M_TT^{-1} comes
  * from the bordered inverse of its triple (y = M3^{-1} r_d by back-substitution
- * through the elimination's factors).  fp64 only.  Host pointers; logp
- * (nullable) receives the forward values.
+ * through the elimination's factors).  fp64 (GBS_PREC_MIXED, or a mixed-tier
+ * plan: fp64 forward and adjoint, every row flagged GBS_PS_ESCALATED).  Host
+ * pointers; logp (nullable) receives the forward values.
  */
 int gbs_grad(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, int order, int prec,
              const double *dL_dlogp, double *logp, double *grad_r, double *grad_eta,
@@ -321,9 +329,10 @@ int gbs_plan_info(gbs_plan *plan, double *rho, double *rconv, int32_t *K, int32_
  * count[GBS_TIMING_GROUPS] (0 model build, 1 row set-up, 2 work-queue build,
  * 3 contour/cluster, 4 DFT and fit, 5 exact subsets, 6 adjoint of the fit and
  * DFT, 7 adjoint of the contour/cluster step, 8 adjoint per row and its
- * scatter into the mode pairs, 9 adjoint of the model build), then clears the
- * record.  Either array may be NULL. */
-#define GBS_TIMING_GROUPS 10
+ * scatter into the mode pairs, 9 adjoint of the model build, 10 the second
+ * pass of a forward call: re-tilted and escalated rows, their contour and
+ * fits), then clears the record.  Either array may be NULL. */
+#define GBS_TIMING_GROUPS 11
 int gbs_set_timing(gbs_ctx *ctx, int on);
 int gbs_timing(gbs_ctx *ctx, double *ms, int32_t *count);
 

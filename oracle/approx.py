@@ -29,7 +29,11 @@ from .sectors import cluster_moments, cluster_sector_weights
 
 
 def prob_approx(Q: np.ndarray, C: Sequence[int], order: int, L0: int = 0,
-                return_detail: bool = False):
+                return_detail: bool = False, moments=None, floor: float = 1e-10):
+    """moments(W, jp, L) -> S[jp+1, L] replaces the fp64 cluster moments (the
+    binary128 ones of sectors128.cluster_moments, for rows whose fp64 series
+    cancels); floor is then the matching noise level (sectors below
+    floor x the absolute series are dropped)."""
     M = Q.shape[0] // 2
     C = list(C)
     n = len(C)
@@ -41,7 +45,7 @@ def prob_approx(Q: np.ndarray, C: Sequence[int], order: int, L0: int = 0,
     jp = min(order, n - 1)
     L = max(L0, 4 * n + 64)
     while True:
-        S = cluster_moments(W, jp, L)
+        S = cluster_moments(W, jp, L) if moments is None else moments(W, jp, L)
         # rounding floor of each S_0 coefficient: 1e-16 x the |lambda| series;
         # sectors within 1e6 of it (pure states: every odd sector) are noise
         S0abs = cluster_sector_weights(W, [()], L, absolute=True)[0]
@@ -49,7 +53,7 @@ def prob_approx(Q: np.ndarray, C: Sequence[int], order: int, L0: int = 0,
         nfail = 0
         failed = []
         for kap in range(n, L):
-            if not S[0, kap] > 1e-10 * S0abs[kap]:
+            if not S[0, kap] > floor * S0abs[kap]:
                 continue
             m = moment_targets(S[:, kap], n, jp)
             lq, ok, _ = maxent_last_point(m, n)
@@ -73,7 +77,7 @@ def prob_approx(Q: np.ndarray, C: Sequence[int], order: int, L0: int = 0,
     out = log_pv + part
     if return_detail:
         fail_weight = float(sum(S[0, k] for k in failed)) / float(np.exp(part))
-        return out, dict(S=S, terms=terms, nfail=nfail, fail_weight=fail_weight, L=L,
+        return out, dict(S=S, S0abs=S0abs, terms=terms, nfail=nfail, fail_weight=fail_weight, L=L,
                          log_pv=log_pv, jp=jp)
     return out
 

@@ -50,3 +50,30 @@ def sector_weights(W: np.ndarray, T: Sequence[int], L: int) -> Tuple[np.ndarray,
     if rc != 0:
         raise ValueError("sectors128: W or W_TT not positive definite")
     return hi, lo
+
+
+def _cluster_job(args):
+    W, T, L = args
+    hi, lo = sector_weights(W, T, L)
+    return hi, lo
+
+
+def cluster_moments(W: np.ndarray, jmax: int, L: int, workers: int = 1) -> np.ndarray:
+    """S_t[kappa] = sum over the clusters T of t positions of g_T[kappa], t = 0..jmax,
+    kappa < L (Methods, Moments calculation), every g_T in binary128: [jmax+1, L].
+    The sum runs in fp64 over the (hi + lo) values; every g_T[kappa] is >= 0 (a
+    sub-ensemble weight), so it adds no cancellation."""
+    import itertools
+    n = W.shape[0] // 2
+    S = np.zeros((jmax + 1, L))
+    for t in range(jmax + 1):
+        jobs = [(W, T, L) for T in itertools.combinations(range(n), t)]
+        if workers > 1 and len(jobs) > 1:
+            from multiprocessing import Pool
+            with Pool(workers) as pool:
+                res = pool.map(_cluster_job, jobs, chunksize=max(1, len(jobs) // (4 * workers)))
+        else:
+            res = [_cluster_job(j) for j in jobs]
+        for hi, lo in res:
+            S[t] += hi + lo
+    return S

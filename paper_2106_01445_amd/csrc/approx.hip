@@ -104,7 +104,9 @@ __global__ __launch_bounds__(1024) void k_build_items(int P, int nbig, int qchun
 // and segment, so the reads of the triple loop are broadcasts (blocks (b,c),
 // (c,c)) or consecutive across lanes (block (a,c)).
 // ---------------------------------------------------------------------------
-template <int ORDER, bool BIG, class C>
+// (RERUN: the same kernel for the second pass of a call, under its own name so
+// that traces keep the two passes apart)
+template <int ORDER, bool BIG, class C, bool RERUN = false>
 __global__ __launch_bounds__(CONT_THREADS) void k_contour(
     int lds_bytes, int qchunk, int gmax, const int *__restrict__ offsets,
     const long long *__restrict__ voff,
@@ -545,14 +547,15 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
 //           runs it again; where that is not possible it is flagged
 //           GBS_PS_CONTOUR.
 // ---------------------------------------------------------------------------
-template <int ORDER>
+template <int ORDER, int PASS = 0>
 __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__ offsets,
                                                          RowPlan *__restrict__ rows,
                                                          const cplx *__restrict__ sw,
                                                          double *__restrict__ logp,
                                                          int *__restrict__ status, double u_clu,
-                                                         double esc_bound, int pass, int allow_retilt)
+                                                         double esc_bound, int allow_retilt)
 {
+    constexpr int pass = PASS;
     extern __shared__ __attribute__((aligned(16))) double sh[];
     __shared__ double red[FIT_THREADS], red2[FIT_THREADS];
     const int p = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
@@ -575,8 +578,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
         return;
     }
     const int K = rp.K, Q = K / 2 + 1, jp = min(ORDER, n - 1);
-    int lg = 0;
-    while ((1 << lg) < K) ++lg;
+    const DftShape dsh = dft_shape(K);
     cplx *X = (cplx *)sh;            // K
     cplx *W = X + K;                 // K/2
     for (int m = tid; m < K / 2; m += nt) {
@@ -596,11 +598,11 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
             const cplx *src = sw + ((long)p * (ORDER + 1) + t) * GBS_QCAP;
             for (int q = tid; q < K; q += nt) {
                 const cplx v = q < Q ? src[q] : cmk(src[K - q].re, -src[K - q].im);
-                const int rq = (int)(__brev((unsigned)q) >> (32 - lg));
+                const int rq = dft_pos(dsh, q);
                 X[rq] = v;
             }
             __syncthreads();
-            fft_lds(X, W, K);
+            dft_lds(X, W, dsh);
 #pragma unroll
             for (int j = 0; j < FIT_KPT; ++j) {
                 const int kap = n + tid + nt * j;
@@ -766,8 +768,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dist_fit(const int *__restrict_
         return;
     }
     const int K = rp.K, Q = K / 2 + 1, jp = min(ORDER, n - 1);
-    int lg = 0;
-    while ((1 << lg) < K) ++lg;
+    const DftShape dsh = dft_shape(K);
     cplx *X = (cplx *)sh;
     cplx *W = X + K;
     for (int m = tid; m < K / 2; m += nt) {
@@ -784,10 +785,10 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dist_fit(const int *__restrict_
             const cplx *src = sw + (long)t * GBS_QCAP;  // (the row's planes: row 0)
             for (int q = tid; q < K; q += nt) {
                 const cplx v = q < Q ? src[q] : cmk(src[K - q].re, -src[K - q].im);
-                X[(int)(__brev((unsigned)q) >> (32 - lg))] = v;
+                X[dft_pos(dsh, q)] = v;
             }
             __syncthreads();
-            fft_lds(X, W, K);
+            dft_lds(X, W, dsh);
 #pragma unroll
             for (int j = 0; j < FIT_KPT; ++j) {
                 const int kap = tid + nt * j;
@@ -883,11 +884,11 @@ __global__ void k_retilt(int P, const int *__restrict__ offsets, const double *_
     rows[p] = rp;
 }
 
-template <int ORDER, bool BIG, class C>
+template <int ORDER, bool BIG, class C, bool RERUN = false>
 int launch_contour(gbs_ctx *ctx, gbs_plan *pl, int nmax)
 {
     hipStream_t st = ctx->stream;
-    const void *fn = (const void *)k_contour<ORDER, BIG, C>;
+    const void *fn = (const void *)k_contour<ORDER, BIG, C, RERUN>;
     int lds_static = 0;
     if (int rc = func_static_lds(ctx, fn, &lds_static)) return rc;
     const int lds_cap = ctx->lds_per_block - lds_static;
@@ -921,7 +922,7 @@ int launch_contour(gbs_ctx *ctx, gbs_plan *pl, int nmax)
     }
     const int *q_end = pl->d_counter + (BIG ? 4 : 0);
     int *q_head = pl->d_counter + (BIG ? 5 : 1);
-    hipLaunchKernelGGL((k_contour<ORDER, BIG, C>), dim3(grid), dim3(CONT_THREADS), lds_c, st, lds_c,
+    hipLaunchKernelGGL((k_contour<ORDER, BIG, C, RERUN>), dim3(grid), dim3(CONT_THREADS), lds_c, st, lds_c,
                        pl->qchunk, pl->gmax, pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_items,
                        q_end, q_head, pl->d_cluster_items, pl->d_cluster_off,
                        pl->order >= 4 ? pl->d_cluster_off + 4 * (pl->max_n + 1) : nullptr, mscr, mstride,
@@ -972,22 +973,19 @@ int launch_order(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
     ts = timer_begin(ctx, TG_FIT);
     hipLaunchKernelGGL(k_dft_fit<ORDER>, dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
                        pl->d_rows, pl->d_sw, logp, status, mixed ? ROUND_FP32 : ROUND_FP64,
-                       mixed ? MIXED_BOUND : 0.0, 0, retilt);
+                       mixed ? MIXED_BOUND : 0.0, retilt);
     timer_end(ctx, ts);
     if (mixed || retilt) {
-        ts = timer_begin(ctx, TG_ITEMS);
+        if ((rc = func_lds_limit(ctx, (const void *)k_dft_fit<ORDER, 1>, (int)lds_f))) return rc;
+        ts = timer_begin(ctx, TG_PASS2);
         hipLaunchKernelGGL(k_retilt, dim3((P + 255) / 256), dim3(256), 0, st, P, pl->d_offsets, pl->d_alpha,
                            pl->d_rows);
         hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, st, P, nbig, pl->qchunk, pl->d_offsets,
                            pl->d_perm, pl->d_rows, pl->d_items, pl->d_counter, GBS_PS_ESCALATED | GBS_ROW_RETILT);
-        timer_end(ctx, ts);
-        ts = timer_begin(ctx, TG_CONTOUR);
-        if (nbig > 0 && (rc = launch_contour<ORDER, true, cplx>(ctx, pl, pl->max_n))) return rc;
-        if (nbig < P && (rc = launch_contour<ORDER, false, cplx>(ctx, pl, nsmall_max))) return rc;
-        timer_end(ctx, ts);
-        ts = timer_begin(ctx, TG_FIT);
-        hipLaunchKernelGGL(k_dft_fit<ORDER>, dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
-                           pl->d_rows, pl->d_sw, logp, status, ROUND_FP64, 0.0, 1, 0);
+        if (nbig > 0 && (rc = launch_contour<ORDER, true, cplx, true>(ctx, pl, pl->max_n))) return rc;
+        if (nbig < P && (rc = launch_contour<ORDER, false, cplx, true>(ctx, pl, nsmall_max))) return rc;
+        hipLaunchKernelGGL((k_dft_fit<ORDER, 1>), dim3(P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
+                           pl->d_rows, pl->d_sw, logp, status, ROUND_FP64, 0.0, 0);
         timer_end(ctx, ts);
     }
     HIP_TRY(ctx, hipGetLastError());
@@ -1029,7 +1027,7 @@ int launch_plain(gbs_ctx *ctx, gbs_plan *pl, double *logp, int32_t *status)
     if ((rc = func_lds_limit(ctx, (const void *)k_dft_fit<ORDER>, (int)lds_f))) return rc;
     ts = timer_begin(ctx, TG_FIT);
     hipLaunchKernelGGL(k_dft_fit<ORDER>, dim3(pl->P), dim3(FIT_THREADS), lds_f, st, pl->d_offsets,
-                       pl->d_rows, pl->d_sw, logp, status, ROUND_FP64, 0.0, 0, 0);
+                       pl->d_rows, pl->d_sw, logp, status, ROUND_FP64, 0.0, 0);
     timer_end(ctx, ts);
     HIP_TRY(ctx, hipGetLastError());
     return 0;
@@ -1049,9 +1047,25 @@ int approx_forward_plain(gbs_ctx *ctx, gbs_plan *pl, double *logp_dev, int32_t *
     }
 }
 
-int approx_forward(gbs_ctx *ctx, gbs_plan *pl, double *logp_dev, int32_t *status_dev)
+namespace {
+__global__ void k_status_or(int P, int32_t *__restrict__ status, int bits)
 {
-    if (pl->P == 0) return 0;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) status[p] |= bits;
+}
+}  // namespace
+
+int status_or(gbs_ctx *ctx, int P, int32_t *status_dev, int bits)
+{
+    if (P == 0 || !status_dev) return 0;
+    hipLaunchKernelGGL(k_status_or, dim3((P + 255) / 256), dim3(256), 0, ctx->stream, P, status_dev, bits);
+    HIP_TRY(ctx, hipGetLastError());
+    return 0;
+}
+
+namespace {
+int forward_order(gbs_ctx *ctx, gbs_plan *pl, double *logp_dev, int32_t *status_dev)
+{
     switch (pl->order) {
     case 1: return launch_order<1>(ctx, pl, logp_dev, status_dev);
     case 2: return launch_order<2>(ctx, pl, logp_dev, status_dev);
@@ -1059,6 +1073,22 @@ int approx_forward(gbs_ctx *ctx, gbs_plan *pl, double *logp_dev, int32_t *status
     case 4: return launch_order<4>(ctx, pl, logp_dev, status_dev);
     default: return set_err(ctx, -1, "order must be 1, 2, 3 or 4");
     }
+}
+}  // namespace
+
+// Order 4 has no fp32 cluster kernels: asked for the mixed tier, it runs in
+// fp64 and every row reports GBS_PS_ESCALATED.
+int approx_forward(gbs_ctx *ctx, gbs_plan *pl, double *logp_dev, int32_t *status_dev)
+{
+    if (pl->P == 0) return 0;
+    const bool esc_all = pl->order == 4 && pl->prec == GBS_PREC_MIXED;
+    if (esc_all) pl->prec = GBS_PREC_FP64;
+    int rc = forward_order(ctx, pl, logp_dev, status_dev);
+    if (esc_all) {
+        pl->prec = GBS_PREC_MIXED;
+        if (rc == 0) rc = status_or(ctx, pl->P, status_dev, GBS_PS_ESCALATED);
+    }
+    return rc;
 }
 
 int click_distribution_run(gbs_ctx *ctx, gbs_plan *pl, int nk, const int *ks_dev, double *pn_dev, double *pk_dev,

@@ -468,8 +468,6 @@ int gbs_plan_create(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *
     if (order < 1 || order > 4) return set_err(ctx, GBS_E_INVAL, "order must be 1, 2, 3 or 4");
     if (prec != GBS_PREC_FP64 && prec != GBS_PREC_MIXED)
         return set_err(ctx, GBS_E_INVAL, "prec must be GBS_PREC_FP64 or GBS_PREC_MIXED");
-    if (order == 4 && prec != GBS_PREC_FP64)
-        return set_err(ctx, GBS_E_INVAL, "order 4 runs in fp64 only");
     int rc = check_csr(ctx, P, offsets, modes, ctx->model.M,
                        order == 4 ? GBS_MAX_N_ORDER4 : order == 3 ? GBS_MAX_N_ORDER3 : GBS_MAX_N_APPROX);
     if (rc) return rc;
@@ -806,13 +804,18 @@ int gbs_prob_exact(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *m
 {
     if (!ctx) return GBS_E_INVAL;
     if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
-    if (prec != GBS_PREC_FP64) return set_err(ctx, GBS_E_INVAL, "prec must be GBS_PREC_FP64");
+    if (prec != GBS_PREC_FP64 && prec != GBS_PREC_MIXED)
+        return set_err(ctx, GBS_E_INVAL, "prec must be GBS_PREC_FP64 or GBS_PREC_MIXED");
     if (P > 0 && (!p || !status)) return set_err(ctx, GBS_E_INVAL, "NULL output array");
     int rc = check_csr(ctx, P, offsets, modes, ctx->model.M, GBS_MAX_N_EXACT);
     if (rc) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     rc = exact_run(ctx, P, offsets, modes, p, logp, kappa, status);
     if (rc) return rc;
+    // the mixed tier: fp32 terms would reach 1e-6 only for kappa_IE <= 10, so
+    // every row runs in the double-double tier and says so
+    if (prec == GBS_PREC_MIXED)
+        for (int i = 0; i < P; ++i) status[i] |= GBS_PS_ESCALATED;
     for (int i = 0; i < P; ++i)
         if (status[i] != 0) return GBS_W_PATTERN;
     return GBS_OK;
@@ -875,14 +878,22 @@ int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, double *logp_
         return set_err(ctx, GBS_E_STATE, "gradient needs a model set by gbs_set_model");
     if (ctx->model.M != pl->M) return set_err(ctx, GBS_E_STATE, "plan was made for a model of another size M");
     if (!dl_dev || !grad_r_dev || !grad_eta_dev) return set_err(ctx, GBS_E_INVAL, "NULL device array");
-    if (pl->prec != GBS_PREC_FP64) return set_err(ctx, GBS_E_INVAL, "the gradient runs in fp64 only");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     double *lp = logp_dev ? logp_dev : pl->d_logp;
     int32_t *stt = status_dev ? status_dev : pl->d_status;
+    // the adjoint exists in fp64 only: a mixed-tier plan runs forward and
+    // adjoint in fp64 here, and every row reports GBS_PS_ESCALATED
+    const bool esc_all = pl->prec != GBS_PREC_FP64;
+    const int prec = pl->prec;
+    pl->prec = GBS_PREC_FP64;
     int rc = approx_forward(ctx, pl, lp, stt);
-    if (rc) return rc;
-    pl->have_run = true;
-    return approx_backward(ctx, pl, dl_dev, stt, grad_r_dev, grad_eta_dev);
+    if (rc == 0) {
+        pl->have_run = true;
+        rc = approx_backward(ctx, pl, dl_dev, stt, grad_r_dev, grad_eta_dev);
+    }
+    pl->prec = prec;
+    if (rc == 0 && esc_all) rc = status_or(ctx, pl->P, stt, GBS_PS_ESCALATED);
+    return rc;
 }
 
 int gbs_click_distribution(gbs_ctx *ctx, int order, int nk, const int32_t *ks, double *p_n, double *p_k,
@@ -935,7 +946,6 @@ int gbs_grad(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, 
     if (!ctx) return GBS_E_INVAL;
     if (!dL_dlogp || !grad_r || !grad_eta || (P > 0 && !status))
         return set_err(ctx, GBS_E_INVAL, "NULL array");
-    if (prec != GBS_PREC_FP64) return set_err(ctx, GBS_E_INVAL, "the gradient runs in fp64 only");
     if (!ctx->model.have || !ctx->model.from_params)
         return set_err(ctx, GBS_E_STATE, "gradient needs a model set by gbs_set_model");
     gbs_plan *pl = nullptr;

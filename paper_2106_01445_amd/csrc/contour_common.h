@@ -128,8 +128,9 @@ __host__ __device__ __forceinline__ int cont_fixed() { return 16 * (CONT_THREADS
 // alpha[i * astride]), run by one thread: log P_vac(Cbar), and unless the plan is
 // frozen the radius rho (the saddle point of the photon-number generating
 // function at n photons, capped at 0.98 of the convergence radius
-// 1/max|alpha - 1|) and the size K (a power of two >= 2n + 32 whose aliasing
-// factor (rho/R_b)^K is below 1e-16, at most GBS_KMAX); then log G_0(rho).
+// 1/max|alpha - 1|) and the size K (the smallest r 2^a, r = 1, 3 or 5, that is
+// >= 2n + 32 and whose aliasing factor (rho/R_b)^K is below 1e-16, at most
+// GBS_KMAX); then log G_0(rho).
 // (The radius thus tilts towards max(n, untilted mean).)
 // A frozen radius is kept only while it still lies inside the current
 // convergence disc with an aliasing factor (rho max|alpha - 1|)^K <= 1e-14 (the
@@ -191,8 +192,13 @@ __device__ __forceinline__ void row_plan(RowPlan &rp, int n, const double *alpha
         }
         double kneed = 2.0 * n + 32.0;
         if (dev >= 1e-300) kneed = fmax(kneed, log(1e-16) / log(rho / rb));
-        int K = 1;
-        while (K < kneed && K < GBS_KMAX) K *= 2;
+        // the smallest r 2^a (r = 1, 3, 5; the sizes dft_lds takes) >= kneed
+        int K = GBS_KMAX;
+        for (int r = 1; r <= 5; r += 2) {
+            int k = 2 * r;
+            while (k < kneed && k < GBS_KMAX) k *= 2;
+            if (k >= kneed && k < K) K = k;
+        }
         rp.rho = rho;
         rp.kbar = target;
         rp.rconv = rb;
@@ -523,21 +529,72 @@ __device__ __forceinline__ void lse_add(double &mx, double &s, double v)
     }
 }
 
-// In-place radix-2 FFT of X[0..K) in LDS (forward sign), K a power of two;
-// W[m] = exp(-2 pi i m / K), m < K/2.  Input must already be in bit-reversed
-// order.  All threads of the block take part.
-__device__ void fft_lds(cplx *X, const cplx *W, int K)
+// Sector transforms.  A contour has K = r 2^a points, r in {1, 3, 5} (the
+// smallest such K that meets the aliasing rule, so that fewer points are
+// evaluated than with powers of two alone).  The forward DFT
+// X[k] = sum_q x[q] W^{qk}, W = exp(-2 pi i / K), runs in LDS by decimation in
+// time: the r interleaved subsequences x[j + r m] (j < r) are transformed by
+// radix-2 stages, each in its own block of L = K / r entries, and combined by
+// r-point DFTs: X[m + s L] = sum_j W^{j m} F_j[m] W^{j s L} (s < r).
+struct DftShape {
+    int K, r, L, lgL;
+};
+__device__ __forceinline__ DftShape dft_shape(int K)
+{
+    DftShape d;
+    d.K = K;
+    d.r = K % 5 == 0 ? 5 : K % 3 == 0 ? 3 : 1;
+    d.L = K / d.r;
+    d.lgL = 0;
+    while ((1 << d.lgL) < d.L) ++d.lgL;
+    return d;
+}
+// Where input sample q goes: block q mod r, bit-reversed position q div r.
+__device__ __forceinline__ int dft_pos(const DftShape &d, int q)
+{
+    const int j = q % d.r, m = q / d.r;
+    return j * d.L + (int)(__brev((unsigned)m) >> (32 - d.lgL));
+}
+// W^e for 0 <= e < K from the half table W[m] = exp(-2 pi i m / K), m < K/2.
+__device__ __forceinline__ cplx dft_tw(const cplx *W, int K, int e)
+{
+    return e < K / 2 ? W[e] : cneg(W[e - K / 2]);
+}
+// In-place forward DFT of X[0..K) in LDS, input placed by dft_pos, output in
+// natural order.  All threads of the block take part.
+__device__ void dft_lds(cplx *X, const cplx *W, const DftShape &d)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (int half = 1; half < K; half <<= 1) {
-        const int tstep = K / (2 * half);
+    const int K = d.K, L = d.L, hl = L / 2;
+    for (int half = 1; half < L; half <<= 1) {
+        // W_L^{pos L / (2 half)} = W^{pos r L / (2 half)}
+        const int tstep = d.r * (L / (2 * half));
         for (int b = tid; b < K / 2; b += nt) {
-            const int grp = b / half, pos = b - grp * half;
-            const int i = grp * 2 * half + pos, j = i + half;
+            const int blk = b / hl, bb = b - blk * hl;
+            const int grp = bb / half, pos = bb - grp * half;
+            const int i = blk * L + grp * 2 * half + pos, j = i + half;
             const cplx w = W[pos * tstep];
             const cplx u = X[i], v = cmul(w, X[j]);
             X[i] = cadd(u, v);
             X[j] = csub(u, v);
+        }
+        __syncthreads();
+    }
+    if (d.r > 1) {
+        for (int m = tid; m < L; m += nt) {
+            cplx f[5];
+#pragma unroll
+            for (int j = 0; j < 5; ++j)
+                if (j < d.r) f[j] = j == 0 ? X[m] : cmul(dft_tw(W, K, j * m), X[j * L + m]);
+#pragma unroll
+            for (int s2 = 0; s2 < 5; ++s2) {
+                if (s2 >= d.r) continue;
+                cplx acc = f[0];
+#pragma unroll
+                for (int j = 1; j < 5; ++j)
+                    if (j < d.r) acc = cadd(acc, cmul(dft_tw(W, K, ((j * s2) % d.r) * L), f[j]));
+                X[s2 * L + m] = acc;
+            }
         }
         __syncthreads();
     }

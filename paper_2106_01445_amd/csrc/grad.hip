@@ -61,8 +61,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
         return;
     }
     const int K = rp.K, Q = K / 2 + 1, jp = min(ORDER, n - 1);
-    int lg = 0;
-    while ((1 << lg) < K) ++lg;
+    const DftShape dsh = dft_shape(K);
     cplx *X = (cplx *)sh;
     cplx *W = X + K;
     for (int m = tid; m < K / 2; m += nt) {
@@ -81,10 +80,10 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
             const cplx *src = sw + ((long)p * (ORDER + 1) + t) * GBS_QCAP;
             for (int q = tid; q < K; q += nt) {
                 const cplx v = q < Q ? src[q] : cmk(src[K - q].re, -src[K - q].im);
-                X[(int)(__brev((unsigned)q) >> (32 - lg))] = v;
+                X[dft_pos(dsh, q)] = v;
             }
             __syncthreads();
-            fft_lds(X, W, K);
+            dft_lds(X, W, dsh);
 #pragma unroll
             for (int j = 0; j < FIT_KPT; ++j) {
                 const int kap = n + tid + nt * j;
@@ -173,10 +172,10 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
 #pragma unroll
         for (int j = 0; j < FIT_KPT; ++j) {
             const int kap = n + tid + nt * j;
-            if (kap < K) X[(int)(__brev((unsigned)kap) >> (32 - lg))] = cmk(tbar[j][t], 0.0);
+            if (kap < K) X[dft_pos(dsh, kap)] = cmk(tbar[j][t], 0.0);
         }
         __syncthreads();
-        fft_lds(X, W, K);
+        dft_lds(X, W, dsh);
         for (int q = tid; q < Q; q += nt) {
             const double cq = (q == 0 || q == K / 2) ? invK : 2.0 * invK;
             dst[q] = cscale(X[q], cq);

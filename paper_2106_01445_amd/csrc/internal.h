@@ -81,7 +81,7 @@ int func_occupancy(gbs_ctx *ctx, const void *f, int threads, int lds, int *block
 int timer_begin(gbs_ctx *ctx, int group);
 void timer_end(gbs_ctx *ctx, int slot);
 enum { TG_MODEL = 0, TG_PREP = 1, TG_ITEMS = 2, TG_CONTOUR = 3, TG_FIT = 4, TG_EXACT = 5,
-       TG_ADJ_FIT = 6, TG_ADJ_CLUSTER = 7, TG_ADJ_ROWS = 8, TG_ADJ_MODEL = 9 };
+       TG_ADJ_FIT = 6, TG_ADJ_CLUSTER = 7, TG_ADJ_ROWS = 8, TG_ADJ_MODEL = 9, TG_PASS2 = 10 };
 
 // Per-row scalar results of the approximate path's set-up step.  status holds
 // the failure bits (the row has no result); flags the informational bits that
@@ -167,6 +167,8 @@ int set_err(gbs_ctx *ctx, int code, const std::string &msg);
 // kernels' host launchers ----------------------------------------------------
 int model_build_dev(gbs_ctx *ctx, const double *sigma_dev, bool sync);
 int approx_forward(gbs_ctx *ctx, gbs_plan *plan, double *logp_dev, int32_t *status_dev);
+// status_dev[p] |= bits for every row (stream-ordered; NULL status: nothing)
+int status_or(gbs_ctx *ctx, int P, int32_t *status_dev, int bits);
 int exact_run(gbs_ctx *ctx, int P, const int32_t *offsets, const int32_t *modes, double *p,
               double *logp, double *kappa, int32_t *status);
 int exact_lgs(int maxn);

@@ -29,7 +29,7 @@ EXPORTS = ["gbs_create", "gbs_destroy", "gbs_last_error", "gbs_set_model", "gbs_
            "gbs_stream", "gbs_click_distribution", "gbs_prob_exact_dev", "gbs_prob_exact_dev_noalloc"]
 TIMING_GROUPS = ["model", "row_setup", "work_queue", "contour_clusters", "dft_fit", "exact",
                  "adjoint_fit_dft", "adjoint_contour_clusters", "adjoint_rows_scatter",
-                 "adjoint_model"]
+                 "adjoint_model", "second_pass"]
 
 _lib = None
 

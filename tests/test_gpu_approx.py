@@ -219,13 +219,31 @@ def test_mixed_precision(gpu_ctx, cfg, order, P):
     assert np.all(err[~esc] <= 1e-5)
 
 
-def test_mixed_precision_rejected_where_unsupported(gpu_ctx):
+def test_mixed_precision_where_no_fp32_kernel_exists(gpu_ctx):
+    """The exact path, order 4 and the gradient have no fp32 kernels: asked for
+    the mixed tier they run at the higher precision and flag every row
+    GBS_PS_ESCALATED, with results equal to the fp64 call's; the plain
+    comparison kernel rejects the tier."""
     import paper_2106_01445_amd as g
     wl = make_workload(1)
     gpu_ctx.gbs_set_model(wl.U, wl.r, wl.eta)
-    for call in (lambda: gpu_ctx.gbs_prob_exact(wl.offsets, wl.modes, prec=g.GBS_PREC_MIXED),
-                 lambda: gpu_ctx.gbs_grad(wl.offsets, wl.modes, 2, np.ones(wl.P), prec=g.GBS_PREC_MIXED),
-                 lambda: gpu_ctx.gbs_prob_approx_plain(wl.offsets, wl.modes, 2, prec=g.GBS_PREC_MIXED)):
-        with pytest.raises(g.GBSError) as e:
-            call()
-        assert e.value.code == -1
+    esc = g.gbs.GBS_PS_ESCALATED
+    a = gpu_ctx.gbs_prob_exact(wl.offsets, wl.modes)
+    b = gpu_ctx.gbs_prob_exact(wl.offsets, wl.modes, prec=g.GBS_PREC_MIXED)
+    assert np.all(a["status"] == 0) and np.all(b["status"] == esc)
+    assert np.array_equal(a["p"], b["p"])
+    a = gpu_ctx.gbs_prob_approx(wl.offsets, wl.modes, 4)
+    b = gpu_ctx.gbs_prob_approx(wl.offsets, wl.modes, 4, prec=g.GBS_PREC_MIXED)
+    assert np.all(a["status"] == 0) and np.all(b["status"] == esc)
+    assert np.array_equal(a["logp"], b["logp"])
+    w = np.linspace(0.5, 1.5, wl.P)
+    a = gpu_ctx.gbs_grad(wl.offsets, wl.modes, 2, w)
+    b = gpu_ctx.gbs_grad(wl.offsets, wl.modes, 2, w, prec=g.GBS_PREC_MIXED)
+    assert np.all(a["status"] == 0) and np.all(b["status"] == esc)
+    assert np.array_equal(a["logp"], b["logp"])
+    # (the adjoint sums over clusters with atomic adds: equal up to their order)
+    for k in ("grad_r", "grad_eta"):
+        assert np.allclose(a[k], b[k], rtol=1e-12, atol=1e-14 * np.max(np.abs(a[k])))
+    with pytest.raises(g.GBSError) as e:
+        gpu_ctx.gbs_prob_approx_plain(wl.offsets, wl.modes, 2, prec=g.GBS_PREC_MIXED)
+    assert e.value.code == -1

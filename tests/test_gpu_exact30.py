@@ -18,6 +18,8 @@ import pytest
 from oracle import exact128
 from workloads import SEED_ROOT, csr_from_lists, haar_unitary
 
+from paper_2106_01445_amd import gbs
+
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
 
@@ -74,6 +76,26 @@ def test_product_state_30_clicks(gpu_ctx):
     assert abs(out["kappa"][0] / np.prod((1 + P0) / (1 - P0)) - 1) < 1e-10
     ref = np.prod(1 - P0)
     assert abs(out["p"][0] / ref - 1) < TOL
+
+
+def test_cancellation_beyond_double_double_is_flagged(gpu_ctx):
+    """A weakly squeezed product state: the signed sum over the 2^n subsets
+    cancels by prod (1 + P0)/(1 - P0) ~ 4e36 at 24 clicks, beyond the 1e20
+    that double-double resolves, so the row is NaN with GBS_PS_CANCEL (the
+    other row, 10 clicks of the same state, cancels by ~2e15 and is exact)."""
+    M = 24
+    r = np.full(M, 0.35)
+    eta = np.full(M, 0.9)
+    gpu_ctx.gbs_set_model(np.eye(M, dtype=complex), r, eta)
+    P0 = (1 + eta * (2 - eta) * np.sinh(r) ** 2) ** -0.5
+    k24 = np.prod((1 + P0) / (1 - P0))
+    k10 = np.prod(((1 + P0) / (1 - P0))[:10])
+    assert k24 > 1e22 and k10 < 1e16
+    out = gpu_ctx.gbs_prob_exact(*csr_from_lists([list(range(M)), list(range(10))]))
+    assert out["status"][0] == gbs.GBS_PS_CANCEL and np.isnan(out["p"][0])
+    assert out["status"][1] == 0
+    ref = np.prod(1 - P0[:10]) * np.prod(P0[10:])
+    assert abs(out["p"][1] / ref - 1) < TOL
 
 
 def test_relabelled_modes_26_clicks(gpu_ctx):
