@@ -557,6 +557,10 @@ def main():
             "all_kernels": {k: {"ms": round(v["ms"], 3), "tflops": round(v["tflops"], 3),
                                 "frac": round(v["tflops"] / PEAK_FP64_VALU_TFLOPS, 4)}
                             for k, v in rates.items()}}
+    roof["traffic_source"] = ("committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary "
+                              "(profiles/counters_m70_order3.md), taken on these kernel sources"
+                              if cnt and cnt.get("bytes_per_launch") is not None else
+                              "none: the committed counter summary was taken on other kernel sources")
     if cnt and cnt.get("valu_fp64_flops") is not None:
         # executed fp64 work of the same launch, from the committed counters
         # (taken on these kernel sources), over this run's kernel time

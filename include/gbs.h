@@ -201,7 +201,7 @@ int gbs_prob_exact_dev_noalloc(gbs_ctx *ctx, int P, const int32_t *offsets_dev, 
  *      log P_vac(Cbar) = -(log det Q + log det A) / 2 (eq. 3, second factor);
  *   2. contour radius rho: the tilted mean photon number equals max(n, the
  *      untilted mean), capped at 0.98 of the convergence radius
- *      1/max|alpha-1|; K points, K the smallest r 2^k (r = 1, 3 or 5) with
+ *      1/max|alpha-1|; K points, K the smallest r 2^k (r odd <= 15, k >= 1) with
  *      (rho/R)^K <= 1e-16 and K >= 2n+32, K <= 2048;
  *   3. at each contour point w: M(w) = ((1-w)I + wA)^{-1} and, for every cluster
  *      T of <= j clicked modes, G_T(w) = det(A)^{1/2} det((1-w)I+wA)^{-1/2}

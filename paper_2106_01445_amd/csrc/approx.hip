@@ -172,9 +172,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
         const int np = n * (n - 1) / 2;
         // the item's contour points w_q = rho e^{2 pi i q / K}
         if (tid < q1 - q0) {
-            double sn, cs;
-            sincospi(2.0 * (double)(q0 + tid) / (double)rp.K, &sn, &cs);
-            s_wq[tid] = cmk(rp.rho * cs, rp.rho * sn);
+            s_wq[tid] = cscale(unit_root(q0 + tid, rp.K), rp.rho);
         }
         __syncthreads();
         // (every pass ends with a barrier, so the next pass may write its slots
@@ -582,9 +580,8 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dft_fit(const int *__restrict__
     cplx *X = (cplx *)sh;            // K
     cplx *W = X + K;                 // K/2
     for (int m = tid; m < K / 2; m += nt) {
-        double sn, cs;
-        sincospi(-2.0 * (double)m / (double)K, &sn, &cs);
-        W[m] = cmk(cs, sn);
+        const cplx u = unit_root(m, K);
+        W[m] = cmk(u.re, -u.im);
     }
     // tilted sector moments tau_t[kappa] = Re FFT(S_t(w_q))[kappa] / K, where the
     // points q > K/2 are the conjugates of K - q (real coefficients)
@@ -772,9 +769,8 @@ __global__ __launch_bounds__(FIT_THREADS) void k_dist_fit(const int *__restrict_
     cplx *X = (cplx *)sh;
     cplx *W = X + K;
     for (int m = tid; m < K / 2; m += nt) {
-        double sn, cs;
-        sincospi(-2.0 * (double)m / (double)K, &sn, &cs);
-        W[m] = cmk(cs, sn);
+        const cplx u = unit_root(m, K);
+        W[m] = cmk(u.re, -u.im);
     }
     constexpr int NT = ORDER >= 4 ? 5 : 4;
     double tau[FIT_KPT][NT];

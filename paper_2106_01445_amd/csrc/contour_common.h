@@ -19,6 +19,10 @@
 #define MIXED_BOUND 1e-5
 #endif
 #define FIT_MAXIT 100
+// largest odd factor of a contour size (K = r 2^a, r odd <= DFT_RMAX)
+#ifndef DFT_RMAX
+#define DFT_RMAX 15
+#endif
 #define FIT_KPT (GBS_KMAX / FIT_THREADS)
 
 namespace {
@@ -128,9 +132,9 @@ __host__ __device__ __forceinline__ int cont_fixed() { return 16 * (CONT_THREADS
 // alpha[i * astride]), run by one thread: log P_vac(Cbar), and unless the plan is
 // frozen the radius rho (the saddle point of the photon-number generating
 // function at n photons, capped at 0.98 of the convergence radius
-// 1/max|alpha - 1|) and the size K (the smallest r 2^a, r = 1, 3 or 5, that is
-// >= 2n + 32 and whose aliasing factor (rho/R_b)^K is below 1e-16, at most
-// GBS_KMAX); then log G_0(rho).
+// 1/max|alpha - 1|) and the size K (the smallest r 2^a, r odd <= DFT_RMAX,
+// a >= 1, that is >= 2n + 32 and whose aliasing factor (rho/R_b)^K is below
+// 1e-16, at most GBS_KMAX); then log G_0(rho).
 // (The radius thus tilts towards max(n, untilted mean).)
 // A frozen radius is kept only while it still lies inside the current
 // convergence disc with an aliasing factor (rho max|alpha - 1|)^K <= 1e-14 (the
@@ -192,9 +196,10 @@ __device__ __forceinline__ void row_plan(RowPlan &rp, int n, const double *alpha
         }
         double kneed = 2.0 * n + 32.0;
         if (dev >= 1e-300) kneed = fmax(kneed, log(1e-16) / log(rho / rb));
-        // the smallest r 2^a (r = 1, 3, 5; the sizes dft_lds takes) >= kneed
+        // the smallest r 2^a (r odd <= DFT_RMAX, a >= 1; the sizes dft_lds
+        // takes) >= kneed
         int K = GBS_KMAX;
-        for (int r = 1; r <= 5; r += 2) {
+        for (int r = 1; r <= DFT_RMAX; r += 2) {
             int k = 2 * r;
             while (k < kneed && k < GBS_KMAX) k *= 2;
             if (k >= kneed && k < K) K = k;
@@ -529,9 +534,30 @@ __device__ __forceinline__ void lse_add(double &mx, double &s, double v)
     }
 }
 
-// Sector transforms.  A contour has K = r 2^a points, r in {1, 3, 5} (the
-// smallest such K that meets the aliasing rule, so that fewer points are
-// evaluated than with powers of two alone).  The forward DFT
+// exp(2 pi i q / K), q >= 0, with the angle reduced to the nearest quarter
+// turn in integers first: 2q/K = k/2 + x, k = round(4q/K), x = (4q - kK)/(2K)
+// in [-1/4, 1/4], so that the only rounding is that of x.  Points near -1 (on
+// a contour, w = -rho, next to the generating function's singularity on the
+// negative axis) and near +-1, +-i then carry phase errors of ~1e-17 rad for
+// every K, where rounding 2q/K itself would cost ~3e-16 rad whenever K is not
+// a power of two.
+__device__ __forceinline__ cplx unit_root(long long q, int K)
+{
+    const long long k = (4 * q + K / 2) / K;
+    const double x = (double)(4 * q - k * K) / (2.0 * (double)K);
+    double s, c;
+    sincospi(x, &s, &c);
+    switch ((int)(k & 3)) {
+    case 0: return cplx{c, s};
+    case 1: return cplx{-s, c};
+    case 2: return cplx{-c, -s};
+    default: return cplx{s, -c};
+    }
+}
+
+// Sector transforms.  A contour has K = r 2^a points, r odd and at most
+// DFT_RMAX, a >= 1 (the smallest such K that meets the aliasing rule, so that
+// fewer points are evaluated than with powers of two alone).  The forward DFT
 // X[k] = sum_q x[q] W^{qk}, W = exp(-2 pi i / K), runs in LDS by decimation in
 // time: the r interleaved subsequences x[j + r m] (j < r) are transformed by
 // radix-2 stages, each in its own block of L = K / r entries, and combined by
@@ -543,7 +569,7 @@ __device__ __forceinline__ DftShape dft_shape(int K)
 {
     DftShape d;
     d.K = K;
-    d.r = K % 5 == 0 ? 5 : K % 3 == 0 ? 3 : 1;
+    d.r = K >> __builtin_ctz((unsigned)K);  // the odd part
     d.L = K / d.r;
     d.lgL = 0;
     while ((1 << d.lgL) < d.L) ++d.lgL;
@@ -582,17 +608,20 @@ __device__ void dft_lds(cplx *X, const cplx *W, const DftShape &d)
     }
     if (d.r > 1) {
         for (int m = tid; m < L; m += nt) {
-            cplx f[5];
+            cplx f[DFT_RMAX];
 #pragma unroll
-            for (int j = 0; j < 5; ++j)
+            for (int j = 0; j < DFT_RMAX; ++j)
                 if (j < d.r) f[j] = j == 0 ? X[m] : cmul(dft_tw(W, K, j * m), X[j * L + m]);
-#pragma unroll
-            for (int s2 = 0; s2 < 5; ++s2) {
-                if (s2 >= d.r) continue;
+            for (int s2 = 0; s2 < d.r; ++s2) {
                 cplx acc = f[0];
+                int e = 0;  // (j s2 mod r) L, stepped by s2 L
 #pragma unroll
-                for (int j = 1; j < 5; ++j)
-                    if (j < d.r) acc = cadd(acc, cmul(dft_tw(W, K, ((j * s2) % d.r) * L), f[j]));
+                for (int j = 1; j < DFT_RMAX; ++j) {
+                    if (j >= d.r) continue;
+                    e += s2 * L;
+                    if (e >= K) e -= K;
+                    acc = cadd(acc, cmul(dft_tw(W, K, e), f[j]));
+                }
                 X[s2 * L + m] = acc;
             }
         }

@@ -65,9 +65,8 @@ __global__ __launch_bounds__(FIT_THREADS) void k_adj_fit(const int *__restrict__
     cplx *X = (cplx *)sh;
     cplx *W = X + K;
     for (int m = tid; m < K / 2; m += nt) {
-        double sn, cs;
-        sincospi(-2.0 * (double)m / (double)K, &sn, &cs);
-        W[m] = cmk(cs, sn);
+        const cplx u = unit_root(m, K);
+        W[m] = cmk(u.re, -u.im);
     }
     // (loops over t and j unrolled: every index into the per-thread arrays is static)
     constexpr int NT = ORDER >= 4 ? 5 : 4;  // moments held per sector
@@ -462,9 +461,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         }
         // the item's contour points w_q = rho e^{2 pi i q / K}
         if (tid < q1 - q0) {
-            double sn, cs;
-            sincospi(2.0 * (double)(q0 + tid) / (double)rp.K, &sn, &cs);
-            s_wq[tid] = cmk(rp.rho * cs, rp.rho * sn);
+            s_wq[tid] = cscale(unit_root(q0 + tid, rp.K), rp.rho);
         }
         __syncthreads();
         // (every pass over a point ends with a barrier, so the next point's d_k

@@ -89,9 +89,7 @@ __global__ __launch_bounds__(PLAIN_THREADS) void k_plain(const int *__restrict__
     __syncthreads();
     for (int q = 0; q < Q; ++q) {
         if (tid == 0) {
-            double sn, cs;
-            sincospi(2.0 * (double)q / (double)rp.K, &sn, &cs);
-            s_w = cmk(rp.rho * cs, rp.rho * sn);
+            s_w = cscale(unit_root(q, rp.K), rp.rho);
         }
         __syncthreads();
         const cplx w = s_w;
