@@ -311,6 +311,50 @@ def order4_leg(ctx, torch):
             "max_abs_dlogp_vs_oracle_2_rows": float(err)}
 
 
+def mcmc_leg(ctx, torch, stream):
+    """Metropolis-Hastings chains of click patterns (Discussion: the
+    approximate probabilities as the target of a Markov chain Monte Carlo
+    sampler): 4096 chains on the 70-mode device, started from the batch's
+    first 4096 patterns (15-40 clicks, fixed per chain), target the order-3 and
+    the order-4 estimate; one step = a swap proposal for every chain, its
+    log p_hat on the device, acceptance (gbs_mcmc_step_dev), uniforms drawn
+    on the library's stream; 4 steps timed after one."""
+    from workloads import make_workload
+    wl = make_workload(3, P=4096)
+    ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    dev = torch.device("cuda:0")
+    out = {"workload": "m70_mcmc", "chains": wl.P, "clicks": "15-40 (fixed per chain)"}
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(2106)
+    for order in (3, 4):
+        plan = ctx.gbs_plan_create(wl.offsets, wl.modes, order)
+        with torch.cuda.stream(stream):
+            modes = torch.tensor(wl.modes, dtype=torch.int32, device=dev)
+            lp = torch.empty(wl.P, dtype=torch.float64, device=dev)
+            acc = torch.empty(wl.P, dtype=torch.int32, device=dev)
+            tot = torch.zeros((), dtype=torch.int64, device=dev)
+            u = torch.empty(3 * wl.P, dtype=torch.float64, device=dev)
+        ctx.gbs_prob_approx_dev(plan, lp)
+        steps = 4
+        for s in range(steps + 1):
+            if s == 1:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            with torch.cuda.stream(stream):
+                u.uniform_(0.0, 1.0, generator=gen)
+            ctx.gbs_mcmc_step_dev(plan, u, modes, lp, acc)
+            if s >= 1:
+                with torch.cuda.stream(stream):
+                    tot += acc.sum()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        out[f"order{order}"] = {"ms_per_step": ms, "chain_steps_per_s": wl.P / (ms * 1e-3),
+                                "acceptance": float(tot.item()) / (steps * wl.P),
+                                "finite_logp": bool(torch.isfinite(lp).all().item())}
+        plan.close()
+    return out
+
+
 def accuracy_leg(ctx):
     """The accuracy study of the paper's Numerical accuracy paragraph (Fig. 4)
     on synthetic Haar interferometers: the relative deviation
@@ -414,6 +458,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain comparison kernel")
     ap.add_argument("--no-order4", action="store_true", help="skip the fourth-order leg")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy-study leg")
+    ap.add_argument("--no-mcmc", action="store_true", help="skip the Metropolis-Hastings leg")
     ap.add_argument("--no-dist", action="store_true", help="skip the click-distribution leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch choices")
     ap.add_argument("--copy-probe", action="store_true",
@@ -602,6 +647,8 @@ def main():
         out["plain_forward"] = plain_leg(ctx, wl, lp, fwd_kernel_ms)
     if not args.no_order4:
         out["m70_order4"] = order4_leg(ctx, torch)
+    if not args.no_mcmc:
+        out["mcmc"] = mcmc_leg(ctx, torch, stream)
     if not args.no_accuracy:
         out["accuracy_study"] = accuracy_leg(ctx)
     if not args.no_dist:

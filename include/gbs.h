@@ -322,6 +322,31 @@ int gbs_plan_tune(gbs_ctx *ctx, gbs_plan *plan, int what, int32_t *params);
  * with the sectors' shares of the estimate. */
 int gbs_plan_info(gbs_plan *plan, double *rho, double *rconv, int32_t *K, int32_t *nsectors, double *err);
 
+/*
+ * gbs_mcmc_step_dev: one Metropolis-Hastings step (Metropolis et al. 1953,
+ * Hastings 1970) of P chains of click patterns whose target is the order-j
+ * estimate p_hat of the plan's order (Discussion: the approximate
+ * probabilities as the basis of a Markov chain Monte Carlo sampler).  Chain p
+ * is row p of the plan (made by gbs_plan_create from the chains' initial
+ * patterns, not frozen) and keeps its number of clicks n_p.  Per step and
+ * chain, from three uniforms u in [0, 1): the clicked mode at position
+ * floor(u[3p] n_p) of the row is swapped for the k-th unclicked mode in
+ * increasing order, k = floor(u[3p+1] (M - n_p)) (a symmetric proposal; rows
+ * with n_p = 0 or M do not move); log p_hat of every proposal is computed on
+ * the plan (the plan's copy of the rows is overwritten with the proposals);
+ * the proposal is accepted when its log p_hat is >= the current one or
+ * u[3p+2] < exp(difference), rejected when its estimate failed (NaN).
+ * Device arrays, stream-ordered: u_dev[3P] (caller-drawn uniforms),
+ * modes_dev[offsets[P]] the chains' current rows (the plan's offsets,
+ * strictly ascending modes; in/out), logp_dev[P] their log p_hat (in/out; from
+ * gbs_prob_approx_dev on the initial rows), accepted_dev[P] (nullable; 1 where
+ * the chain moved, 0 where not, -1 where its row is malformed: modes not
+ * strictly ascending in [0, M); such a chain never moves).  Errors: GBS_E_STATE for a frozen plan or a plan of
+ * another context or model size, GBS_E_INVAL for NULL arrays.
+ */
+int gbs_mcmc_step_dev(gbs_ctx *ctx, gbs_plan *plan, const double *u_dev, int32_t *modes_dev, double *logp_dev,
+                      int32_t *accepted_dev);
+
 /* Per-kernel timing.  With on = 1, every later launch on the context is
  * bracketed by HIP events recorded on the context's stream.  gbs_timing
  * synchronises the stream, writes the summed milliseconds per kernel group

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgbs.so")
-SOURCES = ["capi.hip", "model.hip", "approx.hip", "exact.hip", "grad.hip", "eig.hip", "plain.hip"]
+SOURCES = ["capi.hip", "model.hip", "approx.hip", "exact.hip", "grad.hip", "eig.hip", "plain.hip", "mcmc.hip"]
 # double-double code must not be contracted across statements
 NO_CONTRACT = {"model.hip", "exact.hip"}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -896,6 +896,29 @@ int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, double *logp_
     return rc;
 }
 
+}  // extern "C"
+
+// mcmc.hip: one Metropolis-Hastings step of the chains held in modes (CSR rows
+// of the plan's offsets), their log p_hat in logp; proposals evaluated on the
+// plan
+int mcmc_step(gbs_ctx *ctx, gbs_plan *plan, const double *u, int32_t *modes, double *logp, int32_t *accepted);
+
+extern "C" {
+
+int gbs_mcmc_step_dev(gbs_ctx *ctx, gbs_plan *pl, const double *u_dev, int32_t *modes_dev, double *logp_dev,
+                      int32_t *accepted_dev)
+{
+    if (!ctx || !pl) return GBS_E_INVAL;
+    if (pl->ctx != ctx) return set_err(ctx, GBS_E_STATE, "plan belongs to another context");
+    if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
+    if (ctx->model.M != pl->M) return set_err(ctx, GBS_E_STATE, "plan was made for a model of another size M");
+    if (pl->frozen) return set_err(ctx, GBS_E_STATE, "the chains need a plan that is not frozen (new rows every step)");
+    if (pl->whole) return set_err(ctx, GBS_E_INVAL, "not a plan of click patterns");
+    if (pl->P > 0 && (!u_dev || !modes_dev || !logp_dev)) return set_err(ctx, GBS_E_INVAL, "NULL device array");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    return mcmc_step(ctx, pl, u_dev, modes_dev, logp_dev, accepted_dev);
+}
+
 int gbs_click_distribution(gbs_ctx *ctx, int order, int nk, const int32_t *ks, double *p_n, double *p_k,
                            int32_t *status)
 {

@@ -26,7 +26,8 @@ EXPORTS = ["gbs_create", "gbs_destroy", "gbs_last_error", "gbs_set_model", "gbs_
            "gbs_prob_approx_plain", "gbs_plan_get_params", "gbs_plan_set_params", "gbs_plan_tune",
            "gbs_plan_create", "gbs_plan_destroy", "gbs_plan_freeze", "gbs_prob_approx_dev",
            "gbs_grad", "gbs_grad_dev", "gbs_plan_info", "gbs_set_timing", "gbs_timing",
-           "gbs_stream", "gbs_click_distribution", "gbs_prob_exact_dev", "gbs_prob_exact_dev_noalloc"]
+           "gbs_stream", "gbs_click_distribution", "gbs_prob_exact_dev", "gbs_prob_exact_dev_noalloc",
+           "gbs_mcmc_step_dev"]
 TIMING_GROUPS = ["model", "row_setup", "work_queue", "contour_clusters", "dft_fit", "exact",
                  "adjoint_fit_dft", "adjoint_contour_clusters", "adjoint_rows_scatter",
                  "adjoint_model", "second_pass"]
@@ -81,6 +82,7 @@ def load(path: str = LIB_PATH):
         "gbs_click_distribution": ([vp, ip, ip, i32p, dp, dp, i32p], ip),
         "gbs_prob_exact_dev": ([vp, ip, i32p, i32p, ip, dp, dp, dp, i32p], ip),
         "gbs_prob_exact_dev_noalloc": ([vp, ip, i32p, i32p, ip, dp, dp, dp, i32p], ip),
+        "gbs_mcmc_step_dev": ([vp, vp, dp, i32p, dp, i32p], ip),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -122,8 +124,8 @@ def _dptr(t, dtype: str = None, numel: Optional[int] = None, name: str = "tensor
 
 
 class Plan:
-    def __init__(self, ctx: "Context", handle: ctypes.c_void_p, P: int):
-        self.ctx, self.handle, self.P = ctx, handle, P
+    def __init__(self, ctx: "Context", handle: ctypes.c_void_p, P: int, nnz: int = 0):
+        self.ctx, self.handle, self.P, self.nnz = ctx, handle, P, nnz
 
     def freeze(self, on: bool = True):
         self.ctx._check(load().gbs_plan_freeze(self.handle, int(on)))
@@ -288,7 +290,7 @@ class Context:
         h = ctypes.c_void_p()
         self._check(load().gbs_plan_create(self.handle, len(off) - 1, _ptr(off), _ptr(mod), order,
                                            prec, ctypes.byref(h)))
-        return Plan(self, h, len(off) - 1)
+        return Plan(self, h, len(off) - 1, int(off[-1]) if len(off) else 0)
 
     def gbs_prob_approx_dev(self, plan: Plan, logp_dev, status_dev=None):
         return self._check(load().gbs_prob_approx_dev(self.handle, plan.handle,
@@ -304,6 +306,16 @@ class Context:
         self._check(load().gbs_grad(self.handle, P, _ptr(off), _ptr(mod), order, prec,
                                     _ptr(_f64(dL_dlogp)), _ptr(lp), _ptr(gr), _ptr(ge), _ptr(st)))
         return dict(logp=lp, grad_r=gr, grad_eta=ge, status=st)
+
+    def gbs_mcmc_step_dev(self, plan: Plan, u_dev, modes_dev, logp_dev, accepted_dev=None):
+        """One Metropolis-Hastings step of the plan's chains (device arrays:
+        uniforms float64[3P], the chains' CSR modes int32 (in/out), their
+        log p_hat float64[P] (in/out), accepted int32[P] or None)."""
+        P = plan.P
+        return self._check(load().gbs_mcmc_step_dev(self.handle, plan.handle, _dptr(u_dev, "float64", 3 * P, "u"),
+                                                    _dptr(modes_dev, "int32", plan.nnz, "modes"),
+                                                    _dptr(logp_dev, "float64", P, "logp"),
+                                                    _dptr(accepted_dev, "int32", P, "accepted")))
 
     def gbs_grad_dev(self, plan: Plan, dl_dev, logp_dev, grad_r_dev, grad_eta_dev, status_dev=None):
         P, M, f = plan.P, self.M, "float64"

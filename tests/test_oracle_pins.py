@@ -428,3 +428,49 @@ def test_reference_gradient_product_state_closed_form():
     assert val == pytest.approx(np.sum(np.log(np.where(click, 1 - P0, P0))), abs=1e-12)
     assert np.allclose(gr, dlog * dP0_dr, rtol=1e-9, atol=1e-12)
     assert np.allclose(ge, dlog * dP0_de, rtol=1e-9, atol=1e-12)
+
+
+# ------------------------------------------------- Metropolis-Hastings chains (Discussion)
+def test_mcmc_swap_proposal_is_symmetric():
+    """Every swap neighbour of a pattern is drawn by exactly one cell of the
+    (position, unclicked mode) grid of uniforms, and the reverse swap by exactly
+    one cell from the neighbour: the proposal is symmetric, so the Metropolis
+    ratio is the ratio of the targets."""
+    import itertools
+    from oracle import mcmc
+    M, n = 6, 2
+    grid = [((i + 0.5) / n, (k + 0.5) / (M - n)) for i in range(n) for k in range(M - n)]
+    for row in itertools.combinations(range(M), n):
+        props = [tuple(mcmc.propose(list(row), M, a, b)) for a, b in grid]
+        assert len(set(props)) == n * (M - n)
+        for prop in props:
+            assert len(set(prop) ^ set(row)) == 2 and list(prop) == sorted(prop)
+            back = [tuple(mcmc.propose(list(prop), M, a, b)) for a, b in grid]
+            assert back.count(row) == 1
+
+
+def test_mcmc_chain_converges_to_the_target():
+    """One chain on the 15 two-click patterns of a 6-mode lossy model, target
+    the exact p, 200000 steps: its visit frequencies match p restricted to two
+    clicks, normalised (total variation < 0.02; the statistical spread is
+    about 0.005)."""
+    import itertools
+    from oracle import mcmc
+    M = 6
+    U, r, eta = small_model(M, 41, r_range=(0.6, 1.3), eta_range=(0.4, 0.9))
+    Q = model.q_matrix(model.covariance(U, r, eta))
+    pats = [tuple(c) for c in itertools.combinations(range(M), 2)]
+    lp = {c: float(np.log(exact.prob_exact_direct(Q, list(c))[0])) for c in pats}
+    rng = np.random.default_rng([SEED_ROOT, 77])
+    row, cur = [0, 1], lp[(0, 1)]
+    seen = {c: 0 for c in pats}
+    steps = 200000
+    u = rng.random((steps, 3))
+    for s in range(steps):
+        rows, lps, _, _ = mcmc.mh_step([row], M, u[s], [cur], lambda c: lp[tuple(c)])
+        row, cur = rows[0], lps[0]
+        seen[tuple(row)] += 1
+    p = np.array([np.exp(lp[c]) for c in pats])
+    p /= p.sum()
+    f = np.array([seen[c] for c in pats]) / steps
+    assert 0.5 * np.abs(f - p).sum() < 0.02, 0.5 * np.abs(f - p).sum()
