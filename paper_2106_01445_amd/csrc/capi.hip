@@ -236,16 +236,20 @@ int plan_units(gbs_ctx *ctx, gbs_plan *pl)
     return 0;
 }
 
+long long adj_pair_scratch(int n);
+
 // Gradient workspace of a plan, allocated on first use.
 int adj_workspace(gbs_ctx *ctx, gbs_plan *pl)
 {
     if (pl->have_adj) return 0;
     const int P = pl->P, M = pl->M, order = pl->order;
-    const int chunks = (GBS_QCAP + 63) / 64;
+    const int chunks_s = (GBS_QCAP + GBS_ADJ_CHUNK - 1) / GBS_ADJ_CHUNK;
+    const int chunks_b = (GBS_QCAP + GBS_ADJ_CHUNK_BIG - 1) / GBS_ADJ_CHUNK_BIG;
+    const int chunks = pl->nbig > 0 ? std::max(chunks_s, chunks_b) : chunks_s;
     size_t rtot = 0;
     for (int p = 0; p < P; ++p) {
         const size_t N = 2 * (size_t)pl->h_n[p];
-        rtot += chunks * (N * (N + 1) / 2) * (pl->h_n[p] > GBS_NSMALL ? 1 : GBS_RSLOTS);
+        rtot += (N * (N + 1) / 2) * (pl->h_n[p] > GBS_NSMALL ? chunks_b : chunks_s * GBS_RSLOTS);
     }
     const size_t D = 2 * (size_t)M;
     int e = 0;
@@ -259,10 +263,12 @@ int adj_workspace(gbs_ctx *ctx, gbs_plan *pl)
     e = e ? e : dev_alloc(ctx, &pl->d_qitmp, D * D);
     if (!pl->d_grad) e = e ? e : dev_alloc(ctx, &pl->d_grad, D);
     if (pl->nbig > 0) {
-        // larger rows: M(w), the pair blocks of Z(w) at order <= 2 and Z V, per
-        // workgroup
+        // larger rows, per workgroup: at order 2 the pair blocks of Z(w) as
+        // 16 x 16 planes; otherwise M(w), the pair blocks of Z(w) at order 1 and
+        // Z V
         const long long nb = pl->max_n, npb = nb * (nb - 1) / 2;
-        pl->ascr_stride = 3 * nb + 4 * npb + (order <= 2 ? 4 * npb : 0) + 2 * nb * (32 * ((2 * nb + 31) / 32));
+        pl->ascr_stride = order == 2 ? adj_pair_scratch((int)nb)
+                                     : 3 * nb + 4 * npb + (order <= 1 ? 4 * npb : 0) + 2 * nb * (32 * ((2 * nb + 31) / 32));
         pl->ascr_blocks = 2 * ctx->num_cu;
         e = e ? e : dev_alloc(ctx, &pl->d_ascr, (size_t)pl->ascr_blocks * pl->ascr_stride);
     }

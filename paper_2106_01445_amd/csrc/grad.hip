@@ -22,8 +22,13 @@
 //                  neighbouring lanes over different blocks of Z(w)),
 //                  Z(w) by LDS atomics, V^T Z V on the matrix cores (rows up to
 //                  40 clicks: column units, each wavefront's share of R in
-//                  registers over the item; larger rows: Y = Z V into an HBM
-//                  panel, then X = V^T Y, R read-modified-written per point)
+//                  registers over the item; larger rows at orders 1, 3, 4:
+//                  Y = Z V into an HBM panel, then X = V^T Y, R
+//                  read-modified-written per point)
+//   k_adj_pairs_big  larger rows at order 2: M(w) never stored, each pair's
+//                  block of Z(w) written once, R's tiles formed from 16-row
+//                  blocks of Z with Z V kept in the accumulators
+//                  (k_v_transpose first lays out V's transposed copy)
 //   k_adj_reduce   per row: sum of the items' R in a fixed order, the
 //                  contour-independent terms, A_bar = V R V^T, added into the
 //                  adjoint of Q^{-1} at the row's mode pairs (global atomics)
@@ -32,8 +37,10 @@
 #include "contour_common.h"
 
 #include <algorithm>
+#include <type_traits>
 
-#define ADJ_QCHUNK 64
+#define ADJ_QCHUNK GBS_ADJ_CHUNK
+static_assert(GBS_ADJ_CHUNK_BIG <= ADJ_QCHUNK, "one pass of points per item fits s_wq");
 
 namespace {
 
@@ -431,7 +438,8 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         };
         for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
         const int Qn = rp.K / 2 + 1;
-        const int q0 = ch * ADJ_QCHUNK, q1 = min(q0 + ADJ_QCHUNK, Qn);
+        constexpr int QCH = BIG ? GBS_ADJ_CHUNK_BIG : ADJ_QCHUNK;
+        const int q0 = ch * QCH, q1 = min(q0 + QCH, Qn);
         const int T = (N + 15) >> 4, KS = (N + 3) >> 2;
         // rows up to 40 clicks: this wavefront's share of R (its column unit's
         // tiles), summed over the item's points in registers
@@ -1035,6 +1043,485 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
 }
 
 // ---------------------------------------------------------------------------
+// k_v_transpose: for each larger row (perm[0..nbig)), its eigenvectors in the
+// other orientation, W[i 2n + k] = V[i][k] (Vt holds V[i][k] at k 2n + i), into
+// the row's work area of the eigen-decomposition (free after it), through
+// 32 x 33 LDS tiles, followed by 16 zero rows
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_v_transpose(const int *__restrict__ offsets,
+                                                     const int *__restrict__ perm,
+                                                     const long long *__restrict__ voff,
+                                                     const double *__restrict__ vt, double *__restrict__ wv)
+{
+    __shared__ double tile[32][33];
+    const int p = perm[blockIdx.x];
+    const int N = 2 * (offsets[p + 1] - offsets[p]);
+    const double *src = vt + voff[p];
+    double *dst = wv + 2 * voff[p];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int nt = (N + 31) / 32;
+    for (int t = 0; t < nt * nt; ++t) {
+        const int bi = t / nt, bk = t % nt;
+        // src rows k = 32 bk + ..., columns i = 32 bi + ...
+        for (int r = ty; r < 32; r += 8) {
+            const int k = 32 * bk + r, i = 32 * bi + tx;
+            tile[r][tx] = k < N && i < N ? src[(long)k * N + i] : 0.0;
+        }
+        __syncthreads();
+        for (int r = ty; r < 32; r += 8) {
+            const int i = 32 * bi + r, k = 32 * bk + tx;
+            if (i < N && k < N) dst[(long)i * N + k] = tile[tx][r];
+        }
+        __syncthreads();
+    }
+    // rows 2n .. 2n + 15 zero (read by the padded k-steps of Y = Z V; inside
+    // the row's 2 (2n)^2 area for 2n >= 16)
+    for (int e = threadIdx.x; e < 16 * N; e += blockDim.x) dst[(long)N * N + e] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// k_adj_pairs_big: the adjoint of rows above 40 clicks at order 2.  Per contour
+// point, with V read from L2 and nothing of M(w) stored:
+//  1. the 16 x 16 mode blocks (I, J), I <= J, of M(w) on the matrix cores, the
+//     four quadrant products x_a x_b, x_a p_b, p_a x_b, p_a p_b of a block in
+//     the same accumulator positions (the forward's scheme), after the mode
+//     diagonals M_aa (formed first on the vector units, into LDS);
+//  2. each lane's pairs (a, b) of a block straight from those registers:
+//     c_T M_TT^{-1} split into its off-diagonal 2x2 block, written once into
+//     this workgroup's scratch as the block's four 16 x 16 planes of Z(w)
+//     (plane (q, q') holds Z(q_a, q'_b); tile-contiguous; a diagonal block
+//     holds both orders of its pairs), and its two diagonal 2x2 blocks, added
+//     with the singles' terms into Z's mode diagonals in LDS;
+//  3. R += Re[(w/2) d_k d_l (V^T Z V)_kl] by row blocks of Z (the 16 rows of
+//     one quadrature of one mode block, gathered into LDS, double-buffered so
+//     that one barrier per block suffices): each wavefront owns whole columns
+//     l of R (eigen index) and, per row block, forms its 16 x 16 tiles of
+//     Y = Z V in the accumulators, whose layout is the B operand layout of
+//     R's rank-16 update (A = (w/2) d_k V_rk), so Y never leaves the
+//     registers.  V comes from L2 in the transposed copy k_v_transpose makes
+//     (a wavefront's fetch of one k-step then reads four 128-byte runs), four
+//     k-steps per pass with the loads first.  A wavefront's R tiles stay in
+//     registers for the point and are then added into the item's R slot (one
+//     writer per entry).
+// Column l-tile lt goes to wavefront T-1-lt when lt >= T-8, else to lt+16-T
+// (longest-first on their MFMA counts, 2 ceil(2n/4) + 8(lt+1)): at most two
+// columns per wavefront; the first column's tile kt sits in racc[kt], the
+// second's in racc[16 - kt] (2T - 17 < 16 keeps them apart for 2n <= 256).
+// ---------------------------------------------------------------------------
+#define ADJ_PB_RMAX 17
+static_assert(GBS_MAX_N_APPROX <= 128, "2n <= 256: at most 16 column tiles");
+static_assert(4 * GBS_MAX_N_APPROX <= CONT_THREADS, "four threads per mode for M's mode diagonals");
+// (the k-steps of Y = Z V padded to a multiple of four: 16 ceil(2n/16) + 1)
+__host__ __device__ __forceinline__ int adj_pb_zs(int n) { return 16 * ((2 * n + 15) / 16) + 1; }
+// alpha (2n doubles), d and rz (2n each), M's and Z's mode diagonals (3n
+// each) and two 16-row blocks of Z (row stride adj_pb_zs(n)), complex
+__host__ __device__ __forceinline__ int adj_pb_lds(int n)
+{
+    return 8 * 2 * n + 16 * (2 * 2 * n + 6 * n + 32 * adj_pb_zs(n));
+}
+
+__global__ __launch_bounds__(CONT_THREADS) void k_adj_pairs_big(
+    const int *__restrict__ offsets, const long long *__restrict__ voff,
+    const double *__restrict__ alpha, const double *__restrict__ vt,
+    const double *__restrict__ wv, const RowPlan *__restrict__ rows, const int *__restrict__ items,
+    const int *__restrict__ q_end, int *__restrict__ q_head, const cplx *__restrict__ asw,
+    const long long *__restrict__ roff, double *__restrict__ rscr, cplx *__restrict__ ascr,
+    long long ascr_stride, const int *__restrict__ xq)
+{
+    constexpr int NW = CONT_THREADS / 64;
+    extern __shared__ __attribute__((aligned(16))) double sh[];
+    __shared__ int s_item;
+    __shared__ cplx s_g[3];
+    __shared__ cplx s_wq[ADJ_QCHUNK];
+    cplx *red = (cplx *)sh;  // [waves]
+    double *dyn = (double *)(red + NW + 8);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    cplx *Zt = ascr + blockIdx.x * ascr_stride;
+    for (;;) {
+        if (tid == 0) {
+            // this workgroup's XCD queue first, then the others (as k_adj_contour)
+            int it = -1;
+            for (int d = 0; d < GBS_NXCD && it < 0; ++d) {
+                const int x = (blockIdx.x + d) % GBS_NXCD;
+                if (atomicAdd(&q_head[x], 0) >= q_end[x]) continue;
+                const int h = atomicAdd(&q_head[x], 1);
+                if (h < q_end[x]) it = xq[q_end[GBS_NXCD + x] + h];
+            }
+            s_item = it;
+        }
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item < 0) break;
+        const int p = items[2 * item], ch = items[2 * item + 1];
+        const int o = offsets[p], n = offsets[p + 1] - o, N = 2 * n;
+        const RowPlan rp = rows[p];
+        const double *Vt = vt + voff[p];       // Vt[k N + i] = V[i][k]
+        const double *Wv = wv + 2 * voff[p];   // Wv[i N + k] = V[i][k]
+        const int TM = (n + 15) >> 4, T = (N + 15) >> 4, KS = (N + 3) >> 2, ZS = adj_pb_zs(n);
+        const int KS4 = 4 * T;  // k-steps of Y = Z V, padded (Zs and W zero past 2n)
+        double *al = dyn;
+        cplx *dk = (cplx *)(al + N);
+        cplx *rz = dk + N;
+        cplx *Md0 = rz + N, *Md1 = Md0 + n, *Md2 = Md1 + n;
+        cplx *Zd0 = Md2 + n, *Zd1 = Zd0 + n, *Zd2 = Zd1 + n;  // Z(x_a, x_a), Z(x_a, p_a), Z(p_a, p_a)
+        cplx *Zs0 = Zd0 + 3 * n, *Zs1 = Zs0 + 16 * ZS;
+        // plane (q, q') = 2 q + q' of mode block (I, J), I <= J
+        auto plane = [&](int I, int J, int pl) { return Zt + ((J * (J + 1) / 2 + I) * 4 + pl) * 256; };
+        const long long ro = roff[item];
+        for (int e = tid; e < N * (N + 1) / 2; e += CONT_THREADS) rscr[ro + e] = 0.0;
+        for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
+        // columns 2n .. 16 T - 1 of the row blocks stay zero (never gathered)
+        const int padc = 16 * T - N;
+        for (int idx = tid; idx < 32 * padc; idx += CONT_THREADS) {
+            const int r = idx / padc, c = N + idx % padc;
+            (r < 16 ? Zs0 : Zs1)[(r & 15) * ZS + c] = cmk(0.0, 0.0);
+        }
+        const int Qn = rp.K / 2 + 1;
+        const int q0 = ch * GBS_ADJ_CHUNK_BIG, q1 = min(q0 + GBS_ADJ_CHUNK_BIG, Qn);
+        if (tid < q1 - q0) s_wq[tid] = cscale(unit_root(q0 + tid, rp.K), rp.rho);
+        // this wavefront's columns of R (tiles 0..c1 in racc[0..c1], then 0..c2)
+        const int c1 = T - 1 - wid, c2 = wid + T - 16;
+
+        // the four quadrant products of mode block (I, J): lane holds the pairs
+        // (16 I + 4 e + lq, 16 J + l16), e = 0..3
+        auto quad = [&](int I, int J, dbl4 (&qq)[4][2]) {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) qq[h][0] = qq[h][1] = dbl4{0.0, 0.0, 0.0, 0.0};
+            const int ia = 16 * I + l16, jb = 16 * J + l16;
+#pragma unroll 2
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k = ks * 4 + lq;
+                const bool kok = k < N, aok = kok && ia < n, bok = kok && jb < n;
+                const cplx dl = dk[kok ? k : 0];
+                const double axl = Vt[aok ? k * N + ia : 0], apl = Vt[aok ? k * N + n + ia : 0];
+                const double bxl = Vt[bok ? k * N + jb : 0], bpl = Vt[bok ? k * N + n + jb : 0];
+                const double ax = aok ? axl : 0.0, ap = aok ? apl : 0.0;
+                const double bx = bok ? bxl : 0.0, bp = bok ? bpl : 0.0;
+                const double axr = ax * dl.re, axi = ax * dl.im, apr = ap * dl.re, api = ap * dl.im;
+                qq[0][0] = mfma4(axr, bx, qq[0][0]);
+                qq[0][1] = mfma4(axi, bx, qq[0][1]);
+                qq[1][0] = mfma4(axr, bp, qq[1][0]);
+                qq[1][1] = mfma4(axi, bp, qq[1][1]);
+                qq[2][0] = mfma4(apr, bx, qq[2][0]);
+                qq[2][1] = mfma4(api, bx, qq[2][1]);
+                qq[3][0] = mfma4(apr, bp, qq[3][0]);
+                qq[3][1] = mfma4(api, bp, qq[3][1]);
+            }
+        };
+        // the pairs of block (I, J) from its quadrant products: P = M_TT, T = {a, b},
+        // eliminated through M_aa (ia) and the Schur complement of b (ib);
+        // c_T P^{-1} = c_T [[ia + G ib G^T, -G ib], [-ib G^T, ib]], G = ia M_ab
+        auto pairs = [&](int I, int J, const dbl4 (&qq)[4][2], cplx g2, cplx &bs) {
+            const int b = 16 * J + l16;
+            cplx *t0 = plane(I, J, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int ra_ = 4 * e + lq, a = 16 * I + ra_;
+                if (!(a < b && b < n)) continue;
+                const cplx b00 = cmk(qq[0][0][e], qq[0][1][e]), b01 = cmk(qq[1][0][e], qq[1][1][e]);
+                const cplx b10 = cmk(qq[2][0][e], qq[2][1][e]), b11 = cmk(qq[3][0][e], qq[3][1][e]);
+                const cplx a00 = Md0[a], a01 = Md1[a], a11 = Md2[a];
+                const cplx ra = crsqrt_p(cfnma(a01, a01, cmul(a00, a11)));
+                const cplx ideta = cmul(ra, ra);
+                const cplx ia00 = cmul(a11, ideta), ia11 = cmul(a00, ideta);
+                const cplx ia01 = cneg(cmul(a01, ideta));
+                const cplx G00 = cfma(ia00, b00, cmul(ia01, b10));
+                const cplx G01 = cfma(ia00, b01, cmul(ia01, b11));
+                const cplx G10 = cfma(ia01, b00, cmul(ia11, b10));
+                const cplx G11 = cfma(ia01, b01, cmul(ia11, b11));
+                const cplx sb00 = csub(Md0[b], cfma(b00, G00, cmul(b10, G10)));
+                const cplx sb01 = csub(Md1[b], cfma(b00, G01, cmul(b10, G11)));
+                const cplx sb11 = csub(Md2[b], cfma(b01, G01, cmul(b11, G11)));
+                const cplx rb = crsqrt_p(cfnma(sb01, sb01, cmul(sb00, sb11)));
+                const cplx cp = cmul(g2, cmul(ra, rb));
+                bs = cadd(bs, cp);
+                const cplx idetb = cmul(rb, rb);
+                const cplx ib00 = cmul(sb11, idetb), ib11 = cmul(sb00, idetb);
+                const cplx ib01 = cneg(cmul(sb01, idetb));
+                // (G ib) rows: (H00, H01), (H10, H11)
+                const cplx H00 = cfma(ib00, G00, cmul(ib01, G01)), H01 = cfma(ib01, G00, cmul(ib11, G01));
+                const cplx H10 = cfma(ib00, G10, cmul(ib01, G11)), H11 = cfma(ib01, G10, cmul(ib11, G11));
+                const cplx pa00 = cadd(ia00, cfma(H00, G00, cmul(H01, G01)));
+                const cplx pa01 = cadd(ia01, cfma(H00, G10, cmul(H01, G11)));
+                const cplx pa11 = cadd(ia11, cfma(H10, G10, cmul(H11, G11)));
+                catomic(&Zd0[a], cmul(cp, pa00));
+                catomic(&Zd1[a], cmul(cp, pa01));
+                catomic(&Zd2[a], cmul(cp, pa11));
+                catomic(&Zd0[b], cmul(cp, ib00));
+                catomic(&Zd1[b], cmul(cp, ib01));
+                catomic(&Zd2[b], cmul(cp, ib11));
+                const cplx ncp = cneg(cp);
+                const cplx zxx = cmul(ncp, H00), zxp = cmul(ncp, H01), zpx = cmul(ncp, H10), zpp = cmul(ncp, H11);
+                const int at = ra_ * 16 + l16;
+                t0[at] = zxx;
+                t0[256 + at] = zxp;
+                t0[512 + at] = zpx;
+                t0[768 + at] = zpp;
+                if (I == J) {
+                    // Z(q_b, q'_a) = Z(q'_a, q_b)
+                    const int bt = l16 * 16 + ra_;
+                    t0[bt] = zxx;
+                    t0[256 + bt] = zpx;
+                    t0[512 + bt] = zxp;
+                    t0[768 + bt] = zpp;
+                }
+            }
+        };
+        // rows 16 I .. 16 I + 15 of quadrature qr (row block rbi = qr TM + I) of
+        // Z(w) into Zs (row stride ZS, columns in quadrature-major order); rows
+        // past n are zero
+        auto gather_z = [&](int rbi, cplx *Zs) {
+            const int qr = rbi >= TM ? 1 : 0, I = rbi - qr * TM;
+            for (int idx = tid; idx < 2 * TM * 256; idx += CONT_THREADS) {
+                const int cb = idx >> 8, wv = idx & 255;
+                const int qc = cb >= TM ? 1 : 0, J = cb - qc * TM;
+                // (below the diagonal the stored block is (J, I): walk it in its
+                // own row order)
+                const int r = J < I ? wv & 15 : wv >> 4, c = J < I ? wv >> 4 : wv & 15;
+                const int a = 16 * I + r, b = 16 * J + c;
+                if (b >= n) continue;
+                cplx v = cmk(0.0, 0.0);
+                if (a < n) {
+                    if (J < I)
+                        v = plane(J, I, 2 * qc + qr)[c * 16 + r];
+                    else if (J == I && r == c)
+                        v = Zd0[(qr + qc) * n + a];
+                    else
+                        v = plane(I, J, 2 * qr + qc)[r * 16 + c];
+                }
+                Zs[r * ZS + qc * n + b] = v;
+            }
+        };
+        __syncthreads();
+        for (int q = q0; q < q1; ++q) {
+            const cplx w = s_wq[q - q0];
+            for (int k = tid; k < N; k += CONT_THREADS) {
+                const double am1 = al[k] - 1.0;
+                const cplx z = cmk(fma(w.re, am1, 1.0), w.im * am1);
+                const cplx r = crsqrt_p(z);
+                dk[k] = cmul(r, r);
+                rz[k] = r;
+            }
+            for (int i = tid; i < 3 * n; i += CONT_THREADS) Zd0[i] = cmk(0.0, 0.0);
+            __syncthreads();
+            if (wid == 0) {
+                // G_0(w)/G_0(rho) = exp(log det A/2 - log G_0(rho)) prod_k z_k^{-1/2}
+                cplx pr = cmk(1.0, 0.0);
+                for (int k = lane; k < N; k += 64) pr = cmul(pr, rz[k]);
+                pr = cmul(warp_cprod(pr), cmk(exp(0.5 * rp.logdet_a - rp.log_g_rho), 0.0));
+                if (lane <= 2) s_g[lane] = cmul(asw[((long)p * 3 + lane) * GBS_QCAP + q], pr);
+            }
+            // M's mode-diagonal 2x2 blocks, sum_k V_ak V_bk d_k on the vector
+            // units, four partial sums per mode (threads 4a .. 4a + 3)
+            {
+                const int a = tid >> 2, part = tid & 3;
+                cplx m00 = cmk(0.0, 0.0), m01 = m00, m11 = m00;
+                if (a < n) {
+                    for (int k = part; k < N; k += 4) {
+                        const double vx = Vt[k * N + a], vp = Vt[k * N + n + a];
+                        const cplx d = dk[k];
+                        const double xx = vx * vx, xp = vx * vp, pp = vp * vp;
+                        m00.re = fma(xx, d.re, m00.re); m00.im = fma(xx, d.im, m00.im);
+                        m01.re = fma(xp, d.re, m01.re); m01.im = fma(xp, d.im, m01.im);
+                        m11.re = fma(pp, d.re, m11.re); m11.im = fma(pp, d.im, m11.im);
+                    }
+                }
+#pragma unroll
+                for (int off = 1; off < 4; off <<= 1) {
+                    m00.re += __shfl_xor(m00.re, off); m00.im += __shfl_xor(m00.im, off);
+                    m01.re += __shfl_xor(m01.re, off); m01.im += __shfl_xor(m01.im, off);
+                    m11.re += __shfl_xor(m11.re, off); m11.im += __shfl_xor(m11.im, off);
+                }
+                if (a < n && part == 0) {
+                    Md0[a] = m00;
+                    Md1[a] = m01;
+                    Md2[a] = m11;
+                }
+            }
+            __syncthreads();
+            // singles: Z_aa += c_a M_aa^{-1}, c_a = gamma_1 det(M_aa)^{-1/2}
+            cplx bsum = cmk(0.0, 0.0);
+            const cplx g1 = s_g[1], g2 = s_g[2];
+            for (int a = tid; a < n; a += CONT_THREADS) {
+                const cplx a00 = Md0[a], a01 = Md1[a], a11 = Md2[a];
+                const cplx r = crsqrt_p(cfnma(a01, a01, cmul(a00, a11)));
+                const cplx c = cmul(g1, r);
+                bsum = cadd(bsum, c);
+                const cplx cid = cmul(c, cmul(r, r));
+                catomic(&Zd0[a], cmul(cid, a11));
+                catomic(&Zd1[a], cneg(cmul(cid, a01)));
+                catomic(&Zd2[a], cmul(cid, a00));
+            }
+            // every mode block (I, J), I <= J: quadrant products, then its pairs
+            for (int u = wid; u < TM * (TM + 1) / 2; u += NW) {
+                int I, J;
+                upper_tile(u, I, J);
+                dbl4 qq[4][2];
+                quad(I, J, qq);
+                pairs(I, J, qq, g2, bsum);
+            }
+            bsum = warp_csum(bsum);
+            if (lane == 0) red[wid] = bsum;
+            __syncthreads();
+            cplx beta = s_g[0];
+            for (int i = 0; i < NW; ++i) beta = cadd(beta, red[i]);
+            const cplx hw = cscale(w, 0.5);
+            dbl4 racc[ADJ_PB_RMAX];
+#pragma unroll
+            for (int t = 0; t < ADJ_PB_RMAX; ++t) racc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+            const int l1 = 16 * c1 + l16, l2 = 16 * c2 + l16;
+            const bool l1ok = c1 >= 0 && l1 < N, l2ok = c2 >= 0 && l2 < N;
+            const cplx dl1 = l1ok ? dk[l1] : cmk(0.0, 0.0), dl2 = l2ok ? dk[l2] : cmk(0.0, 0.0);
+            gather_z(0, Zs0);
+            __syncthreads();
+            for (int rbi = 0; rbi < 2 * TM; ++rbi) {
+                const cplx *Zs = (rbi & 1) ? Zs1 : Zs0;
+                if (rbi + 1 < 2 * TM) gather_z(rbi + 1, (rbi & 1) ? Zs0 : Zs1);
+                const int qr = rbi >= TM ? 1 : 0, I = rbi - qr * TM;
+                const int rbase = qr * n + 16 * I, nrow = min(16, n - 16 * I);
+                if (c1 >= 0) {
+                    // Y(rows of the block, column tiles c1 and c2) = Z V over the
+                    // padded k-steps (Zs and W are zero past 2n; W's columns
+                    // past 2n hold finite values, met by d_l = 0 below)
+                    dbl4 y1r = {0.0, 0.0, 0.0, 0.0}, y1i = y1r, y2r = y1r, y2i = y1r;
+                    const double *w1 = Wv + lq * N + 16 * c1 + l16;
+                    const cplx *zrow = Zs + l16 * ZS + lq;
+                    if (c2 >= 0) {
+                        const double *w2 = Wv + lq * N + 16 * c2 + l16;
+                        for (int ks0 = 0; ks0 < KS4; ks0 += 4) {
+                            cplx z[4];
+                            double v1[4], v2[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                z[u] = zrow[4 * (ks0 + u)];
+                                v1[u] = w1[(long)4 * (ks0 + u) * N];
+                                v2[u] = w2[(long)4 * (ks0 + u) * N];
+                            }
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                y1r = mfma4(z[u].re, v1[u], y1r);
+                                y1i = mfma4(z[u].im, v1[u], y1i);
+                                y2r = mfma4(z[u].re, v2[u], y2r);
+                                y2i = mfma4(z[u].im, v2[u], y2i);
+                            }
+                        }
+                    } else {
+                        // one column: even and odd k-steps in separate
+                        // accumulators (four independent chains), summed after
+                        for (int ks0 = 0; ks0 < KS4; ks0 += 4) {
+                            cplx z[4];
+                            double v1[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                z[u] = zrow[4 * (ks0 + u)];
+                                v1[u] = w1[(long)4 * (ks0 + u) * N];
+                            }
+#pragma unroll
+                            for (int u = 0; u < 4; u += 2) {
+                                y1r = mfma4(z[u].re, v1[u], y1r);
+                                y1i = mfma4(z[u].im, v1[u], y1i);
+                                y2r = mfma4(z[u + 1].re, v1[u + 1], y2r);
+                                y2i = mfma4(z[u + 1].im, v1[u + 1], y2i);
+                            }
+                        }
+                        y1r += y2r;
+                        y1i += y2i;
+                        y2r = y2i = dbl4{0.0, 0.0, 0.0, 0.0};
+                    }
+                    // column factor d_l into Y: B = d_l Y_rl
+                    dbl4 b1r, b1i, b2r, b2i;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        b1r[e] = dl1.re * y1r[e] - dl1.im * y1i[e];
+                        b1i[e] = dl1.im * y1r[e] + dl1.re * y1i[e];
+                        b2r[e] = dl2.re * y2r[e] - dl2.im * y2i[e];
+                        b2i[e] = dl2.im * y2r[e] + dl2.re * y2i[e];
+                    }
+                    // R(kt, l) += Re[(g_k V_rk) B_rl], g_k = (w/2) d_k, for the
+                    // tiles kt <= l, two row tiles kt, kt + 1 at a time so that
+                    // up to four accumulators interleave.  V's block rows come
+                    // from the transposed copy unmasked: rows past the block's
+                    // end meet zero rows of Y, columns past 2n a zero g_k.
+                    const double *wa = Wv + (long)(rbase + lq) * N + l16;
+#pragma unroll
+                    for (int kt = 0; kt < 16; kt += 2) {
+                        if (kt > c1) continue;
+                        double ar0[4], ai0[4], ar1[4], ai1[4];
+                        {
+                            const int k0 = 16 * kt + l16, k1 = k0 + 16;
+                            const cplx g0 = k0 < N ? cmul(hw, dk[k0]) : cmk(0.0, 0.0);
+                            const cplx g1 = k1 < N ? cmul(hw, dk[k1]) : cmk(0.0, 0.0);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const double v0 = wa[(long)4 * e * N + 16 * kt];
+                                const double v1 = wa[(long)4 * e * N + 16 * kt + 16];
+                                ar0[e] = g0.re * v0;
+                                ai0[e] = -g0.im * v0;
+                                ar1[e] = g1.re * v1;
+                                ai1[e] = -g1.im * v1;
+                            }
+                        }
+                        auto upd = [&](auto U1, auto V0, auto V1) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                racc[kt] = mfma4(ar0[e], b1r[e], racc[kt]);
+                                if constexpr (decltype(U1)::value) racc[kt + 1] = mfma4(ar1[e], b1r[e], racc[kt + 1]);
+                                if constexpr (decltype(V0)::value) racc[16 - kt] = mfma4(ar0[e], b2r[e], racc[16 - kt]);
+                                if constexpr (decltype(V1)::value) racc[15 - kt] = mfma4(ar1[e], b2r[e], racc[15 - kt]);
+                                racc[kt] = mfma4(ai0[e], b1i[e], racc[kt]);
+                                if constexpr (decltype(U1)::value) racc[kt + 1] = mfma4(ai1[e], b1i[e], racc[kt + 1]);
+                                if constexpr (decltype(V0)::value) racc[16 - kt] = mfma4(ai0[e], b2i[e], racc[16 - kt]);
+                                if constexpr (decltype(V1)::value) racc[15 - kt] = mfma4(ai1[e], b2i[e], racc[15 - kt]);
+                            }
+                        };
+                        using T_ = std::true_type;
+                        using F_ = std::false_type;
+                        // (kt <= c2 implies kt + 1 <= c1, as c2 < c1)
+                        if (kt + 1 > c1)
+                            upd(F_{}, F_{}, F_{});
+                        else if (kt > c2)
+                            upd(T_{}, F_{}, F_{});
+                        else if (kt + 1 > c2)
+                            upd(T_{}, T_{}, F_{});
+                        else
+                            upd(T_{}, T_{}, T_{});
+                    }
+                }
+                __syncthreads();
+            }
+            // this wavefront's R tiles (+ the diagonal beta terms) into the item's slot
+#pragma unroll 1
+            for (int s = 0; s < 2; ++s) {
+                const int lt = s == 0 ? c1 : c2;
+                if (lt < 0) continue;
+                const int jj = 16 * lt + l16;
+#pragma unroll
+                for (int t = 0; t < ADJ_PB_RMAX; ++t) {
+                    const int kt = s == 0 ? t : 16 - t;
+                    if (kt < 0 || kt > lt) continue;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int ii = 16 * kt + 4 * e + lq;
+                        if (ii > jj || jj >= N) continue;
+                        double add = racc[t][e];
+                        if (ii == jj) {
+                            const double dr = 1.0 / (1.0 + rp.rho * (al[ii] - 1.0));
+                            const cplx tt = cmk(0.5 * rp.rho * dr - hw.re * dk[ii].re + hw.im * dk[ii].im,
+                                                -(hw.re * dk[ii].im + hw.im * dk[ii].re));
+                            add += beta.re * tt.re - beta.im * tt.im;
+                        }
+                        rscr[ro + (long long)jj * (jj + 1) / 2 + ii] += add;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_adj_items: backward work items (row, chunk of ADJ_QCHUNK points) and the
 // offsets of their R scratch
 // ---------------------------------------------------------------------------
@@ -1055,7 +1542,8 @@ __global__ __launch_bounds__(1024) void k_adj_items(int P, int nbig, const int *
         const int n = offsets[p + 1] - offsets[p];
         const RowPlan &rp = rows[p];
         if (n == 0 || rp.status != 0 || rp.K <= 0) return 0;
-        return (rp.K / 2 + 1 + ADJ_QCHUNK - 1) / ADJ_QCHUNK;
+        const int qc = n > GBS_NSMALL ? GBS_ADJ_CHUNK_BIG : ADJ_QCHUNK;
+        return (rp.K / 2 + 1 + qc - 1) / qc;
     };
     auto rsz = [&](int i) {
         const int p = perm[i];
@@ -1229,7 +1717,7 @@ __global__ __launch_bounds__(256) void k_adj_reduce_big(int M, const int *__rest
     if (n == 0 || it0 < 0 || rp.status != 0 || (status[p] & GBS_PS_FAILED) || !isfinite(dl[p]) ||
         dl[p] == 0.0)
         return;
-    const int nit = (rp.K / 2 + 1 + ADJ_QCHUNK - 1) / ADJ_QCHUNK;
+    const int nit = (rp.K / 2 + 1 + GBS_ADJ_CHUNK_BIG - 1) / GBS_ADJ_CHUNK_BIG;
     const long long vo = voff[p];
     const double *Vt = vt + vo;          // Vt[k*N + i] = V[i][k]
     double *R = wbig + 2 * vo, *T = R + (long)N * N;
@@ -1344,6 +1832,10 @@ __global__ void k_zero(long n, double *x)
         x[i] = 0.0;
 }
 
+}  // namespace
+long long adj_pair_scratch(int n);
+namespace {
+
 template <int ORDER>
 int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *status,
                    double *grad_r, double *grad_eta)
@@ -1360,7 +1852,30 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
     ts = timer_begin(ctx, TG_ADJ_CLUSTER);
     hipLaunchKernelGGL(k_adj_items, dim3(1), dim3(1024), 0, st, P, pl->nbig, pl->d_offsets, pl->d_perm,
                        pl->d_rows, pl->d_aitems, pl->d_roff, pl->d_ritem0, pl->d_counter, pl->d_axq);
-    if (pl->nbig > 0) {
+    if constexpr (ORDER == 2) {
+        if (pl->nbig > 0) {
+            // larger rows at order 2: M(w) never stored, the pair blocks of Z(w) in
+            // this workgroup's scratch, 16-row blocks of Z(w) in LDS
+            const void *fn = (const void *)k_adj_pairs_big;
+            int lds_static = 0;
+            if (int rc = func_static_lds(ctx, fn, &lds_static)) return rc;
+            const int lds_b = adj_fixed() + adj_pb_lds(nmax);
+            if (lds_b + lds_static > ctx->lds_per_block)
+                return set_err(ctx, GBS_E_INVAL, "rows too large for the gradient kernel's LDS");
+            if (adj_pair_scratch(nmax) > pl->ascr_stride)
+                return set_err(ctx, GBS_E_INVAL, "gradient scratch smaller than the rows need");
+            int occ = 1;
+            if (int rc = func_lds_limit(ctx, fn, lds_b)) return rc;
+            if (int rc = func_occupancy(ctx, fn, CONT_THREADS, lds_b, &occ)) return rc;
+            int grid = std::min(occ * ctx->num_cu, pl->ascr_blocks);
+            hipLaunchKernelGGL(k_v_transpose, dim3(pl->nbig), dim3(256), 0, st, pl->d_offsets, pl->d_perm,
+                               pl->d_voff, pl->d_v, pl->d_wbig);
+            hipLaunchKernelGGL(k_adj_pairs_big, dim3(grid), dim3(CONT_THREADS), lds_b, st, pl->d_offsets,
+                               pl->d_voff, pl->d_alpha, pl->d_v, pl->d_wbig, pl->d_rows, pl->d_aitems,
+                               pl->d_counter + 8 + GBS_NXCD, pl->d_counter + 8, pl->d_asw, pl->d_roff,
+                               pl->d_rscr, pl->d_ascr, pl->ascr_stride, pl->d_axq);
+        }
+    } else if (pl->nbig > 0) {
         // larger rows: V and M(w) in HBM, Z(w) (all of it at order 3, its diagonal
         // blocks and a 32-row block of it otherwise) in LDS
         const void *fn = (const void *)k_adj_contour<ORDER, true>;
@@ -1432,6 +1947,14 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
 }  // namespace
 
 int adj_workspace(gbs_ctx *ctx, gbs_plan *pl);
+
+// complex entries of k_adj_pairs_big's per-workgroup scratch for rows of up to
+// n clicks: the four 16 x 16 planes of each upper 16 x 16 mode block of Z(w)
+long long adj_pair_scratch(int n)
+{
+    const long long tm = (n + 15) / 16;
+    return tm * (tm + 1) / 2 * 4 * 256;
+}
 
 int approx_backward(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, const int32_t *status_dev,
                     double *grad_r_dev, double *grad_eta_dev)

@@ -26,6 +26,11 @@
 // [8..15] heads, [16..23] lengths and [24..31] offsets of the backward queues
 // of the larger rows, one per XCD
 #define GBS_NXCD 8
+// contour points per adjoint work item: rows up to GBS_NSMALL clicks, larger rows
+#define GBS_ADJ_CHUNK 64
+#ifndef GBS_ADJ_CHUNK_BIG
+#define GBS_ADJ_CHUNK_BIG 64
+#endif
 #define GBS_NCOUNTER (8 + 3 * GBS_NXCD)
 #define GBS_CLUSTER_SEG 3      // triples per cluster work unit at order 3 (default)
 
