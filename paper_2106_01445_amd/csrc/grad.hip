@@ -1181,7 +1181,8 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_pairs_big(
         const int Qn = rp.K / 2 + 1;
         const int q0 = ch * GBS_ADJ_CHUNK_BIG, q1 = min(q0 + GBS_ADJ_CHUNK_BIG, Qn);
         if (tid < q1 - q0) s_wq[tid] = cscale(unit_root(q0 + tid, rp.K), rp.rho);
-        // this wavefront's columns of R (tiles 0..c1 in racc[0..c1], then 0..c2)
+        // this wavefront's columns of R (none when negative): column c1's tile kt
+        // in racc[kt], column c2's in racc[16 - kt]
         const int c1 = T - 1 - wid, c2 = wid + T - 16;
 
         // the four quadrant products of mode block (I, J): lane holds the pairs

@@ -184,3 +184,56 @@ def test_capped_rows_in_golden_set():
     """The forward golden set holds at least five 144-mode rows whose radius is
     capped (they are checked with the whole batch above)."""
     assert sum(1 for c in golden(5) if c.get("capped_radius")) >= 5
+
+
+def test_grad_order2_up_to_128_clicks(gpu_ctx):
+    """Order 2, the 144-mode model, rows of 49, 97, 121 and 128 clicks (2n
+    from 98 to 256: one to two column tiles of R per wavefront of the order-2
+    adjoint, up to its 17 register tiles): the adjoint against central
+    differences of the GPU forward on the frozen plan along random directions
+    in (r, eta)."""
+    import torch
+    from paper_2106_01445_amd import gbs as gb
+    wl = make_workload(5)
+    M = wl.M
+    rng = np.random.default_rng(88)
+    rows = [sorted(rng.choice(M, size=k, replace=False).tolist()) for k in (49, 97, 121, 128)]
+    off, mod = csr_from_lists(rows)
+    P = len(rows)
+    gpu_ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    plan = gpu_ctx.gbs_plan_create(off, mod, 2)
+    dev = torch.device("cuda")
+    ure = torch.tensor(np.ascontiguousarray(wl.U.real), device=dev)
+    uim = torch.tensor(np.ascontiguousarray(wl.U.imag), device=dev)
+    logp = torch.empty(P, dtype=torch.float64, device=dev)
+    st = torch.empty(P, dtype=torch.int32, device=dev)
+
+    def f(rr, ee):
+        gpu_ctx.gbs_set_model_dev(ure, uim, torch.tensor(rr, device=dev), torch.tensor(ee, device=dev))
+        gpu_ctx.gbs_prob_approx_dev(plan, logp, st)
+        torch.cuda.synchronize()
+        assert int((st & gb.GBS_PS_FAILED).sum()) == 0
+        return logp.cpu().numpy().copy()
+
+    w = np.array([0.8, 1.2, 0.9, 1.1])
+    f0 = f(wl.r, wl.eta)
+    assert np.all(np.isfinite(f0))
+    plan.freeze(True)
+    dl = torch.tensor(w, device=dev)
+    gr = torch.empty(M, dtype=torch.float64, device=dev)
+    ge = torch.empty(M, dtype=torch.float64, device=dev)
+    gpu_ctx.gbs_set_model_dev(ure, uim, torch.tensor(wl.r, device=dev), torch.tensor(wl.eta, device=dev))
+    gpu_ctx.gbs_grad_dev(plan, dl, logp, gr, ge, st)
+    torch.cuda.synchronize()
+    g = np.concatenate([gr.cpu().numpy(), ge.cpu().numpy()])
+    assert np.all(np.isfinite(g))
+    mask = np.concatenate([wl.r > 0, np.ones(M, bool)])
+    h = 1e-5
+    for _ in range(2):
+        v = rng.standard_normal(2 * M) * mask
+        v /= np.linalg.norm(v)
+        xp = np.concatenate([wl.r, wl.eta]) + h * v
+        xm = np.concatenate([wl.r, wl.eta]) - h * v
+        fd = (w @ f(xp[:M], xp[M:]) - w @ f(xm[:M], xm[M:])) / (2 * h)
+        assert abs(g @ v - fd) < 1e-4 * np.linalg.norm(g), (g @ v, fd)
+    plan.close()
