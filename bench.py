@@ -352,7 +352,57 @@ def mcmc_leg(ctx, torch, stream):
                                 "acceptance": float(tot.item()) / (steps * wl.P),
                                 "finite_logp": bool(torch.isfinite(lp).all().item())}
         plan.close()
+    out["two_stage_m20"] = two_stage_leg(ctx, torch, stream)
     return out
+
+
+def two_stage_leg(ctx, torch, stream):
+    """Two-stage chains (gbs_mcmc_da_step_dev: the order-3 estimate screens
+    each swap proposal, the exact probability corrects the survivors, target
+    the exact p): 4096 chains on the 20-mode device, started from its batch's
+    first 4096 patterns (6-14 clicks); 4 steps timed after one; the shares of
+    proposals rejected by the estimate and by the exact correction."""
+    from workloads import make_workload
+    wl = make_workload(2)
+    ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(2107)
+    plan = ctx.gbs_plan_create(wl.offsets, wl.modes, 3)
+    nmax = int(np.diff(wl.offsets).max())
+    with torch.cuda.stream(stream):
+        off = torch.tensor(wl.offsets, dtype=torch.int32, device=dev)
+        modes = torch.tensor(wl.modes, dtype=torch.int32, device=dev)
+        lh = torch.empty(wl.P, dtype=torch.float64, device=dev)
+        le = torch.empty(wl.P, dtype=torch.float64, device=dev)
+        pe = torch.empty(wl.P, dtype=torch.float64, device=dev)
+        st = torch.empty(wl.P, dtype=torch.int32, device=dev)
+        acc = torch.empty(wl.P, dtype=torch.int32, device=dev)
+        cnt = torch.zeros(3, dtype=torch.int64, device=dev)
+        u = torch.empty(4 * wl.P, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    ctx.gbs_prob_approx_dev(plan, lh)
+    ctx.gbs_prob_exact_dev(off, modes, nmax, pe, le, None, st)
+    steps = 4
+    for s in range(steps + 1):
+        if s == 1:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            u.uniform_(0.0, 1.0, generator=gen)
+        ctx.gbs_mcmc_da_step_dev(plan, u, modes, lh, le, acc)
+        if s >= 1:
+            with torch.cuda.stream(stream):
+                for c in range(3):
+                    cnt[c] += (acc == c).sum()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    c = cnt.cpu().numpy() / (steps * wl.P)
+    plan.close()
+    return {"chains": wl.P, "clicks": "6-14 (fixed per chain)", "screen_order": 3, "ms_per_step": ms,
+            "chain_steps_per_s": wl.P / (ms * 1e-3), "moved": float(c[1]),
+            "rejected_by_estimate": float(c[0]), "rejected_by_exact": float(c[2]),
+            "finite": bool((torch.isfinite(lh).all() & torch.isfinite(le).all()).item())}
 
 
 def accuracy_leg(ctx):

@@ -347,6 +347,32 @@ int gbs_plan_info(gbs_plan *plan, double *rho, double *rconv, int32_t *K, int32_
 int gbs_mcmc_step_dev(gbs_ctx *ctx, gbs_plan *plan, const double *u_dev, int32_t *modes_dev, double *logp_dev,
                       int32_t *accepted_dev);
 
+/*
+ * gbs_mcmc_da_step_dev: one two-stage (delayed-acceptance) Metropolis-Hastings
+ * step (Christen & Fox 2005) of P chains whose target is the exact p, with the
+ * order-j estimate as the proposal filter (Discussion: the approximation as
+ * the proposal distribution of a Markov chain Monte Carlo sampler).  The
+ * swap proposal is that of gbs_mcmc_step_dev; the first stage accepts it with
+ * min(1, p_hat(new) / p_hat(old)), and only proposals that pass get an exact
+ * evaluation (the exact path of gbs_prob_exact_dev, on the packed rows), which
+ * accepts them with min(1, [p(new) p_hat(old)] / [p(old) p_hat(new)]): the
+ * chains' stationary distribution is the exact p restricted to n_p clicks.
+ * Device arrays, stream-ordered: u_dev[4P] (caller-drawn uniforms: swap,
+ * swap, first stage, second stage), modes_dev (as gbs_mcmc_step_dev; in/out),
+ * logp_hat_dev[P] and logp_exact_dev[P] the current rows' log p_hat and exact
+ * log p (in/out; from gbs_prob_approx_dev and gbs_prob_exact_dev on the
+ * initial rows), accepted_dev[P] (nullable; 1 moved, 0 rejected by the
+ * estimate, 2 rejected by the exact correction, -1 malformed row).  A chain
+ * whose current values are not both finite takes any proposal whose two
+ * values are.  Rows of at most 30 clicks (the exact path).  The plan holds the
+ * chains' workspace (allocated on the first call: 4P + 1 + offsets[P] ints and
+ * 2P doubles); the exact path's partial sums are the context's, grown on
+ * demand.  Errors: as gbs_mcmc_step_dev, and GBS_E_INVAL for rows above 30
+ * clicks.
+ */
+int gbs_mcmc_da_step_dev(gbs_ctx *ctx, gbs_plan *plan, const double *u_dev, int32_t *modes_dev,
+                         double *logp_hat_dev, double *logp_exact_dev, int32_t *accepted_dev);
+
 /* Per-kernel timing.  With on = 1, every later launch on the context is
  * bracketed by HIP events recorded on the context's stream.  gbs_timing
  * synchronises the stream, writes the summed milliseconds per kernel group

@@ -119,7 +119,7 @@ void plan_free_dev(gbs_plan *pl)
                     pl->d_cluster_items, pl->d_cluster_off, pl->d_logp, pl->d_status,
                     pl->d_asw, pl->d_aitems, pl->d_roff, pl->d_ritem0, pl->d_axq, pl->d_rscr,
                     pl->d_qibar, pl->d_qitmp, pl->d_grad, pl->d_dl, pl->d_wbig, pl->d_mscr,
-                    pl->d_ascr};
+                    pl->d_ascr, pl->d_da, pl->d_da_x};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -908,6 +908,8 @@ int gbs_grad_dev(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, double *logp_
 // of the plan's offsets), their log p_hat in logp; proposals evaluated on the
 // plan
 int mcmc_step(gbs_ctx *ctx, gbs_plan *plan, const double *u, int32_t *modes, double *logp, int32_t *accepted);
+int mcmc_da_step(gbs_ctx *ctx, gbs_plan *plan, const double *u, int32_t *modes, double *logp_hat, double *logp_exact,
+                 int32_t *accepted);
 
 extern "C" {
 
@@ -923,6 +925,32 @@ int gbs_mcmc_step_dev(gbs_ctx *ctx, gbs_plan *pl, const double *u_dev, int32_t *
     if (pl->P > 0 && (!u_dev || !modes_dev || !logp_dev)) return set_err(ctx, GBS_E_INVAL, "NULL device array");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     return mcmc_step(ctx, pl, u_dev, modes_dev, logp_dev, accepted_dev);
+}
+
+int gbs_mcmc_da_step_dev(gbs_ctx *ctx, gbs_plan *pl, const double *u_dev, int32_t *modes_dev, double *logp_hat_dev,
+                         double *logp_exact_dev, int32_t *accepted_dev)
+{
+    if (!ctx || !pl) return GBS_E_INVAL;
+    if (pl->ctx != ctx) return set_err(ctx, GBS_E_STATE, "plan belongs to another context");
+    if (!ctx->model.have) return set_err(ctx, GBS_E_STATE, "no model set");
+    if (ctx->model.M != pl->M) return set_err(ctx, GBS_E_STATE, "plan was made for a model of another size M");
+    if (pl->frozen) return set_err(ctx, GBS_E_STATE, "the chains need a plan that is not frozen (new rows every step)");
+    if (pl->whole) return set_err(ctx, GBS_E_INVAL, "not a plan of click patterns");
+    if (pl->max_n > GBS_MAX_N_EXACT)
+        return set_err(ctx, GBS_E_INVAL, "the exact correction takes rows of at most " +
+                                             std::to_string(GBS_MAX_N_EXACT) + " clicks");
+    if (pl->P > 0 && (!u_dev || !modes_dev || !logp_hat_dev || !logp_exact_dev))
+        return set_err(ctx, GBS_E_INVAL, "NULL device array");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (pl->P > 0) {
+        // the chains' workspace, on the first call
+        const size_t P = pl->P, nnz = pl->h_offsets[pl->P];
+        if (!pl->d_da)
+            if (int e = dev_alloc(ctx, &pl->d_da, 4 * P + 1 + nnz)) return e;
+        if (!pl->d_da_x)
+            if (int e = dev_alloc(ctx, &pl->d_da_x, 2 * P)) return e;
+    }
+    return mcmc_da_step(ctx, pl, u_dev, modes_dev, logp_hat_dev, logp_exact_dev, accepted_dev);
 }
 
 int gbs_click_distribution(gbs_ctx *ctx, int order, int nk, const int32_t *ks, double *p_n, double *p_k,

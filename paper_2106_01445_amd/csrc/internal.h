@@ -139,6 +139,10 @@ struct gbs_plan {
     int32_t *d_cluster_off = nullptr;     // [n] -> offset, count (2 ints); forward, then adjoint
                                           // at + 2 (max_n + 1)
     double *d_logp = nullptr;             // P (scratch when caller passes none)
+    // two-stage chains: flags, lengths, exact status (P each), packed offsets
+    // (P + 1) and rows (nnz); the exact path's p and log p (P each)
+    int32_t *d_da = nullptr;
+    double *d_da_x = nullptr;
     int32_t *d_status = nullptr;          // P
     size_t v_total = 0;
     int max_items = 0;
