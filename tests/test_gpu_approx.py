@@ -6,6 +6,9 @@ Tolerance: |log p_gpu - log p_oracle| <= 1e-9, i.e. relative error of p_hat
 at radius rho, with aliasing (rho/R)^K <= 1e-16 and rounding of order 1e-16 of
 the tilted sum; the fits add ~1e-12; measured spread is <= 1e-10.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -43,23 +46,27 @@ def test_m8_all_rows(gpu_ctx):
 
 @pytest.mark.parametrize("order", [1, 2, 3])
 def test_m20_sample(gpu_ctx, order):
-    """20 modes: the full 4096-row batch in one launch; 10 rows (smallest and
-    largest click counts included) against the oracle."""
+    """20 modes: the full 4096-row batch in one launch; 35 rows against the
+    oracle: three of every click count 6..14 (seeded draw) and every 512th."""
     wl = make_workload(2)
     gpu_ctx.gbs_set_model(wl.U, wl.r, wl.eta)
     out = gpu_ctx.gbs_prob_approx(wl.offsets, wl.modes, order)
     assert np.all(out["status"] == 0)
     assert np.all(np.isfinite(out["logp"]))
     n = np.diff(wl.offsets)
-    idx = sorted({int(np.argmin(n)), int(np.argmax(n)), *range(0, 4096, 512)})
+    rng = np.random.default_rng(2003)
+    per = [rng.choice(np.flatnonzero(n == k), 3, replace=False) for k in range(int(n.min()), int(n.max()) + 1)]
+    idx = sorted({*(int(i) for i in np.concatenate(per)), *range(0, 4096, 512)})
     ref = oracle_logp(wl, idx, order)
     assert np.max(np.abs(out["logp"][idx] - ref)) < TOL
 
 
 def test_m70_full_batch_sampled(gpu_ctx):
     """70 modes, 10^4 rows of 15-40 clicks, order 3, in the launch configuration
-    the benchmark times; sampled rows (the largest click count among them)
-    against the oracle, every row finite with status 0."""
+    the benchmark times; every row finite with status 0; against the oracle:
+    three rows computed here (the largest click count among them) and the 104
+    rows of tests/golden/m70_rows.json (four of every click count 15..40,
+    written by make_m70_rows.py from the oracle alone)."""
     wl = make_workload(3)
     gpu_ctx.gbs_set_model(wl.U, wl.r, wl.eta)
     out = gpu_ctx.gbs_prob_approx(wl.offsets, wl.modes, 3)
@@ -69,6 +76,13 @@ def test_m70_full_batch_sampled(gpu_ctx):
     idx = [int(np.argmax(n)), 7, 4242]
     ref = oracle_logp(wl, idx, 3)
     assert np.max(np.abs(out["logp"][idx] - ref)) < TOL
+    rec = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "m70_rows.json")))
+    assert len(rec["cases"]) == 104 and {c["n"] for c in rec["cases"]} == set(range(15, 41))
+    rows = np.array([c["row"] for c in rec["cases"]])
+    gold = np.array([c["logp"] for c in rec["cases"]])
+    assert np.all(n[rows] == [c["n"] for c in rec["cases"]])
+    err = np.abs(out["logp"][rows] - gold)
+    assert np.max(err) < TOL, (np.max(err), int(rows[np.argmax(err)]))
 
 
 def test_edge_rows(gpu_ctx):
