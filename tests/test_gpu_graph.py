@@ -18,11 +18,15 @@ def eager(model, r, eta, dl):
     return logp.cpu().numpy(), gr.cpu().numpy(), ge.cpu().numpy()
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("cfg,P,order", [(2, 512, 3), (4, 64, 3), (5, 48, 2)])
+def test_graph_replays_match_eager(cfg, P, order):
+    """20 modes (rows up to 14 clicks), and the first rows of the 100-mode
+    (25-60 clicks, order 3) and 144-mode (40-110 clicks, order 2) batches, whose
+    rows above 40 clicks take the large-row kernels."""
     import torch
     from paper_2106_01445_amd.torch_api import ClickModel, StepGraph
-    wl = make_workload(2, P=512)
-    model = ClickModel(wl.U, wl.offsets, wl.modes, 3)
+    wl = make_workload(cfg, P=P)
+    model = ClickModel(wl.U, wl.offsets, wl.modes, order)
     dev = torch.device("cuda")
     r0 = torch.tensor(wl.r, device=dev)
     eta0 = torch.tensor(wl.eta, device=dev)
