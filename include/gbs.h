@@ -323,6 +323,25 @@ int gbs_plan_tune(gbs_ctx *ctx, gbs_plan *plan, int what, int32_t *params);
 int gbs_plan_info(gbs_plan *plan, double *rho, double *rconv, int32_t *K, int32_t *nsectors, double *err);
 
 /*
+ * Deterministic gradients (on != 0; off by default).  The adjoint adds
+ * cluster terms into Z(w) and rows' terms into the adjoint of Q^-1 with
+ * atomic floating-point adds, whose order, and so the last bits of the
+ * gradient, vary from run to run (~1e-14 relative).  With the switch on, each
+ * such sum runs twice: a first pass finds its largest term, which fixes a
+ * power-of-two scale leaving room for every term, and the second adds the
+ * terms as 64-bit integers, whose sum does not depend on the order; the
+ * results are bitwise reproducible (same plan, model, weights and GPU type).
+ * The integer sums round each term at the scale of the sum's largest term,
+ * with room for one term per cluster holding the entry's mode, so they agree
+ * with the floating-point sums to within 1e-9 of the largest gradient
+ * component (about 4e-12 for 40-click rows at order 3, 4e-10 for 60-click
+ * rows).  The cost: the adjoint's cluster terms are formed twice.  Affects
+ * gbs_grad and gbs_grad_dev on this context.  Errors: GBS_E_INVAL for a NULL
+ * context.
+ */
+int gbs_set_deterministic(gbs_ctx *ctx, int on);
+
+/*
  * gbs_mcmc_step_dev: one Metropolis-Hastings step (Metropolis et al. 1953,
  * Hastings 1970) of P chains of click patterns whose target is the order-j
  * estimate p_hat of the plan's order (Discussion: the approximate

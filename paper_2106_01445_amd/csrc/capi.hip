@@ -119,7 +119,7 @@ void plan_free_dev(gbs_plan *pl)
                     pl->d_cluster_items, pl->d_cluster_off, pl->d_logp, pl->d_status,
                     pl->d_asw, pl->d_aitems, pl->d_roff, pl->d_ritem0, pl->d_axq, pl->d_rscr,
                     pl->d_qibar, pl->d_qitmp, pl->d_grad, pl->d_dl, pl->d_wbig, pl->d_mscr,
-                    pl->d_ascr, pl->d_da, pl->d_da_x};
+                    pl->d_ascr, pl->d_da, pl->d_da_x, pl->d_det};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -261,6 +261,7 @@ int adj_workspace(gbs_ctx *ctx, gbs_plan *pl)
     e = e ? e : dev_alloc(ctx, &pl->d_rscr, rtot);
     e = e ? e : dev_alloc(ctx, &pl->d_qibar, D * D);
     e = e ? e : dev_alloc(ctx, &pl->d_qitmp, D * D);
+    e = e ? e : dev_alloc(ctx, &pl->d_det, 2);
     if (!pl->d_grad) e = e ? e : dev_alloc(ctx, &pl->d_grad, D);
     if (pl->nbig > 0) {
         // larger rows, per workgroup: at order 2 the pair blocks of Z(w) as
@@ -951,6 +952,13 @@ int gbs_mcmc_da_step_dev(gbs_ctx *ctx, gbs_plan *pl, const double *u_dev, int32_
             if (int e = dev_alloc(ctx, &pl->d_da_x, 2 * P)) return e;
     }
     return mcmc_da_step(ctx, pl, u_dev, modes_dev, logp_hat_dev, logp_exact_dev, accepted_dev);
+}
+
+int gbs_set_deterministic(gbs_ctx *ctx, int on)
+{
+    if (!ctx) return GBS_E_INVAL;
+    ctx->deterministic = on != 0;
+    return GBS_OK;
 }
 
 int gbs_click_distribution(gbs_ctx *ctx, int order, int nk, const int32_t *ks, double *p_n, double *p_k,

@@ -37,6 +37,7 @@
 #include "contour_common.h"
 
 #include <algorithm>
+#include <cfloat>
 #include <type_traits>
 
 #define ADJ_QCHUNK GBS_ADJ_CHUNK
@@ -325,7 +326,7 @@ __device__ __forceinline__ void upper_ij(int e, int &i, int &j)
     i = e - j * (j + 1) / 2;
 }
 
-template <int ORDER, bool BIG>
+template <int ORDER, bool BIG, bool DET>
 __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
     const int *__restrict__ offsets, const long long *__restrict__ voff,
     const double *__restrict__ alpha, const double *__restrict__ vt,
@@ -338,6 +339,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
     extern __shared__ __attribute__((aligned(16))) double sh[];
     __shared__ int s_item;
     __shared__ cplx s_g[ORDER + 1];
+    __shared__ double s_zmax[CONT_THREADS / 64];
     __shared__ cplx s_wq[ADJ_QCHUNK];
     cplx *red = (cplx *)sh;                        // [waves]
     double *dyn = (double *)(red + CONT_THREADS / 64 + 8);
@@ -427,8 +429,23 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         // HBM and Z stays interleaved.)
         constexpr bool ZPLANES = !BIG || ORDER >= 3;
         const int zplane = BIG ? 3 * n + 4 * np : ADJ_MREG;
+        // Deterministic mode: the cluster terms are formed twice per point; the
+        // first pass only finds their largest magnitude, which fixes a power-of-two
+        // scale, and the second adds them into Z as 64-bit integers (sums that
+        // do not depend on the order of the adds), converted back after it.
+        int zpass = 1;
+        double zmax = 0.0, zsc = 1.0;
         auto zadd = [&](cplx *p, cplx v) {
-            if constexpr (ZPLANES) {
+            if constexpr (DET) {
+                if (zpass == 0) {
+                    const double m = fmax(fabs(v.re), fabs(v.im));
+                    zmax = m <= DBL_MAX ? fmax(zmax, m) : INFINITY;  // (NaN or inf: non-finite)
+                    return;
+                }
+                unsigned long long *zr = (unsigned long long *)Zd0 + (ZPLANES ? p - Zd0 : 2 * (p - Zd0));
+                atomicAdd(zr, (unsigned long long)llrint(v.re * zsc));
+                atomicAdd(zr + (ZPLANES ? zplane : 1), (unsigned long long)llrint(v.im * zsc));
+            } else if constexpr (ZPLANES) {
                 double *zr = (double *)Zd0 + (p - Zd0);
                 atomicAdd(zr, v.re);
                 atomicAdd(zr + zplane, v.im);
@@ -527,254 +544,291 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             __syncthreads();
             // clusters: Z += c_T E_T M_TT^{-1} E_T^T, c_T = gamma_|T| det(M_TT)^{-1/2}
             cplx bsum = cmk(0.0, 0.0);
-            const cplx g1 = s_g[1 <= ORDER ? 1 : 0];
-            for (int a = tid; a < n; a += CONT_THREADS) {
-                const cplx a00 = Md0[a], a01 = Md1[a], a11 = Md2[a];
-                const cplx r = crsqrt_p(cfnma(a01, a01, cmul(a00, a11)));
-                const cplx c = cmul(g1, r);
-                const cplx id = cmul(r, r);
-                bsum = cadd(bsum, c);
-                const cplx cid = cmul(c, id);
-                zadd(&Zd0[a], cmul(cid, a11));
-                zadd(&Zd1[a], cscale(cmul(cid, a01), -1.0));
-                zadd(&Zd2[a], cmul(cid, a00));
-            }
-            if (ORDER >= 2) {
-                const cplx g2 = s_g[2 <= ORDER ? 2 : 0];
-                const cplx g3 = s_g[3 <= ORDER ? 3 : 0];
-                const int *un = units + unit_off[2 * n];
-                const int nu = unit_off[2 * n + 1];
-                int unext = tid < nu ? un[tid] : 0;
-#pragma unroll 1
-                for (int ui = tid; ui < nu; ui += CONT_THREADS) {
-                    const unsigned u = (unsigned)unext;
-                    if (ui + CONT_THREADS < nu) unext = un[ui + CONT_THREADS];
-                    const int a = u & 255, b = (u >> 8) & 255, c0 = (u >> 16) & 255, c1 = u >> 24;
-                    const int pi = pair_pos<true>(n, a, b);
+            for (int zp = DET ? 0 : 1; zp < 2; ++zp) {
+                zpass = zp;
+                bsum = cmk(0.0, 0.0);
+                const cplx g1 = s_g[1 <= ORDER ? 1 : 0];
+                for (int a = tid; a < n; a += CONT_THREADS) {
                     const cplx a00 = Md0[a], a01 = Md1[a], a11 = Md2[a];
-                    const cplx b00 = Mo0[pi], b01 = Mo1[pi], b10 = Mo2[pi], b11 = Mo3[pi];
-                    const cplx deta = cfnma(a01, a01, cmul(a00, a11));
-                    const cplx ra = crsqrt_p(deta);
-                    const cplx ideta = cmul(ra, ra);
-                    const cplx ia00 = cmul(a11, ideta), ia11 = cmul(a00, ideta);
-                    const cplx ia01 = cscale(cmul(a01, ideta), -1.0);
-                    const cplx G00 = cfma(ia00, b00, cmul(ia01, b10));
-                    const cplx G01 = cfma(ia00, b01, cmul(ia01, b11));
-                    const cplx G10 = cfma(ia01, b00, cmul(ia11, b10));
-                    const cplx G11 = cfma(ia01, b01, cmul(ia11, b11));
-                    const cplx sb00 = csub(Md0[b], cfma(b00, G00, cmul(b10, G10)));
-                    const cplx sb01 = csub(Md1[b], cfma(b00, G01, cmul(b10, G11)));
-                    const cplx sb11 = csub(Md2[b], cfma(b01, G01, cmul(b11, G11)));
-                    const cplx rb = crsqrt_p(cfnma(sb01, sb01, cmul(sb00, sb11)));
-                    const cplx rab = cmul(ra, rb);
-                    const cplx idetb = cmul(rb, rb);
-                    const cplx ib00 = cmul(sb11, idetb), ib11 = cmul(sb00, idetb);
-                    const cplx ib01 = cscale(cmul(sb01, idetb), -1.0);
-                    // coefficient of P^{-1} (the pair itself, carried by its first unit,
-                    // plus the unit's triples) and the pair block of
-                    // sum_c c_T U Sc^{-1} U^T (4x4 symmetric, 10 entries)
-                    cplx cp = c0 == b + 1 ? cmul(g2, rab) : cmk(0.0, 0.0);
-                    bsum = cadd(bsum, cp);
-                    cplx A00 = cmk(0, 0), A01 = cmk(0, 0), A02 = cmk(0, 0), A03 = cmk(0, 0),
-                         A11 = cmk(0, 0), A12 = cmk(0, 0), A13 = cmk(0, 0), A22 = cmk(0, 0),
-                         A23 = cmk(0, 0), A33 = cmk(0, 0);
-                    if (ORDER >= 3) {
-#pragma unroll 1
-                        for (int c = c0; c < c1; ++c) {
-                            const int cur_ac = pair_pos<true>(n, a, c), cur_bc = pair_pos<true>(n, b, c);
-                            const cplx x00 = Mo0[cur_ac], x01 = Mo1[cur_ac], x10 = Mo2[cur_ac], x11 = Mo3[cur_ac];
-                            const cplx yy00 = Mo0[cur_bc], yy01 = Mo1[cur_bc], yy10 = Mo2[cur_bc], yy11 = Mo3[cur_bc];
-                            const cplx m00 = Md0[c], m01 = Md1[c], m11 = Md2[c];
-                            // Za = Maa^{-1} Xa, Y = Xb - G^T Xa, W = Sb^{-1} Y,
-                            // Sc = Mcc - Xa^T Za - Y^T W, U = [Za - G W ; W]
-                            cplx Z00, Z01, Z10, Z11, W00, W01, W10, W11, sc00, sc01, sc11;
-                            {
-                                Z00 = cfma(ia00, x00, cmul(ia01, x10));
-                                Z10 = cfma(ia01, x00, cmul(ia11, x10));
-                                Z01 = cfma(ia00, x01, cmul(ia01, x11));
-                                Z11 = cfma(ia01, x01, cmul(ia11, x11));
-                                sc00 = csub(m00, cfma(x00, Z00, cmul(x10, Z10)));
-                                sc01 = csub(m01, cfma(x00, Z01, cmul(x10, Z11)));
-                                sc11 = csub(m11, cfma(x01, Z01, cmul(x11, Z11)));
-                                const cplx Y00 = csub(yy00, cfma(G00, x00, cmul(G10, x10)));
-                                const cplx Y10 = csub(yy10, cfma(G01, x00, cmul(G11, x10)));
-                                W00 = cfma(ib00, Y00, cmul(ib01, Y10));
-                                W10 = cfma(ib01, Y00, cmul(ib11, Y10));
-                                sc00 = csub(sc00, cfma(Y00, W00, cmul(Y10, W10)));
-                                const cplx Y01 = csub(yy01, cfma(G00, x01, cmul(G10, x11)));
-                                const cplx Y11 = csub(yy11, cfma(G01, x01, cmul(G11, x11)));
-                                W01 = cfma(ib00, Y01, cmul(ib01, Y11));
-                                W11 = cfma(ib01, Y01, cmul(ib11, Y11));
-                                sc01 = csub(sc01, cfma(Y00, W01, cmul(Y10, W11)));
-                                sc11 = csub(sc11, cfma(Y01, W01, cmul(Y11, W11)));
+                    const cplx r = crsqrt_p(cfnma(a01, a01, cmul(a00, a11)));
+                    const cplx c = cmul(g1, r);
+                    const cplx id = cmul(r, r);
+                    bsum = cadd(bsum, c);
+                    const cplx cid = cmul(c, id);
+                    zadd(&Zd0[a], cmul(cid, a11));
+                    zadd(&Zd1[a], cscale(cmul(cid, a01), -1.0));
+                    zadd(&Zd2[a], cmul(cid, a00));
+                }
+                if (ORDER >= 2) {
+                    const cplx g2 = s_g[2 <= ORDER ? 2 : 0];
+                    const cplx g3 = s_g[3 <= ORDER ? 3 : 0];
+                    const int *un = units + unit_off[2 * n];
+                    const int nu = unit_off[2 * n + 1];
+                    int unext = tid < nu ? un[tid] : 0;
+    #pragma unroll 1
+                    for (int ui = tid; ui < nu; ui += CONT_THREADS) {
+                        const unsigned u = (unsigned)unext;
+                        if (ui + CONT_THREADS < nu) unext = un[ui + CONT_THREADS];
+                        const int a = u & 255, b = (u >> 8) & 255, c0 = (u >> 16) & 255, c1 = u >> 24;
+                        const int pi = pair_pos<true>(n, a, b);
+                        const cplx a00 = Md0[a], a01 = Md1[a], a11 = Md2[a];
+                        const cplx b00 = Mo0[pi], b01 = Mo1[pi], b10 = Mo2[pi], b11 = Mo3[pi];
+                        const cplx deta = cfnma(a01, a01, cmul(a00, a11));
+                        const cplx ra = crsqrt_p(deta);
+                        const cplx ideta = cmul(ra, ra);
+                        const cplx ia00 = cmul(a11, ideta), ia11 = cmul(a00, ideta);
+                        const cplx ia01 = cscale(cmul(a01, ideta), -1.0);
+                        const cplx G00 = cfma(ia00, b00, cmul(ia01, b10));
+                        const cplx G01 = cfma(ia00, b01, cmul(ia01, b11));
+                        const cplx G10 = cfma(ia01, b00, cmul(ia11, b10));
+                        const cplx G11 = cfma(ia01, b01, cmul(ia11, b11));
+                        const cplx sb00 = csub(Md0[b], cfma(b00, G00, cmul(b10, G10)));
+                        const cplx sb01 = csub(Md1[b], cfma(b00, G01, cmul(b10, G11)));
+                        const cplx sb11 = csub(Md2[b], cfma(b01, G01, cmul(b11, G11)));
+                        const cplx rb = crsqrt_p(cfnma(sb01, sb01, cmul(sb00, sb11)));
+                        const cplx rab = cmul(ra, rb);
+                        const cplx idetb = cmul(rb, rb);
+                        const cplx ib00 = cmul(sb11, idetb), ib11 = cmul(sb00, idetb);
+                        const cplx ib01 = cscale(cmul(sb01, idetb), -1.0);
+                        // coefficient of P^{-1} (the pair itself, carried by its first unit,
+                        // plus the unit's triples) and the pair block of
+                        // sum_c c_T U Sc^{-1} U^T (4x4 symmetric, 10 entries)
+                        cplx cp = c0 == b + 1 ? cmul(g2, rab) : cmk(0.0, 0.0);
+                        bsum = cadd(bsum, cp);
+                        cplx A00 = cmk(0, 0), A01 = cmk(0, 0), A02 = cmk(0, 0), A03 = cmk(0, 0),
+                             A11 = cmk(0, 0), A12 = cmk(0, 0), A13 = cmk(0, 0), A22 = cmk(0, 0),
+                             A23 = cmk(0, 0), A33 = cmk(0, 0);
+                        if (ORDER >= 3) {
+    #pragma unroll 1
+                            for (int c = c0; c < c1; ++c) {
+                                const int cur_ac = pair_pos<true>(n, a, c), cur_bc = pair_pos<true>(n, b, c);
+                                const cplx x00 = Mo0[cur_ac], x01 = Mo1[cur_ac], x10 = Mo2[cur_ac], x11 = Mo3[cur_ac];
+                                const cplx yy00 = Mo0[cur_bc], yy01 = Mo1[cur_bc], yy10 = Mo2[cur_bc], yy11 = Mo3[cur_bc];
+                                const cplx m00 = Md0[c], m01 = Md1[c], m11 = Md2[c];
+                                // Za = Maa^{-1} Xa, Y = Xb - G^T Xa, W = Sb^{-1} Y,
+                                // Sc = Mcc - Xa^T Za - Y^T W, U = [Za - G W ; W]
+                                cplx Z00, Z01, Z10, Z11, W00, W01, W10, W11, sc00, sc01, sc11;
+                                {
+                                    Z00 = cfma(ia00, x00, cmul(ia01, x10));
+                                    Z10 = cfma(ia01, x00, cmul(ia11, x10));
+                                    Z01 = cfma(ia00, x01, cmul(ia01, x11));
+                                    Z11 = cfma(ia01, x01, cmul(ia11, x11));
+                                    sc00 = csub(m00, cfma(x00, Z00, cmul(x10, Z10)));
+                                    sc01 = csub(m01, cfma(x00, Z01, cmul(x10, Z11)));
+                                    sc11 = csub(m11, cfma(x01, Z01, cmul(x11, Z11)));
+                                    const cplx Y00 = csub(yy00, cfma(G00, x00, cmul(G10, x10)));
+                                    const cplx Y10 = csub(yy10, cfma(G01, x00, cmul(G11, x10)));
+                                    W00 = cfma(ib00, Y00, cmul(ib01, Y10));
+                                    W10 = cfma(ib01, Y00, cmul(ib11, Y10));
+                                    sc00 = csub(sc00, cfma(Y00, W00, cmul(Y10, W10)));
+                                    const cplx Y01 = csub(yy01, cfma(G00, x01, cmul(G10, x11)));
+                                    const cplx Y11 = csub(yy11, cfma(G01, x01, cmul(G11, x11)));
+                                    W01 = cfma(ib00, Y01, cmul(ib01, Y11));
+                                    W11 = cfma(ib01, Y01, cmul(ib11, Y11));
+                                    sc01 = csub(sc01, cfma(Y00, W01, cmul(Y10, W11)));
+                                    sc11 = csub(sc11, cfma(Y01, W01, cmul(Y11, W11)));
+                                }
+                                const cplx rc = crsqrt_p(cfnma(sc01, sc01, cmul(sc00, sc11)));
+                                const cplx ct = cmul(g3, cmul(rab, rc));
+                                bsum = cadd(bsum, ct);
+                                // c_T Sc^{-1}
+                                cplx is00, is01, is11;
+                                {
+                                    const cplx k = cmul(ct, cmul(rc, rc));
+                                    is00 = cmul(sc11, k);
+                                    is11 = cmul(sc00, k);
+                                    is01 = cmul(cneg(sc01), k);
+                                }
+                                zadd(&Zd0[c], is00);
+                                zadd(&Zd1[c], is01);
+                                zadd(&Zd2[c], is11);
+                                // rows a: U_a = Za - G W, then Q_a = -P_a = -U_a c_T Sc^{-1}
+                                // (formed with the sign the Z blocks take, so that no
+                                // negated copy has to be made for the LDS adds)
+                                const cplx U00 = csub(Z00, cfma(G00, W00, cmul(G01, W10)));
+                                const cplx U01 = csub(Z01, cfma(G00, W01, cmul(G01, W11)));
+                                const cplx U10 = csub(Z10, cfma(G10, W00, cmul(G11, W10)));
+                                const cplx U11 = csub(Z11, cfma(G10, W01, cmul(G11, W11)));
+                                const cplx Q00 = cfnma(U00, is00, cmul(cneg(U01), is01));
+                                const cplx Q01 = cfnma(U00, is01, cmul(cneg(U01), is11));
+                                const cplx Q10 = cfnma(U10, is00, cmul(cneg(U11), is01));
+                                const cplx Q11 = cfnma(U10, is01, cmul(cneg(U11), is11));
+                                zadd(&Zo0[cur_ac], Q00);
+                                zadd(&Zo1[cur_ac], Q01);
+                                zadd(&Zo2[cur_ac], Q10);
+                                zadd(&Zo3[cur_ac], Q11);
+                                A00 = cfnma(Q00, U00, cfnma(Q01, U01, A00));
+                                A01 = cfnma(Q00, U10, cfnma(Q01, U11, A01));
+                                A11 = cfnma(Q10, U10, cfnma(Q11, U11, A11));
+                                A02 = cfnma(Q00, W00, cfnma(Q01, W01, A02));
+                                A03 = cfnma(Q00, W10, cfnma(Q01, W11, A03));
+                                A12 = cfnma(Q10, W00, cfnma(Q11, W01, A12));
+                                A13 = cfnma(Q10, W10, cfnma(Q11, W11, A13));
+                                // rows b: Q_b = -P_b = -W c_T Sc^{-1}
+                                const cplx Q20 = cfnma(W00, is00, cmul(cneg(W01), is01));
+                                const cplx Q21 = cfnma(W00, is01, cmul(cneg(W01), is11));
+                                const cplx Q30 = cfnma(W10, is00, cmul(cneg(W11), is01));
+                                const cplx Q31 = cfnma(W10, is01, cmul(cneg(W11), is11));
+                                zadd(&Zo0[cur_bc], Q20);
+                                zadd(&Zo1[cur_bc], Q21);
+                                zadd(&Zo2[cur_bc], Q30);
+                                zadd(&Zo3[cur_bc], Q31);
+                                A22 = cfnma(Q20, W00, cfnma(Q21, W01, A22));
+                                A23 = cfnma(Q20, W10, cfnma(Q21, W11, A23));
+                                A33 = cfnma(Q30, W10, cfnma(Q31, W11, A33));
+                                cp = cadd(cp, ct);
                             }
-                            const cplx rc = crsqrt_p(cfnma(sc01, sc01, cmul(sc00, sc11)));
-                            const cplx ct = cmul(g3, cmul(rab, rc));
-                            bsum = cadd(bsum, ct);
-                            // c_T Sc^{-1}
-                            cplx is00, is01, is11;
-                            {
-                                const cplx k = cmul(ct, cmul(rc, rc));
-                                is00 = cmul(sc11, k);
-                                is11 = cmul(sc00, k);
-                                is01 = cmul(cneg(sc01), k);
-                            }
-                            zadd(&Zd0[c], is00);
-                            zadd(&Zd1[c], is01);
-                            zadd(&Zd2[c], is11);
-                            // rows a: U_a = Za - G W, then Q_a = -P_a = -U_a c_T Sc^{-1}
-                            // (formed with the sign the Z blocks take, so that no
-                            // negated copy has to be made for the LDS adds)
-                            const cplx U00 = csub(Z00, cfma(G00, W00, cmul(G01, W10)));
-                            const cplx U01 = csub(Z01, cfma(G00, W01, cmul(G01, W11)));
-                            const cplx U10 = csub(Z10, cfma(G10, W00, cmul(G11, W10)));
-                            const cplx U11 = csub(Z11, cfma(G10, W01, cmul(G11, W11)));
-                            const cplx Q00 = cfnma(U00, is00, cmul(cneg(U01), is01));
-                            const cplx Q01 = cfnma(U00, is01, cmul(cneg(U01), is11));
-                            const cplx Q10 = cfnma(U10, is00, cmul(cneg(U11), is01));
-                            const cplx Q11 = cfnma(U10, is01, cmul(cneg(U11), is11));
-                            zadd(&Zo0[cur_ac], Q00);
-                            zadd(&Zo1[cur_ac], Q01);
-                            zadd(&Zo2[cur_ac], Q10);
-                            zadd(&Zo3[cur_ac], Q11);
-                            A00 = cfnma(Q00, U00, cfnma(Q01, U01, A00));
-                            A01 = cfnma(Q00, U10, cfnma(Q01, U11, A01));
-                            A11 = cfnma(Q10, U10, cfnma(Q11, U11, A11));
-                            A02 = cfnma(Q00, W00, cfnma(Q01, W01, A02));
-                            A03 = cfnma(Q00, W10, cfnma(Q01, W11, A03));
-                            A12 = cfnma(Q10, W00, cfnma(Q11, W01, A12));
-                            A13 = cfnma(Q10, W10, cfnma(Q11, W11, A13));
-                            // rows b: Q_b = -P_b = -W c_T Sc^{-1}
-                            const cplx Q20 = cfnma(W00, is00, cmul(cneg(W01), is01));
-                            const cplx Q21 = cfnma(W00, is01, cmul(cneg(W01), is11));
-                            const cplx Q30 = cfnma(W10, is00, cmul(cneg(W11), is01));
-                            const cplx Q31 = cfnma(W10, is01, cmul(cneg(W11), is11));
-                            zadd(&Zo0[cur_bc], Q20);
-                            zadd(&Zo1[cur_bc], Q21);
-                            zadd(&Zo2[cur_bc], Q30);
-                            zadd(&Zo3[cur_bc], Q31);
-                            A22 = cfnma(Q20, W00, cfnma(Q21, W01, A22));
-                            A23 = cfnma(Q20, W10, cfnma(Q21, W11, A23));
-                            A33 = cfnma(Q30, W10, cfnma(Q31, W11, A33));
-                            cp = cadd(cp, ct);
                         }
+                        // P^{-1} = [[ia + G ib G^T, -G ib], [-ib G^T, ib]]
+                        const cplx H00 = cfma(ib00, G00, cmul(ib01, G01)), H01 = cfma(ib01, G00, cmul(ib11, G01));
+                        const cplx H10 = cfma(ib00, G10, cmul(ib01, G11)), H11 = cfma(ib01, G10, cmul(ib11, G11));
+                        // (G ib) rows: row0 = (H00, H01), row1 = (H10, H11)
+                        const cplx pa00 = cadd(ia00, cfma(H00, G00, cmul(H01, G01)));
+                        const cplx pa01 = cadd(ia01, cfma(H00, G10, cmul(H01, G11)));
+                        const cplx pa11 = cadd(ia11, cfma(H10, G10, cmul(H11, G11)));
+                        zadd(&Zd0[a], cfma(cp, pa00, A00));
+                        zadd(&Zd1[a], cfma(cp, pa01, A01));
+                        zadd(&Zd2[a], cfma(cp, pa11, A11));
+                        if (BIG && ORDER <= 2) {
+                            // one unit per pair: the pair block has a single writer
+                            Zo0[pi] = cfnma(cp, H00, A02);
+                            Zo1[pi] = cfnma(cp, H01, A03);
+                            Zo2[pi] = cfnma(cp, H10, A12);
+                            Zo3[pi] = cfnma(cp, H11, A13);
+                        } else {
+                            zadd(&Zo0[pi], cfnma(cp, H00, A02));
+                            zadd(&Zo1[pi], cfnma(cp, H01, A03));
+                            zadd(&Zo2[pi], cfnma(cp, H10, A12));
+                            zadd(&Zo3[pi], cfnma(cp, H11, A13));
+                        }
+                        zadd(&Zd0[b], cfma(cp, ib00, A22));
+                        zadd(&Zd1[b], cfma(cp, ib01, A23));
+                        zadd(&Zd2[b], cfma(cp, ib11, A33));
                     }
-                    // P^{-1} = [[ia + G ib G^T, -G ib], [-ib G^T, ib]]
-                    const cplx H00 = cfma(ib00, G00, cmul(ib01, G01)), H01 = cfma(ib01, G00, cmul(ib11, G01));
-                    const cplx H10 = cfma(ib00, G10, cmul(ib01, G11)), H11 = cfma(ib01, G10, cmul(ib11, G11));
-                    // (G ib) rows: row0 = (H00, H01), row1 = (H10, H11)
-                    const cplx pa00 = cadd(ia00, cfma(H00, G00, cmul(H01, G01)));
-                    const cplx pa01 = cadd(ia01, cfma(H00, G10, cmul(H01, G11)));
-                    const cplx pa11 = cadd(ia11, cfma(H10, G10, cmul(H11, G11)));
-                    zadd(&Zd0[a], cfma(cp, pa00, A00));
-                    zadd(&Zd1[a], cfma(cp, pa01, A01));
-                    zadd(&Zd2[a], cfma(cp, pa11, A11));
-                    if (BIG && ORDER <= 2) {
-                        // one unit per pair: the pair block has a single writer
-                        Zo0[pi] = cfnma(cp, H00, A02);
-                        Zo1[pi] = cfnma(cp, H01, A03);
-                        Zo2[pi] = cfnma(cp, H10, A12);
-                        Zo3[pi] = cfnma(cp, H11, A13);
-                    } else {
-                        zadd(&Zo0[pi], cfnma(cp, H00, A02));
-                        zadd(&Zo1[pi], cfnma(cp, H01, A03));
-                        zadd(&Zo2[pi], cfnma(cp, H10, A12));
-                        zadd(&Zo3[pi], cfnma(cp, H11, A13));
+                }
+                if constexpr (ORDER >= 4) {
+                    // quadruples T = {a, b, c, d}: units (a, b, c; d0 .. d0+len-1).  With
+                    // the triple {a, b, c} eliminated as in the forward (ia = Maa^{-1},
+                    // G = ia Mab, ib = Sb^{-1}, Zc = ia Mac, Wc = ib (Mbc - G^T Mac),
+                    // ic = Sc^{-1}), each d has y = M3^{-1} r_d, r_d = [Mad; Mbd; Mcd],
+                    // by back-substitution through those factors:
+                    //   y3 = v = ic u,  y2 = W - Wc v,  y1 = Z - G y2 - Zc v,
+                    // and M_TT^{-1} = [[M3^{-1} + y Sd^{-1} y^T, -y Sd^{-1}], [., Sd^{-1}]].
+                    // c_T M_TT^{-1} goes into Z; the M3^{-1} part, the same for every d of
+                    // the unit, once per unit with the sum of the unit's c_T.
+                    const cplx g4 = s_g[ORDER >= 4 ? 4 : 0];
+                    auto Mdiag = [&](int x) { return Sym{Md0[x], Md1[x], Md2[x]}; };
+                    auto Mpair = [&](int x, int y) {
+                        const int q = pair_pos<true>(n, x, y);
+                        return Blk{Mo0[q], Mo1[q], Mo2[q], Mo3[q]};
+                    };
+                    auto zdiag = [&](int x, const Sym &v) {
+                        zadd(&Zd0[x], v.a);
+                        zadd(&Zd1[x], v.b);
+                        zadd(&Zd2[x], v.d);
+                    };
+                    auto zpair = [&](int x, int y, const Blk &v) {
+                        const int q = pair_pos<true>(n, x, y);
+                        zadd(&Zo0[q], v.a);
+                        zadd(&Zo1[q], v.b);
+                        zadd(&Zo2[q], v.c);
+                        zadd(&Zo3[q], v.d);
+                    };
+                    const int *un4 = units + unit4_off[2 * n];
+                    const int nu4 = unit4_off[2 * n + 1];
+    #pragma unroll 1
+                    for (int ui = tid; ui < nu4; ui += CONT_THREADS) {
+                        const unsigned u4 = (unsigned)un4[ui];
+                        const int a = u4 & 63, b = (u4 >> 6) & 63, c = (u4 >> 12) & 63, d0 = (u4 >> 18) & 63,
+                                  d1 = d0 + (int)(u4 >> 24);
+                        cplx ra, rb, rc;
+                        const Sym ia = sinv(Mdiag(a), ra);
+                        const Blk Mab = Mpair(a, b);
+                        const Blk G = smul(ia, Mab);
+                        const Sym ib = sinv(ssub(Mdiag(b), tmul_sym(Mab, G)), rb);
+                        const Blk Mac = Mpair(a, c);
+                        const Blk Zc = smul(ia, Mac);
+                        const Blk Yc = bsub(Mpair(b, c), tmul(G, Mac));
+                        const Blk Wc = smul(ib, Yc);
+                        const Sym ic = sinv(ssub(ssub(Mdiag(c), tmul_sym(Mac, Zc)), tmul_sym(Yc, Wc)), rc);
+                        const cplx rabc = cmul(cmul(ra, rb), rc);
+                        cplx csum = cmk(0.0, 0.0);
+    #pragma unroll 1
+                        for (int d = d0; d < d1; ++d) {
+                            const Blk x = Mpair(a, d);
+                            const Blk Y = bsub(Mpair(b, d), tmul(G, x));
+                            const Blk W = smul(ib, Y);
+                            const Blk Z = smul(ia, x);
+                            const Sym q = ssub(ssub(Mdiag(d), tmul_sym(x, Z)), tmul_sym(Y, W));
+                            const Blk u = bsub(bsub(Mpair(c, d), tmul(Zc, x)), tmul(Wc, Y));
+                            const Blk v = smul(ic, u);
+                            cplx rd;
+                            const Sym isd0 = sinv(ssub(q, tmul_sym(u, v)), rd);
+                            const cplx ct = cmul(g4, cmul(rabc, rd));
+                            csum = cadd(csum, ct);
+                            const Sym isd = sscale(isd0, ct);
+                            const Blk y2 = bsub(W, bmul(Wc, v));
+                            const Blk y1 = bsub(bsub(Z, bmul(G, y2)), bmul(Zc, v));
+                            const Blk t1 = bsmul(y1, isd), t2 = bsmul(y2, isd), t3 = bsmul(v, isd);
+                            zdiag(d, isd);
+                            zpair(a, d, bneg(t1));
+                            zpair(b, d, bneg(t2));
+                            zpair(c, d, bneg(t3));
+                            zdiag(a, bmul_t_sym(t1, y1));
+                            zdiag(b, bmul_t_sym(t2, y2));
+                            zdiag(c, bmul_t_sym(t3, v));
+                            zpair(a, b, bmul_t(t1, y2));
+                            zpair(a, c, bmul_t(t1, v));
+                            zpair(b, c, bmul_t(t2, v));
+                        }
+                        bsum = cadd(bsum, csum);
+                        // csum M3^{-1}: cc = ic, ac = -Ua ic, bc = -Wc ic,
+                        // aa = ia + G ib G^T + Ua ic Ua^T, ab = -G ib + Ua ic Wc^T,
+                        // bb = ib + Wc ic Wc^T, with Ua = Zc - G Wc
+                        const Blk Ua = bsub(Zc, bmul(G, Wc));
+                        const Blk Uic = bsmul(Ua, ic), Wic = bsmul(Wc, ic), Gib = bsmul(G, ib);
+                        const cplx ncs = cneg(csum);
+                        zdiag(c, sscale(ic, csum));
+                        zpair(a, c, bscale(Uic, ncs));
+                        zpair(b, c, bscale(Wic, ncs));
+                        zdiag(a, sscale(sadd(sadd(ia, bmul_t_sym(Gib, G)), bmul_t_sym(Uic, Ua)), csum));
+                        zpair(a, b, bscale(bsub(bmul_t(Uic, Wc), Gib), csum));
+                        zdiag(b, sscale(sadd(ib, bmul_t_sym(Wic, Wc)), csum));
                     }
-                    zadd(&Zd0[b], cfma(cp, ib00, A22));
-                    zadd(&Zd1[b], cfma(cp, ib01, A23));
-                    zadd(&Zd2[b], cfma(cp, ib11, A33));
+                }
+                if constexpr (DET) {
+                    if (zp == 0) {
+                        // the block's largest term; the scale leaves room for one
+                        // term per cluster holding the entry's mode (ncl of them)
+                        double zm = zmax;
+                        for (int off = 32; off > 0; off >>= 1) zm = fmax(zm, __shfl_xor(zm, off));
+                        if (lane == 0) s_zmax[wid] = zm;
+                        __syncthreads();
+                        zm = 0.0;
+                        for (int i = 0; i < CONT_THREADS / 64; ++i) zm = fmax(zm, s_zmax[i]);
+                        double ncl = 1.0, bin = 1.0;  // sum over t < j of C(n - 1, t)
+                        for (int t = 1; t < ORDER && t < n; ++t) {
+                            bin = bin * (n - t) / t;
+                            ncl += bin;
+                        }
+                        int ez = 0;
+                        frexp(zm, &ez);
+                        zsc = zm > 0.0 && zm <= DBL_MAX ? ldexp(1.0, 61 - (ilogb(ncl) + 2) - ez) : 1.0;
+                        zmax = zm;
+                    }
                 }
             }
-            if constexpr (ORDER >= 4) {
-                // quadruples T = {a, b, c, d}: units (a, b, c; d0 .. d0+len-1).  With
-                // the triple {a, b, c} eliminated as in the forward (ia = Maa^{-1},
-                // G = ia Mab, ib = Sb^{-1}, Zc = ia Mac, Wc = ib (Mbc - G^T Mac),
-                // ic = Sc^{-1}), each d has y = M3^{-1} r_d, r_d = [Mad; Mbd; Mcd],
-                // by back-substitution through those factors:
-                //   y3 = v = ic u,  y2 = W - Wc v,  y1 = Z - G y2 - Zc v,
-                // and M_TT^{-1} = [[M3^{-1} + y Sd^{-1} y^T, -y Sd^{-1}], [., Sd^{-1}]].
-                // c_T M_TT^{-1} goes into Z; the M3^{-1} part, the same for every d of
-                // the unit, once per unit with the sum of the unit's c_T.
-                const cplx g4 = s_g[ORDER >= 4 ? 4 : 0];
-                auto Mdiag = [&](int x) { return Sym{Md0[x], Md1[x], Md2[x]}; };
-                auto Mpair = [&](int x, int y) {
-                    const int q = pair_pos<true>(n, x, y);
-                    return Blk{Mo0[q], Mo1[q], Mo2[q], Mo3[q]};
-                };
-                auto zdiag = [&](int x, const Sym &v) {
-                    zadd(&Zd0[x], v.a);
-                    zadd(&Zd1[x], v.b);
-                    zadd(&Zd2[x], v.d);
-                };
-                auto zpair = [&](int x, int y, const Blk &v) {
-                    const int q = pair_pos<true>(n, x, y);
-                    zadd(&Zo0[q], v.a);
-                    zadd(&Zo1[q], v.b);
-                    zadd(&Zo2[q], v.c);
-                    zadd(&Zo3[q], v.d);
-                };
-                const int *un4 = units + unit4_off[2 * n];
-                const int nu4 = unit4_off[2 * n + 1];
-#pragma unroll 1
-                for (int ui = tid; ui < nu4; ui += CONT_THREADS) {
-                    const unsigned u4 = (unsigned)un4[ui];
-                    const int a = u4 & 63, b = (u4 >> 6) & 63, c = (u4 >> 12) & 63, d0 = (u4 >> 18) & 63,
-                              d1 = d0 + (int)(u4 >> 24);
-                    cplx ra, rb, rc;
-                    const Sym ia = sinv(Mdiag(a), ra);
-                    const Blk Mab = Mpair(a, b);
-                    const Blk G = smul(ia, Mab);
-                    const Sym ib = sinv(ssub(Mdiag(b), tmul_sym(Mab, G)), rb);
-                    const Blk Mac = Mpair(a, c);
-                    const Blk Zc = smul(ia, Mac);
-                    const Blk Yc = bsub(Mpair(b, c), tmul(G, Mac));
-                    const Blk Wc = smul(ib, Yc);
-                    const Sym ic = sinv(ssub(ssub(Mdiag(c), tmul_sym(Mac, Zc)), tmul_sym(Yc, Wc)), rc);
-                    const cplx rabc = cmul(cmul(ra, rb), rc);
-                    cplx csum = cmk(0.0, 0.0);
-#pragma unroll 1
-                    for (int d = d0; d < d1; ++d) {
-                        const Blk x = Mpair(a, d);
-                        const Blk Y = bsub(Mpair(b, d), tmul(G, x));
-                        const Blk W = smul(ib, Y);
-                        const Blk Z = smul(ia, x);
-                        const Sym q = ssub(ssub(Mdiag(d), tmul_sym(x, Z)), tmul_sym(Y, W));
-                        const Blk u = bsub(bsub(Mpair(c, d), tmul(Zc, x)), tmul(Wc, Y));
-                        const Blk v = smul(ic, u);
-                        cplx rd;
-                        const Sym isd0 = sinv(ssub(q, tmul_sym(u, v)), rd);
-                        const cplx ct = cmul(g4, cmul(rabc, rd));
-                        csum = cadd(csum, ct);
-                        const Sym isd = sscale(isd0, ct);
-                        const Blk y2 = bsub(W, bmul(Wc, v));
-                        const Blk y1 = bsub(bsub(Z, bmul(G, y2)), bmul(Zc, v));
-                        const Blk t1 = bsmul(y1, isd), t2 = bsmul(y2, isd), t3 = bsmul(v, isd);
-                        zdiag(d, isd);
-                        zpair(a, d, bneg(t1));
-                        zpair(b, d, bneg(t2));
-                        zpair(c, d, bneg(t3));
-                        zdiag(a, bmul_t_sym(t1, y1));
-                        zdiag(b, bmul_t_sym(t2, y2));
-                        zdiag(c, bmul_t_sym(t3, v));
-                        zpair(a, b, bmul_t(t1, y2));
-                        zpair(a, c, bmul_t(t1, v));
-                        zpair(b, c, bmul_t(t2, v));
-                    }
-                    bsum = cadd(bsum, csum);
-                    // csum M3^{-1}: cc = ic, ac = -Ua ic, bc = -Wc ic,
-                    // aa = ia + G ib G^T + Ua ic Ua^T, ab = -G ib + Ua ic Wc^T,
-                    // bb = ib + Wc ic Wc^T, with Ua = Zc - G Wc
-                    const Blk Ua = bsub(Zc, bmul(G, Wc));
-                    const Blk Uic = bsmul(Ua, ic), Wic = bsmul(Wc, ic), Gib = bsmul(G, ib);
-                    const cplx ncs = cneg(csum);
-                    zdiag(c, sscale(ic, csum));
-                    zpair(a, c, bscale(Uic, ncs));
-                    zpair(b, c, bscale(Wic, ncs));
-                    zdiag(a, sscale(sadd(sadd(ia, bmul_t_sym(Gib, G)), bmul_t_sym(Uic, Ua)), csum));
-                    zpair(a, b, bscale(bsub(bmul_t(Uic, Wc), Gib), csum));
-                    zdiag(b, sscale(sadd(ib, bmul_t_sym(Wic, Wc)), csum));
-                }
+            if constexpr (DET) {
+                __syncthreads();
+                // back to doubles (the scale is a power of two); non-finite terms
+                // make every entry NaN, as the floating-point sums would
+                unsigned long long *zi = (unsigned long long *)Zd0;
+                double *zf = (double *)Zd0;
+                const int nz = ZPLANES ? 2 * zplane : 6 * n;
+                const double inv = 1.0 / zsc;
+                const bool bad = !(zmax <= DBL_MAX);
+                for (int i = tid; i < nz; i += CONT_THREADS)
+                    zf[i] = bad ? NAN : (double)(long long)zi[i] * inv;
             }
             bsum = warp_csum(bsum);
             if (lane == 0) red[wid] = bsum;
@@ -1214,16 +1268,25 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_pairs_big(
         // the pairs of block (I, J) from its quadrant products: P = M_TT, T = {a, b},
         // eliminated through M_aa (ia) and the Schur complement of b (ib);
         // c_T P^{-1} = c_T [[ia + G ib G^T, -G ib], [-ib G^T, ib]], G = ia M_ab
-        auto pairs = [&](int I, int J, const dbl4 (&qq)[4][2], cplx g2, cplx &bs) {
+        // per mode block u: the pairs' contributions to Z's mode-diagonal 2x2
+        // blocks, summed in a fixed order (over the block's 16 partners by a
+        // butterfly of lane shuffles), 16 modes x 3 entries for the rows a of
+        // block I (side 0) and for the rows b of block J (side 1)
+        cplx *Zq = Zt + TM * (TM + 1) / 2 * 1024;
+        auto pairs = [&](int u, int I, int J, const dbl4 (&qq)[4][2], cplx g2, cplx &bs) {
             const int b = 16 * J + l16;
             cplx *t0 = plane(I, J, 0);
+            cplx sb0 = cmk(0.0, 0.0), sb1 = sb0, sb2 = sb0;  // this lane's b, over e
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int ra_ = 4 * e + lq, a = 16 * I + ra_;
-                if (!(a < b && b < n)) continue;
+                // (lanes without a pair compute on safe indices; their terms are
+                // replaced by zeros, so that every lane takes part in the sums)
+                const bool ok = a < b && b < n;
+                const int as = ok ? a : 0, bq = ok ? b : 0;
                 const cplx b00 = cmk(qq[0][0][e], qq[0][1][e]), b01 = cmk(qq[1][0][e], qq[1][1][e]);
                 const cplx b10 = cmk(qq[2][0][e], qq[2][1][e]), b11 = cmk(qq[3][0][e], qq[3][1][e]);
-                const cplx a00 = Md0[a], a01 = Md1[a], a11 = Md2[a];
+                const cplx a00 = Md0[as], a01 = Md1[as], a11 = Md2[as];
                 const cplx ra = crsqrt_p(cfnma(a01, a01, cmul(a00, a11)));
                 const cplx ideta = cmul(ra, ra);
                 const cplx ia00 = cmul(a11, ideta), ia11 = cmul(a00, ideta);
@@ -1232,12 +1295,13 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_pairs_big(
                 const cplx G01 = cfma(ia00, b01, cmul(ia01, b11));
                 const cplx G10 = cfma(ia01, b00, cmul(ia11, b10));
                 const cplx G11 = cfma(ia01, b01, cmul(ia11, b11));
-                const cplx sb00 = csub(Md0[b], cfma(b00, G00, cmul(b10, G10)));
-                const cplx sb01 = csub(Md1[b], cfma(b00, G01, cmul(b10, G11)));
-                const cplx sb11 = csub(Md2[b], cfma(b01, G01, cmul(b11, G11)));
+                const cplx sb00 = csub(Md0[bq], cfma(b00, G00, cmul(b10, G10)));
+                const cplx sb01 = csub(Md1[bq], cfma(b00, G01, cmul(b10, G11)));
+                const cplx sb11 = csub(Md2[bq], cfma(b01, G01, cmul(b11, G11)));
                 const cplx rb = crsqrt_p(cfnma(sb01, sb01, cmul(sb00, sb11)));
                 const cplx cp = cmul(g2, cmul(ra, rb));
-                bs = cadd(bs, cp);
+                const cplx zero = cmk(0.0, 0.0);
+                bs = cadd(bs, ok ? cp : zero);
                 const cplx idetb = cmul(rb, rb);
                 const cplx ib00 = cmul(sb11, idetb), ib11 = cmul(sb00, idetb);
                 const cplx ib01 = cneg(cmul(sb01, idetb));
@@ -1247,27 +1311,55 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_pairs_big(
                 const cplx pa00 = cadd(ia00, cfma(H00, G00, cmul(H01, G01)));
                 const cplx pa01 = cadd(ia01, cfma(H00, G10, cmul(H01, G11)));
                 const cplx pa11 = cadd(ia11, cfma(H10, G10, cmul(H11, G11)));
-                catomic(&Zd0[a], cmul(cp, pa00));
-                catomic(&Zd1[a], cmul(cp, pa01));
-                catomic(&Zd2[a], cmul(cp, pa11));
-                catomic(&Zd0[b], cmul(cp, ib00));
-                catomic(&Zd1[b], cmul(cp, ib01));
-                catomic(&Zd2[b], cmul(cp, ib11));
-                const cplx ncp = cneg(cp);
-                const cplx zxx = cmul(ncp, H00), zxp = cmul(ncp, H01), zpx = cmul(ncp, H10), zpp = cmul(ncp, H11);
-                const int at = ra_ * 16 + l16;
-                t0[at] = zxx;
-                t0[256 + at] = zxp;
-                t0[512 + at] = zpx;
-                t0[768 + at] = zpp;
-                if (I == J) {
-                    // Z(q_b, q'_a) = Z(q'_a, q_b)
-                    const int bt = l16 * 16 + ra_;
-                    t0[bt] = zxx;
-                    t0[256 + bt] = zpx;
-                    t0[512 + bt] = zxp;
-                    t0[768 + bt] = zpp;
+                // row a: the 16 lanes of this lq hold a's partners b
+                cplx d0 = ok ? cmul(cp, pa00) : zero, d1 = ok ? cmul(cp, pa01) : zero;
+                cplx d2 = ok ? cmul(cp, pa11) : zero;
+#pragma unroll
+                for (int off = 1; off < 16; off <<= 1) {
+                    d0 = cadd(d0, cmk(__shfl_xor(d0.re, off), __shfl_xor(d0.im, off)));
+                    d1 = cadd(d1, cmk(__shfl_xor(d1.re, off), __shfl_xor(d1.im, off)));
+                    d2 = cadd(d2, cmk(__shfl_xor(d2.re, off), __shfl_xor(d2.im, off)));
                 }
+                if (l16 == 0) {
+                    cplx *q = Zq + (u * 2) * 48 + ra_ * 3;
+                    q[0] = d0;
+                    q[1] = d1;
+                    q[2] = d2;
+                }
+                if (ok) {
+                    sb0 = cadd(sb0, cmul(cp, ib00));
+                    sb1 = cadd(sb1, cmul(cp, ib01));
+                    sb2 = cadd(sb2, cmul(cp, ib11));
+                    const cplx ncp = cneg(cp);
+                    const cplx zxx = cmul(ncp, H00), zxp = cmul(ncp, H01), zpx = cmul(ncp, H10),
+                               zpp = cmul(ncp, H11);
+                    const int at = ra_ * 16 + l16;
+                    t0[at] = zxx;
+                    t0[256 + at] = zxp;
+                    t0[512 + at] = zpx;
+                    t0[768 + at] = zpp;
+                    if (I == J) {
+                        // Z(q_b, q'_a) = Z(q'_a, q_b)
+                        const int bt = l16 * 16 + ra_;
+                        t0[bt] = zxx;
+                        t0[256 + bt] = zpx;
+                        t0[512 + bt] = zxp;
+                        t0[768 + bt] = zpp;
+                    }
+                }
+            }
+            // row b: the four lq of this l16
+#pragma unroll
+            for (int off = 16; off < 64; off <<= 1) {
+                sb0 = cadd(sb0, cmk(__shfl_xor(sb0.re, off), __shfl_xor(sb0.im, off)));
+                sb1 = cadd(sb1, cmk(__shfl_xor(sb1.re, off), __shfl_xor(sb1.im, off)));
+                sb2 = cadd(sb2, cmk(__shfl_xor(sb2.re, off), __shfl_xor(sb2.im, off)));
+            }
+            if (lq == 0) {
+                cplx *q = Zq + (u * 2 + 1) * 48 + l16 * 3;
+                q[0] = sb0;
+                q[1] = sb1;
+                q[2] = sb2;
             }
         };
         // rows 16 I .. 16 I + 15 of quadrature qr (row block rbi = qr TM + I) of
@@ -1351,9 +1443,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_pairs_big(
                 const cplx c = cmul(g1, r);
                 bsum = cadd(bsum, c);
                 const cplx cid = cmul(c, cmul(r, r));
-                catomic(&Zd0[a], cmul(cid, a11));
-                catomic(&Zd1[a], cneg(cmul(cid, a01)));
-                catomic(&Zd2[a], cmul(cid, a00));
+                Zd0[a] = cmul(cid, a11);
+                Zd1[a] = cneg(cmul(cid, a01));
+                Zd2[a] = cmul(cid, a00);
             }
             // every mode block (I, J), I <= J: quadrant products, then its pairs
             for (int u = wid; u < TM * (TM + 1) / 2; u += NW) {
@@ -1361,7 +1453,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_pairs_big(
                 upper_tile(u, I, J);
                 dbl4 qq[4][2];
                 quad(I, J, qq);
-                pairs(I, J, qq, g2, bsum);
+                pairs(u, I, J, qq, g2, bsum);
             }
             bsum = warp_csum(bsum);
             if (lane == 0) red[wid] = bsum;
@@ -1369,6 +1461,29 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_pairs_big(
             cplx beta = s_g[0];
             for (int i = 0; i < NW; ++i) beta = cadd(beta, red[i]);
             const cplx hw = cscale(w, 0.5);
+            // Z's mode diagonals: the singles' terms plus the pairs' partial sums
+            // of every mode block holding the mode, in a fixed order (so the sum
+            // does not depend on the order the wavefronts ran in)
+            for (int a = tid; a < n; a += CONT_THREADS) {
+                const int Ia = a >> 4, la = a & 15;
+                cplx z0 = Zd0[a], z1 = Zd1[a], z2 = Zd2[a];
+                for (int J = Ia; J < TM; ++J) {
+                    const cplx *q = Zq + ((J * (J + 1) / 2 + Ia) * 2) * 48 + la * 3;
+                    z0 = cadd(z0, q[0]);
+                    z1 = cadd(z1, q[1]);
+                    z2 = cadd(z2, q[2]);
+                }
+                for (int I = 0; I <= Ia; ++I) {
+                    const cplx *q = Zq + ((Ia * (Ia + 1) / 2 + I) * 2 + 1) * 48 + la * 3;
+                    z0 = cadd(z0, q[0]);
+                    z1 = cadd(z1, q[1]);
+                    z2 = cadd(z2, q[2]);
+                }
+                Zd0[a] = z0;
+                Zd1[a] = z1;
+                Zd2[a] = z2;
+            }
+            __syncthreads();
             dbl4 racc[ADJ_PB_RMAX];
 #pragma unroll
             for (int t = 0; t < ADJ_PB_RMAX; ++t) racc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
@@ -1623,6 +1738,51 @@ __global__ __launch_bounds__(1024) void k_adj_items(int P, int nbig, const int *
 }
 
 // ---------------------------------------------------------------------------
+// Psi accumulation.  mode 0: floating-point atomics (the order of the adds,
+// and so the last bits, vary from run to run).  Deterministic gradients run
+// the reduction twice: mode 1 only records the largest |term| (its bit
+// pattern, which orders non-negative doubles; NaN above every number), mode 2
+// adds the terms as 64-bit integers at the power-of-two scale k_det_scale
+// derived from it; k_det_to_double converts Psi back.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void psi_add(double *dst, double s, int mode, unsigned long long *det)
+{
+    if (mode == 0) {
+        atomicAdd(dst, s);
+    } else if (mode == 1) {
+        atomicMax(det, (unsigned long long)__double_as_longlong(fabs(s)));
+    } else {
+        atomicAdd((unsigned long long *)dst, (unsigned long long)llrint(s * __longlong_as_double((long long)det[1])));
+    }
+}
+
+// det[1] = the scale for at most nterm terms per entry (0 when a term was
+// not finite)
+__global__ void k_det_scale(unsigned long long *det, int nterm)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double m = __longlong_as_double((long long)det[0]);
+    double sc = 1.0;
+    if (!(m <= DBL_MAX)) {
+        sc = 0.0;
+    } else if (m > 0.0) {
+        int e = 0;
+        frexp(m, &e);
+        sc = ldexp(1.0, 61 - (ilogb((double)nterm) + 2) - e);
+    }
+    det[1] = (unsigned long long)__double_as_longlong(sc);
+}
+
+__global__ void k_det_to_double(long n, double *x, const unsigned long long *det)
+{
+    const double sc = __longlong_as_double((long long)det[1]);
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const long long v = *(const long long *)&x[i];
+        x[i] = sc > 0.0 ? (double)v / sc : NAN;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_adj_reduce: per row, R = sum of the items' R (fixed order) plus the
 // contour-independent diagonal term of log G_0(rho) and log P_vac(Cbar)
 // (their A^{-1} parts cancel, leaving -w_p rho/2 M(rho)), then A_bar = V R V^T,
@@ -1641,7 +1801,8 @@ __global__ __launch_bounds__(256) void k_adj_reduce(int M, const int *__restrict
                                                     const int *__restrict__ row_item0,
                                                     const long long *__restrict__ roff,
                                                     const double *__restrict__ rscr,
-                                                    double *__restrict__ psi)
+                                                    double *__restrict__ psi, int mode,
+                                                    unsigned long long *__restrict__ det)
 {
     extern __shared__ __attribute__((aligned(16))) double sh[];
     const int p = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
@@ -1689,7 +1850,7 @@ __global__ __launch_bounds__(256) void k_adj_reduce(int M, const int *__restrict
         const int i = idx / N, j = idx - i * N;
         double s = 0.0;
         for (int k = 0; k < N; ++k) s = fma(V[i * N + k], T[k * N + j], s);
-        atomicAdd(&psi[g[i] * D + g[j]], s);
+        psi_add(psi + g[i] * D + g[j], s, mode, det);
     }
 }
 
@@ -1708,7 +1869,8 @@ __global__ __launch_bounds__(256) void k_adj_reduce_big(int M, const int *__rest
                                                         const long long *__restrict__ roff,
                                                         const double *__restrict__ rscr,
                                                         double *__restrict__ wbig,
-                                                        double *__restrict__ psi)
+                                                        double *__restrict__ psi, int mode,
+                                                        unsigned long long *__restrict__ det)
 {
     __shared__ int g[2 * GBS_MAX_N_APPROX];
     const int p = perm[blockIdx.x], tid = threadIdx.x, nt = blockDim.x;
@@ -1749,7 +1911,7 @@ __global__ __launch_bounds__(256) void k_adj_reduce_big(int M, const int *__rest
         const int i = idx / N, j = idx - i * N;
         double s = 0.0;
         for (int k = 0; k < N; ++k) s = fma(Vt[(long)k * N + i], T[(long)k * N + j], s);
-        atomicAdd(&psi[g[i] * D + g[j]], s);
+        psi_add(psi + g[i] * D + g[j], s, mode, det);
     }
 }
 
@@ -1879,7 +2041,9 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
     } else if (pl->nbig > 0) {
         // larger rows: V and M(w) in HBM, Z(w) (all of it at order 3, its diagonal
         // blocks and a 32-row block of it otherwise) in LDS
-        const void *fn = (const void *)k_adj_contour<ORDER, true>;
+        const bool det = ctx->deterministic;
+        const void *fn = det ? (const void *)k_adj_contour<ORDER, true, true>
+                             : (const void *)k_adj_contour<ORDER, true, false>;
         int lds_static = 0;
         if (int rc = func_static_lds(ctx, fn, &lds_static)) return rc;
         const int nb = nmax, npb = nb * (nb - 1) / 2;
@@ -1891,7 +2055,8 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
         if (int rc = func_lds_limit(ctx, fn, lds_b)) return rc;
         if (int rc = func_occupancy(ctx, fn, CONT_THREADS, lds_b, &occ)) return rc;
         int grid = std::min(occ * ctx->num_cu, pl->ascr_blocks);
-        hipLaunchKernelGGL((k_adj_contour<ORDER, true>), dim3(grid), dim3(CONT_THREADS), lds_b, st,
+        hipLaunchKernelGGL((det ? k_adj_contour<ORDER, true, true> : k_adj_contour<ORDER, true, false>),
+                           dim3(grid), dim3(CONT_THREADS), lds_b, st,
                            pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, pl->d_aitems,
                            pl->d_counter + 8 + GBS_NXCD, pl->d_counter + 8,
                            pl->d_cluster_items, pl->d_cluster_off + 2 * (pl->max_n + 1),
@@ -1900,7 +2065,9 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
     }
     const int ns = pl->max_n_small;
     if (pl->nbig < P) {
-        const void *fn = (const void *)k_adj_contour<ORDER, false>;
+        const bool det = ctx->deterministic;
+        const void *fn = det ? (const void *)k_adj_contour<ORDER, false, true>
+                             : (const void *)k_adj_contour<ORDER, false, false>;
         int lds_static = 0;
         if (int rc = func_static_lds(ctx, fn, &lds_static)) return rc;
         int lds_a = 0;
@@ -1911,7 +2078,8 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
         int occ = 1;
         if (int rc = func_lds_limit(ctx, fn, lds_a)) return rc;
         if (int rc = func_occupancy(ctx, fn, CONT_THREADS, lds_a, &occ)) return rc;
-        hipLaunchKernelGGL((k_adj_contour<ORDER, false>), dim3(occ * ctx->num_cu), dim3(CONT_THREADS),
+        hipLaunchKernelGGL((det ? k_adj_contour<ORDER, false, true> : k_adj_contour<ORDER, false, false>),
+                           dim3(occ * ctx->num_cu), dim3(CONT_THREADS),
                            lds_a, st, pl->d_offsets, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows,
                            pl->d_aitems, pl->d_counter + 2, pl->d_counter + 3,
                            pl->d_cluster_items, pl->d_cluster_off + 2 * (pl->max_n + 1),
@@ -1922,18 +2090,29 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
     ts = timer_begin(ctx, TG_ADJ_ROWS);
     const int D = 2 * M;
     hipLaunchKernelGGL(k_zero, dim3((D * D + 255) / 256), dim3(256), 0, st, (long)D * D, pl->d_qibar);
-    if (pl->nbig < P) {
-        const int N = 2 * ns;
-        size_t lds_r = sizeof(double) * 3 * (size_t)N * N + sizeof(int) * N;
-        if (int rc = func_lds_limit(ctx, (const void *)k_adj_reduce, (int)lds_r)) return rc;
-        hipLaunchKernelGGL(k_adj_reduce, dim3(P), dim3(256), lds_r, st, M, pl->d_offsets, pl->d_modes,
-                           pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, dl, status, pl->d_ritem0,
-                           pl->d_roff, pl->d_rscr, pl->d_qibar);
+    // deterministic gradients: the reduction twice (largest term, then the
+    // terms as integers at the scale it fixes), Psi then back to doubles
+    const bool det = ctx->deterministic;
+    if (det) hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, 2L, (double *)pl->d_det);
+    for (int mode = det ? 1 : 0; mode <= (det ? 2 : 0); ++mode) {
+        if (mode == 2) hipLaunchKernelGGL(k_det_scale, dim3(1), dim3(64), 0, st, pl->d_det, P);
+        if (pl->nbig < P) {
+            const int N = 2 * ns;
+            size_t lds_r = sizeof(double) * 3 * (size_t)N * N + sizeof(int) * N;
+            if (int rc = func_lds_limit(ctx, (const void *)k_adj_reduce, (int)lds_r)) return rc;
+            hipLaunchKernelGGL(k_adj_reduce, dim3(P), dim3(256), lds_r, st, M, pl->d_offsets, pl->d_modes,
+                               pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, dl, status, pl->d_ritem0,
+                               pl->d_roff, pl->d_rscr, pl->d_qibar, mode, pl->d_det);
+        }
+        if (pl->nbig > 0)
+            hipLaunchKernelGGL(k_adj_reduce_big, dim3(pl->nbig), dim3(256), 0, st, M, pl->d_offsets,
+                               pl->d_modes, pl->d_perm, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, dl,
+                               status, pl->d_ritem0, pl->d_roff, pl->d_rscr, pl->d_wbig, pl->d_qibar, mode,
+                               pl->d_det);
     }
-    if (pl->nbig > 0)
-        hipLaunchKernelGGL(k_adj_reduce_big, dim3(pl->nbig), dim3(256), 0, st, M, pl->d_offsets,
-                           pl->d_modes, pl->d_perm, pl->d_voff, pl->d_alpha, pl->d_v, pl->d_rows, dl,
-                           status, pl->d_ritem0, pl->d_roff, pl->d_rscr, pl->d_wbig, pl->d_qibar);
+    if (det)
+        hipLaunchKernelGGL(k_det_to_double, dim3((D * D + 255) / 256), dim3(256), 0, st, (long)D * D,
+                           pl->d_qibar, pl->d_det);
     timer_end(ctx, ts);
     ts = timer_begin(ctx, TG_ADJ_MODEL);
     hipLaunchKernelGGL(k_adj_model, dim3(1), dim3(1024), 0, st, M, P, m.qi_hi, m.params, dl,
@@ -1950,11 +2129,12 @@ int backward_order(gbs_ctx *ctx, gbs_plan *pl, const double *dl, const int32_t *
 int adj_workspace(gbs_ctx *ctx, gbs_plan *pl);
 
 // complex entries of k_adj_pairs_big's per-workgroup scratch for rows of up to
-// n clicks: the four 16 x 16 planes of each upper 16 x 16 mode block of Z(w)
+// n clicks: the four 16 x 16 planes of each upper 16 x 16 mode block of Z(w),
+// then each block's partial sums of Z's mode diagonals (2 x 16 x 3)
 long long adj_pair_scratch(int n)
 {
     const long long tm = (n + 15) / 16;
-    return tm * (tm + 1) / 2 * 4 * 256;
+    return tm * (tm + 1) / 2 * (4 * 256 + 96);
 }
 
 int approx_backward(gbs_ctx *ctx, gbs_plan *pl, const double *dl_dev, const int32_t *status_dev,

@@ -66,6 +66,7 @@ struct gbs_ctx {
     int num_cu = 0;
     int lds_per_block = 65536;  // largest LDS allocation of one workgroup (bytes)
     bool timing = false;
+    bool deterministic = false;  // gradients summed in a fixed order (gbs_set_deterministic)
     std::vector<TimedLaunch> timeline;
     std::vector<hipEvent_t> event_pool;
     // per-kernel launch facts, queried once: a launch then makes no call besides
@@ -143,6 +144,8 @@ struct gbs_plan {
     // (P + 1) and rows (nnz); the exact path's p and log p (P each)
     int32_t *d_da = nullptr;
     double *d_da_x = nullptr;
+    // deterministic gradients: the largest term into Psi (bit pattern), its scale
+    unsigned long long *d_det = nullptr;
     int32_t *d_status = nullptr;          // P
     size_t v_total = 0;
     int max_items = 0;

@@ -27,7 +27,7 @@ EXPORTS = ["gbs_create", "gbs_destroy", "gbs_last_error", "gbs_set_model", "gbs_
            "gbs_plan_create", "gbs_plan_destroy", "gbs_plan_freeze", "gbs_prob_approx_dev",
            "gbs_grad", "gbs_grad_dev", "gbs_plan_info", "gbs_set_timing", "gbs_timing",
            "gbs_stream", "gbs_click_distribution", "gbs_prob_exact_dev", "gbs_prob_exact_dev_noalloc",
-           "gbs_mcmc_step_dev", "gbs_mcmc_da_step_dev"]
+           "gbs_mcmc_step_dev", "gbs_mcmc_da_step_dev", "gbs_set_deterministic"]
 TIMING_GROUPS = ["model", "row_setup", "work_queue", "contour_clusters", "dft_fit", "exact",
                  "adjoint_fit_dft", "adjoint_contour_clusters", "adjoint_rows_scatter",
                  "adjoint_model", "second_pass"]
@@ -84,6 +84,7 @@ def load(path: str = LIB_PATH):
         "gbs_prob_exact_dev_noalloc": ([vp, ip, i32p, i32p, ip, dp, dp, dp, i32p], ip),
         "gbs_mcmc_step_dev": ([vp, vp, dp, i32p, dp, i32p], ip),
         "gbs_mcmc_da_step_dev": ([vp, vp, dp, i32p, dp, dp, i32p], ip),
+        "gbs_set_deterministic": ([vp, ip], ip),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -317,6 +318,10 @@ class Context:
                                                     _dptr(modes_dev, "int32", plan.nnz, "modes"),
                                                     _dptr(logp_dev, "float64", P, "logp"),
                                                     _dptr(accepted_dev, "int32", P, "accepted")))
+
+    def gbs_set_deterministic(self, on: bool):
+        """Gradients summed in a fixed order (bitwise reproducible) or not."""
+        return self._check(load().gbs_set_deterministic(self.handle, 1 if on else 0))
 
     def gbs_mcmc_da_step_dev(self, plan: Plan, u_dev, modes_dev, logp_hat_dev, logp_exact_dev, accepted_dev=None):
         """One two-stage step of the plan's chains, target the exact p (device

@@ -11,6 +11,9 @@ Tolerance: relative 1e-4 of the largest gradient component (finite differences
 at h = 1e-5 carry ~1e-8 truncation and ~1e-6 rounding from the 1e-11 spread of
 the forward values).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -221,3 +224,60 @@ def test_grad_run_to_run_spread(gpu_ctx):
         spread = max(spread, float(np.max(np.abs(g - g0))) / scale)
     print(f"gradient run-to-run spread: {spread:.2e} of the largest component")
     assert spread < 1e-12
+
+
+@pytest.mark.parametrize("cfg,P,order", [(3, 512, 3), (2, 512, 4), (2, 512, 1), (4, 64, 3), (5, 48, 2)])
+def test_deterministic_gradients(gpu_ctx, cfg, P, order):
+    """With gbs_set_deterministic on, three calls give bit-identical gradients
+    (70 modes at order 3; 20 modes at orders 4 and 1; the first rows of the
+    100-mode batch at order 3 and of the 144-mode batch at order 2, whose rows
+    above 40 clicks take the large-row kernels), and they agree with the
+    floating-point sums to 1e-9 of the largest component.  That bound is the
+    fixed-point resolution: each point's Z(w) adds its cluster terms at a scale
+    that leaves room for one term per cluster holding an entry's mode, about
+    2^-50 of the point's largest term for 60-click rows at order 3, and the
+    contour sum cancels those terms as it cancels the floating-point ones
+    (measured: 4e-12 at 70 modes, 4e-10 for the 100-mode rows)."""
+    wl = make_workload(cfg, P=P)
+    gpu_ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    w = np.random.default_rng(11).uniform(0.5, 1.5, wl.P)
+    refs = [gpu_ctx.gbs_grad(wl.offsets, wl.modes, order, w) for _ in range(3)]
+    ref = refs[0]
+    fl = [np.concatenate([o["grad_r"], o["grad_eta"]]) for o in refs]
+    spread = max(float(np.max(np.abs(f - fl[0]))) for f in fl[1:])
+    try:
+        gpu_ctx.gbs_set_deterministic(True)
+        outs = [gpu_ctx.gbs_grad(wl.offsets, wl.modes, order, w) for _ in range(3)]
+    finally:
+        gpu_ctx.gbs_set_deterministic(False)
+    g0 = np.concatenate([outs[0]["grad_r"], outs[0]["grad_eta"]])
+    assert np.all(np.isfinite(g0)) and np.all(outs[0]["status"] == ref["status"])
+    for o in outs[1:]:
+        g = np.concatenate([o["grad_r"], o["grad_eta"]])
+        assert np.array_equal(g, g0)
+        assert np.array_equal(o["logp"], outs[0]["logp"])
+    gr = fl[0]
+    scale = np.max(np.abs(gr))
+    dev = float(np.max(np.abs(g0 - gr)))
+    print(f"deterministic vs floating-point: {dev / scale:.2e}, floating-point spread {spread / scale:.2e}")
+    assert dev < 1e-9 * scale, (dev / scale, spread / scale)
+
+
+def test_deterministic_vs_reference_gradient(gpu_ctx):
+    """Deterministic mode against the oracle's reference gradient (torch fp64
+    autograd through the power-series oracle, tests/golden/grad_rows.json):
+    144 modes at order 2, five rows of 40-110 clicks, every component within
+    1e-7 of the largest, the bar the floating-point path is held to."""
+    rec = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "grad_rows.json")))
+    wl = make_workload(5).subset(rec["rows"])
+    gpu_ctx.gbs_set_model(wl.U, wl.r, wl.eta)
+    try:
+        gpu_ctx.gbs_set_deterministic(True)
+        out = gpu_ctx.gbs_grad(wl.offsets, wl.modes, 2, np.array(rec["weights"]))
+    finally:
+        gpu_ctx.gbs_set_deterministic(False)
+    assert np.all(out["status"] == 0), out["status"]
+    g = np.concatenate([out["grad_r"], out["grad_eta"]])
+    ref = np.concatenate([rec["grad_r"], rec["grad_eta"]])
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(g - ref)) < 1e-7 * scale, np.max(np.abs(g - ref)) / scale
