@@ -211,7 +211,7 @@ static_assert(2 * GBS_NSMALL <= ADJ_TP, "padded V must hold the rows kept in LDS
 #define ADJ_OS (GBS_NSMALL * (GBS_NSMALL - 1) / 2)
 #define ADJ_MREG (3 * ADJ_DS + 4 * ADJ_OS)
 static_assert(ADJ_MREG >= 8 * ADJ_TMAX * (16 * ADJ_TMAX + 1), "the M(w) region holds the packed Z");
-// V, alpha, d, rz, the M(w) region and the Z(w) blocks
+// the Z(w) blocks, the M(w) region, V, alpha, d and rz
 __host__ __device__ __forceinline__ int adj_need(int)
 {
     return 8 * (ADJ_TP * ADJ_VS + ADJ_TP) + 16 * (2 * ADJ_TP + 2 * ADJ_MREG);
@@ -400,13 +400,15 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 Zs = Zd0 + 3 * n;
             }
         } else {
-            double *vl = dyn;
+            // Z(w) first, then M(w), V, alpha, d, rz: every entry of Z then lies
+            // within the 64 KB immediate offset of its LDS adds
+            Zd0 = (cplx *)dyn;
+            Zo0 = Zd0 + 3 * ADJ_DS;
+            Md0 = Zd0 + ADJ_MREG;
+            double *vl = (double *)(Md0 + ADJ_MREG);
             al = vl + ADJ_TP * ADJ_VS;
             dk = (cplx *)(al + ADJ_TP);
             rz = dk + ADJ_TP;
-            Md0 = rz + ADJ_TP;
-            Zd0 = Md0 + ADJ_MREG;
-            Zo0 = Zd0 + 3 * ADJ_DS;
             Yp = nullptr;  // (no panel: Y stays in registers)
             for (int idx = tid; idx < ADJ_TP * ADJ_VS; idx += CONT_THREADS) {
                 const int k = idx / ADJ_VS, i = idx - k * ADJ_VS;
@@ -435,24 +437,31 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         // do not depend on the order of the adds), converted back after it.
         int zpass = 1;
         double zmax = 0.0, zsc = 1.0;
-        auto zadd = [&](cplx *p, cplx v) {
+        // (entries are addressed by their complex index from Zd0, so that the
+        // arrays' fixed strides become immediate offsets of the LDS adds)
+        auto zadd = [&](int idx, cplx v) {
             if constexpr (DET) {
                 if (zpass == 0) {
                     const double m = fmax(fabs(v.re), fabs(v.im));
                     zmax = m <= DBL_MAX ? fmax(zmax, m) : INFINITY;  // (NaN or inf: non-finite)
                     return;
                 }
-                unsigned long long *zr = (unsigned long long *)Zd0 + (ZPLANES ? p - Zd0 : 2 * (p - Zd0));
+                unsigned long long *zr = (unsigned long long *)Zd0 + (ZPLANES ? idx : 2 * idx);
                 atomicAdd(zr, (unsigned long long)llrint(v.re * zsc));
                 atomicAdd(zr + (ZPLANES ? zplane : 1), (unsigned long long)llrint(v.im * zsc));
             } else if constexpr (ZPLANES) {
-                double *zr = (double *)Zd0 + (p - Zd0);
+                double *zr = (double *)Zd0 + idx;
                 atomicAdd(zr, v.re);
                 atomicAdd(zr + zplane, v.im);
             } else {
-                catomic(p, v);
+                catomic(Zd0 + idx, v);
             }
         };
+        // diagonal-block array k at mode x; pair-block array k at pair position q
+        // (the pair blocks follow the diagonal ones wherever they are added into)
+        const int zoff = BIG ? 3 * n : 3 * ADJ_DS;
+        auto zd = [&](int k, int x, cplx v) { zadd(k * dstr + x, v); };
+        auto zo = [&](int k, int q, cplx v) { zadd(zoff + k * ostr + q, v); };
         for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
         const int Qn = rp.K / 2 + 1;
         constexpr int QCH = BIG ? GBS_ADJ_CHUNK_BIG : ADJ_QCHUNK;
@@ -555,9 +564,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                     const cplx id = cmul(r, r);
                     bsum = cadd(bsum, c);
                     const cplx cid = cmul(c, id);
-                    zadd(&Zd0[a], cmul(cid, a11));
-                    zadd(&Zd1[a], cscale(cmul(cid, a01), -1.0));
-                    zadd(&Zd2[a], cmul(cid, a00));
+                    zd(0, a, cmul(cid, a11));
+                    zd(1, a, cscale(cmul(cid, a01), -1.0));
+                    zd(2, a, cmul(cid, a00));
                 }
                 if (ORDER >= 2) {
                     const cplx g2 = s_g[2 <= ORDER ? 2 : 0];
@@ -599,11 +608,22 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                              A11 = cmk(0, 0), A12 = cmk(0, 0), A13 = cmk(0, 0), A22 = cmk(0, 0),
                              A23 = cmk(0, 0), A33 = cmk(0, 0);
                         if (ORDER >= 3) {
+                            // (pair positions stepped along c: pos(x, c + 1) = pos(x, c) + n - (c - x))
+                            int cur_ac = pair_pos<true>(n, a, c0), cur_bc = pair_pos<true>(n, b, c0);
     #pragma unroll 1
-                            for (int c = c0; c < c1; ++c) {
-                                const int cur_ac = pair_pos<true>(n, a, c), cur_bc = pair_pos<true>(n, b, c);
-                                const cplx x00 = Mo0[cur_ac], x01 = Mo1[cur_ac], x10 = Mo2[cur_ac], x11 = Mo3[cur_ac];
-                                const cplx yy00 = Mo0[cur_bc], yy01 = Mo1[cur_bc], yy10 = Mo2[cur_bc], yy11 = Mo3[cur_bc];
+                            for (int c = c0; c < c1; cur_ac += n - (c - a), cur_bc += n - (c - b), ++c) {
+                                const cplx *xa = Mo0 + cur_ac, *xb = Mo0 + cur_bc;
+                                if constexpr (!BIG) {
+                                    // (indices from the LDS base, kept opaque, so that each
+                                    // position's address is formed once and the arrays'
+                                    // fixed strides ride as immediate offsets)
+                                    int ia_ = ADJ_MREG + 3 * ADJ_DS + cur_ac, ib_ = ADJ_MREG + 3 * ADJ_DS + cur_bc;
+                                    asm("" : "+v"(ia_), "+v"(ib_));
+                                    xa = Zd0 + ia_;
+                                    xb = Zd0 + ib_;
+                                }
+                                const cplx x00 = xa[0], x01 = xa[ostr], x10 = xa[2 * ostr], x11 = xa[3 * ostr];
+                                const cplx yy00 = xb[0], yy01 = xb[ostr], yy10 = xb[2 * ostr], yy11 = xb[3 * ostr];
                                 const cplx m00 = Md0[c], m01 = Md1[c], m11 = Md2[c];
                                 // Za = Maa^{-1} Xa, Y = Xb - G^T Xa, W = Sb^{-1} Y,
                                 // Sc = Mcc - Xa^T Za - Y^T W, U = [Za - G W ; W]
@@ -639,9 +659,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                                     is11 = cmul(sc00, k);
                                     is01 = cmul(cneg(sc01), k);
                                 }
-                                zadd(&Zd0[c], is00);
-                                zadd(&Zd1[c], is01);
-                                zadd(&Zd2[c], is11);
+                                zd(0, c, is00);
+                                zd(1, c, is01);
+                                zd(2, c, is11);
                                 // rows a: U_a = Za - G W, then Q_a = -P_a = -U_a c_T Sc^{-1}
                                 // (formed with the sign the Z blocks take, so that no
                                 // negated copy has to be made for the LDS adds)
@@ -653,10 +673,10 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                                 const cplx Q01 = cfnma(U00, is01, cmul(cneg(U01), is11));
                                 const cplx Q10 = cfnma(U10, is00, cmul(cneg(U11), is01));
                                 const cplx Q11 = cfnma(U10, is01, cmul(cneg(U11), is11));
-                                zadd(&Zo0[cur_ac], Q00);
-                                zadd(&Zo1[cur_ac], Q01);
-                                zadd(&Zo2[cur_ac], Q10);
-                                zadd(&Zo3[cur_ac], Q11);
+                                zo(0, cur_ac, Q00);
+                                zo(1, cur_ac, Q01);
+                                zo(2, cur_ac, Q10);
+                                zo(3, cur_ac, Q11);
                                 A00 = cfnma(Q00, U00, cfnma(Q01, U01, A00));
                                 A01 = cfnma(Q00, U10, cfnma(Q01, U11, A01));
                                 A11 = cfnma(Q10, U10, cfnma(Q11, U11, A11));
@@ -669,10 +689,10 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                                 const cplx Q21 = cfnma(W00, is01, cmul(cneg(W01), is11));
                                 const cplx Q30 = cfnma(W10, is00, cmul(cneg(W11), is01));
                                 const cplx Q31 = cfnma(W10, is01, cmul(cneg(W11), is11));
-                                zadd(&Zo0[cur_bc], Q20);
-                                zadd(&Zo1[cur_bc], Q21);
-                                zadd(&Zo2[cur_bc], Q30);
-                                zadd(&Zo3[cur_bc], Q31);
+                                zo(0, cur_bc, Q20);
+                                zo(1, cur_bc, Q21);
+                                zo(2, cur_bc, Q30);
+                                zo(3, cur_bc, Q31);
                                 A22 = cfnma(Q20, W00, cfnma(Q21, W01, A22));
                                 A23 = cfnma(Q20, W10, cfnma(Q21, W11, A23));
                                 A33 = cfnma(Q30, W10, cfnma(Q31, W11, A33));
@@ -686,9 +706,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                         const cplx pa00 = cadd(ia00, cfma(H00, G00, cmul(H01, G01)));
                         const cplx pa01 = cadd(ia01, cfma(H00, G10, cmul(H01, G11)));
                         const cplx pa11 = cadd(ia11, cfma(H10, G10, cmul(H11, G11)));
-                        zadd(&Zd0[a], cfma(cp, pa00, A00));
-                        zadd(&Zd1[a], cfma(cp, pa01, A01));
-                        zadd(&Zd2[a], cfma(cp, pa11, A11));
+                        zd(0, a, cfma(cp, pa00, A00));
+                        zd(1, a, cfma(cp, pa01, A01));
+                        zd(2, a, cfma(cp, pa11, A11));
                         if (BIG && ORDER <= 2) {
                             // one unit per pair: the pair block has a single writer
                             Zo0[pi] = cfnma(cp, H00, A02);
@@ -696,14 +716,14 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                             Zo2[pi] = cfnma(cp, H10, A12);
                             Zo3[pi] = cfnma(cp, H11, A13);
                         } else {
-                            zadd(&Zo0[pi], cfnma(cp, H00, A02));
-                            zadd(&Zo1[pi], cfnma(cp, H01, A03));
-                            zadd(&Zo2[pi], cfnma(cp, H10, A12));
-                            zadd(&Zo3[pi], cfnma(cp, H11, A13));
+                            zo(0, pi, cfnma(cp, H00, A02));
+                            zo(1, pi, cfnma(cp, H01, A03));
+                            zo(2, pi, cfnma(cp, H10, A12));
+                            zo(3, pi, cfnma(cp, H11, A13));
                         }
-                        zadd(&Zd0[b], cfma(cp, ib00, A22));
-                        zadd(&Zd1[b], cfma(cp, ib01, A23));
-                        zadd(&Zd2[b], cfma(cp, ib11, A33));
+                        zd(0, b, cfma(cp, ib00, A22));
+                        zd(1, b, cfma(cp, ib01, A23));
+                        zd(2, b, cfma(cp, ib11, A33));
                     }
                 }
                 if constexpr (ORDER >= 4) {
@@ -723,16 +743,16 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                         return Blk{Mo0[q], Mo1[q], Mo2[q], Mo3[q]};
                     };
                     auto zdiag = [&](int x, const Sym &v) {
-                        zadd(&Zd0[x], v.a);
-                        zadd(&Zd1[x], v.b);
-                        zadd(&Zd2[x], v.d);
+                        zd(0, x, v.a);
+                        zd(1, x, v.b);
+                        zd(2, x, v.d);
                     };
                     auto zpair = [&](int x, int y, const Blk &v) {
                         const int q = pair_pos<true>(n, x, y);
-                        zadd(&Zo0[q], v.a);
-                        zadd(&Zo1[q], v.b);
-                        zadd(&Zo2[q], v.c);
-                        zadd(&Zo3[q], v.d);
+                        zo(0, q, v.a);
+                        zo(1, q, v.b);
+                        zo(2, q, v.c);
+                        zo(3, q, v.d);
                     };
                     const int *un4 = units + unit4_off[2 * n];
                     const int nu4 = unit4_off[2 * n + 1];
