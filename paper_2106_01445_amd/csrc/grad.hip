@@ -599,6 +599,14 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                         const cplx idetb = cmul(rb, rb);
                         const cplx ib00 = cmul(sb11, idetb), ib11 = cmul(sb00, idetb);
                         const cplx ib01 = cscale(cmul(sb01, idetb), -1.0);
+                        // P^{-1} = [[ia + G ib G^T, -G ib], [-ib G^T, ib]]: its a block
+                        // pa, its (a, b) block nH = -G ib (rows x_a, p_a), and ib
+                        const cplx H00 = cfma(ib00, G00, cmul(ib01, G01)), H01 = cfma(ib01, G00, cmul(ib11, G01));
+                        const cplx H10 = cfma(ib00, G10, cmul(ib01, G11)), H11 = cfma(ib01, G10, cmul(ib11, G11));
+                        const cplx pa00 = cadd(ia00, cfma(H00, G00, cmul(H01, G01)));
+                        const cplx pa01 = cadd(ia01, cfma(H00, G10, cmul(H01, G11)));
+                        const cplx pa11 = cadd(ia11, cfma(H10, G10, cmul(H11, G11)));
+                        const cplx nH00 = cneg(H00), nH01 = cneg(H01), nH10 = cneg(H10), nH11 = cneg(H11);
                         // coefficient of P^{-1} (the pair itself, carried by its first unit,
                         // plus the unit's triples) and the pair block of
                         // sum_c c_T U Sc^{-1} U^T (4x4 symmetric, 10 entries)
@@ -625,29 +633,20 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                                 const cplx x00 = xa[0], x01 = xa[ostr], x10 = xa[2 * ostr], x11 = xa[3 * ostr];
                                 const cplx yy00 = xb[0], yy01 = xb[ostr], yy10 = xb[2 * ostr], yy11 = xb[3 * ostr];
                                 const cplx m00 = Md0[c], m01 = Md1[c], m11 = Md2[c];
-                                // Za = Maa^{-1} Xa, Y = Xb - G^T Xa, W = Sb^{-1} Y,
-                                // Sc = Mcc - Xa^T Za - Y^T W, U = [Za - G W ; W]
-                                cplx Z00, Z01, Z10, Z11, W00, W01, W10, W11, sc00, sc01, sc11;
-                                {
-                                    Z00 = cfma(ia00, x00, cmul(ia01, x10));
-                                    Z10 = cfma(ia01, x00, cmul(ia11, x10));
-                                    Z01 = cfma(ia00, x01, cmul(ia01, x11));
-                                    Z11 = cfma(ia01, x01, cmul(ia11, x11));
-                                    sc00 = csub(m00, cfma(x00, Z00, cmul(x10, Z10)));
-                                    sc01 = csub(m01, cfma(x00, Z01, cmul(x10, Z11)));
-                                    sc11 = csub(m11, cfma(x01, Z01, cmul(x11, Z11)));
-                                    const cplx Y00 = csub(yy00, cfma(G00, x00, cmul(G10, x10)));
-                                    const cplx Y10 = csub(yy10, cfma(G01, x00, cmul(G11, x10)));
-                                    W00 = cfma(ib00, Y00, cmul(ib01, Y10));
-                                    W10 = cfma(ib01, Y00, cmul(ib11, Y10));
-                                    sc00 = csub(sc00, cfma(Y00, W00, cmul(Y10, W10)));
-                                    const cplx Y01 = csub(yy01, cfma(G00, x01, cmul(G10, x11)));
-                                    const cplx Y11 = csub(yy11, cfma(G01, x01, cmul(G11, x11)));
-                                    W01 = cfma(ib00, Y01, cmul(ib01, Y11));
-                                    W11 = cfma(ib01, Y01, cmul(ib11, Y11));
-                                    sc01 = csub(sc01, cfma(Y00, W01, cmul(Y10, W11)));
-                                    sc11 = csub(sc11, cfma(Y01, W01, cmul(Y11, W11)));
-                                }
+                                // U = P^{-1} B for B = [Xa; Xb] (rows x_a, p_a, x_b, p_b;
+                                // columns x_c, p_c): rows a (U) and rows b (W); then
+                                // Sc = Mcc - B^T U
+                                const cplx U00 = cfma(pa00, x00, cfma(pa01, x10, cfma(nH00, yy00, cmul(nH01, yy10))));
+                                const cplx U01 = cfma(pa00, x01, cfma(pa01, x11, cfma(nH00, yy01, cmul(nH01, yy11))));
+                                const cplx U10 = cfma(pa01, x00, cfma(pa11, x10, cfma(nH10, yy00, cmul(nH11, yy10))));
+                                const cplx U11 = cfma(pa01, x01, cfma(pa11, x11, cfma(nH10, yy01, cmul(nH11, yy11))));
+                                const cplx W00 = cfma(nH00, x00, cfma(nH10, x10, cfma(ib00, yy00, cmul(ib01, yy10))));
+                                const cplx W01 = cfma(nH00, x01, cfma(nH10, x11, cfma(ib00, yy01, cmul(ib01, yy11))));
+                                const cplx W10 = cfma(nH01, x00, cfma(nH11, x10, cfma(ib01, yy00, cmul(ib11, yy10))));
+                                const cplx W11 = cfma(nH01, x01, cfma(nH11, x11, cfma(ib01, yy01, cmul(ib11, yy11))));
+                                const cplx sc00 = cfnma(x00, U00, cfnma(x10, U10, cfnma(yy00, W00, cfnma(yy10, W10, m00))));
+                                const cplx sc01 = cfnma(x00, U01, cfnma(x10, U11, cfnma(yy00, W01, cfnma(yy10, W11, m01))));
+                                const cplx sc11 = cfnma(x01, U01, cfnma(x11, U11, cfnma(yy01, W01, cfnma(yy11, W11, m11))));
                                 const cplx rc = crsqrt_p(cfnma(sc01, sc01, cmul(sc00, sc11)));
                                 const cplx ct = cmul(g3, cmul(rab, rc));
                                 bsum = cadd(bsum, ct);
@@ -662,13 +661,9 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                                 zd(0, c, is00);
                                 zd(1, c, is01);
                                 zd(2, c, is11);
-                                // rows a: U_a = Za - G W, then Q_a = -P_a = -U_a c_T Sc^{-1}
-                                // (formed with the sign the Z blocks take, so that no
-                                // negated copy has to be made for the LDS adds)
-                                const cplx U00 = csub(Z00, cfma(G00, W00, cmul(G01, W10)));
-                                const cplx U01 = csub(Z01, cfma(G00, W01, cmul(G01, W11)));
-                                const cplx U10 = csub(Z10, cfma(G10, W00, cmul(G11, W10)));
-                                const cplx U11 = csub(Z11, cfma(G10, W01, cmul(G11, W11)));
+                                // rows a: Q_a = -P_a = -U_a c_T Sc^{-1} (formed with the
+                                // sign the Z blocks take, so that no negated copy has to
+                                // be made for the LDS adds)
                                 const cplx Q00 = cfnma(U00, is00, cmul(cneg(U01), is01));
                                 const cplx Q01 = cfnma(U00, is01, cmul(cneg(U01), is11));
                                 const cplx Q10 = cfnma(U10, is00, cmul(cneg(U11), is01));
@@ -699,13 +694,6 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                                 cp = cadd(cp, ct);
                             }
                         }
-                        // P^{-1} = [[ia + G ib G^T, -G ib], [-ib G^T, ib]]
-                        const cplx H00 = cfma(ib00, G00, cmul(ib01, G01)), H01 = cfma(ib01, G00, cmul(ib11, G01));
-                        const cplx H10 = cfma(ib00, G10, cmul(ib01, G11)), H11 = cfma(ib01, G10, cmul(ib11, G11));
-                        // (G ib) rows: row0 = (H00, H01), row1 = (H10, H11)
-                        const cplx pa00 = cadd(ia00, cfma(H00, G00, cmul(H01, G01)));
-                        const cplx pa01 = cadd(ia01, cfma(H00, G10, cmul(H01, G11)));
-                        const cplx pa11 = cadd(ia11, cfma(H10, G10, cmul(H11, G11)));
                         zd(0, a, cfma(cp, pa00, A00));
                         zd(1, a, cfma(cp, pa01, A01));
                         zd(2, a, cfma(cp, pa11, A11));
