@@ -370,13 +370,16 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                             const C ib00 = cmul(sb11, idetb), ib11 = cmul(sb00, idetb);
                             const C ib01 = cneg(cmul(sb01, idetb));
                             cplx s3p = cmk(0, 0);
+                            // (column offsets stepped along c: (c + 1) c / 2 = c (c - 1) / 2 + c)
+                            int cb = c0 * (c0 - 1) / 2;
 #pragma unroll 1
-                            for (int c = c0; c < c1; ++c) {
-                                const int cb = c * (c - 1) / 2;
+                            for (int c = c0; c < c1; cb += c, ++c) {
                                 const int iac = cb + a, ibc = cb + b;
                                 // Sc = Mcc - Xa^T Maa^{-1} Xa - Y^T Sb^{-1} Y, Y = Xb - G^T Xa,
-                                // evaluated so that each intermediate dies early
+                                // evaluated so that each intermediate dies early (the
+                                // blocks are all read first, so that their LDS reads overlap)
                                 const C x00 = m.o0[iac], x01 = m.o1[iac], x10 = m.o2[iac], x11 = m.o3[iac];
+                                const C y00 = m.o0[ibc], y01 = m.o1[ibc], y10 = m.o2[ibc], y11 = m.o3[ibc];
                                 C sc00 = m.d0[c], sc01 = m.d1[c], sc11 = m.d2[c];
                                 {
                                     const C Z00 = cfma(ia00, x00, cmul(ia01, x10));
@@ -387,10 +390,10 @@ __global__ __launch_bounds__(CONT_THREADS) void k_contour(
                                     sc01 = csub(sc01, cfma(x00, Z01, cmul(x10, Z11)));
                                     sc11 = csub(sc11, cfma(x01, Z01, cmul(x11, Z11)));
                                 }
-                                const C Y00 = csub(m.o0[ibc], cfma(G00, x00, cmul(G10, x10)));
-                                const C Y01 = csub(m.o1[ibc], cfma(G00, x01, cmul(G10, x11)));
-                                const C Y10 = csub(m.o2[ibc], cfma(G01, x00, cmul(G11, x10)));
-                                const C Y11 = csub(m.o3[ibc], cfma(G01, x01, cmul(G11, x11)));
+                                const C Y00 = csub(y00, cfma(G00, x00, cmul(G10, x10)));
+                                const C Y01 = csub(y01, cfma(G00, x01, cmul(G10, x11)));
+                                const C Y10 = csub(y10, cfma(G01, x00, cmul(G11, x10)));
+                                const C Y11 = csub(y11, cfma(G01, x01, cmul(G11, x11)));
                                 {
                                     const C W00 = cfma(ib00, Y00, cmul(ib01, Y10));
                                     const C W10 = cfma(ib01, Y00, cmul(ib11, Y10));

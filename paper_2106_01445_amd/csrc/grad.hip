@@ -1060,6 +1060,8 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                             const cplx g = cmul(hw, dk[i]);
 #pragma unroll
                             for (int e = 0; e < 4; ++e) {
+                                // (rows of Y from 2n on are zero: their k-steps are skipped)
+                                if (rt * 16 + 4 * e >= N) continue;
                                 const int rr = rt * 16 + 4 * e + lq;
                                 const double av = Vt[i * vs + rr];
                                 racc[it] = mfma4(g.re * av, ure[e], racc[it]);
