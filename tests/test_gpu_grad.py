@@ -281,3 +281,39 @@ def test_deterministic_vs_reference_gradient(gpu_ctx):
     ref = np.concatenate([rec["grad_r"], rec["grad_eta"]])
     scale = np.max(np.abs(ref))
     assert np.max(np.abs(g - ref)) < 1e-7 * scale, np.max(np.abs(g - ref)) / scale
+
+
+@pytest.mark.parametrize("order", [1, 4])
+def test_deterministic_large_rows(gpu_ctx, order):
+    """Deterministic mode on rows of 38-45 clicks of a 50-mode model at orders
+    1 and 4 (the rows above 40 clicks take the large-row adjoint, whose Z(w)
+    pair blocks sit in HBM at order 1): three calls give bit-identical
+    gradients.  Against the floating-point path: 1e-9 of the largest component
+    at order 1, 1e-5 at order 4.  An entry of Z(w) at order 4 collects up to
+    1 + (n-1) + C(n-1, 2) + C(n-1, 3) terms (14,000 at 45 clicks), so the
+    fixed-point scale leaves about 45 bits below the point's largest term, and
+    these rows' order-4 sums cancel hard: the floating-point path's own
+    run-to-run spread is 2e-10 of the largest component here, the fixed-point
+    sums differ from it by up to 3e-6."""
+    M = 50
+    U, r, eta = small_model(M, 21, n_squeezed=25, r_range=(1.0, 1.5), eta_range=(0.3, 0.6))
+    rng = np.random.default_rng(81)
+    rows = [sorted(rng.choice(M, size=k, replace=False).tolist()) for k in (38, 42, 45)]
+    off, mod = csr_from_lists(rows)
+    w = np.array([0.8, 1.2, 1.0])
+    gpu_ctx.gbs_set_model(U, r, eta)
+    ref = gpu_ctx.gbs_grad(off, mod, order, w)
+    assert np.all(ref["status"] == 0), ref["status"]
+    try:
+        gpu_ctx.gbs_set_deterministic(True)
+        outs = [gpu_ctx.gbs_grad(off, mod, order, w) for _ in range(3)]
+    finally:
+        gpu_ctx.gbs_set_deterministic(False)
+    g0 = np.concatenate([outs[0]["grad_r"], outs[0]["grad_eta"]])
+    assert np.all(np.isfinite(g0)) and np.all(outs[0]["status"] == 0)
+    for o in outs[1:]:
+        assert np.array_equal(np.concatenate([o["grad_r"], o["grad_eta"]]), g0)
+    gr = np.concatenate([ref["grad_r"], ref["grad_eta"]])
+    scale = np.max(np.abs(gr))
+    print(f"order {order}: deterministic vs floating-point {np.max(np.abs(g0 - gr)) / scale:.2e}")
+    assert np.max(np.abs(g0 - gr)) < (1e-9 if order == 1 else 1e-5) * scale
