@@ -144,52 +144,83 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(
         s_m = N - 1;
     }
     __syncthreads();
+    // (ed[i] is negligible when |ed[i]| <= eps (|dg[i]| + |dg[i+1]|))
+    auto small = [&](int i) { return fabs(ed[i]) <= eps * (fabs(dg[i]) + fabs(dg[i + 1])); };
     for (int guard = 0; guard < 60 * N + 60; ++guard) {
-        if (tid == 0) {
-            int hi = s_m, lo = -1;
-            // deflate converged entries at the bottom
-            while (hi > 0 && fabs(ed[hi - 1]) <= eps * (fabs(dg[hi - 1]) + fabs(dg[hi]))) {
-                ed[hi - 1] = 0.0;
-                --hi;
-            }
-            if (hi > 0) {
-                lo = hi - 1;
-                while (lo > 0 && !(fabs(ed[lo - 1]) <= eps * (fabs(dg[lo - 1]) + fabs(dg[lo])))) --lo;
-                if (lo > 0) ed[lo - 1] = 0.0;
-                // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block
-                // closer to its last diagonal entry
-                const double e = ed[hi - 1];
-                const double dd = 0.5 * (dg[hi - 1] - dg[hi]);
-                const double den = dd + copysign(sqrt(fma(dd, dd, e * e)), dd);
-                const double mu = den != 0.0 ? dg[hi] - e * e / den : dg[hi];
-                double x = dg[lo] - mu, z = ed[lo], bulge = 0.0;
-                for (int k = lo; k < hi; ++k) {
-                    const double r = sqrt(fma(x, x, z * z));
-                    double c = 1.0, sn = 0.0;
-                    if (r != 0.0) {
-                        c = x / r;
-                        sn = z / r;
-                    }
-                    if (k > lo) ed[k - 1] = r;  // the bulge is gone
-                    const double a = dg[k], b = ed[k], d = dg[k + 1];
-                    const double cs = c * sn, c2 = c * c, s2 = sn * sn;
-                    dg[k] = c2 * a + 2.0 * cs * b + s2 * d;
-                    dg[k + 1] = s2 * a - 2.0 * cs * b + c2 * d;
-                    ed[k] = cs * (d - a) + (c2 - s2) * b;
-                    if (k + 1 < hi) {
-                        const double en = ed[k + 1];
-                        bulge = sn * en;
-                        ed[k + 1] = c * en;
-                    }
-                    rc[k] = c;
-                    rs[k] = sn;
-                    x = ed[k];
-                    z = bulge;
+        if (tid < 64) {
+            // wavefront 0 finds the active block: hi = the highest index at or
+            // below s_m whose coupling to the row above is not negligible (the
+            // negligible ones set to zero), lo = the lowest index joined to hi
+            // by non-negligible couplings; 64 candidates per ballot
+            const int top = s_m;
+            int hi = 0;
+            for (int base = top; base > 0; base -= 64) {
+                const int idx = base - tid;
+                const bool stop = idx > 0 && !small(idx - 1);
+                const unsigned long long bal = __ballot(stop);
+                if (bal != 0ull) {
+                    hi = base - __ffsll((long long)bal) + 1;
+                    break;
                 }
             }
-            s_m = hi;
-            s_lo = lo;
-            if (hi > 0 && guard == 60 * N + 59) s_fail = 1;
+            for (int idx = hi + 1 + tid; idx <= top; idx += 64) ed[idx - 1] = 0.0;
+            int lo = -1;
+            if (hi > 0) {
+                for (int base = hi - 1;; base -= 64) {
+                    const int idx = base - tid;
+                    const bool stop = idx >= 0 && (idx == 0 || small(idx - 1));
+                    const unsigned long long bal = __ballot(stop);
+                    if (bal != 0ull) {
+                        lo = base - __ffsll((long long)bal) + 1;
+                        break;
+                    }
+                }
+            }
+            if (tid == 0) {
+                if (hi > 0) {
+                    if (lo > 0) ed[lo - 1] = 0.0;
+                    // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block
+                    // closer to its last diagonal entry
+                    const double e = ed[hi - 1];
+                    const double dd = 0.5 * (dg[hi - 1] - dg[hi]);
+                    const double den = dd + copysign(sqrt(fma(dd, dd, e * e)), dd);
+                    const double mu = den != 0.0 ? dg[hi] - e * e / den : dg[hi];
+                    // the chase: a = dg[k] and b = ed[k] as rotated by the previous
+                    // step are carried in registers, d = dg[k + 1] and en = ed[k + 1]
+                    // are still the block's own values
+                    double a = dg[lo], b = ed[lo];
+                    double x = a - mu, z = b, bulge = 0.0;
+                    for (int k = lo; k < hi; ++k) {
+                        const double d = dg[k + 1];
+                        const double en = k + 1 < hi ? ed[k + 1] : 0.0;
+                        const double r = sqrt(fma(x, x, z * z));
+                        double c = 1.0, sn = 0.0;
+                        if (r != 0.0) {
+                            c = x / r;
+                            sn = z / r;
+                        }
+                        if (k > lo) ed[k - 1] = r;  // the bulge is gone
+                        const double cs = c * sn, c2 = c * c, s2 = sn * sn;
+                        dg[k] = c2 * a + 2.0 * cs * b + s2 * d;
+                        const double dn = s2 * a - 2.0 * cs * b + c2 * d;
+                        const double ek = cs * (d - a) + (c2 - s2) * b;
+                        ed[k] = ek;
+                        if (k + 1 < hi) {
+                            bulge = sn * en;
+                            b = c * en;
+                        }
+                        rc[k] = c;
+                        rs[k] = sn;
+                        x = ek;
+                        z = bulge;
+                        a = dn;
+                    }
+                    dg[hi] = a;
+                }
+                s_m = hi;
+                s_lo = lo;
+                if (hi > 0 && guard == 60 * N + 59) s_fail = 1;
+            }
         }
         __syncthreads();
         const int hi = s_m, lo = s_lo;
