@@ -625,6 +625,8 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                                     // (indices from the LDS base, kept opaque, so that each
                                     // position's address is formed once and the arrays'
                                     // fixed strides ride as immediate offsets)
+                                    // (Mo0 = Zd0 + ADJ_MREG + 3 ADJ_DS in this layout: Z(w), then
+                                    // the M(w) region with its three diagonal-block arrays first)
                                     int ia_ = ADJ_MREG + 3 * ADJ_DS + cur_ac, ib_ = ADJ_MREG + 3 * ADJ_DS + cur_bc;
                                     asm("" : "+v"(ia_), "+v"(ib_));
                                     xa = Zd0 + ia_;
