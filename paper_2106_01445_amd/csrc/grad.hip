@@ -823,7 +823,8 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                         }
                         int ez = 0;
                         frexp(zm, &ez);
-                        zsc = zm > 0.0 && zm <= DBL_MAX ? ldexp(1.0, 61 - (ilogb(ncl) + 2) - ez) : 1.0;
+                        // (ncl terms below 2^ez sum to less than 2^62 at this scale)
+                        zsc = zm > 0.0 && zm <= DBL_MAX ? ldexp(1.0, 61 - ilogb(ncl) - ez) : 1.0;
                         zmax = zm;
                     }
                 }
@@ -1780,7 +1781,7 @@ __global__ void k_det_scale(unsigned long long *det, int nterm)
     } else if (m > 0.0) {
         int e = 0;
         frexp(m, &e);
-        sc = ldexp(1.0, 61 - (ilogb((double)nterm) + 2) - e);
+        sc = ldexp(1.0, 61 - ilogb((double)nterm) - e);  // (the sum stays below 2^62)
     }
     det[1] = (unsigned long long)__double_as_longlong(sc);
 }
