@@ -331,14 +331,14 @@ int gbs_plan_info(gbs_plan *plan, double *rho, double *rconv, int32_t *K, int32_
  * power-of-two scale leaving room for every term, and the second adds the
  * terms as 64-bit integers, whose sum does not depend on the order; the
  * results are bitwise reproducible (same plan, model, weights and GPU type).
- * The integer sums round each term at the scale of the sum's largest term,
- * with room for one term per cluster holding the entry's mode, which costs
- * precision where there are many clusters and their sums cancel: measured
- * against the floating-point sums, in units of the largest gradient
- * component, about 1e-15 at orders 1 and 2, 1e-12 for 40-click rows and
- * 2e-10 for 60-click rows at order 3, 1e-13 for 14-click rows and 2e-7 for
- * 45-click rows at order 4 (where the floating-point path's own run-to-run
- * spread is 2e-10).  The cost: the adjoint's cluster terms are formed twice.
+ * The integer sums round each term at a power-of-two scale set by the largest
+ * term of its kind (the diagonal or the pair blocks of Z(w)), with room for
+ * one term per cluster holding the entry's modes, which costs precision where
+ * there are many clusters and their sums cancel: measured against the
+ * floating-point sums, in units of the largest gradient component, about
+ * 1e-15 at orders 1 and 2, 4e-13 for 40-click rows and 2e-11 for 60-click
+ * rows at order 3, 5e-14 for 14-click rows and 6e-9 for 45-click rows at
+ * order 4 (where the floating-point path's own run-to-run spread is 2e-10).  The cost: the adjoint's cluster terms are formed twice.
  * Affects gbs_grad and gbs_grad_dev on this context.  Errors: GBS_E_INVAL for
  * a NULL context.
  */

@@ -339,7 +339,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
     extern __shared__ __attribute__((aligned(16))) double sh[];
     __shared__ int s_item;
     __shared__ cplx s_g[ORDER + 1];
-    __shared__ double s_zmax[CONT_THREADS / 64];
+    __shared__ double s_zmax[2 * CONT_THREADS / 64];
     __shared__ cplx s_wq[ADJ_QCHUNK];
     cplx *red = (cplx *)sh;                        // [waves]
     double *dyn = (double *)(red + CONT_THREADS / 64 + 8);
@@ -435,20 +435,27 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         // first pass only finds their largest magnitude, which fixes a power-of-two
         // scale, and the second adds them into Z as 64-bit integers (sums that
         // do not depend on the order of the adds), converted back after it.
+        // The diagonal blocks and the pair blocks take scales of their own (an
+        // entry of a pair block collects far fewer terms).
         int zpass = 1;
-        double zmax = 0.0, zsc = 1.0;
+        double zmax = 0.0, zsc = 1.0, zmaxo = 0.0, zsco = 1.0;
+        // the pair blocks follow the diagonal ones wherever they are added into
+        const int zoff = BIG ? 3 * n : 3 * ADJ_DS;
         // (entries are addressed by their complex index from Zd0, so that the
         // arrays' fixed strides become immediate offsets of the LDS adds)
         auto zadd = [&](int idx, cplx v) {
             if constexpr (DET) {
+                const bool pr = idx >= zoff;
                 if (zpass == 0) {
                     const double m = fmax(fabs(v.re), fabs(v.im));
-                    zmax = m <= DBL_MAX ? fmax(zmax, m) : INFINITY;  // (NaN or inf: non-finite)
+                    double &zm = pr ? zmaxo : zmax;
+                    zm = m <= DBL_MAX ? fmax(zm, m) : INFINITY;  // (NaN or inf: non-finite)
                     return;
                 }
+                const double sc = pr ? zsco : zsc;
                 unsigned long long *zr = (unsigned long long *)Zd0 + (ZPLANES ? idx : 2 * idx);
-                atomicAdd(zr, (unsigned long long)llrint(v.re * zsc));
-                atomicAdd(zr + (ZPLANES ? zplane : 1), (unsigned long long)llrint(v.im * zsc));
+                atomicAdd(zr, (unsigned long long)llrint(v.re * sc));
+                atomicAdd(zr + (ZPLANES ? zplane : 1), (unsigned long long)llrint(v.im * sc));
             } else if constexpr (ZPLANES) {
                 double *zr = (double *)Zd0 + idx;
                 atomicAdd(zr, v.re);
@@ -458,8 +465,6 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             }
         };
         // diagonal-block array k at mode x; pair-block array k at pair position q
-        // (the pair blocks follow the diagonal ones wherever they are added into)
-        const int zoff = BIG ? 3 * n : 3 * ADJ_DS;
         auto zd = [&](int k, int x, cplx v) { zadd(k * dstr + x, v); };
         auto zo = [&](int k, int q, cplx v) { zadd(zoff + k * ostr + q, v); };
         for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
@@ -555,6 +560,7 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             cplx bsum = cmk(0.0, 0.0);
             for (int zp = DET ? 0 : 1; zp < 2; ++zp) {
                 zpass = zp;
+                if (DET && zp == 0) zmax = zmaxo = 0.0;  // (this point's terms only)
                 bsum = cmk(0.0, 0.0);
                 const cplx g1 = s_g[1 <= ORDER ? 1 : 0];
                 for (int a = tid; a < n; a += CONT_THREADS) {
@@ -808,24 +814,45 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 }
                 if constexpr (DET) {
                     if (zp == 0) {
-                        // the block's largest term; the scale leaves room for one
-                        // term per cluster holding the entry's mode (ncl of them)
-                        double zm = zmax;
-                        for (int off = 32; off > 0; off >>= 1) zm = fmax(zm, __shfl_xor(zm, off));
-                        if (lane == 0) s_zmax[wid] = zm;
+                        // the block's largest terms; each scale leaves room for one
+                        // term per cluster holding the entry's modes: a diagonal
+                        // entry's mode is in sum_{t < j} C(n-1, t) clusters, a pair
+                        // entry's two modes in sum_{t < j-1} C(n-2, t)
+                        double zm = zmax, zo_ = zmaxo;
+                        for (int off = 32; off > 0; off >>= 1) {
+                            zm = fmax(zm, __shfl_xor(zm, off));
+                            zo_ = fmax(zo_, __shfl_xor(zo_, off));
+                        }
+                        if (lane == 0) {
+                            s_zmax[wid] = zm;
+                            s_zmax[CONT_THREADS / 64 + wid] = zo_;
+                        }
                         __syncthreads();
-                        zm = 0.0;
-                        for (int i = 0; i < CONT_THREADS / 64; ++i) zm = fmax(zm, s_zmax[i]);
-                        double ncl = 1.0, bin = 1.0;  // sum over t < j of C(n - 1, t)
+                        zm = zo_ = 0.0;
+                        for (int i = 0; i < CONT_THREADS / 64; ++i) {
+                            zm = fmax(zm, s_zmax[i]);
+                            zo_ = fmax(zo_, s_zmax[CONT_THREADS / 64 + i]);
+                        }
+                        double ncl = 1.0, bin = 1.0;
                         for (int t = 1; t < ORDER && t < n; ++t) {
                             bin = bin * (n - t) / t;
                             ncl += bin;
                         }
+                        double nclo = 1.0;
+                        bin = 1.0;
+                        for (int t = 1; t < ORDER - 1 && t < n - 1; ++t) {
+                            bin = bin * (n - 1 - t) / t;
+                            nclo += bin;
+                        }
+                        // (ncl terms below 2^e sum to less than 2^62 at the scale
+                        // 2^(61 - floor(log2 ncl) - e))
                         int ez = 0;
                         frexp(zm, &ez);
-                        // (ncl terms below 2^ez sum to less than 2^62 at this scale)
                         zsc = zm > 0.0 && zm <= DBL_MAX ? ldexp(1.0, 61 - ilogb(ncl) - ez) : 1.0;
+                        frexp(zo_, &ez);
+                        zsco = zo_ > 0.0 && zo_ <= DBL_MAX ? ldexp(1.0, 61 - ilogb(nclo) - ez) : 1.0;
                         zmax = zm;
+                        zmaxo = zo_;
                     }
                 }
             }
@@ -836,10 +863,12 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 unsigned long long *zi = (unsigned long long *)Zd0;
                 double *zf = (double *)Zd0;
                 const int nz = ZPLANES ? 2 * zplane : 6 * n;
-                const double inv = 1.0 / zsc;
-                const bool bad = !(zmax <= DBL_MAX);
-                for (int i = tid; i < nz; i += CONT_THREADS)
-                    zf[i] = bad ? NAN : (double)(long long)zi[i] * inv;
+                const double inv = 1.0 / zsc, invo = 1.0 / zsco;
+                const bool bad = !(zmax <= DBL_MAX) || !(zmaxo <= DBL_MAX);
+                for (int i = tid; i < nz; i += CONT_THREADS) {
+                    const bool pr = ZPLANES && (i < zplane ? i : i - zplane) >= zoff;
+                    zf[i] = bad ? NAN : (double)(long long)zi[i] * (pr ? invo : inv);
+                }
             }
             bsum = warp_csum(bsum);
             if (lane == 0) red[wid] = bsum;
