@@ -326,21 +326,25 @@ int gbs_plan_info(gbs_plan *plan, double *rho, double *rconv, int32_t *K, int32_
  * Deterministic gradients (on != 0; off by default).  The adjoint adds
  * cluster terms into Z(w) and rows' terms into the adjoint of Q^-1 with
  * atomic floating-point adds, whose order, and so the last bits of the
- * gradient, vary from run to run (~1e-14 relative).  With the switch on, each
- * such sum runs twice: a first pass finds its largest term, which fixes a
- * power-of-two scale leaving room for every term, and the second adds the
- * terms as 64-bit integers, whose sum does not depend on the order; the
- * results are bitwise reproducible (same plan, model, weights and GPU type).
- * The integer sums round each term at a power-of-two scale set by the largest
- * term of its kind (the diagonal or the pair blocks of Z(w)), with room for
- * one term per cluster holding the entry's modes, which costs precision where
- * there are many clusters and their sums cancel: measured against the
- * floating-point sums, in units of the largest gradient component, about
- * 1e-15 at orders 1 and 2, 4e-13 for 40-click rows and 2e-11 for 60-click
- * rows at order 3, 5e-14 for 14-click rows and 6e-9 for 45-click rows at
- * order 4 (where the floating-point path's own run-to-run spread is 2e-10).  The cost: the adjoint's cluster terms are formed twice.
- * Affects gbs_grad and gbs_grad_dev on this context.  Errors: GBS_E_INVAL for
- * a NULL context.
+ * gradient, vary from run to run (~1e-14 relative).  With the switch on, the
+ * terms are added as 64-bit integers, llrint(term x scale), whose sum does not
+ * depend on the order, and converted back: the results are bitwise
+ * reproducible (same plan, model, weights and GPU type).  The scales are
+ * powers of two that leave room for every term of an entry (one per cluster
+ * holding its modes; one per row for Q^-1's adjoint) below the largest term
+ * of its kind: for Q^-1's adjoint a first pass over the rows finds it; for
+ * Z(w), separately for its diagonal and its pair blocks, each point adds at
+ * the scales its predecessor's terms set and is run again at exact scales
+ * when its own largest terms do not fit them (an item's first point first
+ * takes a pass that only finds them).  Each term is rounded at its scale,
+ * which costs precision where there are many clusters and their sums
+ * cancel: measured against the floating-point sums, in units of the largest
+ * gradient component, about 1e-15 at orders 1 and 2, 1e-12 for 40-click rows
+ * and 4e-11 for 60-click rows at order 3, 1e-13 for 14-click rows and 1e-8
+ * for 45-click rows at order 4 (where the floating-point path's own
+ * run-to-run spread is 2e-10).  The cost: about 10 % on a forward + gradient
+ * step of 15-40-click rows at order 3.  Affects gbs_grad and gbs_grad_dev on
+ * this context.  Errors: GBS_E_INVAL for a NULL context.
  */
 int gbs_set_deterministic(gbs_ctx *ctx, int on);
 

@@ -437,21 +437,28 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         // do not depend on the order of the adds), converted back after it.
         // The diagonal blocks and the pair blocks take scales of their own (an
         // entry of a pair block collects far fewer terms).
-        int zpass = 1;
+        // Over an item's points the scales are carried: a point's pass adds at
+        // the scales the previous point's terms set (with one power of two of
+        // room), and is run again at exact scales, after Z(w) is cleared, only
+        // if its own largest terms overrun them or sit more than two powers of
+        // two below; the item's first point takes a pass that only finds them.
         double zmax = 0.0, zsc = 1.0, zmaxo = 0.0, zsco = 1.0;
+        bool zhave = false;
+        int zcap = 0, zcapo = 0;  // the scales' exponent caps: terms below 2^cap
         // the pair blocks follow the diagonal ones wherever they are added into
         const int zoff = BIG ? 3 * n : 3 * ADJ_DS;
         // (entries are addressed by their complex index from Zd0, so that the
         // arrays' fixed strides become immediate offsets of the LDS adds)
-        auto zadd = [&](int idx, cplx v) {
+        // (pr: a pair-block entry; every call site passes a constant.  A pass
+        // that only finds the largest terms runs the same code at scale 0.)
+        auto zadd = [&](int idx, cplx v, bool pr) {
             if constexpr (DET) {
-                const bool pr = idx >= zoff;
-                if (zpass == 0) {
-                    const double m = fmax(fabs(v.re), fabs(v.im));
-                    double &zm = pr ? zmaxo : zmax;
-                    zm = m <= DBL_MAX ? fmax(zm, m) : INFINITY;  // (NaN or inf: non-finite)
-                    return;
-                }
+                const double m = fmax(fabs(v.re), fabs(v.im));
+                const double mm = m <= DBL_MAX ? m : INFINITY;  // (NaN or inf: non-finite)
+                if (pr)
+                    zmaxo = fmax(zmaxo, mm);
+                else
+                    zmax = fmax(zmax, mm);
                 const double sc = pr ? zsco : zsc;
                 unsigned long long *zr = (unsigned long long *)Zd0 + (ZPLANES ? idx : 2 * idx);
                 atomicAdd(zr, (unsigned long long)llrint(v.re * sc));
@@ -465,8 +472,8 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             }
         };
         // diagonal-block array k at mode x; pair-block array k at pair position q
-        auto zd = [&](int k, int x, cplx v) { zadd(k * dstr + x, v); };
-        auto zo = [&](int k, int q, cplx v) { zadd(zoff + k * ostr + q, v); };
+        auto zd = [&](int k, int x, cplx v) { zadd(k * dstr + x, v, false); };
+        auto zo = [&](int k, int q, cplx v) { zadd(zoff + k * ostr + q, v, true); };
         for (int i = tid; i < N; i += CONT_THREADS) al[i] = alpha[2 * o + i];
         const int Qn = rp.K / 2 + 1;
         constexpr int QCH = BIG ? GBS_ADJ_CHUNK_BIG : ADJ_QCHUNK;
@@ -558,9 +565,12 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
             __syncthreads();
             // clusters: Z += c_T E_T M_TT^{-1} E_T^T, c_T = gamma_|T| det(M_TT)^{-1/2}
             cplx bsum = cmk(0.0, 0.0);
-            for (int zp = DET ? 0 : 1; zp < 2; ++zp) {
-                zpass = zp;
-                if (DET && zp == 0) zmax = zmaxo = 0.0;  // (this point's terms only)
+            bool zredo = false;
+            for (int zp = DET && !zhave ? 0 : 1; zp < 2; ++zp) {
+                if (DET) {
+                    zmax = zmaxo = 0.0;  // (this pass's terms only)
+                    if (zp == 0) zsc = zsco = 0.0;
+                }
                 bsum = cmk(0.0, 0.0);
                 const cplx g1 = s_g[1 <= ORDER ? 1 : 0];
                 for (int a = tid; a < n; a += CONT_THREADS) {
@@ -813,26 +823,36 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                     }
                 }
                 if constexpr (DET) {
-                    if (zp == 0) {
-                        // the block's largest terms; each scale leaves room for one
-                        // term per cluster holding the entry's modes: a diagonal
-                        // entry's mode is in sum_{t < j} C(n-1, t) clusters, a pair
-                        // entry's two modes in sum_{t < j-1} C(n-2, t)
-                        double zm = zmax, zo_ = zmaxo;
-                        for (int off = 32; off > 0; off >>= 1) {
-                            zm = fmax(zm, __shfl_xor(zm, off));
-                            zo_ = fmax(zo_, __shfl_xor(zo_, off));
-                        }
-                        if (lane == 0) {
-                            s_zmax[wid] = zm;
-                            s_zmax[CONT_THREADS / 64 + wid] = zo_;
-                        }
-                        __syncthreads();
-                        zm = zo_ = 0.0;
-                        for (int i = 0; i < CONT_THREADS / 64; ++i) {
-                            zm = fmax(zm, s_zmax[i]);
-                            zo_ = fmax(zo_, s_zmax[CONT_THREADS / 64 + i]);
-                        }
+                    // the block's largest terms; each scale leaves room for one
+                    // term per cluster holding the entry's modes: a diagonal
+                    // entry's mode is in sum_{t < j} C(n-1, t) clusters, a pair
+                    // entry's two modes in sum_{t < j-1} C(n-2, t)
+                    double zm = zmax, zo_ = zmaxo;
+                    for (int off = 32; off > 0; off >>= 1) {
+                        zm = fmax(zm, __shfl_xor(zm, off));
+                        zo_ = fmax(zo_, __shfl_xor(zo_, off));
+                    }
+                    if (lane == 0) {
+                        s_zmax[wid] = zm;
+                        s_zmax[CONT_THREADS / 64 + wid] = zo_;
+                    }
+                    __syncthreads();
+                    zm = zo_ = 0.0;
+                    for (int i = 0; i < CONT_THREADS / 64; ++i) {
+                        zm = fmax(zm, s_zmax[i]);
+                        zo_ = fmax(zo_, s_zmax[CONT_THREADS / 64 + i]);
+                    }
+                    zmax = zm;
+                    zmaxo = zo_;
+                    const bool fin = zm <= DBL_MAX && zo_ <= DBL_MAX;
+                    // (non-finite terms: every entry becomes NaN below, whatever Z holds)
+                    if (!fin) break;
+                    int ed = 0, eo = 0;
+                    frexp(zm, &ed);
+                    frexp(zo_, &eo);
+                    const bool fits = zp == 1 && (zm == 0.0 || (ed <= zcap && ed >= zcap - 2)) &&
+                                      (zo_ == 0.0 || (eo <= zcapo && eo >= zcapo - 2));
+                    if (!fits && !zredo) {
                         double ncl = 1.0, bin = 1.0;
                         for (int t = 1; t < ORDER && t < n; ++t) {
                             bin = bin * (n - t) / t;
@@ -844,16 +864,29 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                             bin = bin * (n - 1 - t) / t;
                             nclo += bin;
                         }
-                        // (ncl terms below 2^e sum to less than 2^62 at the scale
-                        // 2^(61 - floor(log2 ncl) - e))
-                        int ez = 0;
-                        frexp(zm, &ez);
-                        zsc = zm > 0.0 && zm <= DBL_MAX ? ldexp(1.0, 61 - ilogb(ncl) - ez) : 1.0;
-                        frexp(zo_, &ez);
-                        zsco = zo_ > 0.0 && zo_ <= DBL_MAX ? ldexp(1.0, 61 - ilogb(nclo) - ez) : 1.0;
-                        zmax = zm;
-                        zmaxo = zo_;
+                        // exact caps for this point (ncl terms below 2^e sum to less
+                        // than 2^62 at the scale 2^(61 - floor(log2 ncl) - e))
+                        zcap = zm > 0.0 ? ed : zcap;
+                        zcapo = zo_ > 0.0 ? eo : zcapo;
+                        zsc = ldexp(1.0, 61 - ilogb(ncl) - zcap);
+                        zsco = ldexp(1.0, 61 - ilogb(nclo) - zcapo);
+                        zhave = true;
+                        if (zp == 1) {
+                            // the adds made at the old scales are discarded
+                            if (BIG) {
+                                for (int i = tid; i < 3 * n; i += CONT_THREADS) Zd0[i] = cmk(0.0, 0.0);
+                                if (ORDER != 2)
+                                    for (int i = tid; i < 4 * np; i += CONT_THREADS) Zo0[i] = cmk(0.0, 0.0);
+                            } else {
+                                for (int i = tid; i < ADJ_MREG; i += CONT_THREADS) Zd0[i] = cmk(0.0, 0.0);
+                            }
+                            zredo = true;
+                        }
+                        __syncthreads();
+                        zp = 0;  // (the next pass adds at the new scales)
+                        continue;
                     }
+                    break;
                 }
             }
             if constexpr (DET) {
@@ -868,6 +901,20 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
                 for (int i = tid; i < nz; i += CONT_THREADS) {
                     const bool pr = ZPLANES && (i < zplane ? i : i - zplane) >= zoff;
                     zf[i] = bad ? NAN : (double)(long long)zi[i] * (pr ? invo : inv);
+                }
+                // the next point's scales: one power of two above this point's terms
+                if (!bad && zhave) {
+                    int ed = 0, eo = 0;
+                    frexp(zmax, &ed);
+                    frexp(zmaxo, &eo);
+                    if (zmax > 0.0 && ed + 1 != zcap) {
+                        zsc = ldexp(zsc, zcap - ed - 1);
+                        zcap = ed + 1;
+                    }
+                    if (zmaxo > 0.0 && eo + 1 != zcapo) {
+                        zsco = ldexp(zsco, zcapo - eo - 1);
+                        zcapo = eo + 1;
+                    }
                 }
             }
             bsum = warp_csum(bsum);

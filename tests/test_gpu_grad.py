@@ -238,7 +238,7 @@ def test_deterministic_gradients(gpu_ctx, cfg, P, order):
     diagonal block up to 1800 terms in 60-click rows at order 3, so about
     2^-51 of the largest such term; a pair block at most n - 1), and the
     contour sum cancels those terms as it cancels the floating-point ones
-    (measured: 4e-13 at 70 modes, 2e-11 for the 100-mode rows)."""
+    (measured: 1e-12 at 70 modes, 4e-11 for the 100-mode rows)."""
     wl = make_workload(cfg, P=P)
     gpu_ctx.gbs_set_model(wl.U, wl.r, wl.eta)
     w = np.random.default_rng(11).uniform(0.5, 1.5, wl.P)
@@ -295,7 +295,7 @@ def test_deterministic_large_rows(gpu_ctx, order):
     fixed-point scale leaves about 48 bits below its largest term, and these
     rows' order-4 sums cancel hard: the floating-point path's own run-to-run
     spread is 2e-10 of the largest component here, the fixed-point sums differ
-    from it by 6e-9."""
+    from it by 8e-9."""
     M = 50
     U, r, eta = small_model(M, 21, n_squeezed=25, r_range=(1.0, 1.5), eta_range=(0.3, 0.6))
     rng = np.random.default_rng(81)
