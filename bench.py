@@ -626,6 +626,22 @@ def main():
     torch.cuda.synchronize()
     ms_graph = (time.perf_counter() - t0) * 1e3 / args.steps
     graph_match = bool(np.array_equal(logp.cpu().numpy(), lp))
+    # the same step with bitwise-reproducible gradients (gbs_set_deterministic):
+    # its time, two calls compared bit for bit, and its distance from the
+    # floating-point gradient in units of the largest component
+    g_fp = torch.cat([gr, ge]).cpu().numpy()
+    ctx.gbs_set_deterministic(True)
+    try:
+        ms_det, _ = timed(fwd_grad, args.steps)
+        g_d1 = torch.cat([gr, ge]).cpu().numpy()
+        fwd_grad()
+        torch.cuda.synchronize()
+        g_d2 = torch.cat([gr, ge]).cpu().numpy()
+    finally:
+        ctx.gbs_set_deterministic(False)
+    deterministic = {"ms_per_step": ms_det, "vs_default_step": ms_det / ms_step,
+                     "bitwise_repeat": bool(np.array_equal(g_d1, g_d2)),
+                     "max_dev_vs_floating_point": float(np.max(np.abs(g_d1 - g_fp)) / np.max(np.abs(g_fp)))}
 
     ns = np.diff(wl.offsets)
     npts = (info["K"] // 2 + 1).astype(np.float64)
@@ -682,6 +698,7 @@ def main():
         "autotune": tuning,
         "graph": {"ms_per_step": ms_graph, "probs_per_s": wl.P / (ms_graph * 1e-3),
                   "logp_identical_to_eager": graph_match},
+        "deterministic_gradients": deterministic,
         "subset_dets_per_step": dets,
         "subset_dets_per_s_fwd_grad": dets / (ms_step * 1e-3),
         "kernel_ms_per_step": {k: round(v, 3) for k, v in per.items()},
