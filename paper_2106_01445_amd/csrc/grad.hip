@@ -431,17 +431,17 @@ __global__ __launch_bounds__(CONT_THREADS) void k_adj_contour(
         // HBM and Z stays interleaved.)
         constexpr bool ZPLANES = !BIG || ORDER >= 3;
         const int zplane = BIG ? 3 * n + 4 * np : ADJ_MREG;
-        // Deterministic mode: the cluster terms are formed twice per point; the
-        // first pass only finds their largest magnitude, which fixes a power-of-two
-        // scale, and the second adds them into Z as 64-bit integers (sums that
-        // do not depend on the order of the adds), converted back after it.
-        // The diagonal blocks and the pair blocks take scales of their own (an
-        // entry of a pair block collects far fewer terms).
-        // Over an item's points the scales are carried: a point's pass adds at
-        // the scales the previous point's terms set (with one power of two of
-        // room), and is run again at exact scales, after Z(w) is cleared, only
-        // if its own largest terms overrun them or sit more than two powers of
-        // two below; the item's first point takes a pass that only finds them.
+        // Deterministic mode: the cluster terms go into Z as 64-bit integers,
+        // llrint(term x scale) (sums that do not depend on the order of the
+        // adds), converted back after the point.  The scales are powers of two
+        // with room for every term of an entry below the largest term of its
+        // kind; the diagonal blocks and the pair blocks take scales of their own
+        // (an entry of a pair block collects far fewer terms).  Over an item's
+        // points the scales are carried: a point adds at the scales the previous
+        // point's terms set (with one power of two of room) while it tracks its
+        // own largest terms, and is run again at exact scales, after Z(w) is
+        // cleared, only if they overrun those scales or sit more than two powers
+        // of two below; the item's first point takes a pass that only finds them.
         double zmax = 0.0, zsc = 1.0, zmaxo = 0.0, zsco = 1.0;
         bool zhave = false;
         int zcap = 0, zcapo = 0;  // the scales' exponent caps: terms below 2^cap
