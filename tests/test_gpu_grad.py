@@ -226,10 +226,10 @@ def test_grad_run_to_run_spread(gpu_ctx):
     assert spread < 1e-12
 
 
-@pytest.mark.parametrize("cfg,P,order", [(3, 512, 3), (2, 512, 4), (2, 512, 1), (4, 64, 3), (5, 48, 2)])
+@pytest.mark.parametrize("cfg,P,order", [(3, 512, 3), (2, 512, 4), (2, 512, 2), (2, 512, 1), (4, 64, 3), (5, 48, 2)])
 def test_deterministic_gradients(gpu_ctx, cfg, P, order):
     """With gbs_set_deterministic on, three calls give bit-identical gradients
-    (70 modes at order 3; 20 modes at orders 4 and 1; the first rows of the
+    (70 modes at order 3; 20 modes at orders 4, 2 and 1; the first rows of the
     100-mode batch at order 3 and of the 144-mode batch at order 2, whose rows
     above 40 clicks take the large-row kernels), and they agree with the
     floating-point sums to 1e-10 of the largest component.  That bound is the
